@@ -1,0 +1,276 @@
+"""FP64 CPU oracle for cross-approximation CUR (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The GPU library never imports it and
+shares no code with it.  Everything here is a thin ctypes layer over
+``lra_oracle.c``, a plain C reading of Pan, Luan, Svadlenka and Zhao,
+"Superfast Accurate Low Rank Approximation"; each C routine cites the passage
+it follows.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lra_oracle.c")
+_OUT = os.path.join(_HERE, "_build", "liblra_oracle.so")
+
+OK, EINVAL, ESINGULAR = 0, 1, 2
+F64, F32, BF16 = 0, 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc into ``oracle/_build`` and return the path."""
+    if force or not os.path.exists(_OUT) or os.path.getmtime(_OUT) < os.path.getmtime(_SRC):
+        os.makedirs(os.path.dirname(_OUT), exist_ok=True)
+        tmp = _OUT + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _OUT)
+    return _OUT
+
+
+class _Opts(ct.Structure):
+    _fields_ = [("delta", ct.c_double), ("max_swaps", ct.c_int32), ("preprocess", ct.c_int32),
+                ("ah_depth", ct.c_int32), ("ah_samples", ct.c_int32), ("refine_steps", ct.c_int32),
+                ("init_cols", ct.POINTER(ct.c_int64))]
+
+
+class _Info(ct.Structure):
+    _fields_ = [("sweeps_run", ct.c_int32), ("swaps_total", ct.c_int32), ("converged", ct.c_int32),
+                ("rank_found", ct.c_int32), ("min_margin", ct.c_double), ("det_log_abs", ct.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ct.CDLL(build())
+        P = ct.c_void_p
+        i64, i32, u64, dbl = ct.c_int64, ct.c_int32, ct.c_uint64, ct.c_double
+        L.orc_rng_u64.argtypes = [u64, u64, u64]
+        L.orc_rng_u64.restype = u64
+        L.orc_draw_distinct.argtypes = [u64, u64, i64, i64, P]
+        L.orc_sign.argtypes = [u64, i64]
+        L.orc_sign.restype = dbl
+        L.orc_panel_lu.argtypes = [P, i64, ct.c_int, P, P, P, P]
+        L.orc_maxvol.argtypes = [P, i64, ct.c_int, dbl, i32, P, P, P, P, P, P, P, P]
+        L.orc_sketch.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
+        L.orc_qrp.argtypes = [P, i64, ct.c_int, ct.c_int, P, P, P]
+        L.orc_inverse.argtypes = [P, ct.c_int, P, ct.c_int, P]
+        L.orc_default_opts.argtypes = [P]
+        L.orc_ca_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, u64, P, P, P, P, P]
+        L.orc_residual.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, P, P]
+        L.orc_cur_adjoint.argtypes = [P, P, P, i64, i64, ct.c_int, P, P, P, i64, P, P, P, P]
+        for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
+                  "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint"):
+            getattr(L, f).restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ct.c_void_p) if a is not None else None
+
+
+def _dtype_code(a: np.ndarray) -> int:
+    if a.dtype == np.float64:
+        return F64
+    if a.dtype == np.float32:
+        return F32
+    if a.dtype == np.uint16:  # bfloat16 bit patterns
+        return BF16
+    raise TypeError("oracle input must be float64, float32 or uint16 (bf16 bits)")
+
+
+# --------------------------------------------------------------------------
+# random numbers
+# --------------------------------------------------------------------------
+def rng_u64(seed: int, stream: int, i: int) -> int:
+    return int(lib().orc_rng_u64(seed, stream, i))
+
+
+def draw_distinct(seed: int, stream: int, n: int, k: int) -> np.ndarray:
+    out = np.zeros(k, np.int64)
+    st = lib().orc_draw_distinct(seed, stream, n, k, _p(out))
+    if st:
+        raise ValueError("draw_distinct: status %d" % st)
+    return out
+
+
+def sign(seed: int, c: int) -> float:
+    return float(lib().orc_sign(seed, c))
+
+
+# --------------------------------------------------------------------------
+# panel routines
+# --------------------------------------------------------------------------
+def panel_lu(P: np.ndarray):
+    """Pivoted LU of a tall items x r panel: returns (status, piv, LU, rank, margin)."""
+    P = np.ascontiguousarray(P, np.float64)
+    items, r = P.shape
+    piv = np.full(r, -1, np.int64)
+    LU = np.zeros_like(P)
+    rank = ct.c_int32(0)
+    mm = ct.c_double(1.0)
+    st = lib().orc_panel_lu(_p(P), items, r, _p(piv), _p(LU), ct.byref(rank), ct.byref(mm))
+    return st, piv, LU, rank.value, mm.value
+
+
+@dataclass
+class MaxvolResult:
+    status: int
+    slots: np.ndarray
+    B: np.ndarray
+    swaps: int
+    converged: int
+    rank: int
+    min_margin: float
+    trace_idx: np.ndarray
+    trace_val: np.ndarray
+
+
+def maxvol(P: np.ndarray, delta: float = 0.01, max_swaps: int | None = None) -> MaxvolResult:
+    """Dominant r x r submatrix of a tall panel (GEPP start + swaps)."""
+    P = np.ascontiguousarray(P, np.float64)
+    items, r = P.shape
+    if max_swaps is None:
+        max_swaps = 16 * r
+    slots = np.full(r, -1, np.int64)
+    B = np.zeros_like(P)
+    tr_i = np.full(2 * max(max_swaps, 1), -1, np.int64)
+    tr_v = np.zeros(max(max_swaps, 1))
+    sw, cv, rk = ct.c_int32(0), ct.c_int32(0), ct.c_int32(0)
+    mm = ct.c_double(1.0)
+    st = lib().orc_maxvol(_p(P), items, r, delta, max_swaps, _p(slots), _p(B), _p(tr_i), _p(tr_v),
+                          ct.byref(sw), ct.byref(cv), ct.byref(rk), ct.byref(mm))
+    return MaxvolResult(st, slots, B, sw.value, cv.value, rk.value, mm.value,
+                        tr_i[: 2 * sw.value].reshape(-1, 2), tr_v[: sw.value])
+
+
+def sketch(A: np.ndarray, side: int, d: int, l: int, seed: int):
+    """Abridged SRHT sketch: returns (Y items x l, samples)."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    items = n if side else m
+    Y = np.zeros((items, l))
+    smp = np.zeros(l, np.int64)
+    st = lib().orc_sketch(_p(A), _dtype_code(A), m, n, n, side, d, l, seed, _p(Y), _p(smp))
+    if st:
+        raise ValueError("sketch: status %d" % st)
+    return Y, smp
+
+
+def qrp(Z: np.ndarray, k: int):
+    """Greedy Householder QRP over the items (rows) of Z: returns (status, piv, rank, margin)."""
+    Z = np.array(Z, np.float64, order="C", copy=True)
+    items, w = Z.shape
+    piv = np.full(k, -1, np.int64)
+    rank = ct.c_int32(0)
+    mm = ct.c_double(1.0)
+    st = lib().orc_qrp(_p(Z), items, w, k, _p(piv), ct.byref(rank), ct.byref(mm))
+    return st, piv, rank.value, mm.value
+
+
+def inverse(G: np.ndarray, refine_steps: int = 0):
+    G = np.ascontiguousarray(G, np.float64)
+    r = G.shape[0]
+    U = np.zeros_like(G)
+    ld = ct.c_double(0.0)
+    st = lib().orc_inverse(_p(G), r, _p(U), refine_steps, ct.byref(ld))
+    return st, U, ld.value
+
+
+# --------------------------------------------------------------------------
+# the whole path
+# --------------------------------------------------------------------------
+@dataclass
+class CurResult:
+    status: int
+    I: np.ndarray
+    J: np.ndarray
+    U: np.ndarray
+    sweeps_run: int
+    swaps_total: int
+    converged: int
+    rank_found: int
+    min_margin: float
+    det_log_abs: float
+
+
+def ca_cur(A: np.ndarray, r: int, sweeps: int, seed: int, delta: float = 0.01, max_swaps: int = -1,
+           preprocess: int = 0, ah_depth: int = 3, ah_samples: int = 0, refine_steps: int = 0,
+           init_cols=None) -> CurResult:
+    """C-A CUR of a row-major matrix (float64, float32 or uint16 bf16 bits)."""
+    A = np.ascontiguousarray(A)
+    if A.ndim != 2:
+        raise ValueError("A must be 2-D")
+    m, n = A.shape
+    o = _Opts()
+    lib().orc_default_opts(ct.byref(o))
+    o.delta = delta
+    o.max_swaps = max_swaps
+    o.preprocess = preprocess
+    o.ah_depth = ah_depth
+    o.ah_samples = ah_samples
+    o.refine_steps = refine_steps
+    ic = None
+    if init_cols is not None:
+        ic = np.ascontiguousarray(init_cols, np.int64)
+        o.init_cols = ic.ctypes.data_as(ct.POINTER(ct.c_int64))
+    I = np.full(r, -1, np.int64)
+    J = np.full(r, -1, np.int64)
+    U = np.zeros((r, r))
+    info = _Info()
+    st = lib().orc_ca_cur(_p(A), _dtype_code(A), m, n, n, r, sweeps, seed, ct.byref(o),
+                          _p(I), _p(J), _p(U), ct.byref(info))
+    return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
+                     info.min_margin, info.det_log_abs)
+
+
+def residual(A: np.ndarray, I, J, U):
+    """(||A - C U R||_F^2, ||A||_F^2) in FP64."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    I = np.ascontiguousarray(I, np.int64)
+    J = np.ascontiguousarray(J, np.int64)
+    U = np.ascontiguousarray(U, np.float64)
+    e2, w2 = ct.c_double(0), ct.c_double(0)
+    st = lib().orc_residual(_p(A), _dtype_code(A), m, n, n, len(I), _p(I), _p(J), _p(U), ct.byref(e2),
+                            ct.byref(w2))
+    if st:
+        raise ValueError("residual: status %d" % st)
+    return e2.value, w2.value
+
+
+def rel_fro(A, I, J, U) -> float:
+    e2, w2 = residual(A, I, J, U)
+    return float(np.sqrt(e2 / w2)) if w2 > 0 else float(np.sqrt(e2))
+
+
+def cur_adjoint(C, R, G, om_i, om_j, aval):
+    """Loss and (dC, dR, dG) of sum over Omega of (a - C G^{-1} R)^2, all FP64."""
+    C = np.ascontiguousarray(C, np.float64)
+    R = np.ascontiguousarray(R, np.float64)
+    G = np.ascontiguousarray(G, np.float64)
+    om_i = np.ascontiguousarray(om_i, np.int64)
+    om_j = np.ascontiguousarray(om_j, np.int64)
+    aval = np.ascontiguousarray(aval, np.float64)
+    m, r = C.shape
+    n = R.shape[1]
+    dC = np.zeros_like(C)
+    dR = np.zeros_like(R)
+    dG = np.zeros_like(G)
+    loss = ct.c_double(0)
+    st = lib().orc_cur_adjoint(_p(C), _p(R), _p(G), m, n, r, _p(om_i), _p(om_j), _p(aval), len(om_i),
+                               ct.byref(loss), _p(dC), _p(dR), _p(dG))
+    if st:
+        raise ValueError("cur_adjoint: status %d" % st)
+    return loss.value, dC, dR, dG

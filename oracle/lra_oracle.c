@@ -1,0 +1,697 @@
+/*
+ * lra_oracle.c -- plain, slow FP64 CPU oracle for cross-approximation (C-A)
+ * CUR low-rank approximation, written from Pan, Luan, Svadlenka and Zhao,
+ * "Superfast Accurate Low Rank Approximation" (arXiv 1710.07946).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  The GPU product path
+ * never links, loads or calls it, and the two share no code, header, table or
+ * helper: the only thing both sides follow is the published definition of the
+ * SplitMix64 generator (Steele, Lea and Flood, OOPSLA 2014), which each side
+ * implements on its own.
+ *
+ * Every routine takes the paper's steps in the paper's order, with no blocking,
+ * fusion or reordering.  Where the paper is silent or ambiguous the reading
+ * taken is stated at the routine (tie-breaks, thresholds, scaling).
+ *
+ * Conventions
+ *   - matrices are dense row-major, element (i,j) at p[i*ld + j];
+ *   - A is read through orc_get(), which upcasts FP32 / BF16 exactly to FP64;
+ *   - index sets are 0-based int64; outputs are sorted ascending;
+ *   - status: 0 ok, 1 invalid argument, 2 singular (rank deficient panel).
+ *
+ * Parity pins for every routine live in tests/test_oracle_*.py; the one
+ * routine without an independent pin is the pseudo-inverse fallback, which is
+ * not implemented (a singular nucleus is reported as status 2).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_ESINGULAR 2
+
+#define ORC_F64 0
+#define ORC_F32 1
+#define ORC_BF16 2
+
+/* ------------------------------------------------------------------------ */
+/* Random numbers: SplitMix64 in counter form.                               */
+/* The i-th output (0-based) of the SplitMix64 sequence started at state     */
+/* `seed` is mix(seed + (i+1)*gamma).  Independent streams are obtained by   */
+/* offsetting the counter by stream * 2^40.                                  */
+/* ------------------------------------------------------------------------ */
+static uint64_t orc_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t orc_rng_u64(uint64_t seed, uint64_t stream, uint64_t i) {
+    const uint64_t gamma = 0x9e3779b97f4a7c15ULL;
+    return orc_mix64(seed + gamma * ((stream << 40) + i + 1));
+}
+
+/* k distinct integers in [0, n), in draw order.  Each draw is reduced modulo
+ * n after rejecting the top 2^64 mod n values (so every residue is equally
+ * likely); a value already drawn is skipped.  Used for the random initial
+ * column set of C-A (Tests 2 of the experiments section draw a random initial
+ * index set) and for sampling the columns of the SRHT multiplier (App. B,
+ * "sample l columns uniformly at random and without replacement"). */
+int orc_draw_distinct(uint64_t seed, uint64_t stream, int64_t n, int64_t k, int64_t *out) {
+    if (n <= 0 || k < 0 || k > n || (k > 0 && !out)) return ORC_EINVAL;
+    uint64_t un = (uint64_t)n;
+    uint64_t rem = (0 - un) % un;         /* 2^64 mod n */
+    uint64_t lim = 0 - rem;               /* accept u < lim (all u if rem == 0) */
+    uint64_t ctr = 0;
+    int64_t got = 0;
+    while (got < k) {
+        uint64_t u = orc_rng_u64(seed, stream, ctr++);
+        if (rem != 0 && u >= lim) continue;
+        int64_t v = (int64_t)(u % un);
+        int dup = 0;
+        for (int64_t q = 0; q < got; q++)
+            if (out[q] == v) { dup = 1; break; }
+        if (!dup) out[got++] = v;
+    }
+    return ORC_OK;
+}
+
+/* Rademacher sign of the random diagonal D of the SRHT multiplier: the paper
+ * takes D uniform on the complex unit circle; for real inputs the reading
+ * taken is a uniform +-1 (App. B, randomized Hadamard transform). */
+double orc_sign(uint64_t seed, int64_t c) {
+    return (orc_rng_u64(seed, 1, (uint64_t)c) >> 63) ? -1.0 : 1.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Element access with exact upcast.                                         */
+/* ------------------------------------------------------------------------ */
+static double orc_get(const void *A, int dtype, int64_t lda, int64_t i, int64_t j) {
+    int64_t o = i * lda + j;
+    if (dtype == ORC_F64) return ((const double *)A)[o];
+    if (dtype == ORC_F32) return (double)((const float *)A)[o];
+    uint32_t bits = ((uint32_t)((const uint16_t *)A)[o]) << 16;
+    float f;
+    memcpy(&f, &bits, 4);
+    return (double)f;
+}
+
+static void orc_note_margin(double *mm, double v1, double v2) {
+    /* relative gap between the winning value and the runner-up */
+    if (!mm) return;
+    double g = (v1 > 0) ? (v1 - v2) / v1 : 0.0;
+    if (v2 < 0) g = 1.0; /* no runner-up: nothing was decided */
+    if (g < *mm) *mm = g;
+}
+
+static int cmp_i64(const void *a, const void *b) {
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stage 1 of the iterative C-A by recursive LUP (App. D, Algorithm alggos): */
+/* LU factorization with partial pivoting of a tall panel P (items x r).     */
+/* The paper factors an r x n matrix with column pivoting; a tall panel is   */
+/* its transpose, so here rows are pivoted.  Pivot k is the not-yet-pivoted  */
+/* item with the largest |P[i][k]| after k elimination steps; among equal    */
+/* magnitudes the lowest item index wins (reading: the paper is silent on   */
+/* ties).  Rows stay in place: after the call, LU[piv[k]][j] holds U[k][j]   */
+/* for j >= k and the multiplier L[k][j] for j < k; every other item holds   */
+/* its r multipliers L21.  A zero pivot means the panel has rank k < r.      */
+/* ------------------------------------------------------------------------ */
+int orc_panel_lu(const double *P, int64_t items, int r, int64_t *piv, double *LU, int32_t *rank,
+                 double *min_margin) {
+    if (!P || !piv || !LU || r < 1 || items < r) return ORC_EINVAL;
+    memcpy(LU, P, sizeof(double) * (size_t)items * (size_t)r);
+    char *done = (char *)calloc((size_t)items, 1);
+    if (!done) return ORC_EINVAL;
+    int st = ORC_OK;
+    if (rank) *rank = r;
+    for (int k = 0; k < r; k++) {
+        int64_t best = -1;
+        double v1 = -1.0, v2 = -1.0;
+        for (int64_t i = 0; i < items; i++) {
+            if (done[i]) continue;
+            double a = fabs(LU[i * r + k]);
+            if (a > v1) { v2 = v1; v1 = a; best = i; }
+            else if (a > v2) v2 = a;
+        }
+        if (v1 == 0.0) { st = ORC_ESINGULAR; if (rank) *rank = k; break; }
+        orc_note_margin(min_margin, v1, v2);
+        piv[k] = best;
+        done[best] = 1;
+        const double *prow = LU + best * r;
+        for (int64_t i = 0; i < items; i++) {
+            if (done[i]) continue;
+            double *row = LU + i * r;
+            double l = row[k] / prow[k];
+            row[k] = l;
+            for (int j = k + 1; j < r; j++) row[j] -= l * prow[j];
+        }
+    }
+    free(done);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dominant (locally maximal volume) r x r submatrix of a tall panel.        */
+/* App. D, Algorithm alggos (stages 1-2) for the start, then the swaps of    */
+/* Algorithm algdomin, in transposed (tall) form:                            */
+/*   1. LUP of the panel gives the basis I (piv) and, for the remaining      */
+/*      items, B = P * P[I,:]^{-1} = L21 * L11^{-1} (stage 2 of alggos;      */
+/*      basis rows of B are unit rows);                                      */
+/*   2. find the entry of largest magnitude of B among non-basis items; if   */
+/*      it is at most 1 + delta stop (the paper stops at 1; a threshold a    */
+/*      little above 1 guards against rounding, App. D, before GE96);        */
+/*   3. otherwise item i enters the basis in slot j (the paper's "swap"),    */
+/*      which multiplies |det P[I,:]| by |B[i][j]|, and B is updated by the  */
+/*      rank-one formula B -= B[:,j] (B[i,:] - e_j^T) / B[i][j] that follows */
+/*      from the Sherman-Morrison identity; go to 2.                         */
+/* Reading of the garbled stage 3 of alggos: "go to stage 1" is taken as     */
+/* the swap of algdomin with a rank-one update (no re-factorization), which  */
+/* matches the (n - r) r flops per iteration stated after algdomin.          */
+/* Ties in step 2: lowest item, then lowest slot.                            */
+/* Outputs: slots[j] = item in basis slot j; B_out (items x r) if non-NULL;  */
+/* trace of swaps (item, slot, B value) if non-NULL.                         */
+/* ------------------------------------------------------------------------ */
+int orc_maxvol(const double *P, int64_t items, int r, double delta, int32_t max_swaps,
+               int64_t *slots, double *B_out, int64_t *trace_idx, double *trace_val,
+               int32_t *swaps_out, int32_t *converged_out, int32_t *rank_out, double *min_margin) {
+    if (!P || !slots || r < 1 || items < r || max_swaps < 0) return ORC_EINVAL;
+    double *B = (double *)malloc(sizeof(double) * (size_t)items * (size_t)r);
+    char *inb = (char *)calloc((size_t)items, 1);
+    double *brow = (double *)malloc(sizeof(double) * (size_t)r);
+    if (!B || !inb || !brow) { free(B); free(inb); free(brow); return ORC_EINVAL; }
+    int32_t rank = r;
+    int st = orc_panel_lu(P, items, r, slots, B, &rank, min_margin);
+    if (rank_out) *rank_out = rank;
+    if (swaps_out) *swaps_out = 0;
+    if (converged_out) *converged_out = 0;
+    if (st != ORC_OK) { free(B); free(inb); free(brow); return st; }
+
+    /* L11[k][j] (j < k) is stored in the pivot row of step k. */
+    double *L11 = (double *)calloc((size_t)r * (size_t)r, sizeof(double));
+    for (int k = 0; k < r; k++)
+        for (int j = 0; j < k; j++) L11[k * r + j] = B[slots[k] * r + j];
+    for (int k = 0; k < r; k++) inb[slots[k]] = 1;
+    /* B_i = l_i L11^{-1}: solve x L11 = l_i from the last entry backwards. */
+    for (int64_t i = 0; i < items; i++) {
+        if (inb[i]) continue;
+        double *x = B + i * r;
+        for (int j = r - 1; j >= 0; j--) {
+            double s = x[j];
+            for (int k = j + 1; k < r; k++) s -= x[k] * L11[k * r + j];
+            x[j] = s;
+        }
+    }
+    for (int k = 0; k < r; k++) {
+        double *x = B + slots[k] * r;
+        for (int j = 0; j < r; j++) x[j] = (j == k) ? 1.0 : 0.0;
+    }
+    free(L11);
+
+    int32_t swaps = 0, conv = 0;
+    const double thr = 1.0 + delta;
+    for (;;) {
+        int64_t bi = -1;
+        int bj = -1;
+        double v1 = -1.0, v2 = -1.0;
+        for (int64_t i = 0; i < items; i++) {
+            if (inb[i]) continue;
+            for (int j = 0; j < r; j++) {
+                double a = fabs(B[i * r + j]);
+                if (a > v1) { v2 = v1; v1 = a; bi = i; bj = j; }
+                else if (a > v2) v2 = a;
+            }
+        }
+        if (bi < 0) { conv = 1; break; } /* items == r: nothing to swap */
+        if (min_margin) {
+            double g = fabs(v1 - thr) / thr;
+            if (g < *min_margin) *min_margin = g;
+        }
+        if (v1 <= thr) { conv = 1; break; }
+        if (swaps >= max_swaps) { conv = 0; break; }
+        orc_note_margin(min_margin, v1, v2);
+        double pv = B[bi * r + bj];
+        if (trace_idx) { trace_idx[2 * swaps] = bi; trace_idx[2 * swaps + 1] = bj; }
+        if (trace_val) trace_val[swaps] = pv;
+        memcpy(brow, B + bi * r, sizeof(double) * (size_t)r);
+        brow[bj] -= 1.0; /* B[i,:] - e_j^T */
+        for (int64_t i = 0; i < items; i++) {
+            if (i == bi) continue;
+            double f = B[i * r + bj] / pv;
+            if (f == 0.0) continue;
+            for (int j = 0; j < r; j++) B[i * r + j] -= f * brow[j];
+        }
+        for (int j = 0; j < r; j++) B[bi * r + j] = (j == bj) ? 1.0 : 0.0;
+        inb[slots[bj]] = 0;
+        inb[bi] = 1;
+        slots[bj] = bi;
+        swaps++;
+    }
+    if (B_out) memcpy(B_out, B, sizeof(double) * (size_t)items * (size_t)r);
+    if (swaps_out) *swaps_out = swaps;
+    if (converged_out) *converged_out = conv;
+    free(B); free(inb); free(brow);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Abridged SRHT sketch (App. B).  H_{N,d} is the recursion (eqrfd) stopped  */
+/* at depth d with H_s = I_s, N = 2^d s, i.e. the Kronecker product          */
+/* H_{2^d} (x) I_s: entry (a s + e, b s + e') is (-1)^{popcount(a & b)} if   */
+/* e = e' and 0 otherwise (the printed H_{n,1}, H_{n,2} are the cases d=1,2). */
+/* The multiplier is D H_{N,d} with l of its N columns sampled uniformly     */
+/* without replacement (the random permutation P is absorbed by the uniform */
+/* sampling) and scaled by sqrt(N/l); the factor 2^{-d/2} makes H_{N,d}      */
+/* orthogonal.  Inputs with a dimension that is not a multiple of 2^d are    */
+/* zero-padded to N.                                                         */
+/*   side 0 (post-multiplication, m <= n):  Y = W M_S, items = rows of W;    */
+/*   side 1 (pre-multiplication, m > n, Section 11 remark on m > n):         */
+/*          Y = M_S^T W, items = columns of W.                               */
+/* Output Y is items x l row-major; samples[q] is the q-th sampled column.   */
+/* ------------------------------------------------------------------------ */
+int orc_sketch(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int side, int d, int l,
+               uint64_t seed, double *Y, int64_t *samples) {
+    if (!A || !Y || !samples || d < 0 || d > 20 || l < 1 || m < 1 || n < 1 || lda < n) return ORC_EINVAL;
+    int64_t dim = side ? m : n;      /* the dimension the multiplier acts on */
+    int64_t items = side ? n : m;
+    int64_t q2 = (int64_t)1 << d;
+    int64_t s = (dim + q2 - 1) / q2;
+    int64_t N = q2 * s;
+    if (l > N) return ORC_EINVAL;
+    int st = orc_draw_distinct(seed, 2, N, l, samples);
+    if (st) return st;
+    double scale = pow(2.0, -0.5 * d) * sqrt((double)N / (double)l);
+    for (int64_t it = 0; it < items; it++) {
+        for (int q = 0; q < l; q++) {
+            int64_t t = samples[q];
+            int64_t b = t / s, e = t % s;
+            double acc = 0.0;
+            for (int64_t a = 0; a < q2; a++) {
+                int64_t c = a * s + e;
+                if (c >= dim) continue;
+                double h = (__builtin_popcountll((uint64_t)(a & b)) & 1) ? -1.0 : 1.0;
+                double w = side ? orc_get(A, dtype, lda, c, it) : orc_get(A, dtype, lda, it, c);
+                acc += w * orc_sign(seed, c) * h;
+            }
+            Y[it * l + q] = scale * acc;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Greedy expansion by Householder reflections (App. D, Algorithm alg1tor):  */
+/* the columns of a w x items matrix Z (stored item-major: item it is the    */
+/* w-vector Z[it*w .. it*w+w-1]) are chosen one at a time.  At step g the   */
+/* chosen item is the unchosen one whose coordinates g..w-1 have the largest */
+/* 2-norm (recomputed from the current vectors, not downdated; ties to the  */
+/* lowest item); a Householder reflection acting on coordinates g..w-1 then  */
+/* maps that part of the chosen vector onto a multiple of e_1 and is applied */
+/* to every unchosen vector.  This is greedy QR with column pivoting; the    */
+/* paper uses it (or GE96) at stage 2 of Algorithm algrhtcur to pick rows of */
+/* the sketch.  Z is modified in place.                                      */
+/* ------------------------------------------------------------------------ */
+int orc_qrp(double *Z, int64_t items, int w, int k, int64_t *piv, int32_t *rank, double *min_margin) {
+    if (!Z || !piv || w < 1 || k < 1 || k > w || items < k) return ORC_EINVAL;
+    char *used = (char *)calloc((size_t)items, 1);
+    double *v = (double *)malloc(sizeof(double) * (size_t)w);
+    if (!used || !v) { free(used); free(v); return ORC_EINVAL; }
+    int st = ORC_OK;
+    if (rank) *rank = k;
+    for (int g = 0; g < k; g++) {
+        int64_t best = -1;
+        double v1 = -1.0, v2 = -1.0;
+        for (int64_t it = 0; it < items; it++) {
+            if (used[it]) continue;
+            const double *z = Z + it * w;
+            double s = 0.0;
+            for (int c = g; c < w; c++) s += z[c] * z[c];
+            if (s > v1) { v2 = v1; v1 = s; best = it; }
+            else if (s > v2) v2 = s;
+        }
+        if (v1 <= 0.0) { st = ORC_ESINGULAR; if (rank) *rank = g; break; }
+        orc_note_margin(min_margin, v1, v2);
+        piv[g] = best;
+        used[best] = 1;
+        double *x = Z + best * w;
+        double nx = sqrt(v1);
+        double alpha = (x[g] >= 0.0) ? -nx : nx;
+        int len = w - g;
+        for (int c = 0; c < len; c++) v[c] = x[g + c];
+        v[0] -= alpha;
+        double vtv = 0.0;
+        for (int c = 0; c < len; c++) vtv += v[c] * v[c];
+        if (vtv > 0.0) {
+            for (int64_t it = 0; it < items; it++) {
+                if (used[it]) continue;
+                double *z = Z + it * w;
+                double s = 0.0;
+                for (int c = 0; c < len; c++) s += v[c] * z[g + c];
+                double f = 2.0 * s / vtv;
+                for (int c = 0; c < len; c++) z[g + c] -= f * v[c];
+            }
+        }
+        x[g] = alpha;
+        for (int c = g + 1; c < w; c++) x[c] = 0.0;
+    }
+    free(used); free(v);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nucleus U = G^{-1} of an r x r generator (Section 3, Algorithm algcnnncl  */
+/* with k = l = r, where the truncated pseudo-inverse is the inverse,        */
+/* Remark reklr_kl).  Gauss-Jordan style: LU with partial pivoting (ties to  */
+/* the lowest row) then r triangular solves for the unit vectors.  Optional  */
+/* iterative refinement X <- X + X (I - G X).  log|det G| is returned.       */
+/* ------------------------------------------------------------------------ */
+int orc_inverse(const double *G, int r, double *U, int refine_steps, double *logdet) {
+    if (!G || !U || r < 1) return ORC_EINVAL;
+    double *LU = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+    int *p = (int *)malloc(sizeof(int) * (size_t)r);
+    double *col = (double *)malloc(sizeof(double) * (size_t)r);
+    memcpy(LU, G, sizeof(double) * (size_t)r * (size_t)r);
+    for (int i = 0; i < r; i++) p[i] = i;
+    double ld = 0.0;
+    int st = ORC_OK;
+    for (int k = 0; k < r; k++) {
+        int best = k;
+        double bv = fabs(LU[p[k] * r + k]);
+        for (int i = k + 1; i < r; i++) {
+            double a = fabs(LU[p[i] * r + k]);
+            if (a > bv || (a == bv && p[i] < p[best])) { bv = a; best = i; }
+        }
+        if (bv == 0.0) { st = ORC_ESINGULAR; break; }
+        int t = p[k]; p[k] = p[best]; p[best] = t;
+        double pk = LU[p[k] * r + k];
+        ld += log(fabs(pk));
+        for (int i = k + 1; i < r; i++) {
+            double l = LU[p[i] * r + k] / pk;
+            LU[p[i] * r + k] = l;
+            for (int j = k + 1; j < r; j++) LU[p[i] * r + j] -= l * LU[p[k] * r + j];
+        }
+    }
+    if (st == ORC_OK) {
+        /* solve G x = e_c for every column c: L y = P e_c, U x = y */
+        for (int c = 0; c < r; c++) {
+            for (int i = 0; i < r; i++) {
+                double s = (p[i] == c) ? 1.0 : 0.0;
+                for (int j = 0; j < i; j++) s -= LU[p[i] * r + j] * col[j];
+                col[i] = s;
+            }
+            for (int i = r - 1; i >= 0; i--) {
+                double s = col[i];
+                for (int j = i + 1; j < r; j++) s -= LU[p[i] * r + j] * col[j];
+                col[i] = s / LU[p[i] * r + i];
+            }
+            for (int i = 0; i < r; i++) U[i * r + c] = col[i];
+        }
+        for (int it = 0; it < refine_steps; it++) {
+            double *T = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+            double *X2 = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+            for (int i = 0; i < r; i++)       /* T = I - G X */
+                for (int j = 0; j < r; j++) {
+                    double s = (i == j) ? 1.0 : 0.0;
+                    for (int q = 0; q < r; q++) s -= G[i * r + q] * U[q * r + j];
+                    T[i * r + j] = s;
+                }
+            for (int i = 0; i < r; i++)       /* X + X T */
+                for (int j = 0; j < r; j++) {
+                    double s = U[i * r + j];
+                    for (int q = 0; q < r; q++) s += U[i * r + q] * T[q * r + j];
+                    X2[i * r + j] = s;
+                }
+            memcpy(U, X2, sizeof(double) * (size_t)r * (size_t)r);
+            free(T); free(X2);
+        }
+    }
+    if (logdet) *logdet = ld;
+    free(LU); free(p); free(col);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* C-A CUR driver (Section 1.3 and Fig. 4: alternating vertical m x r and    */
+/* horizontal r x n sketches; Section 13, Tests 2: random initial set, a few */
+/* C-A loops, nucleus U = W_{I,J}^{-1}, W' = C U R as in eq. (eqtsts1)).     */
+/*   column step: C = W[:, J] (J ascending), I = dominant rows of C;         */
+/*   row step:    R = W[I, :] (I ascending), J = dominant columns of R.      */
+/* One sweep is a column step followed by a row step; the loop stops early   */
+/* once a sweep reproduces the previous sweep's sets (a fixed point, after   */
+/* which further sweeps change nothing).  With pre-processing the start set  */
+/* comes from greedy QRP on the abridged-SRHT sketch (Algorithm algrhtcur,   */
+/* stage 2, with C-A replacing stage 3 as its remark rerfnhmt suggests):     */
+/* post-multiplication yields rows I0 and one row step turns them into J0;   */
+/* pre-multiplication yields J0 directly.                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double delta;
+    int32_t max_swaps;
+    int32_t preprocess;   /* 0 none, 1 abridged SRHT */
+    int32_t ah_depth;
+    int32_t ah_samples;
+    int32_t refine_steps;
+    const int64_t *init_cols; /* optional r start columns */
+} orc_opts;
+
+typedef struct {
+    int32_t sweeps_run, swaps_total, converged, rank_found;
+    double min_margin, det_log_abs;
+} orc_info;
+
+static int orc_step(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, int rows,
+                    const int64_t *set_in, const orc_opts *o, int64_t *set_out, orc_info *info) {
+    /* rows = 1: column step (panel = W[:, set_in], items = rows of W);
+       rows = 0: row step    (panel = W[set_in, :]^T, items = columns of W). */
+    int64_t items = rows ? m : n;
+    double *P = (double *)malloc(sizeof(double) * (size_t)items * (size_t)r);
+    if (!P) return ORC_EINVAL;
+    for (int64_t it = 0; it < items; it++)
+        for (int j = 0; j < r; j++)
+            P[it * r + j] = rows ? orc_get(A, dtype, lda, it, set_in[j]) : orc_get(A, dtype, lda, set_in[j], it);
+    int32_t sw = 0, conv = 0, rk = r;
+    int st = orc_maxvol(P, items, r, o->delta, o->max_swaps, set_out, NULL, NULL, NULL, &sw, &conv, &rk,
+                        &info->min_margin);
+    free(P);
+    info->swaps_total += sw;
+    if (st == ORC_ESINGULAR) info->rank_found = rk;
+    if (st == ORC_OK && !conv) info->converged = 0;
+    if (st == ORC_OK) qsort(set_out, (size_t)r, sizeof(int64_t), cmp_i64);
+    return st;
+}
+
+void orc_default_opts(orc_opts *o) {
+    o->delta = 0.01;
+    o->max_swaps = -1; /* -1: 16 r */
+    o->preprocess = 0;
+    o->ah_depth = 3;
+    o->ah_samples = 0; /* 0: 2 r */
+    o->refine_steps = 0;
+    o->init_cols = NULL;
+}
+
+static int orc_finite_scan(const void *A, int dtype, int64_t lda, int64_t rows0, int64_t nrows,
+                           int64_t cols0, int64_t ncols) {
+    for (int64_t i = rows0; i < rows0 + nrows; i++)
+        for (int64_t j = cols0; j < cols0 + ncols; j++)
+            if (!isfinite(orc_get(A, dtype, lda, i, j))) return 0;
+    return 1;
+}
+
+int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, int sweeps, uint64_t seed,
+               const orc_opts *opts_in, int64_t *I_out, int64_t *J_out, double *U_out, orc_info *info_out) {
+    orc_opts o;
+    if (opts_in) o = *opts_in; else orc_default_opts(&o);
+    if (o.max_swaps < 0) o.max_swaps = 16 * r;
+    if (o.ah_samples <= 0) o.ah_samples = 2 * r;
+    orc_info info = {0, 0, 1, 0, 1.0, 0.0};
+    info.rank_found = r;
+    if (!A || !I_out || !J_out || !U_out || r < 1 || sweeps < 1 || m < 1 || n < 1 || lda < n ||
+        (int64_t)r > (m < n ? m : n) || dtype < 0 || dtype > 2 || !(o.delta >= 0.0) ||
+        (o.preprocess != 0 && o.preprocess != 1)) {
+        if (info_out) *info_out = info;
+        return ORC_EINVAL;
+    }
+    int64_t *I = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
+    int64_t *J = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
+    int64_t *Ip = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
+    int64_t *Jp = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
+    int st = ORC_OK;
+
+    if (o.preprocess == 1) {
+        int side = (m > n) ? 1 : 0;
+        int64_t items = side ? n : m;
+        int l = o.ah_samples;
+        if (l < r) { st = ORC_EINVAL; goto done; }
+        double *Y = (double *)malloc(sizeof(double) * (size_t)items * (size_t)l);
+        int64_t *smp = (int64_t *)malloc(sizeof(int64_t) * (size_t)l);
+        st = orc_sketch(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp);
+        int32_t rk = r;
+        if (st == ORC_OK) {
+            for (int64_t q = 0; q < items * l; q++)
+                if (!isfinite(Y[q])) { st = ORC_EINVAL; break; }
+        }
+        if (st == ORC_OK) st = orc_qrp(Y, items, l, r, side ? J : I, &rk, &info.min_margin);
+        if (st == ORC_ESINGULAR) info.rank_found = rk;
+        free(Y); free(smp);
+        if (st) goto done;
+        if (!side) {
+            qsort(I, (size_t)r, sizeof(int64_t), cmp_i64);
+            for (int a = 0; a < r; a++)
+                if (!orc_finite_scan(A, dtype, lda, I[a], 1, 0, n)) { st = ORC_EINVAL; goto done; }
+            st = orc_step(A, dtype, m, n, lda, r, 0, I, &o, J, &info);
+            if (st) goto done;
+        } else {
+            qsort(J, (size_t)r, sizeof(int64_t), cmp_i64);
+        }
+    } else if (o.init_cols) {
+        for (int a = 0; a < r; a++) {
+            if (o.init_cols[a] < 0 || o.init_cols[a] >= n) { st = ORC_EINVAL; goto done; }
+            for (int b = 0; b < a; b++)
+                if (o.init_cols[b] == o.init_cols[a]) { st = ORC_EINVAL; goto done; }
+            J[a] = o.init_cols[a];
+        }
+        qsort(J, (size_t)r, sizeof(int64_t), cmp_i64);
+    } else {
+        orc_draw_distinct(seed, 0, n, r, J);
+        qsort(J, (size_t)r, sizeof(int64_t), cmp_i64);
+    }
+
+    for (int s = 0; s < sweeps; s++) {
+        for (int a = 0; a < r; a++)
+            if (!orc_finite_scan(A, dtype, lda, 0, m, J[a], 1)) { st = ORC_EINVAL; goto done; }
+        st = orc_step(A, dtype, m, n, lda, r, 1, J, &o, I, &info);
+        if (st) goto done;
+        for (int a = 0; a < r; a++)
+            if (!orc_finite_scan(A, dtype, lda, I[a], 1, 0, n)) { st = ORC_EINVAL; goto done; }
+        st = orc_step(A, dtype, m, n, lda, r, 0, I, &o, J, &info);
+        if (st) goto done;
+        info.sweeps_run = s + 1;
+        if (s > 0 && !memcmp(I, Ip, sizeof(int64_t) * (size_t)r) && !memcmp(J, Jp, sizeof(int64_t) * (size_t)r))
+            break;
+        memcpy(Ip, I, sizeof(int64_t) * (size_t)r);
+        memcpy(Jp, J, sizeof(int64_t) * (size_t)r);
+    }
+
+    {
+        double *G = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+        for (int a = 0; a < r; a++)
+            for (int b = 0; b < r; b++) G[a * r + b] = orc_get(A, dtype, lda, I[a], J[b]);
+        st = orc_inverse(G, r, U_out, o.refine_steps, &info.det_log_abs);
+        free(G);
+        if (st == ORC_ESINGULAR) info.rank_found = r - 1;
+    }
+    memcpy(I_out, I, sizeof(int64_t) * (size_t)r);
+    memcpy(J_out, J, sizeof(int64_t) * (size_t)r);
+done:
+    free(I); free(J); free(Ip); free(Jp);
+    if (st != ORC_OK) info.converged = 0;
+    if (info_out) *info_out = info;
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relative Frobenius error ||W - C U R||_F / ||W||_F of a CUR LRA with      */
+/* C = W[:, J], R = W[I, :] and U (r x r, J-order x I-order), eq. (eqcur0).  */
+/* Plain triple loop; out_err2 / out_norm2 receive the two squared sums.     */
+/* ------------------------------------------------------------------------ */
+int orc_residual(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,
+                 const int64_t *J, const double *U, double *out_err2, double *out_norm2) {
+    if (!A || !I || !J || !U || r < 1 || m < 1 || n < 1 || lda < n) return ORC_EINVAL;
+    /* UR = U * W[I,:]  (r x n) */
+    double *UR = (double *)calloc((size_t)r * (size_t)n, sizeof(double));
+    for (int a = 0; a < r; a++)
+        for (int b = 0; b < r; b++) {
+            double u = U[a * r + b];
+            for (int64_t j = 0; j < n; j++) UR[a * n + j] += u * orc_get(A, dtype, lda, I[b], j);
+        }
+    double e2 = 0.0, w2 = 0.0;
+    double *c = (double *)malloc(sizeof(double) * (size_t)r);
+    for (int64_t i = 0; i < m; i++) {
+        for (int a = 0; a < r; a++) c[a] = orc_get(A, dtype, lda, i, J[a]);
+        for (int64_t j = 0; j < n; j++) {
+            double x = 0.0;
+            for (int a = 0; a < r; a++) x += c[a] * UR[a * n + j];
+            double w = orc_get(A, dtype, lda, i, j);
+            e2 += (w - x) * (w - x);
+            w2 += w * w;
+        }
+    }
+    free(UR); free(c);
+    if (out_err2) *out_err2 = e2;
+    if (out_norm2) *out_norm2 = w2;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Loss and gradients of the CUR reconstruction at fixed index sets (plain   */
+/* calculus; the paper has no adjoint):                                      */
+/*   L(C, R, G) = sum_{(i,j) in Omega} (a_ij - (C G^{-1} R)_ij)^2.           */
+/* With Z = G^{-1} R and Ebar = -2 (a - C Z) on Omega:                       */
+/*   dC = Ebar Z^T,  dZ = C^T Ebar,  dR = G^{-T} dZ,  dG = -G^{-T} dZ Z^T.   */
+/* C is m x r, R is r x n, G is r x r, all FP64 row-major; Omega is COO.     */
+/* ------------------------------------------------------------------------ */
+int orc_cur_adjoint(const double *C, const double *R, const double *G, int64_t m, int64_t n, int r,
+                    const int64_t *oi, const int64_t *oj, const double *aval, int64_t nnz,
+                    double *loss, double *dC, double *dR, double *dG) {
+    if (!C || !R || !G || r < 1 || m < 1 || n < 1 || nnz < 0) return ORC_EINVAL;
+    double *Gi = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+    int st = orc_inverse(G, r, Gi, 0, NULL);
+    if (st) { free(Gi); return st; }
+    double *Z = (double *)calloc((size_t)r * (size_t)n, sizeof(double));
+    double *dZ = (double *)calloc((size_t)r * (size_t)n, sizeof(double));
+    for (int a = 0; a < r; a++)
+        for (int b = 0; b < r; b++)
+            for (int64_t j = 0; j < n; j++) Z[a * n + j] += Gi[a * r + b] * R[b * n + j];
+    if (dC) memset(dC, 0, sizeof(double) * (size_t)m * (size_t)r);
+    double L = 0.0;
+    for (int64_t q = 0; q < nnz; q++) {
+        int64_t i = oi[q], j = oj[q];
+        if (i < 0 || i >= m || j < 0 || j >= n) { st = ORC_EINVAL; break; }
+        double x = 0.0;
+        for (int a = 0; a < r; a++) x += C[i * r + a] * Z[a * n + j];
+        double e = aval[q] - x;
+        L += e * e;
+        double eb = -2.0 * e;
+        for (int a = 0; a < r; a++) {
+            if (dC) dC[i * r + a] += eb * Z[a * n + j];
+            dZ[a * n + j] += eb * C[i * r + a];
+        }
+    }
+    if (st == ORC_OK) {
+        if (loss) *loss = L;
+        if (dR) {
+            for (int a = 0; a < r; a++)
+                for (int64_t j = 0; j < n; j++) {
+                    double s = 0.0;
+                    for (int b = 0; b < r; b++) s += Gi[b * r + a] * dZ[b * n + j];
+                    dR[a * n + j] = s;
+                }
+        }
+        if (dG) {
+            /* T = dZ Z^T (r x r), dG = -Gi^T T */
+            double *T = (double *)calloc((size_t)r * (size_t)r, sizeof(double));
+            for (int a = 0; a < r; a++)
+                for (int b = 0; b < r; b++) {
+                    double s = 0.0;
+                    for (int64_t j = 0; j < n; j++) s += dZ[a * n + j] * Z[b * n + j];
+                    T[a * r + b] = s;
+                }
+            for (int a = 0; a < r; a++)
+                for (int b = 0; b < r; b++) {
+                    double s = 0.0;
+                    for (int c = 0; c < r; c++) s += Gi[c * r + a] * T[c * r + b];
+                    dG[a * r + b] = -s;
+                }
+            free(T);
+        }
+    }
+    free(Gi); free(Z); free(dZ);
+    return st;
+}

@@ -1,0 +1,114 @@
+"""Seeded synthetic inputs for the C-A CUR path.
+
+This module only *makes inputs*: it holds none of the method's arithmetic and
+is shared by the tests, the benchmark and the smoke check, so that the GPU
+library and the CPU oracle always see identical matrices.  Every generator is
+a pure function of its seeds (NumPy ``default_rng``), so the same call gives
+the same bytes on any machine.
+
+Workloads (shapes and value distributions of the paper's experiments, which
+used factor-Gaussian matrices plus small Gaussian noise, and FMM far-field
+blocks; see the experiments section and the FMM section of the paper):
+
+* ``orthogonal_lowrank``  A = U diag(sigma) V^T + noise, U, V from QR of
+  Gaussian matrices (512 x 512, rank 10, sigma_i = 2^-i, noise std 1e-10).
+* ``factor_gaussian``     A = X Y / ||X Y||_F + noise (20000 x 20000, rank 50,
+  noise std 1e-6), the perturbed factor-Gaussian family of the experiments.
+* ``fmm_blocks``          off-diagonal interaction blocks 1/|x - y| between
+  well separated 2-D point clusters.
+* ``decaying_spectrum``   tall matrix with 64 unit singular values followed by
+  an i^-2 decay floored at 1e-7.
+
+The noise parameter is a standard deviation.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def orthogonal_lowrank(m: int = 512, n: int = 512, r: int = 10, noise: float = 1e-10,
+                       seeds=(1001, 1002, 1003), sigma=None, dtype=np.float64) -> np.ndarray:
+    """U diag(sigma) V^T + noise * N(0,1); sigma defaults to 2^-i, i = 0..r-1."""
+    U, _ = np.linalg.qr(np.random.default_rng(seeds[0]).standard_normal((m, r)))
+    V, _ = np.linalg.qr(np.random.default_rng(seeds[1]).standard_normal((n, r)))
+    if sigma is None:
+        sigma = 2.0 ** -np.arange(r)
+    A = (U * np.asarray(sigma, np.float64)) @ V.T
+    if noise:
+        A = A + noise * np.random.default_rng(seeds[2]).standard_normal((m, n))
+    return np.ascontiguousarray(A.astype(dtype))
+
+
+def factor_gaussian(m: int, n: int, r: int, noise: float, seeds=(1011, 1012, 1013),
+                    dtype=np.float32, chunk_rows: int = 2048) -> np.ndarray:
+    """X Y scaled to unit Frobenius norm, plus i.i.d. N(0, noise^2), rows made in chunks."""
+    X = np.random.default_rng(seeds[0]).standard_normal((m, r))
+    Y = np.random.default_rng(seeds[1]).standard_normal((r, n))
+    # ||X Y||_F^2 = trace(X^T X Y Y^T)
+    fro = float(np.sqrt(np.trace((X.T @ X) @ (Y @ Y.T))))
+    g = np.random.default_rng(seeds[2])
+    A = np.empty((m, n), dtype)
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        blk = (X[r0:r1] @ Y) / fro
+        if noise:
+            blk += noise * g.standard_normal((r1 - r0, n))
+        A[r0:r1] = blk.astype(dtype)
+    return A
+
+
+def fmm_block_shapes(count: int, lo: int = 64, hi: int = 1024, seed: int = 1021):
+    """Independent uniform row / column counts in [lo, hi] for each block."""
+    g = np.random.default_rng(seed)
+    ms = g.integers(lo, hi + 1, size=count)
+    ns = g.integers(lo, hi + 1, size=count)
+    return ms.astype(np.int64), ns.astype(np.int64)
+
+
+def fmm_block(m: int, n: int, seed: int, dtype=np.float32) -> np.ndarray:
+    """K_ij = 1/|x_i - y_j| for x uniform in [0,1]^2 and y uniform in the unit
+    box [1+g, 2+g] x [0,1], g ~ U[2,3] (separation at least two box widths)."""
+    gen = np.random.default_rng(seed)
+    gap = gen.uniform(2.0, 3.0)
+    x = gen.uniform(0.0, 1.0, size=(m, 2))
+    y = gen.uniform(0.0, 1.0, size=(n, 2))
+    y[:, 0] += 1.0 + gap
+    d = np.sqrt(((x[:, None, :] - y[None, :, :]) ** 2).sum(-1))
+    return (1.0 / d).astype(dtype)
+
+
+def fmm_batch(count: int, shape_seed: int = 1021, block_seed0: int = 1022000, align_elems: int = 64,
+              dtype=np.float32):
+    """All blocks stored row-major one after another in one flat buffer.
+
+    Returns (flat buffer, descriptors int64[count, 4] = (offset, m, n, lda)).
+    Each block starts at a multiple of ``align_elems`` elements (256 B for FP32).
+    """
+    ms, ns = fmm_block_shapes(count, seed=shape_seed)
+    desc = np.zeros((count, 4), np.int64)
+    off = 0
+    for b in range(count):
+        desc[b] = (off, ms[b], ns[b], ns[b])
+        off += int(ms[b] * ns[b])
+        off = (off + align_elems - 1) // align_elems * align_elems
+    flat = np.zeros(off, dtype)
+    for b in range(count):
+        o, m, n, _ = desc[b]
+        flat[o:o + m * n] = fmm_block(int(m), int(n), block_seed0 + b, dtype).ravel()
+    return flat, desc
+
+
+def decaying_spectrum_sigma(n: int, lead: int = 64, floor: float = 1e-7) -> np.ndarray:
+    """sigma_i = 1 for i <= lead, max(i^-2, floor) after (1-based i)."""
+    i = np.arange(1, n + 1, dtype=np.float64)
+    s = np.maximum(i ** -2.0, floor)
+    s[:lead] = 1.0
+    return s
+
+
+def sample_omega(m: int, n: int, count: int, seed: int):
+    """`count` distinct entries drawn uniformly, returned as (rows, cols) sorted by row then column."""
+    g = np.random.default_rng(seed)
+    flat = g.choice(m * n, size=count, replace=False)
+    flat.sort()
+    return (flat // n).astype(np.int64), (flat % n).astype(np.int64)
