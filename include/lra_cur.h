@@ -1,0 +1,122 @@
+/*
+ * lra_cur.h -- C ABI of the MI355X (gfx950) cross-approximation CUR library.
+ *
+ * The library computes CUR low-rank approximations W' = C U R of an m x n
+ * matrix W, with C = W[:, J] (r columns), R = W[I, :] (r rows) and the r x r
+ * nucleus U = W[I, J]^{-1}, by cross-approximation (C-A) iterations:
+ * alternating maxvol searches on the gathered m x r column panel and the
+ * r x n row panel (Pan, Luan, Svadlenka, Zhao, "Superfast Accurate Low Rank
+ * Approximation": CUR definition eq. (eqcur0), C-A loops in Section 1.3 and
+ * Fig. 4, Tests 2 and eq. (eqtsts1) in Section 13, the dominant-submatrix
+ * search of Algorithms alggos and algdomin in Appendix D, the canonical
+ * nucleus of Algorithm algcnnncl in Section 3, and the abridged randomized
+ * Hadamard pre-processing of Section 11 and Appendix B).
+ *
+ * Conventions shared by every entry point
+ *   - W is dense, row-major, element (i, j) at W[i * lda + j], lda >= n, and
+ *     resides in device memory of the current HIP device.
+ *   - Index sets are 0-based int64 and are returned sorted ascending.
+ *   - U is returned row-major r x r with rows ordered like J and columns
+ *     ordered like I, so that W' = W[:, J] * U * W[I, :].
+ *   - All device pointers are owned by the caller.  The library keeps a small
+ *     cached workspace per (device, stream); lra_release() frees it.
+ *   - Calls are asynchronous on `stream`.  The return value reports argument
+ *     and launch errors only.  Failures found while computing (a rank
+ *     deficient panel, a non-finite entry read) are written to the `status`
+ *     field of the optional device-resident lra_info.
+ *   - Results are deterministic for a given input, seed, options and device.
+ *   - Calls that share a (device, stream) workspace are ordered by the stream;
+ *     calls on different streams use different workspaces.
+ */
+#ifndef LRA_CUR_H
+#define LRA_CUR_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LRA_OK = 0,
+    LRA_EINVAL = 1,       /* bad argument, or a non-finite entry in a panel read */
+    LRA_ESINGULAR = 2,    /* a gathered panel (or the sketch) has rank < r */
+    LRA_EDEVICE = 3,      /* HIP runtime error */
+    LRA_ENOMEM = 4,       /* workspace allocation failed */
+    LRA_EUNSUPPORTED = 5  /* shape does not fit the on-chip panel layout */
+} lra_status;
+
+typedef enum { LRA_F64 = 0, LRA_F32 = 1, LRA_BF16 = 2 } lra_dtype;
+
+typedef enum {
+    LRA_PRE_NONE = 0,  /* random initial column set (seeded) */
+    LRA_PRE_ASRHT = 1  /* start set from greedy QRP on an abridged SRHT sketch */
+} lra_pre;
+
+typedef struct {
+    double delta;          /* maxvol stops when every |B_ij| <= 1 + delta; default 0.01 */
+    int32_t max_swaps;     /* swap cap per maxvol search; < 0 selects 16 r (default) */
+    int32_t preprocess;    /* lra_pre; default LRA_PRE_NONE */
+    int32_t ah_depth;      /* abridged Hadamard recursion depth d; default 3 */
+    int32_t ah_samples;    /* sampled multiplier columns l (r <= l <= 256); <= 0 selects 2 r */
+    int32_t refine_steps;  /* iterative refinement steps of the nucleus inverse; default 0 */
+    int32_t team_size;     /* workgroups cooperating on one LRA; <= 0 chooses automatically */
+    const int64_t *init_cols; /* optional HOST array of r distinct start columns (warm start) */
+} lra_opts;
+
+typedef struct {
+    int32_t status;        /* lra_status of the device computation */
+    int32_t sweeps_run;    /* sweeps executed (stops early at a fixed point) */
+    int32_t swaps_total;   /* maxvol swaps over all steps */
+    int32_t converged;     /* 1 if every maxvol search met the 1 + delta rule */
+    int32_t rank_found;    /* r, or the rank of the first rank-deficient panel */
+    int32_t team_size;     /* workgroups used */
+    double det_log_abs;    /* log |det W[I, J]| of the final generator */
+} lra_info;
+
+/* Fill *o with the defaults listed above. */
+void lra_default_opts(lra_opts *o);
+
+/* C-A CUR of one matrix.
+ *   W       device, dtype `dt`, m x n with leading dimension lda.
+ *   r       target rank, 1 <= r <= min(m, n, 64).
+ *   sweeps  number of C-A loops (column step, then row step), >= 1.
+ *   seed    seeds the SplitMix64 draws (initial columns, SRHT signs and samples).
+ *   opts    NULL for defaults.
+ *   I_out, J_out   device int64[r]; U_out device double[r * r];
+ *   info    device lra_info or NULL.
+ * Panels live in on-chip memory: every cooperating workgroup holds
+ * ceil(max(m, n) / team) items of max(r, l) doubles; shapes that do not fit
+ * return LRA_EUNSUPPORTED. */
+lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
+                   int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
+                   double *U_out, lra_info *info, hipStream_t stream);
+
+/* One block of a batch: the block starts `offset` elements after `base`. */
+typedef struct {
+    int64_t offset, m, n, lda;
+} lra_block;
+
+/* C-A CUR of many independent blocks in one persistent launch (one workgroup
+ * per block, blocks taken from a device work queue largest first).  Block b
+ * uses seed + b.  `blocks` is a HOST array of `count` descriptors; outputs
+ * are packed: I_out/J_out int64[count * r], U_out double[count * r * r],
+ * infos lra_info[count] (device, may be NULL).  opts->preprocess and
+ * opts->init_cols are not supported here (LRA_EINVAL). */
+lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
+                           int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
+                           double *U_out, lra_info *infos, hipStream_t stream);
+
+/* Free every cached workspace of the calling process. */
+void lra_release(void);
+
+/* Static description of a status code. */
+const char *lra_strerror(lra_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRA_CUR_H */

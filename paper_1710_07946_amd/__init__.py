@@ -1,0 +1,229 @@
+"""Python binding of the MI355X cross-approximation CUR library.
+
+The functions here carry the names of the C ABI in ``include/lra_cur.h`` and
+only marshal arguments: PyTorch supplies device memory and the current HIP
+stream, and every step of the computation runs in the library's HIP kernels
+(``_build/liblra_cur.so``, built by ``build.py``).  There is no fallback: if
+the library is missing or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+LIB_PATH = os.path.join(HERE, "_build", "liblra_cur.so")
+HEADER = os.path.join(ROOT, "include", "lra_cur.h")
+
+LRA_OK, LRA_EINVAL, LRA_ESINGULAR, LRA_EDEVICE, LRA_ENOMEM, LRA_EUNSUPPORTED = range(6)
+LRA_F64, LRA_F32, LRA_BF16 = 0, 1, 2
+LRA_PRE_NONE, LRA_PRE_ASRHT = 0, 1
+
+
+class LraError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__("%s: %s (status %d)" % (what, lra_strerror(status), status))
+        self.status = status
+
+
+class lra_opts(ct.Structure):
+    _fields_ = [("delta", ct.c_double), ("max_swaps", ct.c_int32), ("preprocess", ct.c_int32),
+                ("ah_depth", ct.c_int32), ("ah_samples", ct.c_int32), ("refine_steps", ct.c_int32),
+                ("team_size", ct.c_int32), ("init_cols", ct.POINTER(ct.c_int64))]
+
+
+class lra_info(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("sweeps_run", ct.c_int32), ("swaps_total", ct.c_int32),
+                ("converged", ct.c_int32), ("rank_found", ct.c_int32), ("team_size", ct.c_int32),
+                ("det_log_abs", ct.c_double)]
+
+
+class lra_block(ct.Structure):
+    _fields_ = [("offset", ct.c_int64), ("m", ct.c_int64), ("n", ct.c_int64), ("lda", ct.c_int64)]
+
+
+INFO_BYTES = ct.sizeof(lra_info)
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load() -> ct.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("HIP library not built: %s (run paper_1710_07946_amd/build.py)" % LIB_PATH)
+        L = ct.CDLL(LIB_PATH)
+        P, i64, i32 = ct.c_void_p, ct.c_int64, ct.c_int32
+        L.lra_default_opts.argtypes = [ct.POINTER(lra_opts)]
+        L.lra_default_opts.restype = None
+        L.lra_strerror.argtypes = [ct.c_int]
+        L.lra_strerror.restype = ct.c_char_p
+        L.lra_release.argtypes = []
+        L.lra_release.restype = None
+        L.lra_cur.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, ct.c_uint64, ct.POINTER(lra_opts), P, P, P, P,
+                              P]
+        L.lra_cur.restype = ct.c_int
+        L.lra_cur_batched.argtypes = [P, ct.c_int, ct.POINTER(lra_block), i64, i32, i32, ct.c_uint64,
+                                      ct.POINTER(lra_opts), P, P, P, P, P]
+        L.lra_cur_batched.restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions the public header declares."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lra_[a-z_]+)\s*\(", text)))
+
+
+def lra_strerror(status: int) -> str:
+    try:
+        return load().lra_strerror(int(status)).decode()
+    except ImportError:
+        return "status %d" % status
+
+
+def lra_release() -> None:
+    load().lra_release()
+
+
+def lra_default_opts() -> lra_opts:
+    o = lra_opts()
+    load().lra_default_opts(ct.byref(o))
+    return o
+
+
+# ------------------------------------------------------------------ helpers
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return LRA_F64
+    if t.dtype == torch.float32:
+        return LRA_F32
+    if t.dtype == torch.bfloat16:
+        return LRA_BF16
+    raise TypeError("unsupported dtype %s" % t.dtype)
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _make_opts(delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps, team_size, init_cols):
+    o = lra_default_opts()
+    o.delta = delta
+    o.max_swaps = max_swaps
+    o.preprocess = preprocess
+    o.ah_depth = ah_depth
+    o.ah_samples = ah_samples
+    o.refine_steps = refine_steps
+    o.team_size = team_size
+    keep = None
+    if init_cols is not None:
+        keep = np.ascontiguousarray(init_cols, np.int64)
+        o.init_cols = keep.ctypes.data_as(ct.POINTER(ct.c_int64))
+    return o, keep
+
+
+def parse_info(raw) -> dict:
+    """Decode lra_info records from a uint8 tensor/array of INFO_BYTES each."""
+    b = np.ascontiguousarray(raw.cpu().numpy() if hasattr(raw, "cpu") else raw, np.uint8).reshape(-1, INFO_BYTES)
+    out = []
+    for row in b:
+        inf = lra_info.from_buffer_copy(row.tobytes())
+        out.append({k: getattr(inf, k) for k, _ in lra_info._fields_})
+    return out
+
+
+@dataclass
+class CurOut:
+    I: object       # device int64[r] (or [count, r])
+    J: object
+    U: object       # device float64[r, r] (or [count, r, r])
+    info_raw: object
+
+    def info(self):
+        recs = parse_info(self.info_raw)
+        return recs[0] if len(recs) == 1 else recs
+
+
+# ------------------------------------------------------------------ entry points
+def lra_cur(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
+            preprocess: int = LRA_PRE_NONE, ah_depth: int = 3, ah_samples: int = 0, refine_steps: int = 0,
+            team_size: int = 0, init_cols=None, out: CurOut | None = None, stream=None) -> CurOut:
+    """C-A CUR of a 2-D device tensor (row-major rows, unit column stride).
+
+    Asynchronous on the current (or given) stream; the returned tensors are
+    filled when the stream reaches the launch.  ``CurOut.info()`` syncs.
+    """
+    torch = _torch()
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor with unit column stride")
+    m, n = A.shape
+    dev = A.device
+    if out is None:
+        out = CurOut(torch.empty(r, dtype=torch.int64, device=dev), torch.empty(r, dtype=torch.int64, device=dev),
+                     torch.empty((r, r), dtype=torch.float64, device=dev),
+                     torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    o, keep = _make_opts(delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps, team_size, init_cols)
+    st = load().lra_cur(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, sweeps,
+                        ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
+                        ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
+                        ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
+    del keep
+    if st != LRA_OK:
+        raise LraError(st, "lra_cur")
+    return out
+
+
+def lra_cur_batched(base, blocks, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
+                    refine_steps: int = 0, out: CurOut | None = None, stream=None) -> CurOut:
+    """C-A CUR of `count` blocks stored in the flat device tensor `base`.
+
+    ``blocks`` is an int64 array of shape (count, 4): (offset, m, n, lda) in
+    elements.  Block b uses seed + b.  Asynchronous like ``lra_cur``.
+    """
+    torch = _torch()
+    if base.dim() != 1 or not base.is_cuda:
+        raise ValueError("base must be a flat device tensor")
+    desc = np.ascontiguousarray(blocks, np.int64).reshape(-1, 4)
+    count = desc.shape[0]
+    if count:
+        off, m, n, ld = desc.T
+        end = off + (m - 1) * ld + n
+        if (off < 0).any() or (m < 1).any() or (n < 1).any() or (ld < n).any() or int(end.max()) > base.numel():
+            raise ValueError("block descriptors reach outside the base tensor")
+    dev = base.device
+    if out is None:
+        out = CurOut(torch.empty((count, r), dtype=torch.int64, device=dev),
+                     torch.empty((count, r), dtype=torch.int64, device=dev),
+                     torch.empty((count, r, r), dtype=torch.float64, device=dev),
+                     torch.empty(count * INFO_BYTES, dtype=torch.uint8, device=dev))
+    arr = (lra_block * max(count, 1))()
+    ct.memmove(arr, desc.ctypes.data, desc.nbytes)
+    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, 0, None)
+    st = load().lra_cur_batched(ct.c_void_p(base.data_ptr()), _dtype_code(base), arr, count, r, sweeps,
+                                ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
+                                ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
+                                ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
+    if st != LRA_OK:
+        raise LraError(st, "lra_cur_batched")
+    return out

@@ -1,0 +1,307 @@
+// lra_api.hip -- host side of the C ABI declared in include/lra_cur.h:
+// argument validation, launch geometry (team size, LDS budget), and the
+// cached per-(device, stream) workspace.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <utility>
+#include <vector>
+
+#include "lra_internal.h"
+
+namespace {
+
+using lra::BlockDesc;
+using lra::CAConfig;
+using lra::kBlock;
+using lra::kLMax;
+using lra::kRMax;
+using lra::TeamWs;
+using lra::XchHeader;
+
+struct Workspace {
+    int device = -1;
+    unsigned *counters = nullptr;   // [0] team barrier, [1] batch queue
+    XchHeader *hdr = nullptr;       // [2][kMaxTeam]
+    double *rows = nullptr;         // [2][kMaxTeam][kLMax]
+    int64_t *init_cols = nullptr;   // [kRMax]
+    BlockDesc *blocks = nullptr;
+    int32_t *order = nullptr;
+    int64_t block_cap = 0;
+};
+
+constexpr int kMaxTeam = 256;
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+struct DevInfo {
+    int cus = 0;
+    int lds = 0;
+};
+std::map<int, DevInfo> g_dev;
+
+lra_status dev_info(int dev, DevInfo *out) {
+    auto it = g_dev.find(dev);
+    if (it == g_dev.end()) {
+        DevInfo d;
+        if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return LRA_EDEVICE;
+        if (hipDeviceGetAttribute(&d.lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            return LRA_EDEVICE;
+        it = g_dev.emplace(dev, d).first;
+    }
+    *out = it->second;
+    return LRA_OK;
+}
+
+lra_status get_ws(hipStream_t stream, Workspace **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LRA_EDEVICE;
+    Workspace &w = g_ws[std::make_pair(dev, stream)];
+    if (!w.counters) {
+        w.device = dev;
+        if (hipMalloc(&w.counters, 64 * sizeof(unsigned)) != hipSuccess) return LRA_ENOMEM;
+        if (hipMalloc(&w.hdr, 2 * kMaxTeam * sizeof(XchHeader)) != hipSuccess) return LRA_ENOMEM;
+        if (hipMalloc(&w.rows, (size_t)2 * kMaxTeam * kLMax * sizeof(double)) != hipSuccess) return LRA_ENOMEM;
+        if (hipMalloc(&w.init_cols, kRMax * sizeof(int64_t)) != hipSuccess) return LRA_ENOMEM;
+    }
+    *out = &w;
+    return LRA_OK;
+}
+
+lra_status fill_config(const lra_opts *opts, int32_t r, int32_t sweeps, CAConfig *c, lra_opts *o_out) {
+    lra_opts o;
+    if (opts) o = *opts;
+    else lra_default_opts(&o);
+    if (!(o.delta >= 0.0) || !std::isfinite(o.delta)) return LRA_EINVAL;
+    if (o.preprocess != LRA_PRE_NONE && o.preprocess != LRA_PRE_ASRHT) return LRA_EINVAL;
+    if (o.max_swaps < 0) o.max_swaps = 16 * r;
+    if (o.ah_samples <= 0) o.ah_samples = 2 * r;
+    if (o.refine_steps < 0 || o.refine_steps > 16) return LRA_EINVAL;
+    if (o.preprocess == LRA_PRE_ASRHT) {
+        if (o.ah_depth < 0 || o.ah_depth > 20) return LRA_EINVAL;
+        if (o.ah_samples < r || o.ah_samples > kLMax) return LRA_EINVAL;
+    }
+    c->r = r;
+    c->sweeps = sweeps;
+    c->delta = o.delta;
+    c->max_swaps = o.max_swaps;
+    c->pre = o.preprocess;
+    c->ah_depth = o.ah_depth;
+    c->ah_samples = o.ah_samples;
+    c->refine_steps = o.refine_steps;
+    c->panel_bytes = 0;
+    c->init_cols = nullptr;
+    *o_out = o;
+    return LRA_OK;
+}
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// Dynamic LDS for a team of `team` workgroups: the largest slice of any panel
+// (column panel, row panel, sketch) plus one flag byte per item, and at least
+// the 4 r^2 doubles of the nucleus workspace.
+size_t panel_bytes_for(int64_t m, int64_t n, int r, int pre, int l, int team, int64_t *ipw_out) {
+    int64_t ipw_m = (m + team - 1) / team, ipw_n = (n + team - 1) / team;
+    int64_t ipw = std::max(ipw_m, ipw_n);
+    size_t cells = (size_t)ipw * r;
+    if (pre == LRA_PRE_ASRHT) {
+        int64_t items = (m > n) ? ipw_n : ipw_m;
+        cells = std::max(cells, (size_t)items * l);
+    }
+    cells = std::max(cells, (size_t)4 * r * r);
+    *ipw_out = ipw;
+    return align16(cells * sizeof(double));
+}
+
+}  // namespace
+
+extern "C" {
+
+void lra_default_opts(lra_opts *o) {
+    if (!o) return;
+    o->delta = 0.01;
+    o->max_swaps = -1;
+    o->preprocess = LRA_PRE_NONE;
+    o->ah_depth = 3;
+    o->ah_samples = 0;
+    o->refine_steps = 0;
+    o->team_size = 0;
+    o->init_cols = nullptr;
+}
+
+const char *lra_strerror(lra_status s) {
+    switch (s) {
+    case LRA_OK: return "ok";
+    case LRA_EINVAL: return "invalid argument or non-finite input entry";
+    case LRA_ESINGULAR: return "rank-deficient panel (rank < r)";
+    case LRA_EDEVICE: return "HIP runtime error";
+    case LRA_ENOMEM: return "device workspace allocation failed";
+    case LRA_EUNSUPPORTED: return "shape does not fit the on-chip panel layout";
+    }
+    return "unknown status";
+}
+
+void lra_release(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_ws) {
+        Workspace &w = kv.second;
+        (void)hipSetDevice(w.device);
+        (void)hipStreamSynchronize(kv.first.second);
+        (void)hipFree(w.counters);
+        (void)hipFree(w.hdr);
+        (void)hipFree(w.rows);
+        (void)hipFree(w.init_cols);
+        (void)hipFree(w.blocks);
+        (void)hipFree(w.order);
+    }
+    g_ws.clear();
+    (void)hipSetDevice(cur);
+}
+
+lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t sweeps,
+                   uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info,
+                   hipStream_t stream) {
+    if (!W || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n || sweeps < 1) return LRA_EINVAL;
+    if (m > ((int64_t)1 << 40) || n > ((int64_t)1 << 40)) return LRA_EINVAL;
+    CAConfig cfg;
+    lra_opts o;
+    lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
+    if (st != LRA_OK) return st;
+    if (o.preprocess == LRA_PRE_ASRHT) {
+        const int64_t dim = (m > n) ? m : n;  // the dimension the multiplier acts on
+        const int64_t q2 = (int64_t)1 << o.ah_depth;
+        const int64_t N = q2 * ((dim + q2 - 1) / q2);
+        if (o.ah_samples > N) return LRA_EINVAL;
+    }
+    if (o.init_cols) {
+        if (o.preprocess != LRA_PRE_NONE) return LRA_EINVAL;
+        for (int a = 0; a < r; a++) {
+            if (o.init_cols[a] < 0 || o.init_cols[a] >= n) return LRA_EINVAL;
+            for (int b = 0; b < a; b++)
+                if (o.init_cols[a] == o.init_cols[b]) return LRA_EINVAL;
+        }
+    }
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    const int max_team = std::min(dinfo.cus, kMaxTeam);
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes();
+
+    int team;
+    if (o.team_size > 0) {
+        team = std::min(o.team_size, max_team);
+    } else {
+        const int64_t items = std::max(m, n);
+        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (items + 255) / 256));
+    }
+    int64_t ipw = 0;
+    size_t pb = panel_bytes_for(m, n, r, o.preprocess, o.ah_samples, team, &ipw);
+    while (pb + align16((size_t)ipw) > lds_budget && team < max_team && o.team_size <= 0) {
+        team = std::min(max_team, team * 2);
+        pb = panel_bytes_for(m, n, r, o.preprocess, o.ah_samples, team, &ipw);
+    }
+    if (pb + align16((size_t)ipw) > lds_budget) return LRA_EUNSUPPORTED;
+    cfg.panel_bytes = (int32_t)pb;
+    const size_t dyn = pb + align16((size_t)ipw);
+
+    if (o.init_cols) {
+        if (hipMemcpyAsync(ws->init_cols, o.init_cols, sizeof(int64_t) * r, hipMemcpyHostToDevice, stream) !=
+            hipSuccess)
+            return LRA_EDEVICE;
+        cfg.init_cols = ws->init_cols;
+    }
+    TeamWs tws{ws->counters, ws->hdr, ws->rows};
+    hipError_t e = lra::launch_team(dt, W, m, n, lda, seed, cfg, tws, team, dyn, I_out, J_out, U_out, info, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
+lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
+                           int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
+                           double *U_out, lra_info *infos, hipStream_t stream) {
+    if (!base || !blocks || count < 0 || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (r < 1 || r > kRMax || sweeps < 1 || count > (int64_t)INT32_MAX) return LRA_EINVAL;
+    CAConfig cfg;
+    lra_opts o;
+    lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
+    if (st != LRA_OK) return st;
+    if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
+    if (count == 0) return LRA_OK;
+    int64_t maxdim = 0;
+    std::vector<BlockDesc> desc((size_t)count);
+    for (int64_t b = 0; b < count; b++) {
+        const lra_block &k = blocks[b];
+        if (k.offset < 0 || k.m < 1 || k.n < 1 || k.lda < k.n || r > k.m || r > k.n) return LRA_EINVAL;
+        desc[b] = BlockDesc{k.offset, k.m, k.n, k.lda};
+        maxdim = std::max(maxdim, std::max(k.m, k.n));
+    }
+    // longest blocks first (cost ~ (m + n) r^2 per sweep): the tail of the
+    // persistent launch is then made of short blocks
+    std::vector<int32_t> order((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return desc[a].m + desc[a].n > desc[b].m + desc[b].n;
+    });
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes();
+    int64_t ipw = 0;
+    size_t pb = panel_bytes_for(maxdim, maxdim, r, LRA_PRE_NONE, 0, 1, &ipw);
+    const size_t dyn = pb + align16((size_t)ipw);
+    if (dyn > lds_budget) return LRA_EUNSUPPORTED;
+    cfg.panel_bytes = (int32_t)pb;
+
+    if (ws->block_cap < count) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(ws->blocks);
+        (void)hipFree(ws->order);
+        ws->blocks = nullptr;
+        ws->order = nullptr;
+        ws->block_cap = 0;
+        if (hipMalloc(&ws->blocks, sizeof(BlockDesc) * count) != hipSuccess) return LRA_ENOMEM;
+        if (hipMalloc(&ws->order, sizeof(int32_t) * count) != hipSuccess) return LRA_ENOMEM;
+        ws->block_cap = count;
+    }
+    if (hipMemcpyAsync(ws->blocks, desc.data(), sizeof(BlockDesc) * count, hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(ws->order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return LRA_EDEVICE;
+    // the host vectors must outlive the copies
+    (void)hipStreamSynchronize(stream);
+
+    int occ = lra::batched_occupancy(dt, dyn);
+    if (occ < 1) occ = 1;
+    const int64_t grid = std::min<int64_t>((int64_t)dinfo.cus * occ, count);
+    hipError_t e = lra::launch_batched(dt, base, ws->blocks, ws->order, count, seed, cfg, ws->counters + 1, (int)grid,
+                                       dyn, I_out, J_out, U_out, infos, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// lra_internal.h -- private declarations shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lra_cur.h"
+
+namespace lra {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
+constexpr int kRMax = 64;    // largest supported rank
+constexpr int kLMax = 256;   // largest number of sampled SRHT columns
+
+// Team exchange record: one per workgroup and barrier parity.
+struct XchHeader {
+    double val;
+    int64_t item;
+    int32_t slot;
+    int32_t flags;
+    int64_t pad;
+};
+
+struct CAConfig {
+    int32_t r, sweeps;
+    double delta;
+    int32_t max_swaps;
+    int32_t pre, ah_depth, ah_samples, refine_steps;
+    int32_t panel_bytes;      // offset of the flag bytes inside dynamic LDS
+    const int64_t *init_cols; // device copy of the warm-start columns, or null
+};
+
+struct TeamWs {
+    unsigned *bar;
+    XchHeader *hdr;   // [2][team]
+    double *rows;     // [2][team][kLMax]
+};
+
+struct BlockDesc {
+    int64_t offset, m, n, lda;
+};
+
+hipError_t launch_team(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, const CAConfig &cfg,
+                       const TeamWs &ws, int team, size_t dyn_bytes, int64_t *I_out, int64_t *J_out, double *U_out,
+                       lra_info *info, hipStream_t stream);
+
+hipError_t launch_batched(int dtype, const void *base, const BlockDesc *blocks, const int32_t *order, int64_t count,
+                          uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
+                          int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
+
+int batched_occupancy(int dtype, size_t dyn_bytes);
+size_t static_lds_bytes();
+
+}  // namespace lra

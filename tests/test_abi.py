@@ -1,0 +1,97 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and rejects invalid arguments on the host before touching a device."""
+import ctypes as ct
+import os
+import subprocess
+
+import pytest
+
+import paper_1710_07946_amd as lra
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lra.library_path()):
+        pytest.skip("library not built")
+    return lra.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = lra.declared_functions()
+    assert {"lra_cur", "lra_cur_batched", "lra_default_opts", "lra_release", "lra_strerror"} <= set(names)
+    out = subprocess.check_output(["nm", "-D", "--defined-only", lra.library_path()], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_default_opts(lib):
+    o = lra.lra_default_opts()
+    assert o.delta == 0.01 and o.max_swaps == -1 and o.preprocess == 0 and o.ah_depth == 3
+    assert o.ah_samples == 0 and o.refine_steps == 0 and o.team_size == 0 and not o.init_cols
+
+
+def test_strerror(lib):
+    for s in range(6):
+        assert lra.lra_strerror(s)
+    assert "rank" in lra.lra_strerror(lra.LRA_ESINGULAR)
+
+
+def test_struct_layouts():
+    assert ct.sizeof(lra.lra_info) == 32
+    assert ct.sizeof(lra.lra_block) == 32
+    assert ct.sizeof(lra.lra_opts) == 40
+
+
+def _call(lib, m=100, n=80, lda=80, r=5, sweeps=2, dt=1, opts=None, ptr=0x1000):
+    fake = ct.c_void_p(ptr)
+    return lib.lra_cur(fake, dt, m, n, lda, r, sweeps, 1, opts, fake, fake, fake, None, None)
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    E = lra.LRA_EINVAL
+    assert _call(lib, r=0) == E
+    assert _call(lib, r=81) == E           # r > min(m, n)
+    assert _call(lib, r=65, m=200, n=200, lda=200) == E  # r > 64
+    assert _call(lib, sweeps=0) == E
+    assert _call(lib, lda=79) == E
+    assert _call(lib, dt=7) == E
+    assert _call(lib, ptr=0) == E          # null pointers
+    o = lra.lra_default_opts()
+    o.delta = -1.0
+    assert _call(lib, opts=ct.byref(o)) == E
+    o = lra.lra_default_opts()
+    o.preprocess = 1
+    o.ah_samples = 3                       # l < r
+    assert _call(lib, opts=ct.byref(o)) == E
+    o = lra.lra_default_opts()
+    bad = (ct.c_int64 * 5)(0, 1, 2, 2, 4)  # duplicate warm-start column
+    o.init_cols = ct.cast(bad, ct.POINTER(ct.c_int64))
+    assert _call(lib, opts=ct.byref(o)) == E
+    bad2 = (ct.c_int64 * 5)(0, 1, 2, 3, 80)  # out of range
+    o.init_cols = ct.cast(bad2, ct.POINTER(ct.c_int64))
+    assert _call(lib, opts=ct.byref(o)) == E
+
+
+def test_batched_invalid_arguments_rejected_on_host(lib):
+    fake = ct.c_void_p(0x1000)
+    blocks = (lra.lra_block * 2)(lra.lra_block(0, 10, 10, 10), lra.lra_block(100, 10, 9, 8))  # lda < n
+    assert lib.lra_cur_batched(fake, 1, blocks, 2, 3, 1, 0, None, fake, fake, fake, None, None) == lra.LRA_EINVAL
+    blocks = (lra.lra_block * 1)(lra.lra_block(0, 2, 10, 10))  # r > m
+    assert lib.lra_cur_batched(fake, 1, blocks, 1, 3, 1, 0, None, fake, fake, fake, None, None) == lra.LRA_EINVAL
+    o = lra.lra_default_opts()
+    o.preprocess = 1
+    blocks = (lra.lra_block * 1)(lra.lra_block(0, 20, 20, 20))
+    assert lib.lra_cur_batched(fake, 1, blocks, 1, 3, 1, 0, ct.byref(o), fake, fake, fake, None,
+                               None) == lra.LRA_EINVAL
+    # an empty batch is a no-op
+    assert lib.lra_cur_batched(fake, 1, blocks, 0, 3, 1, 0, None, fake, fake, fake, None, None) == lra.LRA_OK
+
+
+def test_binding_refuses_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(lra, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(lra, "_lib", None)
+    with pytest.raises(ImportError):
+        lra.load()
