@@ -286,7 +286,8 @@ int orc_sketch(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
     if (l > N) return ORC_EINVAL;
     int st = orc_draw_distinct(seed, 2, N, l, samples);
     if (st) return st;
-    double scale = pow(2.0, -0.5 * d) * sqrt((double)N / (double)l);
+    /* 2^{-d/2} sqrt(N/l) = sqrt(s/l) since N = 2^d s */
+    double scale = sqrt((double)s / (double)l);
     for (int64_t it = 0; it < items; it++) {
         for (int q = 0; q < l; q++) {
             int64_t t = samples[q];
