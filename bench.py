@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the C-A path is single-GPU; "
@@ -53,6 +55,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_ref_mib:
+        src = torch.ones(args.copy_ref_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes": src.numel() * 4}))
+        return
 
     import paper_1710_07946_amd as lra
     from paper_1710_07946_amd import workloads

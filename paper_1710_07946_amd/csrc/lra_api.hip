@@ -23,17 +23,17 @@ using lra::kBlock;
 using lra::kLMax;
 using lra::kRMax;
 using lra::TeamWs;
-using lra::XchHeader;
 
 struct Workspace {
     int device = -1;
     unsigned *counters = nullptr;   // [0] team barrier, [1] batch queue
-    XchHeader *hdr = nullptr;       // [2][kMaxTeam]
-    double *rows = nullptr;         // [2][kMaxTeam][kLMax]
+    uint64_t *xw = nullptr;         // team exchange words [2][kMaxTeam][kSlotWords]
     int64_t *init_cols = nullptr;   // [kRMax]
     BlockDesc *blocks = nullptr;
     int32_t *order = nullptr;
     int64_t block_cap = 0;
+    double *sketch = nullptr;       // global sketch panels when they do not fit LDS
+    size_t sketch_cap = 0;          // bytes
 };
 
 constexpr int kMaxTeam = 256;
@@ -44,6 +44,7 @@ std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
 struct DevInfo {
     int cus = 0;
     int lds = 0;
+    int wall_khz = 0;  // rate of the device wall clock
 };
 std::map<int, DevInfo> g_dev;
 
@@ -55,6 +56,8 @@ lra_status dev_info(int dev, DevInfo *out) {
             return LRA_EDEVICE;
         if (hipDeviceGetAttribute(&d.lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
             return LRA_EDEVICE;
+        if (hipDeviceGetAttribute(&d.wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || d.wall_khz <= 0)
+            d.wall_khz = 100000;
         it = g_dev.emplace(dev, d).first;
     }
     *out = it->second;
@@ -68,8 +71,8 @@ lra_status get_ws(hipStream_t stream, Workspace **out) {
     if (!w.counters) {
         w.device = dev;
         if (hipMalloc(&w.counters, 64 * sizeof(unsigned)) != hipSuccess) return LRA_ENOMEM;
-        if (hipMalloc(&w.hdr, 2 * kMaxTeam * sizeof(XchHeader)) != hipSuccess) return LRA_ENOMEM;
-        if (hipMalloc(&w.rows, (size_t)2 * kMaxTeam * kLMax * sizeof(double)) != hipSuccess) return LRA_ENOMEM;
+        if (hipMalloc(&w.xw, (size_t)2 * kMaxTeam * lra::kSlotWords * sizeof(uint64_t)) != hipSuccess)
+            return LRA_ENOMEM;
         if (hipMalloc(&w.init_cols, kRMax * sizeof(int64_t)) != hipSuccess) return LRA_ENOMEM;
     }
     *out = &w;
@@ -99,26 +102,46 @@ lra_status fill_config(const lra_opts *opts, int32_t r, int32_t sweeps, CAConfig
     c->refine_steps = o.refine_steps;
     c->panel_bytes = 0;
     c->init_cols = nullptr;
+    c->sketch_ws = nullptr;
     *o_out = o;
     return LRA_OK;
 }
 
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
-// Dynamic LDS for a team of `team` workgroups: the largest slice of any panel
-// (column panel, row panel, sketch) plus one flag byte per item, and at least
-// the 4 r^2 doubles of the nucleus workspace.
-size_t panel_bytes_for(int64_t m, int64_t n, int r, int pre, int l, int team, int64_t *ipw_out) {
-    int64_t ipw_m = (m + team - 1) / team, ipw_n = (n + team - 1) / team;
-    int64_t ipw = std::max(ipw_m, ipw_n);
-    size_t cells = (size_t)ipw * r;
+// LDS plan for a team of `team` workgroups: the C-A panel slice (largest of
+// the column and row panels, r doubles per item) and the nucleus workspace
+// (4 r^2 doubles) always live in LDS; the sketch slice (l doubles per item)
+// joins them when it fits, else it goes to global memory.
+struct LdsPlan {
+    size_t panel_bytes = 0;  // dynamic LDS before the flag bytes
+    size_t dyn_bytes = 0;    // total dynamic LDS
+    bool sketch_global = false;
+    int64_t ipw_s = 0;       // sketch items per workgroup
+    bool fits = false;
+};
+
+LdsPlan plan_lds(int64_t m, int64_t n, int r, int pre, int l, int team, size_t budget) {
+    LdsPlan p;
+    const int64_t ipw = std::max((m + team - 1) / team, (n + team - 1) / team);
+    size_t cells = std::max((size_t)ipw * r, (size_t)4 * r * r);
+    int64_t flag_items = ipw;
     if (pre == LRA_PRE_ASRHT) {
-        int64_t items = (m > n) ? ipw_n : ipw_m;
-        cells = std::max(cells, (size_t)items * l);
+        p.ipw_s = ((m > n) ? (n + team - 1) / team : (m + team - 1) / team);
+        const size_t sk = (size_t)p.ipw_s * l;
+        const size_t with = align16(std::max(cells, sk) * sizeof(double)) + align16(std::max(ipw, p.ipw_s));
+        if (with <= budget) {
+            cells = std::max(cells, sk);
+            flag_items = std::max(ipw, p.ipw_s);
+        } else {
+            p.sketch_global = true;
+            flag_items = std::max(ipw, p.ipw_s);
+        }
     }
-    cells = std::max(cells, (size_t)4 * r * r);
-    *ipw_out = ipw;
-    return align16(cells * sizeof(double));
+    p.panel_bytes = align16(cells * sizeof(double));
+    p.dyn_bytes = p.panel_bytes + align16((size_t)flag_items);
+    p.fits = p.dyn_bytes <= budget;
+    return p;
 }
 
 }  // namespace
@@ -158,11 +181,11 @@ void lra_release(void) {
         (void)hipSetDevice(w.device);
         (void)hipStreamSynchronize(kv.first.second);
         (void)hipFree(w.counters);
-        (void)hipFree(w.hdr);
-        (void)hipFree(w.rows);
+        (void)hipFree(w.xw);
         (void)hipFree(w.init_cols);
         (void)hipFree(w.blocks);
         (void)hipFree(w.order);
+        (void)hipFree(w.sketch);
     }
     g_ws.clear();
     (void)hipSetDevice(cur);
@@ -200,24 +223,39 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     DevInfo dinfo;
     if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
     const int max_team = std::min(dinfo.cus, kMaxTeam);
-    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes();
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 1024;
 
+    // Team size: the smallest number of workgroups whose panel slices fit in
+    // LDS, but at least one workgroup per 512 items (more workgroups shorten
+    // the per-decision scans, fewer make each team selection cheaper).
     int team;
+    LdsPlan plan;
     if (o.team_size > 0) {
         team = std::min(o.team_size, max_team);
+        plan = plan_lds(m, n, r, o.preprocess, o.ah_samples, team, lds_budget);
     } else {
-        const int64_t items = std::max(m, n);
-        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (items + 255) / 256));
+        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, n) + 511) / 512));
+        plan = plan_lds(m, n, r, o.preprocess, o.ah_samples, team, lds_budget);
+        while (!plan.fits && team < max_team) {
+            team++;
+            plan = plan_lds(m, n, r, o.preprocess, o.ah_samples, team, lds_budget);
+        }
     }
-    int64_t ipw = 0;
-    size_t pb = panel_bytes_for(m, n, r, o.preprocess, o.ah_samples, team, &ipw);
-    while (pb + align16((size_t)ipw) > lds_budget && team < max_team && o.team_size <= 0) {
-        team = std::min(max_team, team * 2);
-        pb = panel_bytes_for(m, n, r, o.preprocess, o.ah_samples, team, &ipw);
+    if (!plan.fits) return LRA_EUNSUPPORTED;
+    cfg.panel_bytes = (int32_t)plan.panel_bytes;
+    const size_t dyn = plan.dyn_bytes;
+    if (plan.sketch_global) {
+        const size_t need = (size_t)team * plan.ipw_s * o.ah_samples * sizeof(double);
+        if (ws->sketch_cap < need) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(ws->sketch);
+            ws->sketch = nullptr;
+            ws->sketch_cap = 0;
+            if (hipMalloc(&ws->sketch, need) != hipSuccess) return LRA_ENOMEM;
+            ws->sketch_cap = need;
+        }
+        cfg.sketch_ws = ws->sketch;
     }
-    if (pb + align16((size_t)ipw) > lds_budget) return LRA_EUNSUPPORTED;
-    cfg.panel_bytes = (int32_t)pb;
-    const size_t dyn = pb + align16((size_t)ipw);
 
     if (o.init_cols) {
         if (hipMemcpyAsync(ws->init_cols, o.init_cols, sizeof(int64_t) * r, hipMemcpyHostToDevice, stream) !=
@@ -225,7 +263,9 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
             return LRA_EDEVICE;
         cfg.init_cols = ws->init_cols;
     }
-    TeamWs tws{ws->counters, ws->hdr, ws->rows};
+    // a team selection normally completes in microseconds; two seconds
+    // without the expected word means the launch has failed
+    TeamWs tws{ws->xw, (uint64_t)dinfo.wall_khz * 2000ull};
     hipError_t e = lra::launch_team(dt, W, m, n, lda, seed, cfg, tws, team, dyn, I_out, J_out, U_out, info, stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -267,12 +307,11 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
     DevInfo dinfo;
     if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
-    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes();
-    int64_t ipw = 0;
-    size_t pb = panel_bytes_for(maxdim, maxdim, r, LRA_PRE_NONE, 0, 1, &ipw);
-    const size_t dyn = pb + align16((size_t)ipw);
-    if (dyn > lds_budget) return LRA_EUNSUPPORTED;
-    cfg.panel_bytes = (int32_t)pb;
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 1024;
+    const LdsPlan plan = plan_lds(maxdim, maxdim, r, LRA_PRE_NONE, 0, 1, lds_budget);
+    if (!plan.fits) return LRA_EUNSUPPORTED;
+    cfg.panel_bytes = (int32_t)plan.panel_bytes;
+    const size_t dyn = plan.dyn_bytes;
 
     if (ws->block_cap < count) {
         (void)hipStreamSynchronize(stream);

@@ -21,12 +21,37 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lra_internal.h"
 
 namespace lra {
 
 constexpr int kWave = 64;
 constexpr int kNWave = kBlock / kWave;
+
+// ---------------------------------------------------------------- tracing
+// Built with -DLRA_TRACE, workgroup 0 of a launch records phase timestamps
+// (device wall clock) and the time spent inside team selections in a device
+// buffer that lra_trace_read() copies out.  Off by default: no cost.
+#ifdef LRA_TRACE
+constexpr int kTraceMax = 4096;
+__device__ uint64_t g_trace[kTraceMax * 2];
+__device__ int g_trace_n;
+__device__ __forceinline__ void trace(int ev, uint64_t val = 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int i = g_trace_n;
+        if (i < kTraceMax) {
+            g_trace[2 * i] = ((uint64_t)ev << 56) | (wall_clock64() & 0x00ffffffffffffffull);
+            g_trace[2 * i + 1] = val;
+            g_trace_n = i + 1;
+        }
+    }
+}
+#define LRA_TR(ev, val) trace(ev, val)
+#else
+#define LRA_TR(ev, val) ((void)0)
+#endif
 
 // ---------------------------------------------------------------- elements
 template <typename T> struct Elem;
@@ -98,11 +123,13 @@ __device__ void draw_distinct_wave(uint64_t seed, uint64_t stream, int64_t n, in
 }
 
 // ---------------------------------------------------------------- argmax
+// Candidates are ordered by value, then lowest item, then lowest slot: the
+// tie rule of the oracle's sequential scans.
 struct Best {
     double v;      // |value| compared; -1 when there is no candidate
     int64_t item;  // global item id (row or column of W)
     int32_t slot;  // basis slot (swap search) or 0
-    int32_t aux;   // owner workgroup (team reduction) or local item index
+    int32_t aux;   // owner workgroup (team reduction only)
 };
 
 __device__ __forceinline__ bool better(double v1, int64_t i1, int s1, double v2, int64_t i2, int s2) {
@@ -111,7 +138,7 @@ __device__ __forceinline__ bool better(double v1, int64_t i1, int s1, double v2,
 
 __device__ __forceinline__ Best none() { return Best{-1.0, INT64_MAX, 0x7fffffff, -1}; }
 
-__device__ __forceinline__ void consider(Best &b, double v, int64_t item, int slot, int aux) {
+__device__ __forceinline__ void consider(Best &b, double v, int64_t item, int slot, int aux = -1) {
     if (better(v, item, slot, b.v, b.item, b.slot)) b = Best{v, item, slot, aux};
 }
 
@@ -128,6 +155,12 @@ __device__ __forceinline__ Best wave_reduce(Best b) {
     return b;
 }
 
+__device__ __forceinline__ int wave_or(int f) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) f |= __shfl_xor(f, off);
+    return f;
+}
+
 // ---------------------------------------------------------------- LDS state
 struct Smem {
     int64_t Iset[kRMax], Jset[kRMax], Iprev[kRMax], Jprev[kRMax];
@@ -142,117 +175,75 @@ struct Smem {
     int32_t status;
     int32_t rank_found;
     int32_t job;
+    int32_t xfail;   // a team poll timed out
     double vtv;
+    double alpha;
     double logdet;
+#ifdef LRA_TRACE
+    uint64_t t_select;
+#endif
 };
 
 struct Team {
     int rank, size;
-    unsigned epoch;
-    unsigned *bar;
-    XchHeader *hdr;
-    double *rows;  // [2][size][kLMax]
+    unsigned epoch;   // number of team selections so far (same in every workgroup)
+    uint64_t *xw;     // exchange words [2][size][kSlotWords], zeroed before the launch
+    uint64_t spin_limit;  // wall-clock ticks a poll may wait
 };
 
-// Grid-wide barrier for a cooperative team: every workgroup adds one to a
-// counter and waits until it reaches (epoch + 1) * size.  The release fence
-// publishes this workgroup's global writes (exchange buffer) before the
-// arrival; the acquire fence after the wait makes the others' writes visible.
-__device__ void team_barrier(Team &tm) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned target = (tm.epoch + 1u) * (unsigned)tm.size;
-        __hip_atomic_fetch_add(tm.bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        while (__hip_atomic_load(tm.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target)
+// Team exchange without barriers or cache-maintenance fences: every 64-bit
+// word carries a 32-bit tag (selection number + 1) next to 32 data bits and
+// is written and read with single-copy-atomic device-scope accesses, which
+// go to the device-coherent level instead of the per-XCD L2.  A reader polls
+// a word until its tag matches, so a value can never be taken from an older
+// selection, whatever the order in which the writer's stores land.  Words of
+// parity p are rewritten at every selection of that parity, and the buffer
+// is cleared before each launch, so tags never alias.
+__device__ __forceinline__ void xput(uint64_t *p, uint32_t tag, uint32_t data) {
+    __hip_atomic_store(p, ((uint64_t)tag << 32) | data, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t xld(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t lo_hi(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+
+// Read N exchange words that all carry `tag`: the N loads are issued
+// together, and only the words still stale are polled again.  Every wait is
+// bounded in wall-clock time: past `limit` ticks the workgroup records a
+// failure in *fail, stops polling for the rest of the launch (its reads
+// return 0) and runs to the end, so no wave can wait forever; the LRA then
+// reports LRA_EDEVICE.
+template <int N>
+__device__ __forceinline__ void xget(const uint64_t *const (&p)[N], uint32_t tag, uint32_t (&out)[N], int *fail,
+                                     uint64_t limit) {
+    uint64_t v[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] = xld(p[i]);
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < N; i++) ok = ok && ((uint32_t)(v[i] >> 32) == tag);
+    if (!ok && !*(volatile int *)fail) {
+        const uint64_t t0 = wall_clock64();
+        for (;;) {
             __builtin_amdgcn_s_sleep(1);
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    tm.epoch++;
-}
-
-// Workgroup reduction of per-thread candidates; the result lands in sm.win
-// (for a team of one) or is the workgroup's team candidate.
-__device__ Best block_reduce(Best b, int flag, Smem &sm, int32_t *flag_out) {
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    b = wave_reduce(b);
+            ok = true;
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) flag |= __shfl_xor(flag, off);
-    __syncthreads();
-    if (lane == 0) {
-        sm.red[w] = b;
-        sm.red_flag[w] = flag;
-    }
-    __syncthreads();
-    Best r = sm.red[0];
-    int f = sm.red_flag[0];
+            for (int i = 0; i < N; i++) {
+                if ((uint32_t)(v[i] >> 32) != tag) v[i] = xld(p[i]);
+            }
 #pragma unroll
-    for (int q = 1; q < kNWave; q++) {
-        Best o = sm.red[q];
-        if (better(o.v, o.item, o.slot, r.v, r.item, r.slot)) r = o;
-        f |= sm.red_flag[q];
-    }
-    *flag_out = f;
-    return r;
-}
-
-// Team-wide selection: reduce the per-thread candidates to the team's winner
-// and copy the winner's row (width values of its panel column) to sm.wrow.
-// b.aux holds the local item index of the candidate.  All threads must call.
-__device__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *panel, int ipw, int width) {
-    int32_t f;
-    Best local = block_reduce(b, flag, sm, &f);
-    if (tm.size == 1) {
-        if (threadIdx.x < width) sm.wrow[threadIdx.x] = local.v >= 0 ? panel[threadIdx.x * ipw + local.aux] : 0.0;
-        if (threadIdx.x == 0) {
-            sm.win = local;
-            sm.win.aux = 0;
-            sm.win_flag = f;
+            for (int i = 0; i < N; i++) ok = ok && ((uint32_t)(v[i] >> 32) == tag);
+            if (ok) break;
+            if (wall_clock64() - t0 > limit) {
+                *(volatile int *)fail = 1;
+                break;
+            }
         }
-        __syncthreads();
-        return;
     }
-    const int par = tm.epoch & 1;
-    XchHeader *H = tm.hdr + (size_t)par * tm.size;
-    double *Rw = tm.rows + (size_t)par * tm.size * kLMax;
-    if (threadIdx.x == 0) {
-        XchHeader h;
-        h.val = local.v;
-        h.item = local.item;
-        h.slot = local.slot;
-        h.flags = f;
-        H[tm.rank] = h;
-    }
-    if (threadIdx.x < width)
-        Rw[(size_t)tm.rank * kLMax + threadIdx.x] = local.v >= 0 ? panel[threadIdx.x * ipw + local.aux] : 0.0;
-    team_barrier(tm);
-    Best c = none();
-    int cf = 0;
-    for (int g = threadIdx.x; g < tm.size; g += kBlock) {
-        XchHeader h = H[g];
-        consider(c, h.val, h.item, h.slot, g);
-        cf |= h.flags;
-    }
-    Best w = block_reduce(c, cf, sm, &f);
-    if (threadIdx.x < width) sm.wrow[threadIdx.x] = Rw[(size_t)w.aux * kLMax + threadIdx.x];
-    if (threadIdx.x == 0) {
-        sm.win = w;
-        sm.win_flag = f;
-    }
-    __syncthreads();
-}
-
-__device__ void sort_small(int64_t *a, int r) {
-    for (int i = 1; i < r; i++) {
-        int64_t x = a[i];
-        int j = i - 1;
-        while (j >= 0 && a[j] > x) {
-            a[j + 1] = a[j];
-            j--;
-        }
-        a[j + 1] = x;
-    }
+#pragma unroll
+    for (int i = 0; i < N; i++) out[i] = ok ? (uint32_t)v[i] : 0u;
 }
 
 struct Geo {   // item partition of one panel across the team
@@ -270,111 +261,277 @@ __device__ __forceinline__ Geo geo(const Team &tm, int64_t items) {
     return g;
 }
 
+enum SelMode { kSelPlain = 0, kSelHouseholder = 1 };
+
+// Team-wide selection.  Every thread passes its best candidate; the winner
+// of the whole team lands in sm.win and its row (`width` entries of its
+// panel column) in sm.wrow.  Wave 0 alone runs the exchange, so the call
+// costs two workgroup barriers.  With kSelHouseholder, lane 0 also turns
+// sm.wrow into the Householder vector of step `hstep` (oracle order:
+// alpha = -sign(x0) ||x||, v0 = x0 - alpha, vtv = sum of v_c^2 in index order).
+__device__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *panel, const Geo &g, int width,
+                            int mode = kSelPlain, int hstep = 0) {
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#ifdef LRA_TRACE
+    const uint64_t t_in = wall_clock64();
+#endif
+    b = wave_reduce(b);
+    flag = wave_or(flag);
+    if (lane == 0) {
+        sm.red[w] = b;
+        sm.red_flag[w] = flag;
+    }
+    __syncthreads();
+    if (w == 0) {
+        Best loc = lane < kNWave ? sm.red[lane] : none();
+        int f = lane < kNWave ? sm.red_flag[lane] : 0;
+        loc = wave_reduce(loc);
+        f = wave_or(f);
+        Best win;
+        int wf;
+        if (tm.size == 1) {
+            win = loc;
+            wf = f;
+            for (int t = lane; t < width; t += kWave)
+                sm.wrow[t] = loc.v >= 0 ? panel[t * g.ipw + (int)(loc.item - g.base)] : 0.0;
+        } else {
+            const uint32_t tag = tm.epoch + 1u;
+            const int par = tm.epoch & 1;
+            uint64_t *slots = tm.xw + (size_t)par * tm.size * kSlotWords;
+            uint64_t *mine = slots + (size_t)tm.rank * kSlotWords;
+            for (int t = lane; t < width; t += kWave) {
+                const double x = loc.v >= 0 ? panel[t * g.ipw + (int)(loc.item - g.base)] : 0.0;
+                const uint64_t u = (uint64_t)__double_as_longlong(x);
+                xput(mine + kHdrWords + 2 * t, tag, (uint32_t)u);
+                xput(mine + kHdrWords + 2 * t + 1, tag, (uint32_t)(u >> 32));
+            }
+            if (lane == 0) {
+                const uint64_t v = (uint64_t)__double_as_longlong(loc.v);
+                const uint64_t it = (uint64_t)loc.item;
+                xput(mine + 0, tag, (uint32_t)v);
+                xput(mine + 1, tag, (uint32_t)(v >> 32));
+                xput(mine + 2, tag, (uint32_t)it);
+                xput(mine + 3, tag, (uint32_t)(it >> 32));
+                xput(mine + 4, tag, ((uint32_t)(loc.slot & 0xffff) << 16) | (uint32_t)(f & 0xffff));
+            }
+            Best c = none();
+            int cf = 0;
+            for (int g0 = lane; g0 < tm.size; g0 += kWave) {
+                const uint64_t *h = slots + (size_t)g0 * kSlotWords;
+                const uint64_t *const ps[5] = {h, h + 1, h + 2, h + 3, h + 4};
+                uint32_t d[5];
+                xget<5>(ps, tag, d, &sm.xfail, tm.spin_limit);
+                const double v = __longlong_as_double((long long)lo_hi(d[0], d[1]));
+                int sl = (int)(d[4] >> 16);
+                if (sl == 0xffff) sl = 0x7fffffff;
+                consider(c, v, (int64_t)lo_hi(d[2], d[3]), sl, g0);
+                cf |= (int)(d[4] & 0xffff);
+            }
+            win = wave_reduce(c);
+            wf = wave_or(cf);
+            // no candidate in the whole team (every item is in the basis):
+            // there is no winner row to fetch
+            const bool have = win.v >= 0.0 && win.aux >= 0 && win.aux < tm.size;
+            for (int t = lane; t < width; t += kWave) {
+                double x = 0.0;
+                if (have) {
+                    const uint64_t *row = slots + (size_t)win.aux * kSlotWords + kHdrWords + 2 * t;
+                    const uint64_t *const ps[2] = {row, row + 1};
+                    uint32_t d[2];
+                    xget<2>(ps, tag, d, &sm.xfail, tm.spin_limit);
+                    x = __longlong_as_double((long long)lo_hi(d[0], d[1]));
+                }
+                sm.wrow[t] = x;
+            }
+            // after a timed-out poll nothing read in this launch can be
+            // trusted: report "no candidate", which ends every caller loop
+            if (__any(*(volatile int *)&sm.xfail)) {
+                win = none();
+                wf = 0;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // sm.wrow written by every lane above
+        if (lane == 0) {
+            sm.win = win;
+            sm.win_flag = wf;
+            if (mode == kSelHouseholder && win.v > 0.0) {
+                const double nx = sqrt(win.v);
+                const double x0 = sm.wrow[hstep];
+                const double alpha = (x0 >= 0.0) ? -nx : nx;
+                sm.wrow[hstep] = x0 - alpha;
+                double vtv = 0.0;
+                for (int c = hstep; c < width; c++) vtv += sm.wrow[c] * sm.wrow[c];
+                sm.vtv = vtv;
+                sm.alpha = alpha;
+            }
+        }
+    }
+    tm.epoch++;
+    __syncthreads();
+#ifdef LRA_TRACE
+    if (threadIdx.x == 0) sm.t_select += wall_clock64() - t_in;
+#endif
+}
+
+// Sort r <= 64 distinct indices in LDS ascending: every lane of one wave
+// takes one entry, counts the entries below it with shuffles and stores it at
+// its rank.
+__device__ void sort_set_wave(int64_t *a, int r) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t x = lane < r ? a[lane] : INT64_MAX;
+    int rank = 0;
+    for (int j = 0; j < r; j++) {
+        const int64_t y = __shfl(x, j);
+        rank += (y < x) || (y == x && j < lane);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < r) a[rank] = x;
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void fail_status(Smem &sm, int st, int rank) {
+    if (threadIdx.x == 0) {
+        sm.status = st;
+        if (st == LRA_ESINGULAR) sm.rank_found = rank;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- maxvol
 // Dominant r x r submatrix of the tall panel held in `panel` (slot-major,
 // stride g.ipw): pivoted LU start (Algorithm alggos, stages 1-2), then the
 // swaps of Algorithm algdomin with the rank-one update of B.  flags[li] is 0
-// for a candidate item, slot+1 for a basis item.  On return sm.slot_item
-// holds the basis in slot order.  `bad` flags a non-finite entry read.
+// for a candidate item and slot+1 for a basis item; item li is always handled
+// by thread li % kBlock, which alone reads and writes flags[li].  Each
+// elimination step or swap is applied lazily, fused with the scan for the
+// next decision.  On return sm.slot_item holds the basis in slot order.
+// `bad` flags a non-finite entry read by the gather.
 __device__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Geo &g, int r, double delta,
                        int max_swaps, int bad, int32_t &swaps_total, int32_t &converged) {
     const int tid = threadIdx.x;
     const int ipw = g.ipw;
-    // ---- pivoted LU: r steps
+    // ---- pivoted LU: r steps; step k eliminates with the pivot row of step
+    // k-1 (held in sm.wrow) before scanning column k
+    double pk = 1.0;
     for (int k = 0; k < r; k++) {
         Best b = none();
-        for (int li = tid; li < g.cnt; li += kBlock)
-            if (!flags[li]) consider(b, fabs(panel[k * ipw + li]), g.base + li, 0, li);
-        team_select(tm, sm, b, k == 0 ? bad : 0, panel, ipw, r);
-        if (sm.win_flag) {
-            if (tid == 0) sm.status = LRA_EINVAL;
-            __syncthreads();
-            return;
-        }
-        if (!(sm.win.v > 0.0)) {
-            if (tid == 0) {
-                sm.status = LRA_ESINGULAR;
-                sm.rank_found = k;
-            }
-            __syncthreads();
-            return;
-        }
-        const int64_t wit = sm.win.item;
-        if (tid == 0) {
-            sm.slot_item[k] = wit;
-            if (wit >= g.base && wit < g.base + g.cnt) flags[wit - g.base] = (uint8_t)(k + 1);
-        }
-        if (tid < k) sm.L11[k * (k - 1) / 2 + tid] = sm.wrow[tid];
-        __syncthreads();
-        const double pk = sm.wrow[k];
         for (int li = tid; li < g.cnt; li += kBlock) {
             if (flags[li]) continue;
-            double l = panel[k * ipw + li] / pk;
-            panel[k * ipw + li] = l;
-            for (int j = k + 1; j < r; j++) panel[j * ipw + li] -= l * sm.wrow[j];
+            if (k > 0) {
+                const double l = panel[(k - 1) * ipw + li] / pk;
+                panel[(k - 1) * ipw + li] = l;
+#pragma unroll 4
+                for (int j = k; j < r; j++) panel[j * ipw + li] -= l * sm.wrow[j];
+            }
+            consider(b, fabs(panel[k * ipw + li]), g.base + li, 0);
         }
-        __syncthreads();
+        if (k > 0 && tid < k - 1) sm.L11[(k - 1) * (k - 2) / 2 + tid] = sm.wrow[tid];
+        team_select(tm, sm, b, k == 0 ? bad : 0, panel, g, r);
+        if (sm.win_flag) return fail_status(sm, LRA_EINVAL, 0);
+        if (!(sm.win.v > 0.0)) return fail_status(sm, LRA_ESINGULAR, k);
+        const int64_t wit = sm.win.item;
+        if (tid == 0) sm.slot_item[k] = wit;
+        if (wit >= g.base && wit < g.base + g.cnt && (int)((wit - g.base) % kBlock) == tid)
+            flags[wit - g.base] = (uint8_t)(k + 1);
+        pk = sm.wrow[k];
     }
-    // ---- B = L21 L11^{-1} for candidates, unit rows for the basis
-    for (int li = tid; li < g.cnt; li += kBlock) {
-        const int fl = flags[li];
-        if (fl) {
-            for (int j = 0; j < r; j++) panel[j * ipw + li] = (j == fl - 1) ? 1.0 : 0.0;
-            continue;
-        }
-        for (int j = r - 1; j >= 0; j--) {
-            double s = panel[j * ipw + li];
-            for (int kk = j + 1; kk < r; kk++) s -= panel[kk * ipw + li] * sm.L11[kk * (kk - 1) / 2 + j];
-            panel[j * ipw + li] = s;
-        }
-    }
+    // last multipliers (no trailing columns), last row of L11
+    for (int li = tid; li < g.cnt; li += kBlock)
+        if (!flags[li]) panel[(r - 1) * ipw + li] /= pk;
+    if (tid < r - 1) sm.L11[(r - 1) * (r - 2) / 2 + tid] = sm.wrow[tid];
     __syncthreads();
-    // ---- swaps
+    // ---- B = L21 L11^{-1} for candidates and unit rows for the basis,
+    // fused with the first swap scan; then swaps, each update fused with the
+    // next scan
     const double thr = 1.0 + delta;
     int swaps = 0;
+    int js = -1;
+    int64_t wit = -1;
+    double pv = 1.0;
     for (;;) {
         Best b = none();
         for (int li = tid; li < g.cnt; li += kBlock) {
-            if (flags[li]) continue;
+            const int fl = flags[li];
             const int64_t it = g.base + li;
-            for (int j = 0; j < r; j++) consider(b, fabs(panel[j * ipw + li]), it, j, li);
+            if (js < 0) {
+                if (fl) {
+                    for (int j = 0; j < r; j++) panel[j * ipw + li] = (j == fl - 1) ? 1.0 : 0.0;
+                    continue;
+                }
+                for (int j = r - 1; j >= 0; j--) {
+                    double s = panel[j * ipw + li];
+#pragma unroll 4
+                    for (int kk = j + 1; kk < r; kk++) s -= panel[kk * ipw + li] * sm.L11[kk * (kk - 1) / 2 + j];
+                    panel[j * ipw + li] = s;
+                }
+            } else if (it == wit) {  // enters the basis in slot js
+                for (int j = 0; j < r; j++) panel[j * ipw + li] = (j == js) ? 1.0 : 0.0;
+                flags[li] = (uint8_t)(js + 1);
+                continue;
+            } else if (fl == 0 || fl == js + 1) {  // other basis rows have B[i][js] = 0
+                const double f = panel[js * ipw + li] / pv;
+                if (f != 0.0)
+#pragma unroll 4
+                    for (int j = 0; j < r; j++) {
+                        const double d = (j == js) ? sm.wrow[j] - 1.0 : sm.wrow[j];  // B[i*,:] - e_js^T
+                        panel[j * ipw + li] -= f * d;
+                    }
+                if (fl) {
+                    flags[li] = 0;  // leaves the basis
+                }
+            } else {
+                continue;
+            }
+            if (flags[li]) continue;
+#pragma unroll 4
+            for (int j = 0; j < r; j++) consider(b, fabs(panel[j * ipw + li]), it, j);
         }
-        team_select(tm, sm, b, 0, panel, ipw, r);
+        team_select(tm, sm, b, 0, panel, g, r);
         const double v = sm.win.v;
-        if (v < 0.0 || v <= thr) break;         // no candidate left, or dominant
+        if (v < 0.0 || v <= thr) break;  // no candidate left, or dominant
         if (swaps >= max_swaps) {
             converged = 0;
             break;
         }
-        const int js = sm.win.slot;
-        const int64_t wit = sm.win.item;
-        const int64_t old = sm.slot_item[js];
-        const double pv = sm.wrow[js];
-        __syncthreads();
-        if (tid == 0) sm.wrow[js] -= 1.0;  // B[i,:] - e_j^T
-        __syncthreads();
-        for (int li = tid; li < g.cnt; li += kBlock) {
-            const int fl = flags[li];
-            if (g.base + li == wit) continue;
-            if (fl != 0 && fl != js + 1) continue;  // other basis rows: B[i][js] = 0
-            const double f = panel[js * ipw + li] / pv;
-            if (f == 0.0) continue;
-            for (int j = 0; j < r; j++) panel[j * ipw + li] -= f * sm.wrow[j];
-        }
-        __syncthreads();
-        if (wit >= g.base && wit < g.base + g.cnt) {
-            const int lw = (int)(wit - g.base);
-            if (tid < r) panel[tid * ipw + lw] = (tid == js) ? 1.0 : 0.0;
-            if (tid == 0) flags[lw] = (uint8_t)(js + 1);
-        }
-        if (tid == 0) {
-            if (old >= g.base && old < g.base + g.cnt) flags[old - g.base] = 0;
-            sm.slot_item[js] = wit;
-        }
+        js = sm.win.slot;
+        wit = sm.win.item;
+        pv = sm.wrow[js];
+        if (tid == 0) sm.slot_item[js] = wit;
         swaps++;
-        __syncthreads();
     }
     swaps_total += swaps;
+}
+
+// Gather `cnt` items x r entries of W into the slot-major panel, eight
+// independent loads in flight per thread.  col = true: item it, slot j reads
+// W[it][set[j]]; col = false: W[set[j]][it] (coalesced across items).
+template <typename T>
+__device__ int gather_panel(double *panel, const Geo &g, const T *A, int64_t lda, int r, bool col,
+                            const int64_t *set) {
+    int bad = 0;
+    const int tot = g.cnt * r;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += kBlock * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = e0 + u * kBlock;
+            if (e < tot) {
+                const int li = e % g.cnt, j = e / g.cnt;
+                const int64_t it = g.base + li;
+                v[u] = Elem<T>::load(A, col ? it * lda + set[j] : set[j] * lda + it);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = e0 + u * kBlock;
+            if (e < tot) {
+                const int li = e % g.cnt, j = e / g.cnt;
+                if (!isfinite(v[u])) bad = 1;
+                panel[j * g.ipw + li] = v[u];
+            }
+        }
+    }
+    return bad;
 }
 
 // One C-A step.  col = true: panel = W[:, set_in] (items = rows of W);
@@ -385,22 +542,18 @@ __device__ void ca_step(Team &tm, Smem &sm, double *panel, uint8_t *flags, const
                         int64_t lda, int r, bool col, const int64_t *set_in, int64_t *set_out, const CAConfig &cfg,
                         int32_t &swaps_total, int32_t &converged) {
     const Geo g = geo(tm, col ? m : n);
-    int bad = 0;
-    const int tot = g.cnt * r;
-    for (int e = threadIdx.x; e < tot; e += kBlock) {
-        const int li = e % g.cnt, j = e / g.cnt;
-        const int64_t it = g.base + li;
-        const int64_t off = col ? it * lda + set_in[j] : set_in[j] * lda + it;
-        const double v = Elem<T>::load(A, off);
-        if (!isfinite(v)) bad = 1;
-        panel[j * g.ipw + li] = v;
-    }
+    LRA_TR(10 + (col ? 0 : 1), 0);
+    const int bad = gather_panel<T>(panel, g, A, lda, r, col, set_in);
     for (int li = threadIdx.x; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
+    LRA_TR(12, 0);
     maxvol(tm, sm, panel, flags, g, r, cfg.delta, cfg.max_swaps, bad, swaps_total, converged);
-    if (threadIdx.x == 0 && sm.status == LRA_OK) {
-        for (int j = 0; j < r; j++) set_out[j] = sm.slot_item[j];
-        sort_small(set_out, r);
+#ifdef LRA_TRACE
+    LRA_TR(13, sm.t_select);
+#endif
+    if (threadIdx.x < kWave && sm.status == LRA_OK) {
+        if (threadIdx.x < r) set_out[threadIdx.x] = sm.slot_item[threadIdx.x];
+        sort_set_wave(set_out, r);
     }
     __syncthreads();
 }
@@ -409,7 +562,8 @@ __device__ void ca_step(Team &tm, Smem &sm, double *panel, uint8_t *flags, const
 // t = b s + e of D H_{N,d}, Y[item][q] = sqrt(s/l) sum_a W[item][a s + e]
 // D[a s + e] (-1)^{popcount(a & b)} (post-multiplication; pre-multiplication
 // swaps the roles of rows and columns).  Then greedy Householder QRP over the
-// items picks r of them (Algorithm alg1tor).  The chosen items land in out.
+// items picks r of them (Algorithm alg1tor); each reflection is applied
+// lazily, fused with the next norm scan.  The chosen items land in out.
 template <typename T>
 __device__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const T *A, int64_t m, int64_t n,
                            int64_t lda, int r, int side, int d, int l, uint64_t seed, int64_t *out) {
@@ -421,6 +575,7 @@ __device__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, co
     const int64_t N = q2 * s;
     if (tid < kWave) draw_distinct_wave(seed, 2, N, l, sm.samples);
     __syncthreads();
+    LRA_TR(2, 0);
     const double scale = sqrt((double)s / (double)l);
     int bad = 0;
     const int tot = g.cnt * l;
@@ -430,6 +585,7 @@ __device__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, co
         const int64_t t = sm.samples[q];
         const int64_t bb = t / s, ee = t % s;
         double acc = 0.0;
+#pragma unroll 8
         for (int64_t a = 0; a < q2; a++) {
             const int64_t c = a * s + ee;
             if (c >= dim) continue;
@@ -443,57 +599,40 @@ __device__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, co
     }
     for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
+    LRA_TR(3, 0);
     const int ipw = g.ipw;
     for (int gg = 0; gg < r; gg++) {
         Best b = none();
+        const double vtv = sm.vtv;
         for (int li = tid; li < g.cnt; li += kBlock) {
             if (flags[li]) continue;
+            if (gg > 0 && vtv > 0.0) {  // reflection of step gg-1 (vector in sm.wrow[gg-1 ..])
+                double acc = 0.0;
+#pragma unroll 4
+                for (int c = gg - 1; c < l; c++) acc += sm.wrow[c] * panel[c * ipw + li];
+                const double f = 2.0 * acc / vtv;
+#pragma unroll 4
+                for (int c = gg - 1; c < l; c++) panel[c * ipw + li] -= f * sm.wrow[c];
+            }
             double acc = 0.0;
+#pragma unroll 4
             for (int c = gg; c < l; c++) {
                 const double z = panel[c * ipw + li];
                 acc += z * z;
             }
-            consider(b, acc, g.base + li, 0, li);
+            consider(b, acc, g.base + li, 0);
         }
-        team_select(tm, sm, b, gg == 0 ? bad : 0, panel, ipw, l);
-        if (sm.win_flag) {
-            if (tid == 0) sm.status = LRA_EINVAL;
-            __syncthreads();
-            return;
-        }
-        if (!(sm.win.v > 0.0)) {
-            if (tid == 0) {
-                sm.status = LRA_ESINGULAR;
-                sm.rank_found = gg;
-            }
-            __syncthreads();
-            return;
-        }
+        team_select(tm, sm, b, gg == 0 ? bad : 0, panel, g, l, kSelHouseholder, gg);
+        if (sm.win_flag) return fail_status(sm, LRA_EINVAL, 0);
+        if (!(sm.win.v > 0.0)) return fail_status(sm, LRA_ESINGULAR, gg);
         const int64_t wit = sm.win.item;
-        if (tid == 0) {
-            out[gg] = wit;
-            if (wit >= g.base && wit < g.base + g.cnt) flags[wit - g.base] = 1;
-            const double nx = sqrt(sm.win.v);
-            const double x0 = sm.wrow[gg];
-            const double alpha = (x0 >= 0.0) ? -nx : nx;
-            sm.wrow[gg] = x0 - alpha;
-            double vtv = 0.0;
-            for (int c = gg; c < l; c++) vtv += sm.wrow[c] * sm.wrow[c];
-            sm.vtv = vtv;
-        }
-        __syncthreads();
-        const double vtv = sm.vtv;
-        if (vtv > 0.0) {
-            for (int li = tid; li < g.cnt; li += kBlock) {
-                if (flags[li]) continue;
-                double acc = 0.0;
-                for (int c = gg; c < l; c++) acc += sm.wrow[c] * panel[c * ipw + li];
-                const double f = 2.0 * acc / vtv;
-                for (int c = gg; c < l; c++) panel[c * ipw + li] -= f * sm.wrow[c];
-            }
-        }
-        __syncthreads();
+        if (tid == 0) out[gg] = wit;
+        if (wit >= g.base && wit < g.base + g.cnt && (int)((wit - g.base) % kBlock) == tid) flags[wit - g.base] = 1;
     }
+    __syncthreads();
+#ifdef LRA_TRACE
+    LRA_TR(4, sm.t_select);
+#endif
 }
 
 // Nucleus U = G^{-1}, G = W[I, J] (I, J sorted), by LU with partial pivoting
@@ -511,53 +650,72 @@ __device__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, in
         G[e] = v;
         LU[e] = v;
     }
-    if (tid < r) p[tid] = tid;
-    if (tid == 0) sm.logdet = 0.0;
     __syncthreads();
-    for (int k = 0; k < r; k++) {
-        if (tid == 0) {
-            int best = k;
-            double bv = fabs(LU[p[k] * r + k]);
-            for (int i = k + 1; i < r; i++) {
-                const double a = fabs(LU[p[i] * r + k]);
-                if (a > bv || (a == bv && p[i] < p[best])) {
-                    bv = a;
-                    best = i;
+    // LU with partial pivoting in wave 0: lane i works on the row at position
+    // i of the permutation (its original index held in register pi).
+    if (tid < kWave) {
+        const int lane = tid;
+        int pi = lane;
+        double ld = 0.0;
+        int sing = 0;
+        for (int k = 0; k < r; k++) {
+            const bool cand = lane >= k && lane < r;
+            double a = cand ? fabs(LU[pi * r + k]) : -1.0;
+            int key = cand ? pi : 0x7fffffff, who = lane;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                const double oa = __shfl_xor(a, off);
+                const int ok = __shfl_xor(key, off), ow = __shfl_xor(who, off);
+                if (oa > a || (oa == a && ok < key)) {
+                    a = oa;
+                    key = ok;
+                    who = ow;
                 }
             }
-            if (bv == 0.0) {
+            if (a == 0.0) {  // largest magnitude ties go to the lowest row
+                sing = 1;
+                break;
+            }
+            const int p_k = __shfl(pi, k), p_w = __shfl(pi, who);
+            if (lane == k) pi = p_w;
+            else if (lane == who) pi = p_k;
+            ld += log(a);
+            const int prow = p_w;
+            const double piv = LU[prow * r + k];
+            __builtin_amdgcn_wave_barrier();
+            if (lane > k && lane < r) {
+                const double l = LU[pi * r + k] / piv;
+                LU[pi * r + k] = l;
+#pragma unroll 4
+                for (int j = k + 1; j < r; j++) LU[pi * r + j] -= l * LU[prow * r + j];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lane < r) p[lane] = pi;
+        if (lane == 0) {
+            if (sing) {
                 sm.status = LRA_ESINGULAR;
                 sm.rank_found = r - 1;
             } else {
-                const int t = p[k];
-                p[k] = p[best];
-                p[best] = t;
-                sm.logdet += log(bv);
+                sm.logdet = ld;
             }
         }
-        __syncthreads();
-        if (sm.status != LRA_OK) return;
-        const int pk = p[k];
-        const double piv = LU[pk * r + k];
-        for (int i = k + 1 + tid; i < r; i += kBlock) {
-            const int pi = p[i];
-            const double l = LU[pi * r + k] / piv;
-            LU[pi * r + k] = l;
-            for (int j = k + 1; j < r; j++) LU[pi * r + j] -= l * LU[pk * r + j];
-        }
-        __syncthreads();
     }
+    __syncthreads();
+    if (sm.status != LRA_OK) return;
     // column c of G^{-1}: L y = P e_c, U x = y (stored in column c of X)
     for (int c = tid; c < r; c += kBlock) {
         for (int i = 0; i < r; i++) {
             const int pi = p[i];
             double s = (pi == c) ? 1.0 : 0.0;
+#pragma unroll 4
             for (int j = 0; j < i; j++) s -= LU[pi * r + j] * X[j * r + c];
             X[i * r + c] = s;
         }
         for (int i = r - 1; i >= 0; i--) {
             const int pi = p[i];
             double s = X[i * r + c];
+#pragma unroll 4
             for (int j = i + 1; j < r; j++) s -= LU[pi * r + j] * X[j * r + c];
             X[i * r + c] = s / LU[pi * r + i];
         }
@@ -568,6 +726,7 @@ __device__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, in
         for (int e = tid; e < r * r; e += kBlock) {
             const int i = e / r, j = e % r;
             double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll 4
             for (int q = 0; q < r; q++) s -= G[i * r + q] * X[q * r + j];
             Tm[e] = s;
         }
@@ -575,6 +734,7 @@ __device__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, in
         for (int e = tid; e < r * r; e += kBlock) {
             const int i = e / r, j = e % r;
             double s = X[e];
+#pragma unroll 4
             for (int q = 0; q < r; q++) s += X[i * r + q] * Tm[q * r + j];
             X2[e] = s;
         }
@@ -596,15 +756,27 @@ __device__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const 
     if (tid == 0) {
         sm.status = LRA_OK;
         sm.rank_found = r;
+        sm.xfail = 0;
+#ifdef LRA_TRACE
+        sm.t_select = 0;
+#endif
     }
+    LRA_TR(1, 0);
     __syncthreads();
     // ---- start set
     if (cfg.pre == LRA_PRE_ASRHT) {
         const int side = (m > n) ? 1 : 0;
-        sketch_qrp<T>(tm, sm, dyn, flags, A, m, n, lda, r, side, cfg.ah_depth, cfg.ah_samples, seed,
+        // the items x l sketch slice lives in LDS when it fits, else in a
+        // per-workgroup slice of global memory (touched by this workgroup only)
+        double *skp = dyn;
+        if (cfg.sketch_ws) {
+            const int64_t ipw_s = ((side ? n : m) + tm.size - 1) / tm.size;
+            skp = cfg.sketch_ws + (size_t)tm.rank * ipw_s * cfg.ah_samples;
+        }
+        sketch_qrp<T>(tm, sm, skp, flags, A, m, n, lda, r, side, cfg.ah_depth, cfg.ah_samples, seed,
                       side ? sm.Jset : sm.Iset);
         if (sm.status != LRA_OK) goto finish;
-        if (tid == 0) sort_small(side ? sm.Jset : sm.Iset, r);
+        if (tid < kWave) sort_set_wave(side ? sm.Jset : sm.Iset, r);
         __syncthreads();
         if (!side) {
             ca_step<T>(tm, sm, dyn, flags, A, m, n, lda, r, false, sm.Iset, sm.Jset, cfg, swaps_total, converged);
@@ -613,12 +785,14 @@ __device__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const 
     } else if (cfg.init_cols) {
         if (tid < r) sm.Jset[tid] = cfg.init_cols[tid];
         __syncthreads();
-        if (tid == 0) sort_small(sm.Jset, r);
+        if (tid < kWave) sort_set_wave(sm.Jset, r);
         __syncthreads();
     } else {
-        if (tid < kWave) draw_distinct_wave(seed, 0, n, r, sm.Jset);
-        __syncthreads();
-        if (tid == 0) sort_small(sm.Jset, r);
+        if (tid < kWave) {
+            draw_distinct_wave(seed, 0, n, r, sm.Jset);
+            __builtin_amdgcn_wave_barrier();
+            sort_set_wave(sm.Jset, r);
+        }
         __syncthreads();
     }
     // ---- sweeps
@@ -639,11 +813,13 @@ __device__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const 
         }
         __syncthreads();
     }
+    LRA_TR(20, 0);
     if (tm.rank == 0) nucleus<T>(sm, dyn, A, lda, r, cfg.refine_steps, U_out);
+    LRA_TR(21, 0);
 finish:
     __syncthreads();
     if (tm.rank != 0) return;
-    const int st = sm.status;
+    const int st = sm.xfail ? LRA_EDEVICE : sm.status;
     if (tid < r) {
         I_out[tid] = st == LRA_OK ? sm.Iset[tid] : -1;
         J_out[tid] = st == LRA_OK ? sm.Jset[tid] : -1;
@@ -676,9 +852,8 @@ __global__ void __launch_bounds__(kBlock) ca_team_kernel(const T *A, int64_t m, 
     tm.rank = blockIdx.x;
     tm.size = gridDim.x;
     tm.epoch = 0;
-    tm.bar = ws.bar;
-    tm.hdr = ws.hdr;
-    tm.rows = ws.rows;
+    tm.xw = ws.xw;
+    tm.spin_limit = ws.spin_limit;
     ca_solve<T>(tm, sm, dyn, flags, A, m, n, lda, seed, cfg, I_out, J_out, U_out, info);
 }
 
@@ -695,9 +870,8 @@ __global__ void __launch_bounds__(kBlock) ca_batched_kernel(const T *base, const
     tm.rank = 0;
     tm.size = 1;
     tm.epoch = 0;
-    tm.bar = nullptr;
-    tm.hdr = nullptr;
-    tm.rows = nullptr;
+    tm.xw = nullptr;
+    tm.spin_limit = 0;
     const int r = cfg.r;
     for (;;) {
         if (threadIdx.x == 0) sm.job = (int32_t)atomicAdd(queue, 1u);
@@ -718,6 +892,11 @@ __global__ void zero_u32_kernel(unsigned *p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
+__global__ void zero_u64_kernel(uint64_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename T>
 static hipError_t launch_team_t(const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, const CAConfig &cfg,
@@ -726,7 +905,11 @@ static hipError_t launch_team_t(const void *A, int64_t m, int64_t n, int64_t lda
     auto kern = ca_team_kernel<T>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, ws.bar, 1);
+    if (team > 1) {
+        const int64_t words = (int64_t)2 * team * kSlotWords;
+        hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
+                           stream, ws.xw, words);
+    }
     const T *Ap = static_cast<const T *>(A);
     CAConfig c = cfg;
     TeamWs w = ws;
@@ -795,3 +978,16 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
 size_t static_lds_bytes() { return sizeof(Smem) + sizeof(int) * kRMax; }
 
 }  // namespace lra
+
+#ifdef LRA_TRACE
+// Copy the trace of the last traced launches out and reset it (tracing builds only).
+extern "C" int lra_trace_read(uint64_t *host, int max_events) {
+    int n = 0;
+    if (hipMemcpyFromSymbol(&n, HIP_SYMBOL(lra::g_trace_n), sizeof(int)) != hipSuccess) return -1;
+    if (n > max_events) n = max_events;
+    if (n > 0 && hipMemcpyFromSymbol(host, HIP_SYMBOL(lra::g_trace), sizeof(uint64_t) * 2 * n) != hipSuccess) return -1;
+    int z = 0;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(lra::g_trace_n), &z, sizeof(int)) != hipSuccess) return -1;
+    return n;
+}
+#endif

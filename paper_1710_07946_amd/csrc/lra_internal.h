@@ -12,14 +12,10 @@ constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
 constexpr int kRMax = 64;    // largest supported rank
 constexpr int kLMax = 256;   // largest number of sampled SRHT columns
 
-// Team exchange record: one per workgroup and barrier parity.
-struct XchHeader {
-    double val;
-    int64_t item;
-    int32_t slot;
-    int32_t flags;
-    int64_t pad;
-};
+// Team exchange slot (64-bit tagged words): 5 header words (value lo/hi,
+// item lo/hi, slot|flags), then 2 words per row entry.
+constexpr int kHdrWords = 5;
+constexpr int kSlotWords = 8 * ((kHdrWords + 2 * kLMax + 7) / 8);
 
 struct CAConfig {
     int32_t r, sweeps;
@@ -28,12 +24,12 @@ struct CAConfig {
     int32_t pre, ah_depth, ah_samples, refine_steps;
     int32_t panel_bytes;      // offset of the flag bytes inside dynamic LDS
     const int64_t *init_cols; // device copy of the warm-start columns, or null
+    double *sketch_ws;        // global sketch panels [team][ipw * l] when they do not fit LDS, else null
 };
 
 struct TeamWs {
-    unsigned *bar;
-    XchHeader *hdr;   // [2][team]
-    double *rows;     // [2][team][kLMax]
+    uint64_t *xw;         // exchange words [2][team][kSlotWords]
+    uint64_t spin_limit;  // wall-clock ticks one exchange poll may wait before the launch gives up
 };
 
 struct BlockDesc {

@@ -175,10 +175,12 @@ def test_non_finite_entry(lra):
 
 
 # ---------------------------------------------------------------- pre-processing
-@pytest.mark.parametrize("m,n,d,l,team", [(300, 260, 2, 24, 0), (260, 300, 2, 24, 3), (1024, 1000, 3, 40, 6),
-                                          (4000, 700, 3, 64, 16), (333, 333, 0, 20, 2)])
-def test_asrht_start(lra, m, n, d, l, team):
-    r = l // 2
+@pytest.mark.parametrize("m,n,d,l,r,team", [
+    (300, 260, 2, 24, 12, 0), (260, 300, 2, 24, 12, 3), (1024, 1000, 3, 40, 20, 6), (4000, 700, 3, 64, 32, 16),
+    (333, 333, 0, 20, 10, 2),
+    # sketch slice (375 x 256 doubles) too large for LDS: it goes to global memory
+    (3000, 3000, 3, 256, 32, 8)])
+def test_asrht_start(lra, m, n, d, l, r, team):
     A = workloads.factor_gaussian(m, n, r, 1e-7, seeds=(m, n, 3), dtype=np.float32)
     o = oracle.ca_cur(A, r, 3, 2011, preprocess=1, ah_depth=d, ah_samples=l)
     g = gpu_cur(lra, A, r, 3, 2011, preprocess=1, ah_depth=d, ah_samples=l, team_size=team)
