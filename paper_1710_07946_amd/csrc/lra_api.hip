@@ -36,7 +36,7 @@ struct Workspace {
     size_t sketch_cap = 0;          // bytes
 };
 
-constexpr int kMaxTeam = 256;
+using lra::kMaxTeam;
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
@@ -124,11 +124,12 @@ struct LdsPlan {
 LdsPlan plan_lds(int64_t m, int64_t n, int r, int pre, int l, int team, size_t budget) {
     LdsPlan p;
     const int64_t ipw = std::max((m + team - 1) / team, (n + team - 1) / team);
-    size_t cells = std::max((size_t)ipw * r, (size_t)4 * r * r);
+    // panels are slot-major with the slot stride rounded up to odd
+    size_t cells = std::max((size_t)(ipw | 1) * r, (size_t)4 * r * r);
     int64_t flag_items = ipw;
     if (pre == LRA_PRE_ASRHT) {
         p.ipw_s = ((m > n) ? (n + team - 1) / team : (m + team - 1) / team);
-        const size_t sk = (size_t)p.ipw_s * l;
+        const size_t sk = (size_t)(p.ipw_s | 1) * l;
         const size_t with = align16(std::max(cells, sk) * sizeof(double)) + align16(std::max(ipw, p.ipw_s));
         if (with <= budget) {
             cells = std::max(cells, sk);
@@ -197,7 +198,7 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     if (!W || !I_out || !J_out || !U_out) return LRA_EINVAL;
     if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
     if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n || sweeps < 1) return LRA_EINVAL;
-    if (m > ((int64_t)1 << 40) || n > ((int64_t)1 << 40)) return LRA_EINVAL;
+    if (m >= ((int64_t)1 << 39) || n >= ((int64_t)1 << 39)) return LRA_EINVAL;  // item ids travel in 40 bits
     CAConfig cfg;
     lra_opts o;
     lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
@@ -226,15 +227,16 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 1024;
 
     // Team size: the smallest number of workgroups whose panel slices fit in
-    // LDS, but at least one workgroup per 512 items (more workgroups shorten
-    // the per-decision scans, fewer make each team selection cheaper).
+    // LDS, but at least one workgroup per 160 items (more workgroups shorten
+    // the per-decision scans, fewer make each team selection cheaper; 160 was
+    // the best trade-off measured on the 20000 x 20000 rank-50 workload).
     int team;
     LdsPlan plan;
     if (o.team_size > 0) {
         team = std::min(o.team_size, max_team);
         plan = plan_lds(m, n, r, o.preprocess, o.ah_samples, team, lds_budget);
     } else {
-        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, n) + 511) / 512));
+        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, n) + 159) / 160));
         plan = plan_lds(m, n, r, o.preprocess, o.ah_samples, team, lds_budget);
         while (!plan.fits && team < max_team) {
             team++;
@@ -245,7 +247,7 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     cfg.panel_bytes = (int32_t)plan.panel_bytes;
     const size_t dyn = plan.dyn_bytes;
     if (plan.sketch_global) {
-        const size_t need = (size_t)team * plan.ipw_s * o.ah_samples * sizeof(double);
+        const size_t need = (size_t)team * (plan.ipw_s | 1) * o.ah_samples * sizeof(double);
         if (ws->sketch_cap < need) {
             (void)hipStreamSynchronize(stream);
             (void)hipFree(ws->sketch);

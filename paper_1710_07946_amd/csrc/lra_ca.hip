@@ -29,6 +29,7 @@ namespace lra {
 
 constexpr int kWave = 64;
 constexpr int kNWave = kBlock / kWave;
+constexpr int kChunk = 8;  // entries staged in registers per LDS round trip
 
 // ---------------------------------------------------------------- tracing
 // Built with -DLRA_TRACE, workgroup 0 of a launch records phase timestamps
@@ -85,7 +86,7 @@ __device__ __forceinline__ double rademacher(uint64_t seed, int64_t c) {
 // k <= 256 distinct draws from [0, n) in draw order (rejection of the top
 // 2^64 mod n words, duplicates skipped).  Run by all 64 lanes of one wave:
 // 64 counters are hashed at once, then accepted in counter order.
-__device__ void draw_distinct_wave(uint64_t seed, uint64_t stream, int64_t n, int k, int64_t *out) {
+__device__ __forceinline__ void draw_distinct_wave(uint64_t seed, uint64_t stream, int64_t n, int k, int64_t *out) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t un = (uint64_t)n;
     const uint64_t rem = (0 - un) % un;
@@ -180,14 +181,17 @@ struct Smem {
     double alpha;
     double logdet;
 #ifdef LRA_TRACE
-    uint64_t t_select;
+    uint64_t t_select;    // total time inside team selections
+    uint64_t t_part[4];   // block reduce, header polls, row fetch, final barrier
+    uint64_t n_select;
+    uint64_t t_loop[4];   // LU item loop, LU tail, swap item loop, swap tail
 #endif
 };
 
 struct Team {
     int rank, size;
     unsigned epoch;   // number of team selections so far (same in every workgroup)
-    uint64_t *xw;     // exchange words [2][size][kSlotWords], zeroed before the launch
+    uint64_t *xw;     // exchange words: headers [2][size][kHdrWords], then rows [2][size][kRowWords]; zeroed per launch
     uint64_t spin_limit;  // wall-clock ticks a poll may wait
 };
 
@@ -249,6 +253,7 @@ __device__ __forceinline__ void xget(const uint64_t *const (&p)[N], uint32_t tag
 struct Geo {   // item partition of one panel across the team
     int64_t items, base;
     int ipw, cnt;
+    int st;   // slot stride of the slot-major panel: ipw rounded up to odd (spreads LDS banks)
 };
 
 __device__ __forceinline__ Geo geo(const Team &tm, int64_t items) {
@@ -258,7 +263,18 @@ __device__ __forceinline__ Geo geo(const Team &tm, int64_t items) {
     g.base = (int64_t)tm.rank * g.ipw;
     int64_t c = items - g.base;
     g.cnt = (int)(c < 0 ? 0 : (c > g.ipw ? g.ipw : c));
+    g.st = g.ipw | 1;
     return g;
+}
+
+// Lanes that share one item in the maxvol loops: a power of two (at most 16
+// and at most r) small enough that every item of the slice gets its own lane
+// group when possible.  The lanes of a group are consecutive lanes of one
+// wavefront; lane s of a group owns slots s, s + sub, s + 2 sub, ...
+__device__ __forceinline__ int lanes_per_item(int cnt, int r) {
+    int sub = 1;
+    while (sub < 16 && sub * 2 <= r && cnt * sub * 2 <= kBlock) sub *= 2;
+    return sub;
 }
 
 enum SelMode { kSelPlain = 0, kSelHouseholder = 1 };
@@ -269,7 +285,7 @@ enum SelMode { kSelPlain = 0, kSelHouseholder = 1 };
 // costs two workgroup barriers.  With kSelHouseholder, lane 0 also turns
 // sm.wrow into the Householder vector of step `hstep` (oracle order:
 // alpha = -sign(x0) ||x||, v0 = x0 - alpha, vtv = sum of v_c^2 in index order).
-__device__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *panel, const Geo &g, int width,
+__device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *panel, const Geo &g, int width,
                             int mode = kSelPlain, int hstep = 0) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #ifdef LRA_TRACE
@@ -282,6 +298,10 @@ __device__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *
         sm.red_flag[w] = flag;
     }
     __syncthreads();
+#ifdef LRA_TRACE
+    const uint64_t t_a = wall_clock64();
+    uint64_t t_b = t_a, t_c = t_a;
+#endif
     if (w == 0) {
         Best loc = lane < kNWave ? sm.red[lane] : none();
         int f = lane < kNWave ? sm.red_flag[lane] : 0;
@@ -293,49 +313,68 @@ __device__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *
             win = loc;
             wf = f;
             for (int t = lane; t < width; t += kWave)
-                sm.wrow[t] = loc.v >= 0 ? panel[t * g.ipw + (int)(loc.item - g.base)] : 0.0;
+                sm.wrow[t] = loc.v >= 0 ? panel[t * g.st + (int)(loc.item - g.base)] : 0.0;
         } else {
             const uint32_t tag = tm.epoch + 1u;
             const int par = tm.epoch & 1;
-            uint64_t *slots = tm.xw + (size_t)par * tm.size * kSlotWords;
-            uint64_t *mine = slots + (size_t)tm.rank * kSlotWords;
+            // all headers of a parity are contiguous (one coalesced read per
+            // wave); rows live in a separate region
+            uint64_t *hdrs = tm.xw + (size_t)par * tm.size * kHdrWords;
+            uint64_t *rows = tm.xw + (size_t)2 * tm.size * kHdrWords + (size_t)par * tm.size * kRowWords;
+            uint64_t *mine = hdrs + (size_t)tm.rank * kHdrWords;
+            uint64_t *myrow = rows + (size_t)tm.rank * kRowWords;
             for (int t = lane; t < width; t += kWave) {
-                const double x = loc.v >= 0 ? panel[t * g.ipw + (int)(loc.item - g.base)] : 0.0;
+                const double x = loc.v >= 0 ? panel[t * g.st + (int)(loc.item - g.base)] : 0.0;
                 const uint64_t u = (uint64_t)__double_as_longlong(x);
-                xput(mine + kHdrWords + 2 * t, tag, (uint32_t)u);
-                xput(mine + kHdrWords + 2 * t + 1, tag, (uint32_t)(u >> 32));
+                xput(myrow + 2 * t, tag, (uint32_t)u);
+                xput(myrow + 2 * t + 1, tag, (uint32_t)(u >> 32));
             }
             if (lane == 0) {
                 const uint64_t v = (uint64_t)__double_as_longlong(loc.v);
-                const uint64_t it = (uint64_t)loc.item;
+                const uint64_t it = (uint64_t)loc.item;  // < 2^40, or INT64_MAX for "none"
+                const uint32_t hi = it >= (1ull << 40) ? 0xffu : (uint32_t)(it >> 32);
                 xput(mine + 0, tag, (uint32_t)v);
                 xput(mine + 1, tag, (uint32_t)(v >> 32));
                 xput(mine + 2, tag, (uint32_t)it);
-                xput(mine + 3, tag, (uint32_t)(it >> 32));
-                xput(mine + 4, tag, ((uint32_t)(loc.slot & 0xffff) << 16) | (uint32_t)(f & 0xffff));
+                xput(mine + 3, tag, hi | ((uint32_t)(loc.slot & 0xff) << 8) | ((uint32_t)(f & 0xff) << 16));
             }
+            // every lane polls up to kMaxTeam / 64 headers, all loads at once
             Best c = none();
             int cf = 0;
-            for (int g0 = lane; g0 < tm.size; g0 += kWave) {
-                const uint64_t *h = slots + (size_t)g0 * kSlotWords;
-                const uint64_t *const ps[5] = {h, h + 1, h + 2, h + 3, h + 4};
-                uint32_t d[5];
-                xget<5>(ps, tag, d, &sm.xfail, tm.spin_limit);
-                const double v = __longlong_as_double((long long)lo_hi(d[0], d[1]));
-                int sl = (int)(d[4] >> 16);
-                if (sl == 0xffff) sl = 0x7fffffff;
-                consider(c, v, (int64_t)lo_hi(d[2], d[3]), sl, g0);
-                cf |= (int)(d[4] & 0xffff);
+            {
+                const uint64_t *ps[4 * kHdrWords];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const int g0 = min(lane + q * kWave, tm.size - 1);  // past the end: repeat the last
+#pragma unroll
+                    for (int w = 0; w < kHdrWords; w++) ps[q * kHdrWords + w] = hdrs + (size_t)g0 * kHdrWords + w;
+                }
+                uint32_t d[4 * kHdrWords];
+                xget<4 * kHdrWords>(ps, tag, d, &sm.xfail, tm.spin_limit);
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    const uint32_t *h = d + q * kHdrWords;
+                    const double v = __longlong_as_double((long long)lo_hi(h[0], h[1]));
+                    const uint32_t hi = h[3] & 0xffu;
+                    const int64_t it = hi == 0xffu ? INT64_MAX : (int64_t)(((uint64_t)hi << 32) | h[2]);
+                    int sl = (int)((h[3] >> 8) & 0xffu);
+                    if (sl == 0xff) sl = 0x7fffffff;
+                    consider(c, v, it, sl, min(lane + q * kWave, tm.size - 1));
+                    cf |= (int)((h[3] >> 16) & 0xffu);
+                }
             }
             win = wave_reduce(c);
             wf = wave_or(cf);
+#ifdef LRA_TRACE
+            t_b = wall_clock64();
+#endif
             // no candidate in the whole team (every item is in the basis):
             // there is no winner row to fetch
             const bool have = win.v >= 0.0 && win.aux >= 0 && win.aux < tm.size;
             for (int t = lane; t < width; t += kWave) {
                 double x = 0.0;
                 if (have) {
-                    const uint64_t *row = slots + (size_t)win.aux * kSlotWords + kHdrWords + 2 * t;
+                    const uint64_t *row = rows + (size_t)win.aux * kRowWords + 2 * t;
                     const uint64_t *const ps[2] = {row, row + 1};
                     uint32_t d[2];
                     xget<2>(ps, tag, d, &sm.xfail, tm.spin_limit);
@@ -343,6 +382,9 @@ __device__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *
                 }
                 sm.wrow[t] = x;
             }
+#ifdef LRA_TRACE
+            t_c = wall_clock64();
+#endif
             // after a timed-out poll nothing read in this launch can be
             // trusted: report "no candidate", which ends every caller loop
             if (__any(*(volatile int *)&sm.xfail)) {
@@ -366,17 +408,28 @@ __device__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *
             }
         }
     }
+#ifdef LRA_TRACE
+    const uint64_t t_d = wall_clock64();
+#endif
     tm.epoch++;
     __syncthreads();
 #ifdef LRA_TRACE
-    if (threadIdx.x == 0) sm.t_select += wall_clock64() - t_in;
+    if (threadIdx.x == 0) {
+        const uint64_t t_e = wall_clock64();
+        sm.t_select += t_e - t_in;
+        sm.t_part[0] += t_a - t_in;
+        sm.t_part[1] += t_b - t_a;
+        sm.t_part[2] += t_c - t_b;
+        sm.t_part[3] += t_e - t_d;
+        sm.n_select += 1;
+    }
 #endif
 }
 
 // Sort r <= 64 distinct indices in LDS ascending: every lane of one wave
 // takes one entry, counts the entries below it with shuffles and stores it at
 // its rank.
-__device__ void sort_set_wave(int64_t *a, int r) {
+__device__ __forceinline__ void sort_set_wave(int64_t *a, int r) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t x = lane < r ? a[lane] : INT64_MAX;
     int rank = 0;
@@ -399,94 +452,173 @@ __device__ __forceinline__ void fail_status(Smem &sm, int st, int rank) {
 
 // ---------------------------------------------------------------- maxvol
 // Dominant r x r submatrix of the tall panel held in `panel` (slot-major,
-// stride g.ipw): pivoted LU start (Algorithm alggos, stages 1-2), then the
+// stride g.st): pivoted LU start (Algorithm alggos, stages 1-2), then the
 // swaps of Algorithm algdomin with the rank-one update of B.  flags[li] is 0
-// for a candidate item and slot+1 for a basis item; item li is always handled
-// by thread li % kBlock, which alone reads and writes flags[li].  Each
-// elimination step or swap is applied lazily, fused with the scan for the
-// next decision.  On return sm.slot_item holds the basis in slot order.
-// `bad` flags a non-finite entry read by the gather.
-__device__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Geo &g, int r, double delta,
-                       int max_swaps, int bad, int32_t &swaps_total, int32_t &converged) {
+// for a candidate item and slot+1 for a basis item.  Each item is handled by a
+// group of `sub` consecutive lanes of one wavefront (lane s owns slots s,
+// s + sub, ...); all lanes of a group read an item's flag and shared entries
+// before any lane of the group overwrites them (one instruction stream), and
+// lane 0 of the group writes the flag.  Each elimination step or swap is
+// applied lazily, fused with the scan for the next decision; the arithmetic of
+// every entry is the oracle's, in the oracle's order.  On return sm.slot_item
+// holds the basis in slot order.  `bad` flags a non-finite entry gathered.
+__device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Geo &g, int r,
+                                       double delta, int max_swaps, int bad, int32_t &swaps_total, int32_t &converged) {
     const int tid = threadIdx.x;
-    const int ipw = g.ipw;
+    const int st = g.st;
+    const int sub = lanes_per_item(g.cnt, r);
+    const int s = tid % sub;
+    const int grp = tid / sub, ngrp = kBlock / sub;
+    const int jlast = (s < r) ? s + ((r - 1 - s) / sub) * sub : -1;  // last owned slot
     // ---- pivoted LU: r steps; step k eliminates with the pivot row of step
     // k-1 (held in sm.wrow) before scanning column k
     double pk = 1.0;
     for (int k = 0; k < r; k++) {
+#ifdef LRA_TRACE
+        const uint64_t q0 = wall_clock64();
+#endif
         Best b = none();
-        for (int li = tid; li < g.cnt; li += kBlock) {
+        for (int li = grp; li < g.cnt; li += ngrp) {
             if (flags[li]) continue;
             if (k > 0) {
-                const double l = panel[(k - 1) * ipw + li] / pk;
-                panel[(k - 1) * ipw + li] = l;
-#pragma unroll 4
-                for (int j = k; j < r; j++) panel[j * ipw + li] -= l * sm.wrow[j];
+                const double l = panel[(k - 1) * st + li] / pk;
+                const int jf = (k <= s) ? s : s + ((k - s + sub - 1) / sub) * sub;  // first owned slot >= k
+                for (int j0 = jf; j0 <= jlast; j0 += kChunk * sub) {
+                    double x[kChunk], w[kChunk];
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) {
+                        const int j = min(j0 + u * sub, jlast);  // past the end: repeat the last owned slot
+                        x[u] = panel[j * st + li];
+                        w[u] = sm.wrow[j];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) panel[min(j0 + u * sub, jlast) * st + li] = x[u] - l * w[u];
+                }
+                if ((k - 1) % sub == s) panel[(k - 1) * st + li] = l;
             }
-            consider(b, fabs(panel[k * ipw + li]), g.base + li, 0);
+            if (k % sub == s) consider(b, fabs(panel[k * st + li]), g.base + li, 0);
         }
         if (k > 0 && tid < k - 1) sm.L11[(k - 1) * (k - 2) / 2 + tid] = sm.wrow[tid];
+#ifdef LRA_TRACE
+        const uint64_t q1 = wall_clock64();
+        if (tid == 0) sm.t_loop[0] += q1 - q0;
+#endif
         team_select(tm, sm, b, k == 0 ? bad : 0, panel, g, r);
+#ifdef LRA_TRACE
+        const uint64_t q2 = wall_clock64();
+#endif
         if (sm.win_flag) return fail_status(sm, LRA_EINVAL, 0);
         if (!(sm.win.v > 0.0)) return fail_status(sm, LRA_ESINGULAR, k);
         const int64_t wit = sm.win.item;
         if (tid == 0) sm.slot_item[k] = wit;
-        if (wit >= g.base && wit < g.base + g.cnt && (int)((wit - g.base) % kBlock) == tid)
-            flags[wit - g.base] = (uint8_t)(k + 1);
+        if (wit >= g.base && wit < g.base + g.cnt) {
+            const int lw = (int)(wit - g.base);
+            if (lw % ngrp == grp && s == 0) flags[lw] = (uint8_t)(k + 1);
+        }
         pk = sm.wrow[k];
+#ifdef LRA_TRACE
+        if (tid == 0) sm.t_loop[1] += wall_clock64() - q2;
+#endif
     }
     // last multipliers (no trailing columns), last row of L11
-    for (int li = tid; li < g.cnt; li += kBlock)
-        if (!flags[li]) panel[(r - 1) * ipw + li] /= pk;
+    for (int li = grp; li < g.cnt; li += ngrp)
+        if (!flags[li] && (r - 1) % sub == s) panel[(r - 1) * st + li] /= pk;
     if (tid < r - 1) sm.L11[(r - 1) * (r - 2) / 2 + tid] = sm.wrow[tid];
     __syncthreads();
-    // ---- B = L21 L11^{-1} for candidates and unit rows for the basis,
-    // fused with the first swap scan; then swaps, each update fused with the
-    // next scan
+    // ---- B = L21 L11^{-1}: one lane per item solves x L11 = l_i from the
+    // last entry backwards; basis items get unit rows
+    for (int li = grp; li < g.cnt; li += ngrp) {
+        const int fl = flags[li];
+        if (fl) {
+            for (int j = s; j < r; j += sub) panel[j * st + li] = (j == fl - 1) ? 1.0 : 0.0;
+            continue;
+        }
+        if (s != 0) continue;
+        for (int j = r - 1; j >= 0; j--) {
+            double sj = panel[j * st + li];
+            for (int k0 = j + 1; k0 < r; k0 += kChunk) {
+                double x[kChunk], c[kChunk];
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) {
+                    const int kk = min(k0 + u, r - 1);
+                    x[u] = panel[kk * st + li];
+                    c[u] = sm.L11[kk * (kk - 1) / 2 + j];
+                }
+                // terms past the end subtract +0.0, which leaves the sum unchanged
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) sj -= (k0 + u < r) ? x[u] * c[u] : 0.0;
+            }
+            panel[j * st + li] = sj;
+        }
+    }
+    __syncthreads();
+    // ---- swaps; each update is fused with the next scan
     const double thr = 1.0 + delta;
     int swaps = 0;
     int js = -1;
     int64_t wit = -1;
     double pv = 1.0;
     for (;;) {
+#ifdef LRA_TRACE
+        const uint64_t q0 = wall_clock64();
+#endif
         Best b = none();
-        for (int li = tid; li < g.cnt; li += kBlock) {
+        for (int li = grp; li < g.cnt; li += ngrp) {
             const int fl = flags[li];
             const int64_t it = g.base + li;
-            if (js < 0) {
-                if (fl) {
-                    for (int j = 0; j < r; j++) panel[j * ipw + li] = (j == fl - 1) ? 1.0 : 0.0;
+            double f = 0.0;
+            if (js >= 0) {
+                if (it == wit) {  // enters the basis in slot js
+                    for (int j = s; j < r; j += sub) panel[j * st + li] = (j == js) ? 1.0 : 0.0;
+                    if (s == 0) flags[li] = (uint8_t)(js + 1);
                     continue;
                 }
-                for (int j = r - 1; j >= 0; j--) {
-                    double s = panel[j * ipw + li];
-#pragma unroll 4
-                    for (int kk = j + 1; kk < r; kk++) s -= panel[kk * ipw + li] * sm.L11[kk * (kk - 1) / 2 + j];
-                    panel[j * ipw + li] = s;
-                }
-            } else if (it == wit) {  // enters the basis in slot js
-                for (int j = 0; j < r; j++) panel[j * ipw + li] = (j == js) ? 1.0 : 0.0;
-                flags[li] = (uint8_t)(js + 1);
-                continue;
-            } else if (fl == 0 || fl == js + 1) {  // other basis rows have B[i][js] = 0
-                const double f = panel[js * ipw + li] / pv;
-                if (f != 0.0)
-#pragma unroll 4
-                    for (int j = 0; j < r; j++) {
-                        const double d = (j == js) ? sm.wrow[j] - 1.0 : sm.wrow[j];  // B[i*,:] - e_js^T
-                        panel[j * ipw + li] -= f * d;
-                    }
-                if (fl) {
-                    flags[li] = 0;  // leaves the basis
-                }
-            } else {
+                if (fl != 0 && fl != js + 1) continue;  // other basis rows: B[i][js] = 0
+                f = panel[js * st + li] / pv;
+                if (fl && s == 0) flags[li] = 0;  // the old basis item leaves the basis
+            } else if (fl) {
                 continue;
             }
-            if (flags[li]) continue;
-#pragma unroll 4
-            for (int j = 0; j < r; j++) consider(b, fabs(panel[j * ipw + li]), it, j);
+            // B[i,:] -= f (B[i*,:] - e_js^T) on the owned slots, and the scan of
+            // the owned slots (largest magnitude, lowest slot among equals)
+            double vb = -1.0;
+            int jb = 0;
+            for (int j0 = s; j0 <= jlast; j0 += kChunk * sub) {
+                double x[kChunk], w[kChunk];
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) {
+                    const int j = min(j0 + u * sub, jlast);
+                    x[u] = panel[j * st + li];
+                    w[u] = sm.wrow[j];
+                }
+                if (f != 0.0) {
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) {
+                        const int j = min(j0 + u * sub, jlast);
+                        const double d = (j == js) ? w[u] - 1.0 : w[u];
+                        x[u] -= f * d;
+                        panel[j * st + li] = x[u];
+                    }
+                }
+                // a repeated last slot comes after the real one: strict > keeps it
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) {
+                    const double a = fabs(x[u]);
+                    const bool up = a > vb;
+                    vb = up ? a : vb;
+                    jb = up ? min(j0 + u * sub, jlast) : jb;
+                }
+            }
+            if (jlast >= 0) consider(b, vb, it, jb);
         }
+#ifdef LRA_TRACE
+        const uint64_t q1 = wall_clock64();
+        if (tid == 0) sm.t_loop[2] += q1 - q0;
+#endif
         team_select(tm, sm, b, 0, panel, g, r);
+#ifdef LRA_TRACE
+        const uint64_t q2 = wall_clock64();
+#endif
         const double v = sm.win.v;
         if (v < 0.0 || v <= thr) break;  // no candidate left, or dominant
         if (swaps >= max_swaps) {
@@ -498,6 +630,9 @@ __device__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_t *flags, const 
         pv = sm.wrow[js];
         if (tid == 0) sm.slot_item[js] = wit;
         swaps++;
+#ifdef LRA_TRACE
+        if (tid == 0) sm.t_loop[3] += wall_clock64() - q2;
+#endif
     }
     swaps_total += swaps;
 }
@@ -506,7 +641,7 @@ __device__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_t *flags, const 
 // independent loads in flight per thread.  col = true: item it, slot j reads
 // W[it][set[j]]; col = false: W[set[j]][it] (coalesced across items).
 template <typename T>
-__device__ int gather_panel(double *panel, const Geo &g, const T *A, int64_t lda, int r, bool col,
+__device__ __forceinline__ int gather_panel(double *panel, const Geo &g, const T *A, int64_t lda, int r, bool col,
                             const int64_t *set) {
     int bad = 0;
     const int tot = g.cnt * r;
@@ -527,7 +662,7 @@ __device__ int gather_panel(double *panel, const Geo &g, const T *A, int64_t lda
             if (e < tot) {
                 const int li = e % g.cnt, j = e / g.cnt;
                 if (!isfinite(v[u])) bad = 1;
-                panel[j * g.ipw + li] = v[u];
+                panel[j * g.st + li] = v[u];
             }
         }
     }
@@ -538,7 +673,7 @@ __device__ int gather_panel(double *panel, const Geo &g, const T *A, int64_t lda
 // col = false: panel = W[set_in, :]^T (items = columns).  set_out receives
 // the new sorted set.
 template <typename T>
-__device__ void ca_step(Team &tm, Smem &sm, double *panel, uint8_t *flags, const T *A, int64_t m, int64_t n,
+__device__ __forceinline__ void ca_step(Team &tm, Smem &sm, double *panel, uint8_t *flags, const T *A, int64_t m, int64_t n,
                         int64_t lda, int r, bool col, const int64_t *set_in, int64_t *set_out, const CAConfig &cfg,
                         int32_t &swaps_total, int32_t &converged) {
     const Geo g = geo(tm, col ? m : n);
@@ -565,7 +700,7 @@ __device__ void ca_step(Team &tm, Smem &sm, double *panel, uint8_t *flags, const
 // items picks r of them (Algorithm alg1tor); each reflection is applied
 // lazily, fused with the next norm scan.  The chosen items land in out.
 template <typename T>
-__device__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const T *A, int64_t m, int64_t n,
+__device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const T *A, int64_t m, int64_t n,
                            int64_t lda, int r, int side, int d, int l, uint64_t seed, int64_t *out) {
     const int tid = threadIdx.x;
     const int64_t dim = side ? m : n;
@@ -595,30 +730,51 @@ __device__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, co
         }
         const double y = scale * acc;
         if (!isfinite(y)) bad = 1;
-        panel[q * g.ipw + li] = y;
+        panel[q * g.st + li] = y;
     }
     for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
     LRA_TR(3, 0);
-    const int ipw = g.ipw;
+    const int ipw = g.st;
     for (int gg = 0; gg < r; gg++) {
         Best b = none();
         const double vtv = sm.vtv;
         for (int li = tid; li < g.cnt; li += kBlock) {
             if (flags[li]) continue;
             if (gg > 0 && vtv > 0.0) {  // reflection of step gg-1 (vector in sm.wrow[gg-1 ..])
+                // (terms past the end add +0.0 to a sum that is never -0.0)
                 double acc = 0.0;
-#pragma unroll 4
-                for (int c = gg - 1; c < l; c++) acc += sm.wrow[c] * panel[c * ipw + li];
+                for (int c0 = gg - 1; c0 < l; c0 += kChunk) {
+                    double z[kChunk], w[kChunk];
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) {
+                        const int c = min(c0 + u, l - 1);
+                        z[u] = panel[c * ipw + li];
+                        w[u] = sm.wrow[c];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) acc += (c0 + u < l) ? w[u] * z[u] : 0.0;
+                }
                 const double f = 2.0 * acc / vtv;
-#pragma unroll 4
-                for (int c = gg - 1; c < l; c++) panel[c * ipw + li] -= f * sm.wrow[c];
+                for (int c0 = gg - 1; c0 < l; c0 += kChunk) {
+                    double z[kChunk], w[kChunk];
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) {
+                        const int c = min(c0 + u, l - 1);
+                        z[u] = panel[c * ipw + li];
+                        w[u] = sm.wrow[c];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) panel[min(c0 + u, l - 1) * ipw + li] = z[u] - f * w[u];
+                }
             }
             double acc = 0.0;
-#pragma unroll 4
-            for (int c = gg; c < l; c++) {
-                const double z = panel[c * ipw + li];
-                acc += z * z;
+            for (int c0 = gg; c0 < l; c0 += kChunk) {
+                double z[kChunk];
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) z[u] = panel[min(c0 + u, l - 1) * ipw + li];
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) acc += (c0 + u < l) ? z[u] * z[u] : 0.0;
             }
             consider(b, acc, g.base + li, 0);
         }
@@ -640,7 +796,7 @@ __device__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, co
 // X <- X + X (I - G X) (Algorithm algcnnncl with k = l = r).  One workgroup;
 // `ws` holds 4 r^2 doubles.  Writes U (row-major, J-order x I-order).
 template <typename T>
-__device__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, int refine, double *U_out) {
+__device__ __forceinline__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, int refine, double *U_out) {
     const int tid = threadIdx.x;
     double *G = ws, *LU = ws + r * r, *X = ws + 2 * r * r, *X2 = ws + 3 * r * r;
     __shared__ int p[kRMax];
@@ -686,8 +842,17 @@ __device__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, in
             if (lane > k && lane < r) {
                 const double l = LU[pi * r + k] / piv;
                 LU[pi * r + k] = l;
-#pragma unroll 4
-                for (int j = k + 1; j < r; j++) LU[pi * r + j] -= l * LU[prow * r + j];
+                for (int j0 = k + 1; j0 < r; j0 += kChunk) {
+                    double a[kChunk], u_[kChunk];
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) {
+                        const int j = min(j0 + u, r - 1);
+                        a[u] = LU[pi * r + j];
+                        u_[u] = LU[prow * r + j];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) LU[pi * r + min(j0 + u, r - 1)] = a[u] - l * u_[u];
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
@@ -708,15 +873,33 @@ __device__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, in
         for (int i = 0; i < r; i++) {
             const int pi = p[i];
             double s = (pi == c) ? 1.0 : 0.0;
-#pragma unroll 4
-            for (int j = 0; j < i; j++) s -= LU[pi * r + j] * X[j * r + c];
+            for (int j0 = 0; j0 < i; j0 += kChunk) {
+                double a[kChunk], x[kChunk];
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) {
+                    const int j = min(j0 + u, i - 1);
+                    a[u] = LU[pi * r + j];
+                    x[u] = X[j * r + c];
+                }
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) s -= (j0 + u < i) ? a[u] * x[u] : 0.0;
+            }
             X[i * r + c] = s;
         }
         for (int i = r - 1; i >= 0; i--) {
             const int pi = p[i];
             double s = X[i * r + c];
-#pragma unroll 4
-            for (int j = i + 1; j < r; j++) s -= LU[pi * r + j] * X[j * r + c];
+            for (int j0 = i + 1; j0 < r; j0 += kChunk) {
+                double a[kChunk], x[kChunk];
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) {
+                    const int j = min(j0 + u, r - 1);
+                    a[u] = LU[pi * r + j];
+                    x[u] = X[j * r + c];
+                }
+#pragma unroll
+                for (int u = 0; u < kChunk; u++) s -= (j0 + u < r) ? a[u] * x[u] : 0.0;
+            }
             X[i * r + c] = s / LU[pi * r + i];
         }
     }
@@ -747,18 +930,22 @@ __device__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, in
 
 // The whole C-A path for one matrix, executed by every workgroup of a team.
 template <typename T>
-__device__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const T *A, int64_t m, int64_t n,
+__device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const T *A, int64_t m, int64_t n,
                          int64_t lda, uint64_t seed, const CAConfig &cfg, int64_t *I_out, int64_t *J_out,
                          double *U_out, lra_info *info) {
     const int tid = threadIdx.x;
     const int r = cfg.r;
     int32_t swaps_total = 0, converged = 1, sweeps_run = 0;
+    int seed_step = 0;
     if (tid == 0) {
         sm.status = LRA_OK;
         sm.rank_found = r;
         sm.xfail = 0;
 #ifdef LRA_TRACE
         sm.t_select = 0;
+        sm.t_part[0] = sm.t_part[1] = sm.t_part[2] = sm.t_part[3] = 0;
+        sm.n_select = 0;
+        sm.t_loop[0] = sm.t_loop[1] = sm.t_loop[2] = sm.t_loop[3] = 0;
 #endif
     }
     LRA_TR(1, 0);
@@ -768,20 +955,19 @@ __device__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const 
         const int side = (m > n) ? 1 : 0;
         // the items x l sketch slice lives in LDS when it fits, else in a
         // per-workgroup slice of global memory (touched by this workgroup only)
-        double *skp = dyn;
+        // (two call sites so that each copy knows its panel's address space)
         if (cfg.sketch_ws) {
-            const int64_t ipw_s = ((side ? n : m) + tm.size - 1) / tm.size;
-            skp = cfg.sketch_ws + (size_t)tm.rank * ipw_s * cfg.ah_samples;
+            const int64_t st_s = (((side ? n : m) + tm.size - 1) / tm.size) | 1;
+            sketch_qrp<T>(tm, sm, cfg.sketch_ws + (size_t)tm.rank * st_s * cfg.ah_samples, flags, A, m, n, lda, r,
+                          side, cfg.ah_depth, cfg.ah_samples, seed, side ? sm.Jset : sm.Iset);
+        } else {
+            sketch_qrp<T>(tm, sm, dyn, flags, A, m, n, lda, r, side, cfg.ah_depth, cfg.ah_samples, seed,
+                          side ? sm.Jset : sm.Iset);
         }
-        sketch_qrp<T>(tm, sm, skp, flags, A, m, n, lda, r, side, cfg.ah_depth, cfg.ah_samples, seed,
-                      side ? sm.Jset : sm.Iset);
         if (sm.status != LRA_OK) goto finish;
         if (tid < kWave) sort_set_wave(side ? sm.Jset : sm.Iset, r);
         __syncthreads();
-        if (!side) {
-            ca_step<T>(tm, sm, dyn, flags, A, m, n, lda, r, false, sm.Iset, sm.Jset, cfg, swaps_total, converged);
-            if (sm.status != LRA_OK) goto finish;
-        }
+        seed_step = side ? 0 : 1;  // a row start set needs one row step first
     } else if (cfg.init_cols) {
         if (tid < r) sm.Jset[tid] = cfg.init_cols[tid];
         __syncthreads();
@@ -795,14 +981,17 @@ __device__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const 
         }
         __syncthreads();
     }
-    // ---- sweeps
-    for (int s = 0; s < cfg.sweeps; s++) {
-        ca_step<T>(tm, sm, dyn, flags, A, m, n, lda, r, true, sm.Jset, sm.Iset, cfg, swaps_total, converged);
+    // ---- steps: the optional seed row step, then a column step and a row
+    // step per sweep (one call site: the step is inlined once)
+    for (int st = 0; st < seed_step + 2 * cfg.sweeps; st++) {
+        const bool col = st >= seed_step && ((st - seed_step) & 1) == 0;
+        ca_step<T>(tm, sm, dyn, flags, A, m, n, lda, r, col, col ? sm.Jset : sm.Iset, col ? sm.Iset : sm.Jset, cfg,
+                   swaps_total, converged);
         if (sm.status != LRA_OK) goto finish;
-        ca_step<T>(tm, sm, dyn, flags, A, m, n, lda, r, false, sm.Iset, sm.Jset, cfg, swaps_total, converged);
-        if (sm.status != LRA_OK) goto finish;
-        sweeps_run = s + 1;
-        bool same = s > 0;
+        if (st < seed_step || col) continue;
+        const int sw = (st - seed_step) / 2;  // sweep sw is complete
+        sweeps_run = sw + 1;
+        bool same = sw > 0;
         for (int j = 0; j < r && same; j++)
             same = (sm.Iset[j] == sm.Iprev[j]) && (sm.Jset[j] == sm.Jprev[j]);
         __syncthreads();
@@ -814,6 +1003,17 @@ __device__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const 
         __syncthreads();
     }
     LRA_TR(20, 0);
+#ifdef LRA_TRACE
+    LRA_TR(30, sm.t_part[0]);
+    LRA_TR(31, sm.t_part[1]);
+    LRA_TR(32, sm.t_part[2]);
+    LRA_TR(33, sm.t_part[3]);
+    LRA_TR(34, sm.n_select);
+    LRA_TR(35, sm.t_loop[0]);
+    LRA_TR(36, sm.t_loop[1]);
+    LRA_TR(37, sm.t_loop[2]);
+    LRA_TR(38, sm.t_loop[3]);
+#endif
     if (tm.rank == 0) nucleus<T>(sm, dyn, A, lda, r, cfg.refine_steps, U_out);
     LRA_TR(21, 0);
 finish:
@@ -906,7 +1106,7 @@ static hipError_t launch_team_t(const void *A, int64_t m, int64_t n, int64_t lda
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     if (team > 1) {
-        const int64_t words = (int64_t)2 * team * kSlotWords;
+        const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
         hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
                            stream, ws.xw, words);
     }

@@ -8,14 +8,17 @@
 
 namespace lra {
 
-constexpr int kBlock = 256;  // threads per workgroup (4 wavefronts)
+constexpr int kBlock = 512;  // threads per workgroup (8 wavefronts, two per SIMD)
 constexpr int kRMax = 64;    // largest supported rank
 constexpr int kLMax = 256;   // largest number of sampled SRHT columns
 
-// Team exchange slot (64-bit tagged words): 5 header words (value lo/hi,
-// item lo/hi, slot|flags), then 2 words per row entry.
-constexpr int kHdrWords = 5;
-constexpr int kSlotWords = 8 * ((kHdrWords + 2 * kLMax + 7) / 8);
+// Team exchange (64-bit tagged words): per workgroup and parity 4 header
+// words (value lo, value hi, item lo, item hi | slot << 8 | flags << 16) and
+// 2 words per row entry.
+constexpr int kHdrWords = 4;
+constexpr int kMaxTeam = 256;
+constexpr int kRowWords = 2 * kLMax;
+constexpr int kSlotWords = kHdrWords + kRowWords;  // exchange words per workgroup and parity
 
 struct CAConfig {
     int32_t r, sweeps;
