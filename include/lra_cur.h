@@ -109,6 +109,43 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream);
 
+/* Moments of the residual E = W - C U R of a CUR (C = W[:, J], R = W[I, :],
+ * U r x r as returned by lra_cur), for the a-posteriori error estimate of
+ * Section 4 (a random q x s submatrix of E whose entries are treated as
+ * samples of one variable) or for the exact relative error.
+ *   q = s = 0     every entry of W;
+ *   1..256 each   q rows and s columns drawn (distinct, seeded SplitMix64
+ *                 streams 3 and 4 of `seed`).
+ *   I, J  device int64[r]; U device double[r * r];
+ *   moments  device double[4]: sum e, sum e^2, sum |e|, sum w^2 over the
+ *            entries used (relative Frobenius error = sqrt(m[1] / m[3])).
+ * An entry of I or J outside the matrix is not read; it makes the moments NaN.
+ * Computed in FP64; asynchronous on `stream`.  LRA_EUNSUPPORTED when more
+ * than 64 * 65535 rows are used. */
+lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, const int64_t *I,
+                        const int64_t *J, const double *U, int32_t q, int32_t s, uint64_t seed, double *moments,
+                        hipStream_t stream);
+
+/* Adjoint of the CUR reconstruction at fixed index sets, for `count` blocks
+ * of equal shape (the paper has no adjoint; this is the derivative of
+ * W' = C G^{-1} R with the generator G = W[I, J] as an independent input):
+ *   L_b = sum over (i, j) in Omega_b of (a_ij - (C_b G_b^{-1} R_b)_ij)^2,
+ *   dC = Ebar Z^T, dR = G^{-T} C^T Ebar, dG = -G^{-T} C^T Ebar Z^T,
+ *   with Z = G^{-1} R and Ebar = -2 (a - C Z) on Omega.
+ * All pointers are device pointers, FP64 row-major, blocks packed one after
+ * another: C count x m x r, R count x r x n, G count x r x r.  Omega has nnz
+ * entries per block given as om_row / om_col (int32, sorted by row then
+ * column), col_order (int32, the stable permutation that sorts the entries
+ * by column) and a_om (the values of W there).  Outputs: loss[count],
+ * dC, dR, dG (shapes of C, R, G), status[count]: LRA_OK, LRA_ESINGULAR when
+ * G_b is singular, LRA_EINVAL when an Omega index of block b lies outside
+ * the block (then loss[b] is NaN and that block's gradients are not written).
+ * Deterministic: every sum runs in a fixed order. */
+lra_status lra_cur_adjoint(int64_t count, int64_t m, int64_t n, int32_t r, const double *C, const double *R,
+                           const double *G, int64_t nnz, const int32_t *om_row, const int32_t *om_col,
+                           const int32_t *col_order, const double *a_om, double *loss, double *dC, double *dR,
+                           double *dG, int32_t *status, hipStream_t stream);
+
 /* Free every cached workspace of the calling process. */
 void lra_release(void);
 

@@ -69,8 +69,9 @@ def lib():
         L.orc_ca_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, u64, P, P, P, P, P]
         L.orc_residual.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, P, P]
         L.orc_cur_adjoint.argtypes = [P, P, P, i64, i64, ct.c_int, P, P, P, i64, P, P, P, P]
+        L.orc_residual_moments.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, i64, i64, u64, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
-                  "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint"):
+                  "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -248,6 +249,21 @@ def residual(A: np.ndarray, I, J, U):
     if st:
         raise ValueError("residual: status %d" % st)
     return e2.value, w2.value
+
+
+def residual_moments(A, I, J, U, q: int = 0, s: int = 0, seed: int = 0) -> np.ndarray:
+    """[sum e, sum e^2, sum |e|, sum w^2] over all entries (q = s = 0) or a seeded q x s sample."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    I = np.ascontiguousarray(I, np.int64)
+    J = np.ascontiguousarray(J, np.int64)
+    U = np.ascontiguousarray(U, np.float64)
+    out = np.zeros(4)
+    st = lib().orc_residual_moments(_p(A), _dtype_code(A), m, n, n, len(I), _p(I), _p(J), _p(U), q, s, seed,
+                                    _p(out))
+    if st:
+        raise ValueError("residual_moments: status %d" % st)
+    return out
 
 
 def rel_fro(A, I, J, U) -> float:

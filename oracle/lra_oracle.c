@@ -696,3 +696,56 @@ int orc_cur_adjoint(const double *C, const double *R, const double *G, int64_t m
     free(Gi); free(Z); free(dZ);
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Residual moments over all entries (q = 0) or over a random q x s          */
+/* submatrix of E = W - C U R (a-posteriori estimation, Section 4: sample a  */
+/* q x s submatrix of the error matrix, qs >= 100 or so, and use the observed */
+/* statistics of its entries).  Rows are q distinct draws from stream 3,     */
+/* columns s distinct draws from stream 4 of SplitMix64(seed).               */
+/* out[0] = sum e, out[1] = sum e^2, out[2] = sum |e|, out[3] = sum w^2.     */
+/* ------------------------------------------------------------------------ */
+int orc_residual_moments(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,
+                         const int64_t *J, const double *U, int64_t q, int64_t s, uint64_t seed, double *out) {
+    if (!A || !I || !J || !U || !out || r < 1 || m < 1 || n < 1 || lda < n || q < 0 || s < 0 || q > m || s > n ||
+        ((q == 0) != (s == 0)))
+        return ORC_EINVAL;
+    int64_t nq = q ? q : m, ns = s ? s : n;
+    int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)nq);
+    int64_t *cols = (int64_t *)malloc(sizeof(int64_t) * (size_t)ns);
+    if (q) {
+        orc_draw_distinct(seed, 3, m, q, rows);
+        orc_draw_distinct(seed, 4, n, s, cols);
+    } else {
+        for (int64_t i = 0; i < m; i++) rows[i] = i;
+        for (int64_t j = 0; j < n; j++) cols[j] = j;
+    }
+    /* UR = U * W[I, cols]  (r x ns) */
+    double *UR = (double *)calloc((size_t)r * (size_t)ns, sizeof(double));
+    for (int a = 0; a < r; a++)
+        for (int b = 0; b < r; b++) {
+            double u = U[a * r + b];
+            for (int64_t c = 0; c < ns; c++) UR[a * ns + c] += u * orc_get(A, dtype, lda, I[b], cols[c]);
+        }
+    double se = 0.0, se2 = 0.0, sabs = 0.0, sw2 = 0.0;
+    double *cr = (double *)malloc(sizeof(double) * (size_t)r);
+    for (int64_t ii = 0; ii < nq; ii++) {
+        for (int a = 0; a < r; a++) cr[a] = orc_get(A, dtype, lda, rows[ii], J[a]);
+        for (int64_t c = 0; c < ns; c++) {
+            double x = 0.0;
+            for (int a = 0; a < r; a++) x += cr[a] * UR[a * ns + c];
+            double w = orc_get(A, dtype, lda, rows[ii], cols[c]);
+            double e = w - x;
+            se += e;
+            se2 += e * e;
+            sabs += fabs(e);
+            sw2 += w * w;
+        }
+    }
+    out[0] = se;
+    out[1] = se2;
+    out[2] = sabs;
+    out[3] = sw2;
+    free(rows); free(cols); free(UR); free(cr);
+    return ORC_OK;
+}

@@ -75,6 +75,10 @@ def load() -> ct.CDLL:
         L.lra_cur_batched.argtypes = [P, ct.c_int, ct.POINTER(lra_block), i64, i32, i32, ct.c_uint64,
                                       ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_batched.restype = ct.c_int
+        L.lra_residual.argtypes = [P, ct.c_int, i64, i64, i64, i32, P, P, P, i32, i32, ct.c_uint64, P, P]
+        L.lra_residual.restype = ct.c_int
+        L.lra_cur_adjoint.argtypes = [i64, i64, i64, i32, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
+        L.lra_cur_adjoint.restype = ct.c_int
         _lib = L
     return _lib
 
@@ -227,3 +231,100 @@ def lra_cur_batched(base, blocks, r: int, sweeps: int, seed: int, *, delta: floa
     if st != LRA_OK:
         raise LraError(st, "lra_cur_batched")
     return out
+
+
+def lra_residual(A, I, J, U, q: int = 0, s: int = 0, seed: int = 0, out=None, stream=None):
+    """Residual moments [sum e, sum e^2, sum |e|, sum w^2] of E = A - A[:, J] U A[I, :]
+    over all entries (q = s = 0) or a seeded q x s sample; a device float64[4]."""
+    torch = _torch()
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor with unit column stride")
+    m, n = A.shape
+    r = int(I.numel())
+    for t, dt in ((I, torch.int64), (J, torch.int64), (U, torch.float64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("I, J must be contiguous int64 and U contiguous float64 device tensors")
+    if out is None:
+        out = torch.empty(4, dtype=torch.float64, device=A.device)
+    st = load().lra_residual(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r,
+                             ct.c_void_p(I.data_ptr()), ct.c_void_p(J.data_ptr()), ct.c_void_p(U.data_ptr()), q, s,
+                             ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    if st != LRA_OK:
+        raise LraError(st, "lra_residual")
+    return out
+
+
+def omega_column_order(om_row, om_col):
+    """Stable permutation sorting each block's Omega entries by column (int32).
+    Part of the sparse input format of lra_cur_adjoint (like building CSC from CSR)."""
+    torch = _torch()
+    cols = om_col.to(torch.int64)
+    rows = om_row.to(torch.int64)
+    # entries are sorted by (row, col); sorting by col * (max_row + 1) + row keeps row order within a column
+    key = cols * (int(rows.max().item()) + 1 if rows.numel() else 1) + rows
+    return torch.argsort(key, dim=-1).to(torch.int32).contiguous()
+
+
+def lra_cur_adjoint(C, R, G, om_row, om_col, col_order, a_om, stream=None):
+    """Loss and gradients of sum over Omega of (a - C G^{-1} R)^2 for a batch of blocks.
+
+    C (count, m, r), R (count, r, n), G (count, r, r): float64 device tensors;
+    om_row, om_col, col_order (count, nnz) int32; a_om (count, nnz) float64.
+    Returns (loss (count,), dC, dR, dG, status (count,) int32)."""
+    torch = _torch()
+    count, m, r = C.shape
+    n = R.shape[2]
+    nnz = om_row.shape[1] if om_row.dim() == 2 else 0
+    for t in (C, R, G, a_om):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise ValueError("C, R, G, a_om must be contiguous float64 device tensors")
+    for t in (om_row, om_col, col_order):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous():
+            raise ValueError("om_row, om_col, col_order must be contiguous int32 device tensors")
+    if R.shape != (count, r, n) or G.shape != (count, r, r) or a_om.shape != (count, nnz):
+        raise ValueError("inconsistent shapes")
+    dev = C.device
+    loss = torch.empty(count, dtype=torch.float64, device=dev)
+    dC, dR, dG = torch.empty_like(C), torch.empty_like(R), torch.empty_like(G)
+    status = torch.empty(count, dtype=torch.int32, device=dev)
+    P = lambda t: ct.c_void_p(t.data_ptr())  # noqa: E731
+    st = load().lra_cur_adjoint(count, m, n, r, P(C), P(R), P(G), nnz, P(om_row), P(om_col), P(col_order), P(a_om),
+                                P(loss), P(dC), P(dR), P(dG), P(status), _stream_ptr(stream))
+    if st != LRA_OK:
+        raise LraError(st, "lra_cur_adjoint")
+    return loss, dC, dR, dG, status
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class CURReconLoss(torch.autograd.Function):
+        """loss_b = sum over Omega_b of (a - C_b G_b^{-1} R_b)^2, differentiable in
+        C, R and G; forward and backward both come from lra_cur_adjoint."""
+
+        @staticmethod
+        def forward(ctx, C, R, G, om_row, om_col, col_order, a_om):
+            loss, dC, dR, dG, status = lra_cur_adjoint(C.detach().contiguous(), R.detach().contiguous(),
+                                                       G.detach().contiguous(), om_row, om_col, col_order, a_om)
+            ctx.save_for_backward(dC, dR, dG)
+            ctx.status = status
+            return loss
+
+        @staticmethod
+        def backward(ctx, gloss):
+            dC, dR, dG = ctx.saved_tensors
+            g = gloss.to(torch.float64)
+            return (g[:, None, None] * dC, g[:, None, None] * dR, g[:, None, None] * dG, None, None, None, None)
+
+    return CURReconLoss
+
+
+_autograd_fn = None
+
+
+def cur_recon_loss(C, R, G, om_row, om_col, col_order, a_om):
+    """torch.autograd entry point of the CUR adjoint (see CURReconLoss)."""
+    global _autograd_fn
+    if _autograd_fn is None:
+        _autograd_fn = _make_autograd()
+    return _autograd_fn.apply(C, R, G, om_row, om_col, col_order, a_om)

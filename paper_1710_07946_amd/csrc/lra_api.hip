@@ -34,7 +34,23 @@ struct Workspace {
     int64_t block_cap = 0;
     double *sketch = nullptr;       // global sketch panels when they do not fit LDS
     size_t sketch_cap = 0;          // bytes
+    void *scratch = nullptr;        // residual / adjoint work arrays
+    size_t scratch_cap = 0;         // bytes
 };
+
+// Grow-only scratch of a workspace (the stream is drained before a reallocation).
+lra_status ws_scratch(Workspace *w, hipStream_t stream, size_t bytes, void **out) {
+    if (w->scratch_cap < bytes) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(w->scratch);
+        w->scratch = nullptr;
+        w->scratch_cap = 0;
+        if (hipMalloc(&w->scratch, bytes) != hipSuccess) return LRA_ENOMEM;
+        w->scratch_cap = bytes;
+    }
+    *out = w->scratch;
+    return LRA_OK;
+}
 
 using lra::kMaxTeam;
 
@@ -187,6 +203,7 @@ void lra_release(void) {
         (void)hipFree(w.blocks);
         (void)hipFree(w.order);
         (void)hipFree(w.sketch);
+        (void)hipFree(w.scratch);
     }
     g_ws.clear();
     (void)hipSetDevice(cur);
@@ -339,6 +356,52 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
     hipError_t e = lra::launch_batched(dt, base, ws->blocks, ws->order, count, seed, cfg, ws->counters + 1, (int)grid,
                                        dyn, I_out, J_out, U_out, infos, stream);
     if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
+lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, const int64_t *I,
+                        const int64_t *J, const double *U, int32_t q, int32_t s, uint64_t seed, double *moments,
+                        hipStream_t stream) {
+    if (!W || !I || !J || !U || !moments) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n) return LRA_EINVAL;
+    if (q < 0 || s < 0 || (q == 0) != (s == 0) || q > 256 || s > 256 || q > m || s > n) return LRA_EINVAL;
+    if (m >= ((int64_t)1 << 39) || n >= ((int64_t)1 << 39)) return LRA_EINVAL;
+    if ((q ? q : m) > (int64_t)64 * 65535 || (s ? s : n) > (int64_t)256 * 65535) return LRA_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    lra_status st;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    void *scratch = nullptr;
+    if ((st = ws_scratch(ws, stream, lra::residual_scratch_bytes(m, n, r, q, s), &scratch)) != LRA_OK) return st;
+    if (lra::launch_residual(dt, W, m, n, lda, r, I, J, U, q, s, seed, moments, scratch, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
+lra_status lra_cur_adjoint(int64_t count, int64_t m, int64_t n, int32_t r, const double *C, const double *R,
+                           const double *G, int64_t nnz, const int32_t *om_row, const int32_t *om_col,
+                           const int32_t *col_order, const double *a_om, double *loss, double *dC, double *dR,
+                           double *dG, int32_t *status, hipStream_t stream) {
+    if (count < 0 || m < 1 || n < 1 || r < 1 || r > kRMax || nnz < 0) return LRA_EINVAL;
+    if (m > INT32_MAX || n > INT32_MAX) return LRA_EINVAL;
+    if (count == 0) return LRA_OK;
+    if (!C || !R || !G || !loss || !dC || !dR || !dG || !status) return LRA_EINVAL;
+    if (nnz > 0 && (!om_row || !om_col || !col_order || !a_om)) return LRA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    lra_status st;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    void *scratch = nullptr;
+    const size_t bytes = sizeof(double) * 2 * (size_t)r * (size_t)n * (size_t)count;
+    if ((st = ws_scratch(ws, stream, bytes, &scratch)) != LRA_OK) return st;
+    if (lra::launch_adjoint(count, m, n, r, C, R, G, nnz, om_row, om_col, col_order, a_om, loss, dC, dR, dG,
+                            static_cast<double *>(scratch), status, stream) != hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;
     }

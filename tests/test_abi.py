@@ -90,6 +90,41 @@ def test_batched_invalid_arguments_rejected_on_host(lib):
     assert lib.lra_cur_batched(fake, 1, blocks, 0, 3, 1, 0, None, fake, fake, fake, None, None) == lra.LRA_OK
 
 
+def test_residual_invalid_arguments_rejected_on_host(lib):
+    f = ct.c_void_p(0x1000)
+    E = lra.LRA_EINVAL
+
+    def call(W=f, dt=1, m=100, n=80, lda=80, r=5, q=0, s=0, out=f):
+        return lib.lra_residual(W, dt, m, n, lda, r, f, f, f, q, s, 0, out, None)
+
+    assert call(W=None) == E
+    assert call(out=None) == E
+    assert call(dt=9) == E
+    assert call(lda=79) == E
+    assert call(r=0) == E
+    assert call(r=81) == E                 # r > min(m, n)
+    assert call(q=10, s=0) == E            # q and s are both zero or both positive
+    assert call(q=0, s=10) == E
+    assert call(q=257, s=10) == E          # at most 256 sampled rows
+    assert call(q=10, s=81) == E           # s > n
+
+
+def test_adjoint_invalid_arguments_rejected_on_host(lib):
+    f = ct.c_void_p(0x1000)
+
+    def call(count=1, m=20, n=20, r=4, nnz=10, C=f, om=f):
+        return lib.lra_cur_adjoint(count, m, n, r, C, f, f, nnz, om, om, om, f, f, f, f, f, f, None)
+
+    assert call(count=-1) == lra.LRA_EINVAL
+    assert call(r=0) == lra.LRA_EINVAL
+    assert call(r=65) == lra.LRA_EINVAL
+    assert call(nnz=-1) == lra.LRA_EINVAL
+    assert call(C=None) == lra.LRA_EINVAL
+    assert call(om=None) == lra.LRA_EINVAL
+    assert call(m=1 << 31) == lra.LRA_EINVAL  # Omega indices are int32
+    assert call(count=0) == lra.LRA_OK        # an empty batch is a no-op
+
+
 def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(lra, "LIB_PATH", str(tmp_path / "nope.so"))
     monkeypatch.setattr(lra, "_lib", None)
