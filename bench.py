@@ -29,6 +29,7 @@ SAMPLES = 100
 SEED = 2011
 METRIC = "CUR LRAs/sec + HBM GB/s, batched/mixed vs plain, at rel Frobenius err ≤1e-6"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 
 
 def algorithmic_bytes(m, n, r, sweeps_run, depth, samples, elem):
@@ -45,6 +46,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="time only the headline LRA (skip batched, residual and adjoint lines)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -102,6 +105,8 @@ def main():
         raise SystemExit("lra_cur failed on the GPU: %s" % info)
     I, J, U = out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy()
 
+    resid = None if args.no_secondary else residual_fields(lra, torch, A, out.I, out.J, out.U, M, N, RANK, 4,
+                                                          max(2, args.steps // 5))
     nbytes = algorithmic_bytes(M, N, RANK, info["sweeps_run"], DEPTH, SAMPLES, 4)
     achieved = nbytes / (kernel_ms * 1e-3) / 1e9
     rec = {
@@ -131,6 +136,8 @@ def main():
         "swaps_total": info["swaps_total"],
     }
 
+    if resid is not None:
+        rec["residual"] = resid
     if not args.no_cpu_baseline:
         import oracle
         times = []
@@ -153,7 +160,134 @@ def main():
                          "recon_rel_fro_diff_sampled": float(np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)),
                          "oracle_min_margin": res.min_margin,
                          "rel_fro_err_vs_A_sampled": float(np.linalg.norm(A64 - Xg) / np.linalg.norm(A64))}
+    if not args.no_secondary:
+        del A
+        torch.cuda.empty_cache()
+        rec["secondary"] = {
+            "batched_fmm": bench_batched(lra, workloads, torch, np, args),
+            "adjoint_2048": bench_adjoint(lra, workloads, torch, np, args),
+        }
     print(json.dumps(rec), flush=True)
+
+
+def _time_events(torch, fn, steps, warmup):
+    """Mean milliseconds of fn() over `steps` calls, HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def residual_fields(lra, torch, A, I, J, U, m, n, r, elem, steps):
+    """Full and sampled residual moments of a computed CUR, timed."""
+    mom = torch.empty(4, dtype=torch.float64, device=A.device)
+    ms_full = _time_events(torch, lambda: lra.lra_residual(A, I, J, U, out=mom), steps, 1)
+    full = mom.cpu().numpy()
+    ms_samp = _time_events(torch, lambda: lra.lra_residual(A, I, J, U, 256, 256, 7, out=mom), steps, 1)
+    samp = mom.cpu().numpy()
+    flops = 2.0 * m * n * r + 2.0 * r * r * n
+    tflops = flops / (ms_full * 1e-3) / 1e12
+    return {
+        "ms_full": ms_full, "ms_sampled_256x256": ms_samp,
+        "rel_fro_err_full": float(math.sqrt(full[1] / full[3])),
+        "rel_fro_err_sampled_256x256": float(math.sqrt(samp[1] / samp[3])),
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": tflops / FP64_PEAK_TFS, "traffic": None,
+                     "hbm_gbs": m * n * elem / (ms_full * 1e-3) / 1e9},
+    }
+
+
+def bench_batched(lra, workloads, torch, np, args):
+    """4096 FMM far-field blocks (rows, columns uniform in 64..1024), r = 16,
+    3 sweeps: one persistent launch against a loop of single-LRA launches."""
+    count, r, sweeps, seed = 4096, 16, 3, 1000
+    t0 = time.time()
+    base, desc = workloads.fmm_batch_device(count, "cuda")
+    torch.cuda.synchronize()
+    print("# fmm blocks generated in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+    out = lra.lra_cur_batched(base, desc, r, sweeps, seed)
+    ms = _time_events(torch, lambda: lra.lra_cur_batched(base, desc, r, sweeps, seed, out=out),
+                      max(2, args.steps // 5), 1)
+    infos = out.info()
+    bad = [i for i in infos if i["status"] != 0]
+    nbytes = sum(4 * (inf["sweeps_run"] * (int(d[1]) * r + r * int(d[2])) + r * r) for inf, d in zip(infos, desc))
+    loop_n = 256
+    views = [base[int(d[0]):int(d[0]) + int(d[1]) * int(d[2])].view(int(d[1]), int(d[2])) for d in desc[:loop_n]]
+    outs = [lra.lra_cur(views[b], r, sweeps, seed + b) for b in range(loop_n)]
+
+    def loop():
+        for b in range(loop_n):
+            lra.lra_cur(views[b], r, sweeps, seed + b, out=outs[b])
+
+    ms_loop = _time_events(torch, loop, 2, 1)
+    same = all(outs[b].I.cpu().tolist() == out.I[b].cpu().tolist() and
+               outs[b].J.cpu().tolist() == out.J[b].cpu().tolist() for b in range(8))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    res = {
+        "workload": "4096 FMM blocks 1/|x-y|, m, n uniform in 64..1024, fp32; r=16, 3 sweeps, random start",
+        "lras_per_s": count / (ms * 1e-3), "ms_per_batch": ms,
+        "plain_loop_lras_per_s": loop_n / (ms_loop * 1e-3), "plain_loop_sample": "first %d blocks" % loop_n,
+        "speedup_vs_plain_loop": (count / ms) / (loop_n / ms_loop),
+        "failed_blocks": len(bad), "first_8_match_plain_calls": bool(same),
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+        "useful_bytes_per_batch": nbytes,
+    }
+    del base, out, outs, views
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_adjoint(lra, workloads, torch, np, args):
+    """256 blocks of 2048 x 2048 FP32 rank-32 factor products + N(0, 1e-5^2);
+    index sets from a forward C-A at r = 32 (3 sweeps); loss on 1% of the
+    entries; time of one adjoint launch over all blocks."""
+    count, m, n, r, nnz = 256, 2048, 2048, 32, 41943
+    t0 = time.time()
+    Cs, Rs, Gs, rows, cols, vals = [], [], [], [], [], []
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4242)
+    for b in range(count):
+        A = workloads.factor_gaussian_device(m, n, r, 1e-5, 6000 + b, "cuda")
+        res = lra.lra_cur(A, r, 3, 7000 + b)
+        A64 = A.to(torch.float64)
+        Cs.append(A64[:, res.J])
+        Rs.append(A64[res.I])
+        Gs.append(A64[res.I][:, res.J])
+        flat = torch.sort(torch.randperm(m * n, generator=g, device="cuda")[:nnz]).values
+        rows.append((flat // n).to(torch.int32))
+        cols.append((flat % n).to(torch.int32))
+        vals.append(A64.reshape(-1)[flat])
+    C, R, G = (torch.stack(x).contiguous() for x in (Cs, Rs, Gs))
+    om_row, om_col, a_om = (torch.stack(x).contiguous() for x in (rows, cols, vals))
+    order = lra.omega_column_order(om_row, om_col)
+    torch.cuda.synchronize()
+    print("# adjoint inputs prepared in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+    out = {}
+
+    def run():
+        out["r"] = lra.lra_cur_adjoint(C, R, G, om_row, om_col, order, a_om)
+
+    ms = _time_events(torch, run, max(2, args.steps // 2), 1)
+    st = out["r"][4]
+    nbytes = count * (2 * 8 * (m * r + r * n + r * r) + nnz * (4 + 4 + 4 + 8))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {
+        "workload": "256 blocks 2048x2048 fp32 rank-32 + N(0,1e-5^2), r=32, |Omega|=41943 per block, FP64",
+        "blocks_per_s": count / (ms * 1e-3), "ms_per_launch": ms,
+        "failed_blocks": int((st != 0).sum().item()),
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+        "useful_bytes_per_launch": nbytes,
+    }
 
 
 if __name__ == "__main__":

@@ -17,7 +17,12 @@ blocks; see the experiments section and the FMM section of the paper):
 * ``fmm_blocks``          off-diagonal interaction blocks 1/|x - y| between
   well separated 2-D point clusters.
 * ``decaying_spectrum``   tall matrix with 64 unit singular values followed by
-  an i^-2 decay floored at 1e-7.
+  an i^-2 decay floored at 1e-7 (generated on the device: its 8.8 TFLOP
+  construction is out of reach of a host).
+
+The ``*_device`` variants build the same families with torch on a GPU (the
+large batched and tall workloads), seeded by the same integers; the
+benchmark uses them to avoid minutes of host-side generation.
 
 The noise parameter is a standard deviation.
 """
@@ -112,3 +117,71 @@ def sample_omega(m: int, n: int, count: int, seed: int):
     flat = g.choice(m * n, size=count, replace=False)
     flat.sort()
     return (flat // n).astype(np.int64), (flat % n).astype(np.int64)
+
+
+# ---------------------------------------------------------------- device-side generators
+def fmm_batch_device(count: int, device, shape_seed: int = 1021, block_seed0: int = 1022000,
+                     align_elems: int = 64):
+    """``fmm_batch`` evaluated on a GPU: the same shapes, points and layout (points
+    from the same NumPy streams), kernel values computed in FP64 and rounded
+    to FP32.  Returns (flat device tensor, descriptors int64[count, 4])."""
+    import torch
+    ms, ns = fmm_block_shapes(count, seed=shape_seed)
+    desc = np.zeros((count, 4), np.int64)
+    off = 0
+    for b in range(count):
+        desc[b] = (off, ms[b], ns[b], ns[b])
+        off += int(ms[b] * ns[b])
+        off = (off + align_elems - 1) // align_elems * align_elems
+    flat = torch.zeros(off, dtype=torch.float32, device=device)
+    for b in range(count):
+        o, m, n, _ = (int(v) for v in desc[b])
+        gen = np.random.default_rng(block_seed0 + b)
+        gap = gen.uniform(2.0, 3.0)
+        x = gen.uniform(0.0, 1.0, size=(m, 2))
+        y = gen.uniform(0.0, 1.0, size=(n, 2))
+        y[:, 0] += 1.0 + gap
+        xd = torch.from_numpy(x).to(device)
+        yd = torch.from_numpy(y).to(device)
+        dx = xd[:, None, 0] - yd[None, :, 0]
+        dy = xd[:, None, 1] - yd[None, :, 1]
+        d = torch.sqrt(dx * dx + dy * dy)
+        flat[o:o + m * n] = (1.0 / d).to(torch.float32).reshape(-1)
+    return flat, desc
+
+
+def factor_gaussian_device(m: int, n: int, r: int, noise: float, seed: int, device, dtype=None):
+    """X Y / ||X Y||_F + N(0, noise^2) with X, Y standard Gaussian (rank r),
+    drawn by torch's device generator seeded with ``seed``; FP32 by default."""
+    import torch
+    dtype = dtype or torch.float32
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    X = torch.randn(m, r, generator=g, device=device, dtype=torch.float64)
+    Y = torch.randn(r, n, generator=g, device=device, dtype=torch.float64)
+    fro = torch.sqrt(torch.trace((X.T @ X) @ (Y @ Y.T)))
+    A = (X @ Y) / fro
+    if noise:
+        A += noise * torch.randn(m, n, generator=g, device=device, dtype=torch.float64)
+    return A.to(dtype)
+
+
+def decaying_spectrum_device(m: int = 65536, n: int = 8192, lead: int = 64, floor: float = 1e-7,
+                             seed: int = 1031, device="cuda", dtype=None, chunk_rows: int = 8192):
+    """X diag(sigma) Y^T / sqrt(n) with X (m x n), Y (n x n) standard Gaussian and
+    sigma from ``decaying_spectrum_sigma`` (numerical rank ``lead``), built in
+    row chunks in FP64 on the device and rounded to ``dtype`` (FP32 default)."""
+    import torch
+    dtype = dtype or torch.float32
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    sig = torch.from_numpy(decaying_spectrum_sigma(n, lead, floor)).to(device)
+    Y = torch.randn(n, n, generator=g, device=device, dtype=torch.float64)
+    SY = (sig[:, None] * Y.T) / float(np.sqrt(n))   # diag(sigma) Y^T / sqrt(n)
+    del Y
+    A = torch.empty(m, n, dtype=dtype, device=device)
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        X = torch.randn(r1 - r0, n, generator=g, device=device, dtype=torch.float64)
+        A[r0:r1] = (X @ SY).to(dtype)
+    return A

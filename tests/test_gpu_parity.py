@@ -197,6 +197,35 @@ def test_cfg_20000_fp32_asrht_rank50(lra):
     assert_parity(A, g, o, 1e-4, sample_rows=400)
 
 
+def test_cfg_65536x8192_left_asrht_rank64(lra):
+    """Tall 65536 x 8192 FP32 matrix of numerical rank 64 (Gaussian factors, unit
+    singular values then i^-2 decay floored at 1e-7): left-form abridged SRHT
+    (d = 3, l = 128) picks the start columns, r = 64, 4 sweeps, nucleus with two
+    refinement steps; the oracle runs on the same bytes."""
+    Ad = workloads.decaying_spectrum_device(65536, 8192, 64, 1e-7, 1031, "cuda")
+    A = Ad.cpu().numpy()
+    kw = dict(preprocess=1, ah_depth=3, ah_samples=128, refine_steps=2)
+    o = oracle.ca_cur(A, 64, 4, 2051, **kw)
+    print("oracle", o.status, o.sweeps_run, o.swaps_total, o.min_margin, flush=True)
+    out = lra.lra_cur(Ad, 64, 4, 2051, **kw)
+    torch.cuda.synchronize()
+    g = (out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy(), out.info())
+    print("gpu", g[3], flush=True)
+    assert_parity(A, g, o, 1e-4, sample_rows=400)
+
+
+def test_device_generators_match_host(lra):
+    # the FMM batch evaluated on the device equals the host evaluation to one
+    # FP32 rounding (both compute 1/|x - y| in FP64 from the same points)
+    flat, desc = workloads.fmm_batch(12, shape_seed=9, block_seed0=900)
+    dev, desc2 = workloads.fmm_batch_device(12, "cuda", shape_seed=9, block_seed0=900)
+    assert np.array_equal(desc, desc2)
+    d = dev.cpu().numpy()
+    ulp = np.abs(d.view(np.int32).astype(np.int64) - flat.view(np.int32).astype(np.int64))
+    print("fmm device/host entries differing:", int((ulp > 0).sum()), "of", ulp.size, flush=True)
+    assert ulp.max() <= 1
+
+
 # ---------------------------------------------------------------- batched
 def test_batched_matches_oracle_and_plain_calls(lra):
     count = 24
