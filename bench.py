@@ -32,6 +32,26 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
 
+# HBM bytes per launch of the C-A kernel on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes scaled by a plain 1 GiB copy's readings
+# (profiles/ca_team_kernel_20000x20000_r50.md).  They describe the kernel
+# built from the sources with this SHA-1 and are reported only while the
+# sources still hash to it.
+KERNEL_SOURCES = ("paper_1710_07946_amd/csrc/lra_ca.hip", "paper_1710_07946_amd/csrc/lra_device.h",
+                  "paper_1710_07946_amd/csrc/lra_internal.h", "paper_1710_07946_amd/build.py")
+COUNTED_SHA1 = "021a3dbd605b411b1a353c818a0707b78d88379d"
+COUNTED_TRAFFIC = 1296221.14 * (1048576.0 / 524308.8) * 1024 + 162293.81 * 1.0 * 1024
+
+
+def kernel_sources_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def algorithmic_bytes(m, n, r, sweeps_run, depth, samples, elem):
     """Entries of A the LRA must read: 2^d columns per sampled multiplier
     column (sketch), the seed row panel, (m + n) r per sweep, the r x r generator."""
@@ -127,7 +147,8 @@ def main():
                    "m": M, "n": N, "r": RANK, "sweeps": SWEEPS, "ah_depth": DEPTH, "ah_samples": SAMPLES,
                    "seed": SEED, "input_dtype": "fp32"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": COUNTED_TRAFFIC if kernel_sources_sha1() == COUNTED_SHA1 else None},
         "useful_bytes_per_lra": nbytes,
         "kernel_ms": kernel_ms,
         "host_wall_ms_per_step": wall * 1e3 / args.steps,
@@ -187,21 +208,31 @@ def _time_events(torch, fn, steps, warmup):
 
 
 def residual_fields(lra, torch, A, I, J, U, m, n, r, elem, steps):
-    """Full and sampled residual moments of a computed CUR, timed."""
+    """Full residual moments of a computed CUR in FP64 (FP64 matrix cores) and
+    in mixed precision (BF16 x 3 matrix cores, FP32 accumulation), plus the
+    sampled 256 x 256 estimate, each timed."""
     mom = torch.empty(4, dtype=torch.float64, device=A.device)
     ms_full = _time_events(torch, lambda: lra.lra_residual(A, I, J, U, out=mom), steps, 1)
     full = mom.cpu().numpy()
+    ms_mixed = _time_events(torch, lambda: lra.lra_residual(A, I, J, U, prec=lra.LRA_PREC_MIXED, out=mom), steps, 1)
+    mixed = mom.cpu().numpy()
     ms_samp = _time_events(torch, lambda: lra.lra_residual(A, I, J, U, 256, 256, 7, out=mom), steps, 1)
     samp = mom.cpu().numpy()
     flops = 2.0 * m * n * r + 2.0 * r * r * n
     tflops = flops / (ms_full * 1e-3) / 1e12
+    gbs_mixed = m * n * elem / (ms_mixed * 1e-3) / 1e9
+    err_full = math.sqrt(full[1] / full[3])
+    err_mixed = math.sqrt(mixed[1] / mixed[3])
     return {
-        "ms_full": ms_full, "ms_sampled_256x256": ms_samp,
-        "rel_fro_err_full": float(math.sqrt(full[1] / full[3])),
+        "ms_full_fp64": ms_full, "ms_full_mixed": ms_mixed, "ms_sampled_256x256": ms_samp,
+        "rel_fro_err_full_fp64": err_full,
+        "rel_fro_err_full_mixed": err_mixed,
+        "mixed_vs_fp64_rel_diff_of_err": abs(err_mixed - err_full) / err_full,
         "rel_fro_err_sampled_256x256": float(math.sqrt(samp[1] / samp[3])),
-        "roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                     "frac": tflops / FP64_PEAK_TFS, "traffic": None,
-                     "hbm_gbs": m * n * elem / (ms_full * 1e-3) / 1e9},
+        "roofline_fp64": {"bound": "mfma", "achieved": tflops, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                          "frac": tflops / FP64_PEAK_TFS, "traffic": None},
+        "roofline_mixed": {"bound": "hbm", "achieved": gbs_mixed, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": gbs_mixed / HBM_PEAK_GBS, "traffic": None},
     }
 
 

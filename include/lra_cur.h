@@ -51,6 +51,12 @@ typedef enum {
 typedef enum { LRA_F64 = 0, LRA_F32 = 1, LRA_BF16 = 2 } lra_dtype;
 
 typedef enum {
+    LRA_PREC_PLAIN = 0,  /* FP64 arithmetic (FP64 matrix cores for dense products) */
+    LRA_PREC_MIXED = 1   /* dense products as three BF16 matrix-core products of a
+                            hi/lo split, FP32 accumulation; sums stay FP64 */
+} lra_prec;
+
+typedef enum {
     LRA_PRE_NONE = 0,  /* random initial column set (seeded) */
     LRA_PRE_ASRHT = 1  /* start set from greedy QRP on an abridged SRHT sketch */
 } lra_pre;
@@ -117,14 +123,19 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
  *   1..256 each   q rows and s columns drawn (distinct, seeded SplitMix64
  *                 streams 3 and 4 of `seed`).
  *   I, J  device int64[r]; U device double[r * r];
+ *   prec  lra_prec: LRA_PREC_PLAIN computes C (U R), e = w - C U R and the
+ *         sums in FP64.  LRA_PREC_MIXED forms C (U R) in BF16 x 3 with FP32
+ *         accumulation (each entry off by at most about 2^-16 sum_a |C_ia|
+ *         |Z_aj|, Z = U R), e and the sums over each 64-column slice of a
+ *         row in FP32 (relative error about 1e-6), the totals in FP64.
  *   moments  device double[4]: sum e, sum e^2, sum |e|, sum w^2 over the
  *            entries used (relative Frobenius error = sqrt(m[1] / m[3])).
  * An entry of I or J outside the matrix is not read; it makes the moments NaN.
- * Computed in FP64; asynchronous on `stream`.  LRA_EUNSUPPORTED when more
- * than 64 * 65535 rows are used. */
+ * Asynchronous on `stream`.  LRA_EUNSUPPORTED when more than 128 * 65535
+ * rows are used. */
 lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, const int64_t *I,
-                        const int64_t *J, const double *U, int32_t q, int32_t s, uint64_t seed, double *moments,
-                        hipStream_t stream);
+                        const int64_t *J, const double *U, int32_t q, int32_t s, uint64_t seed, int32_t prec,
+                        double *moments, hipStream_t stream);
 
 /* Adjoint of the CUR reconstruction at fixed index sets, for `count` blocks
  * of equal shape (the paper has no adjoint; this is the derivative of

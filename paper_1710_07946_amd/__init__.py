@@ -23,6 +23,7 @@ HEADER = os.path.join(ROOT, "include", "lra_cur.h")
 LRA_OK, LRA_EINVAL, LRA_ESINGULAR, LRA_EDEVICE, LRA_ENOMEM, LRA_EUNSUPPORTED = range(6)
 LRA_F64, LRA_F32, LRA_BF16 = 0, 1, 2
 LRA_PRE_NONE, LRA_PRE_ASRHT = 0, 1
+LRA_PREC_PLAIN, LRA_PREC_MIXED = 0, 1
 
 
 class LraError(RuntimeError):
@@ -75,7 +76,7 @@ def load() -> ct.CDLL:
         L.lra_cur_batched.argtypes = [P, ct.c_int, ct.POINTER(lra_block), i64, i32, i32, ct.c_uint64,
                                       ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_batched.restype = ct.c_int
-        L.lra_residual.argtypes = [P, ct.c_int, i64, i64, i64, i32, P, P, P, i32, i32, ct.c_uint64, P, P]
+        L.lra_residual.argtypes = [P, ct.c_int, i64, i64, i64, i32, P, P, P, i32, i32, ct.c_uint64, i32, P, P]
         L.lra_residual.restype = ct.c_int
         L.lra_cur_adjoint.argtypes = [i64, i64, i64, i32, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
         L.lra_cur_adjoint.restype = ct.c_int
@@ -233,9 +234,10 @@ def lra_cur_batched(base, blocks, r: int, sweeps: int, seed: int, *, delta: floa
     return out
 
 
-def lra_residual(A, I, J, U, q: int = 0, s: int = 0, seed: int = 0, out=None, stream=None):
+def lra_residual(A, I, J, U, q: int = 0, s: int = 0, seed: int = 0, prec: int = 0, out=None, stream=None):
     """Residual moments [sum e, sum e^2, sum |e|, sum w^2] of E = A - A[:, J] U A[I, :]
-    over all entries (q = s = 0) or a seeded q x s sample; a device float64[4]."""
+    over all entries (q = s = 0) or a seeded q x s sample; a device float64[4].
+    prec = LRA_PREC_MIXED computes the product on BF16 matrix cores (hi/lo split)."""
     torch = _torch()
     if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
         raise ValueError("A must be a 2-D device tensor with unit column stride")
@@ -248,7 +250,8 @@ def lra_residual(A, I, J, U, q: int = 0, s: int = 0, seed: int = 0, out=None, st
         out = torch.empty(4, dtype=torch.float64, device=A.device)
     st = load().lra_residual(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r,
                              ct.c_void_p(I.data_ptr()), ct.c_void_p(J.data_ptr()), ct.c_void_p(U.data_ptr()), q, s,
-                             ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.c_void_p(out.data_ptr()), _stream_ptr(stream))
+                             ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), prec, ct.c_void_p(out.data_ptr()),
+                             _stream_ptr(stream))
     if st != LRA_OK:
         raise LraError(st, "lra_residual")
     return out

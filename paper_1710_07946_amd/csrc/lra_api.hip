@@ -363,21 +363,24 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
 }
 
 lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, const int64_t *I,
-                        const int64_t *J, const double *U, int32_t q, int32_t s, uint64_t seed, double *moments,
-                        hipStream_t stream) {
+                        const int64_t *J, const double *U, int32_t q, int32_t s, uint64_t seed, int32_t prec,
+                        double *moments, hipStream_t stream) {
     if (!W || !I || !J || !U || !moments) return LRA_EINVAL;
     if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (prec != LRA_PREC_PLAIN && prec != LRA_PREC_MIXED) return LRA_EINVAL;
     if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n) return LRA_EINVAL;
     if (q < 0 || s < 0 || (q == 0) != (s == 0) || q > 256 || s > 256 || q > m || s > n) return LRA_EINVAL;
     if (m >= ((int64_t)1 << 39) || n >= ((int64_t)1 << 39)) return LRA_EINVAL;
-    if ((q ? q : m) > (int64_t)64 * 65535 || (s ? s : n) > (int64_t)256 * 65535) return LRA_EUNSUPPORTED;
+    if ((q ? q : m) > (int64_t)128 * 65535) return LRA_EUNSUPPORTED;
     std::lock_guard<std::mutex> lk(g_mu);
     Workspace *ws = nullptr;
     lra_status st;
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
     void *scratch = nullptr;
-    if ((st = ws_scratch(ws, stream, lra::residual_scratch_bytes(m, n, r, q, s), &scratch)) != LRA_OK) return st;
-    if (lra::launch_residual(dt, W, m, n, lda, r, I, J, U, q, s, seed, moments, scratch, stream) != hipSuccess) {
+    if ((st = ws_scratch(ws, stream, lra::residual_scratch_bytes(m, n, r, q, s, prec), &scratch)) != LRA_OK)
+        return st;
+    if (lra::launch_residual(dt, W, m, n, lda, r, I, J, U, q, s, seed, prec, moments, scratch, stream) !=
+        hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;
     }

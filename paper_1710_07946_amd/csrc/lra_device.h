@@ -12,17 +12,20 @@ constexpr int kWave = 64;
 constexpr int kInvChunk = 8;
 
 // ---------------------------------------------------------------- elements
+// load(): the entry at offset o as FP64; conv(): the same upcast of a raw
+// value already in a register (BF16 is carried as its 16-bit pattern).
 template <typename T> struct Elem;
 template <> struct Elem<double> {
+    static __device__ __forceinline__ double conv(double v) { return v; }
     static __device__ __forceinline__ double load(const double *p, int64_t o) { return p[o]; }
 };
 template <> struct Elem<float> {
+    static __device__ __forceinline__ double conv(float v) { return (double)v; }
     static __device__ __forceinline__ double load(const float *p, int64_t o) { return (double)p[o]; }
 };
 template <> struct Elem<uint16_t> {
-    static __device__ __forceinline__ double load(const uint16_t *p, int64_t o) {
-        return (double)__uint_as_float(((uint32_t)p[o]) << 16);
-    }
+    static __device__ __forceinline__ double conv(uint16_t v) { return (double)__uint_as_float(((uint32_t)v) << 16); }
+    static __device__ __forceinline__ double load(const uint16_t *p, int64_t o) { return conv(p[o]); }
 };
 
 // ---------------------------------------------------------------- SplitMix64

@@ -11,11 +11,29 @@
 
 namespace lra {
 
-constexpr int kResTileRows = 64;   // rows of E per residual workgroup
-constexpr int kResThreads = 256;   // one column of E per thread
 constexpr int kAdjThreads = 512;
 
 // ------------------------------------------------------------------ residual
+// E = W[rows, cols] - Cg Z with Cg = W[rows, J] (nq x r) and Z = U W[I, cols]
+// (r x ns), zero-padded along the rank to rp.  The product runs on the
+// matrix cores: FP64 MFMA for the plain path, three BF16 MFMAs of a hi/lo
+// split with FP32 accumulation for the mixed path.  A workgroup of 8 waves
+// owns 128 rows (16 per wave, whose Cg part stays in registers) and a range
+// of columns, walked in chunks of CH columns, two 16-column tiles at a time
+// (two independent accumulator chains per wave).  The loop is
+// software-pipelined: while chunk c is multiplied out of one LDS buffer, the
+// W entries and the Z slice of chunk c + 1 are already in flight into
+// registers, and the Z slice goes to the other LDS buffer afterwards.  Every
+// lane keeps FP64 partial sums of e, e^2, |e| and w^2.
+constexpr int kResThreads = 512;
+constexpr int kResWaves = kResThreads / 64;
+constexpr int kResRows = 16 * kResWaves;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+
 // Sample rows (stream 3) and columns (stream 4) of E, q, s <= 256.
 __global__ void resid_sample_kernel(uint64_t seed, int64_t m, int64_t n, int q, int s, int64_t *rows,
                                     int64_t *cols) {
@@ -23,101 +41,351 @@ __global__ void resid_sample_kernel(uint64_t seed, int64_t m, int64_t n, int q, 
     else if (threadIdx.x < 2 * kWave) draw_distinct_wave(seed, 4, n, s, cols);
 }
 
-// Z = U W[I, cols] (r x ns, FP64), one column per thread; the sum over b runs
-// in increasing order.
-template <typename T, int RM>
-__global__ void __launch_bounds__(kResThreads) resid_z_kernel(const T *A, int64_t m, int64_t lda, int r, const int64_t *I,
-                                                              const double *U, const int64_t *cols, int64_t ns,
-                                                              double *Z) {
-    const int64_t c = (int64_t)blockIdx.x * kResThreads + threadIdx.x;
-    if (c >= ns) return;
-    const int64_t col = cols ? cols[c] : c;
-    double rc[RM];
-#pragma unroll
-    for (int b = 0; b < RM; b++) {
-        const int64_t i = b < r ? I[b] : 0;
-        // an index outside [0, m) is not read: it turns the moments into NaN
-        rc[b] = b >= r ? 0.0 : (i >= 0 && i < m) ? Elem<T>::load(A, i * lda + col) : __builtin_nan("");
-    }
-    for (int a = 0; a < r; a++) {
-        double acc = 0.0;
-#pragma unroll
-        for (int b = 0; b < RM; b++)
-            if (b < r) acc += U[a * r + b] * rc[b];
-        Z[(int64_t)a * ns + c] = acc;
-    }
+// Split an FP64 value into BF16 hi + lo (x ~ hi + lo to about 2^-17 relative),
+// returned as their 16-bit patterns.
+__device__ __forceinline__ void split_bf16(double x, uint16_t &hi, uint16_t &lo) {
+    const __bf16 h = (__bf16)(float)x;
+    const __bf16 l = (__bf16)(float)(x - (double)(float)h);
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
 }
 
-// Cg = W[rows, J] (nq x r, FP64).
+// Z[a][c] = sum_b U[a][b] W[I[b]][col c] for a < r (b in increasing order),
+// zero for r <= a < rp; 64 columns per workgroup, the W[I, cols] slice and U
+// staged in LDS.  An index of I outside [0, m) makes its column NaN.  Plain:
+// Z is FP64 [rp][ns].  Mixed: Z is split into BF16 hi and lo patterns stored
+// column-major [ns][rp] (a column's rank entries contiguous).
 template <typename T>
-__global__ void resid_c_kernel(const T *A, int64_t n, int64_t lda, int r, const int64_t *J, const int64_t *rows,
-                               int64_t nq, double *Cg) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nq * r) return;
-    const int64_t i = e / r;
-    const int64_t j = J[e % r];
-    Cg[e] = (j >= 0 && j < n) ? Elem<T>::load(A, (rows ? rows[i] : i) * lda + j) : __builtin_nan("");
+__global__ void __launch_bounds__(256) resid_z_kernel(const T *A, int64_t m, int64_t lda, int r, int rp,
+                                                      const int64_t *I, const double *U, const int64_t *cols,
+                                                      int64_t ns, int mixed, double *Z, uint16_t *Zhi,
+                                                      uint16_t *Zlo) {
+    __shared__ double us[kRMax * kRMax];
+    __shared__ double wg[kRMax * 64];
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    for (int e = tid; e < r * r; e += 256) us[e] = U[e];
+    for (int e = tid; e < r * 64; e += 256) {
+        const int b = e >> 6;
+        const int64_t c = c0 + (e & 63);
+        const int64_t i = I[b];
+        double v = 0.0;
+        if (c < ns) v = (i >= 0 && i < m) ? Elem<T>::load(A, i * lda + (cols ? cols[c] : c)) : __builtin_nan("");
+        wg[e] = v;
+    }
+    __syncthreads();
+    const int c = tid & 63;
+    const int64_t col = c0 + c;
+    if (col >= ns) return;
+    for (int a = tid >> 6; a < rp; a += 4) {
+        double acc = 0.0;
+        if (a < r)
+            for (int b = 0; b < r; b++) acc += us[a * r + b] * wg[b * 64 + c];
+        if (mixed) split_bf16(acc, Zhi[col * rp + a], Zlo[col * rp + a]);
+        else Z[(int64_t)a * ns + col] = acc;
+    }
 }
 
-// Moments of E over a 64-row x 256-column tile: each thread owns one column
-// (its r entries of Z in registers) and walks the tile's rows; the tile's
-// rows of C are staged in LDS.  x = sum_a C[i][a] Z[a][c] in increasing a.
-// Per-workgroup partial sums (sum e, e^2, |e|, w^2) go to `partials`.
-template <typename T, int RM>
-__global__ void __launch_bounds__(kResThreads) resid_kernel(const T *A, int64_t lda, int r, const int64_t *rows,
-                                                            const int64_t *cols, int64_t nq, int64_t ns,
-                                                            const double *Z, const double *Cg, double *partials) {
-    __shared__ double cs[kResTileRows * RM];
-    __shared__ double red[4][kResThreads];
-    const int tid = threadIdx.x;
-    const int64_t row0 = (int64_t)blockIdx.y * kResTileRows;
-    const int64_t c = (int64_t)blockIdx.x * kResThreads + tid;
-    const int nrows = (int)std::min<int64_t>(kResTileRows, nq - row0);
-    for (int e = tid; e < nrows * r; e += kResThreads) cs[e] = Cg[row0 * r + e];
-    __syncthreads();
-    double se = 0.0, se2 = 0.0, sabs = 0.0, sw2 = 0.0;
-    if (c < ns) {
-        double z[RM];
+// Cg[i][a] = W[rows[i]][J[a]] for a < r, zero for r <= a < rp (nq x rp).
+template <typename T>
+__global__ void resid_c_kernel(const T *A, int64_t n, int64_t lda, int r, int rp, const int64_t *J,
+                               const int64_t *rows, int64_t nq, double *Cg) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nq * rp) return;
+    const int64_t i = e / rp;
+    const int a = (int)(e % rp);
+    double v = 0.0;
+    if (a < r) {
+        const int64_t j = J[a];
+        v = (j >= 0 && j < n) ? Elem<T>::load(A, (rows ? rows[i] : i) * lda + j) : __builtin_nan("");
+    }
+    Cg[e] = v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
-        for (int a = 0; a < RM; a++) z[a] = a < r ? Z[(int64_t)a * ns + c] : 0.0;
-        const int64_t col = cols ? cols[c] : c;
-        for (int i = 0; i < nrows; i++) {
-            const int64_t row = rows ? rows[row0 + i] : row0 + i;
-            const double w = Elem<T>::load(A, row * lda + col);
-            double x = 0.0;
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// The product is formed transposed, E^T tile = Z^T Cg^T, so that the four
+// outputs of a lane are four consecutive columns of one row (one vector load
+// of W per tile).  Output v of lane l in a 16 x 16 tile: row l % 16,
+// column 4 (l / 16) + v.
+
+// Plain core: FP64 MFMA 16x16x4 (A operand of lane l: A[l % 16][l / 16], B
+// operand: B[l / 16][l % 16], output v: D[l / 16 + 4 v][l % 16]).  B = the
+// lane's Cg row, held in registers: Cg[row0 + l % 16][4 s + l / 16].  A = Z^T
+// with its 16 rows permuted so that output row l / 16 + 4 v is column
+// 4 (l / 16) + v: lane l reads Z[4 s + l / 16][4 (l % 4) + (l % 16) / 4].
+// KMAX = upper bound of rp / 4.
+template <int KMAX, int CH>
+struct F64Core {
+    typedef double Acc;                                     // arithmetic of the epilogue
+    static constexpr int kStride = CH + 16;                 // doubles per staged Z row
+    static constexpr int kLdsBytes = 4 * KMAX * kStride * 8;
+    static constexpr int kZU = (4 * KMAX * CH + kResThreads - 1) / kResThreads;
+    double bf[KMAX];
+    double zr[kZU];
+    int ks;
+    __device__ __forceinline__ void load_cg(const double *Cg, int rp, int64_t row0, int64_t nq, int lane) {
+        ks = rp / 4;
+        const int64_t row = row0 + (lane & 15);
 #pragma unroll
-            for (int a = 0; a < RM; a++)
-                if (a < r) x += cs[i * r + a] * z[a];
-            const double e = w - x;
-            se += e;
-            se2 += e * e;
-            sabs += fabs(e);
-            sw2 += w * w;
+        for (int s = 0; s < KMAX; s++) bf[s] = (s < ks && row < nq) ? Cg[row * rp + 4 * s + (lane >> 4)] : 0.0;
+    }
+    __device__ __forceinline__ void fetch_z(const double *Zg, const uint16_t *, const uint16_t *, int64_t ns, int rp,
+                                            int64_t c0, int64_t cend, int tid) {
+#pragma unroll
+        for (int u = 0; u < kZU; u++) {
+            const int e = tid + u * kResThreads;
+            const int k = e / CH, c = e % CH;
+            zr[u] = (k < rp && c0 + c < cend) ? Zg[(int64_t)k * ns + c0 + c] : 0.0;
         }
     }
-    red[0][tid] = se;
-    red[1][tid] = se2;
-    red[2][tid] = sabs;
-    red[3][tid] = sw2;
-    __syncthreads();
-    for (int h = kResThreads / 2; h > 0; h >>= 1) {  // fixed pairwise tree
-        if (tid < h)
-            for (int k = 0; k < 4; k++) red[k][tid] += red[k][tid + h];
-        __syncthreads();
+    __device__ __forceinline__ void store_z(char *lds, int tid) {
+        double *z = reinterpret_cast<double *>(lds);
+#pragma unroll
+        for (int u = 0; u < kZU; u++) {
+            const int e = tid + u * kResThreads;
+            if (e < 4 * KMAX * CH) z[(e / CH) * kStride + e % CH] = zr[u];
+        }
     }
-    if (tid < 4) partials[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + tid] = red[tid][0];
+    // tiles t and t + 1 of the chunk
+    __device__ __forceinline__ void tile2(const char *lds, int t, int lane, Acc (&x)[2][4]) const {
+        const double *z = reinterpret_cast<const double *>(lds) + (lane >> 4) * kStride + 16 * t +
+                          4 * (lane & 3) + ((lane & 15) >> 2);
+        v4d acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KMAX; s++) {
+            if (s < ks) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(z[4 * s * kStride], bf[s], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(z[4 * s * kStride + 16], bf[s], acc1, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            x[0][v] = acc0[v];
+            x[1][v] = acc1[v];
+        }
+    }
+};
+
+// Mixed core: BF16 MFMA 16x16x32 with FP32 accumulation on a hi/lo split of
+// both factors (lo*hi + hi*lo + hi*hi; lo*lo is dropped).  A operand of lane
+// l: A[l % 16][8 (l / 16) + e], e = 0..7; B operand: B[8 (l / 16) + e][l % 16];
+// output v: D[4 (l / 16) + v][l % 16].  A = Z^T read from the staged slice,
+// which is column-major (hi, then lo) so that a lane's eight rank entries are
+// one 16-byte read; B = the lane's Cg row in registers.
+template <int KS, int CH>
+struct Bf16x3Core {
+    typedef float Acc;                                       // arithmetic of the epilogue
+    static constexpr int kCol = 32 * KS + 8;                 // bf16 per staged column (16-byte pad)
+    static constexpr int kHalf = CH * kCol;                  // bf16 per half (hi or lo)
+    static constexpr int kLdsBytes = 2 * kHalf * 2;
+    static constexpr int kVec = CH * 32 * KS / 8;            // 16-byte vectors per half
+    static constexpr int kZU = (2 * kVec + kResThreads - 1) / kResThreads;
+    v8bf bhi[KS], blo[KS];
+    v4u zr[kZU];
+    __device__ __forceinline__ void load_cg(const double *Cg, int rp, int64_t row0, int64_t nq, int lane) {
+        const int64_t row = row0 + (lane & 15);
+#pragma unroll
+        for (int s = 0; s < KS; s++)
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int k = 32 * s + 8 * (lane >> 4) + e;
+                uint16_t h, l;
+                split_bf16((row < nq && k < rp) ? Cg[row * rp + k] : 0.0, h, l);
+                bhi[s][e] = __builtin_bit_cast(__bf16, h);
+                blo[s][e] = __builtin_bit_cast(__bf16, l);
+            }
+    }
+    // vector index e: half = e / kVec, column c = (e % kVec) / (4 KS), rank
+    // group g = e % (4 KS) (8 entries each); rp = 32 KS here
+    __device__ __forceinline__ void fetch_z(const double *, const uint16_t *Zhi, const uint16_t *Zlo, int64_t,
+                                            int rp, int64_t c0, int64_t cend, int tid) {
+#pragma unroll
+        for (int u = 0; u < kZU; u++) {
+            const int e = tid + u * kResThreads;
+            const int h = e / kVec, c = (e % kVec) / (4 * KS), g = e % (4 * KS);
+            v4u v = {0u, 0u, 0u, 0u};
+            if (e < 2 * kVec && c0 + c < cend)
+                v = *reinterpret_cast<const v4u *>((h ? Zlo : Zhi) + (c0 + c) * rp + 8 * g);
+            zr[u] = v;
+        }
+    }
+    __device__ __forceinline__ void store_z(char *lds, int tid) {
+        uint16_t *z = reinterpret_cast<uint16_t *>(lds);
+#pragma unroll
+        for (int u = 0; u < kZU; u++) {
+            const int e = tid + u * kResThreads;
+            const int h = e / kVec, c = (e % kVec) / (4 * KS), g = e % (4 * KS);
+            if (e < 2 * kVec) *reinterpret_cast<v4u *>(z + h * kHalf + c * kCol + 8 * g) = zr[u];
+        }
+    }
+    __device__ __forceinline__ void tile2(const char *lds, int t, int lane, Acc (&x)[2][4]) const {
+        const uint16_t *z = reinterpret_cast<const uint16_t *>(lds) + (16 * t + (lane & 15)) * kCol + 8 * (lane >> 4);
+        v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < KS; s++) {
+            const v8bf zh0 = *reinterpret_cast<const v8bf *>(z + 32 * s);
+            const v8bf zl0 = *reinterpret_cast<const v8bf *>(z + kHalf + 32 * s);
+            const v8bf zh1 = *reinterpret_cast<const v8bf *>(z + 16 * kCol + 32 * s);
+            const v8bf zl1 = *reinterpret_cast<const v8bf *>(z + kHalf + 16 * kCol + 32 * s);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh0, blo[s], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh1, blo[s], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl0, bhi[s], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl1, bhi[s], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh0, bhi[s], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh1, bhi[s], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            x[0][v] = acc0[v];
+            x[1][v] = acc1[v];
+        }
+    }
+};
+
+// Four consecutive entries of W (one vector load when `vec`, else one by one
+// with the column bound).
+template <typename T> struct Quad;
+template <> struct Quad<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+};
+template <> struct Quad<double> {
+    typedef double V __attribute__((ext_vector_type(4)));
+};
+template <> struct Quad<uint16_t> {
+    typedef uint16_t V __attribute__((ext_vector_type(4)));
+};
+
+// The residual kernel proper, generic over the core.  Workgroup (x, y) takes
+// rows [128 y, 128 y + 128) and columns [split x, split x + split).  `vec`:
+// rows start 4-entry aligned and the columns are contiguous, so a lane's
+// four columns are one aligned vector.
+template <typename T, class Core, int CH>
+__global__ void __launch_bounds__(kResThreads) resid_kernel(const T *A, int64_t lda, const int64_t *rows,
+                                                            const int64_t *cols, int64_t nq, int64_t ns, int rp,
+                                                            int64_t split, int vec, const double *Cg,
+                                                            const double *Zg, const uint16_t *Zhi,
+                                                            const uint16_t *Zlo, double *partials) {
+    constexpr int NT = CH / 16;   // 16-column tiles per chunk (even)
+    typedef typename Quad<T>::V V;
+    __shared__ __align__(16) char lds[2][Core::kLdsBytes];
+    __shared__ double red[kResWaves][4];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int64_t row0 = (int64_t)blockIdx.y * kResRows + wave * 16;
+    const int64_t cbeg = (int64_t)blockIdx.x * split;
+    const int64_t cend = std::min<int64_t>(ns, cbeg + split);
+    Core core;
+    core.load_cg(Cg, rp, row0, nq, lane);
+    const int64_t myrow = row0 + (lane & 15);
+    const bool rok = myrow < nq;
+    const T *wrow = A + (rok ? (rows ? rows[myrow] : myrow) * lda : 0);
+    const int cq = 4 * (lane >> 4);   // first of the lane's four columns in a tile
+    V wa[NT], wb[NT];
+    double se = 0.0, se2 = 0.0, sabs = 0.0, sw2 = 0.0;
+
+    auto fetch_w = [&](V (&w)[NT], int64_t c0) {
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int64_t cj = c0 + 16 * t + cq;
+            V v = {T(0), T(0), T(0), T(0)};
+            if (rok) {
+                if (vec && cj + 3 < cend) {
+                    v = *reinterpret_cast<const V *>(wrow + cj);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; e++)
+                        if (cj + e < cend) v[e] = wrow[cols ? cols[cj + e] : cj + e];
+                }
+            }
+            w[t] = v;
+        }
+    };
+    // the chunk's sums are formed in the core's epilogue arithmetic (FP32 on
+    // the mixed path) and added to the FP64 totals once per chunk
+    auto compute = [&](const char *buf, V (&w)[NT], int64_t c0) {
+        typedef typename Core::Acc Acc;
+        Acc ce = 0, ce2 = 0, cabs = 0, cw2 = 0;
+#pragma unroll
+        for (int t = 0; t < NT; t += 2) {
+            if (c0 + 16 * t >= cend) break;
+            Acc x[2][4];
+            core.tile2(buf, t, lane, x);
+            if (rok) {
+#pragma unroll
+                for (int h = 0; h < 2; h++)
+#pragma unroll
+                    for (int v = 0; v < 4; v++)
+                        if (c0 + 16 * (t + h) + cq + v < cend) {
+                            const Acc wv = (Acc)Elem<T>::conv(w[t + h][v]);
+                            const Acc e = wv - x[h][v];
+                            ce += e;
+                            ce2 += e * e;
+                            cabs += fabs(e);
+                            cw2 += wv * wv;
+                        }
+            }
+        }
+        se += (double)ce;
+        se2 += (double)ce2;
+        sabs += (double)cabs;
+        sw2 += (double)cw2;
+    };
+
+    if (cbeg < cend) {
+        fetch_w(wa, cbeg);
+        core.fetch_z(Zg, Zhi, Zlo, ns, rp, cbeg, cend, tid);
+        core.store_z(lds[0], tid);
+        __syncthreads();
+        for (int64_t c0 = cbeg; c0 < cend; c0 += 2 * CH) {
+            const bool more1 = c0 + CH < cend;
+            if (more1) {
+                fetch_w(wb, c0 + CH);
+                core.fetch_z(Zg, Zhi, Zlo, ns, rp, c0 + CH, cend, tid);
+            }
+            compute(lds[0], wa, c0);
+            if (more1) core.store_z(lds[1], tid);
+            __syncthreads();
+            if (!more1) break;
+            const bool more2 = c0 + 2 * CH < cend;
+            if (more2) {
+                fetch_w(wa, c0 + 2 * CH);
+                core.fetch_z(Zg, Zhi, Zlo, ns, rp, c0 + 2 * CH, cend, tid);
+            }
+            compute(lds[1], wb, c0 + CH);
+            if (more2) core.store_z(lds[0], tid);
+            __syncthreads();
+        }
+    }
+    // fixed-order reduction: butterfly within each wave, then the waves in order
+    const double v0 = wave_sum(se), v1 = wave_sum(se2), v2 = wave_sum(sabs), v3 = wave_sum(sw2);
+    if (lane == 0) {
+        red[wave][0] = v0;
+        red[wave][1] = v1;
+        red[wave][2] = v2;
+        red[wave][3] = v3;
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double acc = 0.0;
+        for (int w = 0; w < kResWaves; w++) acc += red[w][tid];
+        partials[((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 4 + tid] = acc;
+    }
 }
 
 // Sum the per-workgroup partials in a fixed order.
 __global__ void resid_sum_kernel(const double *partials, int64_t nblocks, double *out) {
-    __shared__ double red[4][kResThreads];
+    __shared__ double red[4][256];
     const int tid = threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t b = tid; b < nblocks; b += kResThreads)
+    for (int64_t b = tid; b < nblocks; b += 256)
         for (int k = 0; k < 4; k++) acc[k] += partials[b * 4 + k];
     for (int k = 0; k < 4; k++) red[k][tid] = acc[k];
     __syncthreads();
-    for (int h = kResThreads / 2; h > 0; h >>= 1) {
+    for (int h = 128; h > 0; h >>= 1) {
         if (tid < h)
             for (int k = 0; k < 4; k++) red[k][tid] += red[k][tid + h];
         __syncthreads();
@@ -125,58 +393,101 @@ __global__ void resid_sum_kernel(const double *partials, int64_t nblocks, double
     if (tid < 4) out[tid] = red[tid][0];
 }
 
-template <typename T, int RM>
+static int resid_rp(int r, int prec) { return prec == LRA_PREC_MIXED ? (r + 31) / 32 * 32 : (r + 3) / 4 * 4; }
+
+// Column range per workgroup: about 2048 workgroups in all (several waves of
+// workgroups per CU, so the last one is short), in whole 64-column chunks.
+static int64_t resid_split(int64_t nq, int64_t ns) {
+    const int64_t ry = (nq + kResRows - 1) / kResRows;
+    const int64_t gx = std::max<int64_t>(1, (2048 + ry - 1) / ry);
+    const int64_t split = ((ns + gx - 1) / gx + 63) / 64 * 64;
+    return std::max<int64_t>(64, split);
+}
+
+static dim3 resid_grid(int64_t nq, int64_t ns) {
+    const int64_t split = resid_split(nq, ns);
+    return dim3((unsigned)((ns + split - 1) / split), (unsigned)((nq + kResRows - 1) / kResRows));
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t residual_scratch_bytes(int64_t m, int64_t n, int r, int q, int s, int prec) {
+    const int64_t nq = q ? q : m, ns = s ? s : n;
+    const int rp = resid_rp(r, prec);
+    const dim3 g = resid_grid(nq, ns);
+    return align256(512 * sizeof(int64_t)) + align256(sizeof(double) * (size_t)rp * ns) +
+           align256(sizeof(double) * (size_t)nq * rp) + align256(sizeof(double) * 4 * (size_t)g.x * g.y);
+}
+
+template <typename T, class Core, int CH>
+static void launch_resid_core(dim3 grid, int64_t split, int vec, hipStream_t stream, const T *A, int64_t lda,
+                              const int64_t *rows, const int64_t *cols, int64_t nq, int64_t ns, int rp,
+                              const double *Cg, const double *Z, const uint16_t *Zhi, const uint16_t *Zlo,
+                              double *partials) {
+    hipLaunchKernelGGL((resid_kernel<T, Core, CH>), grid, dim3(kResThreads), 0, stream, A, lda, rows, cols, nq, ns, rp,
+                       split, vec, Cg, Z, Zhi, Zlo, partials);
+}
+
+template <typename T>
 static hipError_t residual_t(const void *Av, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,
-                             const int64_t *J, const double *U, int q, int s, uint64_t seed, double *out,
+                             const int64_t *J, const double *U, int q, int s, uint64_t seed, int prec, double *out,
                              char *scratch, hipStream_t stream) {
+    // 64-column chunks, 32 for FP64 inputs (the prefetched W takes twice the registers)
+    constexpr int CH = sizeof(T) == 8 ? 32 : 64;
     const T *A = static_cast<const T *>(Av);
     const int64_t nq = q ? q : m, ns = s ? s : n;
-    int64_t *rows = nullptr, *cols = nullptr;
+    const int rp = resid_rp(r, prec);
+    const bool mixed = prec == LRA_PREC_MIXED;
     char *p = scratch;
+    int64_t *rows = nullptr, *cols = nullptr;
     if (q) {
         rows = reinterpret_cast<int64_t *>(p);
-        p += 256 * sizeof(int64_t);
-        cols = reinterpret_cast<int64_t *>(p);
-        p += 256 * sizeof(int64_t);
+        cols = rows + 256;
         hipLaunchKernelGGL(resid_sample_kernel, dim3(1), dim3(2 * kWave), 0, stream, seed, m, n, q, s, rows, cols);
     }
-    double *Z = reinterpret_cast<double *>(p);
-    p += sizeof(double) * (size_t)r * ns;
+    p += align256(512 * sizeof(int64_t));
+    double *Z = reinterpret_cast<double *>(p);   // FP64 [rp][ns], or the BF16 hi and lo halves [ns][rp]
+    uint16_t *Zhi = reinterpret_cast<uint16_t *>(p);
+    uint16_t *Zlo = Zhi + (size_t)rp * ns;
+    p += align256(sizeof(double) * (size_t)rp * ns);
     double *Cg = reinterpret_cast<double *>(p);
-    p += sizeof(double) * (size_t)nq * r;
+    p += align256(sizeof(double) * (size_t)nq * rp);
     double *partials = reinterpret_cast<double *>(p);
-    hipLaunchKernelGGL((resid_z_kernel<T, RM>), dim3((unsigned)((ns + kResThreads - 1) / kResThreads)), dim3(kResThreads),
-                       0, stream, A, m, lda, r, I, U, cols, ns, Z);
-    hipLaunchKernelGGL(resid_c_kernel<T>, dim3((unsigned)((nq * r + 255) / 256)), dim3(256), 0, stream, A, n, lda, r,
-                       J, rows, nq, Cg);
-    const dim3 grid((unsigned)((ns + kResThreads - 1) / kResThreads), (unsigned)((nq + kResTileRows - 1) / kResTileRows));
-    hipLaunchKernelGGL((resid_kernel<T, RM>), grid, dim3(kResThreads), 0, stream, A, lda, r, rows, cols, nq, ns, Z, Cg,
-                       partials);
-    hipLaunchKernelGGL(resid_sum_kernel, dim3(1), dim3(kResThreads), 0, stream, partials,
-                       (int64_t)grid.x * grid.y, out);
+    hipLaunchKernelGGL(resid_z_kernel<T>, dim3((unsigned)((ns + 63) / 64)), dim3(256), 0, stream, A, m, lda, r, rp, I,
+                       U, cols, ns, mixed ? 1 : 0, Z, Zhi, Zlo);
+    hipLaunchKernelGGL(resid_c_kernel<T>, dim3((unsigned)((nq * rp + 255) / 256)), dim3(256), 0, stream, A, n, lda, r,
+                       rp, J, rows, nq, Cg);
+    const dim3 grid = resid_grid(nq, ns);
+    const int64_t split = resid_split(nq, ns);
+    // the rank-64 FP64 core works on 32-column chunks (its fragments take many registers)
+    using CoreM1 = Bf16x3Core<1, CH>;
+    using CoreM2 = Bf16x3Core<2, CH>;
+    using CoreP4 = F64Core<4, CH>;
+    using CoreP8 = F64Core<8, CH>;
+    using CoreP16 = F64Core<16, 32>;
+    const int vec = (!cols && lda % 4 == 0 && reinterpret_cast<uintptr_t>(A) % (4 * sizeof(T)) == 0) ? 1 : 0;
+#define LRA_RES(CORE, C) \
+    launch_resid_core<T, CORE, C>(grid, split, vec, stream, A, lda, rows, cols, nq, ns, rp, Cg, Z, Zhi, Zlo, partials)
+    if (mixed) {
+        if (rp <= 32) LRA_RES(CoreM1, CH);
+        else LRA_RES(CoreM2, CH);
+    } else {
+        if (rp <= 16) LRA_RES(CoreP4, CH);
+        else if (rp <= 32) LRA_RES(CoreP8, CH);
+        else LRA_RES(CoreP16, 32);
+    }
+#undef LRA_RES
+    hipLaunchKernelGGL(resid_sum_kernel, dim3(1), dim3(256), 0, stream, partials, (int64_t)grid.x * grid.y, out);
     return hipGetLastError();
 }
 
-size_t residual_scratch_bytes(int64_t m, int64_t n, int r, int q, int s) {
-    const int64_t nq = q ? q : m, ns = s ? s : n;
-    const int64_t nblocks = ((ns + kResThreads - 1) / kResThreads) * ((nq + kResTileRows - 1) / kResTileRows);
-    return 512 * sizeof(int64_t) + sizeof(double) * ((size_t)r * ns + (size_t)nq * r + 4 * (size_t)nblocks);
-}
-
 hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,
-                           const int64_t *J, const double *U, int q, int s, uint64_t seed, double *out, void *scratch,
-                           hipStream_t stream) {
+                           const int64_t *J, const double *U, int q, int s, uint64_t seed, int prec, double *out,
+                           void *scratch, hipStream_t stream) {
     char *sc = static_cast<char *>(scratch);
-#define LRA_RES(TT, RR) return residual_t<TT, RR>(A, m, n, lda, r, I, J, U, q, s, seed, out, sc, stream)
-#define LRA_RES_R(TT)      \
-    if (r <= 16) LRA_RES(TT, 16); \
-    if (r <= 32) LRA_RES(TT, 32); \
-    LRA_RES(TT, 64)
-    if (dtype == LRA_F64) { LRA_RES_R(double); }
-    if (dtype == LRA_F32) { LRA_RES_R(float); }
-    LRA_RES_R(uint16_t);
-#undef LRA_RES_R
-#undef LRA_RES
+    if (dtype == LRA_F64) return residual_t<double>(A, m, n, lda, r, I, J, U, q, s, seed, prec, out, sc, stream);
+    if (dtype == LRA_F32) return residual_t<float>(A, m, n, lda, r, I, J, U, q, s, seed, prec, out, sc, stream);
+    return residual_t<uint16_t>(A, m, n, lda, r, I, J, U, q, s, seed, prec, out, sc, stream);
 }
 
 // ------------------------------------------------------------------ adjoint

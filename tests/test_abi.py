@@ -94,8 +94,8 @@ def test_residual_invalid_arguments_rejected_on_host(lib):
     f = ct.c_void_p(0x1000)
     E = lra.LRA_EINVAL
 
-    def call(W=f, dt=1, m=100, n=80, lda=80, r=5, q=0, s=0, out=f):
-        return lib.lra_residual(W, dt, m, n, lda, r, f, f, f, q, s, 0, out, None)
+    def call(W=f, dt=1, m=100, n=80, lda=80, r=5, q=0, s=0, prec=0, out=f):
+        return lib.lra_residual(W, dt, m, n, lda, r, f, f, f, q, s, 0, prec, out, None)
 
     assert call(W=None) == E
     assert call(out=None) == E
@@ -107,6 +107,8 @@ def test_residual_invalid_arguments_rejected_on_host(lib):
     assert call(q=0, s=10) == E
     assert call(q=257, s=10) == E          # at most 256 sampled rows
     assert call(q=10, s=81) == E           # s > n
+    assert call(prec=2) == E               # unknown precision
+    assert call(m=128 * 65535 + 1, n=80) == lra.LRA_EUNSUPPORTED  # more rows than the launch grid covers
 
 
 def test_adjoint_invalid_arguments_rejected_on_host(lib):

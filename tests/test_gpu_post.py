@@ -52,6 +52,30 @@ def check_moments(g, o):
         assert abs(g[k] - o[k]) <= 1e-10 * abs(o[k]), (k, g, o)
 
 
+# Mixed precision: each product C_ia Z_aj carries at most about 3 * 2^-18
+# relative error from the BF16 hi/lo split and 64 * 2^-24 from FP32
+# accumulation, so |x_mixed - x| <= delta_ij = EPS_MIXED * sum_a |C_ia| |Z_aj|.
+# The epilogue then rounds e, e^2, |e|, w^2 to FP32 and sums at most 16 of
+# them per lane in FP32 before the FP64 total: relative error below
+# 2^-23 + 15 * 2^-24 < 1e-6 of the sum of magnitudes (SUM_MIXED).
+EPS_MIXED = 2.0 ** -15
+SUM_MIXED = 2e-6
+
+
+def check_mixed_moments(g, o, Af, I, J, U, rows, cols):
+    """|e_m - e| <= delta entrywise, so: |sum e_m - sum e| and |sum |e_m| - sum |e||
+    are at most sum delta, |sum e_m^2 - sum e^2| <= 2 sqrt(sum e^2 sum delta^2) + sum delta^2."""
+    S = np.abs(Af[np.ix_(rows, J)]) @ np.abs(U @ Af[np.ix_(I, cols)])
+    d1 = EPS_MIXED * S.sum()
+    d2 = EPS_MIXED ** 2 * (S ** 2).sum()
+    slack = SUM_MIXED * (o[2] + d1)
+    assert abs(g[0] - o[0]) <= d1 + slack
+    assert abs(g[2] - o[2]) <= d1 + slack
+    bound2 = 2 * np.sqrt(o[1] * d2) + d2
+    assert abs(g[1] - o[1]) <= bound2 + SUM_MIXED * (o[1] + bound2)
+    assert abs(g[3] - o[3]) <= SUM_MIXED * o[3]
+
+
 # ---------------------------------------------------------------- residual
 @pytest.mark.parametrize("m,n,r,dtype,q,s", [
     (512, 512, 10, "float64", 0, 0),
@@ -63,6 +87,8 @@ def check_moments(g, o):
     (300, 2100, 33, "bf16", 256, 129),
     (65, 64, 1, "float64", 0, 0),
     (129, 3000, 32, "float32", 1, 1),
+    (1000, 900, 50, "float32", 0, 0),
+    (333, 517, 4, "float64", 0, 0),
 ])
 def test_residual_moments_match_oracle(lra, m, n, r, dtype, q, s):
     print("residual", m, n, r, dtype, q, s, flush=True)
@@ -78,6 +104,11 @@ def test_residual_moments_match_oracle(lra, m, n, r, dtype, q, s):
     out = lra.lra_residual(to_dev(A), dev(I), dev(J), dev(U), q, s, 31)
     torch.cuda.synchronize()
     check_moments(out.cpu().numpy(), o)
+    mixed = lra.lra_residual(to_dev(A), dev(I), dev(J), dev(U), q, s, 31, prec=lra.LRA_PREC_MIXED)
+    torch.cuda.synchronize()
+    rows = oracle.draw_distinct(31, 3, m, q) if q else np.arange(m)
+    cols = oracle.draw_distinct(31, 4, n, s) if s else np.arange(n)
+    check_mixed_moments(mixed.cpu().numpy(), o, Af, I, J, U, rows, cols)
 
 
 def test_residual_after_gpu_cur(lra):
