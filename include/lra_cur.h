@@ -150,8 +150,10 @@ lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64
  * by column) and a_om (the values of W there).  Outputs: loss[count],
  * dC, dR, dG (shapes of C, R, G), status[count]: LRA_OK, LRA_ESINGULAR when
  * G_b is singular, LRA_EINVAL when an Omega index of block b lies outside
- * the block (then loss[b] is NaN and that block's gradients are not written).
- * Deterministic: every sum runs in a fixed order. */
+ * the block, om_row is not sorted or col_order does not visit the columns
+ * in order (then loss[b] is NaN and that block's gradients are not written).
+ * m, n and nnz must be below 2^31.  Deterministic: every sum runs in a
+ * fixed order. */
 lra_status lra_cur_adjoint(int64_t count, int64_t m, int64_t n, int32_t r, const double *C, const double *R,
                            const double *G, int64_t nnz, const int32_t *om_row, const int32_t *om_col,
                            const int32_t *col_order, const double *a_om, double *loss, double *dC, double *dR,

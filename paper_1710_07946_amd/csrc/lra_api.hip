@@ -392,7 +392,7 @@ lra_status lra_cur_adjoint(int64_t count, int64_t m, int64_t n, int32_t r, const
                            const int32_t *col_order, const double *a_om, double *loss, double *dC, double *dR,
                            double *dG, int32_t *status, hipStream_t stream) {
     if (count < 0 || m < 1 || n < 1 || r < 1 || r > kRMax || nnz < 0) return LRA_EINVAL;
-    if (m > INT32_MAX || n > INT32_MAX) return LRA_EINVAL;
+    if (m > INT32_MAX || n > INT32_MAX || nnz > INT32_MAX) return LRA_EINVAL;
     if (count == 0) return LRA_OK;
     if (!C || !R || !G || !loss || !dC || !dR || !dG || !status) return LRA_EINVAL;
     if (nnz > 0 && (!om_row || !om_col || !col_order || !a_om)) return LRA_EINVAL;
@@ -401,10 +401,9 @@ lra_status lra_cur_adjoint(int64_t count, int64_t m, int64_t n, int32_t r, const
     lra_status st;
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
     void *scratch = nullptr;
-    const size_t bytes = sizeof(double) * 2 * (size_t)r * (size_t)n * (size_t)count;
-    if ((st = ws_scratch(ws, stream, bytes, &scratch)) != LRA_OK) return st;
-    if (lra::launch_adjoint(count, m, n, r, C, R, G, nnz, om_row, om_col, col_order, a_om, loss, dC, dR, dG,
-                            static_cast<double *>(scratch), status, stream) != hipSuccess) {
+    if ((st = ws_scratch(ws, stream, lra::adjoint_scratch_bytes(count, m, n, r), &scratch)) != LRA_OK) return st;
+    if (lra::launch_adjoint(count, m, n, r, C, R, G, nnz, om_row, om_col, col_order, a_om, loss, dC, dR, dG, scratch,
+                            status, stream) != hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;
     }

@@ -4,14 +4,15 @@
 // cooperates on it: every panel (the m x r column panel W[:, J], the n x r
 // transposed row panel W[I, :]^T, the items x l abridged-SRHT sketch) is
 // split by items (rows or columns of W) across the team, each workgroup
-// keeping its slice in LDS as FP64, column-major (slot-major), so that one
-// thread owns one item and LDS accesses are conflict-free.  Every pivot or
+// keeping its slice in LDS as FP64, column-major (slot-major, odd stride), each
+// item handled by a small group of consecutive lanes.  Every pivot or
 // swap decision is an argmax over the whole panel: each workgroup reduces its
 // slice with wavefront shuffles, publishes (value, item, slot) and the
-// candidate's row to a small exchange buffer, and after one grid barrier every
-// workgroup reduces the team's candidates redundantly, so all of them apply
-// the same rank-one update to their own slice.  A team of one workgroup
-// (small matrices, and every block of a batch) skips the barrier entirely.
+// candidate's row as tagged words in a small exchange buffer, reads the other
+// workgroups' words (no grid barrier, see the team exchange below) and
+// reduces the team's candidates redundantly, so all of them apply the same
+// rank-one update to their own slice.  A team of one workgroup (small
+// matrices, and every block of a batch) skips the exchange entirely.
 //
 // The arithmetic follows the paper's steps (Appendix D, Algorithms alggos
 // and algdomin; Appendix B for the sketch; Algorithm alg1tor for the greedy

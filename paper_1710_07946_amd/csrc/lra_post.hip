@@ -11,7 +11,6 @@
 
 namespace lra {
 
-constexpr int kAdjThreads = 512;
 
 // ------------------------------------------------------------------ residual
 // E = W[rows, cols] - Cg Z with Cg = W[rows, J] (nq x r) and Z = U W[I, cols]
@@ -491,62 +490,56 @@ hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64
 }
 
 // ------------------------------------------------------------------ adjoint
-// One workgroup per block b of the batch.  With Z = G^{-1} R, the loss
-// L = sum over Omega of (a_ij - (C Z)_ij)^2 and Ebar = -2 (a - C Z) on Omega:
-//   dC = Ebar Z^T (row pass over Omega in row order),
-//   dZ = C^T Ebar (column pass in column order), dR = G^{-T} dZ,
-//   dG = -G^{-T} dZ Z^T.
-// Omega is given sorted by row (then column) with `corder`, the stable
-// permutation that sorts it by column, so both passes are plain gathers and
-// every sum runs in the order of the oracle's scan.  Z and dZ go to the
-// block's slice of `ws` (2 r n doubles).  The r x r inverse uses LDS.
-__device__ __forceinline__ int64_t lower_bound_i32(const int32_t *a, int64_t n, int32_t key) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
+// L = sum over Omega of (a_ij - (C Z)_ij)^2 with Z = G^{-1} R, for a batch of
+// equal-shape blocks, in five launches:
+//   setup   one workgroup per block: checks the Omega indices, builds the
+//           row pointers (entries are sorted by row) and the column pointers
+//           (through col_order), inverts G (LU with partial pivoting in LDS);
+//   stage   Z^T (n x rp) and a copy of C (m x rp), rank padded to rp = 8 G
+//           (two launches);
+//   rows    G lanes per row of C, 8 rank entries each: x = C_i . Z_j per
+//           entry of the row, loss, dC_i = sum ebar Z_j;
+//   cols    G lanes per column: dZ_j = sum ebar C_i, dR_j = G^{-T} dZ_j, and
+//           this workgroup's share of T = dZ Z^T;
+//   final   one workgroup per block: loss and T summed over the workgroups in
+//           a fixed order, dG = -G^{-T} T.
+// The row and column launches put all workgroups of a block on one XCD (the
+// hardware deals workgroup w to XCD w mod 8), so a block's Z^T and C copy
+// stay in that XCD's L2.  Every sum runs in a fixed order: results are
+// deterministic and independent of timing.
+constexpr int kAdjThreads = 512;
+constexpr int kXcds = 8;
 
-__device__ __forceinline__ int64_t lower_bound_perm(const int32_t *a, const int32_t *perm, int64_t n, int32_t key) {
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a[perm[mid]] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
+struct AdjLayout {   // per-block scratch, byte offsets from the block's base
+    int64_t stride, gi, zt, cp, rowptr, colptr, lossp, tp;
+};
 
-template <int RM>
-__global__ void __launch_bounds__(kAdjThreads) adjoint_kernel(int64_t m, int64_t n, int r, const double *Cb,
-                                                              const double *Rb, const double *Gb, int64_t nnz,
-                                                              const int32_t *orow_b, const int32_t *ocol_b,
-                                                              const int32_t *corder_b, const double *aval_b,
-                                                              double *loss, double *dCb, double *dRb, double *dGb,
-                                                              double *ws, int32_t *status) {
+__device__ __forceinline__ char *adj_base(char *ws, const AdjLayout &L, int64_t b) { return ws + b * L.stride; }
+
+__global__ void __launch_bounds__(kAdjThreads) adj_setup_kernel(int64_t m, int64_t n, int r, const double *Gb,
+                                                                int64_t nnz, const int32_t *orow_b,
+                                                                const int32_t *ocol_b, const int32_t *corder_b,
+                                                                AdjLayout L, char *ws, double *loss,
+                                                                int32_t *status) {
     extern __shared__ __align__(16) double lds[];
-    double *LU = lds, *Gi = lds + r * r, *Tm = lds + 2 * r * r;
-    __shared__ int p[RM];
+    double *LU = lds, *Gi = lds + r * r;
+    __shared__ int p[kRMax];
     __shared__ int sing;
     __shared__ double ld;
-    __shared__ double red[kAdjThreads];
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
-    const double *C = Cb + b * m * r, *R = Rb + b * r * n, *G = Gb + b * r * r;
     const int32_t *orow = orow_b + b * nnz, *ocol = ocol_b + b * nnz, *corder = corder_b + b * nnz;
-    const double *aval = aval_b + b * nnz;
-    double *dC = dCb + b * m * r, *dR = dRb + b * r * n, *dG = dGb + b * r * r;
-    double *Z = ws + b * 2 * r * n, *dZ = Z + (int64_t)r * n;
-
-    // Omega indices outside the block (or a col_order entry outside [0, nnz))
-    // are reported as LRA_EINVAL before anything is read through them
+    char *base = adj_base(ws, L, b);
+    // Omega: indices inside the block, rows non-decreasing, col_order a
+    // permutation index that visits the columns in non-decreasing order
     int bad = 0;
     for (int64_t q = tid; q < nnz; q += kAdjThreads) {
         const int32_t i = orow[q], j = ocol[q], t = corder[q];
         bad |= (i < 0 || i >= m || j < 0 || j >= n || t < 0 || t >= nnz) ? 1 : 0;
+        if (q > 0) bad |= orow[q - 1] > i ? 1 : 0;
+    }
+    if (!__syncthreads_or(bad)) {
+        for (int64_t t = tid + 1; t < nnz; t += kAdjThreads) bad |= ocol[corder[t - 1]] > ocol[corder[t]] ? 1 : 0;
     }
     if (__syncthreads_or(bad)) {
         if (tid == 0) {
@@ -555,7 +548,17 @@ __global__ void __launch_bounds__(kAdjThreads) adjoint_kernel(int64_t m, int64_t
         }
         return;
     }
-    for (int e = tid; e < r * r; e += kAdjThreads) LU[e] = G[e];
+    // row pointers: rowptr[i] = first entry of row i (rowptr[m] = nnz); the
+    // rows between two consecutive entries' rows are filled by the later entry
+    int32_t *rowptr = reinterpret_cast<int32_t *>(base + L.rowptr);
+    int32_t *colptr = reinterpret_cast<int32_t *>(base + L.colptr);
+    for (int64_t q = tid; q <= nnz; q += kAdjThreads) {
+        const int64_t prev = q > 0 ? orow[q - 1] : -1, cur = q < nnz ? orow[q] : m;
+        for (int64_t i = prev + 1; i <= cur; i++) rowptr[i] = (int32_t)q;
+        const int64_t pc = q > 0 ? ocol[corder[q - 1]] : -1, cc = q < nnz ? ocol[corder[q]] : n;
+        for (int64_t j = pc + 1; j <= cc; j++) colptr[j] = (int32_t)q;
+    }
+    for (int e = tid; e < r * r; e += kAdjThreads) LU[e] = Gb[b * r * r + e];
     __syncthreads();
     inverse_lds(LU, Gi, p, r, kAdjThreads, &sing, &ld);
     if (sing) {
@@ -565,123 +568,307 @@ __global__ void __launch_bounds__(kAdjThreads) adjoint_kernel(int64_t m, int64_t
         }
         return;
     }
-    // Z = G^{-1} R, one column per thread
-    for (int64_t j = tid; j < n; j += kAdjThreads) {
-        double rc[RM];
-#pragma unroll
-        for (int q = 0; q < RM; q++) rc[q] = q < r ? R[(int64_t)q * n + j] : 0.0;
-        for (int a = 0; a < r; a++) {
-            double acc = 0.0;
-#pragma unroll
-            for (int q = 0; q < RM; q++)
-                if (q < r) acc += Gi[a * r + q] * rc[q];
-            Z[(int64_t)a * n + j] = acc;
-        }
+    double *gi = reinterpret_cast<double *>(base + L.gi);
+    for (int e = tid; e < r * r; e += kAdjThreads) gi[e] = Gi[e];
+    if (tid == 0) status[b] = LRA_OK;
+}
+
+// Z^T[j][a] = sum_q Gi[a][q] R[q][j] (q increasing; a < r, zero up to rp),
+// 64 columns per workgroup with the R slice and Gi in LDS.  Grid (column
+// chunks, blocks).
+__global__ void __launch_bounds__(256) adj_z_kernel(int64_t n, int r, int rp, const double *Rb, AdjLayout L,
+                                                    char *ws, const int32_t *status) {
+    __shared__ double gs[kRMax * kRMax];
+    __shared__ double rs[kRMax * 64];
+    const int64_t b = blockIdx.y;
+    if (status[b] != LRA_OK) return;
+    const int tid = threadIdx.x;
+    char *base = adj_base(ws, L, b);
+    const double *gi = reinterpret_cast<const double *>(base + L.gi);
+    const double *R = Rb + b * r * n;
+    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    for (int e = tid; e < r * r; e += 256) gs[e] = gi[e];
+    for (int e = tid; e < r * 64; e += 256) {
+        const int64_t c = c0 + (e & 63);
+        rs[e] = c < n ? R[(int64_t)(e >> 6) * n + c] : 0.0;
     }
-    __threadfence();
     __syncthreads();
-    // row pass: loss and dC, one row per thread
+    const int64_t j = c0 + (tid & 63);
+    if (j >= n) return;
+    double *zt = reinterpret_cast<double *>(base + L.zt) + j * rp;
+    for (int a = tid >> 6; a < rp; a += 4) {
+        double acc = 0.0;
+        if (a < r)
+            for (int q = 0; q < r; q++) acc += gs[a * r + q] * rs[q * 64 + (tid & 63)];
+        zt[a] = acc;
+    }
+}
+
+// Cp[i][a] = C[i][a] (zero for r <= a < rp).  Grid (chunks of 256 entries, blocks).
+__global__ void adj_c_kernel(int64_t m, int r, int rp, const double *Cb, AdjLayout L, char *ws,
+                             const int32_t *status) {
+    const int64_t b = blockIdx.y;
+    if (status[b] != LRA_OK) return;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= m * rp) return;
+    const int64_t i = e / rp;
+    const int a = (int)(e % rp);
+    reinterpret_cast<double *>(adj_base(ws, L, b) + L.cp)[e] = a < r ? Cb[b * m * r + i * r + a] : 0.0;
+}
+
+// Work index of workgroup w when `total` work items are dealt so that each
+// XCD gets a contiguous range (w mod 8 = XCD).  Returns -1 past the end.
+__device__ __forceinline__ int64_t xcd_work(int64_t w, int64_t total) {
+    const int64_t per = (total + kXcds - 1) / kXcds;
+    const int64_t l = (w % kXcds) * per + w / kXcds;
+    return l < total ? l : -1;
+}
+
+__device__ __forceinline__ void load8(const double *p, double (&v)[8]) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+        const d2 t = *reinterpret_cast<const d2 *>(p + k);
+        v[k] = t[0];
+        v[k + 1] = t[1];
+    }
+}
+
+// Sum over the G lanes of an item group (consecutive lanes), butterfly order.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Row pass.  Items = rows of C; G lanes per row, lane g holds rank entries
+// 8 g .. 8 g + 7.  Per entry (i, j) of the row: x = sum_a C_ia Z_aj,
+// e = a_ij - x, loss += e^2, dC_i += -2 e Z_j.
+template <int G>
+__global__ void __launch_bounds__(kAdjThreads) adj_row_kernel(int64_t count, int64_t m, int r, int rp, int64_t nnz,
+                                                              const int32_t *ocol_b, const double *aval_b,
+                                                              int64_t chunks, AdjLayout L, char *ws, double *dCb,
+                                                              const int32_t *status) {
+    constexpr int kItems = kAdjThreads / G;
+    __shared__ double red[kAdjThreads / kWave];
+    const int64_t wk = xcd_work(blockIdx.x, count * chunks);
+    if (wk < 0) return;
+    const int64_t b = wk / chunks, chunk = wk % chunks;
+    if (status[b] != LRA_OK) return;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), g = tid % G;
+    char *base = adj_base(ws, L, b);
+    const int32_t *rowptr = reinterpret_cast<const int32_t *>(base + L.rowptr);
+    const double *zt = reinterpret_cast<const double *>(base + L.zt);
+    const double *cp = reinterpret_cast<const double *>(base + L.cp);
+    const int32_t *ocol = ocol_b + b * nnz;
+    const double *aval = aval_b + b * nnz;
+    const int64_t i = chunk * kItems + tid / G;
     double lsum = 0.0;
-    for (int64_t i = tid; i < m; i += kAdjThreads) {
-        const int64_t q0 = lower_bound_i32(orow, nnz, (int32_t)i), q1 = lower_bound_i32(orow, nnz, (int32_t)(i + 1));
-        double ci[RM], dc[RM];
+    if (i < m) {
+        double c[8], dc[8];
+        load8(cp + i * rp + 8 * g, c);
 #pragma unroll
-        for (int a = 0; a < RM; a++) {
-            ci[a] = a < r ? C[i * r + a] : 0.0;
-            dc[a] = 0.0;
-        }
-        for (int64_t q = q0; q < q1; q++) {
-            const int64_t j = ocol[q];
-            double zj[RM];
-#pragma unroll
-            for (int a = 0; a < RM; a++) zj[a] = a < r ? Z[(int64_t)a * n + j] : 0.0;
+        for (int k = 0; k < 8; k++) dc[k] = 0.0;
+        const int32_t q0 = rowptr[i], q1 = rowptr[i + 1];
+        for (int32_t q = q0; q < q1; q++) {
+            double z[8];
+            load8(zt + (int64_t)ocol[q] * rp + 8 * g, z);
             double x = 0.0;
 #pragma unroll
-            for (int a = 0; a < RM; a++)
-                if (a < r) x += ci[a] * zj[a];
+            for (int k = 0; k < 8; k++) x += c[k] * z[k];
+            x = group_sum<G>(x);
             const double e = aval[q] - x;
-            lsum += e * e;
+            if (g == 0) lsum += e * e;
             const double eb = -2.0 * e;
 #pragma unroll
-            for (int a = 0; a < RM; a++)
-                if (a < r) dc[a] += eb * zj[a];
+            for (int k = 0; k < 8; k++) dc[k] += eb * z[k];
         }
-        for (int a = 0; a < r; a++) dC[i * r + a] = dc[a];
+        double *dC = dCb + b * m * r + i * r;
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+            if (8 * g + k < r) dC[8 * g + k] = dc[k];
     }
-    // column pass: dZ and dR, one column per thread
-    for (int64_t j = tid; j < n; j += kAdjThreads) {
-        const int64_t t0 = lower_bound_perm(ocol, corder, nnz, (int32_t)j);
-        const int64_t t1 = lower_bound_perm(ocol, corder, nnz, (int32_t)(j + 1));
-        double zj[RM], dz[RM];
+    const double ws_sum = wave_sum(lsum);
+    if (lane == 0) red[tid / kWave] = ws_sum;
+    __syncthreads();
+    if (tid == 0) {
+        double acc = 0.0;
+        for (int w = 0; w < kAdjThreads / kWave; w++) acc += red[w];
+        reinterpret_cast<double *>(base + L.lossp)[chunk] = acc;
+    }
+}
+
+// Column pass.  Items = columns; G lanes per column.  Per entry (i, j):
+// ebar = -2 (a_ij - C_i . Z_j), dZ_j += ebar C_i; then dR_j = G^{-T} dZ_j and
+// this workgroup's part of T = sum_j dZ_j Z_j^T.
+template <int G>
+__global__ void __launch_bounds__(kAdjThreads) adj_col_kernel(int64_t count, int64_t n, int r, int rp, int64_t nnz,
+                                                              const int32_t *orow_b, const int32_t *corder_b,
+                                                              const double *aval_b, int64_t chunks, AdjLayout L,
+                                                              char *ws, double *dRb, const int32_t *status) {
+    constexpr int kItems = kAdjThreads / G;
+    extern __shared__ __align__(16) double lds[];
+    double *gs = lds;                        // Gi, r x r
+    double *dzs = lds + kRMax * kRMax;       // [kItems][rp]
+    double *zs = dzs + kItems * 8 * G;       // [kItems][rp]
+    const int64_t wk = xcd_work(blockIdx.x, count * chunks);
+    if (wk < 0) return;
+    const int64_t b = wk / chunks, chunk = wk % chunks;
+    if (status[b] != LRA_OK) return;
+    const int tid = threadIdx.x, g = tid % G, li = tid / G;
+    char *base = adj_base(ws, L, b);
+    const double *gi = reinterpret_cast<const double *>(base + L.gi);
+    for (int e = tid; e < r * r; e += kAdjThreads) gs[e] = gi[e];
+    const int32_t *colptr = reinterpret_cast<const int32_t *>(base + L.colptr);
+    const double *zt = reinterpret_cast<const double *>(base + L.zt);
+    const double *cp = reinterpret_cast<const double *>(base + L.cp);
+    const int32_t *orow = orow_b + b * nnz, *corder = corder_b + b * nnz;
+    const double *aval = aval_b + b * nnz;
+    const int64_t j = chunk * kItems + li;
+    double z[8], dz[8];
 #pragma unroll
-        for (int a = 0; a < RM; a++) {
-            zj[a] = a < r ? Z[(int64_t)a * n + j] : 0.0;
-            dz[a] = 0.0;
-        }
-        for (int64_t t = t0; t < t1; t++) {
-            const int64_t q = corder[t];
-            const int64_t i = orow[q];
-            double ci[RM];
-#pragma unroll
-            for (int a = 0; a < RM; a++) ci[a] = a < r ? C[i * r + a] : 0.0;
+    for (int k = 0; k < 8; k++) z[k] = dz[k] = 0.0;
+    if (j < n) {
+        load8(zt + j * rp + 8 * g, z);
+        const int32_t t0 = colptr[j], t1 = colptr[j + 1];
+        for (int32_t t = t0; t < t1; t++) {
+            const int32_t q = corder[t];
+            double c[8];
+            load8(cp + (int64_t)orow[q] * rp + 8 * g, c);
             double x = 0.0;
 #pragma unroll
-            for (int a = 0; a < RM; a++)
-                if (a < r) x += ci[a] * zj[a];
+            for (int k = 0; k < 8; k++) x += c[k] * z[k];
+            x = group_sum<G>(x);
             const double eb = -2.0 * (aval[q] - x);
 #pragma unroll
-            for (int a = 0; a < RM; a++)
-                if (a < r) dz[a] += eb * ci[a];
+            for (int k = 0; k < 8; k++) dz[k] += eb * c[k];
         }
-        for (int a = 0; a < r; a++) {
-            dZ[(int64_t)a * n + j] = dz[a];
-            double acc = 0.0;  // (G^{-T} dZ)[a][j] = sum_q Gi[q][a] dZ[q][j]
+    }
 #pragma unroll
-            for (int q = 0; q < RM; q++)
-                if (q < r) acc += Gi[q * r + a] * dz[q];
+    for (int k = 0; k < 8; k++) {
+        dzs[li * 8 * G + 8 * g + k] = dz[k];
+        zs[li * 8 * G + 8 * g + k] = z[k];
+    }
+    __syncthreads();
+    if (j < n) {
+        // dR[a][j] = sum_q Gi[q][a] dZ[q][j], q increasing
+        double *dR = dRb + b * r * n;
+        for (int k = 0; k < 8; k++) {
+            const int a = 8 * g + k;
+            if (a >= r) break;
+            double acc = 0.0;
+            for (int q = 0; q < r; q++) acc += gs[q * r + a] * dzs[li * 8 * G + q];
             dR[(int64_t)a * n + j] = acc;
         }
     }
-    __threadfence();
-    __syncthreads();
-    // T = dZ Z^T, then dG = -G^{-T} T
+    // T part: Tp[a][c] = sum over this workgroup's columns (in order) of dZ[a] Z[c]
+    const int nit = (int)std::min<int64_t>(kItems, n - chunk * kItems);
+    double *tp = reinterpret_cast<double *>(base + L.tp) + chunk * r * r;
     for (int e = tid; e < r * r; e += kAdjThreads) {
-        const int a = e / r, c2 = e % r;
+        const int a = e / r, c = e % r;
         double acc = 0.0;
-        for (int64_t j = 0; j < n; j++) acc += dZ[(int64_t)a * n + j] * Z[(int64_t)c2 * n + j];
-        Tm[e] = acc;
+        for (int it = 0; it < nit; it++) acc += dzs[it * 8 * G + a] * zs[it * 8 * G + c];
+        tp[e] = acc;
+    }
+}
+
+// Loss = sum of the row workgroups' partials, T = sum of the column
+// workgroups' parts (both in workgroup order), dG = -G^{-T} T.
+__global__ void __launch_bounds__(256) adj_final_kernel(int r, int64_t rchunks, int64_t cchunks, AdjLayout L,
+                                                        char *ws, double *loss, double *dGb, const int32_t *status) {
+    __shared__ double ts[kRMax * kRMax];
+    const int64_t b = blockIdx.x;
+    if (status[b] != LRA_OK) return;
+    char *base = adj_base(ws, L, b);
+    const double *gi = reinterpret_cast<const double *>(base + L.gi);
+    const double *tp = reinterpret_cast<const double *>(base + L.tp);
+    for (int e = threadIdx.x; e < r * r; e += 256) {
+        double acc = 0.0;
+        for (int64_t c = 0; c < cchunks; c++) acc += tp[c * r * r + e];
+        ts[e] = acc;
     }
     __syncthreads();
-    for (int e = tid; e < r * r; e += kAdjThreads) {
-        const int a = e / r, c2 = e % r;
+    double *dG = dGb + b * r * r;
+    for (int e = threadIdx.x; e < r * r; e += 256) {
+        const int a = e / r, c = e % r;
         double acc = 0.0;
-        for (int q = 0; q < r; q++) acc += Gi[q * r + a] * Tm[q * r + c2];
+        for (int q = 0; q < r; q++) acc += gi[q * r + a] * ts[q * r + c];
         dG[e] = -acc;
     }
-    red[tid] = lsum;
-    __syncthreads();
-    for (int h = kAdjThreads / 2; h > 0; h >>= 1) {
-        if (tid < h) red[tid] += red[tid + h];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        const double *lp = reinterpret_cast<const double *>(base + L.lossp);
+        double acc = 0.0;
+        for (int64_t c = 0; c < rchunks; c++) acc += lp[c];
+        loss[b] = acc;
     }
-    if (tid == 0) {
-        loss[b] = red[0];
-        status[b] = LRA_OK;
-    }
+}
+
+static int adj_lanes(int r) { return r <= 8 ? 1 : r <= 16 ? 2 : r <= 32 ? 4 : 8; }
+
+static AdjLayout adj_layout(int64_t m, int64_t n, int r) {
+    const int G = adj_lanes(r), rp = 8 * G, items = kAdjThreads / G;
+    const int64_t rch = (m + items - 1) / items, cch = (n + items - 1) / items;
+    AdjLayout L;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L.gi = take(8 * (int64_t)r * r);
+    L.zt = take(8 * n * rp);
+    L.cp = take(8 * m * rp);
+    L.rowptr = take(4 * (m + 1));
+    L.colptr = take(4 * (n + 1));
+    L.lossp = take(8 * rch);
+    L.tp = take(8 * cch * r * r);
+    L.stride = o;
+    return L;
+}
+
+size_t adjoint_scratch_bytes(int64_t count, int64_t m, int64_t n, int r) {
+    return (size_t)(adj_layout(m, n, r).stride * count);
+}
+
+template <int G>
+static void launch_adj_passes(int64_t count, int64_t m, int64_t n, int r, int64_t nnz, const int32_t *orow,
+                              const int32_t *ocol, const int32_t *corder, const double *aval, const AdjLayout &L,
+                              char *ws, double *dC, double *dR, const int32_t *status, hipStream_t stream) {
+    constexpr int items = kAdjThreads / G;
+    const int rp = 8 * G;
+    const int64_t rch = (m + items - 1) / items, cch = (n + items - 1) / items;
+    // one workgroup per (block, chunk), rounded up to whole rounds of the XCDs
+    auto wgs = [&](int64_t chunks) { return (unsigned)(kXcds * ((count * chunks + kXcds - 1) / kXcds)); };
+    hipLaunchKernelGGL(adj_row_kernel<G>, dim3(wgs(rch)), dim3(kAdjThreads), 0, stream, count, m, r, rp, nnz, ocol,
+                       aval, rch, L, ws, dC, status);
+    const size_t lds = sizeof(double) * ((size_t)kRMax * kRMax + 2 * (size_t)items * rp);
+    hipLaunchKernelGGL(adj_col_kernel<G>, dim3(wgs(cch)), dim3(kAdjThreads), lds, stream, count, n, r, rp, nnz, orow,
+                       corder, aval, cch, L, ws, dR, status);
 }
 
 hipError_t launch_adjoint(int64_t count, int64_t m, int64_t n, int r, const double *C, const double *R,
                           const double *G, int64_t nnz, const int32_t *orow, const int32_t *ocol,
                           const int32_t *corder, const double *aval, double *loss, double *dC, double *dR,
-                          double *dG, double *ws, int32_t *status, hipStream_t stream) {
-    const size_t lds = sizeof(double) * 3 * (size_t)r * r;
-#define LRA_ADJ(RR)                                                                                              \
-    hipLaunchKernelGGL(adjoint_kernel<RR>, dim3((unsigned)count), dim3(kAdjThreads), lds, stream, m, n, r, C, R, G, \
-                       nnz, orow, ocol, corder, aval, loss, dC, dR, dG, ws, status)
-    if (r <= 16) LRA_ADJ(16);
-    else if (r <= 32) LRA_ADJ(32);
-    else LRA_ADJ(64);
-#undef LRA_ADJ
+                          double *dG, void *scratch, int32_t *status, hipStream_t stream) {
+    char *ws = static_cast<char *>(scratch);
+    const AdjLayout L = adj_layout(m, n, r);
+    const int Gl = adj_lanes(r), rp = 8 * Gl, items = kAdjThreads / Gl;
+    const int64_t rch = (m + items - 1) / items, cch = (n + items - 1) / items;
+    hipLaunchKernelGGL(adj_setup_kernel, dim3((unsigned)count), dim3(kAdjThreads), sizeof(double) * 2 * r * r, stream,
+                       m, n, r, G, nnz, orow, ocol, corder, L, ws, loss, status);
+    hipLaunchKernelGGL(adj_z_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)count), dim3(256), 0, stream, n, r, rp,
+                       R, L, ws, status);
+    hipLaunchKernelGGL(adj_c_kernel, dim3((unsigned)((m * rp + 255) / 256), (unsigned)count), dim3(256), 0, stream, m,
+                       r, rp, C, L, ws, status);
+    switch (Gl) {
+    case 1: launch_adj_passes<1>(count, m, n, r, nnz, orow, ocol, corder, aval, L, ws, dC, dR, status, stream); break;
+    case 2: launch_adj_passes<2>(count, m, n, r, nnz, orow, ocol, corder, aval, L, ws, dC, dR, status, stream); break;
+    case 4: launch_adj_passes<4>(count, m, n, r, nnz, orow, ocol, corder, aval, L, ws, dC, dR, status, stream); break;
+    default: launch_adj_passes<8>(count, m, n, r, nnz, orow, ocol, corder, aval, L, ws, dC, dR, status, stream); break;
+    }
+    hipLaunchKernelGGL(adj_final_kernel, dim3((unsigned)count), dim3(256), 0, stream, r, rch, cch, L, ws, loss, dG,
+                       status);
     return hipGetLastError();
 }
 

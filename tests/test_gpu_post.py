@@ -268,6 +268,17 @@ def test_adjoint_empty_omega_and_errors(lra):
     rows2[0, -1] = 40
     loss, dC, dR, dG, st = adjoint_gpu(lra, C, R, G, rows2, cols, vals)
     assert st.tolist() == [1, 0] and np.isnan(loss[0])
+    # rows not sorted in block 1
+    rows3 = rows.copy()
+    rows3[1, [0, -1]] = rows3[1, [-1, 0]]
+    loss, dC, dR, dG, st = adjoint_gpu(lra, C, R, G, rows3, cols, vals)
+    assert st.tolist() == [0, 1] and np.isnan(loss[1])
+    # a col_order that does not visit the columns in order
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()  # noqa: E731
+    om_row, om_col = d(rows.astype(np.int32)), d(cols.astype(np.int32))
+    ident = torch.arange(rows.shape[1], dtype=torch.int32, device="cuda").repeat(2, 1).contiguous()
+    out = lra.lra_cur_adjoint(d(C), d(R), d(G), om_row, om_col, ident, d(vals))
+    assert out[4].cpu().tolist() == [1, 1]
 
 
 def test_autograd_function(lra):
