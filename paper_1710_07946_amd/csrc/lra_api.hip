@@ -401,7 +401,7 @@ lra_status lra_cur_adjoint(int64_t count, int64_t m, int64_t n, int32_t r, const
     lra_status st;
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
     void *scratch = nullptr;
-    if ((st = ws_scratch(ws, stream, lra::adjoint_scratch_bytes(count, m, n, r), &scratch)) != LRA_OK) return st;
+    if ((st = ws_scratch(ws, stream, lra::adjoint_scratch_bytes(count, m, n, nnz, r), &scratch)) != LRA_OK) return st;
     if (lra::launch_adjoint(count, m, n, r, C, R, G, nnz, om_row, om_col, col_order, a_om, loss, dC, dR, dG, scratch,
                             status, stream) != hipSuccess) {
         (void)hipGetLastError();

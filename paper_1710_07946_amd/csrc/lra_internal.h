@@ -53,7 +53,7 @@ size_t residual_scratch_bytes(int64_t m, int64_t n, int r, int q, int s, int pre
 hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,
                            const int64_t *J, const double *U, int q, int s, uint64_t seed, int prec, double *out,
                            void *scratch, hipStream_t stream);
-size_t adjoint_scratch_bytes(int64_t count, int64_t m, int64_t n, int r);
+size_t adjoint_scratch_bytes(int64_t count, int64_t m, int64_t n, int64_t nnz, int r);
 hipError_t launch_adjoint(int64_t count, int64_t m, int64_t n, int r, const double *C, const double *R,
                           const double *G, int64_t nnz, const int32_t *orow, const int32_t *ocol,
                           const int32_t *corder, const double *aval, double *loss, double *dC, double *dR,

@@ -491,12 +491,15 @@ hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64
 
 // ------------------------------------------------------------------ adjoint
 // L = sum over Omega of (a_ij - (C Z)_ij)^2 with Z = G^{-1} R, for a batch of
-// equal-shape blocks, in five launches:
-//   setup   one workgroup per block: checks the Omega indices, builds the
-//           row pointers (entries are sorted by row) and the column pointers
-//           (through col_order), inverts G (LU with partial pivoting in LDS);
-//   stage   Z^T (n x rp) and a copy of C (m x rp), rank padded to rp = 8 G
-//           (two launches);
+// equal-shape blocks:
+//   index   one thread per Omega entry: checks the indices, the row order and
+//           the column order (col_order), fills the row pointers, the column
+//           pointers and the column-ordered copies of the row indices and
+//           values; any violation sets the block's flag;
+//   inverse one workgroup per block: G^{-1} by LU with partial pivoting in
+//           LDS, or the block's error status;
+//   stage   Z^T (n x rp, rank padded to rp = 8 G) and, when r < rp, a padded
+//           copy of C;
 //   rows    G lanes per row of C, 8 rank entries each: x = C_i . Z_j per
 //           entry of the row, loss, dC_i = sum ebar Z_j;
 //   cols    G lanes per column: dZ_j = sum ebar C_i, dR_j = G^{-T} dZ_j, and
@@ -504,23 +507,74 @@ hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64
 //   final   one workgroup per block: loss and T summed over the workgroups in
 //           a fixed order, dG = -G^{-T} T.
 // The row and column launches put all workgroups of a block on one XCD (the
-// hardware deals workgroup w to XCD w mod 8), so a block's Z^T and C copy
-// stay in that XCD's L2.  Every sum runs in a fixed order: results are
-// deterministic and independent of timing.
+// hardware deals workgroup w to XCD w mod 8), so a block's Z^T and C stay in
+// that XCD's L2.  Every sum runs in a fixed order: results are deterministic.
 constexpr int kAdjThreads = 512;
 constexpr int kXcds = 8;
 
 struct AdjLayout {   // per-block scratch, byte offsets from the block's base
-    int64_t stride, gi, zt, cp, rowptr, colptr, lossp, tp;
+    int64_t stride, gi, zt, cp, rowptr, colptr, crow, cval, lossp, tp, flag;
 };
 
 __device__ __forceinline__ char *adj_base(char *ws, const AdjLayout &L, int64_t b) { return ws + b * L.stride; }
 
-__global__ void __launch_bounds__(kAdjThreads) adj_setup_kernel(int64_t m, int64_t n, int r, const double *Gb,
-                                                                int64_t nnz, const int32_t *orow_b,
-                                                                const int32_t *ocol_b, const int32_t *corder_b,
-                                                                AdjLayout L, char *ws, double *loss,
-                                                                int32_t *status) {
+__global__ void adj_clear_kernel(int64_t count, AdjLayout L, char *ws) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < count) *reinterpret_cast<int32_t *>(adj_base(ws, L, b) + L.flag) = 0;
+}
+
+// Thread q in [0, nnz] of block blockIdx.y.  Pointer entries are written only
+// from a pair of consecutive entries whose indices were checked, so every
+// store stays inside the block's arrays whatever the input.
+__global__ void __launch_bounds__(256) adj_index_kernel(int64_t m, int64_t n, int64_t nnz, const int32_t *orow_b,
+                                                        const int32_t *ocol_b, const int32_t *corder_b,
+                                                        const double *aval_b, AdjLayout L, char *ws) {
+    const int64_t b = blockIdx.y;
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q > nnz) return;
+    const int32_t *orow = orow_b + b * nnz, *ocol = ocol_b + b * nnz, *corder = corder_b + b * nnz;
+    char *base = adj_base(ws, L, b);
+    int32_t *rowptr = reinterpret_cast<int32_t *>(base + L.rowptr);
+    int32_t *colptr = reinterpret_cast<int32_t *>(base + L.colptr);
+    bool bad = false;
+    // rows: entry q and its predecessor
+    const int64_t cur = q < nnz ? orow[q] : m;
+    const int64_t prev = q > 0 ? orow[q - 1] : -1;
+    const bool rok = cur >= 0 && cur <= m && prev >= -1 && prev < m && prev <= cur &&
+                     (q == nnz || (cur < m && ocol[q] >= 0 && ocol[q] < n));
+    if (rok) {
+        for (int64_t i = prev + 1; i <= cur; i++) rowptr[i] = (int32_t)q;
+    } else {
+        bad = true;
+    }
+    // columns: position q of the column order and its predecessor
+    bool cok = true;
+    int64_t tq = -1, cc = n, pc = -1;
+    if (q < nnz) {
+        tq = corder[q];
+        if (tq >= 0 && tq < nnz) cc = ocol[tq];
+        else cok = false;
+    }
+    if (q > 0) {
+        const int64_t tp = corder[q - 1];
+        if (tp >= 0 && tp < nnz) pc = ocol[tp];
+        else cok = false;
+    }
+    cok = cok && cc >= 0 && cc <= n && pc >= -1 && pc < n && pc <= cc && (q == nnz || cc < n);
+    if (cok) {
+        for (int64_t j = pc + 1; j <= cc; j++) colptr[j] = (int32_t)q;
+    } else {
+        bad = true;
+    }
+    if (tq >= 0 && tq < nnz) {
+        reinterpret_cast<int32_t *>(base + L.crow)[q] = orow[tq];
+        reinterpret_cast<double *>(base + L.cval)[q] = aval_b[b * nnz + tq];
+    }
+    if (bad) atomicOr(reinterpret_cast<int32_t *>(base + L.flag), 1);
+}
+
+__global__ void __launch_bounds__(kAdjThreads) adj_inverse_kernel(int r, const double *Gb, AdjLayout L, char *ws,
+                                                                  double *loss, int32_t *status) {
     extern __shared__ __align__(16) double lds[];
     double *LU = lds, *Gi = lds + r * r;
     __shared__ int p[kRMax];
@@ -528,35 +582,13 @@ __global__ void __launch_bounds__(kAdjThreads) adj_setup_kernel(int64_t m, int64
     __shared__ double ld;
     const int tid = threadIdx.x;
     const int64_t b = blockIdx.x;
-    const int32_t *orow = orow_b + b * nnz, *ocol = ocol_b + b * nnz, *corder = corder_b + b * nnz;
     char *base = adj_base(ws, L, b);
-    // Omega: indices inside the block, rows non-decreasing, col_order a
-    // permutation index that visits the columns in non-decreasing order
-    int bad = 0;
-    for (int64_t q = tid; q < nnz; q += kAdjThreads) {
-        const int32_t i = orow[q], j = ocol[q], t = corder[q];
-        bad |= (i < 0 || i >= m || j < 0 || j >= n || t < 0 || t >= nnz) ? 1 : 0;
-        if (q > 0) bad |= orow[q - 1] > i ? 1 : 0;
-    }
-    if (!__syncthreads_or(bad)) {
-        for (int64_t t = tid + 1; t < nnz; t += kAdjThreads) bad |= ocol[corder[t - 1]] > ocol[corder[t]] ? 1 : 0;
-    }
-    if (__syncthreads_or(bad)) {
+    if (*reinterpret_cast<const int32_t *>(base + L.flag)) {
         if (tid == 0) {
             status[b] = LRA_EINVAL;
             loss[b] = __builtin_nan("");
         }
         return;
-    }
-    // row pointers: rowptr[i] = first entry of row i (rowptr[m] = nnz); the
-    // rows between two consecutive entries' rows are filled by the later entry
-    int32_t *rowptr = reinterpret_cast<int32_t *>(base + L.rowptr);
-    int32_t *colptr = reinterpret_cast<int32_t *>(base + L.colptr);
-    for (int64_t q = tid; q <= nnz; q += kAdjThreads) {
-        const int64_t prev = q > 0 ? orow[q - 1] : -1, cur = q < nnz ? orow[q] : m;
-        for (int64_t i = prev + 1; i <= cur; i++) rowptr[i] = (int32_t)q;
-        const int64_t pc = q > 0 ? ocol[corder[q - 1]] : -1, cc = q < nnz ? ocol[corder[q]] : n;
-        for (int64_t j = pc + 1; j <= cc; j++) colptr[j] = (int32_t)q;
     }
     for (int e = tid; e < r * r; e += kAdjThreads) LU[e] = Gb[b * r * r + e];
     __syncthreads();
@@ -573,38 +605,42 @@ __global__ void __launch_bounds__(kAdjThreads) adj_setup_kernel(int64_t m, int64
     if (tid == 0) status[b] = LRA_OK;
 }
 
-// Z^T[j][a] = sum_q Gi[a][q] R[q][j] (q increasing; a < r, zero up to rp),
-// 64 columns per workgroup with the R slice and Gi in LDS.  Grid (column
-// chunks, blocks).
-__global__ void __launch_bounds__(256) adj_z_kernel(int64_t n, int r, int rp, const double *Rb, AdjLayout L,
-                                                    char *ws, const int32_t *status) {
-    __shared__ double gs[kRMax * kRMax];
-    __shared__ double rs[kRMax * 64];
+// Z^T[j][a] = sum_q Gi[a][q] R[q][j] (q increasing; a < r, zero up to RP):
+// one column per thread, its RP sums in registers, G^{-1} transposed in LDS
+// (read as broadcasts).  Grid (chunks of 256 columns, blocks).
+template <int RP>
+__global__ void __launch_bounds__(256) adj_z_kernel(int64_t n, int r, const double *Rb, AdjLayout L, char *ws,
+                                                    const int32_t *status) {
+    __shared__ __align__(16) double gt[kRMax * RP];
     const int64_t b = blockIdx.y;
     if (status[b] != LRA_OK) return;
     const int tid = threadIdx.x;
     char *base = adj_base(ws, L, b);
     const double *gi = reinterpret_cast<const double *>(base + L.gi);
-    const double *R = Rb + b * r * n;
-    const int64_t c0 = (int64_t)blockIdx.x * 64;
-    for (int e = tid; e < r * r; e += 256) gs[e] = gi[e];
-    for (int e = tid; e < r * 64; e += 256) {
-        const int64_t c = c0 + (e & 63);
-        rs[e] = c < n ? R[(int64_t)(e >> 6) * n + c] : 0.0;
+    for (int e = tid; e < r * RP; e += 256) {
+        const int q = e / RP, a = e % RP;
+        gt[e] = a < r ? gi[a * r + q] : 0.0;
     }
     __syncthreads();
-    const int64_t j = c0 + (tid & 63);
+    const int64_t j = (int64_t)blockIdx.x * 256 + tid;
     if (j >= n) return;
-    double *zt = reinterpret_cast<double *>(base + L.zt) + j * rp;
-    for (int a = tid >> 6; a < rp; a += 4) {
-        double acc = 0.0;
-        if (a < r)
-            for (int q = 0; q < r; q++) acc += gs[a * r + q] * rs[q * 64 + (tid & 63)];
-        zt[a] = acc;
+    const double *R = Rb + b * r * n + j;
+    double acc[RP];
+#pragma unroll
+    for (int a = 0; a < RP; a++) acc[a] = 0.0;
+    for (int q = 0; q < r; q++) {
+        const double rq = R[(int64_t)q * n];
+#pragma unroll
+        for (int a = 0; a < RP; a++) acc[a] += gt[q * RP + a] * rq;
     }
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 *zt = reinterpret_cast<d2 *>(reinterpret_cast<double *>(base + L.zt) + j * RP);
+#pragma unroll
+    for (int a = 0; a < RP; a += 2) zt[a / 2] = d2{acc[a], acc[a + 1]};
 }
 
-// Cp[i][a] = C[i][a] (zero for r <= a < rp).  Grid (chunks of 256 entries, blocks).
+// Cp[i][a] = C[i][a] (zero for r <= a < rp), only when r < rp.  Grid (chunks
+// of 256 entries, blocks).
 __global__ void adj_c_kernel(int64_t m, int r, int rp, const double *Cb, AdjLayout L, char *ws,
                              const int32_t *status) {
     const int64_t b = blockIdx.y;
@@ -642,15 +678,55 @@ __device__ __forceinline__ double group_sum(double v) {
     return v;
 }
 
+// One pass over the entries of an item (a row for the row pass, a column for
+// the column pass): `fixed` holds the item's own 8 rank entries, `other` is
+// the matrix gathered per entry (Z^T or C, stride rp), idx/val the entries'
+// other index and value.  The next entry's index, value and gather are
+// issued before the current one is used.  Returns in `acc` the sum of
+// ebar * other over the entries and adds e^2 to *lsum.
+template <int G>
+__device__ __forceinline__ void adj_item_pass(const double (&fixed)[8], const double *other, int rp, int g,
+                                              const int32_t *idx, const double *val, int32_t q0, int32_t q1,
+                                              double (&acc)[8], double *lsum) {
+#pragma unroll
+    for (int k = 0; k < 8; k++) acc[k] = 0.0;
+    if (q0 >= q1) return;
+    double o[8];
+    load8(other + (int64_t)idx[q0] * rp + 8 * g, o);
+    double av = val[q0];
+    for (int32_t q = q0; q < q1; q++) {
+        double on[8];
+        double avn = 0.0;
+        if (q + 1 < q1) {
+            load8(other + (int64_t)idx[q + 1] * rp + 8 * g, on);
+            avn = val[q + 1];
+        }
+        double x = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) x += fixed[k] * o[k];
+        x = group_sum<G>(x);
+        const double e = av - x;
+        *lsum += e * e;
+        const double eb = -2.0 * e;
+#pragma unroll
+        for (int k = 0; k < 8; k++) acc[k] += eb * o[k];
+        if (q + 1 < q1) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) o[k] = on[k];
+            av = avn;
+        }
+    }
+}
+
 // Row pass.  Items = rows of C; G lanes per row, lane g holds rank entries
 // 8 g .. 8 g + 7.  Per entry (i, j) of the row: x = sum_a C_ia Z_aj,
 // e = a_ij - x, loss += e^2, dC_i += -2 e Z_j.
 template <int G>
-__global__ void __launch_bounds__(kAdjThreads) adj_row_kernel(int64_t count, int64_t m, int r, int rp, int64_t nnz,
-                                                              const int32_t *ocol_b, const double *aval_b,
-                                                              int64_t chunks, AdjLayout L, char *ws, double *dCb,
-                                                              const int32_t *status) {
-    constexpr int kItems = kAdjThreads / G;
+__global__ void __launch_bounds__(kAdjThreads) adj_row_kernel(int64_t count, int64_t m, int r, int64_t nnz,
+                                                              const double *Cb, const int32_t *ocol_b,
+                                                              const double *aval_b, int64_t chunks, AdjLayout L,
+                                                              char *ws, double *dCb, const int32_t *status) {
+    constexpr int kItems = kAdjThreads / G, RP = 8 * G;
     __shared__ double red[kAdjThreads / kWave];
     const int64_t wk = xcd_work(blockIdx.x, count * chunks);
     if (wk < 0) return;
@@ -660,37 +736,21 @@ __global__ void __launch_bounds__(kAdjThreads) adj_row_kernel(int64_t count, int
     char *base = adj_base(ws, L, b);
     const int32_t *rowptr = reinterpret_cast<const int32_t *>(base + L.rowptr);
     const double *zt = reinterpret_cast<const double *>(base + L.zt);
-    const double *cp = reinterpret_cast<const double *>(base + L.cp);
-    const int32_t *ocol = ocol_b + b * nnz;
-    const double *aval = aval_b + b * nnz;
+    const double *cm = r == RP ? Cb + b * m * r : reinterpret_cast<const double *>(base + L.cp);
     const int64_t i = chunk * kItems + tid / G;
     double lsum = 0.0;
     if (i < m) {
         double c[8], dc[8];
-        load8(cp + i * rp + 8 * g, c);
-#pragma unroll
-        for (int k = 0; k < 8; k++) dc[k] = 0.0;
-        const int32_t q0 = rowptr[i], q1 = rowptr[i + 1];
-        for (int32_t q = q0; q < q1; q++) {
-            double z[8];
-            load8(zt + (int64_t)ocol[q] * rp + 8 * g, z);
-            double x = 0.0;
-#pragma unroll
-            for (int k = 0; k < 8; k++) x += c[k] * z[k];
-            x = group_sum<G>(x);
-            const double e = aval[q] - x;
-            if (g == 0) lsum += e * e;
-            const double eb = -2.0 * e;
-#pragma unroll
-            for (int k = 0; k < 8; k++) dc[k] += eb * z[k];
-        }
+        load8(cm + i * RP + 8 * g, c);
+        adj_item_pass<G>(c, zt, RP, g, ocol_b + b * nnz, aval_b + b * nnz, rowptr[i], rowptr[i + 1], dc, &lsum);
         double *dC = dCb + b * m * r + i * r;
 #pragma unroll
         for (int k = 0; k < 8; k++)
             if (8 * g + k < r) dC[8 * g + k] = dc[k];
     }
-    const double ws_sum = wave_sum(lsum);
-    if (lane == 0) red[tid / kWave] = ws_sum;
+    if (g != 0) lsum = 0.0;   // every lane of a group computed the same e
+    const double wsum = wave_sum(lsum);
+    if (lane == 0) red[tid / kWave] = wsum;
     __syncthreads();
     if (tid == 0) {
         double acc = 0.0;
@@ -703,15 +763,14 @@ __global__ void __launch_bounds__(kAdjThreads) adj_row_kernel(int64_t count, int
 // ebar = -2 (a_ij - C_i . Z_j), dZ_j += ebar C_i; then dR_j = G^{-T} dZ_j and
 // this workgroup's part of T = sum_j dZ_j Z_j^T.
 template <int G>
-__global__ void __launch_bounds__(kAdjThreads) adj_col_kernel(int64_t count, int64_t n, int r, int rp, int64_t nnz,
-                                                              const int32_t *orow_b, const int32_t *corder_b,
-                                                              const double *aval_b, int64_t chunks, AdjLayout L,
+__global__ void __launch_bounds__(kAdjThreads) adj_col_kernel(int64_t count, int64_t m, int64_t n, int r,
+                                                              const double *Cb, int64_t chunks, AdjLayout L,
                                                               char *ws, double *dRb, const int32_t *status) {
-    constexpr int kItems = kAdjThreads / G;
+    constexpr int kItems = kAdjThreads / G, RP = 8 * G;
     extern __shared__ __align__(16) double lds[];
-    double *gs = lds;                        // Gi, r x r
-    double *dzs = lds + kRMax * kRMax;       // [kItems][rp]
-    double *zs = dzs + kItems * 8 * G;       // [kItems][rp]
+    double *dzs = lds;                       // [kItems][RP]
+    double *zs = lds + kItems * RP;          // [kItems][RP]
+    double *gs = lds + 2 * kItems * RP;      // Gi, r x r
     const int64_t wk = xcd_work(blockIdx.x, count * chunks);
     if (wk < 0) return;
     const int64_t b = wk / chunks, chunk = wk % chunks;
@@ -722,44 +781,34 @@ __global__ void __launch_bounds__(kAdjThreads) adj_col_kernel(int64_t count, int
     for (int e = tid; e < r * r; e += kAdjThreads) gs[e] = gi[e];
     const int32_t *colptr = reinterpret_cast<const int32_t *>(base + L.colptr);
     const double *zt = reinterpret_cast<const double *>(base + L.zt);
-    const double *cp = reinterpret_cast<const double *>(base + L.cp);
-    const int32_t *orow = orow_b + b * nnz, *corder = corder_b + b * nnz;
-    const double *aval = aval_b + b * nnz;
+    const double *cm = r == RP ? Cb + b * m * r : reinterpret_cast<const double *>(base + L.cp);
     const int64_t j = chunk * kItems + li;
     double z[8], dz[8];
 #pragma unroll
     for (int k = 0; k < 8; k++) z[k] = dz[k] = 0.0;
     if (j < n) {
-        load8(zt + j * rp + 8 * g, z);
-        const int32_t t0 = colptr[j], t1 = colptr[j + 1];
-        for (int32_t t = t0; t < t1; t++) {
-            const int32_t q = corder[t];
-            double c[8];
-            load8(cp + (int64_t)orow[q] * rp + 8 * g, c);
-            double x = 0.0;
-#pragma unroll
-            for (int k = 0; k < 8; k++) x += c[k] * z[k];
-            x = group_sum<G>(x);
-            const double eb = -2.0 * (aval[q] - x);
-#pragma unroll
-            for (int k = 0; k < 8; k++) dz[k] += eb * c[k];
-        }
+        double unused = 0.0;
+        load8(zt + j * RP + 8 * g, z);
+        adj_item_pass<G>(z, cm, RP, g, reinterpret_cast<const int32_t *>(base + L.crow),
+                         reinterpret_cast<const double *>(base + L.cval), colptr[j], colptr[j + 1], dz, &unused);
     }
 #pragma unroll
     for (int k = 0; k < 8; k++) {
-        dzs[li * 8 * G + 8 * g + k] = dz[k];
-        zs[li * 8 * G + 8 * g + k] = z[k];
+        dzs[li * RP + 8 * g + k] = dz[k];
+        zs[li * RP + 8 * g + k] = z[k];
     }
     __syncthreads();
     if (j < n) {
         // dR[a][j] = sum_q Gi[q][a] dZ[q][j], q increasing
         double *dR = dRb + b * r * n;
+#pragma unroll
         for (int k = 0; k < 8; k++) {
             const int a = 8 * g + k;
-            if (a >= r) break;
-            double acc = 0.0;
-            for (int q = 0; q < r; q++) acc += gs[q * r + a] * dzs[li * 8 * G + q];
-            dR[(int64_t)a * n + j] = acc;
+            if (a < r) {
+                double acc = 0.0;
+                for (int q = 0; q < r; q++) acc += gs[q * r + a] * dzs[li * RP + q];
+                dR[(int64_t)a * n + j] = acc;
+            }
         }
     }
     // T part: Tp[a][c] = sum over this workgroup's columns (in order) of dZ[a] Z[c]
@@ -768,7 +817,7 @@ __global__ void __launch_bounds__(kAdjThreads) adj_col_kernel(int64_t count, int
     for (int e = tid; e < r * r; e += kAdjThreads) {
         const int a = e / r, c = e % r;
         double acc = 0.0;
-        for (int it = 0; it < nit; it++) acc += dzs[it * 8 * G + a] * zs[it * 8 * G + c];
+        for (int it = 0; it < nit; it++) acc += dzs[it * RP + a] * zs[it * RP + c];
         tp[e] = acc;
     }
 }
@@ -806,7 +855,7 @@ __global__ void __launch_bounds__(256) adj_final_kernel(int r, int64_t rchunks, 
 
 static int adj_lanes(int r) { return r <= 8 ? 1 : r <= 16 ? 2 : r <= 32 ? 4 : 8; }
 
-static AdjLayout adj_layout(int64_t m, int64_t n, int r) {
+static AdjLayout adj_layout(int64_t m, int64_t n, int64_t nnz, int r) {
     const int G = adj_lanes(r), rp = 8 * G, items = kAdjThreads / G;
     const int64_t rch = (m + items - 1) / items, cch = (n + items - 1) / items;
     AdjLayout L;
@@ -818,33 +867,40 @@ static AdjLayout adj_layout(int64_t m, int64_t n, int r) {
     };
     L.gi = take(8 * (int64_t)r * r);
     L.zt = take(8 * n * rp);
-    L.cp = take(8 * m * rp);
+    L.cp = take(r == rp ? 0 : 8 * m * rp);
     L.rowptr = take(4 * (m + 1));
     L.colptr = take(4 * (n + 1));
+    L.crow = take(4 * nnz);
+    L.cval = take(8 * nnz);
     L.lossp = take(8 * rch);
     L.tp = take(8 * cch * r * r);
+    L.flag = take(4);
     L.stride = o;
     return L;
 }
 
-size_t adjoint_scratch_bytes(int64_t count, int64_t m, int64_t n, int r) {
-    return (size_t)(adj_layout(m, n, r).stride * count);
+size_t adjoint_scratch_bytes(int64_t count, int64_t m, int64_t n, int64_t nnz, int r) {
+    return (size_t)(adj_layout(m, n, nnz, r).stride * count);
 }
 
 template <int G>
-static void launch_adj_passes(int64_t count, int64_t m, int64_t n, int r, int64_t nnz, const int32_t *orow,
-                              const int32_t *ocol, const int32_t *corder, const double *aval, const AdjLayout &L,
-                              char *ws, double *dC, double *dR, const int32_t *status, hipStream_t stream) {
-    constexpr int items = kAdjThreads / G;
-    const int rp = 8 * G;
+static void launch_adj_passes(int64_t count, int64_t m, int64_t n, int r, int64_t nnz, const double *C,
+                              const double *R, const int32_t *ocol, const double *aval, const AdjLayout &L, char *ws,
+                              double *dC, double *dR, const int32_t *status, hipStream_t stream) {
+    constexpr int items = kAdjThreads / G, RP = 8 * G;
     const int64_t rch = (m + items - 1) / items, cch = (n + items - 1) / items;
+    hipLaunchKernelGGL(adj_z_kernel<RP>, dim3((unsigned)((n + 255) / 256), (unsigned)count), dim3(256), 0, stream, n,
+                       r, R, L, ws, status);
+    if (r < RP)
+        hipLaunchKernelGGL(adj_c_kernel, dim3((unsigned)((m * RP + 255) / 256), (unsigned)count), dim3(256), 0, stream,
+                           m, r, RP, C, L, ws, status);
     // one workgroup per (block, chunk), rounded up to whole rounds of the XCDs
     auto wgs = [&](int64_t chunks) { return (unsigned)(kXcds * ((count * chunks + kXcds - 1) / kXcds)); };
-    hipLaunchKernelGGL(adj_row_kernel<G>, dim3(wgs(rch)), dim3(kAdjThreads), 0, stream, count, m, r, rp, nnz, ocol,
+    hipLaunchKernelGGL(adj_row_kernel<G>, dim3(wgs(rch)), dim3(kAdjThreads), 0, stream, count, m, r, nnz, C, ocol,
                        aval, rch, L, ws, dC, status);
-    const size_t lds = sizeof(double) * ((size_t)kRMax * kRMax + 2 * (size_t)items * rp);
-    hipLaunchKernelGGL(adj_col_kernel<G>, dim3(wgs(cch)), dim3(kAdjThreads), lds, stream, count, n, r, rp, nnz, orow,
-                       corder, aval, cch, L, ws, dR, status);
+    const size_t lds = sizeof(double) * (2 * (size_t)items * RP + (size_t)r * r);
+    hipLaunchKernelGGL(adj_col_kernel<G>, dim3(wgs(cch)), dim3(kAdjThreads), lds, stream, count, m, n, r, C, cch, L,
+                       ws, dR, status);
 }
 
 hipError_t launch_adjoint(int64_t count, int64_t m, int64_t n, int r, const double *C, const double *R,
@@ -852,20 +908,19 @@ hipError_t launch_adjoint(int64_t count, int64_t m, int64_t n, int r, const doub
                           const int32_t *corder, const double *aval, double *loss, double *dC, double *dR,
                           double *dG, void *scratch, int32_t *status, hipStream_t stream) {
     char *ws = static_cast<char *>(scratch);
-    const AdjLayout L = adj_layout(m, n, r);
-    const int Gl = adj_lanes(r), rp = 8 * Gl, items = kAdjThreads / Gl;
+    const AdjLayout L = adj_layout(m, n, nnz, r);
+    const int Gl = adj_lanes(r), items = kAdjThreads / Gl;
     const int64_t rch = (m + items - 1) / items, cch = (n + items - 1) / items;
-    hipLaunchKernelGGL(adj_setup_kernel, dim3((unsigned)count), dim3(kAdjThreads), sizeof(double) * 2 * r * r, stream,
-                       m, n, r, G, nnz, orow, ocol, corder, L, ws, loss, status);
-    hipLaunchKernelGGL(adj_z_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)count), dim3(256), 0, stream, n, r, rp,
-                       R, L, ws, status);
-    hipLaunchKernelGGL(adj_c_kernel, dim3((unsigned)((m * rp + 255) / 256), (unsigned)count), dim3(256), 0, stream, m,
-                       r, rp, C, L, ws, status);
+    hipLaunchKernelGGL(adj_clear_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream, count, L, ws);
+    hipLaunchKernelGGL(adj_index_kernel, dim3((unsigned)((nnz + 1 + 255) / 256), (unsigned)count), dim3(256), 0, stream,
+                       m, n, nnz, orow, ocol, corder, aval, L, ws);
+    hipLaunchKernelGGL(adj_inverse_kernel, dim3((unsigned)count), dim3(kAdjThreads), sizeof(double) * 2 * r * r, stream,
+                       r, G, L, ws, loss, status);
     switch (Gl) {
-    case 1: launch_adj_passes<1>(count, m, n, r, nnz, orow, ocol, corder, aval, L, ws, dC, dR, status, stream); break;
-    case 2: launch_adj_passes<2>(count, m, n, r, nnz, orow, ocol, corder, aval, L, ws, dC, dR, status, stream); break;
-    case 4: launch_adj_passes<4>(count, m, n, r, nnz, orow, ocol, corder, aval, L, ws, dC, dR, status, stream); break;
-    default: launch_adj_passes<8>(count, m, n, r, nnz, orow, ocol, corder, aval, L, ws, dC, dR, status, stream); break;
+    case 1: launch_adj_passes<1>(count, m, n, r, nnz, C, R, ocol, aval, L, ws, dC, dR, status, stream); break;
+    case 2: launch_adj_passes<2>(count, m, n, r, nnz, C, R, ocol, aval, L, ws, dC, dR, status, stream); break;
+    case 4: launch_adj_passes<4>(count, m, n, r, nnz, C, R, ocol, aval, L, ws, dC, dR, status, stream); break;
+    default: launch_adj_passes<8>(count, m, n, r, nnz, C, R, ocol, aval, L, ws, dC, dR, status, stream); break;
     }
     hipLaunchKernelGGL(adj_final_kernel, dim3((unsigned)count), dim3(256), 0, stream, r, rch, cch, L, ws, loss, dG,
                        status);
