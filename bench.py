@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="time only the headline LRA (skip batched, residual and adjoint lines)")
+    ap.add_argument("--only", choices=["batched", "adjoint", "tall", "residual"], default=None,
+                    help="time one secondary line alone and print it (for profiling)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -92,6 +94,10 @@ def main():
     from paper_1710_07946_amd import workloads
 
     lra.load()
+    if args.only in ("batched", "adjoint", "tall"):
+        fn = {"batched": bench_batched, "adjoint": bench_adjoint, "tall": bench_tall}[args.only]
+        print(json.dumps({args.only: fn(lra, workloads, torch, np, args)}), flush=True)
+        return
     t0 = time.time()
     A_np = workloads.factor_gaussian(M, N, RANK, 1e-6)
     print("# input generated in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
@@ -100,6 +106,10 @@ def main():
 
     out = lra.lra_cur(A, RANK, SWEEPS, SEED, **kw)
     torch.cuda.synchronize()
+    if args.only == "residual":
+        print(json.dumps({"residual": residual_fields(lra, torch, A, out.I, out.J, out.U, M, N, RANK, 4,
+                                                      max(2, args.steps // 5))}), flush=True)
+        return
     for _ in range(args.warmup):
         lra.lra_cur(A, RANK, SWEEPS, SEED, out=out, **kw)
     torch.cuda.synchronize()
@@ -187,6 +197,7 @@ def main():
         rec["secondary"] = {
             "batched_fmm": bench_batched(lra, workloads, torch, np, args),
             "adjoint_2048": bench_adjoint(lra, workloads, torch, np, args),
+            "tall_65536x8192": bench_tall(lra, workloads, torch, np, args),
         }
     print(json.dumps(rec), flush=True)
 
@@ -319,6 +330,38 @@ def bench_adjoint(lra, workloads, torch, np, args):
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
         "useful_bytes_per_launch": nbytes,
     }
+
+
+def bench_tall(lra, workloads, torch, np, args):
+    """65536 x 8192 FP32 of numerical rank 64 (Gaussian factors, unit singular
+    values then i^-2 decay floored at 1e-7): left-form abridged SRHT start
+    (d = 3, l = 128), r = 64, 4 sweeps, nucleus with two refinement steps;
+    then the full residual in FP64 and in mixed precision."""
+    m, n, r = 65536, 8192, 64
+    t0 = time.time()
+    A = workloads.decaying_spectrum_device(m, n, r, 1e-7, 1031, "cuda")
+    torch.cuda.synchronize()
+    print("# tall input generated in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+    kw = dict(preprocess=lra.LRA_PRE_ASRHT, ah_depth=3, ah_samples=128, refine_steps=2)
+    out = lra.lra_cur(A, r, 4, 2051, **kw)
+    ms = _time_events(torch, lambda: lra.lra_cur(A, r, 4, 2051, out=out, **kw), max(2, args.steps // 5), 1)
+    info = out.info()
+    nbytes = 4 * (8 * 128 * n + m * r + info["sweeps_run"] * (m * r + r * n) + r * r)
+    res = residual_fields(lra, torch, A, out.I, out.J, out.U, m, n, r, 4, max(2, args.steps // 5))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    rec = {
+        "workload": "65536x8192 fp32, numerical rank 64 (Gaussian factors, sigma_i = 1 then i^-2, floor 1e-7); "
+                    "left-form abridged SRHT d=3 l=128; r=64, 4 sweeps, nucleus with 2 refinement steps",
+        "lras_per_s": 1e3 / ms, "ms_per_lra": ms, "status": info["status"], "team_size": info["team_size"],
+        "sweeps_run": info["sweeps_run"],
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+        "useful_bytes_per_lra": nbytes,
+        "residual": res,
+    }
+    del A
+    torch.cuda.empty_cache()
+    return rec
 
 
 if __name__ == "__main__":
