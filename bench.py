@@ -53,9 +53,13 @@ def kernel_sources_sha1():
 
 
 def algorithmic_bytes(m, n, r, sweeps_run, depth, samples, elem):
-    """Entries of A the LRA must read: 2^d columns per sampled multiplier
-    column (sketch), the seed row panel, (m + n) r per sweep, the r x r generator."""
-    cells = m * (2 ** depth) * samples + r * n + sweeps_run * (m * r + r * n) + r * r
+    """Entries of A the LRA must read: 2^d rows (m >= n) or columns (m < n) per
+    sampled multiplier column for the sketch, the seed row panel when the
+    sketch picks rows (m < n), (m + n) r per sweep, the r x r generator."""
+    if m >= n:
+        cells = n * (2 ** depth) * samples + sweeps_run * (m * r + r * n) + r * r
+    else:
+        cells = m * (2 ** depth) * samples + r * n + sweeps_run * (m * r + r * n) + r * r
     return cells * elem
 
 
@@ -346,7 +350,7 @@ def bench_tall(lra, workloads, torch, np, args):
     out = lra.lra_cur(A, r, 4, 2051, **kw)
     ms = _time_events(torch, lambda: lra.lra_cur(A, r, 4, 2051, out=out, **kw), max(2, args.steps // 5), 1)
     info = out.info()
-    nbytes = 4 * (8 * 128 * n + m * r + info["sweeps_run"] * (m * r + r * n) + r * r)
+    nbytes = algorithmic_bytes(m, n, r, info["sweeps_run"], 3, 128, 4)
     res = residual_fields(lra, torch, A, out.I, out.J, out.U, m, n, r, 4, max(2, args.steps // 5))
     gbs = nbytes / (ms * 1e-3) / 1e9
     rec = {

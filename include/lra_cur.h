@@ -58,7 +58,9 @@ typedef enum {
 
 typedef enum {
     LRA_PRE_NONE = 0,  /* random initial column set (seeded) */
-    LRA_PRE_ASRHT = 1  /* start set from greedy QRP on an abridged SRHT sketch */
+    LRA_PRE_ASRHT = 1  /* start set from greedy QRP on an abridged SRHT sketch: columns
+                          of M^T W (m >= n, the start column set itself) or rows of
+                          W M (m < n, followed by one row step) */
 } lra_pre;
 
 typedef struct {

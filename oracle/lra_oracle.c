@@ -270,8 +270,9 @@ int orc_maxvol(const double *P, int64_t items, int r, double delta, int32_t max_
 /* sampling) and scaled by sqrt(N/l); the factor 2^{-d/2} makes H_{N,d}      */
 /* orthogonal.  Inputs with a dimension that is not a multiple of 2^d are    */
 /* zero-padded to N.                                                         */
-/*   side 0 (post-multiplication, m <= n):  Y = W M_S, items = rows of W;    */
-/*   side 1 (pre-multiplication, m > n, Section 11 remark on m > n):         */
+/*   side 0 (post-multiplication, m < n):  Y = W M_S, items = rows of W;     */
+/*   side 1 (pre-multiplication, m >= n; Section 11 remark on m > n, and     */
+/*          either form for m = n):                                          */
 /*          Y = M_S^T W, items = columns of W.                               */
 /* Output Y is items x l row-major; samples[q] is the q-th sampled column.   */
 /* ------------------------------------------------------------------------ */
@@ -526,7 +527,9 @@ int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
     int st = ORC_OK;
 
     if (o.preprocess == 1) {
-        int side = (m > n) ? 1 : 0;
+        /* pre-multiplication for m >= n (the paper allows either form when   */
+        /* m = n; this one yields the start columns directly)                */
+        int side = (m >= n) ? 1 : 0;
         int64_t items = side ? n : m;
         int l = o.ah_samples;
         if (l < r) { st = ORC_EINVAL; goto done; }

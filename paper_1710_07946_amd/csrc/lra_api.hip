@@ -144,7 +144,7 @@ LdsPlan plan_lds(int64_t m, int64_t n, int r, int pre, int l, int team, size_t b
     size_t cells = std::max((size_t)(ipw | 1) * r, (size_t)4 * r * r);
     int64_t flag_items = ipw;
     if (pre == LRA_PRE_ASRHT) {
-        p.ipw_s = ((m > n) ? (n + team - 1) / team : (m + team - 1) / team);
+        p.ipw_s = ((m >= n) ? (n + team - 1) / team : (m + team - 1) / team);
         const size_t sk = (size_t)(p.ipw_s | 1) * l;
         const size_t with = align16(std::max(cells, sk) * sizeof(double)) + align16(std::max(ipw, p.ipw_s));
         if (with <= budget) {
@@ -221,7 +221,7 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
     if (st != LRA_OK) return st;
     if (o.preprocess == LRA_PRE_ASRHT) {
-        const int64_t dim = (m > n) ? m : n;  // the dimension the multiplier acts on
+        const int64_t dim = (m >= n) ? m : n;  // the dimension the multiplier acts on
         const int64_t q2 = (int64_t)1 << o.ah_depth;
         const int64_t N = q2 * ((dim + q2 - 1) / q2);
         if (o.ah_samples > N) return LRA_EINVAL;

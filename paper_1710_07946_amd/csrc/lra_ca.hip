@@ -51,6 +51,11 @@ __device__ __forceinline__ void trace(int ev, uint64_t val = 0) {
     }
 }
 #define LRA_TR(ev, val) trace(ev, val)
+// per selection and workgroup: wall clock when its header was stored and
+// when its poll of the team's headers completed (first kSelTrace selections)
+constexpr int kSelTrace = 1024;
+__device__ uint64_t g_sel_pub[kSelTrace * 256];
+__device__ uint64_t g_sel_done[kSelTrace * 256];
 #else
 #define LRA_TR(ev, val) ((void)0)
 #endif
@@ -269,6 +274,9 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                 xput(mine + 1, tag, (uint32_t)(v >> 32));
                 xput(mine + 2, tag, (uint32_t)it);
                 xput(mine + 3, tag, hi | ((uint32_t)(loc.slot & 0xff) << 8) | ((uint32_t)(f & 0xff) << 16));
+#ifdef LRA_TRACE
+                if (tm.epoch < kSelTrace && tm.rank < 256) g_sel_pub[tm.epoch * 256 + tm.rank] = wall_clock64();
+#endif
             }
             // every lane polls up to kMaxTeam / 64 headers, all loads at once
             Best c = none();
@@ -299,6 +307,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
             wf = wave_or(cf);
 #ifdef LRA_TRACE
             t_b = wall_clock64();
+            if (lane == 0 && tm.epoch < kSelTrace && tm.rank < 256) g_sel_done[tm.epoch * 256 + tm.rank] = t_b;
 #endif
             // no candidate in the whole team (every item is in the basis):
             // there is no winner row to fetch
@@ -799,7 +808,9 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     __syncthreads();
     // ---- start set
     if (cfg.pre == LRA_PRE_ASRHT) {
-        const int side = (m > n) ? 1 : 0;
+        // pre-multiplication for m >= n (either form is allowed when m = n;
+        // this one reads whole rows of W and yields the start columns directly)
+        const int side = (m >= n) ? 1 : 0;
         // the items x l sketch slice lives in LDS when it fits, else in a
         // per-workgroup slice of global memory (touched by this workgroup only)
         // (two call sites so that each copy knows its panel's address space)
@@ -1028,6 +1039,15 @@ size_t static_lds_bytes() { return sizeof(Smem) + sizeof(int) * kRMax; }
 
 #ifdef LRA_TRACE
 // Copy the trace of the last traced launches out and reset it (tracing builds only).
+// Copy the per-selection publish / poll-done clocks ([kSelTrace][256] each).
+extern "C" int lra_trace_sel(uint64_t *pub, uint64_t *done) {
+    if (hipMemcpyFromSymbol(pub, HIP_SYMBOL(lra::g_sel_pub), sizeof(uint64_t) * lra::kSelTrace * 256) != hipSuccess)
+        return -1;
+    if (hipMemcpyFromSymbol(done, HIP_SYMBOL(lra::g_sel_done), sizeof(uint64_t) * lra::kSelTrace * 256) != hipSuccess)
+        return -1;
+    return lra::kSelTrace;
+}
+
 extern "C" int lra_trace_read(uint64_t *host, int max_events) {
     int n = 0;
     if (hipMemcpyFromSymbol(&n, HIP_SYMBOL(lra::g_trace_n), sizeof(int)) != hipSuccess) return -1;

@@ -160,7 +160,7 @@ def test_preprocessed_start(orc, m, n):
     assert res.status == 0
     assert orc.rel_fro(A, res.I, res.J, res.U) < 1e-6
     # the start set is the greedy QRP choice on the sketch
-    side = 1 if m > n else 0
+    side = 1 if m >= n else 0
     Y, _ = orc.sketch(A, side, 2, 24, 2011)
     st, piv, _, _ = orc.qrp(Y, 12)
     assert st == 0
