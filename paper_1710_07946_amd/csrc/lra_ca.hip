@@ -80,23 +80,64 @@ __device__ __forceinline__ void consider(Best &b, double v, int64_t item, int sl
     if (better(v, item, slot, b.v, b.item, b.slot)) b = Best{v, item, slot, aux};
 }
 
+// Wavefront argmax without LDS traffic: four DPP butterflies (quad swaps,
+// half-row and row mirrors) leave every lane of a 16-lane row with the row's
+// best, then the four rows are read out as uniform values and combined.  The
+// order is total, so the result does not depend on the tree's shape.  All 64
+// lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+    const int lo = dpp32<CTRL>((int)(uint32_t)v), hi = dpp32<CTRL>((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ void dpp_step(Best &b) {
+    Best o;
+    o.v = __longlong_as_double(dpp64<CTRL>(__double_as_longlong(b.v)));
+    o.item = dpp64<CTRL>(b.item);
+    o.slot = dpp32<CTRL>(b.slot);
+    o.aux = dpp32<CTRL>(b.aux);
+    if (better(o.v, o.item, o.slot, b.v, b.item, b.slot)) b = o;
+}
+__device__ __forceinline__ Best rdl_best(const Best &b, int lane) {
+    return Best{__longlong_as_double(rdl64(__double_as_longlong(b.v), lane)), rdl64(b.item, lane),
+                __builtin_amdgcn_readlane(b.slot, lane), __builtin_amdgcn_readlane(b.aux, lane)};
+}
+constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
 __device__ __forceinline__ Best wave_reduce(Best b) {
+    dpp_step<kDppQuadSwap1>(b);
+    dpp_step<kDppQuadSwap2>(b);
+    dpp_step<kDppHalfMirror>(b);
+    dpp_step<kDppMirror>(b);
+    Best r = rdl_best(b, 0);
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        Best o;
-        o.v = __shfl_xor(b.v, off);
-        o.item = __shfl_xor(b.item, off);
-        o.slot = __shfl_xor(b.slot, off);
-        o.aux = __shfl_xor(b.aux, off);
-        if (better(o.v, o.item, o.slot, b.v, b.item, b.slot)) b = o;
+    for (int row = 1; row < 4; row++) {
+        const Best o = rdl_best(b, 16 * row);
+        if (better(o.v, o.item, o.slot, r.v, r.item, r.slot)) r = o;
     }
-    return b;
+    return r;
 }
 
 __device__ __forceinline__ int wave_or(int f) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) f |= __shfl_xor(f, off);
-    return f;
+    f |= dpp32<kDppQuadSwap1>(f);
+    f |= dpp32<kDppQuadSwap2>(f);
+    f |= dpp32<kDppHalfMirror>(f);
+    f |= dpp32<kDppMirror>(f);
+    return __builtin_amdgcn_readlane(f, 0) | __builtin_amdgcn_readlane(f, 16) | __builtin_amdgcn_readlane(f, 32) |
+           __builtin_amdgcn_readlane(f, 48);
 }
 
 // ---------------------------------------------------------------- LDS state
