@@ -145,6 +145,7 @@ struct Smem {
     int64_t Iset[kRMax], Jset[kRMax], Iprev[kRMax], Jprev[kRMax];
     int64_t slot_item[kRMax];
     int64_t samples[kLMax];
+    uint8_t sgn[kLMax];   // sketch: combined signs of a sampled column's 2^d <= 8 terms
     double L11[kRMax * (kRMax - 1) / 2];
     double wrow[kLMax];
     Best red[kNWave];
@@ -695,24 +696,72 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
     LRA_TR(2, 0);
     const double scale = sqrt((double)s / (double)l);
     int bad = 0;
-    const int tot = g.cnt * l;
-    for (int e = tid; e < tot; e += kBlock) {
-        const int li = e % g.cnt, q = e / g.cnt;
-        const int64_t it = g.base + li;
-        const int64_t t = sm.samples[q];
-        const int64_t bb = t / s, ee = t % s;
-        double acc = 0.0;
-#pragma unroll 8
-        for (int64_t a = 0; a < q2; a++) {
-            const int64_t c = a * s + ee;
-            if (c >= dim) continue;
-            const double h = (__popcll((uint64_t)(a & bb)) & 1) ? -1.0 : 1.0;
-            const double w = side ? Elem<T>::load(A, c * lda + it) : Elem<T>::load(A, it * lda + c);
-            acc += w * rademacher(seed, c) * h;
+    if (q2 <= 8) {
+        // per sampled column t = b s + e: the offset e and the signs
+        // D[a s + e] (-1)^{popcount(a & b)} of its 2^d terms as a bit mask, so
+        // the item loop has no division and no hashing (each term is +-w exactly)
+        for (int q = tid; q < l; q += kBlock) {
+            const int64_t t = sm.samples[q];
+            const int64_t bb = t / s, ee = t % s;
+            uint32_t mask = 0;
+            for (int64_t a = 0; a < q2; a++) {
+                const int64_t c = a * s + ee;
+                const double h = (__popcll((uint64_t)(a & bb)) & 1) ? -1.0 : 1.0;
+                if (c < dim && rademacher(seed, c) * h < 0.0) mask |= 1u << a;
+            }
+            sm.sgn[q] = (uint8_t)mask;
+            sm.samples[q] = ee;
         }
-        const double y = scale * acc;
-        if (!isfinite(y)) bad = 1;
-        panel[q * g.st + li] = y;
+        __syncthreads();
+        if (g.cnt > 0) {
+            // thread -> (item, sample) without division: step by kBlock entries
+            int li = tid % g.cnt, q = tid / g.cnt;
+            const int dli = kBlock % g.cnt, dq = kBlock / g.cnt;
+            while (q < l) {
+                const int64_t it = g.base + li;
+                const int64_t ee = sm.samples[q];
+                const uint32_t mask = sm.sgn[q];
+                double w[8];
+#pragma unroll
+                for (int a = 0; a < 8; a++) {
+                    const int64_t c = a * s + ee;
+                    w[a] = 0.0;
+                    if (a < q2 && c < dim) w[a] = side ? Elem<T>::load(A, c * lda + it) : Elem<T>::load(A, it * lda + c);
+                }
+                double acc = 0.0;
+#pragma unroll
+                for (int a = 0; a < 8; a++)
+                    if (a < q2 && a * s + ee < dim) acc += ((mask >> a) & 1u) ? -w[a] : w[a];
+                const double y = scale * acc;
+                if (!isfinite(y)) bad = 1;
+                panel[q * g.st + li] = y;
+                li += dli;
+                q += dq;
+                if (li >= g.cnt) {
+                    li -= g.cnt;
+                    q++;
+                }
+            }
+        }
+    } else {
+        const int tot = g.cnt * l;
+        for (int e = tid; e < tot; e += kBlock) {
+            const int li = e % g.cnt, q = e / g.cnt;
+            const int64_t it = g.base + li;
+            const int64_t t = sm.samples[q];
+            const int64_t bb = t / s, ee = t % s;
+            double acc = 0.0;
+            for (int64_t a = 0; a < q2; a++) {
+                const int64_t c = a * s + ee;
+                if (c >= dim) continue;
+                const double h = (__popcll((uint64_t)(a & bb)) & 1) ? -1.0 : 1.0;
+                const double w = side ? Elem<T>::load(A, c * lda + it) : Elem<T>::load(A, it * lda + c);
+                acc += w * rademacher(seed, c) * h;
+            }
+            const double y = scale * acc;
+            if (!isfinite(y)) bad = 1;
+            panel[q * g.st + li] = y;
+        }
     }
     for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
@@ -723,8 +772,9 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
         const double vtv = sm.vtv;
         for (int li = tid; li < g.cnt; li += kBlock) {
             if (flags[li]) continue;
+            // (terms past the end add +0.0 to a sum that is never -0.0)
+            double nrm = 0.0;
             if (gg > 0 && vtv > 0.0) {  // reflection of step gg-1 (vector in sm.wrow[gg-1 ..])
-                // (terms past the end add +0.0 to a sum that is never -0.0)
                 double acc = 0.0;
                 for (int c0 = gg - 1; c0 < l; c0 += kChunk) {
                     double z[kChunk], w[kChunk];
@@ -738,6 +788,8 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
                     for (int u = 0; u < kChunk; u++) acc += (c0 + u < l) ? w[u] * z[u] : 0.0;
                 }
                 const double f = 2.0 * acc / vtv;
+                // the update and the norm of the entries from gg on in one pass
+                // (the norm's terms still in increasing index order)
                 for (int c0 = gg - 1; c0 < l; c0 += kChunk) {
                     double z[kChunk], w[kChunk];
 #pragma unroll
@@ -747,18 +799,23 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
                         w[u] = sm.wrow[c];
                     }
 #pragma unroll
-                    for (int u = 0; u < kChunk; u++) panel[min(c0 + u, l - 1) * ipw + li] = z[u] - f * w[u];
+                    for (int u = 0; u < kChunk; u++) {
+                        z[u] = z[u] - f * w[u];
+                        panel[min(c0 + u, l - 1) * ipw + li] = z[u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) nrm += (c0 + u >= gg && c0 + u < l) ? z[u] * z[u] : 0.0;
+                }
+            } else {
+                for (int c0 = gg; c0 < l; c0 += kChunk) {
+                    double z[kChunk];
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) z[u] = panel[min(c0 + u, l - 1) * ipw + li];
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) nrm += (c0 + u < l) ? z[u] * z[u] : 0.0;
                 }
             }
-            double acc = 0.0;
-            for (int c0 = gg; c0 < l; c0 += kChunk) {
-                double z[kChunk];
-#pragma unroll
-                for (int u = 0; u < kChunk; u++) z[u] = panel[min(c0 + u, l - 1) * ipw + li];
-#pragma unroll
-                for (int u = 0; u < kChunk; u++) acc += (c0 + u < l) ? z[u] * z[u] : 0.0;
-            }
-            consider(b, acc, g.base + li, 0);
+            consider(b, nrm, g.base + li, 0);
         }
         team_select(tm, sm, b, gg == 0 ? bad : 0, panel, g, l, kSelHouseholder, gg);
         if (sm.win_flag) return fail_status(sm, LRA_EINVAL, 0);
@@ -789,9 +846,11 @@ __device__ __forceinline__ void nucleus(Smem &sm, double *ws, const T *A, int64_
         LU[e] = v;
     }
     __syncthreads();
+    LRA_TR(22, 0);
     __shared__ int sing;
     __shared__ double ld;
     inverse_lds(LU, X, p, r, kBlock, &sing, &ld);
+    LRA_TR(23, 0);
     if (sing) {
         if (tid == 0) {
             sm.status = LRA_ESINGULAR;

@@ -85,106 +85,141 @@ __device__ __forceinline__ void draw_distinct_wave(uint64_t seed, uint64_t strea
 
 
 
-// Inverse of an r x r matrix (r <= 64) held in LDS: LU with partial pivoting
-// (largest magnitude, ties to the lowest row) in wave 0, then one column
-// solve per thread, in the order of the oracle's routine.  LU holds G on entry
-// and the factors on exit, X receives G^{-1}, p (LDS, r ints) the row order.
-// *sing_out = 1 if a pivot is exactly zero (X is then not written);
-// *logdet = log |det G|.  Every thread of the block must call.
+// ---------------------------------------------------------------- DPP argmax
+// Argmax over a wavefront of (value, key) pairs: largest value, then lowest
+// key; also returns the winning lane.  Four DPP butterflies (quad swaps,
+// half-row and row mirrors) leave each 16-lane row with its best, then the
+// four rows are combined from uniform read-outs.  All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int64_t b = __double_as_longlong(v);
+    const int lo = dpp_i32<CTRL>((int)(uint32_t)b), hi = dpp_i32<CTRL>((int)(uint32_t)((uint64_t)b >> 32));
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double rdl_f64(double v, int lane) {
+    const int64_t b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)b >> 32), lane);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+struct KeyMax {
+    double v;
+    int key, who;
+};
+__device__ __forceinline__ bool key_better(double v1, int k1, double v2, int k2) {
+    return v1 > v2 || (v1 == v2 && k1 < k2);
+}
+template <int CTRL>
+__device__ __forceinline__ void keymax_step(KeyMax &b) {
+    const double ov = dpp_f64<CTRL>(b.v);
+    const int ok = dpp_i32<CTRL>(b.key), ow = dpp_i32<CTRL>(b.who);
+    if (key_better(ov, ok, b.v, b.key)) b = KeyMax{ov, ok, ow};
+}
+__device__ __forceinline__ KeyMax wave_keymax(KeyMax b) {
+    keymax_step<0xB1>(b);    // quad_perm [1,0,3,2]
+    keymax_step<0x4E>(b);    // quad_perm [2,3,0,1]
+    keymax_step<0x141>(b);   // row half mirror
+    keymax_step<0x140>(b);   // row mirror
+    KeyMax r{rdl_f64(b.v, 0), __builtin_amdgcn_readlane(b.key, 0), __builtin_amdgcn_readlane(b.who, 0)};
+#pragma unroll
+    for (int row = 1; row < 4; row++) {
+        const KeyMax o{rdl_f64(b.v, 16 * row), __builtin_amdgcn_readlane(b.key, 16 * row),
+                       __builtin_amdgcn_readlane(b.who, 16 * row)};
+        if (key_better(o.v, o.key, r.v, r.key)) r = o;
+    }
+    return r;
+}
+
+// Inverse of an r x r matrix (r <= 64) held in LDS, with the arithmetic of
+// the oracle's routine entry for entry: LU with partial pivoting (largest
+// magnitude, ties to the lowest original row), then for each column c of the
+// inverse L y = P e_c and U x = y.
+//  * pivot search: wave 0, one lane per permutation position (DPP argmax);
+//  * elimination of step k: 8 consecutive lanes per trailing row (one
+//    wavefront reads the row's entry k before its first lane stores the
+//    multiplier there);
+//  * forward solve, column-oriented: after y_j is final every later row
+//    subtracts L_ij y_j, so each row still subtracts its terms in increasing j;
+//  * backward solve: one thread per column, the oracle's row order.
+// LU holds G on entry and the factors on exit (rows in original order, p the
+// permutation), X receives G^{-1}.  *sing_out = 1 if a pivot is exactly zero
+// (X is then not written); *logdet = log |det G|.  Every thread of the block
+// (nthreads >= 512) must call.
 __device__ __forceinline__ void inverse_lds(double *LU, double *X, int *p, int r, int nthreads, int *sing_out,
                                             double *logdet) {
     const int tid = threadIdx.x;
-    __syncthreads();
-    // LU with partial pivoting in wave 0: lane i works on the row at position
-    // i of the permutation (its original index held in register pi).
-    if (tid < kWave) {
-        const int lane = tid;
-        int pi = lane;
-        double ld = 0.0;
-        int sing = 0;
-        for (int k = 0; k < r; k++) {
-            const bool cand = lane >= k && lane < r;
-            double a = cand ? fabs(LU[pi * r + k]) : -1.0;
-            int key = cand ? pi : 0x7fffffff, who = lane;
-#pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1) {
-                const double oa = __shfl_xor(a, off);
-                const int ok = __shfl_xor(key, off), ow = __shfl_xor(who, off);
-                if (oa > a || (oa == a && ok < key)) {
-                    a = oa;
-                    key = ok;
-                    who = ow;
-                }
-            }
-            if (a == 0.0) {  // largest magnitude ties go to the lowest row
-                sing = 1;
-                break;
-            }
-            const int p_k = __shfl(pi, k), p_w = __shfl(pi, who);
-            if (lane == k) pi = p_w;
-            else if (lane == who) pi = p_k;
-            ld += log(a);
-            const int prow = p_w;
-            const double piv = LU[prow * r + k];
-            __builtin_amdgcn_wave_barrier();
-            if (lane > k && lane < r) {
-                const double l = LU[pi * r + k] / piv;
-                LU[pi * r + k] = l;
-                for (int j0 = k + 1; j0 < r; j0 += kInvChunk) {
-                    double av[kInvChunk], uv[kInvChunk];
-#pragma unroll
-                    for (int u = 0; u < kInvChunk; u++) {
-                        const int j = min(j0 + u, r - 1);  // past the end: repeat entry r-1
-                        av[u] = LU[pi * r + j];
-                        uv[u] = LU[prow * r + j];
-                    }
-#pragma unroll
-                    for (int u = 0; u < kInvChunk; u++) LU[pi * r + min(j0 + u, r - 1)] = av[u] - l * uv[u];
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-        if (lane < r) p[lane] = pi;
-        if (lane == 0) {
-            *sing_out = sing;
-            *logdet = ld;
-        }
+    __shared__ double s_pk;
+    if (tid < r) p[tid] = tid;
+    if (tid == 0) {
+        *sing_out = 0;
+        *logdet = 0.0;
     }
     __syncthreads();
-    if (*(volatile int *)sing_out) return;
-    // column c of G^{-1}: L y = P e_c, U x = y (stored in column c of X)
-    for (int c = tid; c < r; c += nthreads) {
-        for (int i = 0; i < r; i++) {
-            const int pi = p[i];
-            double s = (pi == c) ? 1.0 : 0.0;
-            for (int j0 = 0; j0 < i; j0 += kInvChunk) {
-                double a[kInvChunk], x[kInvChunk];
-#pragma unroll
-                for (int u = 0; u < kInvChunk; u++) {
-                    const int j = min(j0 + u, i - 1);
-                    a[u] = LU[pi * r + j];
-                    x[u] = X[j * r + c];
+    for (int k = 0; k < r; k++) {
+        if (tid < kWave) {
+            const int lane = tid;
+            const bool cand = lane >= k && lane < r;
+            const int pl = lane < r ? p[lane] : 0x7fffffff;
+            KeyMax c{cand ? fabs(LU[pl * r + k]) : -1.0, cand ? pl : 0x7fffffff, lane};
+            c = wave_keymax(c);
+            if (lane == 0) {
+                if (c.v == 0.0) {
+                    *sing_out = 1;
+                } else {
+                    const int pk_row = p[c.who];
+                    p[c.who] = p[k];
+                    p[k] = pk_row;
+                    s_pk = LU[pk_row * r + k];
+                    *logdet += log(fabs(s_pk));
                 }
-#pragma unroll
-                for (int u = 0; u < kInvChunk; u++) s -= (j0 + u < i) ? a[u] * x[u] : 0.0;
             }
-            X[i * r + c] = s;
         }
-        for (int i = r - 1; i >= 0; i--) {
+        __syncthreads();
+        if (*(volatile int *)sing_out) return;
+        const double pk = s_pk;
+        const int pr = p[k];
+        const int i = k + 1 + tid / 8, t = tid % 8;
+        if (i < r) {
             const int pi = p[i];
-            double s = X[i * r + c];
-            for (int j0 = i + 1; j0 < r; j0 += kInvChunk) {
+            const double l = LU[pi * r + k] / pk;
+            for (int j = k + 1 + t; j < r; j += 8) LU[pi * r + j] -= l * LU[pr * r + j];
+            if (t == 0) LU[pi * r + k] = l;
+        }
+        __syncthreads();
+    }
+    // forward: X[i][c] = (p_i == c) - sum_{j < i} L[p_i][j] X[j][c], column-oriented
+    const int c = tid % kWave, rg = tid / kWave, ng = nthreads / kWave;
+    if (c < r)
+        for (int i = rg; i < r; i += ng) X[i * r + c] = (p[i] == c) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int j = 0; j < r - 1; j++) {
+        if (c < r) {
+            const double xj = X[j * r + c];
+            for (int i = j + 1 + rg; i < r; i += ng) X[i * r + c] -= LU[p[i] * r + j] * xj;
+        }
+        __syncthreads();
+    }
+    // backward: x_i = (y_i - sum_{j > i} U[p_i][j] x_j) / U[p_i][i], j increasing
+    for (int cc = tid; cc < r; cc += nthreads) {
+        for (int ii = r - 1; ii >= 0; ii--) {
+            const int pi = p[ii];
+            double sum = X[ii * r + cc];
+            for (int j0 = ii + 1; j0 < r; j0 += kInvChunk) {
                 double a[kInvChunk], x[kInvChunk];
 #pragma unroll
                 for (int u = 0; u < kInvChunk; u++) {
                     const int j = min(j0 + u, r - 1);
                     a[u] = LU[pi * r + j];
-                    x[u] = X[j * r + c];
+                    x[u] = X[j * r + cc];
                 }
 #pragma unroll
-                for (int u = 0; u < kInvChunk; u++) s -= (j0 + u < r) ? a[u] * x[u] : 0.0;
+                for (int u = 0; u < kInvChunk; u++) sum -= (j0 + u < r) ? a[u] * x[u] : 0.0;
             }
-            X[i * r + c] = s / LU[pi * r + i];
+            X[ii * r + cc] = sum / LU[pi * r + ii];
         }
     }
     __syncthreads();
