@@ -3,7 +3,8 @@
  *
  * The library computes CUR low-rank approximations W' = C U R of an m x n
  * matrix W, with C = W[:, J] (r columns), R = W[I, :] (r rows) and the r x r
- * nucleus U = W[I, J]^{-1}, by cross-approximation (C-A) iterations:
+ * nucleus U = W[I, J]^{-1} (or, for a numerically singular generator, the
+ * pseudo-inverse of its truncation), by cross-approximation (C-A) iterations:
  * alternating maxvol searches on the gathered m x r column panel and the
  * r x n row panel (Pan, Luan, Svadlenka, Zhao, "Superfast Accurate Low Rank
  * Approximation": CUR definition eq. (eqcur0), C-A loops in Section 1.3 and
@@ -81,7 +82,9 @@ typedef struct {
     int32_t converged;     /* 1 if every maxvol search met the 1 + delta rule */
     int32_t rank_found;    /* r, or the rank of the first rank-deficient panel */
     int32_t team_size;     /* workgroups used */
-    double det_log_abs;    /* log |det W[I, J]| of the final generator */
+    int32_t nucleus_rank;  /* r, or the rank kept by the truncated pseudo-inverse nucleus */
+    int32_t reserved;
+    double det_log_abs;    /* log |det W[I, J]| of the final generator (-inf if singular) */
 } lra_info;
 
 /* Fill *o with the defaults listed above. */

@@ -43,7 +43,8 @@ class _Opts(ct.Structure):
 
 class _Info(ct.Structure):
     _fields_ = [("sweeps_run", ct.c_int32), ("swaps_total", ct.c_int32), ("converged", ct.c_int32),
-                ("rank_found", ct.c_int32), ("min_margin", ct.c_double), ("det_log_abs", ct.c_double)]
+                ("rank_found", ct.c_int32), ("nucleus_rank", ct.c_int32), ("pad", ct.c_int32),
+                ("min_margin", ct.c_double), ("det_log_abs", ct.c_double)]
 
 
 _lib = None
@@ -180,6 +181,27 @@ def qrp(Z: np.ndarray, k: int):
     return st, piv, rank.value, mm.value
 
 
+def pinv_jacobi(G: np.ndarray, rtol: float = 1e-14):
+    """Truncated pseudo-inverse by one-sided Jacobi SVD: (status, X, kept rank)."""
+    G = np.ascontiguousarray(G, np.float64)
+    r = G.shape[0]
+    X = np.zeros_like(G)
+    rk = ct.c_int(0)
+    st = lib().orc_pinv_jacobi(_p(G), r, ct.c_double(rtol), _p(X), ct.byref(rk))
+    return st, X, rk.value
+
+
+def nucleus(G: np.ndarray, refine_steps: int = 0):
+    """The nucleus routine of the C-A driver: (status, U, log|det G|, kept rank)."""
+    G = np.ascontiguousarray(G, np.float64)
+    r = G.shape[0]
+    U = np.zeros_like(G)
+    ld = ct.c_double(0.0)
+    rk = ct.c_int(0)
+    st = lib().orc_nucleus(_p(G), r, refine_steps, _p(U), ct.byref(ld), ct.byref(rk))
+    return st, U, ld.value, rk.value
+
+
 def inverse(G: np.ndarray, refine_steps: int = 0):
     G = np.ascontiguousarray(G, np.float64)
     r = G.shape[0]
@@ -204,6 +226,7 @@ class CurResult:
     rank_found: int
     min_margin: float
     det_log_abs: float
+    nucleus_rank: int = 0
 
 
 def ca_cur(A: np.ndarray, r: int, sweeps: int, seed: int, delta: float = 0.01, max_swaps: int = -1,
@@ -233,7 +256,7 @@ def ca_cur(A: np.ndarray, r: int, sweeps: int, seed: int, delta: float = 0.01, m
     st = lib().orc_ca_cur(_p(A), _dtype_code(A), m, n, n, r, sweeps, seed, ct.byref(o),
                           _p(I), _p(J), _p(U), ct.byref(info))
     return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
-                     info.min_margin, info.det_log_abs)
+                     info.min_margin, info.det_log_abs, info.nucleus_rank)
 
 
 def residual(A: np.ndarray, I, J, U):

@@ -439,6 +439,139 @@ int orc_inverse(const double *G, int r, double *U, int refine_steps, double *log
 }
 
 /* ------------------------------------------------------------------------ */
+/* Truncated pseudo-inverse by one-sided Jacobi (Hestenes) SVD: the nucleus   */
+/* of Algorithm algcnnncl when the generator is singular or too badly         */
+/* conditioned for the LU inverse.  The columns of A = G are orthogonalised   */
+/* by plane rotations (V accumulates them); pairs are visited in round-robin  */
+/* order (position 0 fixed, the others rotating; a dummy position pads odd r);*/
+/* a pair is rotated unless |a_p . a_q| <= 1e-15 sqrt(|a_p|^2 |a_q|^2); sweeps */
+/* repeat until one applies no rotation (at most 60).  Then sigma_j = |a_j|,  */
+/* and G^+ = sum over sigma_j > rtol * max sigma of v_j a_j^T / sigma_j^2     */
+/* (j increasing).  All sums run in increasing index order.  *rank_out gets   */
+/* the number of singular values kept.                                        */
+/* ------------------------------------------------------------------------ */
+static void orc_pair(int t, int k, int rp, int *p, int *q) {
+    int a = (k == 0) ? 0 : ((k - 1 + t) % (rp - 1)) + 1;
+    int kk = rp - 1 - k;
+    int b = ((kk - 1 + t) % (rp - 1)) + 1;
+    *p = a < b ? a : b;
+    *q = a < b ? b : a;
+}
+
+int orc_pinv_jacobi(const double *G, int r, double rtol, double *X, int *rank_out) {
+    if (!G || !X || r < 1) return ORC_EINVAL;
+    double *A = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+    double *V = (double *)calloc((size_t)r * (size_t)r, sizeof(double));
+    double *sg = (double *)malloc(sizeof(double) * (size_t)r);
+    memcpy(A, G, sizeof(double) * (size_t)r * (size_t)r);
+    for (int i = 0; i < r; i++) V[i * r + i] = 1.0;
+    const int rp = r + (r & 1);
+    for (int sweep = 0; sweep < 60 && r > 1; sweep++) {
+        int rotated = 0;
+        for (int t = 0; t < rp - 1; t++) {
+            for (int k = 0; k < rp / 2; k++) {
+                int pc, qc;
+                orc_pair(t, k, rp, &pc, &qc);
+                if (qc >= r) continue;  /* paired with the padding position */
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = 0; i < r; i++) {
+                    al += A[i * r + pc] * A[i * r + pc];
+                    be += A[i * r + qc] * A[i * r + qc];
+                    ga += A[i * r + pc] * A[i * r + qc];
+                }
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                double ze = (be - al) / (2.0 * ga);
+                double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                for (int i = 0; i < r; i++) {
+                    double x = A[i * r + pc], y = A[i * r + qc];
+                    A[i * r + pc] = c * x - sn * y;
+                    A[i * r + qc] = sn * x + c * y;
+                    x = V[i * r + pc];
+                    y = V[i * r + qc];
+                    V[i * r + pc] = c * x - sn * y;
+                    V[i * r + qc] = sn * x + c * y;
+                }
+                rotated = 1;
+            }
+        }
+        if (!rotated) break;
+    }
+    double smax = 0.0;
+    for (int j = 0; j < r; j++) {
+        double s2 = 0.0;
+        for (int i = 0; i < r; i++) s2 += A[i * r + j] * A[i * r + j];
+        sg[j] = sqrt(s2);
+        if (sg[j] > smax) smax = sg[j];
+    }
+    int rank = 0;
+    for (int j = 0; j < r; j++) rank += (sg[j] > rtol * smax) ? 1 : 0;
+    for (int a = 0; a < r; a++)
+        for (int b = 0; b < r; b++) {
+            double acc = 0.0;
+            for (int j = 0; j < r; j++)
+                if (sg[j] > rtol * smax) acc += V[a * r + j] * A[b * r + j] / (sg[j] * sg[j]);
+            X[a * r + b] = acc;
+        }
+    if (rank_out) *rank_out = rank;
+    free(A); free(V); free(sg);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Nucleus (Algorithm algcnnncl with k = l = r): the LU inverse of G with    */
+/* `refine_steps` refinement steps; when a pivot is exactly zero or the      */
+/* ratio of the largest to the smallest pivot magnitude exceeds 1e14 (a      */
+/* cheap condition estimate from the same factors), the truncated            */
+/* pseudo-inverse with relative truncation 1e-14 instead.  *rank_out: r for  */
+/* the inverse, the kept rank for the pseudo-inverse; *logdet: log |det G|   */
+/* (-inf when a pivot is zero).                                              */
+/* ------------------------------------------------------------------------ */
+int orc_nucleus(const double *G, int r, int refine_steps, double *U, double *logdet, int *rank_out) {
+    if (!G || !U || r < 1) return ORC_EINVAL;
+    double ld = 0.0;
+    int st = orc_inverse(G, r, U, refine_steps, &ld);
+    int fallback = (st == ORC_ESINGULAR);
+    if (st == ORC_OK) {
+        /* pivot magnitudes of the same elimination */
+        double *LU = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+        int *p = (int *)malloc(sizeof(int) * (size_t)r);
+        memcpy(LU, G, sizeof(double) * (size_t)r * (size_t)r);
+        for (int i = 0; i < r; i++) p[i] = i;
+        double pmax = 0.0, pmin = INFINITY;
+        for (int k = 0; k < r; k++) {
+            int best = k;
+            double bv = fabs(LU[p[k] * r + k]);
+            for (int i = k + 1; i < r; i++) {
+                double a = fabs(LU[p[i] * r + k]);
+                if (a > bv || (a == bv && p[i] < p[best])) { bv = a; best = i; }
+            }
+            int t = p[k]; p[k] = p[best]; p[best] = t;
+            double pk = LU[p[k] * r + k];
+            if (fabs(pk) > pmax) pmax = fabs(pk);
+            if (fabs(pk) < pmin) pmin = fabs(pk);
+            for (int i = k + 1; i < r; i++) {
+                double l = LU[p[i] * r + k] / pk;
+                LU[p[i] * r + k] = l;
+                for (int j = k + 1; j < r; j++) LU[p[i] * r + j] -= l * LU[p[k] * r + j];
+            }
+        }
+        free(LU); free(p);
+        fallback = pmax > 1e14 * pmin;
+    } else if (st != ORC_ESINGULAR) {
+        return st;
+    }
+    if (fallback) {
+        st = orc_pinv_jacobi(G, r, 1e-14, U, rank_out);
+        if (logdet) *logdet = (st == ORC_OK && *rank_out == r) ? ld : -INFINITY;
+        return st;
+    }
+    if (rank_out) *rank_out = r;
+    if (logdet) *logdet = ld;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* C-A CUR driver (Section 1.3 and Fig. 4: alternating vertical m x r and    */
 /* horizontal r x n sketches; Section 13, Tests 2: random initial set, a few */
 /* C-A loops, nucleus U = W_{I,J}^{-1}, W' = C U R as in eq. (eqtsts1)).     */
@@ -464,6 +597,7 @@ typedef struct {
 
 typedef struct {
     int32_t sweeps_run, swaps_total, converged, rank_found;
+    int32_t nucleus_rank, pad;   /* rank kept by the nucleus (r unless the pseudo-inverse truncated) */
     double min_margin, det_log_abs;
 } orc_info;
 
@@ -512,7 +646,7 @@ int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
     if (opts_in) o = *opts_in; else orc_default_opts(&o);
     if (o.max_swaps < 0) o.max_swaps = 16 * r;
     if (o.ah_samples <= 0) o.ah_samples = 2 * r;
-    orc_info info = {0, 0, 1, 0, 1.0, 0.0};
+    orc_info info = {0, 0, 1, 0, 0, 0, 1.0, 0.0};
     info.rank_found = r;
     if (!A || !I_out || !J_out || !U_out || r < 1 || sweeps < 1 || m < 1 || n < 1 || lda < n ||
         (int64_t)r > (m < n ? m : n) || dtype < 0 || dtype > 2 || !(o.delta >= 0.0) ||
@@ -587,9 +721,10 @@ int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
         double *G = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
         for (int a = 0; a < r; a++)
             for (int b = 0; b < r; b++) G[a * r + b] = orc_get(A, dtype, lda, I[a], J[b]);
-        st = orc_inverse(G, r, U_out, o.refine_steps, &info.det_log_abs);
+        int nr = r;
+        st = orc_nucleus(G, r, o.refine_steps, U_out, &info.det_log_abs, &nr);
+        info.nucleus_rank = nr;
         free(G);
-        if (st == ORC_ESINGULAR) info.rank_found = r - 1;
     }
     memcpy(I_out, I, sizeof(int64_t) * (size_t)r);
     memcpy(J_out, J, sizeof(int64_t) * (size_t)r);

@@ -41,7 +41,7 @@ class lra_opts(ct.Structure):
 class lra_info(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("sweeps_run", ct.c_int32), ("swaps_total", ct.c_int32),
                 ("converged", ct.c_int32), ("rank_found", ct.c_int32), ("team_size", ct.c_int32),
-                ("det_log_abs", ct.c_double)]
+                ("nucleus_rank", ct.c_int32), ("reserved", ct.c_int32), ("det_log_abs", ct.c_double)]
 
 
 class lra_block(ct.Structure):

@@ -241,7 +241,7 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     DevInfo dinfo;
     if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
     const int max_team = std::min(dinfo.cus, kMaxTeam);
-    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 1024;
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
 
     // Team size: the smallest number of workgroups whose panel slices fit in
     // LDS, but at least one workgroup per 160 items (more workgroups shorten
@@ -326,7 +326,7 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
     DevInfo dinfo;
     if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
-    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 1024;
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
     const LdsPlan plan = plan_lds(maxdim, maxdim, r, LRA_PRE_NONE, 0, 1, lds_budget);
     if (!plan.fits) return LRA_EUNSUPPORTED;
     cfg.panel_bytes = (int32_t)plan.panel_bytes;

@@ -154,6 +154,7 @@ struct Smem {
     int32_t win_flag;
     int32_t status;
     int32_t rank_found;
+    int32_t nucleus_rank;
     int32_t job;
     int32_t xfail;   // a team poll timed out
     double vtv;
@@ -851,12 +852,31 @@ __device__ __forceinline__ void nucleus(Smem &sm, double *ws, const T *A, int64_
     __shared__ double ld;
     inverse_lds(LU, X, p, r, kBlock, &sing, &ld);
     LRA_TR(23, 0);
-    if (sing) {
-        if (tid == 0) {
-            sm.status = LRA_ESINGULAR;
-            sm.rank_found = r - 1;
+    // an exactly zero pivot, or pivot magnitudes spread by more than 1e14 (a
+    // condition estimate from the same factors): truncated pseudo-inverse
+    __shared__ int fallback;
+    if (tid == 0) {
+        int fb = sing;
+        if (!sing) {
+            double pmax = 0.0, pmin = INFINITY;
+            for (int k = 0; k < r; k++) {
+                const double a = fabs(LU[p[k] * r + k]);
+                pmax = a > pmax ? a : pmax;
+                pmin = a < pmin ? a : pmin;
+            }
+            fb = pmax > 1e14 * pmin;
         }
-        __syncthreads();
+        fallback = fb;
+    }
+    __syncthreads();
+    if (fallback) {
+        __shared__ int rank;
+        pinv_jacobi_lds(G, LU, X2, X, r, 1e-14, kBlock, &rank);
+        if (tid == 0) {
+            sm.nucleus_rank = rank;
+            sm.logdet = (rank == r && !sing) ? ld : -INFINITY;
+        }
+        for (int e = tid; e < r * r; e += kBlock) U_out[e] = X[e];
         return;
     }
     if (tid == 0) sm.logdet = ld;
@@ -896,6 +916,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     if (tid == 0) {
         sm.status = LRA_OK;
         sm.rank_found = r;
+        sm.nucleus_rank = r;
         sm.xfail = 0;
 #ifdef LRA_TRACE
         sm.t_select = 0;
@@ -992,6 +1013,8 @@ finish:
         inf.converged = (st == LRA_OK) ? converged : 0;
         inf.rank_found = sm.rank_found;
         inf.team_size = tm.size;
+        inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
+        inf.reserved = 0;
         inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
         *info = inf;
     }
@@ -1133,12 +1156,28 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
     return blocks;
 }
 
-size_t static_lds_bytes() { return sizeof(Smem) + sizeof(int) * kRMax; }
+// Static LDS of the C-A kernels as compiled (the Smem block plus the
+// function-level shared variables of the nucleus and inverse), the largest
+// over the element types; queried once.
+size_t static_lds_bytes() {
+    static size_t bytes = 0;
+    if (bytes == 0) {
+        const void *fns[6] = {(const void *)ca_team_kernel<double>,    (const void *)ca_team_kernel<float>,
+                              (const void *)ca_team_kernel<uint16_t>,  (const void *)ca_batched_kernel<double>,
+                              (const void *)ca_batched_kernel<float>,  (const void *)ca_batched_kernel<uint16_t>};
+        size_t mx = sizeof(Smem) + sizeof(int) * kRMax;
+        for (const void *f : fns) {
+            hipFuncAttributes attr;
+            if (hipFuncGetAttributes(&attr, f) == hipSuccess && attr.sharedSizeBytes > mx) mx = attr.sharedSizeBytes;
+        }
+        bytes = mx;
+    }
+    return bytes;
+}
 
 }  // namespace lra
 
 #ifdef LRA_TRACE
-// Copy the trace of the last traced launches out and reset it (tracing builds only).
 // Copy the per-selection publish / poll-done clocks ([kSelTrace][256] each).
 extern "C" int lra_trace_sel(uint64_t *pub, uint64_t *done) {
     if (hipMemcpyFromSymbol(pub, HIP_SYMBOL(lra::g_sel_pub), sizeof(uint64_t) * lra::kSelTrace * 256) != hipSuccess)
@@ -1148,6 +1187,7 @@ extern "C" int lra_trace_sel(uint64_t *pub, uint64_t *done) {
     return lra::kSelTrace;
 }
 
+// Copy the trace of the last traced launches out and reset it (tracing builds only).
 extern "C" int lra_trace_read(uint64_t *host, int max_events) {
     int n = 0;
     if (hipMemcpyFromSymbol(&n, HIP_SYMBOL(lra::g_trace_n), sizeof(int)) != hipSuccess) return -1;

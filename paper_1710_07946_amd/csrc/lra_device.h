@@ -225,4 +225,98 @@ __device__ __forceinline__ void inverse_lds(double *LU, double *X, int *p, int r
     __syncthreads();
 }
 
+// Truncated pseudo-inverse by one-sided Jacobi SVD, the rule of the
+// oracle's routine: columns of A = G rotated in round-robin pair order
+// (position 0 fixed, the others rotating, a dummy position for odd r), a pair
+// rotated unless |a_p . a_q| <= 1e-15 sqrt(|a_p|^2 |a_q|^2), sweeps until one
+// applies no rotation (at most 60); then X = sum over sigma_j > rtol max sigma
+// of v_j a_j^T / sigma_j^2.  Each pair is handled by 16 lanes (its three dot
+// products summed as a butterfly, so rounding differs from the oracle's
+// sequential sums).  G, A, V, X: r x r in LDS (A and V are work space).
+// Every thread of the block (nthreads >= 512) must call; r <= 64.
+__device__ __forceinline__ void jacobi_pair(int t, int k, int rp, int &p, int &q) {
+    const int a = (k == 0) ? 0 : ((k - 1 + t) % (rp - 1)) + 1;
+    const int kk = rp - 1 - k;
+    const int b = ((kk - 1 + t) % (rp - 1)) + 1;
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+__device__ __forceinline__ double sum16(double v) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ void pinv_jacobi_lds(const double *G, double *A, double *V, double *X, int r, double rtol,
+                                                int nthreads, int *rank_out) {
+    const int tid = threadIdx.x;
+    __shared__ int s_rot;
+    __shared__ double s_sig[64];
+    for (int e = tid; e < r * r; e += nthreads) {
+        A[e] = G[e];
+        V[e] = (e / r == e % r) ? 1.0 : 0.0;
+    }
+    const int rp = r + (r & 1);
+    const int grp = tid / 16, j = tid % 16, ngrp = nthreads / 16;
+    for (int sweep = 0; sweep < 60 && r > 1; sweep++) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int t = 0; t < rp - 1; t++) {
+            for (int k = grp; k < rp / 2; k += ngrp) {
+                int pc, qc;
+                jacobi_pair(t, k, rp, pc, qc);
+                if (qc >= r) continue;  // paired with the padding position
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = j; i < r; i += 16) {
+                    const double x = A[i * r + pc], y = A[i * r + qc];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                al = sum16(al);
+                be = sum16(be);
+                ga = sum16(ga);
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                const double ze = (be - al) / (2.0 * ga);
+                const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                const double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                for (int i = j; i < r; i += 16) {
+                    double x = A[i * r + pc], y = A[i * r + qc];
+                    A[i * r + pc] = c * x - sn * y;
+                    A[i * r + qc] = sn * x + c * y;
+                    x = V[i * r + pc];
+                    y = V[i * r + qc];
+                    V[i * r + pc] = c * x - sn * y;
+                    V[i * r + qc] = sn * x + c * y;
+                }
+                if (j == 0) s_rot = 1;
+            }
+            __syncthreads();
+        }
+        const int rot = *(volatile int *)&s_rot;
+        __syncthreads();
+        if (!rot) break;
+    }
+    for (int c = tid; c < r; c += nthreads) {
+        double s2 = 0.0;
+        for (int i = 0; i < r; i++) s2 += A[i * r + c] * A[i * r + c];
+        s_sig[c] = sqrt(s2);
+    }
+    __syncthreads();
+    double smax = 0.0;
+    int rank = 0;
+    for (int c = 0; c < r; c++) smax = s_sig[c] > smax ? s_sig[c] : smax;
+    for (int c = 0; c < r; c++) rank += s_sig[c] > rtol * smax ? 1 : 0;
+    for (int e = tid; e < r * r; e += nthreads) {
+        const int a = e / r, b = e % r;
+        double acc = 0.0;
+        for (int c = 0; c < r; c++)
+            if (s_sig[c] > rtol * smax) acc += V[a * r + c] * A[b * r + c] / (s_sig[c] * s_sig[c]);
+        X[e] = acc;
+    }
+    if (tid == 0) *rank_out = rank;
+    __syncthreads();
+}
+
 }  // namespace lra

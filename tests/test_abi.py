@@ -40,7 +40,7 @@ def test_strerror(lib):
 
 
 def test_struct_layouts():
-    assert ct.sizeof(lra.lra_info) == 32
+    assert ct.sizeof(lra.lra_info) == 40
     assert ct.sizeof(lra.lra_block) == 32
     assert ct.sizeof(lra.lra_opts) == 40
 

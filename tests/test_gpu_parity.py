@@ -165,6 +165,23 @@ def test_rank_deficient_large(lra):
     assert o.status == 2 and g[3]["status"] == 2 and g[3]["rank_found"] == o.rank_found
 
 
+@pytest.mark.parametrize("m,n,r,team", [(120, 100, 6, 1), (2000, 1500, 20, 0)])
+def test_truncated_pseudo_inverse_nucleus(lra, m, n, r, team):
+    """Exactly rank r - 1 plus rounding-level noise: the panels keep full rank,
+    the final generator is numerically singular and both sides fall back to the
+    truncated pseudo-inverse (parity unpinned beyond agreement with the oracle:
+    the GPU's Jacobi sums run in another order)."""
+    g = np.random.default_rng(m + r)
+    A = g.standard_normal((m, r - 1)) @ g.standard_normal((r - 1, n)) + 1e-15 * g.standard_normal((m, n))
+    o = oracle.ca_cur(A, r, 2, 11)
+    gI, gJ, gU, info = gpu_cur(lra, A, r, 2, 11, team_size=team)
+    assert o.status == 0 and info["status"] == 0
+    assert o.nucleus_rank == r - 1 and info["nucleus_rank"] == o.nucleus_rank
+    assert gI.tolist() == o.I.tolist() and gJ.tolist() == o.J.tolist()
+    assert np.max(np.abs(gU - o.U)) <= 1e-8 * np.max(np.abs(o.U))
+    assert info["det_log_abs"] == -np.inf or info["nucleus_rank"] == r
+
+
 def test_non_finite_entry(lra):
     A = workloads.orthogonal_lowrank(120, 100, 4, noise=1e-3)
     A[17, 5] = np.nan
