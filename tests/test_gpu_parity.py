@@ -262,3 +262,25 @@ def test_batched_matches_oracle_and_plain_calls(lra):
             g = gpu_cur(lra, np.ascontiguousarray(blk), r, 3, 1000 + b)
             assert g[0].tolist() == I[b].tolist() and g[1].tolist() == J[b].tolist()
             assert np.array_equal(g[2], U[b])
+
+
+def test_batched_4096_fmm_blocks_sampled(lra):
+    """The benchmark's launch: 4096 FMM blocks (64..1024 rows and columns,
+    device-evaluated), r = 16, 3 sweeps, one persistent launch; 24 blocks
+    spread over the size range checked against the oracle on the same bytes."""
+    count, r = 4096, 16
+    base, desc = workloads.fmm_batch_device(count, "cuda")
+    out = lra.lra_cur_batched(base, desc, r, 3, 1000)
+    torch.cuda.synchronize()
+    infos = out.info()
+    assert all(i["status"] == 0 for i in infos)
+    I, J, U = out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy()
+    sizes = desc[:, 1] * desc[:, 2]
+    order = np.argsort(sizes)
+    picks = sorted(set(order[np.linspace(0, count - 1, 24).astype(int)].tolist()))
+    flat = base.cpu().numpy()
+    for b in picks:
+        o0, m, n, _ = (int(v) for v in desc[b])
+        blk = flat[o0:o0 + m * n].reshape(m, n)
+        o = oracle.ca_cur(blk, r, 3, 1000 + b)
+        assert_parity(blk, (I[b], J[b], U[b], infos[b]), o, 1e-4)

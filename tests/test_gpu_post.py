@@ -298,3 +298,38 @@ def test_autograd_function(lra):
         for t, y in ((Ct, oC), (Rt, oR), (Gt, oG)):
             x = t.grad[b].cpu().numpy()
             assert np.max(np.abs(x - wn[b] * y)) <= 1e-9 * np.max(np.abs(wn[b] * y))
+
+
+def test_adjoint_256_blocks_sampled(lra):
+    """The benchmark's launch: 256 blocks of 2048 x 2048 rank-32 factor
+    products + N(0, 1e-5^2) (device generator), index sets from a forward C-A,
+    1% of the entries; one adjoint call over all blocks, 4 blocks spread over
+    the batch checked against the oracle."""
+    count, m, n, r, nnz = 256, 2048, 2048, 32, 41943
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4242)
+    Cs, Rs, Gs, rows, cols, vals = [], [], [], [], [], []
+    for b in range(count):
+        A = workloads.factor_gaussian_device(m, n, r, 1e-5, 6000 + b, "cuda")
+        res = lra.lra_cur(A, r, 3, 7000 + b)
+        A64 = A.to(torch.float64)
+        Cs.append(A64[:, res.J])
+        Rs.append(A64[res.I])
+        Gs.append(A64[res.I][:, res.J])
+        flat = torch.sort(torch.randperm(m * n, generator=g, device="cuda")[:nnz]).values
+        rows.append((flat // n).to(torch.int32))
+        cols.append((flat % n).to(torch.int32))
+        vals.append(A64.reshape(-1)[flat])
+    C, R, G = (torch.stack(x).contiguous() for x in (Cs, Rs, Gs))
+    om_row, om_col, a_om = (torch.stack(x).contiguous() for x in (rows, cols, vals))
+    order = lra.omega_column_order(om_row, om_col)
+    loss, dC, dR, dG, st = lra.lra_cur_adjoint(C, R, G, om_row, om_col, order, a_om)
+    torch.cuda.synchronize()
+    assert (st == 0).all()
+    for b in (0, 85, 170, 255):
+        lo, oC, oR, oG = oracle.cur_adjoint(C[b].cpu().numpy(), R[b].cpu().numpy(), G[b].cpu().numpy(),
+                                            om_row[b].cpu().numpy(), om_col[b].cpu().numpy(), a_om[b].cpu().numpy())
+        assert abs(loss[b].item() - lo) <= 1e-10 * abs(lo)
+        for x, y in ((dC[b], oC), (dR[b], oR), (dG[b], oG)):
+            x = x.cpu().numpy()
+            assert np.max(np.abs(x - y)) <= 1e-9 * np.max(np.abs(y))
