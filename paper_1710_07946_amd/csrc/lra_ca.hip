@@ -148,6 +148,8 @@ struct Smem {
     uint8_t sgn[kLMax];   // sketch: combined signs of a sampled column's 2^d <= 8 terms
     double L11[kRMax * (kRMax - 1) / 2];
     double wrow[kLMax];
+    double wprev[2][kRMax];  // LU: the pivot rows of the last two steps
+    int64_t loc_item;        // the workgroup's best item of the last selection (-1: none)
     Best red[kNWave];
     int32_t red_flag[kNWave];
     Best win;
@@ -251,22 +253,39 @@ __device__ __forceinline__ Geo geo(const Team &tm, int64_t items) {
 // and at most r) small enough that every item of the slice gets its own lane
 // group when possible.  The lanes of a group are consecutive lanes of one
 // wavefront; lane s of a group owns slots s, s + sub, s + 2 sub, ...
-__device__ __forceinline__ int lanes_per_item(int cnt, int r) {
+__device__ __forceinline__ int lanes_per_item(int cnt, int r, int lanes = kBlock) {
     int sub = 1;
-    while (sub < 16 && sub * 2 <= r && cnt * sub * 2 <= kBlock) sub *= 2;
+    while (sub < 16 && sub * 2 <= r && cnt * sub * 2 <= lanes) sub *= 2;
     return sub;
 }
+
+// Default hooks of team_select: the published row is the candidate's panel
+// column as stored, and there is no work to overlap with the exchange.
+struct PanelRow {
+    const double *panel;
+    int st;
+    int64_t base;
+    __device__ __forceinline__ double operator()(int t, int64_t item) const {
+        return panel[t * st + (int)(item - base)];
+    }
+};
+struct NoOverlap {
+    __device__ __forceinline__ void operator()(int64_t) const {}
+};
 
 enum SelMode { kSelPlain = 0, kSelHouseholder = 1 };
 
 // Team-wide selection.  Every thread passes its best candidate; the winner
-// of the whole team lands in sm.win and its row (`width` entries of its
-// panel column) in sm.wrow.  Wave 0 alone runs the exchange, so the call
-// costs two workgroup barriers.  With kSelHouseholder, lane 0 also turns
-// sm.wrow into the Householder vector of step `hstep` (oracle order:
-// alpha = -sign(x0) ||x||, v0 = x0 - alpha, vtv = sum of v_c^2 in index order).
-__device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *panel, const Geo &g, int width,
-                            int mode = kSelPlain, int hstep = 0) {
+// of the whole team lands in sm.win and its row (`width` entries, rowf(t,
+// item) for t < width) in sm.wrow; the workgroup's own best item lands in
+// sm.loc_item.  Wave 0 alone runs the exchange, so the call costs two
+// workgroup barriers; between them waves 1.. run overlap(local best item).
+// With kSelHouseholder, lane 0 also turns sm.wrow into the Householder vector
+// of step `hstep` (oracle order: alpha = -sign(x0) ||x||, v0 = x0 - alpha,
+// vtv = sum of v_c^2 in index order).
+template <class RowFn, class Overlap>
+__device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const Geo &g, int width, int mode,
+                                            int hstep, const RowFn &rowf, const Overlap &overlap) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #ifdef LRA_TRACE
     const uint64_t t_in = wall_clock64();
@@ -282,18 +301,20 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
     const uint64_t t_a = wall_clock64();
     uint64_t t_b = t_a, t_c = t_a;
 #endif
+    // every wavefront forms the workgroup's best candidate (a uniform value)
+    Best loc = lane < kNWave ? sm.red[lane] : none();
+    int f = lane < kNWave ? sm.red_flag[lane] : 0;
+    loc = wave_reduce(loc);
+    f = wave_or(f);
+    if (w != 0) overlap(loc.v >= 0.0 ? loc.item : (int64_t)-1);
     if (w == 0) {
-        Best loc = lane < kNWave ? sm.red[lane] : none();
-        int f = lane < kNWave ? sm.red_flag[lane] : 0;
-        loc = wave_reduce(loc);
-        f = wave_or(f);
+        if (lane == 0) sm.loc_item = loc.v >= 0.0 ? loc.item : (int64_t)-1;
         Best win;
         int wf;
         if (tm.size == 1) {
             win = loc;
             wf = f;
-            for (int t = lane; t < width; t += kWave)
-                sm.wrow[t] = loc.v >= 0 ? panel[t * g.st + (int)(loc.item - g.base)] : 0.0;
+            for (int t = lane; t < width; t += kWave) sm.wrow[t] = loc.v >= 0 ? rowf(t, loc.item) : 0.0;
         } else {
             const uint32_t tag = tm.epoch + 1u;
             const int par = tm.epoch & 1;
@@ -304,7 +325,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
             uint64_t *mine = hdrs + (size_t)tm.rank * kHdrWords;
             uint64_t *myrow = rows + (size_t)tm.rank * kRowWords;
             for (int t = lane; t < width; t += kWave) {
-                const double x = loc.v >= 0 ? panel[t * g.st + (int)(loc.item - g.base)] : 0.0;
+                const double x = loc.v >= 0 ? rowf(t, loc.item) : 0.0;
                 const uint64_t u = (uint64_t)__double_as_longlong(x);
                 xput(myrow + 2 * t, tag, (uint32_t)u);
                 xput(myrow + 2 * t + 1, tag, (uint32_t)(u >> 32));
@@ -434,6 +455,11 @@ __device__ __forceinline__ void fail_status(Smem &sm, int st, int rank) {
     __syncthreads();
 }
 
+__device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *panel, const Geo &g,
+                                            int width, int mode = kSelPlain, int hstep = 0) {
+    team_select(tm, sm, b, flag, g, width, mode, hstep, PanelRow{panel, g.st, g.base}, NoOverlap{});
+}
+
 // ---------------------------------------------------------------- maxvol
 // Dominant r x r submatrix of the tall panel held in `panel` (slot-major,
 // stride g.st): pivoted LU start (Algorithm alggos, stages 1-2), then the
@@ -454,8 +480,16 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
     const int s = tid % sub;
     const int grp = tid / sub, ngrp = kBlock / sub;
     const int jlast = (s < r) ? s + ((r - 1 - s) / sub) * sub : -1;  // last owned slot
-    // ---- pivoted LU: r steps; step k eliminates with the pivot row of step
-    // k-1 (held in sm.wrow) before scanning column k
+    // ---- pivoted LU with look-ahead: before selection k only column k takes
+    // the elimination with pivot row k-1 (sm.wrow); the other columns take it
+    // inside selection k, on waves 1.. while wave 0 waits for the team, except
+    // for the workgroup's own best item, whose row wave 0 publishes with the
+    // elimination applied on the fly and which is brought up to date after the
+    // selection if another item won.  Every entry still receives the
+    // eliminations in order with the oracle's arithmetic.
+    const int dl = tid - kWave, nd = kBlock - kWave;  // overlap lanes (waves 1..)
+    const int subd = lanes_per_item(g.cnt, r, nd);
+    const int sd = dl % subd, grpd = dl / subd, ngrpd = nd / subd;
     double pk = 1.0;
     for (int k = 0; k < r; k++) {
 #ifdef LRA_TRACE
@@ -466,28 +500,49 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             if (flags[li]) continue;
             if (k > 0) {
                 const double l = panel[(k - 1) * st + li] / pk;
-                const int jf = (k <= s) ? s : s + ((k - s + sub - 1) / sub) * sub;  // first owned slot >= k
-                for (int j0 = jf; j0 <= jlast; j0 += kChunk * sub) {
-                    double x[kChunk], w[kChunk];
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) {
-                        const int j = min(j0 + u * sub, jlast);  // past the end: repeat the last owned slot
-                        x[u] = panel[j * st + li];
-                        w[u] = sm.wrow[j];
-                    }
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) panel[min(j0 + u * sub, jlast) * st + li] = x[u] - l * w[u];
+                if (k % sub == s) {
+                    const double x = panel[k * st + li] - l * sm.wrow[k];
+                    panel[k * st + li] = x;
+                    consider(b, fabs(x), g.base + li, 0);
                 }
                 if ((k - 1) % sub == s) panel[(k - 1) * st + li] = l;
+            } else if (k % sub == s) {
+                consider(b, fabs(panel[k * st + li]), g.base + li, 0);
             }
-            if (k % sub == s) consider(b, fabs(panel[k * st + li]), g.base + li, 0);
         }
         if (k > 0 && tid < k - 1) sm.L11[(k - 1) * (k - 2) / 2 + tid] = sm.wrow[tid];
 #ifdef LRA_TRACE
         const uint64_t q1 = wall_clock64();
         if (tid == 0) sm.t_loop[0] += q1 - q0;
 #endif
-        team_select(tm, sm, b, k == 0 ? bad : 0, panel, g, r);
+        const double *wp = sm.wprev[(k + 1) & 1];  // pivot row k-1 (k >= 1)
+        // the row a workgroup publishes: columns past k still lack elimination k-1
+        auto rowf = [&](int t, int64_t item) -> double {
+            const int li = (int)(item - g.base);
+            double x = panel[t * st + li];
+            if (k > 0 && t > k) x -= panel[(k - 1) * st + li] * wp[t];
+            return x;
+        };
+        // elimination k-1 on columns k+1.. of every other candidate item
+        auto overlap = [&](int64_t lbest) {
+            if (k == 0 || k + 1 >= r) return;
+            const int jf = (k + 1 <= sd) ? sd : sd + ((k + 1 - sd + subd - 1) / subd) * subd;
+            for (int li = grpd; li < g.cnt; li += ngrpd) {
+                if (flags[li] || g.base + li == lbest) continue;
+                const double l = panel[(k - 1) * st + li];
+                for (int j0 = jf; j0 < r; j0 += kChunk * subd) {
+                    double x[kChunk];
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) x[u] = panel[min(j0 + u * subd, r - 1) * st + li];
+#pragma unroll
+                    for (int u = 0; u < kChunk; u++) {
+                        const int j = j0 + u * subd;
+                        if (j < r) panel[j * st + li] = x[u] - l * wp[j];
+                    }
+                }
+            }
+        };
+        team_select(tm, sm, b, k == 0 ? bad : 0, g, r, kSelPlain, 0, rowf, overlap);
 #ifdef LRA_TRACE
         const uint64_t q2 = wall_clock64();
 #endif
@@ -499,7 +554,17 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             const int lw = (int)(wit - g.base);
             if (lw % ngrp == grp && s == 0) flags[lw] = (uint8_t)(k + 1);
         }
+        // the workgroup's best item, if it did not win, takes elimination k-1
+        // on its columns past k (one thread per column), before the next scan
+        const int64_t lb = sm.loc_item;
+        if (k > 0 && lb != wit && lb >= g.base && lb < g.base + g.cnt && tid < r - 1 - k) {
+            const int li = (int)(lb - g.base);
+            const int j = k + 1 + tid;
+            panel[j * st + li] -= panel[(k - 1) * st + li] * wp[j];
+        }
+        if (tid < r) sm.wprev[k & 1][tid] = sm.wrow[tid];
         pk = sm.wrow[k];
+        __syncthreads();
 #ifdef LRA_TRACE
         if (tid == 0) sm.t_loop[1] += wall_clock64() - q2;
 #endif
