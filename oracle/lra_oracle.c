@@ -198,14 +198,15 @@ int orc_maxvol(const double *P, int64_t items, int r, double delta, int32_t max_
     for (int k = 0; k < r; k++)
         for (int j = 0; j < k; j++) L11[k * r + j] = B[slots[k] * r + j];
     for (int k = 0; k < r; k++) inb[slots[k]] = 1;
-    /* B_i = l_i L11^{-1}: solve x L11 = l_i from the last entry backwards. */
+    /* B_i = l_i L11^{-1}: solve x L11 = l_i by column-oriented back        */
+    /* substitution: for k = r-1 down to 1, x_k is final and is eliminated   */
+    /* from every x_j with j < k.                                             */
     for (int64_t i = 0; i < items; i++) {
         if (inb[i]) continue;
         double *x = B + i * r;
-        for (int j = r - 1; j >= 0; j--) {
-            double s = x[j];
-            for (int k = j + 1; k < r; k++) s -= x[k] * L11[k * r + j];
-            x[j] = s;
+        for (int k = r - 1; k >= 1; k--) {
+            const double xk = x[k];
+            for (int j = 0; j < k; j++) x[j] -= xk * L11[k * r + j];
         }
     }
     for (int k = 0; k < r; k++) {

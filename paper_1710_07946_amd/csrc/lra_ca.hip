@@ -161,12 +161,13 @@ struct Smem {
     int32_t xfail;   // a team poll timed out
     double vtv;
     double alpha;
+    double pivot;    // swap selection: the winner's entry B[i*][j*]
     double logdet;
 #ifdef LRA_TRACE
     uint64_t t_select;    // total time inside team selections
     uint64_t t_part[4];   // block reduce, header polls, row fetch, final barrier
     uint64_t n_select;
-    uint64_t t_loop[4];   // LU item loop, LU tail, swap item loop, swap tail
+    uint64_t t_loop[5];   // LU item loop, LU tail, swap item loop, swap tail, B solve
 #endif
 };
 
@@ -273,7 +274,7 @@ struct NoOverlap {
     __device__ __forceinline__ void operator()(int64_t) const {}
 };
 
-enum SelMode { kSelPlain = 0, kSelHouseholder = 1 };
+enum SelMode { kSelPlain = 0, kSelHouseholder = 1, kSelSwap = 2 };
 
 // Team-wide selection.  Every thread passes its best candidate; the winner
 // of the whole team lands in sm.win and its row (`width` entries, rowf(t,
@@ -282,7 +283,9 @@ enum SelMode { kSelPlain = 0, kSelHouseholder = 1 };
 // workgroup barriers; between them waves 1.. run overlap(local best item).
 // With kSelHouseholder, lane 0 also turns sm.wrow into the Householder vector
 // of step `hstep` (oracle order: alpha = -sign(x0) ||x||, v0 = x0 - alpha,
-// vtv = sum of v_c^2 in index order).
+// vtv = sum of v_c^2 in index order).  With kSelSwap it keeps the winner's
+// entry at its slot in sm.pivot and subtracts 1 there in sm.wrow, so that
+// sm.wrow holds B[i*,:] - e_j*^T, the vector of the rank-one swap update.
 template <class RowFn, class Overlap>
 __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const Geo &g, int width, int mode,
                                             int hstep, const RowFn &rowf, const Overlap &overlap) {
@@ -411,6 +414,11 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                 sm.vtv = vtv;
                 sm.alpha = alpha;
             }
+            if (mode == kSelSwap && win.v >= 0.0 && win.slot >= 0 && win.slot < width) {
+                const double x = sm.wrow[win.slot];
+                sm.pivot = x;
+                sm.wrow[win.slot] = x - 1.0;
+            }
         }
     }
 #ifdef LRA_TRACE
@@ -429,6 +437,64 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
         sm.n_select += 1;
     }
 #endif
+}
+
+// One step of the swap scan over N owned slots of an item, in ascending slot
+// order: x <- x - f w (w = B[i*,:] - e_j*^T, skipped when f = 0), then the
+// running largest magnitude, the lowest slot among equals.  `o` is the panel
+// offset of the item's current slot j (stride pstep = sub * st per slot).
+template <int N>
+__device__ __forceinline__ void swap_chunk(double *panel, const double *wrow, int &o, int pstep, int &j, int sub,
+                                           double f, double &vb, int &jb) {
+    double x[N];
+#pragma unroll
+    for (int u = 0; u < N; u++) x[u] = panel[o + u * pstep];
+    if (f != 0.0) {
+        double w[N];  // every load before the first store: they are not reordered
+#pragma unroll
+        for (int u = 0; u < N; u++) w[u] = wrow[j + u * sub];
+#pragma unroll
+        for (int u = 0; u < N; u++) {
+            x[u] -= f * w[u];
+            panel[o + u * pstep] = x[u];
+        }
+    }
+    int kb = -1;
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        const bool up = fabs(x[u]) > vb;
+        kb = up ? u : kb;
+        vb = fmax(vb, fabs(x[u]));  // finite entries: the same value as up ? |x| : vb
+    }
+    if (kb >= 0) jb = j + kb * sub;
+    o += N * pstep;
+    j += N * sub;
+}
+
+// x <- x - f w on N slots of an item (panel offset o, stride pstep; w
+// indexed by slot j, stride sub); all loads are issued before the stores.
+template <int N>
+__device__ __forceinline__ void axpy_chunk(double *panel, const double *w, int &o, int pstep, int &j, int sub,
+                                           double f) {
+    double x[N], y[N];
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        x[u] = panel[o + u * pstep];
+        y[u] = w[j + u * sub];
+    }
+#pragma unroll
+    for (int u = 0; u < N; u++) panel[o + u * pstep] = x[u] - f * y[u];
+    o += N * pstep;
+    j += N * sub;
+}
+
+// The same on n slots starting at slot j: full chunks, then 4, 2 and 1.
+__device__ __forceinline__ void axpy_slots(double *panel, const double *w, int o, int pstep, int j, int sub, int n,
+                                           double f) {
+    for (; n >= kChunk; n -= kChunk) axpy_chunk<kChunk>(panel, w, o, pstep, j, sub, f);
+    if (n & 4) axpy_chunk<4>(panel, w, o, pstep, j, sub, f);
+    if (n & 2) axpy_chunk<2>(panel, w, o, pstep, j, sub, f);
+    if (n & 1) axpy_chunk<1>(panel, w, o, pstep, j, sub, f);
 }
 
 // Sort r <= 64 distinct indices in LDS ascending: every lane of one wave
@@ -480,13 +546,18 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
     const int s = tid % sub;
     const int grp = tid / sub, ngrp = kBlock / sub;
     const int jlast = (s < r) ? s + ((r - 1 - s) / sub) * sub : -1;  // last owned slot
-    // ---- pivoted LU with look-ahead: before selection k only column k takes
-    // the elimination with pivot row k-1 (sm.wrow); the other columns take it
-    // inside selection k, on waves 1.. while wave 0 waits for the team, except
-    // for the workgroup's own best item, whose row wave 0 publishes with the
-    // elimination applied on the fly and which is brought up to date after the
-    // selection if another item won.  Every entry still receives the
-    // eliminations in order with the oracle's arithmetic.
+    const int nown = (s < r) ? (r - 1 - s) / sub + 1 : 0;               // owned slots
+    const int pstep = sub * st;
+    // ---- pivoted LU.  A team of several workgroups uses look-ahead: before
+    // selection k only column k takes the elimination with pivot row k-1
+    // (sm.wrow); the other columns take it inside selection k, on waves 1..
+    // while wave 0 waits for the team, except for the workgroup's own best
+    // item, whose row wave 0 publishes with the elimination applied on the fly
+    // and which is brought up to date after the selection if another item won.
+    // A single workgroup has no exchange to hide work behind and eliminates
+    // every column before the scan.  Every entry receives the eliminations in
+    // order with the oracle's arithmetic either way.
+    const bool ahead = tm.size > 1;
     const int dl = tid - kWave, nd = kBlock - kWave;  // overlap lanes (waves 1..)
     const int subd = lanes_per_item(g.cnt, r, nd);
     const int sd = dl % subd, grpd = dl / subd, ngrpd = nd / subd;
@@ -500,10 +571,16 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             if (flags[li]) continue;
             if (k > 0) {
                 const double l = panel[(k - 1) * st + li] / pk;
-                if (k % sub == s) {
-                    const double x = panel[k * st + li] - l * sm.wrow[k];
-                    panel[k * st + li] = x;
-                    consider(b, fabs(x), g.base + li, 0);
+                if (ahead) {
+                    if (k % sub == s) {
+                        const double x = panel[k * st + li] - l * sm.wrow[k];
+                        panel[k * st + li] = x;
+                        consider(b, fabs(x), g.base + li, 0);
+                    }
+                } else {
+                    const int jf = (k <= s) ? s : s + ((k - s + sub - 1) / sub) * sub;  // first owned slot >= k
+                    if (jf <= jlast) axpy_slots(panel, sm.wrow, jf * st + li, pstep, jf, sub, (jlast - jf) / sub + 1, l);
+                    if (k % sub == s) consider(b, fabs(panel[k * st + li]), g.base + li, 0);
                 }
                 if ((k - 1) % sub == s) panel[(k - 1) * st + li] = l;
             } else if (k % sub == s) {
@@ -520,26 +597,18 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
         auto rowf = [&](int t, int64_t item) -> double {
             const int li = (int)(item - g.base);
             double x = panel[t * st + li];
-            if (k > 0 && t > k) x -= panel[(k - 1) * st + li] * wp[t];
+            if (ahead && k > 0 && t > k) x -= panel[(k - 1) * st + li] * wp[t];
             return x;
         };
         // elimination k-1 on columns k+1.. of every other candidate item
         auto overlap = [&](int64_t lbest) {
-            if (k == 0 || k + 1 >= r) return;
+            if (!ahead || k == 0 || k + 1 >= r) return;
             const int jf = (k + 1 <= sd) ? sd : sd + ((k + 1 - sd + subd - 1) / subd) * subd;
+            if (jf >= r) return;
+            const int n = (r - 1 - jf) / subd + 1;
             for (int li = grpd; li < g.cnt; li += ngrpd) {
                 if (flags[li] || g.base + li == lbest) continue;
-                const double l = panel[(k - 1) * st + li];
-                for (int j0 = jf; j0 < r; j0 += kChunk * subd) {
-                    double x[kChunk];
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) x[u] = panel[min(j0 + u * subd, r - 1) * st + li];
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) {
-                        const int j = j0 + u * subd;
-                        if (j < r) panel[j * st + li] = x[u] - l * wp[j];
-                    }
-                }
+                axpy_slots(panel, wp, jf * st + li, subd * st, jf, subd, n, panel[(k - 1) * st + li]);
             }
         };
         team_select(tm, sm, b, k == 0 ? bad : 0, g, r, kSelPlain, 0, rowf, overlap);
@@ -557,7 +626,7 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
         // the workgroup's best item, if it did not win, takes elimination k-1
         // on its columns past k (one thread per column), before the next scan
         const int64_t lb = sm.loc_item;
-        if (k > 0 && lb != wit && lb >= g.base && lb < g.base + g.cnt && tid < r - 1 - k) {
+        if (ahead && k > 0 && lb != wit && lb >= g.base && lb < g.base + g.cnt && tid < r - 1 - k) {
             const int li = (int)(lb - g.base);
             const int j = k + 1 + tid;
             panel[j * st + li] -= panel[(k - 1) * st + li] * wp[j];
@@ -569,38 +638,36 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
         if (tid == 0) sm.t_loop[1] += wall_clock64() - q2;
 #endif
     }
+#ifdef LRA_TRACE
+    const uint64_t qs = wall_clock64();
+#endif
     // last multipliers (no trailing columns), last row of L11
     for (int li = grp; li < g.cnt; li += ngrp)
         if (!flags[li] && (r - 1) % sub == s) panel[(r - 1) * st + li] /= pk;
     if (tid < r - 1) sm.L11[(r - 1) * (r - 2) / 2 + tid] = sm.wrow[tid];
     __syncthreads();
-    // ---- B = L21 L11^{-1}: one lane per item solves x L11 = l_i from the
-    // last entry backwards; basis items get unit rows
+    // ---- B = L21 L11^{-1}: the sub lanes of an item solve x L11 = l_i by
+    // column-oriented back substitution (for k = r-1 .. 1, x_k is final and
+    // every x_j, j < k, takes x_j - x_k L11[k][j]); basis items get unit rows.
+    // The lanes of an item sit in one wavefront, whose LDS accesses complete
+    // in program order, so step k reads the x_k its owner finished at step
+    // k+1.
     for (int li = grp; li < g.cnt; li += ngrp) {
         const int fl = flags[li];
         if (fl) {
             for (int j = s; j < r; j += sub) panel[j * st + li] = (j == fl - 1) ? 1.0 : 0.0;
             continue;
         }
-        if (s != 0) continue;
-        for (int j = r - 1; j >= 0; j--) {
-            double sj = panel[j * st + li];
-            for (int k0 = j + 1; k0 < r; k0 += kChunk) {
-                double x[kChunk], c[kChunk];
-#pragma unroll
-                for (int u = 0; u < kChunk; u++) {
-                    const int kk = min(k0 + u, r - 1);
-                    x[u] = panel[kk * st + li];
-                    c[u] = sm.L11[kk * (kk - 1) / 2 + j];
-                }
-                // terms past the end subtract +0.0, which leaves the sum unchanged
-#pragma unroll
-                for (int u = 0; u < kChunk; u++) sj -= (k0 + u < r) ? x[u] * c[u] : 0.0;
-            }
-            panel[j * st + li] = sj;
+        for (int k = r - 1; k >= 1; k--) {
+            __builtin_amdgcn_wave_barrier();
+            const double xk = panel[k * st + li];
+            if (s < k) axpy_slots(panel, sm.L11 + k * (k - 1) / 2, s * st + li, pstep, s, sub, (k - 1 - s) / sub + 1, xk);
         }
     }
     __syncthreads();
+#ifdef LRA_TRACE
+    if (tid == 0) sm.t_loop[4] += wall_clock64() - qs;
+#endif
     // ---- swaps; each update is fused with the next scan
     const double thr = 1.0 + delta;
     int swaps = 0;
@@ -629,42 +696,21 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
                 continue;
             }
             // B[i,:] -= f (B[i*,:] - e_js^T) on the owned slots, and the scan of
-            // the owned slots (largest magnitude, lowest slot among equals)
+            // the owned slots (largest magnitude, lowest slot among equals):
+            // full chunks, then the remainder in chunks of 4, 2 and 1
             double vb = -1.0;
-            int jb = 0;
-            for (int j0 = s; j0 <= jlast; j0 += kChunk * sub) {
-                double x[kChunk], w[kChunk];
-#pragma unroll
-                for (int u = 0; u < kChunk; u++) {
-                    const int j = min(j0 + u * sub, jlast);
-                    x[u] = panel[j * st + li];
-                    w[u] = sm.wrow[j];
-                }
-                if (f != 0.0) {
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) {
-                        const int j = min(j0 + u * sub, jlast);
-                        const double d = (j == js) ? w[u] - 1.0 : w[u];
-                        x[u] -= f * d;
-                        panel[j * st + li] = x[u];
-                    }
-                }
-                // a repeated last slot comes after the real one: strict > keeps it
-#pragma unroll
-                for (int u = 0; u < kChunk; u++) {
-                    const double a = fabs(x[u]);
-                    const bool up = a > vb;
-                    vb = up ? a : vb;
-                    jb = up ? min(j0 + u * sub, jlast) : jb;
-                }
-            }
+            int jb = 0, j = s, k = nown, o = s * st + li;
+            for (; k >= kChunk; k -= kChunk) swap_chunk<kChunk>(panel, sm.wrow, o, pstep, j, sub, f, vb, jb);
+            if (k & 4) swap_chunk<4>(panel, sm.wrow, o, pstep, j, sub, f, vb, jb);
+            if (k & 2) swap_chunk<2>(panel, sm.wrow, o, pstep, j, sub, f, vb, jb);
+            if (k & 1) swap_chunk<1>(panel, sm.wrow, o, pstep, j, sub, f, vb, jb);
             if (jlast >= 0) consider(b, vb, it, jb);
         }
 #ifdef LRA_TRACE
         const uint64_t q1 = wall_clock64();
         if (tid == 0) sm.t_loop[2] += q1 - q0;
 #endif
-        team_select(tm, sm, b, 0, panel, g, r);
+        team_select(tm, sm, b, 0, panel, g, r, kSelSwap);
 #ifdef LRA_TRACE
         const uint64_t q2 = wall_clock64();
 #endif
@@ -676,7 +722,7 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
         }
         js = sm.win.slot;
         wit = sm.win.item;
-        pv = sm.wrow[js];
+        pv = sm.pivot;
         if (tid == 0) sm.slot_item[js] = wit;
         swaps++;
 #ifdef LRA_TRACE
@@ -987,7 +1033,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
         sm.t_select = 0;
         sm.t_part[0] = sm.t_part[1] = sm.t_part[2] = sm.t_part[3] = 0;
         sm.n_select = 0;
-        sm.t_loop[0] = sm.t_loop[1] = sm.t_loop[2] = sm.t_loop[3] = 0;
+        sm.t_loop[0] = sm.t_loop[1] = sm.t_loop[2] = sm.t_loop[3] = sm.t_loop[4] = 0;
 #endif
     }
     LRA_TR(1, 0);
@@ -1057,6 +1103,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     LRA_TR(36, sm.t_loop[1]);
     LRA_TR(37, sm.t_loop[2]);
     LRA_TR(38, sm.t_loop[3]);
+    LRA_TR(39, sm.t_loop[4]);
 #endif
     if (tm.rank == 0) nucleus<T>(sm, dyn, A, lda, r, cfg.refine_steps, U_out);
     LRA_TR(21, 0);
