@@ -30,6 +30,7 @@
 namespace lra {
 
 constexpr int kNWave = kBlock / kWave;
+static_assert(kNWave <= 8, "the workgroup reduction combines at most eight wavefront partials");
 constexpr int kChunk = 8;  // entries staged in registers per LDS round trip
 
 // ---------------------------------------------------------------- tracing
@@ -131,6 +132,15 @@ __device__ __forceinline__ Best wave_reduce(Best b) {
     return r;
 }
 
+// The same over lanes 0..7 only (the other lanes' values are ignored): the
+// two quad swaps and the half-row mirror combine the first eight lanes.
+__device__ __forceinline__ Best reduce8(Best b) {
+    dpp_step<kDppQuadSwap1>(b);
+    dpp_step<kDppQuadSwap2>(b);
+    dpp_step<kDppHalfMirror>(b);
+    return rdl_best(b, 0);
+}
+
 __device__ __forceinline__ int wave_or(int f) {
     f |= dpp32<kDppQuadSwap1>(f);
     f |= dpp32<kDppQuadSwap2>(f);
@@ -197,7 +207,8 @@ __device__ __forceinline__ uint64_t xld(const uint64_t *p) {
 __device__ __forceinline__ uint64_t lo_hi(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
 
 // Read N exchange words that all carry `tag`: the N loads are issued
-// together, and only the words still stale are polled again.  Every wait is
+// together, and only the words still stale are polled again; a null pointer
+// stands for no word (its output is 0).  Every wait is
 // bounded in wall-clock time: past `limit` ticks the workgroup records a
 // failure in *fail, stops polling for the rest of the launch (its reads
 // return 0) and runs to the end, so no wave can wait forever; the LRA then
@@ -207,7 +218,7 @@ __device__ __forceinline__ void xget(const uint64_t *const (&p)[N], uint32_t tag
                                      uint64_t limit) {
     uint64_t v[N];
 #pragma unroll
-    for (int i = 0; i < N; i++) v[i] = xld(p[i]);
+    for (int i = 0; i < N; i++) v[i] = p[i] ? xld(p[i]) : (uint64_t)tag << 32;  // null: no word to wait for
     bool ok = true;
 #pragma unroll
     for (int i = 0; i < N; i++) ok = ok && ((uint32_t)(v[i] >> 32) == tag);
@@ -250,14 +261,46 @@ __device__ __forceinline__ Geo geo(const Team &tm, int64_t items) {
     return g;
 }
 
-// Lanes that share one item in the maxvol loops: a power of two (at most 16
-// and at most r) small enough that every item of the slice gets its own lane
-// group when possible.  The lanes of a group are consecutive lanes of one
-// wavefront; lane s of a group owns slots s, s + sub, s + 2 sub, ...
-__device__ __forceinline__ int lanes_per_item(int cnt, int r, int lanes = kBlock) {
-    int sub = 1;
-    while (sub < 16 && sub * 2 <= r && cnt * sub * 2 <= lanes) sub *= 2;
-    return sub;
+// Lanes that share one item in the maxvol loops.  The `nw` wavefronts from
+// wavefront w0 on hold floor(64 / sub) groups of `sub` consecutive lanes each
+// (the last 64 mod sub lanes of a wavefront stay idle: grp is out of range);
+// lane s of a group owns slots s, s + sub, s + 2 sub, ... of an item, and
+// group grp takes items grp, grp + ngrp, ...  sub (1..16, at most r)
+// minimises the busiest SIMD's share of the work (owned slots per item plus a
+// fixed cost per item), wavefront w running on SIMD w mod 4: each lane evaluates one candidate and the wavefront
+// takes the cheapest (the smallest sub among equals).
+struct LaneMap {
+    int sub, s, grp, ngrp;
+};
+__device__ __forceinline__ LaneMap lane_map(int cnt, int r, int w0, int nw) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int key = INT_MAX;
+    {
+        const int sub = lane + 1;
+        if (sub <= 16 && sub <= r) {
+            const int ipw = kWave / sub;
+            const int passes = (cnt + ipw - 1) / ipw;  // wavefront passes over the items, dealt in turn
+            const int nq = (nw + 3) / 4;               // wavefronts on the busiest SIMD (the one of w0)
+            const int load = nq * (passes / nw) + min(nq, (passes % nw + 3) / 4);
+            key = (load * ((r + sub - 1) / sub + 2)) * 32 + sub;  // + 2: the per-item work of a pass
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) key = min(key, __shfl_xor(key, o));
+    LaneMap m;
+    m.sub = key & 31;
+    const int ipw = kWave / m.sub;
+    m.ngrp = nw * ipw;
+    const int t = (int)threadIdx.x - w0 * kWave;
+    const int w = t / kWave, l = t % kWave;
+    if (t < 0 || w >= nw || l >= ipw * m.sub) {
+        m.s = 0;
+        m.grp = INT_MAX / 2;
+    } else {
+        m.s = l % m.sub;
+        m.grp = w * ipw + l / m.sub;
+    }
+    return m;
 }
 
 // Default hooks of team_select: the published row is the candidate's panel
@@ -307,7 +350,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
     // every wavefront forms the workgroup's best candidate (a uniform value)
     Best loc = lane < kNWave ? sm.red[lane] : none();
     int f = lane < kNWave ? sm.red_flag[lane] : 0;
-    loc = wave_reduce(loc);
+    loc = reduce8(loc);
     f = wave_or(f);
     if (w != 0) overlap(loc.v >= 0.0 ? loc.item : (int64_t)-1);
     if (w == 0) {
@@ -327,12 +370,8 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
             uint64_t *rows = tm.xw + (size_t)2 * tm.size * kHdrWords + (size_t)par * tm.size * kRowWords;
             uint64_t *mine = hdrs + (size_t)tm.rank * kHdrWords;
             uint64_t *myrow = rows + (size_t)tm.rank * kRowWords;
-            for (int t = lane; t < width; t += kWave) {
-                const double x = loc.v >= 0 ? rowf(t, loc.item) : 0.0;
-                const uint64_t u = (uint64_t)__double_as_longlong(x);
-                xput(myrow + 2 * t, tag, (uint32_t)u);
-                xput(myrow + 2 * t + 1, tag, (uint32_t)(u >> 32));
-            }
+            // the header goes out first: the team waits on headers, while a
+            // row is read only after its header has won
             if (lane == 0) {
                 const uint64_t v = (uint64_t)__double_as_longlong(loc.v);
                 const uint64_t it = (uint64_t)loc.item;  // < 2^40, or INT64_MAX for "none"
@@ -345,28 +384,37 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                 if (tm.epoch < kSelTrace && tm.rank < 256) g_sel_pub[tm.epoch * 256 + tm.rank] = wall_clock64();
 #endif
             }
+            for (int t = lane; t < width; t += kWave) {
+                const double x = loc.v >= 0 ? rowf(t, loc.item) : 0.0;
+                const uint64_t u = (uint64_t)__double_as_longlong(x);
+                xput(myrow + 2 * t, tag, (uint32_t)u);
+                xput(myrow + 2 * t + 1, tag, (uint32_t)(u >> 32));
+            }
             // every lane polls up to kMaxTeam / 64 headers, all loads at once
+            // (null: past the end of the team, nothing to read)
             Best c = none();
             int cf = 0;
             {
                 const uint64_t *ps[4 * kHdrWords];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    const int g0 = min(lane + q * kWave, tm.size - 1);  // past the end: repeat the last
+                    const int g0 = lane + q * kWave;
 #pragma unroll
-                    for (int w = 0; w < kHdrWords; w++) ps[q * kHdrWords + w] = hdrs + (size_t)g0 * kHdrWords + w;
+                    for (int w = 0; w < kHdrWords; w++)
+                        ps[q * kHdrWords + w] = g0 < tm.size ? hdrs + (size_t)g0 * kHdrWords + w : nullptr;
                 }
                 uint32_t d[4 * kHdrWords];
                 xget<4 * kHdrWords>(ps, tag, d, &sm.xfail, tm.spin_limit);
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
+                    if (lane + q * kWave >= tm.size) continue;
                     const uint32_t *h = d + q * kHdrWords;
                     const double v = __longlong_as_double((long long)lo_hi(h[0], h[1]));
                     const uint32_t hi = h[3] & 0xffu;
                     const int64_t it = hi == 0xffu ? INT64_MAX : (int64_t)(((uint64_t)hi << 32) | h[2]);
                     int sl = (int)((h[3] >> 8) & 0xffu);
                     if (sl == 0xff) sl = 0x7fffffff;
-                    consider(c, v, it, sl, min(lane + q * kWave, tm.size - 1));
+                    consider(c, v, it, sl, lane + q * kWave);
                     cf |= (int)((h[3] >> 16) & 0xffu);
                 }
             }
@@ -531,8 +579,8 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
 // stride g.st): pivoted LU start (Algorithm alggos, stages 1-2), then the
 // swaps of Algorithm algdomin with the rank-one update of B.  flags[li] is 0
 // for a candidate item and slot+1 for a basis item.  Each item is handled by a
-// group of `sub` consecutive lanes of one wavefront (lane s owns slots s,
-// s + sub, ...); all lanes of a group read an item's flag and shared entries
+// group of `sub` consecutive lanes of one wavefront (lane_map: lane s owns
+// slots s, s + sub, ...); all lanes of a group read an item's flag and shared entries
 // before any lane of the group overwrites them (one instruction stream), and
 // lane 0 of the group writes the flag.  Each elimination step or swap is
 // applied lazily, fused with the scan for the next decision; the arithmetic of
@@ -542,9 +590,8 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
                                        double delta, int max_swaps, int bad, int32_t &swaps_total, int32_t &converged) {
     const int tid = threadIdx.x;
     const int st = g.st;
-    const int sub = lanes_per_item(g.cnt, r);
-    const int s = tid % sub;
-    const int grp = tid / sub, ngrp = kBlock / sub;
+    const LaneMap lm = lane_map(g.cnt, r, 0, kNWave);
+    const int sub = lm.sub, s = lm.s, grp = lm.grp, ngrp = lm.ngrp;
     const int jlast = (s < r) ? s + ((r - 1 - s) / sub) * sub : -1;  // last owned slot
     const int nown = (s < r) ? (r - 1 - s) / sub + 1 : 0;               // owned slots
     const int pstep = sub * st;
@@ -558,9 +605,8 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
     // every column before the scan.  Every entry receives the eliminations in
     // order with the oracle's arithmetic either way.
     const bool ahead = tm.size > 1;
-    const int dl = tid - kWave, nd = kBlock - kWave;  // overlap lanes (waves 1..)
-    const int subd = lanes_per_item(g.cnt, r, nd);
-    const int sd = dl % subd, grpd = dl / subd, ngrpd = nd / subd;
+    const LaneMap ld = lane_map(g.cnt, r, 1, kNWave - 1);  // overlap lanes (waves 1..)
+    const int subd = ld.sub, sd = ld.s, grpd = ld.grp, ngrpd = ld.ngrp;
     double pk = 1.0;
     for (int k = 0; k < r; k++) {
 #ifdef LRA_TRACE
