@@ -189,15 +189,22 @@ struct Team {
 };
 
 // Team exchange without barriers or cache-maintenance fences: every 64-bit
-// word carries a 32-bit tag (selection number + 1) next to 32 data bits and
-// is written and read with single-copy-atomic device-scope accesses, which
-// go to the device-coherent level instead of the per-XCD L2.  A reader polls
-// a word until its tag matches, so a value can never be taken from an older
-// selection, whatever the order in which the writer's stores land.  Words of
-// parity p are rewritten at every selection of that parity, and the buffer
-// is cleared before each launch, so tags never alias.
-__device__ __forceinline__ void xput(uint64_t *p, uint32_t tag, uint32_t data) {
-    __hip_atomic_store(p, ((uint64_t)tag << 32) | data, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// word carries a tag (derived from the selection number) above its data bits
+// and is written and read with single-copy-atomic device-scope accesses,
+// which go to the device-coherent level instead of the per-XCD L2.  A reader
+// polls a word until its tag matches, so a value can never be taken from an
+// older selection, whatever the order in which the writer's stores land.
+// Row words carry 32-bit tags (selection + 1) over 32 data bits.  Header
+// words carry 4-bit tags ((selection + 1) mod 16) over 60 data bits: every
+// header word of parity p is rewritten at every selection of that parity,
+// and no workgroup can publish selection e + 2 before every other one has
+// finished reading selection e, so a header word holds either selection e
+// or e - 2 while it is awaited for e, and those two tags differ.  The buffer
+// is cleared before each launch; a cleared word (tag 0) is awaited only for
+// e < 2, whose tags are 1 and 2.
+template <int TB>
+__device__ __forceinline__ void xput(uint64_t *p, uint32_t tag, uint64_t data) {
+    __hip_atomic_store(p, ((uint64_t)tag << (64 - TB)) | data, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t xld(const uint64_t *p) {
@@ -206,22 +213,23 @@ __device__ __forceinline__ uint64_t xld(const uint64_t *p) {
 
 __device__ __forceinline__ uint64_t lo_hi(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
 
-// Read N exchange words that all carry `tag`: the N loads are issued
-// together, and only the words still stale are polled again; a null pointer
-// stands for no word (its output is 0).  Every wait is
-// bounded in wall-clock time: past `limit` ticks the workgroup records a
-// failure in *fail, stops polling for the rest of the launch (its reads
-// return 0) and runs to the end, so no wave can wait forever; the LRA then
-// reports LRA_EDEVICE.
-template <int N>
-__device__ __forceinline__ void xget(const uint64_t *const (&p)[N], uint32_t tag, uint32_t (&out)[N], int *fail,
+// Read N exchange words with TB-bit tags that all carry `tag`: the N loads
+// are issued together, and only the words still stale are polled again; a
+// null pointer stands for no word (its output is 0).  out[i] receives the
+// data bits.  Every wait is bounded in wall-clock time: past `limit` ticks
+// the workgroup records a failure in *fail, stops polling for the rest of
+// the launch (its reads return 0) and runs to the end, so no wave can wait
+// forever; the LRA then reports LRA_EDEVICE.
+template <int N, int TB>
+__device__ __forceinline__ void xget(const uint64_t *const (&p)[N], uint32_t tag, uint64_t (&out)[N], int *fail,
                                      uint64_t limit) {
+    constexpr int kSh = 64 - TB;
     uint64_t v[N];
 #pragma unroll
-    for (int i = 0; i < N; i++) v[i] = p[i] ? xld(p[i]) : (uint64_t)tag << 32;  // null: no word to wait for
+    for (int i = 0; i < N; i++) v[i] = p[i] ? xld(p[i]) : (uint64_t)tag << kSh;  // null: no word to wait for
     bool ok = true;
 #pragma unroll
-    for (int i = 0; i < N; i++) ok = ok && ((uint32_t)(v[i] >> 32) == tag);
+    for (int i = 0; i < N; i++) ok = ok && ((uint32_t)(v[i] >> kSh) == tag);
     if (!ok && !*(volatile int *)fail) {
         const uint64_t t0 = wall_clock64();
         for (;;) {
@@ -229,10 +237,10 @@ __device__ __forceinline__ void xget(const uint64_t *const (&p)[N], uint32_t tag
             ok = true;
 #pragma unroll
             for (int i = 0; i < N; i++) {
-                if ((uint32_t)(v[i] >> 32) != tag) v[i] = xld(p[i]);
+                if ((uint32_t)(v[i] >> kSh) != tag) v[i] = xld(p[i]);
             }
 #pragma unroll
-            for (int i = 0; i < N; i++) ok = ok && ((uint32_t)(v[i] >> 32) == tag);
+            for (int i = 0; i < N; i++) ok = ok && ((uint32_t)(v[i] >> kSh) == tag);
             if (ok) break;
             if (wall_clock64() - t0 > limit) {
                 *(volatile int *)fail = 1;
@@ -241,7 +249,27 @@ __device__ __forceinline__ void xget(const uint64_t *const (&p)[N], uint32_t tag
         }
     }
 #pragma unroll
-    for (int i = 0; i < N; i++) out[i] = ok ? (uint32_t)v[i] : 0u;
+    for (int i = 0; i < N; i++) out[i] = ok ? (v[i] & ((1ull << kSh) - 1)) : 0ull;
+}
+
+// Header of a team candidate in two 60-bit payloads: |value| (sign bit 0)
+// bits 62..3, then value bits 2..0, item (40 bits; all ones: no candidate),
+// slot (8 bits; 0xff: none) and the flags (8 bits).
+constexpr uint64_t kItemNone = (1ull << 40) - 1;
+__device__ __forceinline__ void encode_hdr(const Best &b, int flags, uint64_t &w0, uint64_t &w1) {
+    const bool have = b.v >= 0.0;
+    const uint64_t vb = have ? (uint64_t)__double_as_longlong(b.v) : 0ull;
+    const uint64_t it = have ? (uint64_t)b.item : kItemNone;
+    w0 = vb >> 3;
+    w1 = (vb & 7ull) | (it << 3) | ((uint64_t)(b.slot & 0xff) << 43) | ((uint64_t)(flags & 0xff) << 51);
+}
+__device__ __forceinline__ Best decode_hdr(uint64_t w0, uint64_t w1, int aux, int &flags) {
+    const uint64_t it = (w1 >> 3) & kItemNone;
+    const int sl = (int)((w1 >> 43) & 0xffu);
+    flags = (int)((w1 >> 51) & 0xffu);
+    if (it == kItemNone) return none();
+    return Best{__longlong_as_double((long long)((w0 << 3) | (w1 & 7ull))), (int64_t)it, sl == 0xff ? 0x7fffffff : sl,
+                aux};
 }
 
 struct Geo {   // item partition of one panel across the team
@@ -362,7 +390,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
             wf = f;
             for (int t = lane; t < width; t += kWave) sm.wrow[t] = loc.v >= 0 ? rowf(t, loc.item) : 0.0;
         } else {
-            const uint32_t tag = tm.epoch + 1u;
+            const uint32_t tag = tm.epoch + 1u, htag = tag & 0xfu;
             const int par = tm.epoch & 1;
             // all headers of a parity are contiguous (one coalesced read per
             // wave); rows live in a separate region
@@ -373,13 +401,10 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
             // the header goes out first: the team waits on headers, while a
             // row is read only after its header has won
             if (lane == 0) {
-                const uint64_t v = (uint64_t)__double_as_longlong(loc.v);
-                const uint64_t it = (uint64_t)loc.item;  // < 2^40, or INT64_MAX for "none"
-                const uint32_t hi = it >= (1ull << 40) ? 0xffu : (uint32_t)(it >> 32);
-                xput(mine + 0, tag, (uint32_t)v);
-                xput(mine + 1, tag, (uint32_t)(v >> 32));
-                xput(mine + 2, tag, (uint32_t)it);
-                xput(mine + 3, tag, hi | ((uint32_t)(loc.slot & 0xff) << 8) | ((uint32_t)(f & 0xff) << 16));
+                uint64_t h0, h1;
+                encode_hdr(loc, f, h0, h1);
+                xput<4>(mine + 0, htag, h0);
+                xput<4>(mine + 1, htag, h1);
 #ifdef LRA_TRACE
                 if (tm.epoch < kSelTrace && tm.rank < 256) g_sel_pub[tm.epoch * 256 + tm.rank] = wall_clock64();
 #endif
@@ -387,8 +412,8 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
             for (int t = lane; t < width; t += kWave) {
                 const double x = loc.v >= 0 ? rowf(t, loc.item) : 0.0;
                 const uint64_t u = (uint64_t)__double_as_longlong(x);
-                xput(myrow + 2 * t, tag, (uint32_t)u);
-                xput(myrow + 2 * t + 1, tag, (uint32_t)(u >> 32));
+                xput<32>(myrow + 2 * t, tag, (uint32_t)u);
+                xput<32>(myrow + 2 * t + 1, tag, (uint32_t)(u >> 32));
             }
             // every lane polls up to kMaxTeam / 64 headers, all loads at once
             // (null: past the end of the team, nothing to read)
@@ -403,19 +428,15 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                     for (int w = 0; w < kHdrWords; w++)
                         ps[q * kHdrWords + w] = g0 < tm.size ? hdrs + (size_t)g0 * kHdrWords + w : nullptr;
                 }
-                uint32_t d[4 * kHdrWords];
-                xget<4 * kHdrWords>(ps, tag, d, &sm.xfail, tm.spin_limit);
+                uint64_t d[4 * kHdrWords];
+                xget<4 * kHdrWords, 4>(ps, htag, d, &sm.xfail, tm.spin_limit);
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
                     if (lane + q * kWave >= tm.size) continue;
-                    const uint32_t *h = d + q * kHdrWords;
-                    const double v = __longlong_as_double((long long)lo_hi(h[0], h[1]));
-                    const uint32_t hi = h[3] & 0xffu;
-                    const int64_t it = hi == 0xffu ? INT64_MAX : (int64_t)(((uint64_t)hi << 32) | h[2]);
-                    int sl = (int)((h[3] >> 8) & 0xffu);
-                    if (sl == 0xff) sl = 0x7fffffff;
-                    consider(c, v, it, sl, lane + q * kWave);
-                    cf |= (int)((h[3] >> 16) & 0xffu);
+                    int fl;
+                    const Best o = decode_hdr(d[q * kHdrWords], d[q * kHdrWords + 1], lane + q * kWave, fl);
+                    if (better(o.v, o.item, o.slot, c.v, c.item, c.slot)) c = o;
+                    cf |= fl;
                 }
             }
             win = wave_reduce(c);
@@ -432,9 +453,9 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                 if (have) {
                     const uint64_t *row = rows + (size_t)win.aux * kRowWords + 2 * t;
                     const uint64_t *const ps[2] = {row, row + 1};
-                    uint32_t d[2];
-                    xget<2>(ps, tag, d, &sm.xfail, tm.spin_limit);
-                    x = __longlong_as_double((long long)lo_hi(d[0], d[1]));
+                    uint64_t d[2];
+                    xget<2, 32>(ps, tag, d, &sm.xfail, tm.spin_limit);
+                    x = __longlong_as_double((long long)lo_hi((uint32_t)d[0], (uint32_t)d[1]));
                 }
                 sm.wrow[t] = x;
             }

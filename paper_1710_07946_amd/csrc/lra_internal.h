@@ -12,10 +12,10 @@ constexpr int kBlock = 512;  // threads per workgroup (8 wavefronts, two per SIM
 constexpr int kRMax = 64;    // largest supported rank
 constexpr int kLMax = 256;   // largest number of sampled SRHT columns
 
-// Team exchange (64-bit tagged words): per workgroup and parity 4 header
-// words (value lo, value hi, item lo, item hi | slot << 8 | flags << 16) and
-// 2 words per row entry.
-constexpr int kHdrWords = 4;
+// Team exchange (64-bit tagged words): per workgroup and parity 2 header
+// words (value, item, slot and flags in two 60-bit payloads) and 2 words per
+// row entry.
+constexpr int kHdrWords = 2;
 constexpr int kMaxTeam = 256;
 constexpr int kRowWords = 2 * kLMax;
 constexpr int kSlotWords = kHdrWords + kRowWords;  // exchange words per workgroup and parity
