@@ -175,7 +175,8 @@ struct Smem {
     double logdet;
 #ifdef LRA_TRACE
     uint64_t t_select;    // total time inside team selections
-    uint64_t t_part[4];   // block reduce, header polls, row fetch, final barrier
+    uint64_t t_part[5];   // block reduce, header polls, row fetch, final barrier, wave arrival spread
+    uint64_t t_arr[8];    // arrival time of each wavefront at the current selection
     uint64_t n_select;
     uint64_t t_loop[5];   // LU item loop, LU tail, swap item loop, swap tail, B solve
 #endif
@@ -331,6 +332,62 @@ __device__ __forceinline__ LaneMap lane_map(int cnt, int r, int w0, int nw) {
     return m;
 }
 
+// Sketch QRP, per item (entries panel[c * ipw + li]) and in the oracle's
+// order of operations: chunks of N entries from entry c, offset o, all loads
+// of a chunk issued before its arithmetic.  dot: acc += w_c z_c; upd:
+// z_c <- z_c - f w_c, then nrm += z_c^2; nrm: nrm += z_c^2.
+template <int N>
+__device__ __forceinline__ void qrp_dot(const double *panel, int &o, int ipw, const double *w, int &c, double &acc) {
+    double z[N], y[N];
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        z[u] = panel[o + u * ipw];
+        y[u] = w[c + u];
+    }
+#pragma unroll
+    for (int u = 0; u < N; u++) acc += y[u] * z[u];
+    o += N * ipw;
+    c += N;
+}
+template <int N>
+__device__ __forceinline__ void qrp_upd(double *panel, int &o, int ipw, const double *w, int &c, double f, double &nrm) {
+    double z[N], y[N];
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        z[u] = panel[o + u * ipw];
+        y[u] = w[c + u];
+    }
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        z[u] = z[u] - f * y[u];
+        panel[o + u * ipw] = z[u];
+    }
+#pragma unroll
+    for (int u = 0; u < N; u++) nrm += z[u] * z[u];
+    o += N * ipw;
+    c += N;
+}
+template <int N>
+__device__ __forceinline__ void qrp_nrm(const double *panel, int &o, int ipw, int &c, double &nrm) {
+    double z[N];
+#pragma unroll
+    for (int u = 0; u < N; u++) z[u] = panel[o + u * ipw];
+#pragma unroll
+    for (int u = 0; u < N; u++) nrm += z[u] * z[u];
+    o += N * ipw;
+    c += N;
+}
+// The entries c0 .. l-1 of an item in chunks of 16, then 8, 4, 2 and 1.
+#define LRA_QRP_RUN(FN, n, ...)                        \
+    do {                                               \
+        int n_ = (n);                                  \
+        for (; n_ >= 16; n_ -= 16) FN<16>(__VA_ARGS__); \
+        if (n_ & 8) FN<8>(__VA_ARGS__);                \
+        if (n_ & 4) FN<4>(__VA_ARGS__);                \
+        if (n_ & 2) FN<2>(__VA_ARGS__);                \
+        if (n_ & 1) FN<1>(__VA_ARGS__);                \
+    } while (0)
+
 // Default hooks of team_select: the published row is the candidate's panel
 // column as stored, and there is no work to overlap with the exchange.
 struct PanelRow {
@@ -364,6 +421,9 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
 #ifdef LRA_TRACE
     const uint64_t t_in = wall_clock64();
 #endif
+#ifdef LRA_TRACE
+    if (lane == 0) sm.t_arr[w] = t_in;
+#endif
     b = wave_reduce(b);
     flag = wave_or(flag);
     if (lane == 0) {
@@ -372,6 +432,11 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
     }
     __syncthreads();
 #ifdef LRA_TRACE
+    if (threadIdx.x == 0) {
+        uint64_t last = sm.t_arr[0];
+        for (int q = 1; q < kNWave; q++) last = sm.t_arr[q] > last ? sm.t_arr[q] : last;
+        sm.t_part[4] += last - sm.t_arr[0];
+    }
     const uint64_t t_a = wall_clock64();
     uint64_t t_b = t_a, t_c = t_a;
 #endif
@@ -479,7 +544,8 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                 const double alpha = (x0 >= 0.0) ? -nx : nx;
                 sm.wrow[hstep] = x0 - alpha;
                 double vtv = 0.0;
-                for (int c = hstep; c < width; c++) vtv += sm.wrow[c] * sm.wrow[c];
+                int o = hstep, c = hstep;
+                LRA_QRP_RUN(qrp_nrm, width - hstep, sm.wrow, o, 1, c, vtv);
                 sm.vtv = vtv;
                 sm.alpha = alpha;
             }
@@ -951,48 +1017,22 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
         const double vtv = sm.vtv;
         for (int li = tid; li < g.cnt; li += kBlock) {
             if (flags[li]) continue;
-            // (terms past the end add +0.0 to a sum that is never -0.0)
             double nrm = 0.0;
             if (gg > 0 && vtv > 0.0) {  // reflection of step gg-1 (vector in sm.wrow[gg-1 ..])
                 double acc = 0.0;
-                for (int c0 = gg - 1; c0 < l; c0 += kChunk) {
-                    double z[kChunk], w[kChunk];
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) {
-                        const int c = min(c0 + u, l - 1);
-                        z[u] = panel[c * ipw + li];
-                        w[u] = sm.wrow[c];
-                    }
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) acc += (c0 + u < l) ? w[u] * z[u] : 0.0;
-                }
+                int o = (gg - 1) * ipw + li, c = gg - 1;
+                LRA_QRP_RUN(qrp_dot, l - gg + 1, panel, o, ipw, sm.wrow, c, acc);
                 const double f = 2.0 * acc / vtv;
-                // the update and the norm of the entries from gg on in one pass
-                // (the norm's terms still in increasing index order)
-                for (int c0 = gg - 1; c0 < l; c0 += kChunk) {
-                    double z[kChunk], w[kChunk];
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) {
-                        const int c = min(c0 + u, l - 1);
-                        z[u] = panel[c * ipw + li];
-                        w[u] = sm.wrow[c];
-                    }
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) {
-                        z[u] = z[u] - f * w[u];
-                        panel[min(c0 + u, l - 1) * ipw + li] = z[u];
-                    }
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) nrm += (c0 + u >= gg && c0 + u < l) ? z[u] * z[u] : 0.0;
-                }
+                // the update, and the norm of the entries from gg on in the
+                // same pass (its terms in increasing index order)
+                o = (gg - 1) * ipw + li;
+                c = gg - 1;
+                double nrm0 = 0.0;  // entry gg-1 takes the update only
+                qrp_upd<1>(panel, o, ipw, sm.wrow, c, f, nrm0);
+                LRA_QRP_RUN(qrp_upd, l - gg, panel, o, ipw, sm.wrow, c, f, nrm);
             } else {
-                for (int c0 = gg; c0 < l; c0 += kChunk) {
-                    double z[kChunk];
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) z[u] = panel[min(c0 + u, l - 1) * ipw + li];
-#pragma unroll
-                    for (int u = 0; u < kChunk; u++) nrm += (c0 + u < l) ? z[u] * z[u] : 0.0;
-                }
+                int o = gg * ipw + li, c = gg;
+                LRA_QRP_RUN(qrp_nrm, l - gg, panel, o, ipw, c, nrm);
             }
             consider(b, nrm, g.base + li, 0);
         }
@@ -1098,7 +1138,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
         sm.xfail = 0;
 #ifdef LRA_TRACE
         sm.t_select = 0;
-        sm.t_part[0] = sm.t_part[1] = sm.t_part[2] = sm.t_part[3] = 0;
+        sm.t_part[0] = sm.t_part[1] = sm.t_part[2] = sm.t_part[3] = sm.t_part[4] = 0;
         sm.n_select = 0;
         sm.t_loop[0] = sm.t_loop[1] = sm.t_loop[2] = sm.t_loop[3] = sm.t_loop[4] = 0;
 #endif
@@ -1166,6 +1206,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     LRA_TR(32, sm.t_part[2]);
     LRA_TR(33, sm.t_part[3]);
     LRA_TR(34, sm.n_select);
+    LRA_TR(40, sm.t_part[4]);
     LRA_TR(35, sm.t_loop[0]);
     LRA_TR(36, sm.t_loop[1]);
     LRA_TR(37, sm.t_loop[2]);
