@@ -71,8 +71,9 @@ struct Best {
     int32_t aux;   // owner workgroup (team reduction only)
 };
 
+// (bitwise on the comparisons: no branches in the wavefront reductions)
 __device__ __forceinline__ bool better(double v1, int64_t i1, int s1, double v2, int64_t i2, int s2) {
-    return v1 > v2 || (v1 == v2 && (i1 < i2 || (i1 == i2 && s1 < s2)));
+    return (v1 > v2) | ((v1 == v2) & ((i1 < i2) | ((i1 == i2) & (s1 < s2))));
 }
 
 __device__ __forceinline__ Best none() { return Best{-1.0, INT64_MAX, 0x7fffffff, -1}; }
@@ -83,16 +84,17 @@ __device__ __forceinline__ void consider(Best &b, double v, int64_t item, int sl
 
 // Wavefront argmax without LDS traffic: four DPP butterflies (quad swaps,
 // half-row and row mirrors) leave every lane of a 16-lane row with the row's
-// best, then the four rows are read out as uniform values and combined.  The
-// order is total, so the result does not depend on the tree's shape.  All 64
-// lanes must be active.
-template <int CTRL>
+// best, then two row broadcasts (row 0 into row 1 and row 2 into row 3, then
+// row 1 into rows 2 and 3) leave the wavefront's best in lane 63.  Lanes a
+// step does not write keep their own value.  The order is total, so the
+// result does not depend on the tree's shape.  All 64 lanes must be active.
+template <int CTRL, int RM = 0xf>
 __device__ __forceinline__ int dpp32(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, RM, 0xf, false);
 }
-template <int CTRL>
+template <int CTRL, int RM = 0xf>
 __device__ __forceinline__ int64_t dpp64(int64_t v) {
-    const int lo = dpp32<CTRL>((int)(uint32_t)v), hi = dpp32<CTRL>((int)(uint32_t)((uint64_t)v >> 32));
+    const int lo = dpp32<CTRL, RM>((int)(uint32_t)v), hi = dpp32<CTRL, RM>((int)(uint32_t)((uint64_t)v >> 32));
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 __device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
@@ -100,14 +102,16 @@ __device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
     const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
-template <int CTRL>
+template <int CTRL, int RM = 0xf>
 __device__ __forceinline__ void dpp_step(Best &b) {
-    Best o;
-    o.v = __longlong_as_double(dpp64<CTRL>(__double_as_longlong(b.v)));
-    o.item = dpp64<CTRL>(b.item);
-    o.slot = dpp32<CTRL>(b.slot);
-    o.aux = dpp32<CTRL>(b.aux);
-    if (better(o.v, o.item, o.slot, b.v, b.item, b.slot)) b = o;
+    const double ov = __longlong_as_double(dpp64<CTRL, RM>(__double_as_longlong(b.v)));
+    const int64_t oi = dpp64<CTRL, RM>(b.item);
+    const int os = dpp32<CTRL, RM>(b.slot), oa = dpp32<CTRL, RM>(b.aux);
+    const bool up = better(ov, oi, os, b.v, b.item, b.slot);
+    b.v = up ? ov : b.v;
+    b.item = up ? oi : b.item;
+    b.slot = up ? os : b.slot;
+    b.aux = up ? oa : b.aux;
 }
 __device__ __forceinline__ Best rdl_best(const Best &b, int lane) {
     return Best{__longlong_as_double(rdl64(__double_as_longlong(b.v), lane)), rdl64(b.item, lane),
@@ -117,19 +121,17 @@ constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
 constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;
 constexpr int kDppMirror = 0x140;
+constexpr int kDppRowBcast15 = 0x142;  // lane 15 of a row to the whole next row
+constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
 
 __device__ __forceinline__ Best wave_reduce(Best b) {
     dpp_step<kDppQuadSwap1>(b);
     dpp_step<kDppQuadSwap2>(b);
     dpp_step<kDppHalfMirror>(b);
     dpp_step<kDppMirror>(b);
-    Best r = rdl_best(b, 0);
-#pragma unroll
-    for (int row = 1; row < 4; row++) {
-        const Best o = rdl_best(b, 16 * row);
-        if (better(o.v, o.item, o.slot, r.v, r.item, r.slot)) r = o;
-    }
-    return r;
+    dpp_step<kDppRowBcast15, 0xa>(b);
+    dpp_step<kDppRowBcast31, 0xc>(b);
+    return rdl_best(b, 63);
 }
 
 // The same over lanes 0..7 only (the other lanes' values are ignored): the
@@ -146,8 +148,9 @@ __device__ __forceinline__ int wave_or(int f) {
     f |= dpp32<kDppQuadSwap2>(f);
     f |= dpp32<kDppHalfMirror>(f);
     f |= dpp32<kDppMirror>(f);
-    return __builtin_amdgcn_readlane(f, 0) | __builtin_amdgcn_readlane(f, 16) | __builtin_amdgcn_readlane(f, 32) |
-           __builtin_amdgcn_readlane(f, 48);
+    f |= dpp32<kDppRowBcast15, 0xa>(f);
+    f |= dpp32<kDppRowBcast31, 0xc>(f);
+    return __builtin_amdgcn_readlane(f, 63);
 }
 
 // ---------------------------------------------------------------- LDS state
