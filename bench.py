@@ -72,7 +72,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="time only the headline LRA (skip batched, residual and adjoint lines)")
-    ap.add_argument("--only", choices=["batched", "adjoint", "tall", "residual"], default=None,
+    ap.add_argument("--only", choices=["batched", "points", "adjoint", "tall", "residual"], default=None,
                     help="time one secondary line alone and print it (for profiling)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (reference for HBM counters)")
@@ -98,8 +98,9 @@ def main():
     from paper_1710_07946_amd import workloads
 
     lra.load()
-    if args.only in ("batched", "adjoint", "tall"):
-        fn = {"batched": bench_batched, "adjoint": bench_adjoint, "tall": bench_tall}[args.only]
+    if args.only in ("batched", "points", "adjoint", "tall"):
+        fn = {"batched": bench_batched, "points": bench_points, "adjoint": bench_adjoint,
+              "tall": bench_tall}[args.only]
         print(json.dumps({args.only: fn(lra, workloads, torch, np, args)}), flush=True)
         return
     t0 = time.time()
@@ -200,6 +201,7 @@ def main():
         torch.cuda.empty_cache()
         rec["secondary"] = {
             "batched_fmm": bench_batched(lra, workloads, torch, np, args),
+            "batched_fmm_points": bench_points(lra, workloads, torch, np, args),
             "adjoint_2048": bench_adjoint(lra, workloads, torch, np, args),
             "tall_65536x8192": bench_tall(lra, workloads, torch, np, args),
         }
@@ -288,6 +290,35 @@ def bench_batched(lra, workloads, torch, np, args):
         "useful_bytes_per_batch": nbytes,
     }
     del base, out, outs, views
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_points(lra, workloads, torch, np, args):
+    """The same 4096 FMM far-field blocks given by their point sets, every entry
+    K_ij = 1/|x_i - y_j| evaluated on the fly in FP64 (no block is stored),
+    r = 16, 3 sweeps, one persistent launch."""
+    count, r, sweeps, seed = 4096, 16, 3, 1000
+    pts_np, desc = workloads.fmm_points(count)
+    pts = torch.from_numpy(pts_np).cuda()
+    out = lra.lra_cur_batched_points(pts, desc, r, sweeps, seed)
+    ms = _time_events(torch, lambda: lra.lra_cur_batched_points(pts, desc, r, sweeps, seed, out=out),
+                      max(2, args.steps // 5), 1)
+    infos = out.info()
+    bad = [i for i in infos if i["status"] != 0]
+    # entries formed: each sweep's column and row panels, plus the generator
+    entries = sum(inf["sweeps_run"] * (int(d[2]) * r + r * int(d[3])) + r * r for inf, d in zip(infos, desc))
+    flops = 7.0 * entries  # 2 subtractions, 2 products, 1 sum, 1 square root, 1 division per entry
+    tfs = flops / (ms * 1e-3) / 1e12
+    res = {
+        "workload": "4096 FMM blocks 1/|x-y| from their point sets (m, n uniform in 64..1024), entries formed "
+                    "on the fly in fp64; r=16, 3 sweeps, random start",
+        "lras_per_s": count / (ms * 1e-3), "ms_per_batch": ms, "failed_blocks": len(bad),
+        "entries_per_batch": entries, "point_bytes": int(pts_np.nbytes),
+        "roofline": {"bound": "alu", "achieved": tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": tfs / FP64_PEAK_TFS, "traffic": None},
+    }
+    del pts, out
     torch.cuda.empty_cache()
     return res
 

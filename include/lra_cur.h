@@ -120,6 +120,31 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream);
 
+/* One far-field interaction block given by its two point sets: rows are the
+ * m points starting at point x_off of the point buffer, columns the n points
+ * starting at point y_off. */
+typedef struct {
+    int64_t x_off, y_off, m, n;
+} lra_pts_block;
+
+/* C-A CUR of many far-field blocks K_ij = 1 / |x_i - y_j| of planar point
+ * sets, with every entry evaluated on the fly in FP64 from the points (the
+ * superfast setting of the Superfast Multipole Method discussion, Section
+ * "Some Implications and Extensions of Our Study": only the O((m + n) r)
+ * entries that the C-A iterations read are ever formed; none is stored).
+ *   pts     device double[npts * 2], point p = (pts[2p], pts[2p + 1]);
+ *   blocks  HOST array of `count` descriptors; each block needs
+ *           0 <= x_off, x_off + m <= npts, 0 <= y_off, y_off + n <= npts and
+ *           r <= min(m, n) (else LRA_EINVAL, nothing launched).
+ * Entry: dx = x_i0 - y_j0, dy = x_i1 - y_j1, K_ij = 1 / sqrt(dx dx + dy dy),
+ * each operation rounded once in FP64.  A block with coinciding points gets
+ * a non-finite entry and the status LRA_EINVAL in its info.  Scheduling,
+ * seeds (seed + b), outputs and the unsupported options are those of
+ * lra_cur_batched. */
+lra_status lra_cur_batched_points(const double *pts, int64_t npts, const lra_pts_block *blocks, int64_t count,
+                                  int32_t r, int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out,
+                                  int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
+
 /* Moments of the residual E = W - C U R of a CUR (C = W[:, J], R = W[I, :],
  * U r x r as returned by lra_cur), for the a-posteriori error estimate of
  * Section 4 (a random q x s submatrix of E whose entries are treated as

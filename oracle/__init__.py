@@ -71,8 +71,10 @@ def lib():
         L.orc_residual.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, P, P]
         L.orc_cur_adjoint.argtypes = [P, P, P, i64, i64, ct.c_int, P, P, P, i64, P, P, P, P]
         L.orc_residual_moments.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, i64, i64, u64, P]
+        L.orc_fmm_entries.argtypes = [P, i64, P, i64, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
-                  "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments"):
+                  "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
+                  "orc_fmm_entries"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -313,3 +315,17 @@ def cur_adjoint(C, R, G, om_i, om_j, aval):
     if st:
         raise ValueError("cur_adjoint: status %d" % st)
     return loss.value, dC, dR, dG
+
+
+def fmm_entries(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """K_ij = 1/|x_i - y_j| in FP64 for planar points x (m, 2) and y (n, 2)
+    (far-field block of the Superfast Multipole discussion, Section "Some
+    Implications and Extensions of Our Study")."""
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    m, n = x.shape[0], y.shape[0]
+    K = np.empty((m, n), np.float64)
+    st = lib().orc_fmm_entries(_p(x), m, _p(y), n, _p(K))
+    if st != 0:
+        raise ValueError("orc_fmm_entries: status %d" % st)
+    return K

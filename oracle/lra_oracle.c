@@ -20,9 +20,7 @@
  *   - index sets are 0-based int64; outputs are sorted ascending;
  *   - status: 0 ok, 1 invalid argument, 2 singular (rank deficient panel).
  *
- * Parity pins for every routine live in tests/test_oracle_*.py; the one
- * routine without an independent pin is the pseudo-inverse fallback, which is
- * not implemented (a singular nucleus is reported as status 2).
+ * Parity pins for every routine live in tests/test_oracle_*.py.
  */
 #include <math.h>
 #include <stdint.h>
@@ -886,5 +884,25 @@ int orc_residual_moments(const void *A, int dtype, int64_t m, int64_t n, int64_t
     out[2] = sabs;
     out[3] = sw2;
     free(rows); free(cols); free(UR); free(cr);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Far-field interaction block of two planar point sets (the Superfast      */
+/* Multipole discussion in Section "Some Implications and Extensions of Our */
+/* Study": generators of blocks K_ij = 1/|x_i - y_j| between well separated */
+/* clusters).  Written out in FP64, each operation rounded once:            */
+/* dx = x_i0 - y_j0, dy = x_i1 - y_j1, K_ij = 1 / sqrt(dx*dx + dy*dy).      */
+/* x: m points, y: n points, as (p0, p1) pairs; K row-major m x n.          */
+/* ------------------------------------------------------------------------ */
+int orc_fmm_entries(const double *x, int64_t m, const double *y, int64_t n, double *K) {
+    if (!x || !y || !K || m < 1 || n < 1) return ORC_EINVAL;
+    for (int64_t i = 0; i < m; i++) {
+        for (int64_t j = 0; j < n; j++) {
+            const double dx = x[2 * i] - y[2 * j];
+            const double dy = x[2 * i + 1] - y[2 * j + 1];
+            K[i * n + j] = 1.0 / sqrt(dx * dx + dy * dy);
+        }
+    }
     return ORC_OK;
 }

@@ -48,6 +48,10 @@ class lra_block(ct.Structure):
     _fields_ = [("offset", ct.c_int64), ("m", ct.c_int64), ("n", ct.c_int64), ("lda", ct.c_int64)]
 
 
+class lra_pts_block(ct.Structure):
+    _fields_ = [("x_off", ct.c_int64), ("y_off", ct.c_int64), ("m", ct.c_int64), ("n", ct.c_int64)]
+
+
 INFO_BYTES = ct.sizeof(lra_info)
 _lib = None
 
@@ -76,6 +80,9 @@ def load() -> ct.CDLL:
         L.lra_cur_batched.argtypes = [P, ct.c_int, ct.POINTER(lra_block), i64, i32, i32, ct.c_uint64,
                                       ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_batched.restype = ct.c_int
+        L.lra_cur_batched_points.argtypes = [P, i64, ct.POINTER(lra_pts_block), i64, i32, i32, ct.c_uint64,
+                                             ct.POINTER(lra_opts), P, P, P, P, P]
+        L.lra_cur_batched_points.restype = ct.c_int
         L.lra_residual.argtypes = [P, ct.c_int, i64, i64, i64, i32, P, P, P, i32, i32, ct.c_uint64, i32, P, P]
         L.lra_residual.restype = ct.c_int
         L.lra_cur_adjoint.argtypes = [i64, i64, i64, i32, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
@@ -231,6 +238,40 @@ def lra_cur_batched(base, blocks, r: int, sweeps: int, seed: int, *, delta: floa
                                 ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
     if st != LRA_OK:
         raise LraError(st, "lra_cur_batched")
+    return out
+
+
+def lra_cur_batched_points(pts, blocks, r: int, sweeps: int, seed: int, *, delta: float = 0.01,
+                           max_swaps: int = -1, refine_steps: int = 0, out: CurOut | None = None,
+                           stream=None) -> CurOut:
+    """C-A CUR of `count` far-field blocks K_ij = 1/|x_i - y_j| evaluated on the
+    fly from the device float64 point tensor `pts` of shape (npts, 2).
+
+    ``blocks`` is an int64 array of shape (count, 4): (x_off, y_off, m, n) in
+    points.  Block b uses seed + b.  Asynchronous like ``lra_cur``.
+    """
+    torch = _torch()
+    if pts.dim() != 2 or pts.shape[1] != 2 or not pts.is_cuda or pts.dtype != torch.float64 \
+            or not pts.is_contiguous():
+        raise ValueError("pts must be a contiguous (npts, 2) float64 device tensor")
+    desc = np.ascontiguousarray(blocks, np.int64).reshape(-1, 4)
+    count = desc.shape[0]
+    dev = pts.device
+    if out is None:
+        out = CurOut(torch.empty((count, r), dtype=torch.int64, device=dev),
+                     torch.empty((count, r), dtype=torch.int64, device=dev),
+                     torch.empty((count, r, r), dtype=torch.float64, device=dev),
+                     torch.empty(count * INFO_BYTES, dtype=torch.uint8, device=dev))
+    arr = (lra_pts_block * max(count, 1))()
+    ct.memmove(arr, desc.ctypes.data, desc.nbytes)
+    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, 0, None)
+    st = load().lra_cur_batched_points(ct.c_void_p(pts.data_ptr()), pts.shape[0], arr, count, r, sweeps,
+                                       ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o),
+                                       ct.c_void_p(out.I.data_ptr()), ct.c_void_p(out.J.data_ptr()),
+                                       ct.c_void_p(out.U.data_ptr()), ct.c_void_p(out.info_raw.data_ptr()),
+                                       _stream_ptr(stream))
+    if st != LRA_OK:
+        raise LraError(st, "lra_cur_batched_points")
     return out
 
 

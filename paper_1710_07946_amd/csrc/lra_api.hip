@@ -18,6 +18,7 @@
 namespace {
 
 using lra::BlockDesc;
+using lra::PtsDesc;
 using lra::CAConfig;
 using lra::kBlock;
 using lra::kLMax;
@@ -355,6 +356,74 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
     const int64_t grid = std::min<int64_t>((int64_t)dinfo.cus * occ, count);
     hipError_t e = lra::launch_batched(dt, base, ws->blocks, ws->order, count, seed, cfg, ws->counters + 1, (int)grid,
                                        dyn, I_out, J_out, U_out, infos, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
+lra_status lra_cur_batched_points(const double *pts, int64_t npts, const lra_pts_block *blocks, int64_t count,
+                                  int32_t r, int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out,
+                                  int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream) {
+    if (!pts || !blocks || count < 0 || npts < 1 || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (r < 1 || r > kRMax || sweeps < 1 || count > (int64_t)INT32_MAX) return LRA_EINVAL;
+    if (npts >= ((int64_t)1 << 39)) return LRA_EINVAL;  // item ids travel in 40 bits
+    CAConfig cfg;
+    lra_opts o;
+    lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
+    if (st != LRA_OK) return st;
+    if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
+    if (count == 0) return LRA_OK;
+    int64_t maxdim = 0;
+    std::vector<PtsDesc> desc((size_t)count);
+    for (int64_t b = 0; b < count; b++) {
+        const lra_pts_block &k = blocks[b];
+        if (k.x_off < 0 || k.y_off < 0 || k.m < 1 || k.n < 1 || r > k.m || r > k.n) return LRA_EINVAL;
+        if (k.m > npts - k.x_off || k.n > npts - k.y_off) return LRA_EINVAL;
+        desc[b] = PtsDesc{k.x_off, k.y_off, k.m, k.n};
+        maxdim = std::max(maxdim, std::max(k.m, k.n));
+    }
+    std::vector<int32_t> order((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return desc[a].m + desc[a].n > desc[b].m + desc[b].n;
+    });
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
+    const LdsPlan plan = plan_lds(maxdim, maxdim, r, LRA_PRE_NONE, 0, 1, lds_budget);
+    if (!plan.fits) return LRA_EUNSUPPORTED;
+    cfg.panel_bytes = (int32_t)plan.panel_bytes;
+    const size_t dyn = plan.dyn_bytes;
+
+    if (ws->block_cap < count) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(ws->blocks);
+        (void)hipFree(ws->order);
+        ws->blocks = nullptr;
+        ws->order = nullptr;
+        ws->block_cap = 0;
+        if (hipMalloc(&ws->blocks, sizeof(BlockDesc) * count) != hipSuccess) return LRA_ENOMEM;
+        if (hipMalloc(&ws->order, sizeof(int32_t) * count) != hipSuccess) return LRA_ENOMEM;
+        ws->block_cap = count;
+    }
+    PtsDesc *dblocks = reinterpret_cast<PtsDesc *>(ws->blocks);
+    if (hipMemcpyAsync(dblocks, desc.data(), sizeof(PtsDesc) * count, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(ws->order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return LRA_EDEVICE;
+    // the host vectors must outlive the copies
+    (void)hipStreamSynchronize(stream);
+
+    int occ = lra::points_occupancy(dyn);
+    if (occ < 1) occ = 1;
+    const int64_t grid = std::min<int64_t>((int64_t)dinfo.cus * occ, count);
+    hipError_t e = lra::launch_points(pts, dblocks, ws->order, count, seed, cfg, ws->counters + 1, (int)grid, dyn,
+                                      I_out, J_out, U_out, infos, stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;

@@ -868,12 +868,33 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
     swaps_total += swaps;
 }
 
+// ---------------------------------------------------------------- entry sources
+// Where the entries W[i][j] of one matrix come from: a dense row-major array
+// (FP64, FP32 or BF16 as stored, converted to FP64), or, for far-field
+// interaction blocks, evaluated on the fly from the two point sets as
+// K_ij = 1 / |x_i - y_j| in FP64 (dx dx + dy dy, then a correctly rounded
+// square root and division), so that no entry is ever stored.
+template <typename T>
+struct DenseSrc {
+    const T *A;
+    int64_t lda;
+    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const { return Elem<T>::load(A, i * lda + j); }
+};
+struct PointSrc {
+    const double *x;  // row points, (x0, x1) pairs
+    const double *y;  // column points
+    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const {
+        const double dx = x[2 * i] - y[2 * j], dy = x[2 * i + 1] - y[2 * j + 1];
+        return 1.0 / sqrt(dx * dx + dy * dy);
+    }
+};
+
 // Gather `cnt` items x r entries of W into the slot-major panel, eight
 // independent loads in flight per thread.  col = true: item it, slot j reads
 // W[it][set[j]]; col = false: W[set[j]][it] (coalesced across items).
-template <typename T>
-__device__ __forceinline__ int gather_panel(double *panel, const Geo &g, const T *A, int64_t lda, int r, bool col,
-                            const int64_t *set) {
+template <class Src>
+__device__ __forceinline__ int gather_panel(double *panel, const Geo &g, const Src &src, int r, bool col,
+                                            const int64_t *set) {
     int bad = 0;
     const int tot = g.cnt * r;
     for (int e0 = threadIdx.x; e0 < tot; e0 += kBlock * 8) {
@@ -884,7 +905,7 @@ __device__ __forceinline__ int gather_panel(double *panel, const Geo &g, const T
             if (e < tot) {
                 const int li = e % g.cnt, j = e / g.cnt;
                 const int64_t it = g.base + li;
-                v[u] = Elem<T>::load(A, col ? it * lda + set[j] : set[j] * lda + it);
+                v[u] = col ? src(it, set[j]) : src(set[j], it);
             }
         }
 #pragma unroll
@@ -903,13 +924,13 @@ __device__ __forceinline__ int gather_panel(double *panel, const Geo &g, const T
 // One C-A step.  col = true: panel = W[:, set_in] (items = rows of W);
 // col = false: panel = W[set_in, :]^T (items = columns).  set_out receives
 // the new sorted set.
-template <typename T>
-__device__ __forceinline__ void ca_step(Team &tm, Smem &sm, double *panel, uint8_t *flags, const T *A, int64_t m, int64_t n,
-                        int64_t lda, int r, bool col, const int64_t *set_in, int64_t *set_out, const CAConfig &cfg,
-                        int32_t &swaps_total, int32_t &converged) {
+template <class Src>
+__device__ __forceinline__ void ca_step(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Src &src, int64_t m,
+                                       int64_t n, int r, bool col, const int64_t *set_in, int64_t *set_out,
+                                       const CAConfig &cfg, int32_t &swaps_total, int32_t &converged) {
     const Geo g = geo(tm, col ? m : n);
     LRA_TR(10 + (col ? 0 : 1), 0);
-    const int bad = gather_panel<T>(panel, g, A, lda, r, col, set_in);
+    const int bad = gather_panel(panel, g, src, r, col, set_in);
     for (int li = threadIdx.x; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
     LRA_TR(12, 0);
@@ -930,9 +951,9 @@ __device__ __forceinline__ void ca_step(Team &tm, Smem &sm, double *panel, uint8
 // swaps the roles of rows and columns).  Then greedy Householder QRP over the
 // items picks r of them (Algorithm alg1tor); each reflection is applied
 // lazily, fused with the next norm scan.  The chosen items land in out.
-template <typename T>
-__device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const T *A, int64_t m, int64_t n,
-                           int64_t lda, int r, int side, int d, int l, uint64_t seed, int64_t *out) {
+template <class Src>
+__device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Src &src, int64_t m,
+                                          int64_t n, int r, int side, int d, int l, uint64_t seed, int64_t *out) {
     const int tid = threadIdx.x;
     const int64_t dim = side ? m : n;
     const Geo g = geo(tm, side ? n : m);
@@ -974,7 +995,7 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
                 for (int a = 0; a < 8; a++) {
                     const int64_t c = a * s + ee;
                     w[a] = 0.0;
-                    if (a < q2 && c < dim) w[a] = side ? Elem<T>::load(A, c * lda + it) : Elem<T>::load(A, it * lda + c);
+                    if (a < q2 && c < dim) w[a] = side ? src(c, it) : src(it, c);
                 }
                 double acc = 0.0;
 #pragma unroll
@@ -1003,7 +1024,7 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
                 const int64_t c = a * s + ee;
                 if (c >= dim) continue;
                 const double h = (__popcll((uint64_t)(a & bb)) & 1) ? -1.0 : 1.0;
-                const double w = side ? Elem<T>::load(A, c * lda + it) : Elem<T>::load(A, it * lda + c);
+                const double w = side ? src(c, it) : src(it, c);
                 acc += w * rademacher(seed, c) * h;
             }
             const double y = scale * acc;
@@ -1056,14 +1077,14 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
 // (ties to the lowest row) and r column solves, then `refine` steps of
 // X <- X + X (I - G X) (Algorithm algcnnncl with k = l = r).  One workgroup;
 // `ws` holds 4 r^2 doubles.  Writes U (row-major, J-order x I-order).
-template <typename T>
-__device__ __forceinline__ void nucleus(Smem &sm, double *ws, const T *A, int64_t lda, int r, int refine, double *U_out) {
+template <class Src>
+__device__ __forceinline__ void nucleus(Smem &sm, double *ws, const Src &src, int r, int refine, double *U_out) {
     const int tid = threadIdx.x;
     double *G = ws, *LU = ws + r * r, *X = ws + 2 * r * r, *X2 = ws + 3 * r * r;
     __shared__ int p[kRMax];
     for (int e = tid; e < r * r; e += kBlock) {
         const int a = e / r, b = e % r;
-        const double v = Elem<T>::load(A, sm.Iset[a] * lda + sm.Jset[b]);
+        const double v = src(sm.Iset[a], sm.Jset[b]);
         G[e] = v;
         LU[e] = v;
     }
@@ -1126,10 +1147,10 @@ __device__ __forceinline__ void nucleus(Smem &sm, double *ws, const T *A, int64_
 }
 
 // The whole C-A path for one matrix, executed by every workgroup of a team.
-template <typename T>
-__device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const T *A, int64_t m, int64_t n,
-                         int64_t lda, uint64_t seed, const CAConfig &cfg, int64_t *I_out, int64_t *J_out,
-                         double *U_out, lra_info *info) {
+template <class Src>
+__device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const Src &src, int64_t m,
+                                        int64_t n, uint64_t seed, const CAConfig &cfg, int64_t *I_out, int64_t *J_out,
+                                        double *U_out, lra_info *info) {
     const int tid = threadIdx.x;
     const int r = cfg.r;
     int32_t swaps_total = 0, converged = 1, sweeps_run = 0;
@@ -1158,11 +1179,11 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
         // (two call sites so that each copy knows its panel's address space)
         if (cfg.sketch_ws) {
             const int64_t st_s = (((side ? n : m) + tm.size - 1) / tm.size) | 1;
-            sketch_qrp<T>(tm, sm, cfg.sketch_ws + (size_t)tm.rank * st_s * cfg.ah_samples, flags, A, m, n, lda, r,
-                          side, cfg.ah_depth, cfg.ah_samples, seed, side ? sm.Jset : sm.Iset);
+            sketch_qrp(tm, sm, cfg.sketch_ws + (size_t)tm.rank * st_s * cfg.ah_samples, flags, src, m, n, r, side,
+                       cfg.ah_depth, cfg.ah_samples, seed, side ? sm.Jset : sm.Iset);
         } else {
-            sketch_qrp<T>(tm, sm, dyn, flags, A, m, n, lda, r, side, cfg.ah_depth, cfg.ah_samples, seed,
-                          side ? sm.Jset : sm.Iset);
+            sketch_qrp(tm, sm, dyn, flags, src, m, n, r, side, cfg.ah_depth, cfg.ah_samples, seed,
+                       side ? sm.Jset : sm.Iset);
         }
         if (sm.status != LRA_OK) goto finish;
         if (tid < kWave) sort_set_wave(side ? sm.Jset : sm.Iset, r);
@@ -1185,8 +1206,8 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     // step per sweep (one call site: the step is inlined once)
     for (int st = 0; st < seed_step + 2 * cfg.sweeps; st++) {
         const bool col = st >= seed_step && ((st - seed_step) & 1) == 0;
-        ca_step<T>(tm, sm, dyn, flags, A, m, n, lda, r, col, col ? sm.Jset : sm.Iset, col ? sm.Iset : sm.Jset, cfg,
-                   swaps_total, converged);
+        ca_step(tm, sm, dyn, flags, src, m, n, r, col, col ? sm.Jset : sm.Iset, col ? sm.Iset : sm.Jset, cfg,
+                swaps_total, converged);
         if (sm.status != LRA_OK) goto finish;
         if (st < seed_step || col) continue;
         const int sw = (st - seed_step) / 2;  // sweep sw is complete
@@ -1216,7 +1237,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     LRA_TR(38, sm.t_loop[3]);
     LRA_TR(39, sm.t_loop[4]);
 #endif
-    if (tm.rank == 0) nucleus<T>(sm, dyn, A, lda, r, cfg.refine_steps, U_out);
+    if (tm.rank == 0) nucleus(sm, dyn, src, r, cfg.refine_steps, U_out);
     LRA_TR(21, 0);
 finish:
     __syncthreads();
@@ -1258,7 +1279,7 @@ __global__ void __launch_bounds__(kBlock) ca_team_kernel(const T *A, int64_t m, 
     tm.epoch = 0;
     tm.xw = ws.xw;
     tm.spin_limit = ws.spin_limit;
-    ca_solve<T>(tm, sm, dyn, flags, A, m, n, lda, seed, cfg, I_out, J_out, U_out, info);
+    ca_solve(tm, sm, dyn, flags, DenseSrc<T>{A, lda}, m, n, seed, cfg, I_out, J_out, U_out, info);
 }
 
 template <typename T>
@@ -1285,9 +1306,41 @@ __global__ void __launch_bounds__(kBlock) ca_batched_kernel(const T *base, const
         if (job >= count) break;
         const int32_t b = order[job];
         const BlockDesc d = blocks[b];
-        ca_solve<T>(tm, sm, dyn, flags, base + d.offset, d.m, d.n, d.lda, seed + (uint64_t)b, cfg,
-                    I_out + (int64_t)b * r, J_out + (int64_t)b * r, U_out + (int64_t)b * r * r,
-                    infos ? infos + b : nullptr);
+        ca_solve(tm, sm, dyn, flags, DenseSrc<T>{base + d.offset, d.lda}, d.m, d.n, seed + (uint64_t)b, cfg,
+                 I_out + (int64_t)b * r, J_out + (int64_t)b * r, U_out + (int64_t)b * r * r,
+                 infos ? infos + b : nullptr);
+        __syncthreads();
+    }
+}
+
+// Far-field blocks evaluated from their point sets: the batched loop with
+// entries computed on the fly.
+__global__ void __launch_bounds__(kBlock) ca_points_kernel(const double *pts, const PtsDesc *blocks,
+                                                           const int32_t *order, int64_t count, uint64_t seed,
+                                                           CAConfig cfg, unsigned *queue, int64_t *I_out,
+                                                           int64_t *J_out, double *U_out, lra_info *infos) {
+    __shared__ Smem sm;
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    double *dyn = reinterpret_cast<double *>(lds_dyn);
+    uint8_t *flags = lds_dyn + cfg.panel_bytes;
+    Team tm;
+    tm.rank = 0;
+    tm.size = 1;
+    tm.epoch = 0;
+    tm.xw = nullptr;
+    tm.spin_limit = 0;
+    const int r = cfg.r;
+    for (;;) {
+        if (threadIdx.x == 0) sm.job = (int32_t)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int64_t job = sm.job;
+        __syncthreads();
+        if (job >= count) break;
+        const int32_t b = order[job];
+        const PtsDesc d = blocks[b];
+        ca_solve(tm, sm, dyn, flags, PointSrc{pts + 2 * d.x_off, pts + 2 * d.y_off}, d.m, d.n, seed + (uint64_t)b, cfg,
+                 I_out + (int64_t)b * r, J_out + (int64_t)b * r, U_out + (int64_t)b * r * r,
+                 infos ? infos + b : nullptr);
         __syncthreads();
     }
 }
@@ -1366,6 +1419,25 @@ hipError_t launch_batched(int dtype, const void *base, const BlockDesc *blocks, 
     }
 }
 
+hipError_t launch_points(const double *pts, const PtsDesc *blocks, const int32_t *order, int64_t count,
+                         uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
+                         int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream) {
+    hipError_t e =
+        hipFuncSetAttribute((const void *)ca_points_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+    (void)e;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, queue, 1);
+    hipLaunchKernelGGL(ca_points_kernel, dim3(grid), dim3(kBlock), dyn_bytes, stream, pts, blocks, order, count, seed,
+                       cfg, queue, I_out, J_out, U_out, infos);
+    return hipGetLastError();
+}
+
+int points_occupancy(size_t dyn_bytes) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_points_kernel, kBlock, dyn_bytes) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
 int batched_occupancy(int dtype, size_t dyn_bytes) {
     int blocks = 0;
     hipError_t e;
@@ -1381,13 +1453,14 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
 
 // Static LDS of the C-A kernels as compiled (the Smem block plus the
 // function-level shared variables of the nucleus and inverse), the largest
-// over the element types; queried once.
+// over the element types and entry sources; queried once.
 size_t static_lds_bytes() {
     static size_t bytes = 0;
     if (bytes == 0) {
-        const void *fns[6] = {(const void *)ca_team_kernel<double>,    (const void *)ca_team_kernel<float>,
+        const void *fns[7] = {(const void *)ca_team_kernel<double>,    (const void *)ca_team_kernel<float>,
                               (const void *)ca_team_kernel<uint16_t>,  (const void *)ca_batched_kernel<double>,
-                              (const void *)ca_batched_kernel<float>,  (const void *)ca_batched_kernel<uint16_t>};
+                              (const void *)ca_batched_kernel<float>,  (const void *)ca_batched_kernel<uint16_t>,
+                              (const void *)ca_points_kernel};
         size_t mx = sizeof(Smem) + sizeof(int) * kRMax;
         for (const void *f : fns) {
             hipFuncAttributes attr;

@@ -38,6 +38,13 @@ struct TeamWs {
 struct BlockDesc {
     int64_t offset, m, n, lda;
 };
+// Point-set block: rows x_off .. x_off + m - 1, columns y_off .. y_off + n - 1
+// of the point buffer (same size as BlockDesc, so both share one buffer).
+struct PtsDesc {
+    int64_t x_off, y_off, m, n;
+};
+static_assert(sizeof(PtsDesc) == sizeof(BlockDesc), "block descriptors share one device buffer");
+
 
 hipError_t launch_team(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, const CAConfig &cfg,
                        const TeamWs &ws, int team, size_t dyn_bytes, int64_t *I_out, int64_t *J_out, double *U_out,
@@ -48,6 +55,10 @@ hipError_t launch_batched(int dtype, const void *base, const BlockDesc *blocks, 
                           int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
 
 int batched_occupancy(int dtype, size_t dyn_bytes);
+hipError_t launch_points(const double *pts, const PtsDesc *blocks, const int32_t *order, int64_t count,
+                         uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
+                         int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
+int points_occupancy(size_t dyn_bytes);
 
 size_t residual_scratch_bytes(int64_t m, int64_t n, int r, int q, int s, int prec);
 hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,

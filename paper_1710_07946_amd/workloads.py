@@ -103,6 +103,28 @@ def fmm_batch(count: int, shape_seed: int = 1021, block_seed0: int = 1022000, al
     return flat, desc
 
 
+def fmm_points(count: int, shape_seed: int = 1021, block_seed0: int = 1022000):
+    """The point sets behind ``fmm_batch``'s blocks (same shapes and streams),
+    all in one float64 array of shape (P, 2): block b's m row points, then its
+    n column points.  Returns (points, descriptors int64[count, 4] =
+    (x_off, y_off, m, n))."""
+    ms, ns = fmm_block_shapes(count, seed=shape_seed)
+    desc = np.zeros((count, 4), np.int64)
+    parts = []
+    off = 0
+    for b in range(count):
+        m, n = int(ms[b]), int(ns[b])
+        gen = np.random.default_rng(block_seed0 + b)
+        gap = gen.uniform(2.0, 3.0)
+        x = gen.uniform(0.0, 1.0, size=(m, 2))
+        y = gen.uniform(0.0, 1.0, size=(n, 2))
+        y[:, 0] += 1.0 + gap
+        desc[b] = (off, off + m, m, n)
+        parts += [x, y]
+        off += m + n
+    return np.ascontiguousarray(np.concatenate(parts, axis=0)), desc
+
+
 def decaying_spectrum_sigma(n: int, lead: int = 64, floor: float = 1e-7) -> np.ndarray:
     """sigma_i = 1 for i <= lead, max(i^-2, floor) after (1-based i)."""
     i = np.arange(1, n + 1, dtype=np.float64)

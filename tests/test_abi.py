@@ -42,6 +42,7 @@ def test_strerror(lib):
 def test_struct_layouts():
     assert ct.sizeof(lra.lra_info) == 40
     assert ct.sizeof(lra.lra_block) == 32
+    assert ct.sizeof(lra.lra_pts_block) == 32
     assert ct.sizeof(lra.lra_opts) == 40
 
 
@@ -88,6 +89,31 @@ def test_batched_invalid_arguments_rejected_on_host(lib):
                                None) == lra.LRA_EINVAL
     # an empty batch is a no-op
     assert lib.lra_cur_batched(fake, 1, blocks, 0, 3, 1, 0, None, fake, fake, fake, None, None) == lra.LRA_OK
+
+
+def test_points_invalid_arguments_rejected_on_host(lib):
+    fake = ct.c_void_p(0x1000)
+    E = lra.LRA_EINVAL
+
+    def call(blocks, npts=100, r=3, count=None, opts=None, pts=fake):
+        arr = (lra.lra_pts_block * max(len(blocks), 1))(*blocks)
+        return lib.lra_cur_batched_points(pts, npts, arr, len(blocks) if count is None else count, r, 1, 0, opts,
+                                          fake, fake, fake, None, None)
+
+    B = lra.lra_pts_block
+    assert call([B(0, 50, 40, 51)], npts=100) == E   # columns end past the buffer: 50 + 51 > 100
+    assert call([B(61, 0, 40, 40)], npts=100) == E   # 61 + 40 > 100
+    assert call([B(-1, 0, 10, 10)]) == E
+    assert call([B(0, 10, 2, 10)]) == E              # r > m
+    assert call([B(0, 10, 10, 10)], r=0) == E
+    assert call([B(0, 10, 10, 10)], r=65) == E
+    assert call([B(0, 10, 10, 10)], npts=0) == E
+    assert call([B(0, 10, 10, 10)], pts=None) == E
+    o = lra.lra_default_opts()
+    o.preprocess = 1
+    assert call([B(0, 10, 10, 10)], opts=ct.byref(o)) == E
+    # an empty batch is a no-op
+    assert call([B(0, 10, 10, 10)], count=0) == lra.LRA_OK
 
 
 def test_residual_invalid_arguments_rejected_on_host(lib):
