@@ -72,9 +72,11 @@ def lib():
         L.orc_cur_adjoint.argtypes = [P, P, P, i64, i64, ct.c_int, P, P, P, i64, P, P, P, P]
         L.orc_residual_moments.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, i64, i64, u64, P]
         L.orc_fmm_entries.argtypes = [P, i64, P, i64, P]
+        L.orc_cynical.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P,
+                                  P, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
                   "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
-                  "orc_fmm_entries"):
+                  "orc_fmm_entries", "orc_cynical"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -257,6 +259,27 @@ def ca_cur(A: np.ndarray, r: int, sweeps: int, seed: int, delta: float = 0.01, m
     info = _Info()
     st = lib().orc_ca_cur(_p(A), _dtype_code(A), m, n, n, r, sweeps, seed, ct.byref(o),
                           _p(I), _p(J), _p(U), ct.byref(info))
+    return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
+                     info.min_margin, info.det_log_abs, info.nucleus_rank)
+
+
+def cynical(A: np.ndarray, r: int, k: int, loops: int, sweeps: int, seed: int, delta: float = 0.01,
+            max_swaps: int = -1, refine_steps: int = 0) -> CurResult:
+    """Cynical CUR on a k x k sketch (Tests 3, loops = 0) or after `loops` C-A
+    loops at rank k (Tests 4, loops = 1); see orc_cynical."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    o = _Opts()
+    lib().orc_default_opts(ct.byref(o))
+    o.delta = delta
+    o.max_swaps = max_swaps
+    o.refine_steps = refine_steps
+    I = np.full(r, -1, np.int64)
+    J = np.full(r, -1, np.int64)
+    U = np.zeros((r, r))
+    info = _Info()
+    st = lib().orc_cynical(_p(A), _dtype_code(A), m, n, n, r, k, loops, sweeps, seed, ct.byref(o),
+                           _p(I), _p(J), _p(U), ct.byref(info))
     return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
                      info.min_margin, info.det_log_abs, info.nucleus_rank)
 

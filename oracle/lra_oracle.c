@@ -906,3 +906,95 @@ int orc_fmm_entries(const double *x, int64_t m, const double *y, int64_t n, doub
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Cynical CUR and its combination with C-A loops (Section 1.3, the cynical */
+/* algorithms of Fig. 3; Section 13, Tests 3 and Tests 4 with k = l = 4r).  */
+/*   L: k distinct random columns (stream 0 of `seed`), ascending.           */
+/*   loops = 0 (Tests 3): K: k distinct random rows (stream 5), ascending.   */
+/*   loops >= 1 (Tests 4 for loops = 1): `loops` C-A loops at rank k from L  */
+/*     (column step: K = dominant rows of W[:, L]; row step: L = dominant    */
+/*     columns of W[K, :]), stopping early at a fixed point.                 */
+/*   Then the k x k sketch S = W[K, L]: C-A at rank r on S (orc_ca_cur with  */
+/*   seed + 1, `sweeps` loops), an r x r submatrix of locally maximal volume  */
+/*   in S, mapped back: I = K[I_S], J = L[J_S]; U = W[I, J]^{-1}.            */
+/* The paper's inner routine (Algorithms 1 and 2 of its reference P00) is   */
+/* not given in the paper; C-A on the sketch, which ends in a set that is    */
+/* dominant in its rows and in its columns, stands in for it.  info          */
+/* describes the inner C-A; swaps_total counts both phases.                  */
+/* ------------------------------------------------------------------------ */
+int orc_cynical(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, int k, int loops,
+                int sweeps, uint64_t seed, const orc_opts *opts_in, int64_t *I_out, int64_t *J_out, double *U_out,
+                orc_info *info_out) {
+    orc_opts o;
+    if (opts_in) o = *opts_in; else orc_default_opts(&o);
+    if (o.max_swaps < 0) o.max_swaps = 16 * k;
+    orc_info info = {0, 0, 1, 0, 0, 0, 1.0, 0.0};
+    info.rank_found = r;
+    if (!A || !I_out || !J_out || !U_out || r < 1 || k < r || loops < 0 || sweeps < 1 || m < 1 || n < 1 ||
+        lda < n || (int64_t)k > (m < n ? m : n) || dtype < 0 || dtype > 2 || !(o.delta >= 0.0) ||
+        o.preprocess != 0 || o.init_cols) {
+        if (info_out) *info_out = info;
+        return ORC_EINVAL;
+    }
+    int64_t *K = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    int64_t *L = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    int64_t *Kp = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    int64_t *Lp = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    double *S = (double *)malloc(sizeof(double) * (size_t)k * (size_t)k);
+    int64_t *Is = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
+    int64_t *Js = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
+    int st = ORC_OK;
+    int32_t outer_swaps = 0;
+    orc_draw_distinct(seed, 0, n, k, L);
+    qsort(L, (size_t)k, sizeof(int64_t), cmp_i64);
+    if (loops == 0) {
+        orc_draw_distinct(seed, 5, m, k, K);
+        qsort(K, (size_t)k, sizeof(int64_t), cmp_i64);
+    }
+    for (int s = 0; s < loops; s++) {
+        orc_info oi = {0, 0, 1, 0, 0, 0, 1.0, 0.0};
+        oi.rank_found = k;
+        for (int a = 0; a < k; a++)
+            if (!orc_finite_scan(A, dtype, lda, 0, m, L[a], 1)) { st = ORC_EINVAL; goto done; }
+        st = orc_step(A, dtype, m, n, lda, k, 1, L, &o, K, &oi);
+        if (st == ORC_OK) {
+            for (int a = 0; a < k; a++)
+                if (!orc_finite_scan(A, dtype, lda, K[a], 1, 0, n)) { st = ORC_EINVAL; goto done; }
+            st = orc_step(A, dtype, m, n, lda, k, 0, K, &o, L, &oi);
+        }
+        outer_swaps += oi.swaps_total;
+        if (oi.min_margin < info.min_margin) info.min_margin = oi.min_margin;
+        if (st) {
+            if (st == ORC_ESINGULAR) info.rank_found = oi.rank_found;
+            goto done;
+        }
+        if (s > 0 && !memcmp(K, Kp, sizeof(int64_t) * (size_t)k) && !memcmp(L, Lp, sizeof(int64_t) * (size_t)k))
+            break;
+        memcpy(Kp, K, sizeof(int64_t) * (size_t)k);
+        memcpy(Lp, L, sizeof(int64_t) * (size_t)k);
+    }
+    for (int a = 0; a < k; a++)
+        for (int b = 0; b < k; b++) S[a * k + b] = orc_get(A, dtype, lda, K[a], L[b]);
+    {
+        orc_opts oi = o;
+        oi.max_swaps = opts_in ? opts_in->max_swaps : -1;
+        orc_info ii;
+        st = orc_ca_cur(S, 0, k, k, k, r, sweeps, seed + 1, &oi, Is, Js, U_out, &ii);
+        double mm = info.min_margin;
+        info = ii;
+        if (mm < info.min_margin) info.min_margin = mm;
+        info.swaps_total += outer_swaps;
+        if (st == ORC_OK) {
+            for (int a = 0; a < r; a++) {
+                I_out[a] = K[Is[a]];
+                J_out[a] = L[Js[a]];
+            }
+        }
+    }
+done:
+    free(K); free(L); free(Kp); free(Lp); free(S); free(Is); free(Js);
+    if (st != ORC_OK) info.converged = 0;
+    if (info_out) *info_out = info;
+    return st;
+}
