@@ -72,7 +72,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="time only the headline LRA (skip batched, residual and adjoint lines)")
-    ap.add_argument("--only", choices=["batched", "points", "adjoint", "tall", "residual"], default=None,
+    ap.add_argument("--only", choices=["batched", "points", "cynical", "adjoint", "tall", "residual"], default=None,
                     help="time one secondary line alone and print it (for profiling)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (reference for HBM counters)")
@@ -98,8 +98,8 @@ def main():
     from paper_1710_07946_amd import workloads
 
     lra.load()
-    if args.only in ("batched", "points", "adjoint", "tall"):
-        fn = {"batched": bench_batched, "points": bench_points, "adjoint": bench_adjoint,
+    if args.only in ("batched", "points", "cynical", "adjoint", "tall"):
+        fn = {"batched": bench_batched, "points": bench_points, "cynical": bench_cynical, "adjoint": bench_adjoint,
               "tall": bench_tall}[args.only]
         print(json.dumps({args.only: fn(lra, workloads, torch, np, args)}), flush=True)
         return
@@ -204,6 +204,7 @@ def main():
             "batched_fmm_points": bench_points(lra, workloads, torch, np, args),
             "adjoint_2048": bench_adjoint(lra, workloads, torch, np, args),
             "tall_65536x8192": bench_tall(lra, workloads, torch, np, args),
+            "cynical_20000x20000_r16": bench_cynical(lra, workloads, torch, np, args),
         }
     print(json.dumps(rec), flush=True)
 
@@ -365,6 +366,41 @@ def bench_adjoint(lra, workloads, torch, np, args):
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
         "useful_bytes_per_launch": nbytes,
     }
+
+
+def bench_cynical(lra, workloads, torch, np, args):
+    """Cynical CUR on a 20000 x 20000 FP32 factor-Gaussian rank-16 input
+    (+ N(0, 1e-6^2)): Tests 4 (one C-A loop at rank k = 4r = 64, then the
+    r x r generator inside the 64 x 64 sketch) and Tests 3 (random 64 x 64
+    sketch), beside plain C-A at r = 16 (4 sweeps); relative Frobenius errors
+    from the FP64 residual."""
+    m = n = 20000
+    r, k = 16, 64
+    A = workloads.factor_gaussian_device(m, n, r, 1e-6, 3011, "cuda")
+    reps = max(2, args.steps // 5)
+    rec = {"workload": "20000x20000 fp32 factor-Gaussian rank 16 + N(0,1e-6^2); r=16, k=l=64"}
+
+    def err(out):
+        mom = lra.lra_residual(A, out.I, out.J, out.U).cpu().numpy()
+        return float(np.sqrt(mom[1] / mom[3]))
+
+    for name, loops in (("tests4_one_loop", 1), ("tests3_random_sketch", 0)):
+        out = lra.lra_cur_cynical(A, r, k, loops, 3, 2031)
+        ms = _time_events(torch, lambda: lra.lra_cur_cynical(A, r, k, loops, 3, 2031, out=out), reps, 1)
+        info = out.info()
+        nbytes = 4 * (loops * (m + n) * k + k * k + r * r)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        rec[name] = {"lras_per_s": 1e3 / ms, "ms_per_lra": ms, "status": info["status"],
+                     "team_size": info["team_size"], "rel_fro_err": err(out),
+                     "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+                     "useful_bytes_per_lra": nbytes}
+    out = lra.lra_cur(A, r, 4, 2031)
+    ms = _time_events(torch, lambda: lra.lra_cur(A, r, 4, 2031, out=out), reps, 1)
+    rec["plain_ca_r16_4_sweeps"] = {"lras_per_s": 1e3 / ms, "ms_per_lra": ms, "rel_fro_err": err(out)}
+    del A
+    torch.cuda.empty_cache()
+    return rec
 
 
 def bench_tall(lra, workloads, torch, np, args):

@@ -105,7 +105,26 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
                    int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                    double *U_out, lra_info *info, hipStream_t stream);
 
-/* One block of a batch: the block starts `offset` elements after `base`. */
+/* Cynical CUR (Section 1.3 and Fig. 3: an r x r generator of locally maximal
+ * volume inside a random k x k sketch; Section 13, Tests 3 with loops = 0 and
+ * Tests 4 with loops = 1, k = l = 4r in the paper).
+ *   L   k distinct random columns (stream 0 of `seed`);
+ *   loops = 0: K k distinct random rows (stream 5);
+ *   loops >= 1: that many C-A loops at rank k from L (column step, row step),
+ *               stopping early at a fixed point, give K and L;
+ *   then C-A at rank r on the k x k matrix W[K, L] (seed + 1, `sweeps` loops)
+ *   and U = W[I, J]^{-1} with the same nucleus rules as lra_cur.
+ * 1 <= r <= k <= min(m, n, 64); opts->preprocess and opts->init_cols are not
+ * supported (LRA_EINVAL); opts->max_swaps applies to both ranks (default 16
+ * times the rank).  info describes the rank-r C-A on the sketch, with
+ * swaps_total counting both phases and team_size the team of the rank-k
+ * loops (1 when loops = 0).  Arguments, layout and errors otherwise as for
+ * lra_cur. */
+lra_status lra_cur_cynical(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t k,
+                           int32_t loops, int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out,
+                           int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);
+
+/* One block of a batch: the block starts `offset` elements after `base`. *//* One block of a batch: the block starts `offset` elements after `base`. */
 typedef struct {
     int64_t offset, m, n, lda;
 } lra_block;

@@ -294,6 +294,57 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     return LRA_OK;
 }
 
+lra_status lra_cur_cynical(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t k,
+                           int32_t loops, int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out,
+                           int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    if (!W || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (m < 1 || n < 1 || lda < n || r < 1 || k < r || k > kRMax || k > m || k > n || loops < 0 || sweeps < 1)
+        return LRA_EINVAL;
+    if (m >= ((int64_t)1 << 39) || n >= ((int64_t)1 << 39)) return LRA_EINVAL;  // item ids travel in 40 bits
+    CAConfig ck, cr;
+    lra_opts o, o2;
+    lra_status st = fill_config(opts, k, std::max(loops, 1), &ck, &o);
+    if (st != LRA_OK) return st;
+    if ((st = fill_config(opts, r, sweeps, &cr, &o2)) != LRA_OK) return st;
+    if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    const int max_team = std::min(dinfo.cus, kMaxTeam);
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
+    // without loops only the k x k sketch is solved, by one workgroup; with
+    // loops the rank-k steps use the team rule of lra_cur
+    int team = 1;
+    LdsPlan plan;
+    if (loops == 0) {
+        plan = plan_lds(k, k, k, LRA_PRE_NONE, 0, 1, lds_budget);
+    } else if (o.team_size > 0) {
+        team = std::min(o.team_size, max_team);
+        plan = plan_lds(m, n, k, LRA_PRE_NONE, 0, team, lds_budget);
+    } else {
+        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, n) + 159) / 160));
+        plan = plan_lds(m, n, k, LRA_PRE_NONE, 0, team, lds_budget);
+        while (!plan.fits && team < max_team) {
+            team++;
+            plan = plan_lds(m, n, k, LRA_PRE_NONE, 0, team, lds_budget);
+        }
+    }
+    if (!plan.fits) return LRA_EUNSUPPORTED;
+    ck.panel_bytes = cr.panel_bytes = (int32_t)plan.panel_bytes;
+    TeamWs tws{ws->xw, (uint64_t)dinfo.wall_khz * 2000ull};
+    hipError_t e = lra::launch_cynical(dt, W, m, n, lda, seed, loops, ck, cr, tws, team, plan.dyn_bytes, I_out, J_out,
+                                       U_out, info, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
 lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream) {

@@ -157,7 +157,7 @@ __device__ __forceinline__ int wave_or(int f) {
 struct Smem {
     int64_t Iset[kRMax], Jset[kRMax], Iprev[kRMax], Jprev[kRMax];
     int64_t slot_item[kRMax];
-    int64_t samples[kLMax];
+    int64_t samples[kLMax];  // sketch samples; the cynical CUR keeps its sketch rows and columns here
     uint8_t sgn[kLMax];   // sketch: combined signs of a sampled column's 2^d <= 8 terms
     double L11[kRMax * (kRMax - 1) / 2];
     double wrow[kLMax];
@@ -889,6 +889,18 @@ struct PointSrc {
     }
 };
 
+// The sketch W[K, L] of a dense matrix (cynical CUR): entry (i, j) is
+// W[K[i]][L[j]].
+template <typename T>
+struct IndexedSrc {
+    const T *A;
+    int64_t lda;
+    const int64_t *K, *L;
+    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const {
+        return Elem<T>::load(A, K[i] * lda + L[j]);
+    }
+};
+
 // Gather `cnt` items x r entries of W into the slot-major panel, eight
 // independent loads in flight per thread.  col = true: item it, slot j reads
 // W[it][set[j]]; col = false: W[set[j]][it] (coalesced across items).
@@ -1147,10 +1159,14 @@ __device__ __forceinline__ void nucleus(Smem &sm, double *ws, const Src &src, in
 }
 
 // The whole C-A path for one matrix, executed by every workgroup of a team.
+// imap / jmap (optional) translate the returned row and column ids (a solve
+// on a sketch); swaps_base and team_report fold in an earlier phase.
 template <class Src>
 __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const Src &src, int64_t m,
                                         int64_t n, uint64_t seed, const CAConfig &cfg, int64_t *I_out, int64_t *J_out,
-                                        double *U_out, lra_info *info) {
+                                        double *U_out, lra_info *info, const int64_t *imap = nullptr,
+                                        const int64_t *jmap = nullptr, int32_t swaps_base = 0,
+                                        int32_t team_report = 0) {
     const int tid = threadIdx.x;
     const int r = cfg.r;
     int32_t swaps_total = 0, converged = 1, sweeps_run = 0;
@@ -1244,8 +1260,8 @@ finish:
     if (tm.rank != 0) return;
     const int st = sm.xfail ? LRA_EDEVICE : sm.status;
     if (tid < r) {
-        I_out[tid] = st == LRA_OK ? sm.Iset[tid] : -1;
-        J_out[tid] = st == LRA_OK ? sm.Jset[tid] : -1;
+        I_out[tid] = st == LRA_OK ? (imap ? imap[sm.Iset[tid]] : sm.Iset[tid]) : -1;
+        J_out[tid] = st == LRA_OK ? (jmap ? jmap[sm.Jset[tid]] : sm.Jset[tid]) : -1;
     }
     if (st != LRA_OK)
         for (int e = tid; e < r * r; e += kBlock) U_out[e] = __builtin_nan("");
@@ -1253,10 +1269,10 @@ finish:
         lra_info inf;
         inf.status = st;
         inf.sweeps_run = sweeps_run;
-        inf.swaps_total = swaps_total;
+        inf.swaps_total = swaps_base + swaps_total;
         inf.converged = (st == LRA_OK) ? converged : 0;
         inf.rank_found = sm.rank_found;
-        inf.team_size = tm.size;
+        inf.team_size = team_report ? team_report : tm.size;
         inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
         inf.reserved = 0;
         inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
@@ -1280,6 +1296,104 @@ __global__ void __launch_bounds__(kBlock) ca_team_kernel(const T *A, int64_t m, 
     tm.xw = ws.xw;
     tm.spin_limit = ws.spin_limit;
     ca_solve(tm, sm, dyn, flags, DenseSrc<T>{A, lda}, m, n, seed, cfg, I_out, J_out, U_out, info);
+}
+
+// Cynical CUR (Section 1.3, Fig. 3; Tests 3 and 4 of Section 13): k random
+// columns L (and, with no loops, k random rows K, stream 5), `loops` C-A loops
+// at rank k over the whole team (cfg_k), then workgroup 0 alone runs C-A at
+// rank r on the k x k sketch W[K, L] (cfg_r, seed + 1) and maps its sets back.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) ca_cynical_kernel(const T *A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
+                                                            int32_t loops, CAConfig cfg_k, CAConfig cfg_r, TeamWs ws,
+                                                            int64_t *I_out, int64_t *J_out, double *U_out,
+                                                            lra_info *info) {
+    __shared__ Smem sm;
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    double *dyn = reinterpret_cast<double *>(lds_dyn);
+    uint8_t *flags = lds_dyn + cfg_k.panel_bytes;
+    Team tm;
+    tm.rank = blockIdx.x;
+    tm.size = gridDim.x;
+    tm.epoch = 0;
+    tm.xw = ws.xw;
+    tm.spin_limit = ws.spin_limit;
+    const int tid = threadIdx.x;
+    const int k = cfg_k.r, r = cfg_r.r;
+    const DenseSrc<T> src{A, lda};
+    if (tid == 0) {
+        sm.status = LRA_OK;
+        sm.rank_found = k;
+        sm.xfail = 0;
+    }
+    if (tid < kWave) {
+        draw_distinct_wave(seed, 0, n, k, sm.Jset);
+        __builtin_amdgcn_wave_barrier();
+        sort_set_wave(sm.Jset, k);
+        if (loops == 0) {
+            __builtin_amdgcn_wave_barrier();
+            draw_distinct_wave(seed, 5, m, k, sm.Iset);
+            __builtin_amdgcn_wave_barrier();
+            sort_set_wave(sm.Iset, k);
+        }
+    }
+    __syncthreads();
+    int32_t swaps = 0, converged = 1;
+    for (int s = 0; s < loops; s++) {
+        ca_step(tm, sm, dyn, flags, src, m, n, k, true, sm.Jset, sm.Iset, cfg_k, swaps, converged);
+        if (sm.status != LRA_OK) break;
+        ca_step(tm, sm, dyn, flags, src, m, n, k, false, sm.Iset, sm.Jset, cfg_k, swaps, converged);
+        if (sm.status != LRA_OK) break;
+        bool same = s > 0;
+        for (int j = 0; j < k && same; j++) same = (sm.Iset[j] == sm.Iprev[j]) && (sm.Jset[j] == sm.Jprev[j]);
+        __syncthreads();
+        if (same) break;
+        if (tid < k) {
+            sm.Iprev[tid] = sm.Iset[tid];
+            sm.Jprev[tid] = sm.Jset[tid];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (tm.rank != 0) return;
+    const int team = tm.size;
+    if (sm.status != LRA_OK || sm.xfail) {
+        const int st = sm.xfail ? LRA_EDEVICE : sm.status;
+        if (tid < r) {
+            I_out[tid] = -1;
+            J_out[tid] = -1;
+        }
+        for (int e = tid; e < r * r; e += kBlock) U_out[e] = __builtin_nan("");
+        if (tid == 0 && info) {
+            lra_info inf;
+            inf.status = st;
+            inf.sweeps_run = 0;
+            inf.swaps_total = swaps;
+            inf.converged = 0;
+            inf.rank_found = sm.rank_found;
+            inf.team_size = team;
+            inf.nucleus_rank = 0;
+            inf.reserved = 0;
+            inf.det_log_abs = 0.0;
+            *info = inf;
+        }
+        return;
+    }
+    // the sketch's rows and columns (the inner solve draws no samples)
+    static_assert(kLMax >= 2 * kRMax, "the sketch sets fit in the sample buffer");
+    int64_t *const Kset = sm.samples, *const Lset = sm.samples + kRMax;
+    if (tid < k) {
+        Kset[tid] = sm.Iset[tid];
+        Lset[tid] = sm.Jset[tid];
+    }
+    __syncthreads();
+    Team solo;
+    solo.rank = 0;
+    solo.size = 1;
+    solo.epoch = 0;
+    solo.xw = nullptr;
+    solo.spin_limit = 0;
+    ca_solve(solo, sm, dyn, flags, IndexedSrc<T>{A, lda, Kset, Lset}, k, k, seed + 1, cfg_r, I_out, J_out, U_out,
+             info, Kset, Lset, swaps, team);
 }
 
 template <typename T>
@@ -1390,6 +1504,44 @@ hipError_t launch_team(int dtype, const void *A, int64_t m, int64_t n, int64_t l
 }
 
 template <typename T>
+static hipError_t launch_cynical_t(const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int32_t loops,
+                                   const CAConfig &cfg_k, const CAConfig &cfg_r, const TeamWs &ws, int team,
+                                   size_t dyn_bytes, int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info,
+                                   hipStream_t stream) {
+    auto kern = ca_cynical_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+    (void)e;
+    if (team > 1) {
+        const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
+        hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
+                           stream, ws.xw, words);
+    }
+    const T *Ap = static_cast<const T *>(A);
+    CAConfig ck = cfg_k, cr = cfg_r;
+    TeamWs w = ws;
+    void *args[] = {(void *)&Ap, (void *)&m,  (void *)&n,     (void *)&lda,   (void *)&seed, (void *)&loops,
+                    (void *)&ck, (void *)&cr, (void *)&w,     (void *)&I_out, (void *)&J_out, (void *)&U_out,
+                    (void *)&info};
+    return hipLaunchCooperativeKernel((const void *)kern, dim3(team), dim3(kBlock), args, (unsigned)dyn_bytes, stream);
+}
+
+hipError_t launch_cynical(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int32_t loops,
+                          const CAConfig &cfg_k, const CAConfig &cfg_r, const TeamWs &ws, int team, size_t dyn_bytes,
+                          int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    switch (dtype) {
+    case LRA_F64:
+        return launch_cynical_t<double>(A, m, n, lda, seed, loops, cfg_k, cfg_r, ws, team, dyn_bytes, I_out, J_out,
+                                        U_out, info, stream);
+    case LRA_F32:
+        return launch_cynical_t<float>(A, m, n, lda, seed, loops, cfg_k, cfg_r, ws, team, dyn_bytes, I_out, J_out,
+                                       U_out, info, stream);
+    default:
+        return launch_cynical_t<uint16_t>(A, m, n, lda, seed, loops, cfg_k, cfg_r, ws, team, dyn_bytes, I_out, J_out,
+                                          U_out, info, stream);
+    }
+}
+
+template <typename T>
 static hipError_t launch_batched_t(const void *base, const BlockDesc *blocks, const int32_t *order, int64_t count,
                                    uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
                                    int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos,
@@ -1457,10 +1609,11 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
 size_t static_lds_bytes() {
     static size_t bytes = 0;
     if (bytes == 0) {
-        const void *fns[7] = {(const void *)ca_team_kernel<double>,    (const void *)ca_team_kernel<float>,
-                              (const void *)ca_team_kernel<uint16_t>,  (const void *)ca_batched_kernel<double>,
-                              (const void *)ca_batched_kernel<float>,  (const void *)ca_batched_kernel<uint16_t>,
-                              (const void *)ca_points_kernel};
+        const void *fns[10] = {(const void *)ca_team_kernel<double>,    (const void *)ca_team_kernel<float>,
+                               (const void *)ca_team_kernel<uint16_t>,  (const void *)ca_batched_kernel<double>,
+                               (const void *)ca_batched_kernel<float>,  (const void *)ca_batched_kernel<uint16_t>,
+                               (const void *)ca_points_kernel,          (const void *)ca_cynical_kernel<double>,
+                               (const void *)ca_cynical_kernel<float>,  (const void *)ca_cynical_kernel<uint16_t>};
         size_t mx = sizeof(Smem) + sizeof(int) * kRMax;
         for (const void *f : fns) {
             hipFuncAttributes attr;

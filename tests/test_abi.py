@@ -116,6 +116,28 @@ def test_points_invalid_arguments_rejected_on_host(lib):
     assert call([B(0, 10, 10, 10)], count=0) == lra.LRA_OK
 
 
+def test_cynical_invalid_arguments_rejected_on_host(lib):
+    fake = ct.c_void_p(0x1000)
+    E = lra.LRA_EINVAL
+
+    def call(m=100, n=80, lda=80, r=4, k=16, loops=1, sweeps=2, dt=1, opts=None, W=fake):
+        return lib.lra_cur_cynical(W, dt, m, n, lda, r, k, loops, sweeps, 1, opts, fake, fake, fake, None, None)
+
+    assert call(k=3) == E            # k < r
+    assert call(k=65) == E           # k > 64
+    assert call(m=10, k=16) == E     # k > m
+    assert call(n=12, lda=12) == E   # k > n
+    assert call(loops=-1) == E
+    assert call(sweeps=0) == E
+    assert call(r=0) == E
+    assert call(lda=79) == E
+    assert call(dt=7) == E
+    assert call(W=None) == E
+    o = lra.lra_default_opts()
+    o.preprocess = 1
+    assert call(opts=ct.byref(o)) == E
+
+
 def test_residual_invalid_arguments_rejected_on_host(lib):
     f = ct.c_void_p(0x1000)
     E = lra.LRA_EINVAL
