@@ -72,11 +72,15 @@ def lib():
         L.orc_cur_adjoint.argtypes = [P, P, P, i64, i64, ct.c_int, P, P, P, i64, P, P, P, P]
         L.orc_residual_moments.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, i64, i64, u64, P]
         L.orc_fmm_entries.argtypes = [P, i64, P, i64, P]
+        L.orc_feistel.argtypes = [u64, ct.c_int, i64, i64]
+        L.orc_feistel.restype = i64
+        L.orc_bidiag_column.argtypes = [u64, i64, ct.c_int, i64, P, P, P]
+        L.orc_sketch_bidiag.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
         L.orc_cynical.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P,
                                   P, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
                   "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
-                  "orc_fmm_entries", "orc_cynical"):
+                  "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -352,3 +356,32 @@ def fmm_entries(x: np.ndarray, y: np.ndarray) -> np.ndarray:
     if st != 0:
         raise ValueError("orc_fmm_entries: status %d" % st)
     return K
+
+
+def feistel(seed: int, factor: int, N: int, x: int) -> int:
+    """pi_factor(x): the random permutation of [0, N) of bidiagonal factor `factor` (1-based)."""
+    return int(lib().orc_feistel(seed, factor, N, x))
+
+
+def bidiag_column(seed: int, N: int, q: int, c: int):
+    """Column c of G_q = B_1 P_1 ... B_q P_q as (positions, integer coefficients), ascending."""
+    pos = np.zeros(64, np.int64)
+    coef = np.zeros(64, np.int64)
+    cnt = ct.c_int(0)
+    st = lib().orc_bidiag_column(seed, N, q, c, _p(pos), _p(coef), ct.byref(cnt))
+    if st != 0:
+        raise ValueError("orc_bidiag_column: status %d" % st)
+    return pos[:cnt.value].copy(), coef[:cnt.value].copy()
+
+
+def sketch_bidiag(A: np.ndarray, side: int, q: int, l: int, seed: int):
+    """Sketch with l sampled columns of the bidiagonal-product multiplier (see orc_sketch_bidiag)."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    items = n if side else m
+    Y = np.zeros((items, l))
+    smp = np.zeros(l, np.int64)
+    st = lib().orc_sketch_bidiag(_p(A), _dtype_code(A), m, n, n, side, q, l, seed, _p(Y), _p(smp))
+    if st != 0:
+        raise ValueError("orc_sketch_bidiag: status %d" % st)
+    return Y, smp

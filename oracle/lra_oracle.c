@@ -307,6 +307,110 @@ int orc_sketch(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Quasi-Gaussian multipliers made of random bidiagonal factors (the        */
+/* section on pre-processing with quasi Gaussian matrices, eq. (def11)):    */
+/* G_q = B_1 P_1 B_2 P_2 ... B_q P_q with B_i cyclic bidiagonal (ones on     */
+/* the diagonal, a random sign s_{i,j} at row j, column (j - 1) mod N) and   */
+/* P_i a random permutation.  Readings: P_i e_c = e_{pi_i(c)} with pi_i a   */
+/* four-round Feistel network on [0, 2^b), b = the even bit count with      */
+/* 2^b >= N (at least 2), round function the low b/2 bits of SplitMix64      */
+/* stream 6 at index (4 (i - 1) + round) 2^32 + right half, and cycle       */
+/* walking back into [0, N) (Black and Rogaway, 2002); s_{i,j} = -1 when the */
+/* top bit of stream 7 at index (i - 1) N + j is set, else +1.              */
+/* ------------------------------------------------------------------------ */
+int64_t orc_feistel(uint64_t seed, int factor, int64_t N, int64_t x) {
+    int b = 2;
+    while (((int64_t)1 << b) < N) b += 2;
+    const int half = b / 2;
+    const uint64_t mask = ((uint64_t)1 << half) - 1;
+    uint64_t y = (uint64_t)x;
+    do {
+        uint64_t L = y >> half, R = y & mask;
+        for (int rd = 0; rd < 4; rd++) {
+            const uint64_t key = ((uint64_t)(4 * (factor - 1) + rd) << 32) | R;
+            const uint64_t f = orc_rng_u64(seed, 6, key) & mask;
+            const uint64_t nl = R, nr = L ^ f;
+            L = nl;
+            R = nr;
+        }
+        y = (L << half) | R;
+    } while ((int64_t)y >= N);
+    return (int64_t)y;
+}
+
+/* Column c of G_q: start from e_c and apply B_q P_q first, B_1 P_1 last;   */
+/* B e_p = e_p + s_{(p+1) mod N} e_{(p+1) mod N}.  The terms (position,      */
+/* integer coefficient) come out merged, without zeros, in ascending         */
+/* position order; *cnt <= 2^q.                                              */
+int orc_bidiag_column(uint64_t seed, int64_t N, int q, int64_t c, int64_t *pos, int64_t *coef, int *cnt) {
+    if (!pos || !coef || !cnt || q < 0 || q > 6 || N < 2 || c < 0 || c >= N) return ORC_EINVAL;
+    int k = 1;
+    pos[0] = c;
+    coef[0] = 1;
+    for (int i = q; i >= 1; i--) {
+        int64_t np[64], nc[64];
+        int nk = 0;
+        for (int t = 0; t < k; t++) {
+            const int64_t p = orc_feistel(seed, i, N, pos[t]);
+            const int64_t p1 = (p + 1) % N;
+            const int64_t s = (orc_rng_u64(seed, 7, (uint64_t)((i - 1) * N + p1)) >> 63) ? -1 : 1;
+            np[nk] = p;
+            nc[nk++] = coef[t];
+            np[nk] = p1;
+            nc[nk++] = coef[t] * s;
+        }
+        /* merge equal positions, ascending (insertion sort of <= 64 terms) */
+        for (int a = 1; a < nk; a++) {
+            int64_t kp = np[a], kc = nc[a];
+            int b2 = a - 1;
+            while (b2 >= 0 && np[b2] > kp) { np[b2 + 1] = np[b2]; nc[b2 + 1] = nc[b2]; b2--; }
+            np[b2 + 1] = kp;
+            nc[b2 + 1] = kc;
+        }
+        k = 0;
+        for (int a = 0; a < nk; a++) {
+            if (k > 0 && pos[k - 1] == np[a]) coef[k - 1] += nc[a];
+            else { pos[k] = np[a]; coef[k] = nc[a]; k++; }
+        }
+        int z = 0;
+        for (int a = 0; a < k; a++)
+            if (coef[a] != 0) { pos[z] = pos[a]; coef[z] = coef[a]; z++; }
+        k = z;
+    }
+    *cnt = k;
+    return ORC_OK;
+}
+
+/* Sketch with l sampled columns of G_q (distinct draws, stream 2, in draw  */
+/* order), in the two forms of orc_sketch: side 0, Y = W G_q S (items =     */
+/* rows); side 1, Y = (G_q S)^T W (items = columns), G_q of order m.  Each   */
+/* entry sums coef * w over the column's terms in ascending position order. */
+/* No scale factor (a common factor cannot change a QRP decision).          */
+int orc_sketch_bidiag(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int side, int q, int l,
+                      uint64_t seed, double *Y, int64_t *samples) {
+    if (!A || !Y || !samples || q < 0 || q > 6 || l < 1 || m < 1 || n < 1 || lda < n) return ORC_EINVAL;
+    const int64_t dim = side ? m : n;
+    const int64_t items = side ? n : m;
+    if (dim < 2 || l > dim) return ORC_EINVAL;
+    int st = orc_draw_distinct(seed, 2, dim, l, samples);
+    if (st) return st;
+    int64_t pos[64], coef[64];
+    for (int t = 0; t < l; t++) {
+        int cnt = 0;
+        orc_bidiag_column(seed, dim, q, samples[t], pos, coef, &cnt);
+        for (int64_t it = 0; it < items; it++) {
+            double acc = 0.0;
+            for (int k = 0; k < cnt; k++) {
+                const double w = side ? orc_get(A, dtype, lda, pos[k], it) : orc_get(A, dtype, lda, it, pos[k]);
+                acc += (double)coef[k] * w;
+            }
+            Y[it * l + t] = acc;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Greedy expansion by Householder reflections (App. D, Algorithm alg1tor):  */
 /* the columns of a w x items matrix Z (stored item-major: item it is the    */
 /* w-vector Z[it*w .. it*w+w-1]) are chosen one at a time.  At step g the   */
@@ -587,7 +691,7 @@ int orc_nucleus(const double *G, int r, int refine_steps, double *U, double *log
 typedef struct {
     double delta;
     int32_t max_swaps;
-    int32_t preprocess;   /* 0 none, 1 abridged SRHT */
+    int32_t preprocess;   /* 0 none, 1 abridged SRHT, 2 random bidiagonal factors */
     int32_t ah_depth;
     int32_t ah_samples;
     int32_t refine_steps;
@@ -649,7 +753,7 @@ int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
     info.rank_found = r;
     if (!A || !I_out || !J_out || !U_out || r < 1 || sweeps < 1 || m < 1 || n < 1 || lda < n ||
         (int64_t)r > (m < n ? m : n) || dtype < 0 || dtype > 2 || !(o.delta >= 0.0) ||
-        (o.preprocess != 0 && o.preprocess != 1)) {
+        (o.preprocess != 0 && o.preprocess != 1 && o.preprocess != 2)) {
         if (info_out) *info_out = info;
         return ORC_EINVAL;
     }
@@ -659,7 +763,7 @@ int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
     int64_t *Jp = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
     int st = ORC_OK;
 
-    if (o.preprocess == 1) {
+    if (o.preprocess == 1 || o.preprocess == 2) {
         /* pre-multiplication for m >= n (the paper allows either form when   */
         /* m = n; this one yields the start columns directly)                */
         int side = (m >= n) ? 1 : 0;
@@ -668,7 +772,8 @@ int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
         if (l < r) { st = ORC_EINVAL; goto done; }
         double *Y = (double *)malloc(sizeof(double) * (size_t)items * (size_t)l);
         int64_t *smp = (int64_t *)malloc(sizeof(int64_t) * (size_t)l);
-        st = orc_sketch(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp);
+        st = o.preprocess == 1 ? orc_sketch(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp)
+                               : orc_sketch_bidiag(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp);
         int32_t rk = r;
         if (st == ORC_OK) {
             for (int64_t q = 0; q < items * l; q++)
