@@ -59,16 +59,21 @@ typedef enum {
 
 typedef enum {
     LRA_PRE_NONE = 0,  /* random initial column set (seeded) */
-    LRA_PRE_ASRHT = 1  /* start set from greedy QRP on an abridged SRHT sketch: columns
+    LRA_PRE_ASRHT = 1, /* start set from greedy QRP on an abridged SRHT sketch: columns
                           of M^T W (m >= n, the start column set itself) or rows of
                           W M (m < n, followed by one row step) */
+    LRA_PRE_BIDIAG = 2 /* the same with the quasi-Gaussian multiplier of random
+                          bidiagonal factors G_q = B_1 P_1 ... B_q P_q (eq. (def11),
+                          section on pre-processing with quasi Gaussian matrices),
+                          q = ah_depth <= 6 factors, l = ah_samples sampled columns;
+                          the multiplied dimension must stay below 2^31 */
 } lra_pre;
 
 typedef struct {
     double delta;          /* maxvol stops when every |B_ij| <= 1 + delta; default 0.01 */
     int32_t max_swaps;     /* swap cap per maxvol search; < 0 selects 16 r (default) */
     int32_t preprocess;    /* lra_pre; default LRA_PRE_NONE */
-    int32_t ah_depth;      /* abridged Hadamard recursion depth d; default 3 */
+    int32_t ah_depth;      /* abridged Hadamard recursion depth d, or bidiagonal factor count q; default 3 */
     int32_t ah_samples;    /* sampled multiplier columns l (r <= l <= 256); <= 0 selects 2 r */
     int32_t refine_steps;  /* iterative refinement steps of the nucleus inverse; default 0 */
     int32_t team_size;     /* workgroups cooperating on one LRA; <= 0 chooses automatically */

@@ -33,6 +33,7 @@ struct Workspace {
     BlockDesc *blocks = nullptr;
     int32_t *order = nullptr;
     int64_t block_cap = 0;
+    int32_t *bidiag = nullptr;      // bidiagonal-multiplier column table (kBdTableInts)
     double *sketch = nullptr;       // global sketch panels when they do not fit LDS
     size_t sketch_cap = 0;          // bytes
     void *scratch = nullptr;        // residual / adjoint work arrays
@@ -101,12 +102,17 @@ lra_status fill_config(const lra_opts *opts, int32_t r, int32_t sweeps, CAConfig
     if (opts) o = *opts;
     else lra_default_opts(&o);
     if (!(o.delta >= 0.0) || !std::isfinite(o.delta)) return LRA_EINVAL;
-    if (o.preprocess != LRA_PRE_NONE && o.preprocess != LRA_PRE_ASRHT) return LRA_EINVAL;
+    if (o.preprocess != LRA_PRE_NONE && o.preprocess != LRA_PRE_ASRHT && o.preprocess != LRA_PRE_BIDIAG)
+        return LRA_EINVAL;
     if (o.max_swaps < 0) o.max_swaps = 16 * r;
     if (o.ah_samples <= 0) o.ah_samples = 2 * r;
     if (o.refine_steps < 0 || o.refine_steps > 16) return LRA_EINVAL;
     if (o.preprocess == LRA_PRE_ASRHT) {
         if (o.ah_depth < 0 || o.ah_depth > 20) return LRA_EINVAL;
+        if (o.ah_samples < r || o.ah_samples > kLMax) return LRA_EINVAL;
+    }
+    if (o.preprocess == LRA_PRE_BIDIAG) {
+        if (o.ah_depth < 0 || (1 << o.ah_depth) > lra::kBdTerms) return LRA_EINVAL;
         if (o.ah_samples < r || o.ah_samples > kLMax) return LRA_EINVAL;
     }
     c->r = r;
@@ -120,6 +126,7 @@ lra_status fill_config(const lra_opts *opts, int32_t r, int32_t sweeps, CAConfig
     c->panel_bytes = 0;
     c->init_cols = nullptr;
     c->sketch_ws = nullptr;
+    c->bd_table = nullptr;
     *o_out = o;
     return LRA_OK;
 }
@@ -144,7 +151,7 @@ LdsPlan plan_lds(int64_t m, int64_t n, int r, int pre, int l, int team, size_t b
     // panels are slot-major with the slot stride rounded up to odd
     size_t cells = std::max((size_t)(ipw | 1) * r, (size_t)4 * r * r);
     int64_t flag_items = ipw;
-    if (pre == LRA_PRE_ASRHT) {
+    if (pre == LRA_PRE_ASRHT || pre == LRA_PRE_BIDIAG) {
         p.ipw_s = ((m >= n) ? (n + team - 1) / team : (m + team - 1) / team);
         const size_t sk = (size_t)(p.ipw_s | 1) * l;
         const size_t with = align16(std::max(cells, sk) * sizeof(double)) + align16(std::max(ipw, p.ipw_s));
@@ -204,6 +211,7 @@ void lra_release(void) {
         (void)hipFree(w.blocks);
         (void)hipFree(w.order);
         (void)hipFree(w.sketch);
+        (void)hipFree(w.bidiag);
         (void)hipFree(w.scratch);
     }
     g_ws.clear();
@@ -226,6 +234,10 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
         const int64_t q2 = (int64_t)1 << o.ah_depth;
         const int64_t N = q2 * ((dim + q2 - 1) / q2);
         if (o.ah_samples > N) return LRA_EINVAL;
+    }
+    if (o.preprocess == LRA_PRE_BIDIAG) {
+        const int64_t dim = (m >= n) ? m : n;  // the dimension the multiplier acts on
+        if (dim < 2 || dim > (int64_t)INT32_MAX || o.ah_samples > dim) return LRA_EINVAL;
     }
     if (o.init_cols) {
         if (o.preprocess != LRA_PRE_NONE) return LRA_EINVAL;
@@ -282,6 +294,16 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
             hipSuccess)
             return LRA_EDEVICE;
         cfg.init_cols = ws->init_cols;
+    }
+    if (o.preprocess == LRA_PRE_BIDIAG) {
+        if (!ws->bidiag && hipMalloc(&ws->bidiag, sizeof(int32_t) * lra::kBdTableInts) != hipSuccess)
+            return LRA_ENOMEM;
+        if (lra::launch_bidiag_table(seed, (m >= n) ? m : n, o.ah_depth, o.ah_samples, ws->bidiag, stream) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return LRA_EDEVICE;
+        }
+        cfg.bd_table = ws->bidiag;
     }
     // a team selection normally completes in microseconds; two seconds
     // without the expected word means the launch has failed

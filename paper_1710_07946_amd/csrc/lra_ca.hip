@@ -957,26 +957,144 @@ __device__ __forceinline__ void ca_step(Team &tm, Smem &sm, double *panel, uint8
     __syncthreads();
 }
 
+// ---------------------------------------------------------------- bidiagonal multiplier
+// Quasi-Gaussian multiplier G_q = B_1 P_1 ... B_q P_q (eq. (def11), section on
+// pre-processing with quasi Gaussian matrices): B_i cyclic bidiagonal with
+// ones on the diagonal and a random sign s_{i,j} at row j, column (j-1) mod N;
+// P_i e_c = e_{pi_i(c)}.  pi_i: four Feistel rounds on [0, 2^b) (b the even
+// bit count with 2^b >= N, at least 2), round function the low b/2 bits of
+// SplitMix64 stream 6 at index (4 (i-1) + round) 2^32 + right half, walked
+// back into [0, N) (Black and Rogaway's cycle walking); s_{i,j} = -1 when
+// the top bit of stream 7 at index (i-1) N + j is set.
+__device__ int64_t feistel_perm(uint64_t seed, int factor, int64_t N, int64_t x) {
+    int b = 2;
+    while (((int64_t)1 << b) < N) b += 2;
+    const int half = b / 2;
+    const uint64_t mask = ((uint64_t)1 << half) - 1;
+    uint64_t y = (uint64_t)x;
+    // a cycle of the network through x returns into [0, N) within 2^b steps
+    for (int64_t guard = (int64_t)1 << b; guard > 0; guard--) {
+        uint64_t L = y >> half, R = y & mask;
+#pragma unroll
+        for (int rd = 0; rd < 4; rd++) {
+            const uint64_t f = sm64(seed, 6, ((uint64_t)(4 * (factor - 1) + rd) << 32) | R) & mask;
+            const uint64_t nl = R;
+            R = L ^ f;
+            L = nl;
+        }
+        y = (L << half) | R;
+        if ((int64_t)y < N) return (int64_t)y;
+    }
+    return x;
+}
+
+// Table of the l sampled columns (distinct draws, stream 2, in draw order):
+// for column t its term count, then positions and integer coefficients in
+// ascending position order (equal positions merged, zero terms dropped).
+// One workgroup of 256 threads; each thread expands whole columns.
+__global__ void __launch_bounds__(256) bidiag_table_kernel(uint64_t seed, int64_t N, int q, int l, int32_t *tab) {
+    __shared__ int64_t samples[kLMax];
+    if (threadIdx.x < kWave) draw_distinct_wave(seed, 2, N, l, samples);
+    __syncthreads();
+    int32_t *cnt = tab, *pos_out = tab + kLMax, *coef_out = tab + kLMax + (size_t)kLMax * kBdTerms;
+    for (int t = threadIdx.x; t < l; t += blockDim.x) {
+        int64_t pos[kBdTerms], np[kBdTerms];
+        int32_t coef[kBdTerms], nc[kBdTerms];
+        int k = 1;
+        pos[0] = samples[t];
+        coef[0] = 1;
+        for (int i = q; i >= 1; i--) {
+            int nk = 0;
+            for (int u = 0; u < k; u++) {
+                const int64_t p = feistel_perm(seed, i, N, pos[u]);
+                const int64_t p1 = (p + 1) % N;
+                const int32_t sg = (sm64(seed, 7, (uint64_t)((i - 1) * N + p1)) >> 63) ? -1 : 1;
+                np[nk] = p;
+                nc[nk++] = coef[u];
+                np[nk] = p1;
+                nc[nk++] = coef[u] * sg;
+            }
+            for (int a = 1; a < nk; a++) {  // ascending positions
+                const int64_t kp = np[a];
+                const int32_t kc = nc[a];
+                int b2 = a - 1;
+                while (b2 >= 0 && np[b2] > kp) {
+                    np[b2 + 1] = np[b2];
+                    nc[b2 + 1] = nc[b2];
+                    b2--;
+                }
+                np[b2 + 1] = kp;
+                nc[b2 + 1] = kc;
+            }
+            k = 0;
+            for (int a = 0; a < nk; a++) {
+                if (k > 0 && pos[k - 1] == np[a]) {
+                    coef[k - 1] += nc[a];
+                } else {
+                    pos[k] = np[a];
+                    coef[k] = nc[a];
+                    k++;
+                }
+            }
+            int z = 0;
+            for (int a = 0; a < k; a++)
+                if (coef[a] != 0) {
+                    pos[z] = pos[a];
+                    coef[z] = coef[a];
+                    z++;
+                }
+            k = z;
+        }
+        cnt[t] = k;
+        for (int a = 0; a < k; a++) {
+            pos_out[(size_t)t * kBdTerms + a] = (int32_t)pos[a];
+            coef_out[(size_t)t * kBdTerms + a] = coef[a];
+        }
+    }
+}
+
 // Abridged SRHT sketch of the team's items (Appendix B): for sampled column
 // t = b s + e of D H_{N,d}, Y[item][q] = sqrt(s/l) sum_a W[item][a s + e]
 // D[a s + e] (-1)^{popcount(a & b)} (post-multiplication; pre-multiplication
 // swaps the roles of rows and columns).  Then greedy Householder QRP over the
 // items picks r of them (Algorithm alg1tor); each reflection is applied
 // lazily, fused with the next norm scan.  The chosen items land in out.
+// With `bd` (a bidiagonal-multiplier column table) the sketch entries are the
+// table's signed-integer combinations of W's entries instead.
 template <class Src>
 __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Src &src, int64_t m,
-                                          int64_t n, int r, int side, int d, int l, uint64_t seed, int64_t *out) {
+                                          int64_t n, int r, int side, int d, int l, uint64_t seed, int64_t *out,
+                                          const int32_t *bd) {
     const int tid = threadIdx.x;
     const int64_t dim = side ? m : n;
     const Geo g = geo(tm, side ? n : m);
     const int64_t q2 = (int64_t)1 << d;
     const int64_t s = (dim + q2 - 1) / q2;
     const int64_t N = q2 * s;
+    int bad = 0;
+    if (bd) {
+        // bidiagonal-product multiplier: y = sum over the sampled column's
+        // terms, in ascending position order, of coef * w (no scale)
+        const int32_t *cnt = bd, *bpos = bd + kLMax, *bcoef = bd + kLMax + (size_t)kLMax * kBdTerms;
+        const int tot = g.cnt * l;
+        for (int e = tid; e < tot; e += kBlock) {
+            const int li = e % g.cnt, q = e / g.cnt;
+            const int64_t it = g.base + li;
+            const int c = cnt[q];
+            const int32_t *P = bpos + (size_t)q * kBdTerms, *C = bcoef + (size_t)q * kBdTerms;
+            double acc = 0.0;
+            for (int k = 0; k < c; k++) {
+                const double w = side ? src(P[k], it) : src(it, P[k]);
+                acc += (double)C[k] * w;
+            }
+            if (!isfinite(acc)) bad = 1;
+            panel[q * g.st + li] = acc;
+        }
+    } else {
     if (tid < kWave) draw_distinct_wave(seed, 2, N, l, sm.samples);
     __syncthreads();
     LRA_TR(2, 0);
     const double scale = sqrt((double)s / (double)l);
-    int bad = 0;
     if (q2 <= 8) {
         // per sampled column t = b s + e: the offset e and the signs
         // D[a s + e] (-1)^{popcount(a & b)} of its 2^d terms as a bit mask, so
@@ -1044,6 +1162,7 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
             panel[q * g.st + li] = y;
         }
     }
+    }  // sketch forms
     for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
     LRA_TR(3, 0);
@@ -1186,20 +1305,21 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     LRA_TR(1, 0);
     __syncthreads();
     // ---- start set
-    if (cfg.pre == LRA_PRE_ASRHT) {
+    if (cfg.pre == LRA_PRE_ASRHT || cfg.pre == LRA_PRE_BIDIAG) {
         // pre-multiplication for m >= n (either form is allowed when m = n;
         // this one reads whole rows of W and yields the start columns directly)
         const int side = (m >= n) ? 1 : 0;
+        const int32_t *bd = cfg.pre == LRA_PRE_BIDIAG ? cfg.bd_table : nullptr;
         // the items x l sketch slice lives in LDS when it fits, else in a
         // per-workgroup slice of global memory (touched by this workgroup only)
         // (two call sites so that each copy knows its panel's address space)
         if (cfg.sketch_ws) {
             const int64_t st_s = (((side ? n : m) + tm.size - 1) / tm.size) | 1;
             sketch_qrp(tm, sm, cfg.sketch_ws + (size_t)tm.rank * st_s * cfg.ah_samples, flags, src, m, n, r, side,
-                       cfg.ah_depth, cfg.ah_samples, seed, side ? sm.Jset : sm.Iset);
+                       cfg.ah_depth, cfg.ah_samples, seed, side ? sm.Jset : sm.Iset, bd);
         } else {
             sketch_qrp(tm, sm, dyn, flags, src, m, n, r, side, cfg.ah_depth, cfg.ah_samples, seed,
-                       side ? sm.Jset : sm.Iset);
+                       side ? sm.Jset : sm.Iset, bd);
         }
         if (sm.status != LRA_OK) goto finish;
         if (tid < kWave) sort_set_wave(side ? sm.Jset : sm.Iset, r);
@@ -1501,6 +1621,11 @@ hipError_t launch_team(int dtype, const void *A, int64_t m, int64_t n, int64_t l
         return launch_team_t<uint16_t>(A, m, n, lda, seed, cfg, ws, team, dyn_bytes, I_out, J_out, U_out, info,
                                        stream);
     }
+}
+
+hipError_t launch_bidiag_table(uint64_t seed, int64_t N, int q, int l, int32_t *table, hipStream_t stream) {
+    hipLaunchKernelGGL(bidiag_table_kernel, dim3(1), dim3(256), 0, stream, seed, N, q, l, table);
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -28,7 +28,13 @@ struct CAConfig {
     int32_t panel_bytes;      // offset of the flag bytes inside dynamic LDS
     const int64_t *init_cols; // device copy of the warm-start columns, or null
     double *sketch_ws;        // global sketch panels [team][ipw * l] when they do not fit LDS, else null
+    const int32_t *bd_table;  // bidiagonal start: per sampled column its term count, positions, coefficients
 };
+
+// Terms of one sampled column of the bidiagonal-product multiplier (2^q, q <= 6).
+constexpr int kBdTerms = 64;
+// Table layout: cnt[kLMax], then pos[kLMax][kBdTerms], then coef[kLMax][kBdTerms].
+constexpr size_t kBdTableInts = (size_t)kLMax * (1 + 2 * kBdTerms);
 
 struct TeamWs {
     uint64_t *xw;         // exchange words [2][team][kSlotWords]
@@ -59,6 +65,7 @@ hipError_t launch_points(const double *pts, const PtsDesc *blocks, const int32_t
                          uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
                          int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
 int points_occupancy(size_t dyn_bytes);
+hipError_t launch_bidiag_table(uint64_t seed, int64_t N, int q, int l, int32_t *table, hipStream_t stream);
 hipError_t launch_cynical(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int32_t loops,
                           const CAConfig &cfg_k, const CAConfig &cfg_r, const TeamWs &ws, int team, size_t dyn_bytes,
                           int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);
