@@ -72,6 +72,7 @@ def lib():
         L.orc_cur_adjoint.argtypes = [P, P, P, i64, i64, ct.c_int, P, P, P, i64, P, P, P, P]
         L.orc_residual_moments.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, i64, i64, u64, P]
         L.orc_fmm_entries.argtypes = [P, i64, P, i64, P]
+        L.orc_hadamard_apply.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, u64, P]
         L.orc_feistel.argtypes = [u64, ct.c_int, i64, i64]
         L.orc_feistel.restype = i64
         L.orc_bidiag_column.argtypes = [u64, i64, ct.c_int, i64, P, P, P]
@@ -80,7 +81,8 @@ def lib():
                                   P, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
                   "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
-                  "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag"):
+                  "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag",
+                  "orc_hadamard_apply"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -385,3 +387,16 @@ def sketch_bidiag(A: np.ndarray, side: int, q: int, l: int, seed: int):
     if st != 0:
         raise ValueError("orc_sketch_bidiag: status %d" % st)
     return Y, smp
+
+
+def hadamard_apply(A: np.ndarray, d: int, seed: int) -> np.ndarray:
+    """W' = W D (H_{2^d} (x) I_s) for the pre-processed C-A (see orc_hadamard_apply); m x N."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    q2 = 1 << d
+    N = q2 * ((n + q2 - 1) // q2)
+    Wp = np.zeros((m, N))
+    st = lib().orc_hadamard_apply(_p(A), _dtype_code(A), m, n, n, d, seed, _p(Wp))
+    if st != 0:
+        raise ValueError("orc_hadamard_apply: status %d" % st)
+    return Wp

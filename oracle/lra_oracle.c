@@ -1103,3 +1103,33 @@ done:
     if (info_out) *info_out = info;
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The pre-processed matrix W' = W M of Tests 2 with abridged randomized    */
+/* Hadamard pre-processing (Section 13; Appendix B for the multiplier):     */
+/* M = D (H_{2^d} (x) I_s), N = 2^d s >= n, W zero-padded to N columns, D   */
+/* the Rademacher signs of stream 1 (orc_sign), no scale.  Entry (i, b s + e) */
+/* sums W[i][a s + e] D[a s + e] (-1)^{popcount(a & b)} over a = 0 .. 2^d-1 */
+/* in order.  Wp is m x N row-major.                                        */
+/* ------------------------------------------------------------------------ */
+int orc_hadamard_apply(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int d, uint64_t seed,
+                       double *Wp) {
+    if (!A || !Wp || d < 0 || d > 20 || m < 1 || n < 1 || lda < n) return ORC_EINVAL;
+    const int64_t q2 = (int64_t)1 << d;
+    const int64_t s = (n + q2 - 1) / q2;
+    const int64_t N = q2 * s;
+    for (int64_t i = 0; i < m; i++) {
+        for (int64_t j = 0; j < N; j++) {
+            const int64_t b = j / s, e = j % s;
+            double acc = 0.0;
+            for (int64_t a = 0; a < q2; a++) {
+                const int64_t c = a * s + e;
+                if (c >= n) continue;
+                const double h = (__builtin_popcountll((uint64_t)(a & b)) & 1) ? -1.0 : 1.0;
+                acc += orc_get(A, dtype, lda, i, c) * orc_sign(seed, c) * h;
+            }
+            Wp[i * N + j] = acc;
+        }
+    }
+    return ORC_OK;
+}
