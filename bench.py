@@ -198,6 +198,7 @@ def main():
                          "rel_fro_err_vs_A_sampled": float(np.linalg.norm(A64 - Xg) / np.linalg.norm(A64))}
     if not args.no_secondary:
         rec["bidiag_start"] = bench_bidiag_start(lra, torch, np, A, args)
+        rec["preprocessed_ca"] = bench_preprocessed(lra, torch, np, A, args)
         del A
         torch.cuda.empty_cache()
         rec["secondary"] = {
@@ -222,6 +223,47 @@ def bench_bidiag_start(lra, torch, np, A, args):
     return {"workload": "headline matrix; start from QRP on W^T G_3 S (3 bidiagonal factors, l=100); r=50, 4 sweeps",
             "lras_per_s": 1e3 / ms, "ms_per_lra": ms, "status": info["status"], "sweeps_run": info["sweeps_run"],
             "rel_fro_err": float(np.sqrt(mom[1] / mom[3]))}
+
+
+def bench_preprocessed(lra, torch, np, A, args):
+    """C-A on the pre-processed headline matrix W' = W D (H_8 (x) I_2500)
+    (entries formed on the fly, r = 50, 4 sweeps).  Since M M^T = 8 I, the LRA
+    of W is W'[:, J] U W[I, :]; its error is measured on 2000 sampled rows."""
+    d = 3
+    out = lra.lra_cur_hadamard(A, RANK, SWEEPS, SEED, d)
+    ms = _time_events(torch, lambda: lra.lra_cur_hadamard(A, RANK, SWEEPS, SEED, d, out=out), max(2, args.steps // 5), 1)
+    info = out.info()
+    rows = torch.from_numpy(np.sort(np.random.default_rng(1).choice(M, 2000, replace=False))).cuda()
+    W = A.to(torch.float64)
+    q2, s = 1 << d, (N + (1 << d) - 1) >> d
+    sgn = torch.from_numpy(np.array([oracle_free_sign(SEED, c) for c in range(N)])).cuda()
+    Jh = out.J.cpu().numpy()
+    cols = []
+    for j in Jh:
+        b, e = divmod(int(j), s)
+        acc = torch.zeros(len(rows), dtype=torch.float64, device="cuda")
+        for a in range(q2):
+            c = a * s + e
+            if c < N:
+                h = -1.0 if bin(a & b).count("1") & 1 else 1.0
+                acc += W[rows, c] * sgn[c] * h
+        cols.append(acc)
+    Cp = torch.stack(cols, 1)
+    E = W[rows] - Cp @ out.U @ W[out.I]
+    err = float(torch.linalg.norm(E) / torch.linalg.norm(W[rows]))
+    return {"workload": "headline matrix pre-processed by D (H_8 kron I_2500), entries on the fly; r=50, 4 sweeps",
+            "lras_per_s": 1e3 / ms, "ms_per_lra": ms, "status": info["status"], "team_size": info["team_size"],
+            "sweeps_run": info["sweeps_run"], "rel_fro_err_sampled_2000_rows": err}
+
+
+def oracle_free_sign(seed, c):
+    """The Rademacher sign of column c (SplitMix64 stream 1, the multiplier's D), for the error check."""
+    mask = (1 << 64) - 1
+    z = (seed + 0x9E3779B97F4A7C15 * ((1 << 40) + c + 1)) & mask
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+    z ^= z >> 31
+    return -1.0 if z >> 63 else 1.0
 
 
 def _time_events(torch, fn, steps, warmup):

@@ -110,6 +110,24 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
                    int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                    double *U_out, lra_info *info, hipStream_t stream);
 
+/* C-A CUR of the pre-processed matrix W' = W M (Section 13: Tests 2 on inputs
+ * multiplied by an abridged randomized Hadamard matrix; Appendix B for the
+ * multiplier).  M = D (H_{2^d} (x) I_s) has order N = 2^d s, s = ceil(n / 2^d)
+ * (W is zero-padded to N columns), D = diag of the Rademacher signs of
+ * SplitMix64 stream 1 of `seed` (the signs of LRA_PRE_ASRHT), H_{2^d} the
+ * Sylvester-Hadamard matrix, no scale: entry (i, b s + e) of W' is the sum
+ * over a = 0 .. 2^d - 1 (in that order, a s + e < n) of
+ * W[i][a s + e] D[a s + e] (-1)^{popcount(a & b)}.  The entries are formed on
+ * the fly; W' is never stored.  Returns I (rows of W' = rows of W), J
+ * (columns of W', in [0, N)) and U for W' ~ W'[:, J] U W'[I, :]; since
+ * M M^T = 2^d I, the LRA of W is W ~ W'[:, J] U W'[I, :] M^T / 2^d.
+ *   0 <= d <= 6; 1 <= r <= min(m, n, 64); opts->preprocess and
+ *   opts->init_cols are not supported (LRA_EINVAL).  Start set, sweeps,
+ *   outputs and errors otherwise as lra_cur on an m x N matrix. */
+lra_status lra_cur_hadamard(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
+                            int32_t sweeps, uint64_t seed, int32_t d, const lra_opts *opts, int64_t *I_out,
+                            int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);
+
 /* Cynical CUR (Section 1.3 and Fig. 3: an r x r generator of locally maximal
  * volume inside a random k x k sketch; Section 13, Tests 3 with loops = 0 and
  * Tests 4 with loops = 1, k = l = 4r in the paper).

@@ -86,6 +86,9 @@ def load() -> ct.CDLL:
         L.lra_cur_cynical.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, i32, i32, ct.c_uint64,
                                       ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_cynical.restype = ct.c_int
+        L.lra_cur_hadamard.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, ct.c_uint64, i32,
+                                       ct.POINTER(lra_opts), P, P, P, P, P]
+        L.lra_cur_hadamard.restype = ct.c_int
         L.lra_residual.argtypes = [P, ct.c_int, i64, i64, i64, i32, P, P, P, i32, i32, ct.c_uint64, i32, P, P]
         L.lra_residual.restype = ct.c_int
         L.lra_cur_adjoint.argtypes = [i64, i64, i64, i32, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
@@ -206,6 +209,31 @@ def lra_cur(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps
     del keep
     if st != LRA_OK:
         raise LraError(st, "lra_cur")
+    return out
+
+
+def lra_cur_hadamard(A, r: int, sweeps: int, seed: int, d: int, *, delta: float = 0.01, max_swaps: int = -1,
+                     refine_steps: int = 0, team_size: int = 0, out: CurOut | None = None, stream=None) -> CurOut:
+    """C-A CUR of the pre-processed matrix W' = W D (H_{2^d} (x) I_s) (m x N, N the
+    multiple of 2^d at or above n), its entries formed on the fly; J indexes the
+    columns of W'.  Asynchronous like ``lra_cur``."""
+    torch = _torch()
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor with unit column stride")
+    m, n = A.shape
+    dev = A.device
+    if out is None:
+        out = CurOut(torch.empty(r, dtype=torch.int64, device=dev), torch.empty(r, dtype=torch.int64, device=dev),
+                     torch.empty((r, r), dtype=torch.float64, device=dev),
+                     torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, team_size, None)
+    st = load().lra_cur_hadamard(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, sweeps,
+                                 ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), d, ct.byref(o), ct.c_void_p(out.I.data_ptr()),
+                                 ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
+                                 ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
+    del keep
+    if st != LRA_OK:
+        raise LraError(st, "lra_cur_hadamard")
     return out
 
 

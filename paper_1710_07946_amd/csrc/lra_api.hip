@@ -316,6 +316,54 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     return LRA_OK;
 }
 
+lra_status lra_cur_hadamard(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
+                            int32_t sweeps, uint64_t seed, int32_t d, const lra_opts *opts, int64_t *I_out,
+                            int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    if (!W || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (d < 0 || d > 6 || m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n || sweeps < 1)
+        return LRA_EINVAL;
+    const int64_t q2 = (int64_t)1 << d;
+    const int64_t N = q2 * ((n + q2 - 1) / q2);  // order of the multiplier
+    if (m >= ((int64_t)1 << 39) || N >= ((int64_t)1 << 39)) return LRA_EINVAL;  // item ids travel in 40 bits
+    CAConfig cfg;
+    lra_opts o;
+    lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
+    if (st != LRA_OK) return st;
+    if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    const int max_team = std::min(dinfo.cus, kMaxTeam);
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
+    int team;
+    LdsPlan plan;
+    if (o.team_size > 0) {
+        team = std::min(o.team_size, max_team);
+        plan = plan_lds(m, N, r, LRA_PRE_NONE, 0, team, lds_budget);
+    } else {
+        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, N) + 159) / 160));
+        plan = plan_lds(m, N, r, LRA_PRE_NONE, 0, team, lds_budget);
+        while (!plan.fits && team < max_team) {
+            team++;
+            plan = plan_lds(m, N, r, LRA_PRE_NONE, 0, team, lds_budget);
+        }
+    }
+    if (!plan.fits) return LRA_EUNSUPPORTED;
+    cfg.panel_bytes = (int32_t)plan.panel_bytes;
+    TeamWs tws{ws->xw, (uint64_t)dinfo.wall_khz * 2000ull};
+    hipError_t e = lra::launch_hadamard(dt, W, m, n, lda, d, seed, cfg, tws, team, plan.dyn_bytes, I_out, J_out, U_out,
+                                        info, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
 lra_status lra_cur_cynical(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t k,
                            int32_t loops, int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out,
                            int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {

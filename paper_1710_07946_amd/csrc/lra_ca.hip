@@ -901,7 +901,33 @@ struct IndexedSrc {
     }
 };
 
-// Gather `cnt` items x r entries of W into the slot-major panel, eight
+// Entries of the pre-processed matrix W' = W M (Section 13, Tests 2 with
+// abridged randomized Hadamard pre-processing): M = D (H_{2^d} (x) I_s) of
+// order N = 2^d s >= n, D the Rademacher signs of SplitMix64 stream 1 (those
+// of the abridged SRHT), W zero-padded to N columns.  Entry (i, b s + e) is
+// the sum over a = 0 .. 2^d - 1 of +-W[i][a s + e] (sign D[a s + e]
+// (-1)^{popcount(a & b)}), in that order; nothing of W' is stored.
+template <typename T>
+struct HadamardSrc {
+    const T *A;
+    int64_t lda, n, s;
+    int q2;
+    uint64_t seed;
+    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const {
+        const int64_t b = j / s, e = j - b * s;
+        double acc = 0.0;
+        for (int a = 0; a < q2; a++) {
+            const int64_t c = a * s + e;
+            if (c >= n) break;  // c grows with a
+            const double w = Elem<T>::load(A, i * lda + c);
+            const bool neg = ((sm64(seed, 1, (uint64_t)c) >> 63) != 0) != ((__popcll((uint64_t)(a & b)) & 1) != 0);
+            acc += neg ? -w : w;
+        }
+        return acc;
+    }
+};
+
+// Gather `cnt` items x r entries of W into the slot-major panel, eight// Gather `cnt` items x r entries of W into the slot-major panel, eight
 // independent loads in flight per thread.  col = true: item it, slot j reads
 // W[it][set[j]]; col = false: W[set[j]][it] (coalesced across items).
 template <class Src>
@@ -1418,6 +1444,27 @@ __global__ void __launch_bounds__(kBlock) ca_team_kernel(const T *A, int64_t m, 
     ca_solve(tm, sm, dyn, flags, DenseSrc<T>{A, lda}, m, n, seed, cfg, I_out, J_out, U_out, info);
 }
 
+// C-A CUR of the pre-processed matrix W' = W M (HadamardSrc), m x N.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) ca_hadamard_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int d,
+                                                             uint64_t seed, CAConfig cfg, TeamWs ws, int64_t *I_out,
+                                                             int64_t *J_out, double *U_out, lra_info *info) {
+    __shared__ Smem sm;
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    double *dyn = reinterpret_cast<double *>(lds_dyn);
+    uint8_t *flags = lds_dyn + cfg.panel_bytes;
+    Team tm;
+    tm.rank = blockIdx.x;
+    tm.size = gridDim.x;
+    tm.epoch = 0;
+    tm.xw = ws.xw;
+    tm.spin_limit = ws.spin_limit;
+    const int q2 = 1 << d;
+    const int64_t s = (n + q2 - 1) / q2;
+    ca_solve(tm, sm, dyn, flags, HadamardSrc<T>{A, lda, n, s, q2, seed}, m, (int64_t)q2 * s, seed, cfg, I_out, J_out,
+             U_out, info);
+}
+
 // Cynical CUR (Section 1.3, Fig. 3; Tests 3 and 4 of Section 13): k random
 // columns L (and, with no loops, k random rows K, stream 5), `loops` C-A loops
 // at rank k over the whole team (cfg_k), then workgroup 0 alone runs C-A at
@@ -1623,6 +1670,42 @@ hipError_t launch_team(int dtype, const void *A, int64_t m, int64_t n, int64_t l
     }
 }
 
+template <typename T>
+static hipError_t launch_hadamard_t(const void *A, int64_t m, int64_t n, int64_t lda, int d, uint64_t seed,
+                                    const CAConfig &cfg, const TeamWs &ws, int team, size_t dyn_bytes, int64_t *I_out,
+                                    int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    auto kern = ca_hadamard_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+    (void)e;
+    if (team > 1) {
+        const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
+        hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
+                           stream, ws.xw, words);
+    }
+    const T *Ap = static_cast<const T *>(A);
+    CAConfig c = cfg;
+    TeamWs w = ws;
+    void *args[] = {(void *)&Ap,   (void *)&m,     (void *)&n,     (void *)&lda,  (void *)&d,   (void *)&seed,
+                    (void *)&c,    (void *)&w,     (void *)&I_out, (void *)&J_out, (void *)&U_out, (void *)&info};
+    return hipLaunchCooperativeKernel((const void *)kern, dim3(team), dim3(kBlock), args, (unsigned)dyn_bytes, stream);
+}
+
+hipError_t launch_hadamard(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int d, uint64_t seed,
+                           const CAConfig &cfg, const TeamWs &ws, int team, size_t dyn_bytes, int64_t *I_out,
+                           int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    switch (dtype) {
+    case LRA_F64:
+        return launch_hadamard_t<double>(A, m, n, lda, d, seed, cfg, ws, team, dyn_bytes, I_out, J_out, U_out, info,
+                                         stream);
+    case LRA_F32:
+        return launch_hadamard_t<float>(A, m, n, lda, d, seed, cfg, ws, team, dyn_bytes, I_out, J_out, U_out, info,
+                                        stream);
+    default:
+        return launch_hadamard_t<uint16_t>(A, m, n, lda, d, seed, cfg, ws, team, dyn_bytes, I_out, J_out, U_out,
+                                           info, stream);
+    }
+}
+
 hipError_t launch_bidiag_table(uint64_t seed, int64_t N, int q, int l, int32_t *table, hipStream_t stream) {
     hipLaunchKernelGGL(bidiag_table_kernel, dim3(1), dim3(256), 0, stream, seed, N, q, l, table);
     return hipGetLastError();
@@ -1734,11 +1817,13 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
 size_t static_lds_bytes() {
     static size_t bytes = 0;
     if (bytes == 0) {
-        const void *fns[10] = {(const void *)ca_team_kernel<double>,    (const void *)ca_team_kernel<float>,
-                               (const void *)ca_team_kernel<uint16_t>,  (const void *)ca_batched_kernel<double>,
-                               (const void *)ca_batched_kernel<float>,  (const void *)ca_batched_kernel<uint16_t>,
-                               (const void *)ca_points_kernel,          (const void *)ca_cynical_kernel<double>,
-                               (const void *)ca_cynical_kernel<float>,  (const void *)ca_cynical_kernel<uint16_t>};
+        const void *fns[13] = {(const void *)ca_team_kernel<double>,     (const void *)ca_team_kernel<float>,
+                               (const void *)ca_team_kernel<uint16_t>,   (const void *)ca_batched_kernel<double>,
+                               (const void *)ca_batched_kernel<float>,   (const void *)ca_batched_kernel<uint16_t>,
+                               (const void *)ca_points_kernel,           (const void *)ca_cynical_kernel<double>,
+                               (const void *)ca_cynical_kernel<float>,   (const void *)ca_cynical_kernel<uint16_t>,
+                               (const void *)ca_hadamard_kernel<double>, (const void *)ca_hadamard_kernel<float>,
+                               (const void *)ca_hadamard_kernel<uint16_t>};
         size_t mx = sizeof(Smem) + sizeof(int) * kRMax;
         for (const void *f : fns) {
             hipFuncAttributes attr;

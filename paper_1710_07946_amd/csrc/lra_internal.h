@@ -65,6 +65,9 @@ hipError_t launch_points(const double *pts, const PtsDesc *blocks, const int32_t
                          uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
                          int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
 int points_occupancy(size_t dyn_bytes);
+hipError_t launch_hadamard(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int d, uint64_t seed,
+                           const CAConfig &cfg, const TeamWs &ws, int team, size_t dyn_bytes, int64_t *I_out,
+                           int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);
 hipError_t launch_bidiag_table(uint64_t seed, int64_t N, int q, int l, int32_t *table, hipStream_t stream);
 hipError_t launch_cynical(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int32_t loops,
                           const CAConfig &cfg_k, const CAConfig &cfg_r, const TeamWs &ws, int team, size_t dyn_bytes,
