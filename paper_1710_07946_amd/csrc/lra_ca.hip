@@ -1139,32 +1139,50 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
         }
         __syncthreads();
         if (g.cnt > 0) {
-            // thread -> (item, sample) without division: step by kBlock entries
+            // thread -> (item, sample) without division: step by kBlock
+            // entries, four entries per round so that 32 loads are in flight;
+            // loads past the end read a valid entry and are discarded
+            constexpr int kNP = 4;
             int li = tid % g.cnt, q = tid / g.cnt;
             const int dli = kBlock % g.cnt, dq = kBlock / g.cnt;
             while (q < l) {
-                const int64_t it = g.base + li;
-                const int64_t ee = sm.samples[q];
-                const uint32_t mask = sm.sgn[q];
-                double w[8];
+                int pli[kNP], pq[kNP];
 #pragma unroll
-                for (int a = 0; a < 8; a++) {
-                    const int64_t c = a * s + ee;
-                    w[a] = 0.0;
-                    if (a < q2 && c < dim) w[a] = side ? src(c, it) : src(it, c);
+                for (int p = 0; p < kNP; p++) {
+                    pli[p] = li;
+                    pq[p] = q;
+                    li += dli;
+                    q += dq;
+                    if (li >= g.cnt) {
+                        li -= g.cnt;
+                        q++;
+                    }
                 }
-                double acc = 0.0;
+                double w[kNP][8];
 #pragma unroll
-                for (int a = 0; a < 8; a++)
-                    if (a < q2 && a * s + ee < dim) acc += ((mask >> a) & 1u) ? -w[a] : w[a];
-                const double y = scale * acc;
-                if (!isfinite(y)) bad = 1;
-                panel[q * g.st + li] = y;
-                li += dli;
-                q += dq;
-                if (li >= g.cnt) {
-                    li -= g.cnt;
-                    q++;
+                for (int p = 0; p < kNP; p++) {
+                    const bool on = pq[p] < l;
+                    const int64_t it = g.base + pli[p];
+                    const int64_t ee = sm.samples[on ? pq[p] : 0];
+#pragma unroll
+                    for (int a = 0; a < 8; a++) {
+                        const int64_t c = a * s + ee;
+                        const int64_t cc = (a < q2 && c < dim) ? c : ee;  // ee < dim always
+                        w[p][a] = side ? src(cc, it) : src(it, cc);
+                    }
+                }
+#pragma unroll
+                for (int p = 0; p < kNP; p++) {
+                    if (pq[p] >= l) continue;
+                    const int64_t ee = sm.samples[pq[p]];
+                    const uint32_t mask = sm.sgn[pq[p]];
+                    double acc = 0.0;
+#pragma unroll
+                    for (int a = 0; a < 8; a++)
+                        if (a < q2 && a * s + ee < dim) acc += ((mask >> a) & 1u) ? -w[p][a] : w[p][a];
+                    const double y = scale * acc;
+                    if (!isfinite(y)) bad = 1;
+                    panel[pq[p] * g.st + pli[p]] = y;
                 }
             }
         }
