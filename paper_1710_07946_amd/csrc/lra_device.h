@@ -60,8 +60,11 @@ __device__ __forceinline__ void draw_distinct_wave(uint64_t seed, uint64_t strea
         int ok = !(rem != 0 && u >= lim);
         int64_t v = (int64_t)(u % un);
         for (int t = 0; t < kWave && got < k; t++) {
-            int okt = __shfl(ok, t);
-            int64_t vt = __shfl(v, t);
+            // candidate t of this round, read out of its lane (t is uniform)
+            const int okt = __builtin_amdgcn_readlane(ok, t);
+            const int64_t vt = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)((uint64_t)v >> 32), t)
+                                          << 32) |
+                                         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, t));
             if (!okt) continue;
             bool dup = (lane < got && m0 == vt) || (lane + 64 < got && m1 == vt) ||
                        (lane + 128 < got && m2 == vt) || (lane + 192 < got && m3 == vt);
