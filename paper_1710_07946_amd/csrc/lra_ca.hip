@@ -767,9 +767,15 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             const int j = k + 1 + tid;
             panel[j * st + li] -= panel[(k - 1) * st + li] * wp[j];
         }
-        if (tid < r) sm.wprev[k & 1][tid] = sm.wrow[tid];
         pk = sm.wrow[k];
-        __syncthreads();
+        if (ahead) {
+            // the look-ahead keeps the pivot row for the next overlap, and the
+            // fix-up above must land before the next scan reads column k+1
+            if (tid < r) sm.wprev[k & 1][tid] = sm.wrow[tid];
+            __syncthreads();
+        }
+        // (eager: the next scan touches only entries its own lanes own, and
+        // the next selection's first barrier orders everything shared)
 #ifdef LRA_TRACE
         if (tid == 0) sm.t_loop[1] += wall_clock64() - q2;
 #endif
