@@ -79,10 +79,14 @@ def lib():
         L.orc_sketch_bidiag.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
         L.orc_cynical.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P,
                                   P, P]
+        L.orc_pinv_trunc.argtypes = [P, ct.c_int, ct.c_int, ct.c_int, P, P, P]
+        L.orc_projective_select.argtypes = [P, i64, ct.c_int, ct.c_int, ct.c_int, P, P, P]
+        L.orc_projective_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64,
+                                         P, P, P, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
                   "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
                   "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag",
-                  "orc_hadamard_apply"):
+                  "orc_hadamard_apply", "orc_pinv_trunc", "orc_projective_select", "orc_projective_cur"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -201,6 +205,30 @@ def pinv_jacobi(G: np.ndarray, rtol: float = 1e-14):
     return st, X, rk.value
 
 
+def pinv_trunc(G: np.ndarray, r: int):
+    """Pseudo-inverse of the rank-r SVD truncation of a k x l generator:
+    (status, X (l x k), kept rank, log of the product of the kept sigmas)."""
+    G = np.ascontiguousarray(G, np.float64)
+    k, l = G.shape
+    X = np.zeros((l, k))
+    rk = ct.c_int(0)
+    lv = ct.c_double(0.0)
+    st = lib().orc_pinv_trunc(_p(G), k, l, r, _p(X), ct.byref(rk), ct.byref(lv))
+    return st, X, rk.value, lv.value
+
+
+def projective_select(P: np.ndarray, r: int, k: int):
+    """k items (rows of P) chosen for r-projective volume: (status, items in
+    selection order, rank reached, min margin)."""
+    P = np.ascontiguousarray(P, np.float64)
+    items, w = P.shape
+    out = np.full(k, -1, np.int64)
+    rank = ct.c_int32(0)
+    mm = ct.c_double(1.0)
+    st = lib().orc_projective_select(_p(P), items, w, r, k, _p(out), ct.byref(rank), ct.byref(mm))
+    return st, out, rank.value, mm.value
+
+
 def nucleus(G: np.ndarray, refine_steps: int = 0):
     """The nucleus routine of the C-A driver: (status, U, log|det G|, kept rank)."""
     G = np.ascontiguousarray(G, np.float64)
@@ -286,6 +314,22 @@ def cynical(A: np.ndarray, r: int, k: int, loops: int, sweeps: int, seed: int, d
     info = _Info()
     st = lib().orc_cynical(_p(A), _dtype_code(A), m, n, n, r, k, loops, sweeps, seed, ct.byref(o),
                            _p(I), _p(J), _p(U), ct.byref(info))
+    return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
+                     info.min_margin, info.det_log_abs, info.nucleus_rank)
+
+
+def projective_cur(A: np.ndarray, r: int, k: int, l: int, sweeps: int, seed: int) -> CurResult:
+    """C-A with k x l generators of large r-projective volume and the
+    canonical nucleus (see orc_projective_cur): I has k rows, J l columns,
+    U is l x k."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    I = np.full(k, -1, np.int64)
+    J = np.full(l, -1, np.int64)
+    U = np.zeros((l, k))
+    info = _Info()
+    st = lib().orc_projective_cur(_p(A), _dtype_code(A), m, n, n, r, k, l, sweeps, seed, _p(I), _p(J), _p(U),
+                                  ct.byref(info))
     return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
                      info.min_margin, info.det_log_abs, info.nucleus_rank)
 

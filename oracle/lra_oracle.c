@@ -1133,3 +1133,233 @@ int orc_hadamard_apply(const void *A, int dtype, int64_t m, int64_t n, int64_t l
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Truncated pseudo-inverse of a k x l generator (Section 3, Algorithm      */
+/* algcnnncl: U = W_{k,l,r}^+, the pseudo-inverse of the rank-r SVD          */
+/* truncation).  One-sided Jacobi (Hestenes) SVD of G (k x l, row-major):   */
+/* its l columns are rotated in round-robin pair order (orc_pair, a dummy   */
+/* position for odd l) until a sweep rotates nothing (at most 60); a pair   */
+/* is rotated unless |a_p . a_q| <= 1e-15 sqrt(|a_p|^2 |a_q|^2).  Then      */
+/* sigma_j = |a_j|; the kept set is the r largest sigma_j (ties to the      */
+/* lower j) among those above 1e-14 max sigma; X (l x k, row-major) =       */
+/* sum over kept j (increasing) of v_j a_j^T / sigma_j^2.  *rank_out gets   */
+/* the number kept and *logvol the sum of their logs, log v_{2,r}(G) of     */
+/* eq. (eqvol) when all r are kept.                                         */
+/* ------------------------------------------------------------------------ */
+int orc_pinv_trunc(const double *G, int k, int l, int r, double *X, int *rank_out, double *logvol) {
+    if (!G || !X || k < 1 || l < 1 || r < 1 || r > (k < l ? k : l)) return ORC_EINVAL;
+    double *A = (double *)malloc(sizeof(double) * (size_t)k * (size_t)l);
+    double *V = (double *)calloc((size_t)l * (size_t)l, sizeof(double));
+    double *sg = (double *)malloc(sizeof(double) * (size_t)l);
+    char *keep = (char *)calloc((size_t)l, 1);
+    memcpy(A, G, sizeof(double) * (size_t)k * (size_t)l);
+    for (int j = 0; j < l; j++) V[j * l + j] = 1.0;
+    const int lp = l + (l & 1);
+    for (int sweep = 0; sweep < 60 && l > 1; sweep++) {
+        int rotated = 0;
+        for (int t = 0; t < lp - 1; t++) {
+            for (int s = 0; s < lp / 2; s++) {
+                int pc, qc;
+                orc_pair(t, s, lp, &pc, &qc);
+                if (qc >= l) continue;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = 0; i < k; i++) {
+                    al += A[i * l + pc] * A[i * l + pc];
+                    be += A[i * l + qc] * A[i * l + qc];
+                    ga += A[i * l + pc] * A[i * l + qc];
+                }
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                double ze = (be - al) / (2.0 * ga);
+                double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                for (int i = 0; i < k; i++) {
+                    double x = A[i * l + pc], y = A[i * l + qc];
+                    A[i * l + pc] = c * x - sn * y;
+                    A[i * l + qc] = sn * x + c * y;
+                }
+                for (int i = 0; i < l; i++) {
+                    double x = V[i * l + pc], y = V[i * l + qc];
+                    V[i * l + pc] = c * x - sn * y;
+                    V[i * l + qc] = sn * x + c * y;
+                }
+                rotated = 1;
+            }
+        }
+        if (!rotated) break;
+    }
+    double smax = 0.0;
+    for (int j = 0; j < l; j++) {
+        double s2 = 0.0;
+        for (int i = 0; i < k; i++) s2 += A[i * l + j] * A[i * l + j];
+        sg[j] = sqrt(s2);
+        if (sg[j] > smax) smax = sg[j];
+    }
+    int kept = 0;
+    double lv = 0.0;
+    for (int j = 0; j < l; j++) {
+        int above = 0;  /* sigma values ranked before j */
+        for (int i = 0; i < l; i++)
+            if (sg[i] > sg[j] || (sg[i] == sg[j] && i < j)) above++;
+        if (above < r && sg[j] > 1e-14 * smax) { keep[j] = 1; kept++; lv += log(sg[j]); }
+    }
+    for (int a = 0; a < l; a++)
+        for (int b = 0; b < k; b++) {
+            double acc = 0.0;
+            for (int j = 0; j < l; j++)
+                if (keep[j]) acc += V[a * l + j] * A[b * l + j] / (sg[j] * sg[j]);
+            X[a * k + b] = acc;
+        }
+    if (rank_out) *rank_out = kept;
+    if (logvol) *logvol = lv;
+    free(A); free(V); free(sg); free(keep);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Greedy choice of k items whose vectors span a submatrix of large         */
+/* r-projective volume (Section "Extension of the maximization of the       */
+/* r-projective volume", Algorithm algprjvlm transposed as its remark       */
+/* reprvtov allows; Appendix, Algorithms alg1tor and algrup as its          */
+/* black box).  P (items x w, item-major) holds one w-vector per item: a    */
+/* row of W[:, J] in a column step, a column of W[I, :] in a row step.      */
+/*  1. Rank-revealing QRP of the w x items matrix P^T, truncated at r: r    */
+/*     greedy Householder steps (orc_qrp).  Its first r rows R' (r x items) */
+/*     are Q_r^T P^T, Q_r the first r columns of the orthogonal factor.     */
+/*  2. Algorithm alg1tor on R': r greedy Householder steps over all items.  */
+/*  3. Algorithm algrup: for g = r .. k-1 add the unchosen item y (column   */
+/*     of R') maximising y^T (S S^T)^{-1} y, S = R'[:, chosen]: by eq. (eqb) */
+/*     the factor 1 + y^T (S S^T)^{-1} y multiplies v_2(S)^2 when y joins.   */
+/*     The quadratic form is recomputed at every step (Cholesky factor of    */
+/*     S S^T, one forward solve per item); ties to the lowest item.          */
+/* out[0..k-1] receives the items in selection order.  Every decision's      */
+/* margin (gap to the runner-up, relative) goes into *min_margin.  Status:   */
+/* singular when step 1 or 2 meets a zero remaining norm (*rank = step).     */
+/* ------------------------------------------------------------------------ */
+int orc_projective_select(const double *P, int64_t items, int w, int r, int k, int64_t *out, int32_t *rank,
+                          double *min_margin) {
+    if (!P || !out || w < 1 || r < 1 || r > w || k < r || (int64_t)k > items) return ORC_EINVAL;
+    double *Z = (double *)malloc(sizeof(double) * (size_t)items * (size_t)w);
+    double *Rp = (double *)malloc(sizeof(double) * (size_t)items * (size_t)r);
+    double *Y = (double *)malloc(sizeof(double) * (size_t)items * (size_t)r);
+    double *Ch = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+    double *z = (double *)malloc(sizeof(double) * (size_t)r);
+    char *used = (char *)calloc((size_t)items, 1);
+    int64_t *piv = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
+    int st = ORC_OK;
+    if (rank) *rank = r;
+    /* 1: R' from r steps of QRP on P^T */
+    memcpy(Z, P, sizeof(double) * (size_t)items * (size_t)w);
+    st = orc_qrp(Z, items, w, r, piv, rank, min_margin);
+    if (st) goto out;
+    for (int64_t it = 0; it < items; it++)
+        for (int c = 0; c < r; c++) Rp[it * r + c] = Z[it * w + c];
+    /* 2: alg1tor on R' */
+    memcpy(Y, Rp, sizeof(double) * (size_t)items * (size_t)r);
+    st = orc_qrp(Y, items, r, r, out, rank, min_margin);
+    if (st) goto out;
+    for (int g = 0; g < r; g++) used[out[g]] = 1;
+    /* 3: algrup */
+    for (int g = r; g < k; g++) {
+        /* Ch = Cholesky factor (lower) of S S^T, S = R'[:, out[0..g-1]] */
+        for (int a = 0; a < r; a++)
+            for (int b = 0; b <= a; b++) {
+                double s = 0.0;
+                for (int q = 0; q < g; q++) s += Rp[out[q] * r + a] * Rp[out[q] * r + b];
+                for (int c = 0; c < b; c++) s -= Ch[a * r + c] * Ch[b * r + c];
+                if (a == b) {
+                    if (!(s > 0.0)) { st = ORC_ESINGULAR; if (rank) *rank = g; goto out; }
+                    Ch[a * r + a] = sqrt(s);
+                } else {
+                    Ch[a * r + b] = s / Ch[b * r + b];
+                }
+            }
+        int64_t best = -1;
+        double v1 = -1.0, v2 = -1.0;
+        for (int64_t it = 0; it < items; it++) {
+            if (used[it]) continue;
+            double s = 0.0;
+            for (int a = 0; a < r; a++) {
+                double x = Rp[it * r + a];
+                for (int c = 0; c < a; c++) x -= Ch[a * r + c] * z[c];
+                z[a] = x / Ch[a * r + a];
+                s += z[a] * z[a];
+            }
+            if (s > v1) { v2 = v1; v1 = s; best = it; }
+            else if (s > v2) v2 = s;
+        }
+        orc_note_margin(min_margin, v1, v2);
+        out[g] = best;
+        used[best] = 1;
+    }
+out:
+    free(Z); free(Rp); free(Y); free(Ch); free(z); free(used); free(piv);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* C-A with k x l generators of large r-projective volume (Section 1.3 and  */
+/* Fig. 4 with k x l sketches; Theorem th3 bounds the error of the          */
+/* canonical CUR of such a generator).  J: l distinct random columns        */
+/* (stream 0), ascending.  A sweep is a column step (I = the k rows that    */
+/* orc_projective_select picks from W[:, J]) and a row step (J = the l      */
+/* columns it picks from W[I, :]^T), sets sorted; the loop stops early at a */
+/* fixed point.  Nucleus U = W[I, J]_r^+ (l x k, J-order x I-order) by      */
+/* orc_pinv_trunc; info.det_log_abs = log v_{2,r}(W[I, J]).                 */
+/* ------------------------------------------------------------------------ */
+int orc_projective_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, int k, int l, int sweeps,
+                       uint64_t seed, int64_t *I_out, int64_t *J_out, double *U_out, orc_info *info_out) {
+    orc_info info = {0, 0, 1, 0, 0, 0, 1.0, 0.0};
+    info.rank_found = r;
+    if (!A || !I_out || !J_out || !U_out || r < 1 || k < r || l < r || sweeps < 1 || m < 1 || n < 1 || lda < n ||
+        (int64_t)k > m || (int64_t)l > n || dtype < 0 || dtype > 2) {
+        if (info_out) *info_out = info;
+        return ORC_EINVAL;
+    }
+    int64_t *I = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    int64_t *J = (int64_t *)malloc(sizeof(int64_t) * (size_t)l);
+    int64_t *Ip = (int64_t *)malloc(sizeof(int64_t) * (size_t)k);
+    int64_t *Jp = (int64_t *)malloc(sizeof(int64_t) * (size_t)l);
+    int64_t wmax = (m > n ? m : n) * (int64_t)(k > l ? k : l);
+    double *P = (double *)malloc(sizeof(double) * (size_t)wmax);
+    double *G = (double *)malloc(sizeof(double) * (size_t)k * (size_t)l);
+    int st = ORC_OK;
+    orc_draw_distinct(seed, 0, n, l, J);
+    qsort(J, (size_t)l, sizeof(int64_t), cmp_i64);
+    for (int s = 0; s < sweeps; s++) {
+        int32_t rk = r;
+        for (int b = 0; b < l; b++)
+            if (!orc_finite_scan(A, dtype, lda, 0, m, J[b], 1)) { st = ORC_EINVAL; goto done; }
+        for (int64_t i = 0; i < m; i++)
+            for (int b = 0; b < l; b++) P[i * l + b] = orc_get(A, dtype, lda, i, J[b]);
+        st = orc_projective_select(P, m, l, r, k, I, &rk, &info.min_margin);
+        if (st) { if (st == ORC_ESINGULAR) info.rank_found = rk; goto done; }
+        qsort(I, (size_t)k, sizeof(int64_t), cmp_i64);
+        for (int a = 0; a < k; a++)
+            if (!orc_finite_scan(A, dtype, lda, I[a], 1, 0, n)) { st = ORC_EINVAL; goto done; }
+        for (int64_t j = 0; j < n; j++)
+            for (int a = 0; a < k; a++) P[j * k + a] = orc_get(A, dtype, lda, I[a], j);
+        st = orc_projective_select(P, n, k, r, l, J, &rk, &info.min_margin);
+        if (st) { if (st == ORC_ESINGULAR) info.rank_found = rk; goto done; }
+        qsort(J, (size_t)l, sizeof(int64_t), cmp_i64);
+        info.sweeps_run = s + 1;
+        if (s > 0 && !memcmp(I, Ip, sizeof(int64_t) * (size_t)k) && !memcmp(J, Jp, sizeof(int64_t) * (size_t)l))
+            break;
+        memcpy(Ip, I, sizeof(int64_t) * (size_t)k);
+        memcpy(Jp, J, sizeof(int64_t) * (size_t)l);
+    }
+    for (int a = 0; a < k; a++)
+        for (int b = 0; b < l; b++) G[a * l + b] = orc_get(A, dtype, lda, I[a], J[b]);
+    {
+        int nr = r;
+        st = orc_pinv_trunc(G, k, l, r, U_out, &nr, &info.det_log_abs);
+        info.nucleus_rank = nr;
+    }
+    memcpy(I_out, I, sizeof(int64_t) * (size_t)k);
+    memcpy(J_out, J, sizeof(int64_t) * (size_t)l);
+done:
+    free(I); free(J); free(Ip); free(Jp); free(P); free(G);
+    if (st != ORC_OK) info.converged = 0;
+    if (info_out) *info_out = info;
+    return st;
+}
