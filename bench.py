@@ -429,8 +429,9 @@ def bench_cynical(lra, workloads, torch, np, args):
     """Cynical CUR on a 20000 x 20000 FP32 factor-Gaussian rank-16 input
     (+ N(0, 1e-6^2)): Tests 4 (one C-A loop at rank k = 4r = 64, then the
     r x r generator inside the 64 x 64 sketch) and Tests 3 (random 64 x 64
-    sketch), beside plain C-A at r = 16 (4 sweeps); relative Frobenius errors
-    from the FP64 residual."""
+    sketch), beside plain C-A at r = 16 (4 sweeps) and C-A with 64 x 64
+    generators of large 16-projective volume (3 sweeps); relative Frobenius
+    errors from the FP64 residual."""
     m = n = 20000
     r, k = 16, 64
     A = workloads.factor_gaussian_device(m, n, r, 1e-6, 3011, "cuda")
@@ -455,6 +456,19 @@ def bench_cynical(lra, workloads, torch, np, args):
     out = lra.lra_cur(A, r, 4, 2031)
     ms = _time_events(torch, lambda: lra.lra_cur(A, r, 4, 2031, out=out), reps, 1)
     rec["plain_ca_r16_4_sweeps"] = {"lras_per_s": 1e3 / ms, "ms_per_lra": ms, "rel_fro_err": err(out)}
+    # k x l = 64 x 64 generators of large r-projective volume, canonical
+    # nucleus (U is l x k, so the r x r residual kernel takes it at rank 64)
+    out = lra.lra_cur_projective(A, r, k, k, 3, 2031)
+    ms = _time_events(torch, lambda: lra.lra_cur_projective(A, r, k, k, 3, 2031, out=out), reps, 1)
+    info = out.info()
+    nbytes = 4 * (info["sweeps_run"] * (m + n) * k + k * k)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    rec["projective_volume_k64_l64_3_sweeps"] = {
+        "lras_per_s": 1e3 / ms, "ms_per_lra": ms, "status": info["status"], "team_size": info["team_size"],
+        "sweeps_run": info["sweeps_run"], "nucleus_rank": info["nucleus_rank"], "rel_fro_err": err(out),
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+        "useful_bytes_per_lra": nbytes}
     del A
     torch.cuda.empty_cache()
     return rec

@@ -86,6 +86,9 @@ def load() -> ct.CDLL:
         L.lra_cur_cynical.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, i32, i32, ct.c_uint64,
                                       ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_cynical.restype = ct.c_int
+        L.lra_cur_projective.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, i32, i32, ct.c_uint64,
+                                         ct.POINTER(lra_opts), P, P, P, P, P]
+        L.lra_cur_projective.restype = ct.c_int
         L.lra_cur_hadamard.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, ct.c_uint64, i32,
                                        ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_hadamard.restype = ct.c_int
@@ -260,6 +263,31 @@ def lra_cur_cynical(A, r: int, k: int, loops: int, sweeps: int, seed: int, *, de
     del keep
     if st != LRA_OK:
         raise LraError(st, "lra_cur_cynical")
+    return out
+
+
+def lra_cur_projective(A, r: int, k: int, l: int, sweeps: int, seed: int, *, team_size: int = 0,
+                       out: CurOut | None = None, stream=None) -> CurOut:
+    """C-A with k x l generators of large r-projective volume and the
+    canonical nucleus: I has k rows, J l columns, U is l x k (W ~ W[:, J] U
+    W[I, :]).  Asynchronous like ``lra_cur``."""
+    torch = _torch()
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor with unit column stride")
+    m, n = A.shape
+    dev = A.device
+    if out is None:
+        out = CurOut(torch.empty(k, dtype=torch.int64, device=dev), torch.empty(l, dtype=torch.int64, device=dev),
+                     torch.empty((l, k), dtype=torch.float64, device=dev),
+                     torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    o, keep = _make_opts(0.01, -1, LRA_PRE_NONE, 3, 0, 0, team_size, None)
+    st = load().lra_cur_projective(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, k, l, sweeps,
+                                   ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
+                                   ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
+                                   ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
+    del keep
+    if st != LRA_OK:
+        raise LraError(st, "lra_cur_projective")
     return out
 
 

@@ -415,6 +415,55 @@ lra_status lra_cur_cynical(const void *W, lra_dtype dt, int64_t m, int64_t n, in
     return LRA_OK;
 }
 
+lra_status lra_cur_projective(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t k,
+                              int32_t l, int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out,
+                              int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    if (!W || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (m < 1 || n < 1 || lda < n || r < 1 || k < r || l < r || k > kRMax || l > kRMax || k > m || l > n ||
+        sweeps < 1)
+        return LRA_EINVAL;
+    if (m >= ((int64_t)1 << 39) || n >= ((int64_t)1 << 39)) return LRA_EINVAL;  // item ids travel in 40 bits
+    CAConfig cfg;
+    lra_opts o;
+    lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
+    if (st != LRA_OK) return st;
+    if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    const int max_team = std::min(dinfo.cus, kMaxTeam);
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
+    // panels are items x max(k, l); the nucleus needs k l + l^2 <= 4 max(k, l)^2
+    const int w = std::max(k, l);
+    int team;
+    LdsPlan plan;
+    if (o.team_size > 0) {
+        team = std::min(o.team_size, max_team);
+        plan = plan_lds(m, n, w, LRA_PRE_NONE, 0, team, lds_budget);
+    } else {
+        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, n) + 159) / 160));
+        plan = plan_lds(m, n, w, LRA_PRE_NONE, 0, team, lds_budget);
+        while (!plan.fits && team < max_team) {
+            team++;
+            plan = plan_lds(m, n, w, LRA_PRE_NONE, 0, team, lds_budget);
+        }
+    }
+    if (!plan.fits) return LRA_EUNSUPPORTED;
+    cfg.panel_bytes = (int32_t)plan.panel_bytes;
+    TeamWs tws{ws->xw, (uint64_t)dinfo.wall_khz * 2000ull};
+    hipError_t e = lra::launch_projective(dt, W, m, n, lda, seed, k, l, cfg, tws, team, plan.dyn_bytes, I_out, J_out,
+                                          U_out, info, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
 lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream) {

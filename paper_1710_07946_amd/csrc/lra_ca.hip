@@ -1085,6 +1085,72 @@ __global__ void __launch_bounds__(256) bidiag_table_kernel(uint64_t seed, int64_
     }
 }
 
+// Greedy Householder QRP over the team's items (Algorithm alg1tor): `steps`
+// choices over the first `width` coordinates of every item (coordinate c of
+// item li at panel[c * g.st + li]); flags[li] != 0 keeps an item out of the
+// running and is set for every chosen item.  Step gg takes the item whose
+// coordinates gg.. have the largest 2-norm (ties to the lowest item) and
+// reflects them onto a multiple of e_gg; each reflection is applied lazily,
+// fused with the next step's norms, in the oracle's order of operations.
+// flush: also apply the last step's reflection, and write every chosen
+// item's own image (alpha at its step, zeros after), so that on return the
+// panel holds H_{steps-1} ... H_0 of every item.  tup / tdiag (optional)
+// receive the chosen items in that final basis, an upper triangular matrix:
+// tup[gg (gg - 1) / 2 + c] = coordinate c < gg of the item chosen at step
+// gg, tdiag[gg] = its alpha.  out[gg] = the item chosen at step gg.  A zero
+// norm ends the loop with ESINGULAR (rank = the step), a flagged non-finite
+// entry (`bad`) with EINVAL.  Same thread-to-item mapping as every other
+// per-item loop here (li = tid, tid + kBlock, ...).
+__device__ __forceinline__ void team_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Geo &g, int width,
+                                         int steps, int bad, bool flush, int64_t *out, double *tup, double *tdiag) {
+    const int tid = threadIdx.x;
+    const int ipw = g.st;
+    for (int gg = 0; gg < steps + (flush ? 1 : 0); gg++) {
+        const bool last = gg == steps;
+        Best b = none();
+        const double vtv = sm.vtv;
+        for (int li = tid; li < g.cnt; li += kBlock) {
+            if (flags[li]) continue;
+            double nrm = 0.0;
+            if (gg > 0 && vtv > 0.0) {  // reflection of step gg-1 (vector in sm.wrow[gg-1 ..])
+                double acc = 0.0;
+                int o = (gg - 1) * ipw + li, c = gg - 1;
+                LRA_QRP_RUN(qrp_dot, width - gg + 1, panel, o, ipw, sm.wrow, c, acc);
+                const double f = 2.0 * acc / vtv;
+                // the update, and the norm of the entries from gg on in the
+                // same pass (its terms in increasing index order)
+                o = (gg - 1) * ipw + li;
+                c = gg - 1;
+                double nrm0 = 0.0;  // entry gg-1 takes the update only
+                qrp_upd<1>(panel, o, ipw, sm.wrow, c, f, nrm0);
+                LRA_QRP_RUN(qrp_upd, width - gg, panel, o, ipw, sm.wrow, c, f, nrm);
+            } else if (!last) {
+                int o = gg * ipw + li, c = gg;
+                LRA_QRP_RUN(qrp_nrm, width - gg, panel, o, ipw, c, nrm);
+            }
+            consider(b, nrm, g.base + li, 0);
+        }
+        if (last) break;
+        team_select(tm, sm, b, gg == 0 ? bad : 0, panel, g, width, kSelHouseholder, gg);
+        if (sm.win_flag) return fail_status(sm, LRA_EINVAL, 0);
+        if (!(sm.win.v > 0.0)) return fail_status(sm, LRA_ESINGULAR, gg);
+        const int64_t wit = sm.win.item;
+        if (tid == 0) out[gg] = wit;
+        if (tup && tid < gg) tup[gg * (gg - 1) / 2 + tid] = sm.wrow[tid];
+        if (tdiag && tid == 0) tdiag[gg] = sm.alpha;
+        if (wit >= g.base && wit < g.base + g.cnt && (int)((wit - g.base) % kBlock) == tid) {
+            const int li = (int)(wit - g.base);
+            flags[li] = 1;
+            if (flush) {
+                // the published row was read before this point, by every
+                // workgroup, from sm.wrow of its own
+                panel[gg * ipw + li] = sm.alpha;
+                for (int c = gg + 1; c < width; c++) panel[c * ipw + li] = 0.0;
+            }
+        }
+    }
+}
+
 // Abridged SRHT sketch of the team's items (Appendix B): for sampled column
 // t = b s + e of D H_{N,d}, Y[item][q] = sqrt(s/l) sum_a W[item][a s + e]
 // D[a s + e] (-1)^{popcount(a & b)} (post-multiplication; pre-multiplication
@@ -1216,38 +1282,8 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
     for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
     LRA_TR(3, 0);
-    const int ipw = g.st;
-    for (int gg = 0; gg < r; gg++) {
-        Best b = none();
-        const double vtv = sm.vtv;
-        for (int li = tid; li < g.cnt; li += kBlock) {
-            if (flags[li]) continue;
-            double nrm = 0.0;
-            if (gg > 0 && vtv > 0.0) {  // reflection of step gg-1 (vector in sm.wrow[gg-1 ..])
-                double acc = 0.0;
-                int o = (gg - 1) * ipw + li, c = gg - 1;
-                LRA_QRP_RUN(qrp_dot, l - gg + 1, panel, o, ipw, sm.wrow, c, acc);
-                const double f = 2.0 * acc / vtv;
-                // the update, and the norm of the entries from gg on in the
-                // same pass (its terms in increasing index order)
-                o = (gg - 1) * ipw + li;
-                c = gg - 1;
-                double nrm0 = 0.0;  // entry gg-1 takes the update only
-                qrp_upd<1>(panel, o, ipw, sm.wrow, c, f, nrm0);
-                LRA_QRP_RUN(qrp_upd, l - gg, panel, o, ipw, sm.wrow, c, f, nrm);
-            } else {
-                int o = gg * ipw + li, c = gg;
-                LRA_QRP_RUN(qrp_nrm, l - gg, panel, o, ipw, c, nrm);
-            }
-            consider(b, nrm, g.base + li, 0);
-        }
-        team_select(tm, sm, b, gg == 0 ? bad : 0, panel, g, l, kSelHouseholder, gg);
-        if (sm.win_flag) return fail_status(sm, LRA_EINVAL, 0);
-        if (!(sm.win.v > 0.0)) return fail_status(sm, LRA_ESINGULAR, gg);
-        const int64_t wit = sm.win.item;
-        if (tid == 0) out[gg] = wit;
-        if (wit >= g.base && wit < g.base + g.cnt && (int)((wit - g.base) % kBlock) == tid) flags[wit - g.base] = 1;
-    }
+    team_qrp(tm, sm, panel, flags, g, l, r, bad, false, out, nullptr, nullptr);
+    if (sm.status != LRA_OK) return;
     __syncthreads();
 #ifdef LRA_TRACE
     LRA_TR(4, sm.t_select);
@@ -1325,6 +1361,174 @@ __device__ __forceinline__ void nucleus(Smem &sm, double *ws, const Src &src, in
         __syncthreads();
     }
     for (int e = tid; e < r * r; e += kBlock) U_out[e] = X[e];
+}
+
+// ---------------------------------------------------------------- r-projective volume
+// k items whose vectors span a submatrix of large r-projective volume
+// (Algorithm algprjvlm, transposed; Algorithms alg1tor and algrup as its
+// black box).  The panel holds one w-vector per item (a row of W[:, J] in a
+// column step, a column of W[I, :] in a row step).
+//  1. r QRP steps over all w coordinates, flushed: the first r coordinates
+//     of every item are then R' = Q_r^T (item), Q_r spanning the r pivots.
+//  2. Algorithm alg1tor on R' (r QRP steps over the first r coordinates,
+//     every item a candidate again); its chosen vectors, in the final basis,
+//     form the upper triangular T (sm.L11 packed by columns, sm.wprev[0] the
+//     diagonal).
+//  3. Algorithm algrup: every candidate y becomes z = T^{-1} y, so that the
+//     chosen set has orthonormal rows and y's expansion factor of eq. (eqb)
+//     is 1 + |z|^2.  Each step takes the largest |z|^2 (ties to the lowest
+//     item); with b its z and beta = |b|^2, the orthogonaliser of the grown
+//     set is I + gamma b b^T / beta, gamma = 1 / sqrt(1 + beta) - 1, applied
+//     to every candidate as z <- z - (b . z) b / (q (1 + q)), q = sqrt(1 + beta).
+// out[0..k-1] = the items in selection order; ESINGULAR (rank = the step)
+// when stage 1 or 2 meets a zero norm.
+__device__ __forceinline__ void projvol_select(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Geo &g, int w,
+                                               int r, int k, int bad, int64_t *out) {
+    const int tid = threadIdx.x;
+    const int ipw = g.st;
+    double *const tup = sm.L11, *const tdiag = sm.wprev[0];
+    team_qrp(tm, sm, panel, flags, g, w, r, bad, true, out, nullptr, nullptr);
+    if (sm.status != LRA_OK) return;
+    for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
+    team_qrp(tm, sm, panel, flags, g, r, r, 0, true, out, tup, tdiag);
+    if (sm.status != LRA_OK) return;
+    __syncthreads();  // T complete in every workgroup
+    Best b = none();
+    for (int li = tid; li < g.cnt; li += kBlock) {
+        if (flags[li]) continue;
+        double s = 0.0;
+        for (int c = r - 1; c >= 0; c--) {
+            double x = panel[c * ipw + li];
+            for (int j = c + 1; j < r; j++) x -= tup[j * (j - 1) / 2 + c] * panel[j * ipw + li];
+            x /= tdiag[c];
+            panel[c * ipw + li] = x;
+        }
+        for (int c = 0; c < r; c++) s += panel[c * ipw + li] * panel[c * ipw + li];
+        consider(b, s, g.base + li, 0);
+    }
+    for (int gg = r; gg < k; gg++) {
+        team_select(tm, sm, b, 0, panel, g, r);
+        if (!(sm.win.v >= 0.0)) return fail_status(sm, LRA_ESINGULAR, gg);
+        const int64_t wit = sm.win.item;
+        if (tid == 0) out[gg] = wit;
+        if (wit >= g.base && wit < g.base + g.cnt && (int)((wit - g.base) % kBlock) == tid) flags[wit - g.base] = 1;
+        if (gg == k - 1) break;
+        const double q = sqrt(1.0 + sm.win.v);
+        const double coef = 1.0 / (q * (1.0 + q));
+        b = none();
+        for (int li = tid; li < g.cnt; li += kBlock) {
+            if (flags[li]) continue;
+            double acc = 0.0;
+            int o = li, c = 0;
+            LRA_QRP_RUN(qrp_dot, r, panel, o, ipw, sm.wrow, c, acc);
+            double nrm = 0.0;
+            o = li;
+            c = 0;
+            LRA_QRP_RUN(qrp_upd, r, panel, o, ipw, sm.wrow, c, coef * acc, nrm);
+            consider(b, nrm, g.base + li, 0);
+        }
+    }
+    __syncthreads();
+}
+
+// Nucleus of a k x l generator (Algorithm algcnnncl): U = G_r^+, the
+// pseudo-inverse of G's rank-r SVD truncation, G = src(I[a], J[b]).
+// One-sided Jacobi on G's l columns in the oracle's round-robin order (a
+// dummy position for odd l; a pair rotated unless |a_p . a_q| <= 1e-15
+// sqrt(|a_p|^2 |a_q|^2); sweeps until none rotates, at most 60), each pair
+// on 16 lanes (dot products summed as a butterfly); then the r largest
+// sigma_j above 1e-14 max sigma (ties to the lower j) are kept and
+// U[a][b] = sum over kept j of V[a][j] A[b][j] / sigma_j^2 (l x k, row-major).
+// ws: k l + l^2 doubles.  sm.nucleus_rank = the number kept, sm.logdet = the
+// sum of their logs.  One workgroup, every thread calls.
+template <class Src>
+__device__ __forceinline__ void nucleus_trunc(Smem &sm, double *ws, const Src &src, int k, int l, int r,
+                                              double *U_out) {
+    const int tid = threadIdx.x;
+    double *A = ws, *V = ws + k * l;
+    __shared__ int s_rot;
+    __shared__ double s_sig[kRMax];
+    __shared__ int s_keep[kRMax];
+    for (int e = tid; e < k * l; e += kBlock) A[e] = src(sm.Iset[e / l], sm.Jset[e % l]);
+    for (int e = tid; e < l * l; e += kBlock) V[e] = (e / l == e % l) ? 1.0 : 0.0;
+    __syncthreads();
+    const int lp = l + (l & 1);
+    const int grp = tid / 16, j = tid % 16, ngrp = kBlock / 16;
+    for (int sweep = 0; sweep < 60 && l > 1; sweep++) {
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        for (int t = 0; t < lp - 1; t++) {
+            for (int pr = grp; pr < lp / 2; pr += ngrp) {
+                int pc, qc;
+                jacobi_pair(t, pr, lp, pc, qc);
+                if (qc >= l) continue;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = j; i < k; i += 16) {
+                    const double x = A[i * l + pc], y = A[i * l + qc];
+                    al += x * x;
+                    be += y * y;
+                    ga += x * y;
+                }
+                al = sum16(al);
+                be = sum16(be);
+                ga = sum16(ga);
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                const double ze = (be - al) / (2.0 * ga);
+                const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                for (int i = j; i < k; i += 16) {
+                    const double x = A[i * l + pc], y = A[i * l + qc];
+                    A[i * l + pc] = cs * x - sn * y;
+                    A[i * l + qc] = sn * x + cs * y;
+                }
+                for (int i = j; i < l; i += 16) {
+                    const double x = V[i * l + pc], y = V[i * l + qc];
+                    V[i * l + pc] = cs * x - sn * y;
+                    V[i * l + qc] = sn * x + cs * y;
+                }
+                if (j == 0) s_rot = 1;
+            }
+            __syncthreads();
+        }
+        const int rot = *(volatile int *)&s_rot;
+        __syncthreads();
+        if (!rot) break;
+    }
+    for (int c = tid; c < l; c += kBlock) {
+        double s2 = 0.0;
+        for (int i = 0; i < k; i++) s2 += A[i * l + c] * A[i * l + c];
+        s_sig[c] = sqrt(s2);
+    }
+    __syncthreads();
+    if (tid < l) {
+        double smax = 0.0;
+        int above = 0;
+        for (int c = 0; c < l; c++) {
+            smax = s_sig[c] > smax ? s_sig[c] : smax;
+            above += (s_sig[c] > s_sig[tid] || (s_sig[c] == s_sig[tid] && c < tid)) ? 1 : 0;
+        }
+        s_keep[tid] = (above < r && s_sig[tid] > 1e-14 * smax) ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int kept = 0;
+        double lv = 0.0;
+        for (int c = 0; c < l; c++)
+            if (s_keep[c]) {
+                kept++;
+                lv += log(s_sig[c]);
+            }
+        sm.nucleus_rank = kept;
+        sm.logdet = lv;
+    }
+    for (int e = tid; e < l * k; e += kBlock) {
+        const int a = e / k, bb = e % k;
+        double acc = 0.0;
+        for (int c = 0; c < l; c++)
+            if (s_keep[c]) acc += V[a * l + c] * A[bb * l + c] / (s_sig[c] * s_sig[c]);
+        U_out[e] = acc;
+    }
+    __syncthreads();
 }
 
 // The whole C-A path for one matrix, executed by every workgroup of a team.
@@ -1587,6 +1791,97 @@ __global__ void __launch_bounds__(kBlock) ca_cynical_kernel(const T *A, int64_t 
              info, Kset, Lset, swaps, team);
 }
 
+// C-A with k x l generators of large r-projective volume: l random start
+// columns (stream 0), then sweeps of a column step (k rows of W[:, J] by
+// projvol_select) and a row step (l columns of W[I, :]), stopping at a fixed
+// point; nucleus W[I, J]_r^+ in workgroup 0.  cfg.r = r.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) ca_projective_kernel(const T *A, int64_t m, int64_t n, int64_t lda,
+                                                               uint64_t seed, int32_t k, int32_t l, CAConfig cfg,
+                                                               TeamWs ws, int64_t *I_out, int64_t *J_out,
+                                                               double *U_out, lra_info *info) {
+    __shared__ Smem sm;
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    double *dyn = reinterpret_cast<double *>(lds_dyn);
+    uint8_t *flags = lds_dyn + cfg.panel_bytes;
+    Team tm;
+    tm.rank = blockIdx.x;
+    tm.size = gridDim.x;
+    tm.epoch = 0;
+    tm.xw = ws.xw;
+    tm.spin_limit = ws.spin_limit;
+    const int tid = threadIdx.x;
+    const int r = cfg.r;
+    const DenseSrc<T> src{A, lda};
+    if (tid == 0) {
+        sm.status = LRA_OK;
+        sm.rank_found = r;
+        sm.nucleus_rank = r;
+        sm.xfail = 0;
+        sm.vtv = 0.0;
+        sm.logdet = 0.0;
+    }
+    if (tid < kWave) {
+        draw_distinct_wave(seed, 0, n, l, sm.Jset);
+        __builtin_amdgcn_wave_barrier();
+        sort_set_wave(sm.Jset, l);
+    }
+    __syncthreads();
+    int32_t sweeps_run = 0;
+    for (int s = 0; s < cfg.sweeps; s++) {
+        {
+            const Geo g = geo(tm, m);
+            const int bad = gather_panel(dyn, g, src, l, true, sm.Jset);
+            for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
+            __syncthreads();
+            projvol_select(tm, sm, dyn, flags, g, l, r, k, bad, sm.Iset);
+            if (sm.status != LRA_OK) break;
+            if (tid < kWave) sort_set_wave(sm.Iset, k);
+            __syncthreads();
+        }
+        {
+            const Geo g = geo(tm, n);
+            const int bad = gather_panel(dyn, g, src, k, false, sm.Iset);
+            for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
+            __syncthreads();
+            projvol_select(tm, sm, dyn, flags, g, k, r, l, bad, sm.Jset);
+            if (sm.status != LRA_OK) break;
+            if (tid < kWave) sort_set_wave(sm.Jset, l);
+            __syncthreads();
+        }
+        sweeps_run = s + 1;
+        bool same = s > 0;
+        for (int j = 0; j < k && same; j++) same = sm.Iset[j] == sm.Iprev[j];
+        for (int j = 0; j < l && same; j++) same = sm.Jset[j] == sm.Jprev[j];
+        __syncthreads();
+        if (same) break;
+        if (tid < k) sm.Iprev[tid] = sm.Iset[tid];
+        if (tid < l) sm.Jprev[tid] = sm.Jset[tid];
+        __syncthreads();
+    }
+    __syncthreads();
+    if (tm.rank != 0) return;
+    const int st = sm.xfail ? LRA_EDEVICE : sm.status;
+    if (st == LRA_OK) nucleus_trunc(sm, dyn, src, k, l, r, U_out);
+    if (tid < k) I_out[tid] = st == LRA_OK ? sm.Iset[tid] : -1;
+    if (tid < l) J_out[tid] = st == LRA_OK ? sm.Jset[tid] : -1;
+    if (st != LRA_OK)
+        for (int e = tid; e < l * k; e += kBlock) U_out[e] = __builtin_nan("");
+    if (tid == 0 && info) {
+        lra_info inf;
+        inf.status = st;
+        inf.sweeps_run = sweeps_run;
+        inf.swaps_total = 0;
+        inf.converged = st == LRA_OK ? 1 : 0;
+        inf.rank_found = sm.rank_found;
+        inf.team_size = tm.size;
+        inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
+        inf.reserved = 0;
+        inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
+        *info = inf;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) ca_batched_kernel(const T *base, const BlockDesc *blocks, const int32_t *order,
                                                             int64_t count, uint64_t seed, CAConfig cfg, unsigned *queue,
@@ -1774,6 +2069,44 @@ hipError_t launch_cynical(int dtype, const void *A, int64_t m, int64_t n, int64_
 }
 
 template <typename T>
+static hipError_t launch_projective_t(const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int32_t k,
+                                      int32_t l, const CAConfig &cfg, const TeamWs &ws, int team, size_t dyn_bytes,
+                                      int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info,
+                                      hipStream_t stream) {
+    auto kern = ca_projective_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+    (void)e;
+    if (team > 1) {
+        const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
+        hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
+                           stream, ws.xw, words);
+    }
+    const T *Ap = static_cast<const T *>(A);
+    CAConfig c = cfg;
+    TeamWs w = ws;
+    void *args[] = {(void *)&Ap, (void *)&m, (void *)&n,     (void *)&lda,   (void *)&seed,  (void *)&k,
+                    (void *)&l,  (void *)&c, (void *)&w,     (void *)&I_out, (void *)&J_out, (void *)&U_out,
+                    (void *)&info};
+    return hipLaunchCooperativeKernel((const void *)kern, dim3(team), dim3(kBlock), args, (unsigned)dyn_bytes, stream);
+}
+
+hipError_t launch_projective(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int32_t k,
+                             int32_t l, const CAConfig &cfg, const TeamWs &ws, int team, size_t dyn_bytes,
+                             int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    switch (dtype) {
+    case LRA_F64:
+        return launch_projective_t<double>(A, m, n, lda, seed, k, l, cfg, ws, team, dyn_bytes, I_out, J_out, U_out,
+                                           info, stream);
+    case LRA_F32:
+        return launch_projective_t<float>(A, m, n, lda, seed, k, l, cfg, ws, team, dyn_bytes, I_out, J_out, U_out,
+                                          info, stream);
+    default:
+        return launch_projective_t<uint16_t>(A, m, n, lda, seed, k, l, cfg, ws, team, dyn_bytes, I_out, J_out, U_out,
+                                             info, stream);
+    }
+}
+
+template <typename T>
 static hipError_t launch_batched_t(const void *base, const BlockDesc *blocks, const int32_t *order, int64_t count,
                                    uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
                                    int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos,
@@ -1841,13 +2174,14 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
 size_t static_lds_bytes() {
     static size_t bytes = 0;
     if (bytes == 0) {
-        const void *fns[13] = {(const void *)ca_team_kernel<double>,     (const void *)ca_team_kernel<float>,
-                               (const void *)ca_team_kernel<uint16_t>,   (const void *)ca_batched_kernel<double>,
-                               (const void *)ca_batched_kernel<float>,   (const void *)ca_batched_kernel<uint16_t>,
-                               (const void *)ca_points_kernel,           (const void *)ca_cynical_kernel<double>,
-                               (const void *)ca_cynical_kernel<float>,   (const void *)ca_cynical_kernel<uint16_t>,
-                               (const void *)ca_hadamard_kernel<double>, (const void *)ca_hadamard_kernel<float>,
-                               (const void *)ca_hadamard_kernel<uint16_t>};
+        const void *fns[16] = {(const void *)ca_team_kernel<double>,       (const void *)ca_team_kernel<float>,
+                               (const void *)ca_team_kernel<uint16_t>,     (const void *)ca_batched_kernel<double>,
+                               (const void *)ca_batched_kernel<float>,     (const void *)ca_batched_kernel<uint16_t>,
+                               (const void *)ca_points_kernel,             (const void *)ca_cynical_kernel<double>,
+                               (const void *)ca_cynical_kernel<float>,     (const void *)ca_cynical_kernel<uint16_t>,
+                               (const void *)ca_hadamard_kernel<double>,   (const void *)ca_hadamard_kernel<float>,
+                               (const void *)ca_hadamard_kernel<uint16_t>, (const void *)ca_projective_kernel<double>,
+                               (const void *)ca_projective_kernel<float>,  (const void *)ca_projective_kernel<uint16_t>};
         size_t mx = sizeof(Smem) + sizeof(int) * kRMax;
         for (const void *f : fns) {
             hipFuncAttributes attr;

@@ -138,6 +138,29 @@ def test_cynical_invalid_arguments_rejected_on_host(lib):
     assert call(opts=ct.byref(o)) == E
 
 
+def test_projective_invalid_arguments_rejected_on_host(lib):
+    fake = ct.c_void_p(0x1000)
+    E = lra.LRA_EINVAL
+
+    def call(m=100, n=80, lda=80, r=4, k=16, l=12, sweeps=2, dt=1, opts=None, W=fake):
+        return lib.lra_cur_projective(W, dt, m, n, lda, r, k, l, sweeps, 1, opts, fake, fake, fake, None, None)
+
+    assert call(k=3) == E            # k < r
+    assert call(l=3) == E            # l < r
+    assert call(k=65) == E           # k > 64
+    assert call(l=65) == E           # l > 64
+    assert call(m=10, k=16) == E     # k > m
+    assert call(n=10, lda=10) == E   # l > n
+    assert call(sweeps=0) == E
+    assert call(r=0) == E
+    assert call(lda=79) == E
+    assert call(dt=7) == E
+    assert call(W=None) == E
+    o = lra.lra_default_opts()
+    o.preprocess = 1
+    assert call(opts=ct.byref(o)) == E
+
+
 def test_residual_invalid_arguments_rejected_on_host(lib):
     f = ct.c_void_p(0x1000)
     E = lra.LRA_EINVAL
