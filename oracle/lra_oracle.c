@@ -1140,7 +1140,10 @@ int orc_hadamard_apply(const void *A, int dtype, int64_t m, int64_t n, int64_t l
 /* truncation).  One-sided Jacobi (Hestenes) SVD of G (k x l, row-major):   */
 /* its l columns are rotated in round-robin pair order (orc_pair, a dummy   */
 /* position for odd l) until a sweep rotates nothing (at most 60); a pair   */
-/* is rotated unless |a_p . a_q| <= 1e-15 sqrt(|a_p|^2 |a_q|^2).  Then      */
+/* is rotated unless |a_p . a_q| <= k eps sqrt(|a_p|^2 |a_q|^2), eps =       */
+/* 2^-52 (the usual one-sided Jacobi test, scaled by the column length, so  */
+/* that rounding in the dot products cannot keep a converged pair turning). */
+/* Then                                                                     */
 /* sigma_j = |a_j|; the kept set is the r largest sigma_j (ties to the      */
 /* lower j) among those above 1e-14 max sigma; X (l x k, row-major) =       */
 /* sum over kept j (increasing) of v_j a_j^T / sigma_j^2.  *rank_out gets   */
@@ -1156,6 +1159,7 @@ int orc_pinv_trunc(const double *G, int k, int l, int r, double *X, int *rank_ou
     memcpy(A, G, sizeof(double) * (size_t)k * (size_t)l);
     for (int j = 0; j < l; j++) V[j * l + j] = 1.0;
     const int lp = l + (l & 1);
+    const double tol = (double)k * 0x1p-52;
     for (int sweep = 0; sweep < 60 && l > 1; sweep++) {
         int rotated = 0;
         for (int t = 0; t < lp - 1; t++) {
@@ -1169,7 +1173,7 @@ int orc_pinv_trunc(const double *G, int k, int l, int r, double *X, int *rank_ou
                     be += A[i * l + qc] * A[i * l + qc];
                     ga += A[i * l + pc] * A[i * l + qc];
                 }
-                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+                if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
                 double ze = (be - al) / (2.0 * ga);
                 double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
                 double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
