@@ -83,10 +83,13 @@ def lib():
         L.orc_projective_select.argtypes = [P, i64, ct.c_int, ct.c_int, ct.c_int, P, P, P]
         L.orc_projective_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64,
                                          P, P, P, P]
+        L.orc_draw_uniform.argtypes = [u64, u64, i64, i64, P]
+        L.orc_uniform_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
                   "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
                   "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag",
-                  "orc_hadamard_apply", "orc_pinv_trunc", "orc_projective_select", "orc_projective_cur"):
+                  "orc_hadamard_apply", "orc_pinv_trunc", "orc_projective_select", "orc_projective_cur",
+                  "orc_draw_uniform", "orc_uniform_cur"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -330,6 +333,29 @@ def projective_cur(A: np.ndarray, r: int, k: int, l: int, sweeps: int, seed: int
     info = _Info()
     st = lib().orc_projective_cur(_p(A), _dtype_code(A), m, n, n, r, k, l, sweeps, seed, _p(I), _p(J), _p(U),
                                   ct.byref(info))
+    return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
+                     info.min_margin, info.det_log_abs, info.nucleus_rank)
+
+
+def draw_uniform(seed: int, stream: int, n: int, k: int) -> np.ndarray:
+    """k uniform draws from [0, n) with replacement, in draw order."""
+    out = np.zeros(k, np.int64)
+    st = lib().orc_draw_uniform(seed, stream, n, k, _p(out))
+    if st:
+        raise ValueError("draw_uniform: status %d" % st)
+    return out
+
+
+def uniform_cur(A: np.ndarray, r: int, k: int, l: int, seed: int) -> CurResult:
+    """CUR with uniform leverage scores (see orc_uniform_cur): I has k rows,
+    J l columns (sorted, duplicates kept), U is l x k."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    I = np.full(k, -1, np.int64)
+    J = np.full(l, -1, np.int64)
+    U = np.zeros((l, k))
+    info = _Info()
+    st = lib().orc_uniform_cur(_p(A), _dtype_code(A), m, n, n, r, k, l, seed, _p(I), _p(J), _p(U), ct.byref(info))
     return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
                      info.min_margin, info.det_log_abs, info.nucleus_rank)
 

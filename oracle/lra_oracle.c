@@ -1367,3 +1367,75 @@ done:
     if (info_out) *info_out = info;
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* k i.i.d. uniform draws from [0, n) WITH replacement, in draw order: the   */
+/* accepted outputs of the stream (the top 2^64 mod n values rejected, as in */
+/* orc_draw_distinct), reduced modulo n.  This is the sampling matrix of     */
+/* Algorithm algsmplex (exactly k columns, each drawn with probability p_i)  */
+/* for uniform leverage scores p_i = 1/n.                                    */
+/* ------------------------------------------------------------------------ */
+int orc_draw_uniform(uint64_t seed, uint64_t stream, int64_t n, int64_t k, int64_t *out) {
+    if (n <= 0 || k < 0 || (k > 0 && !out)) return ORC_EINVAL;
+    uint64_t un = (uint64_t)n;
+    uint64_t rem = (0 - un) % un;
+    uint64_t lim = 0 - rem;
+    uint64_t ctr = 0;
+    int64_t got = 0;
+    while (got < k) {
+        uint64_t u = orc_rng_u64(seed, stream, ctr++);
+        if (rem != 0 && u >= lim) continue;
+        out[got++] = (int64_t)(u % un);
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* CUR LRA with uniform leverage scores (Algorithm algcurlevsc with        */
+/* p_j = 1/n and pbar_i = 1/m, the superfast case of the section on          */
+/* leverage scores for random and average inputs):                          */
+/*   stage 2: J = l uniform draws with replacement (stream 8),              */
+/*            D = diag(1 / sqrt(l p_j)) = sqrt(n / l) I_l;                   */
+/*   stage 4: I = k uniform draws with replacement (stream 9),              */
+/*            Dbar = sqrt(m / k) I_k;                                        */
+/*   stage 6: M = Dbar W[I, J] D, U = D M_r^+ Dbar.                          */
+/* Reading: M^+ is the canonical nucleus of the k x l generator, the pseudo- */
+/* inverse of its rank-r SVD truncation (orc_pinv_trunc), r being the       */
+/* numerical rank the algorithm assumes of W.  I and J are returned sorted   */
+/* ascending, duplicates kept (U's rows and columns follow that order).     */
+/* Only the k l entries of W[I, J] are read; a non-finite one is EINVAL.    */
+/* info.det_log_abs = log v_{2,r}(M), info.nucleus_rank = values kept.      */
+/* ------------------------------------------------------------------------ */
+int orc_uniform_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, int k, int l, uint64_t seed,
+                    int64_t *I_out, int64_t *J_out, double *U_out, orc_info *info_out) {
+    orc_info info = {0, 0, 1, 0, 0, 0, 1.0, 0.0};
+    info.rank_found = r;
+    if (!A || !I_out || !J_out || !U_out || r < 1 || k < r || l < r || m < 1 || n < 1 || lda < n || dtype < 0 ||
+        dtype > 2) {
+        if (info_out) *info_out = info;
+        return ORC_EINVAL;
+    }
+    orc_draw_uniform(seed, 8, n, l, J_out);
+    orc_draw_uniform(seed, 9, m, k, I_out);
+    qsort(J_out, (size_t)l, sizeof(int64_t), cmp_i64);
+    qsort(I_out, (size_t)k, sizeof(int64_t), cmp_i64);
+    double *M = (double *)malloc(sizeof(double) * (size_t)k * (size_t)l);
+    const double dn = sqrt((double)n / (double)l), dm = sqrt((double)m / (double)k);
+    int st = ORC_OK;
+    for (int a = 0; a < k && st == ORC_OK; a++)
+        for (int b = 0; b < l; b++) {
+            double w = orc_get(A, dtype, lda, I_out[a], J_out[b]);
+            if (!isfinite(w)) { st = ORC_EINVAL; break; }
+            M[a * l + b] = (dm * w) * dn;
+        }
+    if (st == ORC_OK) {
+        int nr = r;
+        st = orc_pinv_trunc(M, k, l, r, U_out, &nr, &info.det_log_abs);
+        info.nucleus_rank = nr;
+        for (int64_t e = 0; e < (int64_t)l * k; e++) U_out[e] = (dn * U_out[e]) * dm;
+    }
+    free(M);
+    if (st != ORC_OK) info.converged = 0;
+    if (info_out) *info_out = info;
+    return st;
+}
