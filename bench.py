@@ -347,7 +347,36 @@ def bench_batched(lra, workloads, torch, np, args):
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
         "useful_bytes_per_batch": nbytes,
     }
-    del base, out, outs, views
+    # the same blocks by CUR with uniform leverage scores (k = l = 4r = 64
+    # rows and columns drawn with replacement, rank-16 canonical nucleus):
+    # only the 64 x 64 generator of each block is read
+    k = 64
+    uo = lra.lra_cur_uniform_batched(base, desc, r, k, k, seed)
+    ms_u = _time_events(torch, lambda: lra.lra_cur_uniform_batched(base, desc, r, k, k, seed, out=uo),
+                        max(2, args.steps // 5), 1)
+    uinfos = uo.info()
+
+    def rel_err(b, I, J, U):
+        o0, m, n = int(desc[b][0]), int(desc[b][1]), int(desc[b][2])
+        blk = base[o0:o0 + m * n].view(m, n).double()
+        E = blk - blk[:, J] @ U @ blk[I]
+        return float(torch.linalg.norm(E) / torch.linalg.norm(blk))
+
+    sample = range(0, count, count // 8)
+    errs_u = [rel_err(b, uo.I[b], uo.J[b], uo.U[b]) for b in sample]
+    errs_ca = [rel_err(b, out.I[b], out.J[b], out.U[b]) for b in sample]
+    nbytes_u = count * 4 * k * k
+    gbs_u = nbytes_u / (ms_u * 1e-3) / 1e9
+    res["uniform_leverage_k64_l64"] = {
+        "lras_per_s": count / (ms_u * 1e-3), "ms_per_batch": ms_u,
+        "failed_blocks": sum(1 for i in uinfos if i["status"] != 0),
+        "median_rel_fro_err_8_blocks": float(np.median(errs_u)),
+        "ca_median_rel_fro_err_same_blocks": float(np.median(errs_ca)),
+        "roofline": {"bound": "hbm", "achieved": gbs_u, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs_u / HBM_PEAK_GBS, "traffic": None},
+        "useful_bytes_per_batch": nbytes_u,
+    }
+    del base, out, outs, views, uo
     torch.cuda.empty_cache()
     return res
 

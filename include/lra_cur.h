@@ -190,6 +190,28 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream);
 
+/* CUR with uniform leverage scores for many blocks (Algorithm algcurlevsc
+ * with p_j = 1/n and pbar_i = 1/m: the superfast case of the section on
+ * leverage scores for random and average inputs; sampling by Algorithm
+ * algsmplex; nucleus by Algorithm algcnnncl).  For block b (seed + b):
+ *   J = l column draws from [0, n) with replacement (stream 8),
+ *   I = k row draws from [0, m) with replacement (stream 9), both sorted
+ *   ascending with duplicates kept;
+ *   U = D M_r^+ Dbar, M = Dbar W[I, J] D, D = sqrt(n / l), Dbar = sqrt(m / k),
+ *   M_r^+ the pseudo-inverse of M's rank-r SVD truncation (one-sided Jacobi;
+ *   the r largest singular values above 1e-14 times the largest).
+ * Only the k l entries of W[I, J] are read.  `blocks` is a HOST array;
+ * outputs (device) are packed: I_out int64[count * k], J_out int64[count * l],
+ * U_out double[count * l * k] (each l x k row-major, W ~ W[:, J] U W[I, :]),
+ * infos lra_info[count] (may be NULL: status, nucleus_rank, det_log_abs =
+ * log of the kept singular values' product of M).  A non-finite generator
+ * entry gives that block status LRA_EINVAL, I = J = -1 and U = NaN.
+ * 1 <= r <= min(k, l); k, l <= 64 (k > m or l > n allowed: draws repeat).
+ * Asynchronous on `stream`. */
+lra_status lra_cur_uniform_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
+                                   int32_t k, int32_t l, uint64_t seed, int64_t *I_out, int64_t *J_out, double *U_out,
+                                   lra_info *infos, hipStream_t stream);
+
 /* One far-field interaction block given by its two point sets: rows are the
  * m points starting at point x_off of the point buffer, columns the n points
  * starting at point y_off. */

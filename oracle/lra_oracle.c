@@ -1142,8 +1142,11 @@ int orc_hadamard_apply(const void *A, int dtype, int64_t m, int64_t n, int64_t l
 /* position for odd l) until a sweep rotates nothing (at most 60); a pair   */
 /* is rotated unless |a_p . a_q| <= k eps sqrt(|a_p|^2 |a_q|^2), eps =       */
 /* 2^-52 (the usual one-sided Jacobi test, scaled by the column length, so  */
-/* that rounding in the dot products cannot keep a converged pair turning). */
-/* Then                                                                     */
+/* that rounding in the dot products cannot keep a converged pair turning), */
+/* or one of its columns is negligible, |a|^2 <= (k eps)^2 times the largest */
+/* squared column norm at the start of the sweep (a column at the rounding  */
+/* level of G, e.g. after duplicate columns cancel), or the rotation's sine  */
+/* is zero.  Then                                                           */
 /* sigma_j = |a_j|; the kept set is the r largest sigma_j (ties to the      */
 /* lower j) among those above 1e-14 max sigma; X (l x k, row-major) =       */
 /* sum over kept j (increasing) of v_j a_j^T / sigma_j^2.  *rank_out gets   */
@@ -1162,6 +1165,12 @@ int orc_pinv_trunc(const double *G, int k, int l, int r, double *X, int *rank_ou
     const double tol = (double)k * 0x1p-52;
     for (int sweep = 0; sweep < 60 && l > 1; sweep++) {
         int rotated = 0;
+        double big = 0.0;
+        for (int j = 0; j < l; j++) {
+            double s2 = 0.0;
+            for (int i = 0; i < k; i++) s2 += A[i * l + j] * A[i * l + j];
+            if (s2 > big) big = s2;
+        }
         for (int t = 0; t < lp - 1; t++) {
             for (int s = 0; s < lp / 2; s++) {
                 int pc, qc;
@@ -1174,9 +1183,11 @@ int orc_pinv_trunc(const double *G, int k, int l, int r, double *X, int *rank_ou
                     ga += A[i * l + pc] * A[i * l + qc];
                 }
                 if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+                if (al <= tol * tol * big || be <= tol * tol * big) continue;
                 double ze = (be - al) / (2.0 * ga);
                 double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
                 double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                if (sn == 0.0) continue;
                 for (int i = 0; i < k; i++) {
                     double x = A[i * l + pc], y = A[i * l + qc];
                     A[i * l + pc] = c * x - sn * y;

@@ -464,6 +464,55 @@ lra_status lra_cur_projective(const void *W, lra_dtype dt, int64_t m, int64_t n,
     return LRA_OK;
 }
 
+lra_status lra_cur_uniform_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
+                                   int32_t k, int32_t l, uint64_t seed, int64_t *I_out, int64_t *J_out, double *U_out,
+                                   lra_info *infos, hipStream_t stream) {
+    if (!base || !blocks || count < 0 || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (r < 1 || k < r || l < r || k > kRMax || l > kRMax || count > (int64_t)INT32_MAX) return LRA_EINVAL;
+    std::vector<BlockDesc> desc((size_t)count);
+    for (int64_t b = 0; b < count; b++) {
+        const lra_block &q = blocks[b];
+        if (q.offset < 0 || q.m < 1 || q.n < 1 || q.lda < q.n) return LRA_EINVAL;
+        desc[b] = BlockDesc{q.offset, q.m, q.n, q.lda};
+    }
+    if (count == 0) return LRA_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    lra_status st;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    // the nucleus works on max(k, l) x min(k, l) and min(k, l)^2 doubles
+    const size_t dyn = align16(sizeof(double) * (size_t)std::min(k, l) * (size_t)(k + l));
+    if (ws->block_cap < count) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(ws->blocks);
+        (void)hipFree(ws->order);
+        ws->blocks = nullptr;
+        ws->order = nullptr;
+        ws->block_cap = 0;
+        if (hipMalloc(&ws->blocks, sizeof(BlockDesc) * count) != hipSuccess) return LRA_ENOMEM;
+        if (hipMalloc(&ws->order, sizeof(int32_t) * count) != hipSuccess) return LRA_ENOMEM;
+        ws->block_cap = count;
+    }
+    if (hipMemcpyAsync(ws->blocks, desc.data(), sizeof(BlockDesc) * count, hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+        return LRA_EDEVICE;
+    // the host vector must outlive the copy
+    (void)hipStreamSynchronize(stream);
+    int occ = lra::uniform_occupancy(dt, dyn);
+    if (occ < 1) occ = 1;
+    const int64_t grid = std::min<int64_t>((int64_t)dinfo.cus * occ, count);
+    hipError_t e = lra::launch_uniform(dt, base, ws->blocks, count, seed, r, k, l, (int)grid, dyn, I_out, J_out,
+                                       U_out, infos, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
 lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream) {

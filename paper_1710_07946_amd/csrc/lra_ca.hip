@@ -1447,27 +1447,32 @@ __device__ __forceinline__ double row_sum16(double v) {
 // One-sided Jacobi on the nc = min(k, l) columns (length nr = max(k, l)) of
 // G, or of G^T when G is wide, in the oracle's round-robin order (a dummy
 // position for odd nc; a pair rotated unless |a_p . a_q| <= nr eps
-// sqrt(|a_p|^2 |a_q|^2), eps = 2^-52; sweeps until none rotates, at most
-// 60), each pair on the 16 lanes of a DPP row; then the r largest sigma_j
+// sqrt(|a_p|^2 |a_q|^2), eps = 2^-52, or a column is negligible, |a|^2 <=
+// (nr eps)^2 times the largest squared column norm at the sweep's start, or
+// the sine is zero; sweeps until none rotates, at most 60), each pair on
+// the 16 lanes of a DPP row; then the r largest sigma_j
 // above 1e-14 max sigma (ties to the lower j) are kept.  With B = A V
 // rotated: U = sum over kept j of v_j b_j^T / sigma_j^2 (G tall) or
 // b_j v_j^T / sigma_j^2 (G wide), l x k row-major.  ws: nr nc + nc^2
 // doubles, column-major, so that a pair's lanes read consecutive entries.
 // sm.nucleus_rank = the number kept, sm.logdet = the sum of their logs.
+// dl, dr: the generator is taken as (dl G) dr entrywise and U returned as
+// (dr U) dl, the scalar rescalings Dbar, D of a CUR by sampling.
 // One workgroup, every thread calls.
 template <class Src>
 __device__ __forceinline__ void nucleus_trunc(Smem &sm, double *ws, const Src &src, int k, int l, int r,
-                                              double *U_out) {
+                                              double *U_out, double dl = 1.0, double dr = 1.0) {
     const int tid = threadIdx.x;
     const bool wide = k < l;
     const int nr = wide ? l : k, nc = wide ? k : l;
     double *A = ws, *V = ws + nr * nc;
     __shared__ int s_rot;
     __shared__ double s_sig[kRMax];
+    __shared__ double s_big;
     __shared__ int s_keep[kRMax];
     for (int e = tid; e < nr * nc; e += kBlock) {
         const int i = e % nr, c = e / nr;
-        A[e] = wide ? src(sm.Iset[c], sm.Jset[i]) : src(sm.Iset[i], sm.Jset[c]);
+        A[e] = (dl * (wide ? src(sm.Iset[c], sm.Jset[i]) : src(sm.Iset[i], sm.Jset[c]))) * dr;
     }
     for (int e = tid; e < nc * nc; e += kBlock) V[e] = (e / nc == e % nc) ? 1.0 : 0.0;
     __syncthreads();
@@ -1475,8 +1480,27 @@ __device__ __forceinline__ void nucleus_trunc(Smem &sm, double *ws, const Src &s
     const int grp = tid / 16, j = tid % 16, ngrp = kBlock / 16;
     const double tol = (double)nr * 0x1p-52;
     for (int sweep = 0; sweep < 60 && nc > 1; sweep++) {
+        // squared column norms (s_sig as scratch), then their maximum
+        for (int c = grp; c < nc; c += ngrp) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int u = 0; u < kRMax / 16; u++) {
+                const int i = j + 16 * u;
+                const double x = i < nr ? A[c * nr + i] : 0.0;
+                s2 += x * x;
+            }
+            s2 = row_sum16(s2);
+            if (j == 0) s_sig[c] = s2;
+        }
         if (tid == 0) s_rot = 0;
         __syncthreads();
+        if (tid == 0) {
+            double bg = 0.0;
+            for (int c = 0; c < nc; c++) bg = s_sig[c] > bg ? s_sig[c] : bg;
+            s_big = bg;
+        }
+        __syncthreads();
+        const double negl = tol * tol * s_big;
         for (int t = 0; t < lp - 1; t++) {
             for (int pr = grp; pr < lp / 2; pr += ngrp) {
                 int pc, qc;
@@ -1501,9 +1525,11 @@ __device__ __forceinline__ void nucleus_trunc(Smem &sm, double *ws, const Src &s
                 be = row_sum16(be);
                 ga = row_sum16(ga);
                 if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+                if (al <= negl || be <= negl) continue;
                 const double ze = (be - al) / (2.0 * ga);
                 const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
                 const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                if (sn == 0.0) continue;
 #pragma unroll
                 for (int u = 0; u < kRMax / 16; u++) {
                     const int i = j + 16 * u;
@@ -1569,7 +1595,7 @@ __device__ __forceinline__ void nucleus_trunc(Smem &sm, double *ws, const Src &s
             if (s_keep[c])
                 acc += (wide ? A[c * nr + a] * V[c * nc + bb] : V[c * nc + a] * A[c * nr + bb]) /
                        (s_sig[c] * s_sig[c]);
-        U_out[e] = acc;
+        U_out[e] = (dr * acc) * dl;
     }
     __syncthreads();
 }
@@ -1925,6 +1951,62 @@ __global__ void __launch_bounds__(kBlock) ca_projective_kernel(const T *A, int64
     }
 }
 
+// CUR with uniform leverage scores (Algorithm algcurlevsc with p_j = 1/n,
+// pbar_i = 1/m) for many blocks, one workgroup per block in turn: l column
+// draws (stream 8) and k row draws (stream 9) with replacement, sorted;
+// M = Dbar W[I, J] D with Dbar = sqrt(m / k), D = sqrt(n / l); U = D M_r^+
+// Dbar by nucleus_trunc.  Only the k l generator entries are read.  Block b
+// uses seed + b; every block costs the same, so blocks are dealt round-robin.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) ca_uniform_kernel(const T *base, const BlockDesc *blocks, int64_t count,
+                                                            uint64_t seed, int32_t r, int32_t k, int32_t l,
+                                                            int64_t *I_out, int64_t *J_out, double *U_out,
+                                                            lra_info *infos) {
+    __shared__ Smem sm;
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    double *dyn = reinterpret_cast<double *>(lds_dyn);
+    const int tid = threadIdx.x;
+    for (int64_t b = blockIdx.x; b < count; b += gridDim.x) {
+        const BlockDesc d = blocks[b];
+        const DenseSrc<T> src{base + d.offset, d.lda};
+        const uint64_t sd = seed + (uint64_t)b;
+        if (tid < kWave) {
+            draw_uniform_wave(sd, 8, d.n, l, sm.Jset);
+            draw_uniform_wave(sd, 9, d.m, k, sm.Iset);
+            __builtin_amdgcn_wave_barrier();
+            sort_set_wave(sm.Jset, l);
+            sort_set_wave(sm.Iset, k);
+        }
+        __syncthreads();
+        int bad = 0;
+        for (int e = tid; e < k * l; e += kBlock) bad |= !isfinite(src(sm.Iset[e / l], sm.Jset[e % l]));
+        bad = __syncthreads_or(bad);
+        double *const U = U_out + b * (int64_t)l * k;
+        if (!bad) {
+            const double dm = sqrt((double)d.m / (double)k), dn = sqrt((double)d.n / (double)l);
+            nucleus_trunc(sm, dyn, src, k, l, r, U, dm, dn);
+        } else {
+            for (int e = tid; e < l * k; e += kBlock) U[e] = __builtin_nan("");
+        }
+        if (tid < k) I_out[b * k + tid] = bad ? -1 : sm.Iset[tid];
+        if (tid < l) J_out[b * l + tid] = bad ? -1 : sm.Jset[tid];
+        if (tid == 0 && infos) {
+            lra_info inf;
+            inf.status = bad ? LRA_EINVAL : LRA_OK;
+            inf.sweeps_run = 0;
+            inf.swaps_total = 0;
+            inf.converged = bad ? 0 : 1;
+            inf.rank_found = r;
+            inf.team_size = 1;
+            inf.nucleus_rank = bad ? 0 : sm.nucleus_rank;
+            inf.reserved = 0;
+            inf.det_log_abs = bad ? 0.0 : sm.logdet;
+            infos[b] = inf;
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) ca_batched_kernel(const T *base, const BlockDesc *blocks, const int32_t *order,
                                                             int64_t count, uint64_t seed, CAConfig cfg, unsigned *queue,
@@ -2150,6 +2232,47 @@ hipError_t launch_projective(int dtype, const void *A, int64_t m, int64_t n, int
 }
 
 template <typename T>
+static hipError_t launch_uniform_t(const void *base, const BlockDesc *blocks, int64_t count, uint64_t seed, int32_t r,
+                                   int32_t k, int32_t l, int grid, size_t dyn_bytes, int64_t *I_out, int64_t *J_out,
+                                   double *U_out, lra_info *infos, hipStream_t stream) {
+    auto kern = ca_uniform_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+    (void)e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), dyn_bytes, stream, static_cast<const T *>(base), blocks, count,
+                       seed, r, k, l, I_out, J_out, U_out, infos);
+    return hipGetLastError();
+}
+
+hipError_t launch_uniform(int dtype, const void *base, const BlockDesc *blocks, int64_t count, uint64_t seed,
+                          int32_t r, int32_t k, int32_t l, int grid, size_t dyn_bytes, int64_t *I_out, int64_t *J_out,
+                          double *U_out, lra_info *infos, hipStream_t stream) {
+    switch (dtype) {
+    case LRA_F64:
+        return launch_uniform_t<double>(base, blocks, count, seed, r, k, l, grid, dyn_bytes, I_out, J_out, U_out,
+                                        infos, stream);
+    case LRA_F32:
+        return launch_uniform_t<float>(base, blocks, count, seed, r, k, l, grid, dyn_bytes, I_out, J_out, U_out, infos,
+                                       stream);
+    default:
+        return launch_uniform_t<uint16_t>(base, blocks, count, seed, r, k, l, grid, dyn_bytes, I_out, J_out, U_out,
+                                          infos, stream);
+    }
+}
+
+int uniform_occupancy(int dtype, size_t dyn_bytes) {
+    int blocks = 0;
+    hipError_t e;
+    if (dtype == LRA_F64)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_uniform_kernel<double>, kBlock, dyn_bytes);
+    else if (dtype == LRA_F32)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_uniform_kernel<float>, kBlock, dyn_bytes);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_uniform_kernel<uint16_t>, kBlock, dyn_bytes);
+    if (e != hipSuccess) return 0;
+    return blocks;
+}
+
+template <typename T>
 static hipError_t launch_batched_t(const void *base, const BlockDesc *blocks, const int32_t *order, int64_t count,
                                    uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
                                    int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos,
@@ -2217,14 +2340,16 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
 size_t static_lds_bytes() {
     static size_t bytes = 0;
     if (bytes == 0) {
-        const void *fns[16] = {(const void *)ca_team_kernel<double>,       (const void *)ca_team_kernel<float>,
+        const void *fns[19] = {(const void *)ca_team_kernel<double>,       (const void *)ca_team_kernel<float>,
                                (const void *)ca_team_kernel<uint16_t>,     (const void *)ca_batched_kernel<double>,
                                (const void *)ca_batched_kernel<float>,     (const void *)ca_batched_kernel<uint16_t>,
                                (const void *)ca_points_kernel,             (const void *)ca_cynical_kernel<double>,
                                (const void *)ca_cynical_kernel<float>,     (const void *)ca_cynical_kernel<uint16_t>,
                                (const void *)ca_hadamard_kernel<double>,   (const void *)ca_hadamard_kernel<float>,
                                (const void *)ca_hadamard_kernel<uint16_t>, (const void *)ca_projective_kernel<double>,
-                               (const void *)ca_projective_kernel<float>,  (const void *)ca_projective_kernel<uint16_t>};
+                               (const void *)ca_projective_kernel<float>,  (const void *)ca_projective_kernel<uint16_t>,
+                               (const void *)ca_uniform_kernel<double>,    (const void *)ca_uniform_kernel<float>,
+                               (const void *)ca_uniform_kernel<uint16_t>};
         size_t mx = sizeof(Smem) + sizeof(int) * kRMax;
         for (const void *f : fns) {
             hipFuncAttributes attr;

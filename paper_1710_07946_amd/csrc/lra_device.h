@@ -228,6 +228,28 @@ __device__ __forceinline__ void inverse_lds(double *LU, double *X, int *p, int r
     __syncthreads();
 }
 
+// k i.i.d. draws from [0, n) with replacement, in draw order: the accepted
+// outputs of the stream (the top 2^64 mod n words rejected), reduced mod n.
+// Run by all 64 lanes of one wave: 64 counters are hashed at once and the
+// accepted ones placed by their rank among the round's accepted lanes.
+__device__ __forceinline__ void draw_uniform_wave(uint64_t seed, uint64_t stream, int64_t n, int k, int64_t *out) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t un = (uint64_t)n;
+    const uint64_t rem = (0 - un) % un;
+    const uint64_t lim = 0 - rem;
+    int got = 0;
+    uint64_t ctr = 0;
+    while (got < k) {
+        const uint64_t u = sm64(seed, stream, ctr + (uint64_t)lane);
+        const bool ok = !(rem != 0 && u >= lim);
+        const uint64_t acc = __ballot(ok);
+        const int pos = got + __popcll(acc & ((1ull << lane) - 1ull));
+        if (ok && pos < k) out[pos] = (int64_t)(u % un);
+        got += __popcll(acc);
+        ctr += kWave;
+    }
+}
+
 // Truncated pseudo-inverse by one-sided Jacobi SVD, the rule of the
 // oracle's routine: columns of A = G rotated in round-robin pair order
 // (position 0 fixed, the others rotating, a dummy position for odd r), a pair

@@ -75,6 +75,10 @@ hipError_t launch_cynical(int dtype, const void *A, int64_t m, int64_t n, int64_
 hipError_t launch_projective(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, int32_t k,
                              int32_t l, const CAConfig &cfg, const TeamWs &ws, int team, size_t dyn_bytes,
                              int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);
+hipError_t launch_uniform(int dtype, const void *base, const BlockDesc *blocks, int64_t count, uint64_t seed,
+                          int32_t r, int32_t k, int32_t l, int grid, size_t dyn_bytes, int64_t *I_out, int64_t *J_out,
+                          double *U_out, lra_info *infos, hipStream_t stream);
+int uniform_occupancy(int dtype, size_t dyn_bytes);
 
 size_t residual_scratch_bytes(int64_t m, int64_t n, int r, int q, int s, int prec);
 hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,

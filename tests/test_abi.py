@@ -161,6 +161,31 @@ def test_projective_invalid_arguments_rejected_on_host(lib):
     assert call(opts=ct.byref(o)) == E
 
 
+def test_uniform_invalid_arguments_rejected_on_host(lib):
+    fake = ct.c_void_p(0x1000)
+    E = lra.LRA_EINVAL
+    B = lra.lra_block
+
+    def call(blocks, r=4, k=8, l=8, count=None, dt=1, base=fake):
+        arr = (B * max(1, len(blocks)))(*blocks)
+        cnt = len(blocks) if count is None else count
+        return lib.lra_cur_uniform_batched(base, dt, arr, cnt, r, k, l, 1, fake, fake, fake, None, None)
+
+    good = [B(0, 10, 10, 10)]
+    assert call(good, k=3) == E      # k < r
+    assert call(good, l=3) == E      # l < r
+    assert call(good, k=65) == E     # k > 64
+    assert call(good, l=65) == E     # l > 64
+    assert call(good, r=0) == E
+    assert call(good, dt=7) == E
+    assert call(good, base=None) == E
+    assert call(good, count=-1) == E
+    assert call([B(0, 10, 10, 9)]) == E    # lda < n
+    assert call([B(-1, 10, 10, 10)]) == E  # negative offset
+    assert call([B(0, 0, 10, 10)]) == E    # empty block
+    assert call(good, count=0) == lra.LRA_OK  # an empty batch is a no-op
+
+
 def test_residual_invalid_arguments_rejected_on_host(lib):
     f = ct.c_void_p(0x1000)
     E = lra.LRA_EINVAL
