@@ -1459,8 +1459,8 @@ __device__ __forceinline__ double row_sum16(double v) {
 // dl, dr: the generator is taken as (dl G) dr entrywise and U returned as
 // (dr U) dl, the scalar rescalings Dbar, D of a CUR by sampling.
 // One workgroup, every thread calls.
-template <class Src>
-__device__ __forceinline__ void nucleus_trunc(Smem &sm, double *ws, const Src &src, int k, int l, int r,
+template <class SM, class Src>
+__device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src, int k, int l, int r,
                                               double *U_out, double dl = 1.0, double dr = 1.0) {
     const int tid = threadIdx.x;
     const bool wide = k < l;
@@ -1951,6 +1951,14 @@ __global__ void __launch_bounds__(kBlock) ca_projective_kernel(const T *A, int64
     }
 }
 
+// The few LDS fields the uniform-score CUR needs (sets, nucleus results):
+// a small static footprint lets two workgroups share a CU at k = l = 64.
+struct UniSmem {
+    int64_t Iset[kRMax], Jset[kRMax];
+    int32_t nucleus_rank;
+    double logdet;
+};
+
 // CUR with uniform leverage scores (Algorithm algcurlevsc with p_j = 1/n,
 // pbar_i = 1/m) for many blocks, one workgroup per block in turn: l column
 // draws (stream 8) and k row draws (stream 9) with replacement, sorted;
@@ -1962,7 +1970,7 @@ __global__ void __launch_bounds__(kBlock) ca_uniform_kernel(const T *base, const
                                                             uint64_t seed, int32_t r, int32_t k, int32_t l,
                                                             int64_t *I_out, int64_t *J_out, double *U_out,
                                                             lra_info *infos) {
-    __shared__ Smem sm;
+    __shared__ UniSmem sm;
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     double *dyn = reinterpret_cast<double *>(lds_dyn);
     const int tid = threadIdx.x;
