@@ -494,7 +494,8 @@ def bench_cynical(lra, workloads, torch, np, args):
     gbs = nbytes / (ms * 1e-3) / 1e9
     rec["projective_volume_k64_l64_3_sweeps"] = {
         "lras_per_s": 1e3 / ms, "ms_per_lra": ms, "status": info["status"], "team_size": info["team_size"],
-        "sweeps_run": info["sweeps_run"], "nucleus_rank": info["nucleus_rank"], "rel_fro_err": err(out),
+        "sweeps_run": info["sweeps_run"], "swaps_total": info["swaps_total"], "nucleus_rank": info["nucleus_rank"],
+        "rel_fro_err": err(out),
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
         "useful_bytes_per_lra": nbytes}

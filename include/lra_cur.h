@@ -150,7 +150,8 @@ lra_status lra_cur_cynical(const void *W, lra_dtype dt, int64_t m, int64_t n, in
 /* C-A with k x l CUR generators of large r-projective volume (section
  * "Extension of the maximization of the r-projective volume", Algorithm
  * algprjvlm transposed as its Remark reprvtov allows, with the greedy
- * Algorithms alg1tor and algrup of the Appendix as its black box) and the
+ * Algorithms alg1tor and algrup of the Appendix and the expansion-
+ * contraction exchanges that follow them as its black box) and the
  * canonical nucleus U = W[I, J]_r^+ of Algorithm algcnnncl; Theorem th3
  * bounds the error of such a CUR by a factor that shrinks as k, l grow past r.
  *   J starts as l distinct random columns (stream 0 of `seed`).  A sweep is a
@@ -159,17 +160,22 @@ lra_status lra_cur_cynical(const void *W, lra_dtype dt, int64_t m, int64_t n, in
  *   panel's items truncated at r (R' = Q_r^T panel^T), greedy QRP on R'
  *   (r items), then greedy expansion to k (or l) items, each time the item
  *   y maximising y^T (S S^T)^{-1} y, S the chosen columns of R' (ties to the
- *   lowest item).  The loop stops early when a sweep repeats the sets.
+ *   lowest item); then exchanges: add the best candidate b, drop the member
+ *   s != b of least y_s^T (S' S'^T)^{-1} y_s in the grown set S', while the
+ *   product of the two volume factors exceeds 1 + opts->delta, at most
+ *   opts->max_swaps times per step (defaults 0.01 and 16 r).  The loop stops
+ *   early when a sweep repeats the sets.
  *   U = pseudo-inverse of the rank-r SVD truncation of W[I, J] (one-sided
  *   Jacobi; the r largest singular values above 1e-14 times the largest).
  * Outputs (device): I_out int64[k], J_out int64[l], both ascending; U_out
  * double[l * k], row-major, J-order x I-order, so W ~ W[:, J] U W[I, :].
  * info (device, may be NULL): nucleus_rank = singular values kept,
  * det_log_abs = log of their product (the r-projective volume of W[I, J]),
- * swaps_total = 0, converged = 1.
- * 1 <= r <= min(k, l); k <= min(m, 64); l <= min(n, 64); sweeps >= 1.  Only
- * opts->team_size is used; opts->preprocess and opts->init_cols must be
- * unset (LRA_EINVAL).  ESINGULAR: a panel of rank below r (rank_found = the
+ * swaps_total = exchanges over all steps, converged = 0 when a cap stopped
+ * a profitable exchange.
+ * 1 <= r <= min(k, l); k <= min(m, 64); l <= min(n, 64); sweeps >= 1.
+ * opts->delta, opts->max_swaps and opts->team_size are used;
+ * opts->preprocess and opts->init_cols must be unset (LRA_EINVAL).  ESINGULAR: a panel of rank below r (rank_found = the
  * step).  Errors and asynchrony otherwise as for lra_cur. */
 lra_status lra_cur_projective(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t k,
                               int32_t l, int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out,

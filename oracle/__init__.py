@@ -80,9 +80,9 @@ def lib():
         L.orc_cynical.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P,
                                   P, P]
         L.orc_pinv_trunc.argtypes = [P, ct.c_int, ct.c_int, ct.c_int, P, P, P]
-        L.orc_projective_select.argtypes = [P, i64, ct.c_int, ct.c_int, ct.c_int, P, P, P]
+        L.orc_projective_select.argtypes = [P, i64, ct.c_int, ct.c_int, ct.c_int, dbl, i32, P, P, P, P, P]
         L.orc_projective_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64,
-                                         P, P, P, P]
+                                         dbl, i32, P, P, P, P]
         L.orc_draw_uniform.argtypes = [u64, u64, i64, i64, P]
         L.orc_uniform_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
@@ -220,15 +220,21 @@ def pinv_trunc(G: np.ndarray, r: int):
     return st, X, rk.value, lv.value
 
 
-def projective_select(P: np.ndarray, r: int, k: int):
-    """k items (rows of P) chosen for r-projective volume: (status, items in
-    selection order, rank reached, min margin)."""
+def projective_select(P: np.ndarray, r: int, k: int, delta: float = 0.01, max_swaps: int = 0, full: bool = False):
+    """k items (rows of P) chosen for r-projective volume: (status, items,
+    rank reached, min margin), plus (swaps, converged) when full.  The
+    default max_swaps = 0 stops after the greedy stages."""
     P = np.ascontiguousarray(P, np.float64)
     items, w = P.shape
     out = np.full(k, -1, np.int64)
     rank = ct.c_int32(0)
     mm = ct.c_double(1.0)
-    st = lib().orc_projective_select(_p(P), items, w, r, k, _p(out), ct.byref(rank), ct.byref(mm))
+    sw = ct.c_int32(0)
+    cv = ct.c_int32(0)
+    st = lib().orc_projective_select(_p(P), items, w, r, k, ct.c_double(delta), max_swaps, _p(out), ct.byref(rank),
+                                     ct.byref(mm), ct.byref(sw), ct.byref(cv))
+    if full:
+        return st, out, rank.value, mm.value, sw.value, cv.value
     return st, out, rank.value, mm.value
 
 
@@ -321,7 +327,8 @@ def cynical(A: np.ndarray, r: int, k: int, loops: int, sweeps: int, seed: int, d
                      info.min_margin, info.det_log_abs, info.nucleus_rank)
 
 
-def projective_cur(A: np.ndarray, r: int, k: int, l: int, sweeps: int, seed: int) -> CurResult:
+def projective_cur(A: np.ndarray, r: int, k: int, l: int, sweeps: int, seed: int, delta: float = 0.01,
+                   max_swaps: int = -1) -> CurResult:
     """C-A with k x l generators of large r-projective volume and the
     canonical nucleus (see orc_projective_cur): I has k rows, J l columns,
     U is l x k."""
@@ -331,8 +338,8 @@ def projective_cur(A: np.ndarray, r: int, k: int, l: int, sweeps: int, seed: int
     J = np.full(l, -1, np.int64)
     U = np.zeros((l, k))
     info = _Info()
-    st = lib().orc_projective_cur(_p(A), _dtype_code(A), m, n, n, r, k, l, sweeps, seed, _p(I), _p(J), _p(U),
-                                  ct.byref(info))
+    st = lib().orc_projective_cur(_p(A), _dtype_code(A), m, n, n, r, k, l, sweeps, seed, ct.c_double(delta),
+                                  max_swaps, _p(I), _p(J), _p(U), ct.byref(info))
     return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
                      info.min_margin, info.det_log_abs, info.nucleus_rank)
 

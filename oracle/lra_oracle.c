@@ -1232,12 +1232,47 @@ int orc_pinv_trunc(const double *G, int k, int l, int r, double *X, int *rank_ou
 }
 
 /* ------------------------------------------------------------------------ */
-/* Greedy choice of k items whose vectors span a submatrix of large         */
-/* r-projective volume (Section "Extension of the maximization of the       */
-/* r-projective volume", Algorithm algprjvlm transposed as its remark       */
-/* reprvtov allows; Appendix, Algorithms alg1tor and algrup as its          */
-/* black box).  P (items x w, item-major) holds one w-vector per item: a    */
-/* row of W[:, J] in a column step, a column of W[I, :] in a row step.      */
+/* Lower Cholesky factor Ch (r x r) of S S^T + e e^T, S = Rp[:, set[0..g-1]] */
+/* (Rp item-major, r per item), e = Rp[:, extra] or nothing (extra < 0).     */
+/* Returns 0 when the matrix is not positive definite.                      */
+/* ------------------------------------------------------------------------ */
+static int orc_gram_chol(const double *Rp, int r, const int64_t *set, int g, int64_t extra, double *Ch) {
+    for (int a = 0; a < r; a++)
+        for (int b = 0; b <= a; b++) {
+            double s = 0.0;
+            for (int q = 0; q < g; q++) s += Rp[set[q] * r + a] * Rp[set[q] * r + b];
+            if (extra >= 0) s += Rp[extra * r + a] * Rp[extra * r + b];
+            for (int c = 0; c < b; c++) s -= Ch[a * r + c] * Ch[b * r + c];
+            if (a == b) {
+                if (!(s > 0.0)) return 0;
+                Ch[a * r + a] = sqrt(s);
+            } else {
+                Ch[a * r + b] = s / Ch[b * r + b];
+            }
+        }
+    return 1;
+}
+
+/* y^T (L L^T)^{-1} y for y = Rp[:, it], by one forward solve L z = y.      */
+static double orc_qform(const double *Rp, int r, const double *Ch, int64_t it, double *z) {
+    double s = 0.0;
+    for (int a = 0; a < r; a++) {
+        double x = Rp[it * r + a];
+        for (int c = 0; c < a; c++) x -= Ch[a * r + c] * z[c];
+        z[a] = x / Ch[a * r + a];
+        s += z[a] * z[a];
+    }
+    return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Choice of k items whose vectors span a submatrix of large r-projective   */
+/* volume (Section "Extension of the maximization of the r-projective      */
+/* volume", Algorithm algprjvlm transposed as its remark reprvtov allows;   */
+/* Appendix, Algorithms alg1tor and algrup and the expansion-contraction   */
+/* recipe after them as its black box).  P (items x w, item-major) holds    */
+/* one w-vector per item: a row of W[:, J] in a column step, a column of    */
+/* W[I, :] in a row step.                                                   */
 /*  1. Rank-revealing QRP of the w x items matrix P^T, truncated at r: r    */
 /*     greedy Householder steps (orc_qrp).  Its first r rows R' (r x items) */
 /*     are Q_r^T P^T, Q_r the first r columns of the orthogonal factor.     */
@@ -1245,15 +1280,24 @@ int orc_pinv_trunc(const double *G, int k, int l, int r, double *X, int *rank_ou
 /*  3. Algorithm algrup: for g = r .. k-1 add the unchosen item y (column   */
 /*     of R') maximising y^T (S S^T)^{-1} y, S = R'[:, chosen]: by eq. (eqb) */
 /*     the factor 1 + y^T (S S^T)^{-1} y multiplies v_2(S)^2 when y joins.   */
-/*     The quadratic form is recomputed at every step (Cholesky factor of    */
-/*     S S^T, one forward solve per item); ties to the lowest item.          */
-/* out[0..k-1] receives the items in selection order.  Every decision's      */
-/* margin (gap to the runner-up, relative) goes into *min_margin.  Status:   */
-/* singular when step 1 or 2 meets a zero remaining norm (*rank = step).     */
+/*  4. Refinement with p = 1: expand by the item b of step 3's rule, then   */
+/*     contract by the member s (other than b) of smallest y_s^T (S' S'^T)^-1 */
+/*     y_s, S' = S with b, whose removal multiplies v_2^2 by 1 minus that    */
+/*     (eq. (eqa)).  The exchange is made while the product of the two       */
+/*     factors exceeds 1 + delta (the threshold of the swaps of Algorithm    */
+/*     algdomin) and at most max_swaps times (*converged = 0 when the cap    */
+/*     stops a profitable exchange).                                         */
+/* Every quadratic form is recomputed from a Cholesky factor of the Gram    */
+/* matrix; ties go to the lowest item.  out[0..k-1] receives the items (an  */
+/* exchange puts b in s's place).  Every decision's margin (gap to the      */
+/* runner-up, relative; for the stop test |gain - (1 + delta)| / (1 +       */
+/* delta)) goes into *min_margin.  Status: singular when step 1 or 2 meets  */
+/* a zero remaining norm (*rank = step).                                    */
 /* ------------------------------------------------------------------------ */
-int orc_projective_select(const double *P, int64_t items, int w, int r, int k, int64_t *out, int32_t *rank,
-                          double *min_margin) {
-    if (!P || !out || w < 1 || r < 1 || r > w || k < r || (int64_t)k > items) return ORC_EINVAL;
+int orc_projective_select(const double *P, int64_t items, int w, int r, int k, double delta, int32_t max_swaps,
+                          int64_t *out, int32_t *rank, double *min_margin, int32_t *swaps, int32_t *converged) {
+    if (!P || !out || w < 1 || r < 1 || r > w || k < r || (int64_t)k > items || !(delta >= 0.0) || max_swaps < 0)
+        return ORC_EINVAL;
     double *Z = (double *)malloc(sizeof(double) * (size_t)items * (size_t)w);
     double *Rp = (double *)malloc(sizeof(double) * (size_t)items * (size_t)r);
     double *Y = (double *)malloc(sizeof(double) * (size_t)items * (size_t)r);
@@ -1262,6 +1306,7 @@ int orc_projective_select(const double *P, int64_t items, int w, int r, int k, i
     char *used = (char *)calloc((size_t)items, 1);
     int64_t *piv = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
     int st = ORC_OK;
+    int32_t sw = 0, conv = 1;
     if (rank) *rank = r;
     /* 1: R' from r steps of QRP on P^T */
     memcpy(Z, P, sizeof(double) * (size_t)items * (size_t)w);
@@ -1276,38 +1321,58 @@ int orc_projective_select(const double *P, int64_t items, int w, int r, int k, i
     for (int g = 0; g < r; g++) used[out[g]] = 1;
     /* 3: algrup */
     for (int g = r; g < k; g++) {
-        /* Ch = Cholesky factor (lower) of S S^T, S = R'[:, out[0..g-1]] */
-        for (int a = 0; a < r; a++)
-            for (int b = 0; b <= a; b++) {
-                double s = 0.0;
-                for (int q = 0; q < g; q++) s += Rp[out[q] * r + a] * Rp[out[q] * r + b];
-                for (int c = 0; c < b; c++) s -= Ch[a * r + c] * Ch[b * r + c];
-                if (a == b) {
-                    if (!(s > 0.0)) { st = ORC_ESINGULAR; if (rank) *rank = g; goto out; }
-                    Ch[a * r + a] = sqrt(s);
-                } else {
-                    Ch[a * r + b] = s / Ch[b * r + b];
-                }
-            }
+        if (!orc_gram_chol(Rp, r, out, g, -1, Ch)) { st = ORC_ESINGULAR; if (rank) *rank = g; goto out; }
         int64_t best = -1;
         double v1 = -1.0, v2 = -1.0;
         for (int64_t it = 0; it < items; it++) {
             if (used[it]) continue;
-            double s = 0.0;
-            for (int a = 0; a < r; a++) {
-                double x = Rp[it * r + a];
-                for (int c = 0; c < a; c++) x -= Ch[a * r + c] * z[c];
-                z[a] = x / Ch[a * r + a];
-                s += z[a] * z[a];
-            }
-            if (s > v1) { v2 = v1; v1 = s; best = it; }
-            else if (s > v2) v2 = s;
+            double q = orc_qform(Rp, r, Ch, it, z);
+            if (q > v1) { v2 = v1; v1 = q; best = it; }
+            else if (q > v2) v2 = q;
         }
         orc_note_margin(min_margin, v1, v2);
         out[g] = best;
         used[best] = 1;
     }
+    /* 4: expansion-contraction exchanges */
+    while ((int64_t)k < items) {
+        if (!orc_gram_chol(Rp, r, out, k, -1, Ch)) { st = ORC_ESINGULAR; if (rank) *rank = k; goto out; }
+        int64_t b = -1;
+        double v1 = -1.0, v2 = -1.0;
+        for (int64_t it = 0; it < items; it++) {
+            if (used[it]) continue;
+            double q = orc_qform(Rp, r, Ch, it, z);
+            if (q > v1) { v2 = v1; v1 = q; b = it; }
+            else if (q > v2) v2 = q;
+        }
+        orc_note_margin(min_margin, v1, v2);
+        const double grow = 1.0 + v1;
+        if (!orc_gram_chol(Rp, r, out, k, b, Ch)) { st = ORC_ESINGULAR; if (rank) *rank = k; goto out; }
+        int64_t s = -1;
+        double c1 = -1.0, c2 = -1.0;  /* contraction factors 1 - y^T (S' S'^T)^{-1} y */
+        for (int64_t it = 0; it < items; it++) {
+            if (!used[it]) continue;
+            double c = 1.0 - orc_qform(Rp, r, Ch, it, z);
+            if (c > c1) { c2 = c1; c1 = c; s = it; }
+            else if (c > c2) c2 = c;
+        }
+        orc_note_margin(min_margin, c1, c2);
+        const double gain = grow * c1;
+        if (min_margin) {
+            double mg = fabs(gain - (1.0 + delta)) / (1.0 + delta);
+            if (mg < *min_margin) *min_margin = mg;
+        }
+        if (!(gain > 1.0 + delta)) break;
+        if (sw >= max_swaps) { conv = 0; break; }
+        for (int g = 0; g < k; g++)
+            if (out[g] == s) { out[g] = b; break; }
+        used[s] = 0;
+        used[b] = 1;
+        sw++;
+    }
 out:
+    if (swaps) *swaps = sw;
+    if (converged) *converged = conv;
     free(Z); free(Rp); free(Y); free(Ch); free(z); free(used); free(piv);
     return st;
 }
@@ -1320,14 +1385,18 @@ out:
 /* orc_projective_select picks from W[:, J]) and a row step (J = the l      */
 /* columns it picks from W[I, :]^T), sets sorted; the loop stops early at a */
 /* fixed point.  Nucleus U = W[I, J]_r^+ (l x k, J-order x I-order) by      */
-/* orc_pinv_trunc; info.det_log_abs = log v_{2,r}(W[I, J]).                 */
+/* orc_pinv_trunc; info.det_log_abs = log v_{2,r}(W[I, J]); swaps_total     */
+/* counts the exchanges of every step (delta and max_swaps per step, the    */
+/* cap defaulting to 16 r when negative).                                   */
 /* ------------------------------------------------------------------------ */
 int orc_projective_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, int k, int l, int sweeps,
-                       uint64_t seed, int64_t *I_out, int64_t *J_out, double *U_out, orc_info *info_out) {
+                       uint64_t seed, double delta, int32_t max_swaps, int64_t *I_out, int64_t *J_out, double *U_out,
+                       orc_info *info_out) {
     orc_info info = {0, 0, 1, 0, 0, 0, 1.0, 0.0};
     info.rank_found = r;
+    if (max_swaps < 0) max_swaps = 16 * r;
     if (!A || !I_out || !J_out || !U_out || r < 1 || k < r || l < r || sweeps < 1 || m < 1 || n < 1 || lda < n ||
-        (int64_t)k > m || (int64_t)l > n || dtype < 0 || dtype > 2) {
+        (int64_t)k > m || (int64_t)l > n || dtype < 0 || dtype > 2 || !(delta >= 0.0)) {
         if (info_out) *info_out = info;
         return ORC_EINVAL;
     }
@@ -1347,14 +1416,19 @@ int orc_projective_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t l
             if (!orc_finite_scan(A, dtype, lda, 0, m, J[b], 1)) { st = ORC_EINVAL; goto done; }
         for (int64_t i = 0; i < m; i++)
             for (int b = 0; b < l; b++) P[i * l + b] = orc_get(A, dtype, lda, i, J[b]);
-        st = orc_projective_select(P, m, l, r, k, I, &rk, &info.min_margin);
+        int32_t sw = 0, cv = 1;
+        st = orc_projective_select(P, m, l, r, k, delta, max_swaps, I, &rk, &info.min_margin, &sw, &cv);
+        info.swaps_total += sw;
+        if (!cv) info.converged = 0;
         if (st) { if (st == ORC_ESINGULAR) info.rank_found = rk; goto done; }
         qsort(I, (size_t)k, sizeof(int64_t), cmp_i64);
         for (int a = 0; a < k; a++)
             if (!orc_finite_scan(A, dtype, lda, I[a], 1, 0, n)) { st = ORC_EINVAL; goto done; }
         for (int64_t j = 0; j < n; j++)
             for (int a = 0; a < k; a++) P[j * k + a] = orc_get(A, dtype, lda, I[a], j);
-        st = orc_projective_select(P, n, k, r, l, J, &rk, &info.min_margin);
+        st = orc_projective_select(P, n, k, r, l, delta, max_swaps, J, &rk, &info.min_margin, &sw, &cv);
+        info.swaps_total += sw;
+        if (!cv) info.converged = 0;
         if (st) { if (st == ORC_ESINGULAR) info.rank_found = rk; goto done; }
         qsort(J, (size_t)l, sizeof(int64_t), cmp_i64);
         info.sweeps_run = s + 1;

@@ -269,11 +269,13 @@ def lra_cur_cynical(A, r: int, k: int, loops: int, sweeps: int, seed: int, *, de
     return out
 
 
-def lra_cur_projective(A, r: int, k: int, l: int, sweeps: int, seed: int, *, team_size: int = 0,
-                       out: CurOut | None = None, stream=None) -> CurOut:
+def lra_cur_projective(A, r: int, k: int, l: int, sweeps: int, seed: int, *, delta: float = 0.01,
+                       max_swaps: int = -1, team_size: int = 0, out: CurOut | None = None,
+                       stream=None) -> CurOut:
     """C-A with k x l generators of large r-projective volume and the
     canonical nucleus: I has k rows, J l columns, U is l x k (W ~ W[:, J] U
-    W[I, :]).  Asynchronous like ``lra_cur``."""
+    W[I, :]).  delta and max_swaps govern each step's exchanges (max_swaps
+    -1: 16 r).  Asynchronous like ``lra_cur``."""
     torch = _torch()
     if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
         raise ValueError("A must be a 2-D device tensor with unit column stride")
@@ -283,7 +285,7 @@ def lra_cur_projective(A, r: int, k: int, l: int, sweeps: int, seed: int, *, tea
         out = CurOut(torch.empty(k, dtype=torch.int64, device=dev), torch.empty(l, dtype=torch.int64, device=dev),
                      torch.empty((l, k), dtype=torch.float64, device=dev),
                      torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
-    o, keep = _make_opts(0.01, -1, LRA_PRE_NONE, 3, 0, 0, team_size, None)
+    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, 0, team_size, None)
     st = load().lra_cur_projective(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, k, l, sweeps,
                                    ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
                                    ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),

@@ -1364,26 +1364,63 @@ __device__ __forceinline__ void nucleus(Smem &sm, double *ws, const Src &src, in
 }
 
 // ---------------------------------------------------------------- r-projective volume
+// One orthogonaliser pass over every item of the slice: z <- z - f (w . z) w,
+// f = f0 (w . z), w = sm.wrow[0 .. r-1] (the picked item's z), the dot
+// product and the new |z|^2 in index order.  Returns the best candidate
+// (flag 0) by |z|^2 when want_members is false, else the best member (flag
+// nonzero) by max(0, 1 - |z|^2) (the factor by which dropping it scales
+// v_2^2 in an orthonormal-row set, eq. (eqa)).
+__device__ __forceinline__ Best orth_pass(Smem &sm, double *panel, const uint8_t *flags, const Geo &g, int r,
+                                          double f0, bool want_members) {
+    const int ipw = g.st;
+    Best b = none();
+    for (int li = threadIdx.x; li < g.cnt; li += kBlock) {
+        double acc = 0.0;
+        int o = li, c = 0;
+        LRA_QRP_RUN(qrp_dot, r, panel, o, ipw, sm.wrow, c, acc);
+        double nrm = 0.0;
+        o = li;
+        c = 0;
+        LRA_QRP_RUN(qrp_upd, r, panel, o, ipw, sm.wrow, c, f0 * acc, nrm);
+        if (want_members) {
+            if (flags[li]) consider(b, fmax(0.0, 1.0 - nrm), g.base + li, 0);
+        } else if (!flags[li]) {
+            consider(b, nrm, g.base + li, 0);
+        }
+    }
+    return b;
+}
+
 // k items whose vectors span a submatrix of large r-projective volume
-// (Algorithm algprjvlm, transposed; Algorithms alg1tor and algrup as its
-// black box).  The panel holds one w-vector per item (a row of W[:, J] in a
-// column step, a column of W[I, :] in a row step).
+// (Algorithm algprjvlm, transposed; Algorithms alg1tor and algrup and the
+// expansion-contraction recipe after them as its black box).  The panel
+// holds one w-vector per item (a row of W[:, J] in a column step, a column
+// of W[I, :] in a row step).
 //  1. r QRP steps over all w coordinates, flushed: the first r coordinates
 //     of every item are then R' = Q_r^T (item), Q_r spanning the r pivots.
 //  2. Algorithm alg1tor on R' (r QRP steps over the first r coordinates,
 //     every item a candidate again); its chosen vectors, in the final basis,
 //     form the upper triangular T (sm.L11 packed by columns, sm.wprev[0] the
 //     diagonal).
-//  3. Algorithm algrup: every candidate y becomes z = T^{-1} y, so that the
-//     chosen set has orthonormal rows and y's expansion factor of eq. (eqb)
-//     is 1 + |z|^2.  Each step takes the largest |z|^2 (ties to the lowest
-//     item); with b its z and beta = |b|^2, the orthogonaliser of the grown
-//     set is I + gamma b b^T / beta, gamma = 1 / sqrt(1 + beta) - 1, applied
-//     to every candidate as z <- z - (b . z) b / (q (1 + q)), q = sqrt(1 + beta).
-// out[0..k-1] = the items in selection order; ESINGULAR (rank = the step)
-// when stage 1 or 2 meets a zero norm.
+//  3. Algorithm algrup: every item y becomes z = T^{-1} y, so that the
+//     chosen set has orthonormal rows (its members become e_g exactly) and a
+//     candidate's expansion factor of eq. (eqb) is 1 + |z|^2.  Each step
+//     takes the largest |z|^2 (ties to the lowest item); with b its z and
+//     beta = |b|^2, the orthogonaliser of the grown set, I + gamma b b^T /
+//     beta with gamma = 1 / sqrt(1 + beta) - 1, is applied to every item as
+//     z <- z - (b . z) b / (q (1 + q)), q = sqrt(1 + beta).
+//  4. Exchanges: expand by the best candidate b (factor 1 + beta), then the
+//     member s (not b) of least leverage |z_s|^2 in the grown set would
+//     leave (factor 1 - |z_s|^2); while the product exceeds 1 + delta (at
+//     most max_swaps times) s leaves, and the orthogonaliser of the shrunk
+//     set, z <- z + (s . z) s / (q (1 + q)) with q = sqrt(1 - |z_s|^2), is
+//     applied to every item.
+// out[0..k-1] = the items (an exchange puts b in s's place); ESINGULAR
+// (rank = the step) when stage 1 or 2 meets a zero norm.  swaps and
+// converged accumulate over calls.
 __device__ __forceinline__ void projvol_select(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Geo &g, int w,
-                                               int r, int k, int bad, int64_t *out) {
+                                               int r, int k, int bad, int64_t *out, double delta, int max_swaps,
+                                               int32_t &swaps, int32_t &converged) {
     const int tid = threadIdx.x;
     const int ipw = g.st;
     double *const tup = sm.L11, *const tdiag = sm.wprev[0];
@@ -1395,39 +1432,59 @@ __device__ __forceinline__ void projvol_select(Team &tm, Smem &sm, double *panel
     __syncthreads();  // T complete in every workgroup
     Best b = none();
     for (int li = tid; li < g.cnt; li += kBlock) {
-        if (flags[li]) continue;
-        double s = 0.0;
         for (int c = r - 1; c >= 0; c--) {
             double x = panel[c * ipw + li];
             for (int j = c + 1; j < r; j++) x -= tup[j * (j - 1) / 2 + c] * panel[j * ipw + li];
             x /= tdiag[c];
             panel[c * ipw + li] = x;
         }
+        if (flags[li]) continue;
+        double s = 0.0;
         for (int c = 0; c < r; c++) s += panel[c * ipw + li] * panel[c * ipw + li];
         consider(b, s, g.base + li, 0);
     }
+    auto owner = [&](int64_t it) {
+        return it >= g.base && it < g.base + g.cnt && (int)((it - g.base) % kBlock) == tid;
+    };
     for (int gg = r; gg < k; gg++) {
         team_select(tm, sm, b, 0, panel, g, r);
         if (!(sm.win.v >= 0.0)) return fail_status(sm, LRA_ESINGULAR, gg);
         const int64_t wit = sm.win.item;
         if (tid == 0) out[gg] = wit;
-        if (wit >= g.base && wit < g.base + g.cnt && (int)((wit - g.base) % kBlock) == tid) flags[wit - g.base] = 1;
-        if (gg == k - 1) break;
+        if (owner(wit)) flags[wit - g.base] = 1;
         const double q = sqrt(1.0 + sm.win.v);
-        const double coef = 1.0 / (q * (1.0 + q));
-        b = none();
-        for (int li = tid; li < g.cnt; li += kBlock) {
-            if (flags[li]) continue;
-            double acc = 0.0;
-            int o = li, c = 0;
-            LRA_QRP_RUN(qrp_dot, r, panel, o, ipw, sm.wrow, c, acc);
-            double nrm = 0.0;
-            o = li;
-            c = 0;
-            LRA_QRP_RUN(qrp_upd, r, panel, o, ipw, sm.wrow, c, coef * acc, nrm);
-            consider(b, nrm, g.base + li, 0);
-        }
+        b = orth_pass(sm, panel, flags, g, r, 1.0 / (q * (1.0 + q)), false);
     }
+    int32_t sw = 0;
+    while ((int64_t)k < g.items) {
+        team_select(tm, sm, b, 0, panel, g, r);
+        if (!(sm.win.v >= 0.0)) break;
+        const int64_t bi = sm.win.item;
+        const double grow = 1.0 + sm.win.v;
+        const double q = sqrt(grow);
+        Best m = orth_pass(sm, panel, flags, g, r, 1.0 / (q * (1.0 + q)), true);
+        team_select(tm, sm, m, 0, panel, g, r);
+        if (!(sm.win.v >= 0.0)) break;
+        const int64_t si = sm.win.item;
+        const double shrink = sm.win.v;
+        if (!(grow * shrink > 1.0 + delta)) break;
+        if (sw >= max_swaps) {
+            converged = 0;
+            break;
+        }
+        if (owner(bi)) flags[bi - g.base] = 1;
+        if (owner(si)) flags[si - g.base] = 0;
+        if (tid == 0)
+            for (int j = 0; j < k; j++)
+                if (out[j] == si) {
+                    out[j] = bi;
+                    break;
+                }
+        sw++;
+        const double q2 = sqrt(shrink);
+        b = orth_pass(sm, panel, flags, g, r, -1.0 / (q2 * (1.0 + q2)), false);
+    }
+    swaps += sw;
     __syncthreads();
 }
 
@@ -1863,7 +1920,8 @@ __global__ void __launch_bounds__(kBlock) ca_cynical_kernel(const T *A, int64_t 
 // C-A with k x l generators of large r-projective volume: l random start
 // columns (stream 0), then sweeps of a column step (k rows of W[:, J] by
 // projvol_select) and a row step (l columns of W[I, :]), stopping at a fixed
-// point; nucleus W[I, J]_r^+ in workgroup 0.  cfg.r = r.
+// point; nucleus W[I, J]_r^+ in workgroup 0.  cfg.r = r; cfg.delta and
+// cfg.max_swaps govern each step's exchanges.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) ca_projective_kernel(const T *A, int64_t m, int64_t n, int64_t lda,
                                                                uint64_t seed, int32_t k, int32_t l, CAConfig cfg,
@@ -1896,14 +1954,14 @@ __global__ void __launch_bounds__(kBlock) ca_projective_kernel(const T *A, int64
         sort_set_wave(sm.Jset, l);
     }
     __syncthreads();
-    int32_t sweeps_run = 0;
+    int32_t sweeps_run = 0, swaps = 0, converged = 1;
     for (int s = 0; s < cfg.sweeps; s++) {
         {
             const Geo g = geo(tm, m);
             const int bad = gather_panel(dyn, g, src, l, true, sm.Jset);
             for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
             __syncthreads();
-            projvol_select(tm, sm, dyn, flags, g, l, r, k, bad, sm.Iset);
+            projvol_select(tm, sm, dyn, flags, g, l, r, k, bad, sm.Iset, cfg.delta, cfg.max_swaps, swaps, converged);
             if (sm.status != LRA_OK) break;
             if (tid < kWave) sort_set_wave(sm.Iset, k);
             __syncthreads();
@@ -1913,7 +1971,7 @@ __global__ void __launch_bounds__(kBlock) ca_projective_kernel(const T *A, int64
             const int bad = gather_panel(dyn, g, src, k, false, sm.Iset);
             for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
             __syncthreads();
-            projvol_select(tm, sm, dyn, flags, g, k, r, l, bad, sm.Jset);
+            projvol_select(tm, sm, dyn, flags, g, k, r, l, bad, sm.Jset, cfg.delta, cfg.max_swaps, swaps, converged);
             if (sm.status != LRA_OK) break;
             if (tid < kWave) sort_set_wave(sm.Jset, l);
             __syncthreads();
@@ -1940,8 +1998,8 @@ __global__ void __launch_bounds__(kBlock) ca_projective_kernel(const T *A, int64
         lra_info inf;
         inf.status = st;
         inf.sweeps_run = sweeps_run;
-        inf.swaps_total = 0;
-        inf.converged = st == LRA_OK ? 1 : 0;
+        inf.swaps_total = swaps;
+        inf.converged = st == LRA_OK ? converged : 0;
         inf.rank_found = sm.rank_found;
         inf.team_size = tm.size;
         inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;

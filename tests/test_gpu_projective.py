@@ -65,6 +65,7 @@ def check(A64, g, o, k, l, tol, rows=None):
         assert same
         assert np.abs(U - o.U).max() <= 1e-9 * np.abs(o.U).max()
         assert info["sweeps_run"] == o.sweeps_run
+        assert info["swaps_total"] == o.swaps_total and info["converged"] == o.converged
         assert info["nucleus_rank"] == o.nucleus_rank
         assert info["det_log_abs"] == pytest.approx(o.det_log_abs, abs=1e-9)
 
@@ -91,6 +92,25 @@ def test_edge_sizes(lra, r, k, l):
     o = oracle.projective_cur(A, r, k, l, 2, 5)
     g = gpu_proj(lra, A, r, k, l, 2, 5)
     check(A, g, o, k, l, 1e-6)
+
+
+@pytest.mark.parametrize("seed,team", [(1, 3), (11, 1), (8, 5)])
+def test_exchanges_match_the_oracle(lra, seed, team):
+    # delta = 0 on a Gaussian 300 x 260: the greedy sets are improved by a few
+    # expansion-contraction exchanges per run
+    A = np.random.default_rng(seed).standard_normal((300, 260))
+    o = oracle.projective_cur(A, 6, 12, 10, 3, seed, delta=0.0)
+    assert o.swaps_total > 0
+    g = gpu_proj(lra, A, 6, 12, 10, 3, seed, delta=0.0, team_size=team)
+    check(A, g, o, 12, 10, 1e-6)
+
+
+def test_exchange_cap_clears_converged(lra):
+    A = np.random.default_rng(1).standard_normal((300, 260))
+    o = oracle.projective_cur(A, 6, 12, 10, 3, 1, delta=0.0, max_swaps=0)
+    assert o.swaps_total == 0 and o.converged == 0
+    g = gpu_proj(lra, A, 6, 12, 10, 3, 1, delta=0.0, max_swaps=0)
+    check(A, g, o, 12, 10, 1e-6)
 
 
 def test_single_workgroup(lra):

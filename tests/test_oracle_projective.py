@@ -3,11 +3,13 @@
 Theorem th2 for the expansion factor; Algorithm algcnnncl for the canonical
 nucleus; Theorems thcandec and th3 for what the resulting CUR guarantees).
 
-The selection is checked against an independent route (LAPACK's pivoted QR
-for the two QRP stages, explicit determinants for every expansion), against
-closed forms (r = 1), against its invariance under an orthogonal change of
-the panel's coordinates (Lemma leprwnmp) and, for the whole loop, against
-exact recovery and the brute-force Chebyshev bound of Theorem th3."""
+The greedy stages are checked against an independent route (LAPACK's
+pivoted QR for the two QRP stages, explicit determinants for every
+expansion), against closed forms (r = 1) and against their invariance under
+an orthogonal change of the panel's coordinates (Lemma leprwnmp); the
+expansion-contraction exchanges against brute-force local maximality and the
+product of eqs. (eqb) and (eqa); the whole loop against exact recovery and
+the brute-force Chebyshev bound of Theorem th3."""
 import itertools
 
 import numpy as np
@@ -180,9 +182,9 @@ def test_start_set_is_the_seeded_draw_and_loops_reach_a_fixed_point():
     # the one-sweep result is what a column step from the seeded columns and a
     # row step give
     J0 = np.sort(oracle.draw_distinct(99, 0, 100, 8))
-    st, I, _, _ = oracle.projective_select(W[:, J0], 4, 8)
+    st, I, _, _ = oracle.projective_select(W[:, J0], 4, 8, max_swaps=64)
     I = np.sort(I)
-    st2, J, _, _ = oracle.projective_select(W[I].T, 4, 8)
+    st2, J, _, _ = oracle.projective_select(W[I].T, 4, 8, max_swaps=64)
     assert st == 0 and st2 == 0
     assert one.I.tolist() == I.tolist() and one.J.tolist() == sorted(J.tolist())
 
@@ -209,6 +211,76 @@ def test_theorem_th3_chebyshev_bound_by_brute_force():
     sig = np.linalg.svd(W, compute_uv=False)
     E = W - W[:, c.J] @ c.U @ W[c.I]
     assert np.abs(E).max() <= h * f * sig[r] * (1 + 1e-12)
+
+
+def r_prime(P, r):
+    """R' by another route (LAPACK's pivoted QR of P^T), up to a rotation."""
+    piv1 = scipy.linalg.qr(P.T, pivoting=True, mode="r")[1][:r]
+    Q, _ = np.linalg.qr(P[piv1].T)
+    return Q.T @ P.T
+
+
+def gram_det(Rp, S):
+    return np.linalg.det(Rp[:, S] @ Rp[:, S].T)
+
+
+@pytest.mark.parametrize("items,w,r,k,seed,delta", [(200, 20, 8, 12, 30, 0.0), (70, 10, 4, 8, 20, 0.0),
+                                                    (60, 9, 3, 7, 11, 0.01), (80, 8, 4, 12, 58, 0.0)])
+def test_refinement_ends_locally_maximal(items, w, r, k, seed, delta):
+    # no single exchange (add a candidate, drop a member) multiplies v_2^2 by
+    # more than 1 + delta (the stop rule), by brute force over all pairs
+    P = np.random.default_rng(seed).standard_normal((items, w))
+    st, out, _, mm, sw, cv = oracle.projective_select(P, r, k, delta=delta, max_swaps=100, full=True)
+    assert st == 0 and cv == 1 and mm > 1e-8
+    Rp = r_prime(P, r)
+    S = list(out)
+    base = gram_det(Rp, S)
+    for c in range(items):
+        if c in S:
+            continue
+        for q in range(k):
+            T = S[:q] + [c] + S[q + 1:]
+            assert gram_det(Rp, T) <= (1 + delta) * base * (1 + 1e-9)
+    # and the exchanges only ever raised the volume of the greedy choice
+    g = oracle.projective_select(P, r, k, max_swaps=0)[1]
+    assert base >= gram_det(Rp, list(g)) * (1 - 1e-12)
+    print("exchanges", sw)
+
+
+def test_exchange_gain_is_the_product_of_eq_b_and_eq_a():
+    # the volume after one exchange equals the greedy set's volume times
+    # (1 + y_b^T (S S^T)^{-1} y_b) (1 - y_s^T (S' S'^T)^{-1} y_s)
+    P = np.random.default_rng(20).standard_normal((70, 10))
+    r, k = 4, 8
+    g = list(oracle.projective_select(P, r, k, max_swaps=0)[1])
+    st, one, _, _, sw, cv = oracle.projective_select(P, r, k, delta=0.0, max_swaps=1, full=True)
+    assert st == 0 and sw == 1
+    Rp = r_prime(P, r)
+    b = [i for i in one if i not in g]
+    s_ = [i for i in g if i not in one]
+    assert len(b) == 1 and len(s_) == 1
+    M = Rp[:, g] @ Rp[:, g].T
+    yb = Rp[:, b[0]]
+    grow = 1 + yb @ np.linalg.solve(M, yb)
+    M2 = M + np.outer(yb, yb)
+    ys = Rp[:, s_[0]]
+    shrink = 1 - ys @ np.linalg.solve(M2, ys)
+    assert gram_det(Rp, list(one)) == pytest.approx(gram_det(Rp, g) * grow * shrink, rel=1e-9)
+    assert grow * shrink > 1.0
+
+
+def test_refinement_caps_and_thresholds():
+    P = np.random.default_rng(30).standard_normal((200, 20))
+    full = oracle.projective_select(P, 8, 12, delta=0.0, max_swaps=100, full=True)
+    assert full[4] == 2 and full[5] == 1
+    capped = oracle.projective_select(P, 8, 12, delta=0.0, max_swaps=1, full=True)
+    assert capped[4] == 1 and capped[5] == 0          # stopped by the cap with gain left
+    none = oracle.projective_select(P, 8, 12, delta=1e9, max_swaps=100, full=True)
+    greedy = oracle.projective_select(P, 8, 12, max_swaps=0)
+    assert none[4] == 0 and none[5] == 1 and none[1].tolist() == greedy[1].tolist()
+    # r = 1: the greedy order of |R'_i| is already locally maximal
+    r1 = oracle.projective_select(P, 1, 6, delta=0.0, max_swaps=100, full=True)
+    assert r1[4] == 0 and r1[5] == 1
 
 
 def test_bigger_generators_do_not_lose_accuracy():
