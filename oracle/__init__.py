@@ -77,6 +77,7 @@ def lib():
         L.orc_feistel.restype = i64
         L.orc_bidiag_column.argtypes = [u64, i64, ct.c_int, i64, P, P, P]
         L.orc_sketch_bidiag.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
+        L.orc_sketch_fourier.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
         L.orc_cynical.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P,
                                   P, P]
         L.orc_pinv_trunc.argtypes = [P, ct.c_int, ct.c_int, ct.c_int, P, P, P]
@@ -89,7 +90,7 @@ def lib():
                   "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
                   "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag",
                   "orc_hadamard_apply", "orc_pinv_trunc", "orc_projective_select", "orc_projective_cur",
-                  "orc_draw_uniform", "orc_uniform_cur"):
+                  "orc_draw_uniform", "orc_uniform_cur", "orc_sketch_fourier"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -184,6 +185,20 @@ def sketch(A: np.ndarray, side: int, d: int, l: int, seed: int):
     st = lib().orc_sketch(_p(A), _dtype_code(A), m, n, n, side, d, l, seed, _p(Y), _p(smp))
     if st:
         raise ValueError("sketch: status %d" % st)
+    return Y, smp
+
+
+def sketch_fourier(A: np.ndarray, side: int, d: int, l: int, seed: int):
+    """Abridged randomized Fourier sketch in real form: (Y items x 2l with
+    Re y_q at q and Im y_q at l + q, sampled columns)."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    items = n if side else m
+    Y = np.zeros((items, 2 * l))
+    smp = np.zeros(l, np.int64)
+    st = lib().orc_sketch_fourier(_p(A), _dtype_code(A), m, n, n, side, d, l, seed, _p(Y), _p(smp))
+    if st:
+        raise ValueError("sketch_fourier: status %d" % st)
     return Y, smp
 
 

@@ -307,6 +307,68 @@ int orc_sketch(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Abridged randomized Fourier sketch (App. B, the d-abridged DFT Omega_{N,d} */
+/* of eq. (eqfd): the decimation-in-frequency recursion stopped after d      */
+/* stages, Omega_s replaced by I_s, N = 2^d s).  Carrying the recursion out  */
+/* with the stage twiddles omega_{2q}^i, i < q (the printed diag(omega_n^i)_ */
+/* {i<n} has the wrong size: a length-2q stage multiplies the difference    */
+/* half by the 2q-th roots of unity), output (k, e) of the abridged         */
+/* transform is sum over a of x_{a s + e} omega_N^{k (a s + e)}, omega_N =   */
+/* exp(2 pi i / N): column b s + e of the multiplier has the 2^d entries     */
+/* omega_N^{b j} at rows j = a s + e (its rows and columns are orthogonal,  */
+/* squared norm 2^d; completing every class e with an s-point DFT yields    */
+/* the N-point DFT).  D: for a real input, the uniform law on the complex   */
+/* unit circle is read as uniform on {1, i, -1, -i}: D_j = i^{t_j}, t_j the */
+/* top two bits of SplitMix64 stream 1 at j.  l columns sampled as for the  */
+/* SRHT (stream 2, distinct), scale sqrt(s / l).  Complex arithmetic in its */
+/* real form: sampled column q contributes Re y_q as coordinate q and Im y_q */
+/* as coordinate l + q of a real items x 2l sketch, so that the real QRP of  */
+/* the seed runs on it (W real: W M = W Re M + i W Im M).  Sides as for     */
+/* orc_sketch; dimensions padded to N with zeros.                           */
+/* ------------------------------------------------------------------------ */
+int orc_sketch_fourier(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int side, int d, int l,
+                       uint64_t seed, double *Y, int64_t *samples) {
+    if (!A || !Y || !samples || d < 0 || d > 20 || l < 1 || m < 1 || n < 1 || lda < n) return ORC_EINVAL;
+    int64_t dim = side ? m : n;
+    int64_t items = side ? n : m;
+    int64_t q2 = (int64_t)1 << d;
+    int64_t s = (dim + q2 - 1) / q2;
+    int64_t N = q2 * s;
+    if (l > N) return ORC_EINVAL;
+    int st = orc_draw_distinct(seed, 2, N, l, samples);
+    if (st) return st;
+    const double scale = sqrt((double)s / (double)l);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t it = 0; it < items; it++) {
+        for (int q = 0; q < l; q++) {
+            int64_t t = samples[q];
+            int64_t b = t / s, e = t % s;
+            double re = 0.0, im = 0.0;
+            for (int64_t a = 0; a < q2; a++) {
+                int64_t j = a * s + e;
+                if (j >= dim) continue;
+                double w = side ? orc_get(A, dtype, lda, j, it) : orc_get(A, dtype, lda, it, j);
+                /* omega_N^{b j} times i^{t_j}: the angle 2 pi (b j mod N) / N + t_j pi / 2 */
+                int64_t mexp = (int64_t)(((unsigned __int128)b * (unsigned __int128)j) % (unsigned __int128)N);
+                double ang = two_pi * (double)mexp / (double)N;
+                double c = cos(ang), sn = sin(ang);
+                int tq = (int)(orc_rng_u64(seed, 1, (uint64_t)j) >> 62);
+                double cr, ci;  /* (c + i sn) i^tq */
+                if (tq == 0) { cr = c; ci = sn; }
+                else if (tq == 1) { cr = -sn; ci = c; }
+                else if (tq == 2) { cr = -c; ci = -sn; }
+                else { cr = sn; ci = -c; }
+                re += w * cr;
+                im += w * ci;
+            }
+            Y[it * 2 * l + q] = scale * re;
+            Y[it * 2 * l + l + q] = scale * im;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Quasi-Gaussian multipliers made of random bidiagonal factors (the        */
 /* section on pre-processing with quasi Gaussian matrices, eq. (def11)):    */
 /* G_q = B_1 P_1 B_2 P_2 ... B_q P_q with B_i cyclic bidiagonal (ones on     */
@@ -691,7 +753,7 @@ int orc_nucleus(const double *G, int r, int refine_steps, double *U, double *log
 typedef struct {
     double delta;
     int32_t max_swaps;
-    int32_t preprocess;   /* 0 none, 1 abridged SRHT, 2 random bidiagonal factors */
+    int32_t preprocess;   /* 0 none, 1 abridged SRHT, 2 random bidiagonal factors, 3 abridged SRFT */
     int32_t ah_depth;
     int32_t ah_samples;
     int32_t refine_steps;
@@ -753,7 +815,7 @@ int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
     info.rank_found = r;
     if (!A || !I_out || !J_out || !U_out || r < 1 || sweeps < 1 || m < 1 || n < 1 || lda < n ||
         (int64_t)r > (m < n ? m : n) || dtype < 0 || dtype > 2 || !(o.delta >= 0.0) ||
-        (o.preprocess != 0 && o.preprocess != 1 && o.preprocess != 2)) {
+        (o.preprocess != 0 && o.preprocess != 1 && o.preprocess != 2 && o.preprocess != 3)) {
         if (info_out) *info_out = info;
         return ORC_EINVAL;
     }
@@ -763,23 +825,25 @@ int orc_ca_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
     int64_t *Jp = (int64_t *)malloc(sizeof(int64_t) * (size_t)r);
     int st = ORC_OK;
 
-    if (o.preprocess == 1 || o.preprocess == 2) {
+    if (o.preprocess == 1 || o.preprocess == 2 || o.preprocess == 3) {
         /* pre-multiplication for m >= n (the paper allows either form when   */
         /* m = n; this one yields the start columns directly)                */
         int side = (m >= n) ? 1 : 0;
         int64_t items = side ? n : m;
         int l = o.ah_samples;
-        if (l < r) { st = ORC_EINVAL; goto done; }
-        double *Y = (double *)malloc(sizeof(double) * (size_t)items * (size_t)l);
+        int wy = o.preprocess == 3 ? 2 * l : l;  /* real width of the sketch */
+        if (wy < r) { st = ORC_EINVAL; goto done; }
+        double *Y = (double *)malloc(sizeof(double) * (size_t)items * (size_t)wy);
         int64_t *smp = (int64_t *)malloc(sizeof(int64_t) * (size_t)l);
-        st = o.preprocess == 1 ? orc_sketch(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp)
-                               : orc_sketch_bidiag(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp);
+        st = o.preprocess == 1   ? orc_sketch(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp)
+             : o.preprocess == 2 ? orc_sketch_bidiag(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp)
+                                 : orc_sketch_fourier(A, dtype, m, n, lda, side, o.ah_depth, l, seed, Y, smp);
         int32_t rk = r;
         if (st == ORC_OK) {
-            for (int64_t q = 0; q < items * l; q++)
+            for (int64_t q = 0; q < items * wy; q++)
                 if (!isfinite(Y[q])) { st = ORC_EINVAL; break; }
         }
-        if (st == ORC_OK) st = orc_qrp(Y, items, l, r, side ? J : I, &rk, &info.min_margin);
+        if (st == ORC_OK) st = orc_qrp(Y, items, wy, r, side ? J : I, &rk, &info.min_margin);
         if (st == ORC_ESINGULAR) info.rank_found = rk;
         free(Y); free(smp);
         if (st) goto done;
