@@ -62,11 +62,19 @@ typedef enum {
     LRA_PRE_ASRHT = 1, /* start set from greedy QRP on an abridged SRHT sketch: columns
                           of M^T W (m >= n, the start column set itself) or rows of
                           W M (m < n, followed by one row step) */
-    LRA_PRE_BIDIAG = 2 /* the same with the quasi-Gaussian multiplier of random
+    LRA_PRE_BIDIAG = 2, /* the same with the quasi-Gaussian multiplier of random
                           bidiagonal factors G_q = B_1 P_1 ... B_q P_q (eq. (def11),
                           section on pre-processing with quasi Gaussian matrices),
                           q = ah_depth <= 6 factors, l = ah_samples sampled columns;
                           the multiplied dimension must stay below 2^31 */
+    LRA_PRE_ASRFT = 3  /* the same with the abridged randomized Fourier multiplier
+                          D Omega_{N,d} (App. B, eq. (eqfd) stopped after d <= 3
+                          stages: column b s + e holds omega_N^{b j} at rows
+                          j = a s + e, omega_N = exp(2 pi i / N)), D_j = i^{t_j}
+                          with t_j the top two bits of SplitMix64 stream 1, l =
+                          ah_samples complex columns (r <= 2l, l 2^d <= 1008,
+                          l <= 128); the seed QRP runs on the real form of the
+                          sketch, Re y_q and Im y_q as coordinates q and l + q */
 } lra_pre;
 
 typedef struct {

@@ -22,7 +22,7 @@ HEADER = os.path.join(ROOT, "include", "lra_cur.h")
 
 LRA_OK, LRA_EINVAL, LRA_ESINGULAR, LRA_EDEVICE, LRA_ENOMEM, LRA_EUNSUPPORTED = range(6)
 LRA_F64, LRA_F32, LRA_BF16 = 0, 1, 2
-LRA_PRE_NONE, LRA_PRE_ASRHT, LRA_PRE_BIDIAG = 0, 1, 2
+LRA_PRE_NONE, LRA_PRE_ASRHT, LRA_PRE_BIDIAG, LRA_PRE_ASRFT = 0, 1, 2, 3
 LRA_PREC_PLAIN, LRA_PREC_MIXED = 0, 1
 
 

@@ -102,7 +102,8 @@ lra_status fill_config(const lra_opts *opts, int32_t r, int32_t sweeps, CAConfig
     if (opts) o = *opts;
     else lra_default_opts(&o);
     if (!(o.delta >= 0.0) || !std::isfinite(o.delta)) return LRA_EINVAL;
-    if (o.preprocess != LRA_PRE_NONE && o.preprocess != LRA_PRE_ASRHT && o.preprocess != LRA_PRE_BIDIAG)
+    if (o.preprocess != LRA_PRE_NONE && o.preprocess != LRA_PRE_ASRHT && o.preprocess != LRA_PRE_BIDIAG &&
+        o.preprocess != LRA_PRE_ASRFT)
         return LRA_EINVAL;
     if (o.max_swaps < 0) o.max_swaps = 16 * r;
     if (o.ah_samples <= 0) o.ah_samples = 2 * r;
@@ -114,6 +115,13 @@ lra_status fill_config(const lra_opts *opts, int32_t r, int32_t sweeps, CAConfig
     if (o.preprocess == LRA_PRE_BIDIAG) {
         if (o.ah_depth < 0 || (1 << o.ah_depth) > lra::kBdTerms) return LRA_EINVAL;
         if (o.ah_samples < r || o.ah_samples > kLMax) return LRA_EINVAL;
+    }
+    if (o.preprocess == LRA_PRE_ASRFT) {
+        // the coefficient table (l 2^d complex entries) lives in the LU
+        // scratch of the workgroup, which the sketch does not use
+        if (o.ah_depth < 0 || o.ah_depth > 3) return LRA_EINVAL;
+        if (2 * o.ah_samples < r || 2 * o.ah_samples > kLMax || (o.ah_samples << o.ah_depth) > lra::kAftCoefs)
+            return LRA_EINVAL;
     }
     c->r = r;
     c->sweeps = sweeps;
@@ -151,7 +159,7 @@ LdsPlan plan_lds(int64_t m, int64_t n, int r, int pre, int l, int team, size_t b
     // panels are slot-major with the slot stride rounded up to odd
     size_t cells = std::max((size_t)(ipw | 1) * r, (size_t)4 * r * r);
     int64_t flag_items = ipw;
-    if (pre == LRA_PRE_ASRHT || pre == LRA_PRE_BIDIAG) {
+    if (pre == LRA_PRE_ASRHT || pre == LRA_PRE_BIDIAG || pre == LRA_PRE_ASRFT) {
         p.ipw_s = ((m >= n) ? (n + team - 1) / team : (m + team - 1) / team);
         const size_t sk = (size_t)(p.ipw_s | 1) * l;
         const size_t with = align16(std::max(cells, sk) * sizeof(double)) + align16(std::max(ipw, p.ipw_s));
@@ -229,7 +237,7 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     lra_opts o;
     lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
     if (st != LRA_OK) return st;
-    if (o.preprocess == LRA_PRE_ASRHT) {
+    if (o.preprocess == LRA_PRE_ASRHT || o.preprocess == LRA_PRE_ASRFT) {
         const int64_t dim = (m >= n) ? m : n;  // the dimension the multiplier acts on
         const int64_t q2 = (int64_t)1 << o.ah_depth;
         const int64_t N = q2 * ((dim + q2 - 1) / q2);
@@ -262,22 +270,24 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     // the best trade-off measured on the 20000 x 20000 rank-50 workload).
     int team;
     LdsPlan plan;
+    // real width of the sketch panel (the Fourier sketch keeps Re and Im)
+    const int wsk = o.preprocess == LRA_PRE_ASRFT ? 2 * o.ah_samples : o.ah_samples;
     if (o.team_size > 0) {
         team = std::min(o.team_size, max_team);
-        plan = plan_lds(m, n, r, o.preprocess, o.ah_samples, team, lds_budget);
+        plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
     } else {
         team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, n) + 159) / 160));
-        plan = plan_lds(m, n, r, o.preprocess, o.ah_samples, team, lds_budget);
+        plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
         while (!plan.fits && team < max_team) {
             team++;
-            plan = plan_lds(m, n, r, o.preprocess, o.ah_samples, team, lds_budget);
+            plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
         }
     }
     if (!plan.fits) return LRA_EUNSUPPORTED;
     cfg.panel_bytes = (int32_t)plan.panel_bytes;
     const size_t dyn = plan.dyn_bytes;
     if (plan.sketch_global) {
-        const size_t need = (size_t)team * (plan.ipw_s | 1) * o.ah_samples * sizeof(double);
+        const size_t need = (size_t)team * (plan.ipw_s | 1) * wsk * sizeof(double);
         if (ws->sketch_cap < need) {
             (void)hipStreamSynchronize(stream);
             (void)hipFree(ws->sketch);

@@ -31,6 +31,7 @@ namespace lra {
 
 constexpr int kNWave = kBlock / kWave;
 static_assert(kNWave <= 8, "the workgroup reduction combines at most eight wavefront partials");
+static_assert(2 * kAftCoefs <= kRMax * (kRMax - 1) / 2, "the Fourier coefficient table fits the LU scratch");
 constexpr int kChunk = 8;  // entries staged in registers per LDS round trip
 
 // ---------------------------------------------------------------- tracing
@@ -1159,7 +1160,7 @@ __device__ __forceinline__ void team_qrp(Team &tm, Smem &sm, double *panel, uint
 // lazily, fused with the next norm scan.  The chosen items land in out.
 // With `bd` (a bidiagonal-multiplier column table) the sketch entries are the
 // table's signed-integer combinations of W's entries instead.
-template <class Src>
+template <bool kFourier, class Src>
 __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Src &src, int64_t m,
                                           int64_t n, int r, int side, int d, int l, uint64_t seed, int64_t *out,
                                           const int32_t *bd) {
@@ -1170,6 +1171,59 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
     const int64_t s = (dim + q2 - 1) / q2;
     const int64_t N = q2 * s;
     int bad = 0;
+    if constexpr (kFourier) {
+        // abridged randomized Fourier multiplier: sampled column t = b s + e
+        // has coefficient i^{t_j} omega_N^{b j} at rows j = a s + e (zero past
+        // the end); the table (cos and sin parts, l 2^d <= kAftCoefs each) sits
+        // in the LU scratch, which no sketch touches
+        if (tid < kWave) draw_distinct_wave(seed, 2, N, l, sm.samples);
+        __syncthreads();
+        double *const cre = sm.L11, *const cim = sm.L11 + kAftCoefs;
+        const double two_pi = 6.283185307179586476925286766559;
+        for (int e2 = tid; e2 < l * (int)q2; e2 += kBlock) {
+            const int q = e2 / (int)q2, a = e2 % (int)q2;
+            const int64_t t = sm.samples[q];
+            const int64_t bb = t / s, ee = t % s;
+            const int64_t j = a * s + ee;
+            double cr = 0.0, ci = 0.0;
+            if (j < dim) {
+                const int64_t mexp = (int64_t)(((uint64_t)bb * (uint64_t)j) % (uint64_t)N);
+                const double ang = two_pi * (double)mexp / (double)N;
+                const double c = cos(ang), sn = sin(ang);
+                const int tq = (int)(sm64(seed, 1, (uint64_t)j) >> 62);
+                cr = tq == 0 ? c : tq == 1 ? -sn : tq == 2 ? -c : sn;
+                ci = tq == 0 ? sn : tq == 1 ? c : tq == 2 ? -sn : -c;
+            }
+            cre[e2] = cr;
+            cim[e2] = ci;
+        }
+        __syncthreads();
+        LRA_TR(2, 0);
+        const double scale = sqrt((double)s / (double)l);
+        const int tot = g.cnt * l;
+        for (int e = tid; e < tot; e += kBlock) {
+            const int li = e % g.cnt, q = e / g.cnt;
+            const int64_t it = g.base + li;
+            const int64_t ee = sm.samples[q] % s;
+            double w[8];
+#pragma unroll
+            for (int a = 0; a < 8; a++) {
+                const int64_t j = a * s + ee;
+                w[a] = (a < q2 && j < dim) ? (side ? src(j, it) : src(it, j)) : 0.0;
+            }
+            double re = 0.0, im = 0.0;
+#pragma unroll
+            for (int a = 0; a < 8; a++)
+                if (a < q2 && a * s + ee < dim) {
+                    re += w[a] * cre[q * (int)q2 + a];
+                    im += w[a] * cim[q * (int)q2 + a];
+                }
+            const double yr = scale * re, yi = scale * im;
+            if (!isfinite(yr) || !isfinite(yi)) bad = 1;
+            panel[q * g.st + li] = yr;
+            panel[(l + q) * g.st + li] = yi;
+        }
+    } else {
     if (bd) {
         // bidiagonal-product multiplier: y = sum over the sampled column's
         // terms, in ascending position order, of coef * w (no scale)
@@ -1279,10 +1333,11 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
         }
     }
     }  // sketch forms
+    }  // the Fourier form is a separate instantiation
     for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
     LRA_TR(3, 0);
-    team_qrp(tm, sm, panel, flags, g, l, r, bad, false, out, nullptr, nullptr);
+    team_qrp(tm, sm, panel, flags, g, kFourier ? 2 * l : l, r, bad, false, out, nullptr, nullptr);
     if (sm.status != LRA_OK) return;
     __syncthreads();
 #ifdef LRA_TRACE
@@ -1660,7 +1715,9 @@ __device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src
 // The whole C-A path for one matrix, executed by every workgroup of a team.
 // imap / jmap (optional) translate the returned row and column ids (a solve
 // on a sketch); swaps_base and team_report fold in an earlier phase.
-template <class Src>
+// kFourier: the instantiation that seeds from the abridged Fourier sketch
+// (a separate kernel, so that the other starts carry none of its code).
+template <bool kFourier = false, class Src>
 __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const Src &src, int64_t m,
                                         int64_t n, uint64_t seed, const CAConfig &cfg, int64_t *I_out, int64_t *J_out,
                                         double *U_out, lra_info *info, const int64_t *imap = nullptr,
@@ -1685,7 +1742,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     LRA_TR(1, 0);
     __syncthreads();
     // ---- start set
-    if (cfg.pre == LRA_PRE_ASRHT || cfg.pre == LRA_PRE_BIDIAG) {
+    if (cfg.pre == LRA_PRE_ASRHT || cfg.pre == LRA_PRE_BIDIAG || cfg.pre == LRA_PRE_ASRFT) {
         // pre-multiplication for m >= n (either form is allowed when m = n;
         // this one reads whole rows of W and yields the start columns directly)
         const int side = (m >= n) ? 1 : 0;
@@ -1695,11 +1752,12 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
         // (two call sites so that each copy knows its panel's address space)
         if (cfg.sketch_ws) {
             const int64_t st_s = (((side ? n : m) + tm.size - 1) / tm.size) | 1;
-            sketch_qrp(tm, sm, cfg.sketch_ws + (size_t)tm.rank * st_s * cfg.ah_samples, flags, src, m, n, r, side,
-                       cfg.ah_depth, cfg.ah_samples, seed, side ? sm.Jset : sm.Iset, bd);
+            const int wsk = kFourier ? 2 * cfg.ah_samples : cfg.ah_samples;
+            sketch_qrp<kFourier>(tm, sm, cfg.sketch_ws + (size_t)tm.rank * st_s * wsk, flags, src, m, n, r, side,
+                                 cfg.ah_depth, cfg.ah_samples, seed, side ? sm.Jset : sm.Iset, bd);
         } else {
-            sketch_qrp(tm, sm, dyn, flags, src, m, n, r, side, cfg.ah_depth, cfg.ah_samples, seed,
-                       side ? sm.Jset : sm.Iset, bd);
+            sketch_qrp<kFourier>(tm, sm, dyn, flags, src, m, n, r, side, cfg.ah_depth, cfg.ah_samples, seed,
+                                 side ? sm.Jset : sm.Iset, bd);
         }
         if (sm.status != LRA_OK) goto finish;
         if (tid < kWave) sort_set_wave(side ? sm.Jset : sm.Iset, r);
@@ -1781,7 +1839,7 @@ finish:
 }
 
 // ---------------------------------------------------------------- kernels
-template <typename T>
+template <typename T, bool kFourier = false>
 __global__ void __launch_bounds__(kBlock) ca_team_kernel(const T *A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
                                                          CAConfig cfg, TeamWs ws, int64_t *I_out, int64_t *J_out,
                                                          double *U_out, lra_info *info) {
@@ -1795,7 +1853,7 @@ __global__ void __launch_bounds__(kBlock) ca_team_kernel(const T *A, int64_t m, 
     tm.epoch = 0;
     tm.xw = ws.xw;
     tm.spin_limit = ws.spin_limit;
-    ca_solve(tm, sm, dyn, flags, DenseSrc<T>{A, lda}, m, n, seed, cfg, I_out, J_out, U_out, info);
+    ca_solve<kFourier>(tm, sm, dyn, flags, DenseSrc<T>{A, lda}, m, n, seed, cfg, I_out, J_out, U_out, info);
 }
 
 // C-A CUR of the pre-processed matrix W' = W M (HadamardSrc), m x N.
@@ -2150,7 +2208,7 @@ template <typename T>
 static hipError_t launch_team_t(const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, const CAConfig &cfg,
                                 const TeamWs &ws, int team, size_t dyn_bytes, int64_t *I_out, int64_t *J_out,
                                 double *U_out, lra_info *info, hipStream_t stream) {
-    auto kern = ca_team_kernel<T>;
+    auto kern = cfg.pre == LRA_PRE_ASRFT ? ca_team_kernel<T, true> : ca_team_kernel<T, false>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     if (team > 1) {
@@ -2406,7 +2464,7 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
 size_t static_lds_bytes() {
     static size_t bytes = 0;
     if (bytes == 0) {
-        const void *fns[19] = {(const void *)ca_team_kernel<double>,       (const void *)ca_team_kernel<float>,
+        const void *fns[22] = {(const void *)ca_team_kernel<double>,       (const void *)ca_team_kernel<float>,
                                (const void *)ca_team_kernel<uint16_t>,     (const void *)ca_batched_kernel<double>,
                                (const void *)ca_batched_kernel<float>,     (const void *)ca_batched_kernel<uint16_t>,
                                (const void *)ca_points_kernel,             (const void *)ca_cynical_kernel<double>,
@@ -2415,7 +2473,8 @@ size_t static_lds_bytes() {
                                (const void *)ca_hadamard_kernel<uint16_t>, (const void *)ca_projective_kernel<double>,
                                (const void *)ca_projective_kernel<float>,  (const void *)ca_projective_kernel<uint16_t>,
                                (const void *)ca_uniform_kernel<double>,    (const void *)ca_uniform_kernel<float>,
-                               (const void *)ca_uniform_kernel<uint16_t>};
+                               (const void *)ca_uniform_kernel<uint16_t>,  (const void *)ca_team_kernel<double, true>,
+                               (const void *)ca_team_kernel<float, true>,  (const void *)ca_team_kernel<uint16_t, true>};
         size_t mx = sizeof(Smem) + sizeof(int) * kRMax;
         for (const void *f : fns) {
             hipFuncAttributes attr;

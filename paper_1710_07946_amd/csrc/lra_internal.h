@@ -31,6 +31,11 @@ struct CAConfig {
     const int32_t *bd_table;  // bidiagonal start: per sampled column its term count, positions, coefficients
 };
 
+// Complex coefficients of the abridged Fourier sketch (l 2^d <= kAftCoefs,
+// cos and sin each): they fit the LU scratch of Smem (kRMax (kRMax - 1) / 2
+// doubles).
+constexpr int kAftCoefs = 1008;
+
 // Terms of one sampled column of the bidiagonal-product multiplier (2^q, q <= 6).
 constexpr int kBdTerms = 64;
 // Table layout: cnt[kLMax], then pos[kLMax][kBdTerms], then coef[kLMax][kBdTerms].

@@ -138,6 +138,25 @@ def test_cynical_invalid_arguments_rejected_on_host(lib):
     assert call(opts=ct.byref(o)) == E
 
 
+def test_fourier_start_invalid_arguments_rejected_on_host(lib):
+    fake = ct.c_void_p(0x1000)
+    E = lra.LRA_EINVAL
+
+    def call(d=3, l=20, r=8, m=500, n=400):
+        o = lra.lra_default_opts()
+        o.preprocess = lra.LRA_PRE_ASRFT
+        o.ah_depth = d
+        o.ah_samples = l
+        return lib.lra_cur(fake, 1, m, n, n, r, 2, 1, ct.byref(o), fake, fake, fake, None, None)
+
+    assert call(d=4) == E            # more than three abridged stages
+    assert call(d=-1) == E
+    assert call(l=127) == E          # l 2^d above the coefficient table
+    assert call(l=3) == E            # 2l < r
+    assert call(d=0, l=129) == E     # 2l above the sketch width limit
+    assert call(l=100, d=0, m=60, n=50) == E    # more samples than columns of the multiplier
+
+
 def test_projective_invalid_arguments_rejected_on_host(lib):
     fake = ct.c_void_p(0x1000)
     E = lra.LRA_EINVAL

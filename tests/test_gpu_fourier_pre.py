@@ -1,0 +1,62 @@
+"""GPU parity of the C-A path started from the abridged randomized Fourier
+multiplier (App. B, eq. (eqfd) stopped after d stages; the seed QRP on the
+real form of the sketch) against the oracle; bar as in test_gpu_parity.  The
+two sides evaluate the twiddles' cosines and sines with their own libraries,
+so a sketch entry may differ in its last bit; decisions are compared where
+the oracle's margins allow."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_07946_amd import workloads
+from test_gpu_parity import assert_parity, gpu_cur
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lra():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1710_07946_amd as lra
+    lra.load()
+    return lra
+
+
+@pytest.mark.parametrize("d,l", [(0, 20), (1, 20), (2, 10), (3, 20), (3, 126)])
+def test_fourier_start_512_fp64(lra, d, l):
+    A = workloads.orthogonal_lowrank()
+    kw = dict(preprocess=3, ah_depth=d, ah_samples=l)
+    o = oracle.ca_cur(A, 10, 3, 2001, **kw)
+    g = gpu_cur(lra, A, 10, 3, 2001, **kw)
+    assert_parity(A, g, o, 1e-6)
+
+
+def test_fourier_start_wide_fp64(lra):
+    # m < n: the multiplier acts on the columns; its QRP picks rows and one row
+    # step turns them into the start columns
+    A = workloads.orthogonal_lowrank(300, 700, 8, noise=1e-7, seeds=(11, 12, 13))
+    kw = dict(preprocess=3, ah_depth=3, ah_samples=12)
+    o = oracle.ca_cur(A, 8, 3, 5, **kw)
+    g = gpu_cur(lra, A, 8, 3, 5, **kw)
+    assert_parity(A, g, o, 1e-6)
+
+
+@pytest.mark.parametrize("team", [2, 3, 7])
+def test_fourier_start_fp32_ragged_team(lra, team):
+    # 1998 rows: not a multiple of 2^d, so the multiplier pads with zeros
+    A = workloads.factor_gaussian(1998, 1500, 16, 1e-6, seeds=(7, 8, 9)).astype(np.float32)
+    kw = dict(preprocess=3, ah_depth=3, ah_samples=16)
+    o = oracle.ca_cur(A, 16, 3, 31, **kw)
+    g = gpu_cur(lra, A, 16, 3, 31, team_size=team, **kw)
+    assert g[3]["team_size"] == team
+    assert_parity(A, g, o, 1e-4)
+
+
+def test_fourier_start_rejects_bad_parameters(lra):
+    A = torch.zeros((64, 64), dtype=torch.float64, device="cuda")
+    for kw in (dict(ah_depth=4, ah_samples=8), dict(ah_depth=3, ah_samples=127), dict(ah_depth=3, ah_samples=4)):
+        with pytest.raises(lra.LraError):
+            lra.lra_cur(A, 10, 1, 1, preprocess=3, **kw)
