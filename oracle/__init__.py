@@ -78,6 +78,8 @@ def lib():
         L.orc_bidiag_column.argtypes = [u64, i64, ct.c_int, i64, P, P, P]
         L.orc_sketch_bidiag.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
         L.orc_sketch_fourier.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
+        L.orc_unit_root.argtypes = [i64, i64, P, P]
+        L.orc_unit_root.restype = None
         L.orc_cynical.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P,
                                   P, P]
         L.orc_pinv_trunc.argtypes = [P, ct.c_int, ct.c_int, ct.c_int, P, P, P]
@@ -186,6 +188,13 @@ def sketch(A: np.ndarray, side: int, d: int, l: int, seed: int):
     if st:
         raise ValueError("sketch: status %d" % st)
     return Y, smp
+
+
+def unit_root(m: int, N: int):
+    """(cos, sin) of 2 pi m / N by the oracle's fixed-order evaluation."""
+    c, s = ct.c_double(0.0), ct.c_double(0.0)
+    lib().orc_unit_root(m, N, ct.byref(c), ct.byref(s))
+    return c.value, s.value
 
 
 def sketch_fourier(A: np.ndarray, side: int, d: int, l: int, seed: int):

@@ -326,6 +326,61 @@ int orc_sketch(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int 
 /* the seed runs on it (W real: W M = W Re M + i W Im M).  Sides as for     */
 /* orc_sketch; dimensions padded to N with zeros.                           */
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* cos and sin of 2 pi m / N for integers 0 <= m < N, evaluated in a fixed   */
+/* order of IEEE operations (so that any implementation written from this   */
+/* definition gives the same bits): the octant o = floor(8 m / N) and the    */
+/* remainder rem = 8 m - o N are exact integers; the angle inside the       */
+/* octant is x = (pi/4) rem / N (or (pi/4) (N - rem) / N from the octant's  */
+/* far end for odd o), in [0, pi/4]; cos x and sin x are the Taylor series  */
+/* through x^20 and x^21 by Horner's rule in x^2, with coefficients from    */
+/* the recurrences a_k = -a_{k-1} / ((2k - 1) 2k), b_k = -b_{k-1} /         */
+/* (2k (2k + 1)); then the octant's symmetry.  pi/4 is the double nearest   */
+/* to it.  The truncation error is below 1e-23.                            */
+/* ------------------------------------------------------------------------ */
+static void orc_cos_sin_small(double x, double *c, double *s) {
+    double a[11], b[11];
+    a[0] = 1.0;
+    b[0] = 1.0;
+    for (int k = 1; k < 11; k++) {
+        a[k] = -a[k - 1] / (double)((2 * k - 1) * (2 * k));
+        b[k] = -b[k - 1] / (double)((2 * k) * (2 * k + 1));
+    }
+    double x2 = x * x;
+    double pc = a[10], ps = b[10];
+    for (int k = 9; k >= 0; k--) {
+        pc = pc * x2 + a[k];
+        ps = ps * x2 + b[k];
+    }
+    *c = pc;
+    *s = x * ps;
+}
+
+void orc_unit_root(int64_t m, int64_t N, double *c_out, double *s_out) {
+    const double pi4 = 0x1.921fb54442d18p-1;
+    int64_t u = 8 * m;
+    int64_t o = u / N;
+    int64_t rem = u - o * N;
+    double c, s;
+    if ((o & 1) == 0) {
+        orc_cos_sin_small((pi4 * (double)rem) / (double)N, &c, &s);
+        switch (o / 2) {
+        case 0: *c_out = c; *s_out = s; break;
+        case 1: *c_out = -s; *s_out = c; break;
+        case 2: *c_out = -c; *s_out = -s; break;
+        default: *c_out = s; *s_out = -c; break;
+        }
+    } else {
+        orc_cos_sin_small((pi4 * (double)(N - rem)) / (double)N, &c, &s);
+        switch ((o + 1) / 2) {
+        case 1: *c_out = s; *s_out = c; break;
+        case 2: *c_out = -c; *s_out = s; break;
+        case 3: *c_out = -s; *s_out = -c; break;
+        default: *c_out = c; *s_out = -s; break;
+        }
+    }
+}
+
 int orc_sketch_fourier(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int side, int d, int l,
                        uint64_t seed, double *Y, int64_t *samples) {
     if (!A || !Y || !samples || d < 0 || d > 20 || l < 1 || m < 1 || n < 1 || lda < n) return ORC_EINVAL;
@@ -338,7 +393,6 @@ int orc_sketch_fourier(const void *A, int dtype, int64_t m, int64_t n, int64_t l
     int st = orc_draw_distinct(seed, 2, N, l, samples);
     if (st) return st;
     const double scale = sqrt((double)s / (double)l);
-    const double two_pi = 6.283185307179586476925286766559;
     for (int64_t it = 0; it < items; it++) {
         for (int q = 0; q < l; q++) {
             int64_t t = samples[q];
@@ -348,10 +402,10 @@ int orc_sketch_fourier(const void *A, int dtype, int64_t m, int64_t n, int64_t l
                 int64_t j = a * s + e;
                 if (j >= dim) continue;
                 double w = side ? orc_get(A, dtype, lda, j, it) : orc_get(A, dtype, lda, it, j);
-                /* omega_N^{b j} times i^{t_j}: the angle 2 pi (b j mod N) / N + t_j pi / 2 */
+                /* omega_N^{b j} times i^{t_j} (orc_unit_root for the root) */
                 int64_t mexp = (int64_t)(((unsigned __int128)b * (unsigned __int128)j) % (unsigned __int128)N);
-                double ang = two_pi * (double)mexp / (double)N;
-                double c = cos(ang), sn = sin(ang);
+                double c, sn;
+                orc_unit_root(mexp, N, &c, &sn);
                 int tq = (int)(orc_rng_u64(seed, 1, (uint64_t)j) >> 62);
                 double cr, ci;  /* (c + i sn) i^tq */
                 if (tq == 0) { cr = c; ci = sn; }

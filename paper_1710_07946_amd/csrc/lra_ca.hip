@@ -1160,6 +1160,50 @@ __device__ __forceinline__ void team_qrp(Team &tm, Smem &sm, double *panel, uint
 // lazily, fused with the next norm scan.  The chosen items land in out.
 // With `bd` (a bidiagonal-multiplier column table) the sketch entries are the
 // table's signed-integer combinations of W's entries instead.
+// cos and sin of 2 pi m / N (0 <= m < N) in a fixed order of IEEE
+// operations, the oracle's definition: octant o = floor(8 m / N) and
+// remainder rem = 8 m - o N as integers; x = (pi/4) rem / N for even o, or
+// (pi/4) (N - rem) / N from the far end for odd o; cos x and sin x by their
+// Taylor series through x^20 and x^21 (Horner in x^2, coefficients from
+// a_k = -a_{k-1} / ((2k - 1) 2k) and b_k = -b_{k-1} / (2k (2k + 1))); then
+// the octant's symmetry.
+__device__ __forceinline__ void unit_root(int64_t m, int64_t N, double &c_out, double &s_out) {
+    const double pi4 = 0x1.921fb54442d18p-1;
+    const int64_t u = 8 * m;
+    const int64_t o = u / N;
+    const int64_t rem = u - o * N;
+    const bool odd = (o & 1) != 0;
+    const double x = (pi4 * (double)(odd ? N - rem : rem)) / (double)N;
+    double a = 1.0, b = 1.0;
+    double ak[11], bk[11];
+    ak[0] = a;
+    bk[0] = b;
+#pragma unroll
+    for (int k = 1; k < 11; k++) {
+        a = -a / (double)((2 * k - 1) * (2 * k));
+        b = -b / (double)((2 * k) * (2 * k + 1));
+        ak[k] = a;
+        bk[k] = b;
+    }
+    const double x2 = x * x;
+    double pc = ak[10], ps = bk[10];
+#pragma unroll
+    for (int k = 9; k >= 0; k--) {
+        pc = pc * x2 + ak[k];
+        ps = ps * x2 + bk[k];
+    }
+    const double c = pc, s = x * ps;
+    if (!odd) {
+        const int q = (int)(o / 2);
+        c_out = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+        s_out = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+    } else {
+        const int q = (int)((o + 1) / 2);
+        c_out = q == 1 ? s : q == 2 ? -c : q == 3 ? -s : c;
+        s_out = q == 1 ? c : q == 2 ? s : q == 3 ? -c : -s;
+    }
+}
+
 template <bool kFourier, class Src>
 __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Src &src, int64_t m,
                                           int64_t n, int r, int side, int d, int l, uint64_t seed, int64_t *out,
@@ -1179,7 +1223,6 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
         if (tid < kWave) draw_distinct_wave(seed, 2, N, l, sm.samples);
         __syncthreads();
         double *const cre = sm.L11, *const cim = sm.L11 + kAftCoefs;
-        const double two_pi = 6.283185307179586476925286766559;
         for (int e2 = tid; e2 < l * (int)q2; e2 += kBlock) {
             const int q = e2 / (int)q2, a = e2 % (int)q2;
             const int64_t t = sm.samples[q];
@@ -1188,8 +1231,8 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
             double cr = 0.0, ci = 0.0;
             if (j < dim) {
                 const int64_t mexp = (int64_t)(((uint64_t)bb * (uint64_t)j) % (uint64_t)N);
-                const double ang = two_pi * (double)mexp / (double)N;
-                const double c = cos(ang), sn = sin(ang);
+                double c, sn;
+                unit_root(mexp, N, c, sn);
                 const int tq = (int)(sm64(seed, 1, (uint64_t)j) >> 62);
                 cr = tq == 0 ? c : tq == 1 ? -sn : tq == 2 ? -c : sn;
                 ci = tq == 0 ? sn : tq == 1 ? c : tq == 2 ? -sn : -c;

@@ -60,3 +60,18 @@ def test_fourier_start_rejects_bad_parameters(lra):
     for kw in (dict(ah_depth=4, ah_samples=8), dict(ah_depth=3, ah_samples=127), dict(ah_depth=3, ah_samples=4)):
         with pytest.raises(lra.LraError):
             lra.lra_cur(A, 10, 1, 1, preprocess=3, **kw)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_fourier_sketch_is_bit_identical_at_full_width(lra, seed):
+    # r = 2l: the seed QRP uses every coordinate of the real sketch, so its
+    # last pivots are decided by tiny remainders; both sides evaluate the
+    # roots of unity in the same fixed order, so the sketches agree bit for
+    # bit and so do the sets and the nucleus, margins or not
+    A = np.random.default_rng(seed).standard_normal((64, 233)).astype(np.float32)
+    kw = dict(preprocess=3, ah_depth=2, ah_samples=8)
+    o = oracle.ca_cur(A, 16, 2, 77 + seed, **kw)
+    g = gpu_cur(lra, A, 16, 2, 77 + seed, team_size=5, **kw)
+    assert g[3]["status"] == o.status == 0
+    assert g[0].tolist() == o.I.tolist() and g[1].tolist() == o.J.tolist()
+    assert np.array_equal(g[2], o.U)

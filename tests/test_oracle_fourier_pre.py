@@ -97,3 +97,26 @@ def test_seed_picks_the_largest_sketch_row_first():
     # the C-A start columns are the QRP's first r pivots on that sketch
     c = oracle.ca_cur(W, 5, 1, 3, preprocess=3, ah_depth=2, ah_samples=10)
     assert c.status == 0
+
+
+def test_unit_roots_are_accurate_and_exactly_symmetric():
+    # the fixed-order evaluation against the C library's cos and sin (within
+    # 2 ulp of 1), conjugate symmetry m -> N - m bit for bit (except at the
+    # odd multiples of pi/4, where the cosine and sine series of pi/4 meet and
+    # may differ by one ulp), and the exact quarter points
+    g = np.random.default_rng(17)
+    for N in [1, 2, 3, 5, 8, 12, 236, 20000, 1000003, (1 << 39) - 7]:
+        ms = set(range(min(N, 40))) | {int(v) for v in g.integers(0, N, 40)}
+        for m in ms:
+            c, s = oracle.unit_root(m, N)
+            ang = 2 * np.pi * (m / N)
+            assert abs(c - np.cos(ang)) <= 4.5e-16 * max(1.0, m / N * 8) and abs(s - np.sin(ang)) <= 4.5e-16 * max(1.0, m / N * 8)
+            if m > 0 and not ((8 * m) % N == 0 and ((8 * m) // N) % 2 == 1):
+                c2, s2 = oracle.unit_root(N - m, N)
+                assert c2 == c and s2 == -s
+    for N in [4, 8, 12, 100]:
+        for k in range(4):
+            c, s = oracle.unit_root(k * N // 4, N)
+            assert (c, s) in [(1.0, 0.0), (0.0, 1.0), (-1.0, 0.0), (0.0, -1.0)]
+    c, s = oracle.unit_root(1, 8)
+    assert abs(c - np.sqrt(0.5)) <= 2.3e-16 and abs(s - np.sqrt(0.5)) <= 2.3e-16
