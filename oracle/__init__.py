@@ -79,6 +79,9 @@ def lib():
         L.orc_sketch_bidiag.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
         L.orc_sketch_fourier.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
         L.orc_unit_root.argtypes = [i64, i64, P, P]
+        L.orc_leverage_scores.argtypes = [P, i64, ct.c_int, P, P]
+        L.orc_leverage_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, ct.c_int, ct.c_int, u64, P, P, P,
+                                       P]
         L.orc_unit_root.restype = None
         L.orc_cynical.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P,
                                   P, P]
@@ -92,7 +95,8 @@ def lib():
                   "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
                   "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag",
                   "orc_hadamard_apply", "orc_pinv_trunc", "orc_projective_select", "orc_projective_cur",
-                  "orc_draw_uniform", "orc_uniform_cur", "orc_sketch_fourier"):
+                  "orc_draw_uniform", "orc_uniform_cur", "orc_sketch_fourier", "orc_leverage_scores",
+                  "orc_leverage_cur"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -387,6 +391,35 @@ def uniform_cur(A: np.ndarray, r: int, k: int, l: int, seed: int) -> CurResult:
     U = np.zeros((l, k))
     info = _Info()
     st = lib().orc_uniform_cur(_p(A), _dtype_code(A), m, n, n, r, k, l, seed, _p(I), _p(J), _p(U), ct.byref(info))
+    return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
+                     info.min_margin, info.det_log_abs, info.nucleus_rank)
+
+
+def leverage_scores(P: np.ndarray):
+    """(status, q, cdf): leverage scores of the rows of P (items x r) in its
+    column space and their running sums."""
+    P = np.ascontiguousarray(P, np.float64)
+    items, r = P.shape
+    q = np.zeros(items)
+    cdf = np.zeros(items)
+    st = lib().orc_leverage_scores(_p(P), items, r, _p(q), _p(cdf))
+    return st, q, cdf
+
+
+def leverage_cur(A: np.ndarray, I0, J0, k: int, l: int, seed: int) -> CurResult:
+    """Refinement of the CUR of (I0, J0) by its leverage scores (see
+    orc_leverage_cur): I has k rows, J l columns, U is l x k."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    I0 = np.ascontiguousarray(I0, np.int64)
+    J0 = np.ascontiguousarray(J0, np.int64)
+    r = len(I0)
+    I = np.full(k, -1, np.int64)
+    J = np.full(l, -1, np.int64)
+    U = np.zeros((l, k))
+    info = _Info()
+    st = lib().orc_leverage_cur(_p(A), _dtype_code(A), m, n, n, r, _p(I0), _p(J0), k, l, seed, _p(I), _p(J),
+                                _p(U), ct.byref(info))
     return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
                      info.min_margin, info.det_log_abs, info.nucleus_rank)
 

@@ -1642,3 +1642,154 @@ int orc_uniform_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda,
     if (info_out) *info_out = info;
     return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Leverage scores of the items of a panel P (items x r, item-major) with   */
+/* respect to its column space: q_i = P_i (P^T P)^{-1} P_i^T, formed as      */
+/* |L^{-1} P_i^T|^2 with L the lower Cholesky factor of the Gram matrix      */
+/* P^T P (every entry summed over the items in increasing order, the solve  */
+/* and the norm in increasing index order).  cdf[i] = q_0 + ... + q_i in    */
+/* that order.  Status singular when the Gram matrix is not positive        */
+/* definite.                                                                */
+/* ------------------------------------------------------------------------ */
+static int orc_leverage(const double *P, int64_t items, int r, double *q, double *cdf) {
+    double *Gm = (double *)calloc((size_t)r * (size_t)r, sizeof(double));
+    double *L = (double *)calloc((size_t)r * (size_t)r, sizeof(double));
+    double *z = (double *)malloc(sizeof(double) * (size_t)r);
+    int st = ORC_OK;
+    for (int a = 0; a < r; a++)
+        for (int b = 0; b <= a; b++) {
+            double s = 0.0;
+            for (int64_t i = 0; i < items; i++) s += P[i * r + a] * P[i * r + b];
+            Gm[a * r + b] = s;
+        }
+    for (int a = 0; a < r && st == ORC_OK; a++)
+        for (int b = 0; b <= a; b++) {
+            double s = Gm[a * r + b];
+            for (int c = 0; c < b; c++) s -= L[a * r + c] * L[b * r + c];
+            if (a == b) {
+                if (!(s > 0.0)) { st = ORC_ESINGULAR; break; }
+                L[a * r + a] = sqrt(s);
+            } else {
+                L[a * r + b] = s / L[b * r + b];
+            }
+        }
+    double acc = 0.0;
+    for (int64_t i = 0; i < items && st == ORC_OK; i++) {
+        double s = 0.0;
+        for (int a = 0; a < r; a++) {
+            double x = P[i * r + a];
+            for (int c = 0; c < a; c++) x -= L[a * r + c] * z[c];
+            z[a] = x / L[a * r + a];
+            s += z[a] * z[a];
+        }
+        q[i] = s;
+        acc += s;
+        cdf[i] = acc;
+    }
+    free(Gm); free(L); free(z);
+    return st;
+}
+
+/* k i.i.d. draws by scores (Algorithm algsmplex, exactly k items, item i    */
+/* with probability q_i / S, S = cdf[items - 1]): draw t takes u_t = (x >>   */
+/* 11) 2^-53 from SplitMix64 output t of `stream` and picks the first item   */
+/* i with cdf[i] > u_t S.                                                    */
+static void orc_sample_scores(const double *cdf, int64_t items, uint64_t seed, uint64_t stream, int k, int64_t *out) {
+    const double S = cdf[items - 1];
+    for (int t = 0; t < k; t++) {
+        const double u = (double)(orc_rng_u64(seed, stream, (uint64_t)t) >> 11) * 0x1p-53;
+        const double target = u * S;
+        int64_t lo = 0, hi = items - 1;
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        out[t] = lo;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Refinement of a CUR LRA by its leverage scores (section on refining an   */
+/* LRA with leverage scores: the scores of a crude LRA W' stand in for     */
+/* those of W; Algorithm algcurlevsc with them, sampling by Algorithm       */
+/* algsmplex).  The crude LRA is the CUR of (I0, J0) (r rows and columns):  */
+/* W' = C U R with C = W[:, J0], R = W[I0, :], so its column space is that  */
+/* of C and its row space that of R.                                        */
+/*   column scores q_j of R^T and row scores qbar_i of C (orc_leverage);    */
+/*   J = l draws by q (stream 8), I = k draws by qbar (stream 9), sorted;   */
+/*   D = diag(1 / sqrt(l q_j / S)), Dbar = diag(1 / sqrt(k qbar_i / Sbar)); */
+/*   M = Dbar W[I, J] D (entry (dbar_a w) d_b), U = D M_r^+ Dbar (entry     */
+/*   (d_b x) dbar_a), M_r^+ by orc_pinv_trunc (the canonical nucleus, R29). */
+/* Reading: the scores are taken with beta = 1 from the crude LRA's own     */
+/* factors (their leverage scores are those of W' when U is nonsingular).   */
+/* I, J (k and l entries) sorted ascending, duplicates kept; U is l x k.    */
+/* ------------------------------------------------------------------------ */
+int orc_leverage_cur(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I0,
+                     const int64_t *J0, int k, int l, uint64_t seed, int64_t *I_out, int64_t *J_out, double *U_out,
+                     orc_info *info_out) {
+    orc_info info = {0, 0, 1, 0, 0, 0, 1.0, 0.0};
+    info.rank_found = r;
+    if (!A || !I0 || !J0 || !I_out || !J_out || !U_out || r < 1 || k < r || l < r || m < 1 || n < 1 || lda < n ||
+        (int64_t)r > (m < n ? m : n) || dtype < 0 || dtype > 2) {
+        if (info_out) *info_out = info;
+        return ORC_EINVAL;
+    }
+    double *Pr = (double *)malloc(sizeof(double) * (size_t)n * (size_t)r);   /* R^T, n x r */
+    double *Pc = (double *)malloc(sizeof(double) * (size_t)m * (size_t)r);   /* C, m x r */
+    double *qc = (double *)malloc(sizeof(double) * (size_t)n), *cc = (double *)malloc(sizeof(double) * (size_t)n);
+    double *qr = (double *)malloc(sizeof(double) * (size_t)m), *cr = (double *)malloc(sizeof(double) * (size_t)m);
+    double *M = (double *)malloc(sizeof(double) * (size_t)k * (size_t)l);
+    double *dl = (double *)malloc(sizeof(double) * (size_t)l), *dk = (double *)malloc(sizeof(double) * (size_t)k);
+    int st = ORC_OK;
+    for (int a = 0; a < r && st == ORC_OK; a++) {
+        if (I0[a] < 0 || I0[a] >= m || J0[a] < 0 || J0[a] >= n) st = ORC_EINVAL;
+    }
+    for (int64_t j = 0; j < n && st == ORC_OK; j++)
+        for (int a = 0; a < r; a++) {
+            double w = orc_get(A, dtype, lda, I0[a], j);
+            if (!isfinite(w)) { st = ORC_EINVAL; break; }
+            Pr[j * r + a] = w;
+        }
+    for (int64_t i = 0; i < m && st == ORC_OK; i++)
+        for (int a = 0; a < r; a++) {
+            double w = orc_get(A, dtype, lda, i, J0[a]);
+            if (!isfinite(w)) { st = ORC_EINVAL; break; }
+            Pc[i * r + a] = w;
+        }
+    if (st == ORC_OK) st = orc_leverage(Pr, n, r, qc, cc);
+    if (st == ORC_OK) st = orc_leverage(Pc, m, r, qr, cr);
+    if (st == ORC_OK) {
+        orc_sample_scores(cc, n, seed, 8, l, J_out);
+        orc_sample_scores(cr, m, seed, 9, k, I_out);
+        qsort(J_out, (size_t)l, sizeof(int64_t), cmp_i64);
+        qsort(I_out, (size_t)k, sizeof(int64_t), cmp_i64);
+        const double S = cc[n - 1], Sb = cr[m - 1];
+        for (int b = 0; b < l; b++) dl[b] = 1.0 / sqrt(((double)l * qc[J_out[b]]) / S);
+        for (int a = 0; a < k; a++) dk[a] = 1.0 / sqrt(((double)k * qr[I_out[a]]) / Sb);
+        for (int a = 0; a < k && st == ORC_OK; a++)
+            for (int b = 0; b < l; b++) {
+                double w = orc_get(A, dtype, lda, I_out[a], J_out[b]);
+                if (!isfinite(w)) { st = ORC_EINVAL; break; }
+                M[a * l + b] = (dk[a] * w) * dl[b];
+            }
+    }
+    if (st == ORC_OK) {
+        int nr = r;
+        st = orc_pinv_trunc(M, k, l, r, U_out, &nr, &info.det_log_abs);
+        info.nucleus_rank = nr;
+        for (int b = 0; b < l; b++)
+            for (int a = 0; a < k; a++) U_out[b * k + a] = (dl[b] * U_out[b * k + a]) * dk[a];
+    }
+    if (st == ORC_ESINGULAR) info.rank_found = 0;
+    free(Pr); free(Pc); free(qc); free(cc); free(qr); free(cr); free(M); free(dl); free(dk);
+    if (st != ORC_OK) info.converged = 0;
+    if (info_out) *info_out = info;
+    return st;
+}
+
+/* Leverage scores and their running sums, exported for the pins. */
+int orc_leverage_scores(const double *P, int64_t items, int r, double *q, double *cdf) {
+    if (!P || !q || !cdf || items < 1 || r < 1) return ORC_EINVAL;
+    return orc_leverage(P, items, r, q, cdf);
+}
