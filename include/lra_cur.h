@@ -204,6 +204,32 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream);
 
+/* Refinement of a CUR LRA by its leverage scores (section on refining an
+ * LRA with leverage scores: the scores of a crude LRA stand in for those of
+ * W; Algorithm algcurlevsc with them, Algorithm algsmplex for the draws;
+ * canonical nucleus of Algorithm algcnnncl).  The crude LRA is the CUR of
+ * the r rows I0 and r columns J0 (device arrays, e.g. from lra_cur):
+ *   column scores q_j = R_j^T (R R^T)^{-1} R_j of R = W[I0, :] and row
+ *   scores of C = W[:, J0] likewise (Cholesky factor of the Gram matrix, sums
+ *   in increasing item order);
+ *   J = l draws by q (first column whose running sum exceeds u S, u the
+ *   53-bit uniform from SplitMix64 stream 8 output t), I = k draws by the
+ *   row scores (stream 9), both sorted ascending, duplicates kept;
+ *   U = D M_r^+ Dbar with D = diag(1 / sqrt(l q_j / S)), Dbar likewise,
+ *   M = Dbar W[I, J] D and M_r^+ the pseudo-inverse of M's rank-r SVD
+ *   truncation.
+ * Outputs (device): I_out int64[k], J_out int64[l], U_out double[l * k]
+ * (row-major, W ~ W[:, J] U W[I, :]); info (device, may be NULL):
+ * nucleus_rank, det_log_abs = log of the kept singular values' product of M.
+ * 1 <= r <= min(m, n, 64); r <= k, l <= 64.  The call copies I0 and J0 to
+ * the host and synchronizes `stream` to check them (LRA_EINVAL when out of
+ * range); a non-finite entry read gives status LRA_EINVAL, a rank-deficient
+ * factor LRA_ESINGULAR (in info), with I = J = -1 and U = NaN.  Scratch:
+ * 16 (n + m) + 64 KiB bytes of the stream's cached workspace. */
+lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
+                            const int64_t *I0, const int64_t *J0, int32_t k, int32_t l, uint64_t seed,
+                            int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);
+
 /* CUR with uniform leverage scores for many blocks (Algorithm algcurlevsc
  * with p_j = 1/n and pbar_i = 1/m: the superfast case of the section on
  * leverage scores for random and average inputs; sampling by Algorithm

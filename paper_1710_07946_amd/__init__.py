@@ -89,6 +89,8 @@ def load() -> ct.CDLL:
         L.lra_cur_projective.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, i32, i32, ct.c_uint64,
                                          ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_projective.restype = ct.c_int
+        L.lra_cur_leverage.argtypes = [P, ct.c_int, i64, i64, i64, i32, P, P, i32, i32, ct.c_uint64, P, P, P, P, P]
+        L.lra_cur_leverage.restype = ct.c_int
         L.lra_cur_uniform_batched.argtypes = [P, ct.c_int, ct.POINTER(lra_block), i64, i32, i32, i32, ct.c_uint64,
                                               P, P, P, P, P]
         L.lra_cur_uniform_batched.restype = ct.c_int
@@ -373,6 +375,35 @@ def lra_cur_uniform(A, r: int, k: int, l: int, seed: int, *, stream=None) -> Cur
     flat = A.as_strided(((m - 1) * A.stride(0) + n,), (1,))
     out = lra_cur_uniform_batched(flat, [[0, m, n, A.stride(0)]], r, k, l, seed, stream=stream)
     return CurOut(out.I[0], out.J[0], out.U[0], out.info_raw)
+
+
+def lra_cur_leverage(A, I0, J0, k: int, l: int, seed: int, *, out: CurOut | None = None, stream=None) -> CurOut:
+    """Refinement of the CUR LRA of (I0, J0) (device int64 tensors of r
+    entries) by its leverage scores: k rows and l columns drawn by the crude
+    LRA's scores, U = D M_r^+ Dbar (l x k).  Synchronizes the stream once to
+    check I0 and J0."""
+    torch = _torch()
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor with unit column stride")
+    for t in (I0, J0):
+        if not t.is_cuda or t.dtype != torch.int64 or not t.is_contiguous():
+            raise ValueError("I0 and J0 must be contiguous int64 device tensors")
+    if I0.numel() != J0.numel():
+        raise ValueError("I0 and J0 must have the same length")
+    m, n = A.shape
+    dev = A.device
+    if out is None:
+        out = CurOut(torch.empty(k, dtype=torch.int64, device=dev), torch.empty(l, dtype=torch.int64, device=dev),
+                     torch.empty((l, k), dtype=torch.float64, device=dev),
+                     torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    st = load().lra_cur_leverage(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), int(I0.numel()),
+                                 ct.c_void_p(I0.data_ptr()), ct.c_void_p(J0.data_ptr()), k, l,
+                                 ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.c_void_p(out.I.data_ptr()),
+                                 ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
+                                 ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
+    if st != LRA_OK:
+        raise LraError(st, "lra_cur_leverage")
+    return out
 
 
 def lra_cur_batched_points(pts, blocks, r: int, sweeps: int, seed: int, *, delta: float = 0.01,

@@ -523,6 +523,44 @@ lra_status lra_cur_uniform_batched(const void *base, lra_dtype dt, const lra_blo
     return LRA_OK;
 }
 
+lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
+                            const int64_t *I0, const int64_t *J0, int32_t k, int32_t l, uint64_t seed,
+                            int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    if (!W || !I0 || !J0 || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n || k < r || l < r || k > kRMax ||
+        l > kRMax)
+        return LRA_EINVAL;
+    // the crude LRA's sets are read back and checked before any kernel reads
+    // the matrix through them
+    int64_t hi[kRMax], hj[kRMax];
+    if (hipMemcpyAsync(hi, I0, sizeof(int64_t) * r, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(hj, J0, sizeof(int64_t) * r, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    for (int a = 0; a < r; a++)
+        if (hi[a] < 0 || hi[a] >= m || hj[a] < 0 || hj[a] >= n) return LRA_EINVAL;
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    lra_status st;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    const size_t bytes = lra::leverage_scratch_bytes(m, n);
+    void *scr = nullptr;
+    if ((st = ws_scratch(ws, stream, bytes + 64, &scr)) != LRA_OK) return st;
+    double *lw = static_cast<double *>(scr);
+    int32_t *flags = reinterpret_cast<int32_t *>(static_cast<char *>(scr) + bytes);
+    hipError_t e = lra::launch_leverage(dt, W, m, n, lda, r, I0, J0, k, l, seed, lw, flags, I_out, J_out, U_out,
+                                        info, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
 lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream) {

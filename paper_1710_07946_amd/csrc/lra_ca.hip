@@ -1612,11 +1612,13 @@ __device__ __forceinline__ double row_sum16(double v) {
 // doubles, column-major, so that a pair's lanes read consecutive entries.
 // sm.nucleus_rank = the number kept, sm.logdet = the sum of their logs.
 // dl, dr: the generator is taken as (dl G) dr entrywise and U returned as
-// (dr U) dl, the scalar rescalings Dbar, D of a CUR by sampling.
+// (dr U) dl, the scalar rescalings Dbar, D of a CUR by sampling; dla / dra
+// (optional) give one factor per row of G and per column instead.
 // One workgroup, every thread calls.
 template <class SM, class Src>
 __device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src, int k, int l, int r,
-                                              double *U_out, double dl = 1.0, double dr = 1.0) {
+                                              double *U_out, double dl = 1.0, double dr = 1.0,
+                                              const double *dla = nullptr, const double *dra = nullptr) {
     const int tid = threadIdx.x;
     const bool wide = k < l;
     const int nr = wide ? l : k, nc = wide ? k : l;
@@ -1627,7 +1629,8 @@ __device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src
     __shared__ int s_keep[kRMax];
     for (int e = tid; e < nr * nc; e += kBlock) {
         const int i = e % nr, c = e / nr;
-        A[e] = (dl * (wide ? src(sm.Iset[c], sm.Jset[i]) : src(sm.Iset[i], sm.Jset[c]))) * dr;
+        const int ia = wide ? c : i, jb = wide ? i : c;  // row (I) and column (J) of the entry
+        A[e] = ((dla ? dla[ia] : dl) * src(sm.Iset[ia], sm.Jset[jb])) * (dra ? dra[jb] : dr);
     }
     for (int e = tid; e < nc * nc; e += kBlock) V[e] = (e / nc == e % nc) ? 1.0 : 0.0;
     __syncthreads();
@@ -1750,7 +1753,7 @@ __device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src
             if (s_keep[c])
                 acc += (wide ? A[c * nr + a] * V[c * nc + bb] : V[c * nc + a] * A[c * nr + bb]) /
                        (s_sig[c] * s_sig[c]);
-        U_out[e] = (dr * acc) * dl;
+        U_out[e] = ((dra ? dra[a] : dr) * acc) * (dla ? dla[bb] : dl);
     }
     __syncthreads();
 }
@@ -2174,6 +2177,220 @@ __global__ void __launch_bounds__(kBlock) ca_uniform_kernel(const T *base, const
     }
 }
 
+// ---------------------------------------------------------------- leverage scores
+// Refinement of a CUR LRA by its leverage scores (section on refining an LRA
+// with leverage scores; Algorithm algcurlevsc with the crude LRA's scores,
+// Algorithm algsmplex for the draws): three launches on one stream.
+//  1. lev_gram_kernel (one workgroup): the Gram matrices R R^T (R = W[I0, :])
+//     and C^T C (C = W[:, J0]), every entry summed over the items in
+//     increasing order, then their lower Cholesky factors (entry formulas
+//     and orders of the oracle) into ws.
+//  2. lev_score_kernel (one thread per item): q_i = |L^{-1} x_i|^2 by the
+//     row-oriented forward solve, x_i the item's r-vector.
+//  3. lev_cdf_kernel: running sums of the scores in item order; then
+//     lev_pick_kernel (one workgroup): k + l draws u_t = (x >> 11) 2^-53 from SplitMix64 streams 8 / 9
+//     (first item whose running sum exceeds u_t S), sorted; D = 1 / sqrt(l
+//     q_j / S), Dbar likewise; U = D M_r^+ Dbar by nucleus_trunc.
+// ws layout (doubles): L_R [64 x 64], L_C [64 x 64], q (n + m), cdf (n + m);
+// flags: [0] non-finite entry, [1] Gram not positive definite.
+struct LevSmem {
+    int64_t Iset[kRMax], Jset[kRMax];
+    int64_t I0[kRMax], J0[kRMax];
+    double dk[kRMax], dl[kRMax];
+    int32_t nucleus_rank;
+    double logdet;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lev_gram_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int r,
+                                                          const int64_t *I0, const int64_t *J0, double *ws,
+                                                          int32_t *flags) {
+    __shared__ int64_t s_i0[kRMax], s_j0[kRMax];
+    __shared__ double s_g[kRMax * kRMax];
+    __shared__ double s_l[kRMax * kRMax];
+    __shared__ double s_chunk[kRMax * 64];
+    const int tid = threadIdx.x;
+    const DenseSrc<T> src{A, lda};
+    if (tid < r) {
+        s_i0[tid] = I0[tid];
+        s_j0[tid] = J0[tid];
+    }
+    __syncthreads();
+    const int tri = r * (r + 1) / 2;
+    int bad = 0;
+    for (int side = 0; side < 2; side++) {
+        // side 0: items = columns j of R (entries W[I0[a], j]); side 1: items =
+        // rows i of C (entries W[i, J0[a]])
+        const int64_t items = side == 0 ? n : m;
+        double acc[5];
+        int ea[5], eb[5];
+#pragma unroll
+        for (int u = 0; u < 5; u++) {
+            acc[u] = 0.0;
+            const int e = tid + u * kBlock;
+            int a = 0;
+            while ((a + 1) * (a + 2) / 2 <= e) a++;
+            ea[u] = e < tri ? a : 0;
+            eb[u] = e < tri ? e - a * (a + 1) / 2 : 0;
+        }
+        for (int64_t i0 = 0; i0 < items; i0 += 64) {
+            const int cnt = (int)min<int64_t>(64, items - i0);
+            __syncthreads();
+            for (int e = tid; e < r * 64; e += kBlock) {
+                const int a = e / 64, t = e % 64;
+                double v = 0.0;
+                if (t < cnt) {
+                    v = side == 0 ? src(s_i0[a], i0 + t) : src(i0 + t, s_j0[a]);
+                    if (!isfinite(v)) bad = 1;
+                }
+                s_chunk[a * 64 + t] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 5; u++) {
+                if (tid + u * kBlock >= tri) continue;
+                const double *xa = s_chunk + ea[u] * 64, *xb = s_chunk + eb[u] * 64;
+                double sacc = acc[u];
+                for (int t = 0; t < cnt; t++) sacc += xa[t] * xb[t];
+                acc[u] = sacc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 5; u++)
+            if (tid + u * kBlock < tri) s_g[ea[u] * r + eb[u]] = acc[u];
+        __syncthreads();
+        // Cholesky, column b at a time: the diagonal, then the column below it
+        // (in LDS; copied out once complete)
+        double *L = s_l;
+        __shared__ int s_sing;
+        if (tid == 0) s_sing = 0;
+        __syncthreads();
+        for (int b = 0; b < r; b++) {
+            if (tid == 0) {
+                double sd = s_g[b * r + b];
+                for (int c = 0; c < b; c++) sd -= L[b * kRMax + c] * L[b * kRMax + c];
+                if (!(sd > 0.0)) s_sing = 1;
+                L[b * kRMax + b] = sqrt(sd);
+            }
+            __syncthreads();
+            if (s_sing) break;
+            const int a = b + 1 + tid;
+            if (a < r) {
+                double sa = s_g[a * r + b];
+                for (int c = 0; c < b; c++) sa -= L[a * kRMax + c] * L[b * kRMax + c];
+                L[a * kRMax + b] = sa / L[b * kRMax + b];
+            }
+            __syncthreads();
+        }
+        if (tid == 0 && s_sing) flags[1] = 1;
+        for (int e = tid; e < r * kRMax; e += kBlock) ws[(size_t)side * kRMax * kRMax + e] = L[e];
+        __syncthreads();
+    }
+    bad = __syncthreads_or(bad);
+    if (tid == 0 && bad) flags[0] = 1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) lev_score_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int r,
+                                                        const int64_t *I0, const int64_t *J0, double *ws) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= n + m) return;
+    const int side = it < n ? 0 : 1;
+    const int64_t item = side == 0 ? it : it - n;
+    const double *L = ws + (size_t)side * kRMax * kRMax;
+    const DenseSrc<T> src{A, lda};
+    double z[kRMax];
+    double s = 0.0;
+    for (int a = 0; a < r; a++) {
+        double x = side == 0 ? src(I0[a], item) : src(item, J0[a]);
+        for (int c = 0; c < a; c++) x -= L[a * kRMax + c] * z[c];
+        z[a] = x / L[a * kRMax + a];
+        s += z[a] * z[a];
+    }
+    ws[2 * kRMax * kRMax + it] = s;
+}
+
+// running sums of the scores in item order: thread 0 the columns (n), thread
+// 1 the rows (m)
+__global__ void lev_cdf_kernel(int64_t m, int64_t n, double *ws) {
+    const int tid = threadIdx.x;
+    if (tid >= 2) return;
+    const double *q = ws + 2 * kRMax * kRMax;
+    double *cdf = ws + 2 * kRMax * kRMax + n + m;
+    const int64_t off = tid == 0 ? 0 : n, cnt = tid == 0 ? n : m;
+    double acc = 0.0;
+    for (int64_t i = 0; i < cnt; i++) {
+        acc += q[off + i];
+        cdf[off + i] = acc;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lev_pick_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int r,
+                                                          int k, int l, uint64_t seed, double *ws,
+                                                          const int32_t *flags, int64_t *I_out, int64_t *J_out,
+                                                          double *U_out, lra_info *info) {
+    __shared__ LevSmem sm;
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    double *dyn = reinterpret_cast<double *>(lds_dyn);
+    const int tid = threadIdx.x;
+    const DenseSrc<T> src{A, lda};
+    const double *q = ws + 2 * kRMax * kRMax;
+    const double *cdf = ws + 2 * kRMax * kRMax + n + m;
+    int st = flags[0] ? LRA_EINVAL : flags[1] ? LRA_ESINGULAR : LRA_OK;
+    if (st == LRA_OK) {
+        // draws: threads 0 .. l-1 columns, l .. l+k-1 rows
+        if (tid < k + l) {
+            const bool col = tid < l;
+            const int t = col ? tid : tid - l;
+            const int64_t off = col ? 0 : n, cnt = col ? n : m;
+            const double S = cdf[off + cnt - 1];
+            const double u = (double)(sm64(seed, col ? 8 : 9, (uint64_t)t) >> 11) * 0x1p-53;
+            const double target = u * S;
+            int64_t lo = 0, hi = cnt - 1;
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (cdf[off + mid] > target) hi = mid;
+                else lo = mid + 1;
+            }
+            if (col) sm.Jset[t] = lo;
+            else sm.Iset[t] = lo;
+        }
+        __syncthreads();
+        if (tid < kWave) {
+            sort_set_wave(sm.Jset, l);
+            sort_set_wave(sm.Iset, k);
+        }
+        __syncthreads();
+        if (tid < l) sm.dl[tid] = 1.0 / sqrt(((double)l * q[sm.Jset[tid]]) / cdf[n - 1]);
+        if (tid >= kRMax && tid < kRMax + k)
+            sm.dk[tid - kRMax] = 1.0 / sqrt(((double)k * q[n + sm.Iset[tid - kRMax]]) / cdf[n + m - 1]);
+        __syncthreads();
+        int bad = 0;
+        for (int e = tid; e < k * l; e += kBlock) bad |= !isfinite(src(sm.Iset[e / l], sm.Jset[e % l]));
+        if (__syncthreads_or(bad)) st = LRA_EINVAL;
+    }
+    if (st == LRA_OK) nucleus_trunc(sm, dyn, src, k, l, r, U_out, 1.0, 1.0, sm.dk, sm.dl);
+    if (tid < k) I_out[tid] = st == LRA_OK ? sm.Iset[tid] : -1;
+    if (tid < l) J_out[tid] = st == LRA_OK ? sm.Jset[tid] : -1;
+    if (st != LRA_OK)
+        for (int e = tid; e < l * k; e += kBlock) U_out[e] = __builtin_nan("");
+    if (tid == 0 && info) {
+        lra_info inf;
+        inf.status = st;
+        inf.sweeps_run = 0;
+        inf.swaps_total = 0;
+        inf.converged = st == LRA_OK ? 1 : 0;
+        inf.rank_found = st == LRA_ESINGULAR ? 0 : r;
+        inf.team_size = 1;
+        inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
+        inf.reserved = 0;
+        inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
+        *info = inf;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) ca_batched_kernel(const T *base, const BlockDesc *blocks, const int32_t *order,
                                                             int64_t count, uint64_t seed, CAConfig cfg, unsigned *queue,
@@ -2437,6 +2654,46 @@ int uniform_occupancy(int dtype, size_t dyn_bytes) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_uniform_kernel<uint16_t>, kBlock, dyn_bytes);
     if (e != hipSuccess) return 0;
     return blocks;
+}
+
+template <typename T>
+static hipError_t launch_leverage_t(const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I0,
+                                   const int64_t *J0, int k, int l, uint64_t seed, double *ws, int32_t *flags,
+                                   int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    const T *Ap = static_cast<const T *>(A);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned *>(flags), 2);
+    hipLaunchKernelGGL(lev_gram_kernel<T>, dim3(1), dim3(kBlock), 0, stream, Ap, m, n, lda, r, I0, J0, ws, flags);
+    const int64_t items = n + m;
+    hipLaunchKernelGGL(lev_score_kernel<T>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, stream, Ap, m, n,
+                       lda, r, I0, J0, ws);
+    hipLaunchKernelGGL(lev_cdf_kernel, dim3(1), dim3(64), 0, stream, m, n, ws);
+    const size_t dyn = sizeof(double) * (size_t)std::min(k, l) * (size_t)(k + l);
+    auto kern = lev_pick_kernel<T>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    (void)e;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kBlock), dyn, stream, Ap, m, n, lda, r, k, l, seed, ws,
+                       static_cast<const int32_t *>(flags), I_out, J_out, U_out, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_leverage(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I0,
+                           const int64_t *J0, int k, int l, uint64_t seed, double *ws, int32_t *flags,
+                           int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
+    switch (dtype) {
+    case LRA_F64:
+        return launch_leverage_t<double>(A, m, n, lda, r, I0, J0, k, l, seed, ws, flags, I_out, J_out, U_out, info,
+                                         stream);
+    case LRA_F32:
+        return launch_leverage_t<float>(A, m, n, lda, r, I0, J0, k, l, seed, ws, flags, I_out, J_out, U_out, info,
+                                        stream);
+    default:
+        return launch_leverage_t<uint16_t>(A, m, n, lda, r, I0, J0, k, l, seed, ws, flags, I_out, J_out, U_out, info,
+                                           stream);
+    }
+}
+
+size_t leverage_scratch_bytes(int64_t m, int64_t n) {
+    return sizeof(double) * ((size_t)2 * kRMax * kRMax + (size_t)2 * (size_t)(n + m));
 }
 
 template <typename T>

@@ -157,6 +157,27 @@ def test_fourier_start_invalid_arguments_rejected_on_host(lib):
     assert call(l=100, d=0, m=60, n=50) == E    # more samples than columns of the multiplier
 
 
+def test_leverage_invalid_arguments_rejected_on_host(lib):
+    # every check here runs before the call reads the device sets
+    fake = ct.c_void_p(0x1000)
+    E = lra.LRA_EINVAL
+
+    def call(m=100, n=80, lda=80, r=4, k=8, l=8, dt=1, W=fake, I0=fake):
+        return lib.lra_cur_leverage(W, dt, m, n, lda, r, I0, fake, k, l, 1, fake, fake, fake, None, None)
+
+    assert call(k=3) == E            # k < r
+    assert call(l=3) == E            # l < r
+    assert call(k=65) == E
+    assert call(l=65) == E
+    assert call(r=0) == E
+    assert call(r=65, k=65, l=65) == E
+    assert call(m=3, r=4) == E       # r > m
+    assert call(lda=79) == E
+    assert call(dt=7) == E
+    assert call(W=None) == E
+    assert call(I0=None) == E
+
+
 def test_projective_invalid_arguments_rejected_on_host(lib):
     fake = ct.c_void_p(0x1000)
     E = lra.LRA_EINVAL
