@@ -1266,7 +1266,10 @@ int orc_hadamard_apply(const void *A, int dtype, int64_t m, int64_t n, int64_t l
 /* level of G, e.g. after duplicate columns cancel), or the rotation's sine  */
 /* is zero.  Then                                                           */
 /* sigma_j = |a_j|; the kept set is the r largest sigma_j (ties to the      */
-/* lower j) among those above 1e-14 max sigma; X (l x k, row-major) =       */
+/* lower j) among those above max(1e-14, max(k, l) eps) max sigma (the      */
+/* usual numerical-rank tolerance, and at least the negligible-column       */
+/* level, so a column left at rounding level is never kept); X (l x k,      */
+/* row-major) =                                                             */
 /* sum over kept j (increasing) of v_j a_j^T / sigma_j^2.  *rank_out gets   */
 /* the number kept and *logvol the sum of their logs, log v_{2,r}(G) of     */
 /* eq. (eqvol) when all r are kept.                                         */
@@ -1328,13 +1331,17 @@ int orc_pinv_trunc(const double *G, int k, int l, int r, double *X, int *rank_ou
         sg[j] = sqrt(s2);
         if (sg[j] > smax) smax = sg[j];
     }
+    /* a singular value counts only above the rounding level of the process:
+       max(1e-14, max(k, l) eps) times the largest, never below the level at
+       which the rotation test leaves a column as negligible */
+    const double thr = fmax(1e-14, (double)(k > l ? k : l) * 0x1p-52);
     int kept = 0;
     double lv = 0.0;
     for (int j = 0; j < l; j++) {
         int above = 0;  /* sigma values ranked before j */
         for (int i = 0; i < l; i++)
             if (sg[i] > sg[j] || (sg[i] == sg[j] && i < j)) above++;
-        if (above < r && sg[j] > 1e-14 * smax) { keep[j] = 1; kept++; lv += log(sg[j]); }
+        if (above < r && sg[j] > thr * smax) { keep[j] = 1; kept++; lv += log(sg[j]); }
     }
     for (int a = 0; a < l; a++)
         for (int b = 0; b < k; b++) {

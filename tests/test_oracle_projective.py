@@ -300,3 +300,24 @@ def test_invalid_arguments():
     assert oracle.projective_cur(W, 3, 2, 4, 1, 0).status == oracle.EINVAL   # k < r
     assert oracle.projective_cur(W, 3, 4, 9, 1, 0).status == oracle.EINVAL   # l > n
     assert oracle.projective_cur(W, 3, 4, 4, 0, 0).status == oracle.EINVAL   # no sweep
+
+
+@pytest.mark.parametrize("k,l,distinct,seed", [(56, 63, 50, 1), (63, 56, 50, 2), (64, 64, 40, 3), (60, 48, 45, 4)])
+def test_pinv_trunc_of_repeated_rows_keeps_the_exact_rank(k, l, distinct, seed):
+    # a generator drawn with repetition (as by sampling): k rows of which only
+    # `distinct` differ, each rescaled, so its exact rank is `distinct`.  The
+    # columns the rotations leave at rounding level must not count: the kept
+    # rank is LAPACK's numerical rank and X its pseudo-inverse
+    g = np.random.default_rng(seed)
+    Q1, _ = np.linalg.qr(g.standard_normal((distinct, distinct)))
+    Q2, _ = np.linalg.qr(g.standard_normal((l, l)))
+    s = np.geomspace(1.0, 7e-4, distinct)
+    base = (Q1 * s) @ Q2[:distinct]
+    pick = np.sort(np.concatenate([np.arange(distinct), g.integers(0, distinct, k - distinct)]))
+    G = base[pick] * g.uniform(0.5, 2.0, k)[:, None]
+    r = min(k, l) - 1
+    st, X, rk, _ = oracle.pinv_trunc(G, r)
+    assert st == 0 and rk == np.linalg.matrix_rank(G) == distinct
+    ref, _ = trunc_pinv(G, distinct)
+    assert np.linalg.norm(X - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert np.linalg.norm(G @ X @ G - G) <= 1e-10 * np.linalg.norm(G)
