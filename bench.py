@@ -72,7 +72,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="time only the headline LRA (skip batched, residual and adjoint lines)")
-    ap.add_argument("--only", choices=["batched", "points", "cynical", "adjoint", "tall", "residual"], default=None,
+    ap.add_argument("--only", choices=["batched", "points", "cynical", "adjoint", "tall", "residual", "starts"],
+                    default=None,
                     help="time one secondary line alone and print it (for profiling)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (reference for HBM counters)")
@@ -114,6 +115,11 @@ def main():
     if args.only == "residual":
         print(json.dumps({"residual": residual_fields(lra, torch, A, out.I, out.J, out.U, M, N, RANK, 4,
                                                       max(2, args.steps // 5))}), flush=True)
+        return
+    if args.only == "starts":
+        print(json.dumps({"bidiag_start": bench_bidiag_start(lra, torch, np, A, args),
+                          "fourier_start": bench_fourier_start(lra, torch, np, A, args),
+                          "leverage_refinement": bench_leverage(lra, torch, np, A, args)}), flush=True)
         return
     for _ in range(args.warmup):
         lra.lra_cur(A, RANK, SWEEPS, SEED, out=out, **kw)

@@ -174,7 +174,8 @@ lra_status lra_cur_cynical(const void *W, lra_dtype dt, int64_t m, int64_t n, in
  *   opts->max_swaps times per step (defaults 0.01 and 16 r).  The loop stops
  *   early when a sweep repeats the sets.
  *   U = pseudo-inverse of the rank-r SVD truncation of W[I, J] (one-sided
- *   Jacobi; the r largest singular values above 1e-14 times the largest).
+ *   Jacobi; the r largest singular values above max(1e-14, max(k, l) 2^-52) times the
+ *   largest).
  * Outputs (device): I_out int64[k], J_out int64[l], both ascending; U_out
  * double[l * k], row-major, J-order x I-order, so W ~ W[:, J] U W[I, :].
  * info (device, may be NULL): nucleus_rank = singular values kept,
@@ -239,7 +240,8 @@ lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, i
  *   ascending with duplicates kept;
  *   U = D M_r^+ Dbar, M = Dbar W[I, J] D, D = sqrt(n / l), Dbar = sqrt(m / k),
  *   M_r^+ the pseudo-inverse of M's rank-r SVD truncation (one-sided Jacobi;
- *   the r largest singular values above 1e-14 times the largest).
+ *   the r largest singular values above max(1e-14, max(k, l) 2^-52) times the
+ *   largest).
  * Only the k l entries of W[I, J] are read.  `blocks` is a HOST array;
  * outputs (device) are packed: I_out int64[count * k], J_out int64[count * l],
  * U_out double[count * l * k] (each l x k row-major, W ~ W[:, J] U W[I, :]),

@@ -547,7 +547,7 @@ lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, i
     Workspace *ws = nullptr;
     lra_status st;
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
-    const size_t bytes = lra::leverage_scratch_bytes(m, n);
+    const size_t bytes = lra::leverage_scratch_bytes(m, n, r);
     void *scr = nullptr;
     if ((st = ws_scratch(ws, stream, bytes + 64, &scr)) != LRA_OK) return st;
     double *lw = static_cast<double *>(scr);

@@ -1606,7 +1606,7 @@ __device__ __forceinline__ double row_sum16(double v) {
 // (nr eps)^2 times the largest squared column norm at the sweep's start, or
 // the sine is zero; sweeps until none rotates, at most 60), each pair on
 // the 16 lanes of a DPP row; then the r largest sigma_j
-// above 1e-14 max sigma (ties to the lower j) are kept.  With B = A V
+// above max(1e-14, nr eps) max sigma (ties to the lower j) are kept.  With B = A V
 // rotated: U = sum over kept j of v_j b_j^T / sigma_j^2 (G tall) or
 // b_j v_j^T / sigma_j^2 (G wide), l x k row-major.  ws: nr nc + nc^2
 // doubles, column-major, so that a pair's lanes read consecutive entries.
@@ -1732,7 +1732,10 @@ __device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src
             smax = s_sig[c] > smax ? s_sig[c] : smax;
             above += (s_sig[c] > s_sig[tid] || (s_sig[c] == s_sig[tid] && c < tid)) ? 1 : 0;
         }
-        s_keep[tid] = (above < r && s_sig[tid] > 1e-14 * smax) ? 1 : 0;
+        // rank tolerance max(1e-14, max(k, l) eps): never below the level at
+        // which the rotation test leaves a column as negligible
+        const double thr = fmax(1e-14, (double)nr * 0x1p-52);
+        s_keep[tid] = (above < r && s_sig[tid] > thr * smax) ? 1 : 0;
     }
     __syncthreads();
     if (tid == 0) {
@@ -2180,19 +2183,27 @@ __global__ void __launch_bounds__(kBlock) ca_uniform_kernel(const T *base, const
 // ---------------------------------------------------------------- leverage scores
 // Refinement of a CUR LRA by its leverage scores (section on refining an LRA
 // with leverage scores; Algorithm algcurlevsc with the crude LRA's scores,
-// Algorithm algsmplex for the draws): three launches on one stream.
-//  1. lev_gram_kernel (one workgroup): the Gram matrices R R^T (R = W[I0, :])
-//     and C^T C (C = W[:, J0]), every entry summed over the items in
-//     increasing order, then their lower Cholesky factors (entry formulas
-//     and orders of the oracle) into ws.
-//  2. lev_score_kernel (one thread per item): q_i = |L^{-1} x_i|^2 by the
-//     row-oriented forward solve, x_i the item's r-vector.
-//  3. lev_cdf_kernel: running sums of the scores in item order; then
-//     lev_pick_kernel (one workgroup): k + l draws u_t = (x >> 11) 2^-53 from SplitMix64 streams 8 / 9
-//     (first item whose running sum exceeds u_t S), sorted; D = 1 / sqrt(l
-//     q_j / S), Dbar likewise; U = D M_r^+ Dbar by nucleus_trunc.
-// ws layout (doubles): L_R [64 x 64], L_C [64 x 64], q (n + m), cdf (n + m);
-// flags: [0] non-finite entry, [1] Gram not positive definite.
+// Algorithm algsmplex for the draws): six launches on one stream.
+//  1. lev_gather_kernel (grid-stride): the items' r-vectors in FP64, one row
+//     per a of P (r x (n + m)): columns j of R = W[I0, :] at 0 .. n-1, rows i
+//     of C = W[:, J0] at n .. n+m-1, so that every later pass reads them
+//     coalesced; flags a non-finite entry.
+//  2. lev_gram_kernel (a thread per lower-triangle entry of R R^T and C^T C):
+//     each entry summed over the items in increasing order (the oracle's
+//     order), two batches of loads in flight ahead of the dependent sum.
+//  3. lev_chol_kernel (a workgroup per side): the lower Cholesky factors in
+//     LDS, entry formulas and orders of the oracle.
+//  4. lev_score_kernel (a thread per item): q_i = |L^{-1} x_i|^2 by the
+//     row-oriented forward solve.
+//  5. lev_cdf_kernel (a workgroup per side): running sums of the scores in
+//     item order, chunks staged through LDS, one lane adding.
+//  6. lev_pick_kernel (one workgroup): k + l draws u_t = (x >> 11) 2^-53 from
+//     SplitMix64 streams 8 / 9 (first item whose running sum exceeds u_t S),
+//     sorted; D = 1 / sqrt(l q_j / S), Dbar likewise; U = D M_r^+ Dbar by
+//     nucleus_trunc.
+// ws layout (doubles): L_R, L_C, G_R, G_C [64 x 64 each], q (n + m), cdf
+// (n + m), P (r x (n + m)); flags: [0] non-finite entry, [1] Gram not
+// positive definite.
 struct LevSmem {
     int64_t Iset[kRMax], Jset[kRMax];
     int64_t I0[kRMax], J0[kRMax];
@@ -2201,128 +2212,182 @@ struct LevSmem {
     double logdet;
 };
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) lev_gram_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int r,
-                                                          const int64_t *I0, const int64_t *J0, double *ws,
-                                                          int32_t *flags) {
-    __shared__ int64_t s_i0[kRMax], s_j0[kRMax];
-    __shared__ double s_g[kRMax * kRMax];
-    __shared__ double s_l[kRMax * kRMax];
-    __shared__ double s_chunk[kRMax * 64];
-    const int tid = threadIdx.x;
-    const DenseSrc<T> src{A, lda};
-    if (tid < r) {
-        s_i0[tid] = I0[tid];
-        s_j0[tid] = J0[tid];
-    }
-    __syncthreads();
-    const int tri = r * (r + 1) / 2;
-    int bad = 0;
-    for (int side = 0; side < 2; side++) {
-        // side 0: items = columns j of R (entries W[I0[a], j]); side 1: items =
-        // rows i of C (entries W[i, J0[a]])
-        const int64_t items = side == 0 ? n : m;
-        double acc[5];
-        int ea[5], eb[5];
-#pragma unroll
-        for (int u = 0; u < 5; u++) {
-            acc[u] = 0.0;
-            const int e = tid + u * kBlock;
-            int a = 0;
-            while ((a + 1) * (a + 2) / 2 <= e) a++;
-            ea[u] = e < tri ? a : 0;
-            eb[u] = e < tri ? e - a * (a + 1) / 2 : 0;
-        }
-        for (int64_t i0 = 0; i0 < items; i0 += 64) {
-            const int cnt = (int)min<int64_t>(64, items - i0);
-            __syncthreads();
-            for (int e = tid; e < r * 64; e += kBlock) {
-                const int a = e / 64, t = e % 64;
-                double v = 0.0;
-                if (t < cnt) {
-                    v = side == 0 ? src(s_i0[a], i0 + t) : src(i0 + t, s_j0[a]);
-                    if (!isfinite(v)) bad = 1;
-                }
-                s_chunk[a * 64 + t] = v;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < 5; u++) {
-                if (tid + u * kBlock >= tri) continue;
-                const double *xa = s_chunk + ea[u] * 64, *xb = s_chunk + eb[u] * 64;
-                double sacc = acc[u];
-                for (int t = 0; t < cnt; t++) sacc += xa[t] * xb[t];
-                acc[u] = sacc;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 5; u++)
-            if (tid + u * kBlock < tri) s_g[ea[u] * r + eb[u]] = acc[u];
-        __syncthreads();
-        // Cholesky, column b at a time: the diagonal, then the column below it
-        // (in LDS; copied out once complete)
-        double *L = s_l;
-        __shared__ int s_sing;
-        if (tid == 0) s_sing = 0;
-        __syncthreads();
-        for (int b = 0; b < r; b++) {
-            if (tid == 0) {
-                double sd = s_g[b * r + b];
-                for (int c = 0; c < b; c++) sd -= L[b * kRMax + c] * L[b * kRMax + c];
-                if (!(sd > 0.0)) s_sing = 1;
-                L[b * kRMax + b] = sqrt(sd);
-            }
-            __syncthreads();
-            if (s_sing) break;
-            const int a = b + 1 + tid;
-            if (a < r) {
-                double sa = s_g[a * r + b];
-                for (int c = 0; c < b; c++) sa -= L[a * kRMax + c] * L[b * kRMax + c];
-                L[a * kRMax + b] = sa / L[b * kRMax + b];
-            }
-            __syncthreads();
-        }
-        if (tid == 0 && s_sing) flags[1] = 1;
-        for (int e = tid; e < r * kRMax; e += kBlock) ws[(size_t)side * kRMax * kRMax + e] = L[e];
-        __syncthreads();
-    }
-    bad = __syncthreads_or(bad);
-    if (tid == 0 && bad) flags[0] = 1;
-}
+__device__ __forceinline__ double *lev_scores(double *ws) { return ws + 4 * kRMax * kRMax; }
 
 template <typename T>
-__global__ void __launch_bounds__(256) lev_score_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int r,
-                                                        const int64_t *I0, const int64_t *J0, double *ws) {
-    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (it >= n + m) return;
-    const int side = it < n ? 0 : 1;
-    const int64_t item = side == 0 ? it : it - n;
-    const double *L = ws + (size_t)side * kRMax * kRMax;
+__global__ void __launch_bounds__(256) lev_gather_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int r,
+                                                         const int64_t *I0, const int64_t *J0, double *ws,
+                                                         int32_t *flags) {
     const DenseSrc<T> src{A, lda};
+    const int64_t items = n + m, total = items * r;
+    double *P = lev_scores(ws) + 2 * items;
+    int bad = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e / items);
+        const int64_t it = e - (int64_t)a * items;
+        const double v = it < n ? src(I0[a], it) : src(it - n, J0[a]);
+        if (!isfinite(v)) bad = 1;
+        P[e] = v;
+    }
+    if (bad) flags[0] = 1;
+}
+
+// A thread per lower-triangle entry (a, b), b <= a, of one side's Gram
+// matrix, summing x_a x_b over the items in increasing order.  The items go
+// by in batches of 12 held in three register sets, so that two batches'
+// loads are in flight while one is added (the sum itself is a dependent
+// chain and cannot be split without changing the order).
+__global__ void __launch_bounds__(64) lev_gram_kernel(int64_t m, int64_t n, int r, double *ws) {
+    constexpr int kB = 12;
+    const int tri = r * (r + 1) / 2;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 2 * tri) return;
+    const int side = e / tri, t = e - side * tri;
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= t) a++;
+    const int b = t - a * (a + 1) / 2;
+    const int64_t items = n + m, cnt = side == 0 ? n : m;
+    const double *P = lev_scores(ws) + 2 * items + (side == 0 ? 0 : n);
+    const double *xa = P + (int64_t)a * items, *xb = P + (int64_t)b * items;
+    double s = 0.0;
+    double a0[kB], b0[kB], a1[kB], b1[kB], a2[kB], b2[kB];
+    auto load = [&](double(&pa)[kB], double(&pb)[kB], int64_t j) {
+#pragma unroll
+        for (int u = 0; u < kB; u++) {
+            pa[u] = xa[j * kB + u];
+            pb[u] = xb[j * kB + u];
+        }
+    };
+    auto add = [&](const double(&pa)[kB], const double(&pb)[kB]) {
+#pragma unroll
+        for (int u = 0; u < kB; u++) s += pa[u] * pb[u];
+    };
+    const int64_t nb = cnt / kB;  // full batches
+    int64_t j = 0;
+    if (nb > 0) load(a0, b0, 0);
+    if (nb > 1) load(a1, b1, 1);
+    // on entry: set 0 holds batch j, set 1 batch j + 1 (when they exist)
+    for (; j + 3 <= nb; j += 3) {
+        load(a2, b2, j + 2);
+        add(a0, b0);
+        if (j + 3 < nb) load(a0, b0, j + 3);
+        add(a1, b1);
+        if (j + 4 < nb) load(a1, b1, j + 4);
+        add(a2, b2);
+    }
+    if (j < nb) add(a0, b0);
+    if (j + 1 < nb) add(a1, b1);
+    for (int64_t i = nb * kB; i < cnt; i++) s += xa[i] * xb[i];
+    ws[(size_t)(2 + side) * kRMax * kRMax + a * r + b] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) lev_chol_kernel(int r, double *ws, int32_t *flags) {
+    __shared__ double s_g[kRMax * kRMax];
+    __shared__ double L[kRMax * kRMax];
+    __shared__ int s_sing;
+    const int tid = threadIdx.x, side = blockIdx.x;
+    const double *G = ws + (size_t)(2 + side) * kRMax * kRMax;
+    for (int e = tid; e < r * r; e += kBlock) {
+        const int a = e / r, b = e % r;
+        s_g[e] = b <= a ? G[e] : 0.0;
+    }
+    for (int e = tid; e < kRMax * kRMax; e += kBlock) L[e] = 0.0;
+    if (tid == 0) s_sing = 0;
+    __syncthreads();
+    // column b at a time: the diagonal, then the column below it
+    for (int b = 0; b < r; b++) {
+        if (tid == 0) {
+            double sd = s_g[b * r + b];
+            for (int c = 0; c < b; c++) sd -= L[b * kRMax + c] * L[b * kRMax + c];
+            if (!(sd > 0.0)) s_sing = 1;
+            L[b * kRMax + b] = sqrt(sd);
+        }
+        __syncthreads();
+        if (s_sing) break;
+        const int a = b + 1 + tid;
+        if (a < r) {
+            double sa = s_g[a * r + b];
+            for (int c = 0; c < b; c++) sa -= L[a * kRMax + c] * L[b * kRMax + c];
+            L[a * kRMax + b] = sa / L[b * kRMax + b];
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && s_sing) flags[1] = 1;
+    for (int e = tid; e < r * kRMax; e += kBlock) ws[(size_t)side * kRMax * kRMax + e] = L[e];
+}
+
+__global__ void __launch_bounds__(256) lev_score_kernel(int64_t m, int64_t n, int r, double *ws) {
+    const int64_t items = n + m;
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= items) return;
+    const int side = it < n ? 0 : 1;
+    const double *L = ws + (size_t)side * kRMax * kRMax;
+    const double *P = lev_scores(ws) + 2 * items + it;
+    // fully unrolled over the largest rank so that z stays in registers
     double z[kRMax];
     double s = 0.0;
-    for (int a = 0; a < r; a++) {
-        double x = side == 0 ? src(I0[a], item) : src(item, J0[a]);
-        for (int c = 0; c < a; c++) x -= L[a * kRMax + c] * z[c];
-        z[a] = x / L[a * kRMax + a];
-        s += z[a] * z[a];
+#pragma unroll
+    for (int a = 0; a < kRMax; a++) {
+        if (a < r) {
+            double x = P[(int64_t)a * items];
+#pragma unroll
+            for (int c = 0; c < a; c++) x -= L[a * kRMax + c] * z[c];
+            z[a] = x / L[a * kRMax + a];
+            s += z[a] * z[a];
+        }
     }
-    ws[2 * kRMax * kRMax + it] = s;
+    lev_scores(ws)[it] = s;
 }
 
-// running sums of the scores in item order: thread 0 the columns (n), thread
-// 1 the rows (m)
-__global__ void lev_cdf_kernel(int64_t m, int64_t n, double *ws) {
-    const int tid = threadIdx.x;
-    if (tid >= 2) return;
-    const double *q = ws + 2 * kRMax * kRMax;
-    double *cdf = ws + 2 * kRMax * kRMax + n + m;
-    const int64_t off = tid == 0 ? 0 : n, cnt = tid == 0 ? n : m;
+// running sums of the scores in item order: workgroup 0 the columns (n),
+// workgroup 1 the rows (m); each chunk is staged in LDS by the workgroup and
+// summed by lane 0, eight values loaded ahead of the dependent adds
+__global__ void __launch_bounds__(256) lev_cdf_kernel(int64_t m, int64_t n, double *ws) {
+    constexpr int kChunk = 2048;
+    __shared__ double s_q[kChunk], s_c[kChunk];
+    const int tid = threadIdx.x, side = blockIdx.x;
+    double *q = lev_scores(ws), *cdf = q + n + m;
+    const int64_t off = side == 0 ? 0 : n, cnt = side == 0 ? n : m;
     double acc = 0.0;
-    for (int64_t i = 0; i < cnt; i++) {
-        acc += q[off + i];
-        cdf[off + i] = acc;
+    for (int64_t i0 = 0; i0 < cnt; i0 += kChunk) {
+        const int len = (int)min<int64_t>(kChunk, cnt - i0);
+        for (int t = tid; t < len; t += 256) s_q[t] = q[off + i0 + t];
+        __syncthreads();
+        if (tid == 0) {
+            // the next 16 values are read while the current 16 are added
+            constexpr int kB = 16;
+            int t = 0;
+            double cur[kB];
+            if (len >= kB) {
+#pragma unroll
+                for (int u = 0; u < kB; u++) cur[u] = s_q[u];
+                for (; t + 2 * kB <= len; t += kB) {
+                    double nxt[kB];
+#pragma unroll
+                    for (int u = 0; u < kB; u++) nxt[u] = s_q[t + kB + u];
+#pragma unroll
+                    for (int u = 0; u < kB; u++) {
+                        acc += cur[u];
+                        s_c[t + u] = acc;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kB; u++) cur[u] = nxt[u];
+                }
+#pragma unroll
+                for (int u = 0; u < kB; u++) {
+                    acc += cur[u];
+                    s_c[t + u] = acc;
+                }
+                t += kB;
+            }
+            for (; t < len; t++) {
+                acc += s_q[t];
+                s_c[t] = acc;
+            }
+        }
+        __syncthreads();
+        for (int t = tid; t < len; t += 256) cdf[off + i0 + t] = s_c[t];
+        __syncthreads();
     }
 }
 
@@ -2336,8 +2401,8 @@ __global__ void __launch_bounds__(kBlock) lev_pick_kernel(const T *A, int64_t m,
     double *dyn = reinterpret_cast<double *>(lds_dyn);
     const int tid = threadIdx.x;
     const DenseSrc<T> src{A, lda};
-    const double *q = ws + 2 * kRMax * kRMax;
-    const double *cdf = ws + 2 * kRMax * kRMax + n + m;
+    const double *q = lev_scores(ws);
+    const double *cdf = q + n + m;
     int st = flags[0] ? LRA_EINVAL : flags[1] ? LRA_ESINGULAR : LRA_OK;
     if (st == LRA_OK) {
         // draws: threads 0 .. l-1 columns, l .. l+k-1 rows
@@ -2662,11 +2727,15 @@ static hipError_t launch_leverage_t(const void *A, int64_t m, int64_t n, int64_t
                                    int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
     const T *Ap = static_cast<const T *>(A);
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, reinterpret_cast<unsigned *>(flags), 2);
-    hipLaunchKernelGGL(lev_gram_kernel<T>, dim3(1), dim3(kBlock), 0, stream, Ap, m, n, lda, r, I0, J0, ws, flags);
     const int64_t items = n + m;
-    hipLaunchKernelGGL(lev_score_kernel<T>, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, stream, Ap, m, n,
-                       lda, r, I0, J0, ws);
-    hipLaunchKernelGGL(lev_cdf_kernel, dim3(1), dim3(64), 0, stream, m, n, ws);
+    const int64_t gather_blocks = std::min<int64_t>((items * r + 255) / 256, 4096);
+    hipLaunchKernelGGL(lev_gather_kernel<T>, dim3((unsigned)gather_blocks), dim3(256), 0, stream, Ap, m, n, lda, r,
+                       I0, J0, ws, flags);
+    const int entries = r * (r + 1);
+    hipLaunchKernelGGL(lev_gram_kernel, dim3((unsigned)((entries + 63) / 64)), dim3(64), 0, stream, m, n, r, ws);
+    hipLaunchKernelGGL(lev_chol_kernel, dim3(2), dim3(kBlock), 0, stream, r, ws, flags);
+    hipLaunchKernelGGL(lev_score_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, stream, m, n, r, ws);
+    hipLaunchKernelGGL(lev_cdf_kernel, dim3(2), dim3(256), 0, stream, m, n, ws);
     const size_t dyn = sizeof(double) * (size_t)std::min(k, l) * (size_t)(k + l);
     auto kern = lev_pick_kernel<T>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
@@ -2692,8 +2761,8 @@ hipError_t launch_leverage(int dtype, const void *A, int64_t m, int64_t n, int64
     }
 }
 
-size_t leverage_scratch_bytes(int64_t m, int64_t n) {
-    return sizeof(double) * ((size_t)2 * kRMax * kRMax + (size_t)2 * (size_t)(n + m));
+size_t leverage_scratch_bytes(int64_t m, int64_t n, int r) {
+    return sizeof(double) * ((size_t)4 * kRMax * kRMax + (size_t)(2 + r) * (size_t)(n + m));
 }
 
 template <typename T>

@@ -87,7 +87,7 @@ int uniform_occupancy(int dtype, size_t dyn_bytes);
 hipError_t launch_leverage(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I0,
                            const int64_t *J0, int k, int l, uint64_t seed, double *ws, int32_t *flags,
                            int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);
-size_t leverage_scratch_bytes(int64_t m, int64_t n);
+size_t leverage_scratch_bytes(int64_t m, int64_t n, int r);
 
 size_t residual_scratch_bytes(int64_t m, int64_t n, int r, int q, int s, int prec);
 hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,

@@ -135,3 +135,46 @@ def test_headline_size_sampled(lra):
     o = oracle.leverage_cur(A, I0, J0, 64, 64, 7)
     rows = np.sort(np.random.default_rng(0).choice(m, 2000, replace=False))
     check(A, g, o, 50, rows=rows)
+
+
+def draw_cases(count, seed):
+    rng = np.random.default_rng(seed)
+    cases = []
+    for _ in range(count):
+        hi = 1500 if rng.random() < 0.3 else 400
+        m, n = int(rng.integers(20, hi)), int(rng.integers(20, hi))
+        r = int(rng.integers(1, min(64, m, n) + 1))
+        cases.append(dict(m=m, n=n, r=r, k=int(rng.integers(r, 65)), l=int(rng.integers(r, 65)),
+                          dt=["f64", "f32", "bf16"][int(rng.integers(0, 3))], kind=int(rng.integers(0, 2)),
+                          seed=int(rng.integers(0, 1 << 40)), gen=int(rng.integers(0, 1 << 30))))
+    # the largest rank and sample sizes on a ragged shape
+    cases.append(dict(m=1037, n=771, r=64, k=64, l=64, dt="f32", kind=1, seed=99, gen=5))
+    return cases
+
+
+CASES = draw_cases(24, 20261204)
+
+
+@pytest.mark.parametrize("idx", range(len(CASES)))
+def test_random_case(lra, idx):
+    # random shapes (ragged against the 64-item chunks), ranks up to 64 (Gram
+    # matrices over several wavefronts), FP64 / FP32 / BF16; crude sets drawn
+    # uniformly without repetition
+    c = CASES[idx]
+    g = np.random.default_rng(c["gen"])
+    m, n, r = c["m"], c["n"], c["r"]
+    if c["kind"] == 0:
+        A = workloads.orthogonal_lowrank(m, n, r, noise=10.0 ** g.uniform(-6, -2),
+                                         seeds=tuple(int(v) for v in g.integers(0, 1 << 30, 3)))
+    else:
+        A = g.standard_normal((m, n))
+    if c["dt"] == "f32":
+        A = A.astype(np.float32)
+    elif c["dt"] == "bf16":
+        A = (A.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    A = np.ascontiguousarray(A)
+    I0 = np.sort(g.choice(m, r, replace=False))
+    J0 = np.sort(g.choice(n, r, replace=False))
+    print("case", idx, c, flush=True)
+    o = oracle.leverage_cur(A, I0, J0, c["k"], c["l"], c["seed"])
+    check(A, run(lra, A, I0, J0, c["k"], c["l"], c["seed"]), o, r)
