@@ -178,3 +178,15 @@ def test_random_case(lra, idx):
     print("case", idx, c, flush=True)
     o = oracle.leverage_cur(A, I0, J0, c["k"], c["l"], c["seed"])
     check(A, run(lra, A, I0, J0, c["k"], c["l"], c["seed"]), o, r)
+
+
+@pytest.mark.parametrize("m,n,k,l", [(1, 1, 1, 1), (1, 300, 3, 5), (257, 1, 6, 2), (64, 64, 64, 64)])
+def test_degenerate_shapes(lra, m, n, k, l):
+    # a single row or column (every draw on the same item, the generator of
+    # rank one), a 1 x 1 matrix, and k = l = m = n = 64 with r = 1
+    g = np.random.default_rng(m * 1000 + n)
+    A = np.ascontiguousarray(g.standard_normal((m, 1)) @ g.standard_normal((1, n)) + 0.5)
+    I0, J0 = [m // 2], [n // 3]
+    o = oracle.leverage_cur(A, I0, J0, k, l, 3)
+    assert o.status == 0
+    check(A, run(lra, A, I0, J0, k, l, 3), o, 1)
