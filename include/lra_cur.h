@@ -226,7 +226,8 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
  * the host and synchronizes `stream` to check them (LRA_EINVAL when out of
  * range); a non-finite entry read gives status LRA_EINVAL, a rank-deficient
  * factor LRA_ESINGULAR (in info), with I = J = -1 and U = NaN.  Scratch:
- * 16 (n + m) + 64 KiB bytes of the stream's cached workspace. */
+ * 8 (2 + r) (n + m) bytes + 128 KiB of the stream's cached workspace (the
+ * FP64 copy of C and R, scores, running sums, Gram matrices and factors). */
 lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
                             const int64_t *I0, const int64_t *J0, int32_t k, int32_t l, uint64_t seed,
                             int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);
