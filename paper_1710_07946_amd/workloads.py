@@ -16,6 +16,10 @@ blocks; see the experiments section and the FMM section of the paper):
   noise std 1e-6), the perturbed factor-Gaussian family of the experiments.
 * ``fmm_blocks``          off-diagonal interaction blocks 1/|x - y| between
   well separated 2-D point clusters.
+* ``laplacian_single_layer``  the discretized single-layer potential of the
+  Laplacian from the unit circle to the circle of radius 2 (the integral-
+  equation input of the tests of the pre-processors), normalized to unit
+  spectral norm; deterministic.
 * ``decaying_spectrum``   tall matrix with 64 unit singular values followed by
   an i^-2 decay floored at 1e-7 (generated on the device: its 8.8 TFLOP
   construction is out of reach of a host).
@@ -123,6 +127,28 @@ def fmm_points(count: int, shape_seed: int = 1021, block_seed0: int = 1022000):
         parts += [x, y]
         off += m + n
     return np.ascontiguousarray(np.concatenate(parts, axis=0)), desc
+
+
+def laplacian_single_layer(n: int, quad: int = 8, dtype=np.float64) -> np.ndarray:
+    """n x n matrix w_ij = psi * integral of log|2 omega^i - y| over the arc of
+    the unit circle between the angles 2 pi j / n and 2 pi (j + 1) / n,
+    omega = exp(2 pi i / n), psi such that ||W||_2 = 1 (the input matrices
+    (i) of the tests of the pre-processors).
+
+    The distance from 2 omega^i to a point of the arc depends only on the
+    angle between them, so w_ij = c[(j - i) mod n] with c[d] the integral
+    of log|2 - e^{i phi}| over [2 pi d / n, 2 pi (d + 1) / n], evaluated by
+    `quad`-point Gauss-Legendre on each arc (the integrand is analytic
+    there: |2 - e^{i phi}| >= 1).  W is circulant, so its singular values
+    are |DFT(c)| and psi = 1 / max |DFT(c)|."""
+    h = 2.0 * np.pi / n
+    x, w = np.polynomial.legendre.leggauss(quad)
+    d = np.arange(n, dtype=np.float64)
+    phi = h * (d[:, None] + 0.5 * (x[None, :] + 1.0))
+    c = 0.5 * h * (np.log(np.abs(2.0 - np.exp(1j * phi))) * w[None, :]).sum(axis=1)
+    c /= np.abs(np.fft.fft(c)).max()
+    idx = (np.arange(n)[None, :] - np.arange(n)[:, None]) % n
+    return np.ascontiguousarray(c[idx].astype(dtype))
 
 
 def decaying_spectrum_sigma(n: int, lead: int = 64, floor: float = 1e-7) -> np.ndarray:
