@@ -531,6 +531,14 @@ def bench_cynical(lra, workloads, torch, np, args):
     out = lra.lra_cur(A, r, 4, 2031)
     ms = _time_events(torch, lambda: lra.lra_cur(A, r, 4, 2031, out=out), reps, 1)
     rec["plain_ca_r16_4_sweeps"] = {"lras_per_s": 1e3 / ms, "ms_per_lra": ms, "rel_fro_err": err(out)}
+    # refinement by leverage scores of a crude one-sweep C-A CUR, k = l = 4r
+    crude = lra.lra_cur(A, r, 1, 2031)
+    lev = lra.lra_cur_leverage(A, crude.I, crude.J, k, k, 2031)
+    ms = _time_events(torch, lambda: lra.lra_cur_leverage(A, crude.I, crude.J, k, k, 2031, out=lev), reps, 1)
+    info = lev.info()
+    rec["leverage_refinement_of_1_sweep_ca_k64_l64"] = {
+        "lras_per_s": 1e3 / ms, "ms_per_lra": ms, "status": info["status"], "nucleus_rank": info["nucleus_rank"],
+        "rel_fro_err": err(lev), "crude_rel_fro_err": err(crude)}
     # k x l = 64 x 64 generators of large r-projective volume, canonical
     # nucleus (U is l x k, so the r x r residual kernel takes it at rank 64)
     out = lra.lra_cur_projective(A, r, k, k, 3, 2031)
