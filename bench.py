@@ -119,7 +119,8 @@ def main():
     if args.only == "starts":
         print(json.dumps({"bidiag_start": bench_bidiag_start(lra, torch, np, A, args),
                           "fourier_start": bench_fourier_start(lra, torch, np, A, args),
-                          "leverage_refinement": bench_leverage(lra, torch, np, A, args)}), flush=True)
+                          "leverage_refinement": bench_leverage(lra, torch, np, A, args),
+                          "preprocessed_ca": bench_preprocessed(lra, torch, np, A, args)}), flush=True)
         return
     for _ in range(args.warmup):
         lra.lra_cur(A, RANK, SWEEPS, SEED, out=out, **kw)
