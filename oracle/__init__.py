@@ -29,7 +29,9 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(_OUT) or os.path.getmtime(_OUT) < os.path.getmtime(_SRC):
         os.makedirs(os.path.dirname(_OUT), exist_ok=True)
         tmp = _OUT + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+        # no contraction of a * b + c into a fused multiply-add: every
+        # operation rounds once, whatever the host compiler's default target
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-Wall", "-Wextra", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _OUT)
     return _OUT
@@ -66,6 +68,7 @@ def lib():
         L.orc_sketch.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P]
         L.orc_qrp.argtypes = [P, i64, ct.c_int, ct.c_int, P, P, P]
         L.orc_inverse.argtypes = [P, ct.c_int, P, ct.c_int, P]
+        L.orc_refine_inverse.argtypes = [P, ct.c_int, P, ct.c_int]
         L.orc_default_opts.argtypes = [P]
         L.orc_ca_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, u64, P, P, P, P, P]
         L.orc_residual.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, P, P]
@@ -92,7 +95,7 @@ def lib():
         L.orc_draw_uniform.argtypes = [u64, u64, i64, i64, P]
         L.orc_uniform_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
-                  "orc_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
+                  "orc_inverse", "orc_refine_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
                   "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag",
                   "orc_hadamard_apply", "orc_pinv_trunc", "orc_projective_select", "orc_projective_cur",
                   "orc_draw_uniform", "orc_uniform_cur", "orc_sketch_fourier", "orc_leverage_scores",
@@ -275,6 +278,15 @@ def nucleus(G: np.ndarray, refine_steps: int = 0):
     rk = ct.c_int(0)
     st = lib().orc_nucleus(_p(G), r, refine_steps, _p(U), ct.byref(ld), ct.byref(rk))
     return st, U, ld.value, rk.value
+
+
+def refine_inverse(G: np.ndarray, X0: np.ndarray, steps: int):
+    """`steps` refinement steps X <- X + X (I - G X) from the start X0."""
+    G = np.ascontiguousarray(G, np.float64)
+    X = np.array(X0, dtype=np.float64, order="C", copy=True)
+    st = lib().orc_refine_inverse(_p(G), G.shape[0], _p(X), steps)
+    assert st == OK, st
+    return X
 
 
 def inverse(G: np.ndarray, refine_steps: int = 0):

@@ -586,6 +586,35 @@ int orc_qrp(double *Z, int64_t items, int w, int k, int64_t *piv, int32_t *rank,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Iterative refinement of an approximate inverse X of G (the refinement of  */
+/* the nucleus in Section 3): `steps` times T = I - G X, then X <- X + X T,  */
+/* every sum in increasing index order.  With E = I - G X, one step leaves   */
+/* I - G (X + X E) = E - (I - E) E = E^2: the residual is squared.           */
+/* ------------------------------------------------------------------------ */
+int orc_refine_inverse(const double *G, int r, double *X, int steps) {
+    if (!G || !X || r < 1 || steps < 0) return ORC_EINVAL;
+    double *T = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+    double *X2 = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
+    for (int it = 0; it < steps; it++) {
+        for (int i = 0; i < r; i++)       /* T = I - G X */
+            for (int j = 0; j < r; j++) {
+                double s = (i == j) ? 1.0 : 0.0;
+                for (int q = 0; q < r; q++) s -= G[i * r + q] * X[q * r + j];
+                T[i * r + j] = s;
+            }
+        for (int i = 0; i < r; i++)       /* X + X T */
+            for (int j = 0; j < r; j++) {
+                double s = X[i * r + j];
+                for (int q = 0; q < r; q++) s += X[i * r + q] * T[q * r + j];
+                X2[i * r + j] = s;
+            }
+        memcpy(X, X2, sizeof(double) * (size_t)r * (size_t)r);
+    }
+    free(T); free(X2);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Nucleus U = G^{-1} of an r x r generator (Section 3, Algorithm algcnnncl  */
 /* with k = l = r, where the truncated pseudo-inverse is the inverse,        */
 /* Remark reklr_kl).  Gauss-Jordan style: LU with partial pivoting (ties to  */
@@ -633,24 +662,7 @@ int orc_inverse(const double *G, int r, double *U, int refine_steps, double *log
             }
             for (int i = 0; i < r; i++) U[i * r + c] = col[i];
         }
-        for (int it = 0; it < refine_steps; it++) {
-            double *T = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
-            double *X2 = (double *)malloc(sizeof(double) * (size_t)r * (size_t)r);
-            for (int i = 0; i < r; i++)       /* T = I - G X */
-                for (int j = 0; j < r; j++) {
-                    double s = (i == j) ? 1.0 : 0.0;
-                    for (int q = 0; q < r; q++) s -= G[i * r + q] * U[q * r + j];
-                    T[i * r + j] = s;
-                }
-            for (int i = 0; i < r; i++)       /* X + X T */
-                for (int j = 0; j < r; j++) {
-                    double s = U[i * r + j];
-                    for (int q = 0; q < r; q++) s += U[i * r + q] * T[q * r + j];
-                    X2[i * r + j] = s;
-                }
-            memcpy(U, X2, sizeof(double) * (size_t)r * (size_t)r);
-            free(T); free(X2);
-        }
+        orc_refine_inverse(G, r, U, refine_steps);
     }
     if (logdet) *logdet = ld;
     free(LU); free(p); free(col);

@@ -8,6 +8,7 @@ the library is missing or no GPU is present the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as ct
 import os
 import re
@@ -102,6 +103,9 @@ def load() -> ct.CDLL:
         L.lra_cur_adjoint.argtypes = [i64, i64, i64, i32, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
         L.lra_cur_adjoint.restype = ct.c_int
         _lib = L
+        # free the cached device workspaces while the HIP runtime is still up
+        # (interpreter exit runs this before the runtime's own teardown)
+        atexit.register(L.lra_release)
     return _lib
 
 
@@ -191,6 +195,21 @@ class CurOut:
         return recs[0] if len(recs) == 1 else recs
 
 
+def _check_out(out: CurOut, n_i: int, n_j: int, n_u: int, n_info: int, dev) -> None:
+    """A caller-supplied output set must hold exactly what the kernels write:
+    contiguous device tensors of n_i and n_j int64 indices, n_u float64
+    nucleus entries and n_info lra_info records, on the input's device."""
+    torch = _torch()
+    for name, t, numel, dt in (("I", out.I, n_i, torch.int64), ("J", out.J, n_j, torch.int64),
+                               ("U", out.U, n_u, torch.float64), ("info_raw", out.info_raw, n_info * INFO_BYTES,
+                                                                  torch.uint8)):
+        if not hasattr(t, "device") or t.device != dev:
+            raise ValueError("out.%s must be a tensor on %s" % (name, dev))
+        if t.dtype != dt or t.numel() != numel or not t.is_contiguous():
+            raise ValueError("out.%s must be a contiguous %s tensor of %d elements (got %s, %d)"
+                             % (name, dt, numel, t.dtype, t.numel()))
+
+
 # ------------------------------------------------------------------ entry points
 def lra_cur(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
             preprocess: int = LRA_PRE_NONE, ah_depth: int = 3, ah_samples: int = 0, refine_steps: int = 0,
@@ -209,6 +228,8 @@ def lra_cur(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps
         out = CurOut(torch.empty(r, dtype=torch.int64, device=dev), torch.empty(r, dtype=torch.int64, device=dev),
                      torch.empty((r, r), dtype=torch.float64, device=dev),
                      torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, r, r, r * r, 1, dev)
     o, keep = _make_opts(delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps, team_size, init_cols)
     st = load().lra_cur(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, sweeps,
                         ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
@@ -234,6 +255,8 @@ def lra_cur_hadamard(A, r: int, sweeps: int, seed: int, d: int, *, delta: float 
         out = CurOut(torch.empty(r, dtype=torch.int64, device=dev), torch.empty(r, dtype=torch.int64, device=dev),
                      torch.empty((r, r), dtype=torch.float64, device=dev),
                      torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, r, r, r * r, 1, dev)
     o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, team_size, None)
     st = load().lra_cur_hadamard(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, sweeps,
                                  ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), d, ct.byref(o), ct.c_void_p(out.I.data_ptr()),
@@ -260,6 +283,8 @@ def lra_cur_cynical(A, r: int, k: int, loops: int, sweeps: int, seed: int, *, de
         out = CurOut(torch.empty(r, dtype=torch.int64, device=dev), torch.empty(r, dtype=torch.int64, device=dev),
                      torch.empty((r, r), dtype=torch.float64, device=dev),
                      torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, r, r, r * r, 1, dev)
     o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, team_size, None)
     st = load().lra_cur_cynical(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, k, loops, sweeps,
                                 ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
@@ -287,6 +312,8 @@ def lra_cur_projective(A, r: int, k: int, l: int, sweeps: int, seed: int, *, del
         out = CurOut(torch.empty(k, dtype=torch.int64, device=dev), torch.empty(l, dtype=torch.int64, device=dev),
                      torch.empty((l, k), dtype=torch.float64, device=dev),
                      torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, k, l, l * k, 1, dev)
     o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, 0, team_size, None)
     st = load().lra_cur_projective(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, k, l, sweeps,
                                    ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
@@ -321,6 +348,8 @@ def lra_cur_batched(base, blocks, r: int, sweeps: int, seed: int, *, delta: floa
                      torch.empty((count, r), dtype=torch.int64, device=dev),
                      torch.empty((count, r, r), dtype=torch.float64, device=dev),
                      torch.empty(count * INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, count * r, count * r, count * r * r, count, dev)
     arr = (lra_block * max(count, 1))()
     ct.memmove(arr, desc.ctypes.data, desc.nbytes)
     o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, 0, None)
@@ -355,6 +384,8 @@ def lra_cur_uniform_batched(base, blocks, r: int, k: int, l: int, seed: int, *, 
                      torch.empty((count, l), dtype=torch.int64, device=dev),
                      torch.empty((count, l, k), dtype=torch.float64, device=dev),
                      torch.empty(count * INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, count * k, count * l, count * l * k, count, dev)
     arr = (lra_block * max(count, 1))()
     ct.memmove(arr, desc.ctypes.data, desc.nbytes)
     st = load().lra_cur_uniform_batched(ct.c_void_p(base.data_ptr()), _dtype_code(base), arr, count, r, k, l,
@@ -396,6 +427,8 @@ def lra_cur_leverage(A, I0, J0, k: int, l: int, seed: int, *, out: CurOut | None
         out = CurOut(torch.empty(k, dtype=torch.int64, device=dev), torch.empty(l, dtype=torch.int64, device=dev),
                      torch.empty((l, k), dtype=torch.float64, device=dev),
                      torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, k, l, l * k, 1, dev)
     st = load().lra_cur_leverage(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), int(I0.numel()),
                                  ct.c_void_p(I0.data_ptr()), ct.c_void_p(J0.data_ptr()), k, l,
                                  ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.c_void_p(out.I.data_ptr()),
@@ -427,6 +460,8 @@ def lra_cur_batched_points(pts, blocks, r: int, sweeps: int, seed: int, *, delta
                      torch.empty((count, r), dtype=torch.int64, device=dev),
                      torch.empty((count, r, r), dtype=torch.float64, device=dev),
                      torch.empty(count * INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, count * r, count * r, count * r * r, count, dev)
     arr = (lra_pts_block * max(count, 1))()
     ct.memmove(arr, desc.ctypes.data, desc.nbytes)
     o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, 0, None)

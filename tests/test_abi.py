@@ -268,3 +268,33 @@ def test_binding_refuses_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(lra, "_lib", None)
     with pytest.raises(ImportError):
         lra.load()
+
+
+def test_caller_outputs_are_checked_before_any_call():
+    """A caller-supplied out= must hold exactly what the kernels write; an
+    undersized or mistyped buffer is refused on the host (ValueError)."""
+    torch = pytest.importorskip("torch")
+    dev = torch.device("cpu")
+    r = 5
+
+    def outs(nI=r, nJ=r, nU=r * r, ninfo=1, dtI=torch.int64, dtU=torch.float64):
+        return lra.CurOut(torch.empty(nI, dtype=dtI), torch.empty(nJ, dtype=torch.int64),
+                          torch.empty(nU, dtype=dtU), torch.empty(ninfo * lra.INFO_BYTES, dtype=torch.uint8))
+
+    lra._check_out(outs(), r, r, r * r, 1, dev)
+    for bad in (outs(nI=r - 1), outs(nJ=r + 1), outs(nU=r * r - 1), outs(ninfo=0), outs(dtI=torch.int32),
+                outs(dtU=torch.float32)):
+        with pytest.raises(ValueError):
+            lra._check_out(bad, r, r, r * r, 1, dev)
+    # a non-contiguous view of the right size
+    o = outs()
+    o.U = torch.empty((r, 2 * r), dtype=torch.float64)[:, ::2]
+    with pytest.raises(ValueError):
+        lra._check_out(o, r, r, r * r, 1, dev)
+    # the k x l generators: I has k entries, J l, U l x k
+    k, l = 7, 9
+    o = lra.CurOut(torch.empty(k, dtype=torch.int64), torch.empty(l, dtype=torch.int64),
+                   torch.empty((l, k), dtype=torch.float64), torch.empty(lra.INFO_BYTES, dtype=torch.uint8))
+    lra._check_out(o, k, l, l * k, 1, dev)
+    with pytest.raises(ValueError):
+        lra._check_out(o, l, k, l * k, 1, dev)

@@ -7,8 +7,10 @@ the same on every run.
 
 Bars, as in the per-path tests: where the oracle's smallest decision margin
 is at least 1e-6 the index sets are equal and the reconstructions agree to
-1e-6 (FP64 input) or 1e-4 (FP32 / BF16); the r-projective runs also make the
-same number of exchanges; the uniform-score draws are integer work and are
+1e-6 (FP64 input) or 1e-4 (FP32 / BF16); below that margin equal sets are
+held to the same bar, and differing sets must be dominant (C-A paths) with
+an error against the input within the tolerance of the oracle's; the
+r-projective runs also make the same number of exchanges; the uniform-score draws are integer work and are
 equal always, and its reconstructions agree within the truncated
 pseudo-inverse's own condition.  A launch the layout cannot hold (a team of
 one with too large a panel) returns LRA_EUNSUPPORTED and the case is
@@ -105,15 +107,33 @@ def recon(A64, I, J, U):
     return A64[:, J] @ U @ A64[I]
 
 
-def check_sets(A, I, J, U, info, o, tol):
+def check_sets(A, I, J, U, info, o, tol, dominant_rows=False, delta=0.01):
+    """Where the oracle's decisions are stable (margin >= 1e-6), or the sets
+    agree anyway, the sets and reconstructions must match.  Otherwise (a
+    near-tie the two sides may break differently) the GPU's own result must
+    still be a valid answer: J dominant in A[I, :] after the last row step
+    of a converged C-A run, and an error against A that agrees with the
+    oracle's to tol * max(err_oracle, 1)."""
     assert info["status"] == o.status, (info, o.status)
-    if o.status != 0 or o.min_margin < 1e-6:
+    if o.status != 0:
         return
-    assert I.tolist() == o.I.tolist() and J.tolist() == o.J.tolist()
     A64 = as_f64(A)
-    Xo, Xg = recon(A64, o.I, o.J, o.U), recon(A64, I, J, U)
-    den = np.linalg.norm(Xo)
-    assert (np.linalg.norm(Xg - Xo) / den if den > 0 else np.linalg.norm(Xg)) <= tol
+    same = I.tolist() == o.I.tolist() and J.tolist() == o.J.tolist()
+    if o.min_margin >= 1e-6:
+        assert same
+    if same:
+        Xo, Xg = recon(A64, o.I, o.J, o.U), recon(A64, I, J, U)
+        den = np.linalg.norm(Xo)
+        assert (np.linalg.norm(Xg - Xo) / den if den > 0 else np.linalg.norm(Xg)) <= tol
+        return
+    print("low margin %.3e: sets differ, checking validity" % o.min_margin, flush=True)
+    if dominant_rows and info["converged"]:
+        R = A64[I]
+        assert np.abs(np.linalg.solve(R[:, J], R)).max() <= 1.0 + delta + 1e-9
+    nA = np.linalg.norm(A64)
+    err_o = np.linalg.norm(A64 - recon(A64, o.I, o.J, o.U)) / nA
+    err_g = np.linalg.norm(A64 - recon(A64, I, J, U)) / nA
+    assert abs(err_g - err_o) <= tol * max(err_o, 1.0), (err_g, err_o)
 
 
 @pytest.mark.parametrize("idx", range(len(CASES)))
@@ -155,6 +175,6 @@ def test_random_case(lra, idx):
             Xo, Xg = recon(A64, o.I, o.J, o.U), recon(A64, I, J, U)
             assert np.linalg.norm(Xg - Xo) / max(np.linalg.norm(Xo), 1e-300) <= bar
         return
-    check_sets(A, I, J, U, info, o, tol)
+    check_sets(A, I, J, U, info, o, tol, dominant_rows=path in ("plain", "asrht", "bidiag", "fourier"))
     if path == "projective" and o.status == 0 and o.min_margin >= 1e-6:
         assert info["swaps_total"] == o.swaps_total
