@@ -118,6 +118,33 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
                    int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                    double *U_out, lra_info *info, hipStream_t stream);
 
+/* Bytes of device scratch that lra_cur_noalloc keeps on each GPU it runs on. */
+#define LRA_NOALLOC_SCRATCH_BYTES 10626048
+
+/* lra_cur for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * computation, results and arguments as lra_cur, but every work buffer of
+ * the launch (the team exchange words, the bidiagonal column table, the
+ * global sketch panel) lives in one fixed device array of
+ * LRA_NOALLOC_SCRATCH_BYTES per GPU, set up on the first call on that GPU and
+ * held until the process ends.  The call allocates nothing: no hipMalloc,
+ * no hipFree, no host allocation.  The caller still owns W and the outputs.
+ *   - All calls on one GPU share its array, which keeps the last call's
+ *     contents: calls that overlap in time on one GPU (on different streams
+ *     or from different threads) race, and the caller must order them.  The
+ *     exchange words are cleared by a kernel at the start of every
+ *     multi-workgroup launch; nothing else has to start at zero.
+ *   - opts->init_cols must be NULL (LRA_EINVAL): a host start set would need
+ *     a staging copy.
+ *   - When the sketch slices do not fit on chip the launch needs
+ *     team x ceil(items / team) x l doubles of global sketch panel (items =
+ *     the dimension the multiplier acts on); above 8 MiB the call returns
+ *     LRA_EUNSUPPORTED and launches nothing.
+ * Errors and asynchrony otherwise as for lra_cur. */
+lra_status lra_cur_noalloc(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
+                           int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
+                           double *U_out, lra_info *info, hipStream_t stream);
+
 /* C-A CUR of the pre-processed matrix W' = W M (Section 13: Tests 2 on inputs
  * multiplied by an abridged randomized Hadamard matrix; Appendix B for the
  * multiplier).  M = D (H_{2^d} (x) I_s) has order N = 2^d s, s = ceil(n / 2^d)

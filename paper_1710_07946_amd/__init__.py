@@ -78,6 +78,8 @@ def load() -> ct.CDLL:
         L.lra_cur.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, ct.c_uint64, ct.POINTER(lra_opts), P, P, P, P,
                               P]
         L.lra_cur.restype = ct.c_int
+        L.lra_cur_noalloc.argtypes = L.lra_cur.argtypes
+        L.lra_cur_noalloc.restype = ct.c_int
         L.lra_cur_batched.argtypes = [P, ct.c_int, ct.POINTER(lra_block), i64, i32, i32, ct.c_uint64,
                                       ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_batched.restype = ct.c_int
@@ -211,14 +213,8 @@ def _check_out(out: CurOut, n_i: int, n_j: int, n_u: int, n_info: int, dev) -> N
 
 
 # ------------------------------------------------------------------ entry points
-def lra_cur(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
-            preprocess: int = LRA_PRE_NONE, ah_depth: int = 3, ah_samples: int = 0, refine_steps: int = 0,
-            team_size: int = 0, init_cols=None, out: CurOut | None = None, stream=None) -> CurOut:
-    """C-A CUR of a 2-D device tensor (row-major rows, unit column stride).
-
-    Asynchronous on the current (or given) stream; the returned tensors are
-    filled when the stream reaches the launch.  ``CurOut.info()`` syncs.
-    """
+def _cur_entry(name: str, A, r, sweeps, seed, delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps,
+               team_size, init_cols, out, stream) -> CurOut:
     torch = _torch()
     if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
         raise ValueError("A must be a 2-D device tensor with unit column stride")
@@ -231,14 +227,36 @@ def lra_cur(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps
     else:
         _check_out(out, r, r, r * r, 1, dev)
     o, keep = _make_opts(delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps, team_size, init_cols)
-    st = load().lra_cur(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, sweeps,
-                        ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
-                        ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
-                        ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
+    st = getattr(load(), name)(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, sweeps,
+                               ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
+                               ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
+                               ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
     del keep
     if st != LRA_OK:
-        raise LraError(st, "lra_cur")
+        raise LraError(st, name)
     return out
+
+
+def lra_cur(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
+            preprocess: int = LRA_PRE_NONE, ah_depth: int = 3, ah_samples: int = 0, refine_steps: int = 0,
+            team_size: int = 0, init_cols=None, out: CurOut | None = None, stream=None) -> CurOut:
+    """C-A CUR of a 2-D device tensor (row-major rows, unit column stride).
+
+    Asynchronous on the current (or given) stream; the returned tensors are
+    filled when the stream reaches the launch.  ``CurOut.info()`` syncs.
+    """
+    return _cur_entry("lra_cur", A, r, sweeps, seed, delta, max_swaps, preprocess, ah_depth, ah_samples,
+                      refine_steps, team_size, init_cols, out, stream)
+
+
+def lra_cur_noalloc(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
+                    preprocess: int = LRA_PRE_NONE, ah_depth: int = 3, ah_samples: int = 0, refine_steps: int = 0,
+                    team_size: int = 0, out: CurOut | None = None, stream=None) -> CurOut:
+    """``lra_cur`` with every work buffer in the library's fixed per-GPU scratch
+    (no device allocation by the library; pass ``out`` to allocate nothing
+    here either).  Calls that overlap on one GPU race."""
+    return _cur_entry("lra_cur_noalloc", A, r, sweeps, seed, delta, max_swaps, preprocess, ah_depth, ah_samples,
+                      refine_steps, team_size, None, out, stream)
 
 
 def lra_cur_hadamard(A, r: int, sweeps: int, seed: int, d: int, *, delta: float = 0.01, max_swaps: int = -1,

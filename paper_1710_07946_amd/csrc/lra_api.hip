@@ -36,21 +36,21 @@ struct Workspace {
     int32_t *bidiag = nullptr;      // bidiagonal-multiplier column table (kBdTableInts)
     double *sketch = nullptr;       // global sketch panels when they do not fit LDS
     size_t sketch_cap = 0;          // bytes
-    void *scratch = nullptr;        // residual / adjoint work arrays
-    size_t scratch_cap = 0;         // bytes
+    void *work = nullptr;           // residual / adjoint / leverage work arrays
+    size_t work_cap = 0;            // bytes
 };
 
-// Grow-only scratch of a workspace (the stream is drained before a reallocation).
-lra_status ws_scratch(Workspace *w, hipStream_t stream, size_t bytes, void **out) {
-    if (w->scratch_cap < bytes) {
+// Grow-only work array of a workspace (the stream is drained before a reallocation).
+lra_status ws_work(Workspace *w, hipStream_t stream, size_t bytes, void **out) {
+    if (w->work_cap < bytes) {
         (void)hipStreamSynchronize(stream);
-        (void)hipFree(w->scratch);
-        w->scratch = nullptr;
-        w->scratch_cap = 0;
-        if (hipMalloc(&w->scratch, bytes) != hipSuccess) return LRA_ENOMEM;
-        w->scratch_cap = bytes;
+        (void)hipFree(w->work);
+        w->work = nullptr;
+        w->work_cap = 0;
+        if (hipMalloc(&w->work, bytes) != hipSuccess) return LRA_ENOMEM;
+        w->work_cap = bytes;
     }
-    *out = w->scratch;
+    *out = w->work;
     return LRA_OK;
 }
 
@@ -66,16 +66,14 @@ struct DevInfo {
 };
 std::map<int, DevInfo> g_dev;
 
+lra_status query_dev(int dev, DevInfo *d);
+
 lra_status dev_info(int dev, DevInfo *out) {
     auto it = g_dev.find(dev);
     if (it == g_dev.end()) {
         DevInfo d;
-        if (hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-            return LRA_EDEVICE;
-        if (hipDeviceGetAttribute(&d.lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-            return LRA_EDEVICE;
-        if (hipDeviceGetAttribute(&d.wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || d.wall_khz <= 0)
-            d.wall_khz = 100000;
+        lra_status st = query_dev(dev, &d);
+        if (st != LRA_OK) return st;
         it = g_dev.emplace(dev, d).first;
     }
     *out = it->second;
@@ -177,6 +175,141 @@ LdsPlan plan_lds(int64_t m, int64_t n, int r, int pre, int l, int team, size_t b
     return p;
 }
 
+// Options, launch geometry and global sketch size of one lra_cur call (shared
+// by lra_cur and lra_cur_noalloc).
+struct CurPlan {
+    CAConfig cfg;
+    lra_opts o;
+    int team = 0;
+    LdsPlan lds;
+    size_t sketch_bytes = 0;  // global sketch panel (0: the sketch slices live in LDS)
+};
+
+// Argument checks of lra_cur that need no device state.
+lra_status check_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t sweeps,
+                     const lra_opts *opts, const int64_t *I_out, const int64_t *J_out, const double *U_out,
+                     CurPlan *cp) {
+    if (!W || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n || sweeps < 1) return LRA_EINVAL;
+    if (m >= ((int64_t)1 << 39) || n >= ((int64_t)1 << 39)) return LRA_EINVAL;  // item ids travel in 40 bits
+    lra_opts &o = cp->o;
+    lra_status st = fill_config(opts, r, sweeps, &cp->cfg, &o);
+    if (st != LRA_OK) return st;
+    if (o.preprocess == LRA_PRE_ASRHT || o.preprocess == LRA_PRE_ASRFT) {
+        const int64_t dim = (m >= n) ? m : n;  // the dimension the multiplier acts on
+        const int64_t q2 = (int64_t)1 << o.ah_depth;
+        const int64_t N = q2 * ((dim + q2 - 1) / q2);
+        if (o.ah_samples > N) return LRA_EINVAL;
+    }
+    if (o.preprocess == LRA_PRE_BIDIAG) {
+        const int64_t dim = (m >= n) ? m : n;  // the dimension the multiplier acts on
+        if (dim < 2 || dim > (int64_t)INT32_MAX || o.ah_samples > dim) return LRA_EINVAL;
+    }
+    if (o.init_cols) {
+        if (o.preprocess != LRA_PRE_NONE) return LRA_EINVAL;
+        for (int a = 0; a < r; a++) {
+            if (o.init_cols[a] < 0 || o.init_cols[a] >= n) return LRA_EINVAL;
+            for (int b = 0; b < a; b++)
+                if (o.init_cols[a] == o.init_cols[b]) return LRA_EINVAL;
+        }
+    }
+    return LRA_OK;
+}
+
+// Team size and LDS plan of an lra_cur call.  Team size: the smallest number
+// of workgroups whose panel slices fit in LDS, but at least one workgroup per
+// 160 items (more workgroups shorten the per-decision scans, fewer make each
+// team selection cheaper; 160 was the best trade-off measured on the
+// 20000 x 20000 rank-50 workload).
+lra_status plan_cur(const DevInfo &dinfo, int64_t m, int64_t n, int32_t r, CurPlan *cp) {
+    const lra_opts &o = cp->o;
+    const int max_team = std::min(dinfo.cus, kMaxTeam);
+    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
+    // real width of the sketch panel (the Fourier sketch keeps Re and Im)
+    const int wsk = o.preprocess == LRA_PRE_ASRFT ? 2 * o.ah_samples : o.ah_samples;
+    int team;
+    LdsPlan plan;
+    if (o.team_size > 0) {
+        team = std::min(o.team_size, max_team);
+        plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
+    } else {
+        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, n) + 159) / 160));
+        plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
+        while (!plan.fits && team < max_team) {
+            team++;
+            plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
+        }
+    }
+    if (!plan.fits) return LRA_EUNSUPPORTED;
+    cp->team = team;
+    cp->lds = plan;
+    cp->cfg.panel_bytes = (int32_t)plan.panel_bytes;
+    cp->sketch_bytes = plan.sketch_global ? (size_t)team * (plan.ipw_s | 1) * wsk * sizeof(double) : 0;
+    return LRA_OK;
+}
+
+lra_status query_dev(int dev, DevInfo *d) {
+    if (hipDeviceGetAttribute(&d->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return LRA_EDEVICE;
+    if (hipDeviceGetAttribute(&d->lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return LRA_EDEVICE;
+    if (hipDeviceGetAttribute(&d->wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || d->wall_khz <= 0)
+        d->wall_khz = 100000;
+    return LRA_OK;
+}
+
+// Layout of the no-allocation scratch (byte offsets): the team exchange
+// words for the largest team, the bidiagonal column table, then the global
+// sketch panel, whose size bounds the shapes lra_cur_noalloc accepts.
+constexpr size_t kNaXwOffset = 0;
+constexpr size_t kNaXwBytes = (size_t)2 * kMaxTeam * lra::kSlotWords * sizeof(uint64_t);
+constexpr size_t kNaBdOffset = kNaXwOffset + ((kNaXwBytes + 255) & ~size_t(255));
+constexpr size_t kNaBdBytes = sizeof(int32_t) * lra::kBdTableInts;
+constexpr size_t kNaSketchOffset = kNaBdOffset + ((kNaBdBytes + 255) & ~size_t(255));
+constexpr size_t kNaSketchBytes = (size_t)8 << 20;
+constexpr size_t kNaBytes = kNaSketchOffset + kNaSketchBytes;
+static_assert(kNaBytes == LRA_NOALLOC_SCRATCH_BYTES, "the header states the scratch size");
+
+}  // namespace
+
+// Device scratch of lra_cur_noalloc: one copy per GPU, kept until the
+// process ends.  In host code `scratch` only names the symbol; kernels get
+// the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+// Per device: the address of `scratch` and the launch limits, set up once
+// with the device current (fixed table: the no-allocation path allocates no
+// host memory either).
+constexpr int kNaMaxDev = 64;
+struct NaDev {
+    bool ready = false;
+    unsigned char *ptr = nullptr;
+    DevInfo info;
+};
+NaDev g_na[kNaMaxDev];
+
+lra_status na_dev(NaDev **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LRA_EDEVICE;
+    if (dev < 0 || dev >= kNaMaxDev) return LRA_EUNSUPPORTED;
+    NaDev &d = g_na[dev];
+    if (!d.ready) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return LRA_EDEVICE;
+        }
+        lra_status st = query_dev(dev, &d.info);
+        if (st != LRA_OK) return st;
+        d.ptr = static_cast<unsigned char *>(p);
+        d.ready = true;
+    }
+    *out = &d;
+    return LRA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -220,7 +353,7 @@ void lra_release(void) {
         (void)hipFree(w.order);
         (void)hipFree(w.sketch);
         (void)hipFree(w.bidiag);
-        (void)hipFree(w.scratch);
+        (void)hipFree(w.work);
     }
     g_ws.clear();
     (void)hipSetDevice(cur);
@@ -229,86 +362,38 @@ void lra_release(void) {
 lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t sweeps,
                    uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info,
                    hipStream_t stream) {
-    if (!W || !I_out || !J_out || !U_out) return LRA_EINVAL;
-    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
-    if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n || sweeps < 1) return LRA_EINVAL;
-    if (m >= ((int64_t)1 << 39) || n >= ((int64_t)1 << 39)) return LRA_EINVAL;  // item ids travel in 40 bits
-    CAConfig cfg;
-    lra_opts o;
-    lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
+    CurPlan cp;
+    lra_status st = check_cur(W, dt, m, n, lda, r, sweeps, opts, I_out, J_out, U_out, &cp);
     if (st != LRA_OK) return st;
-    if (o.preprocess == LRA_PRE_ASRHT || o.preprocess == LRA_PRE_ASRFT) {
-        const int64_t dim = (m >= n) ? m : n;  // the dimension the multiplier acts on
-        const int64_t q2 = (int64_t)1 << o.ah_depth;
-        const int64_t N = q2 * ((dim + q2 - 1) / q2);
-        if (o.ah_samples > N) return LRA_EINVAL;
-    }
-    if (o.preprocess == LRA_PRE_BIDIAG) {
-        const int64_t dim = (m >= n) ? m : n;  // the dimension the multiplier acts on
-        if (dim < 2 || dim > (int64_t)INT32_MAX || o.ah_samples > dim) return LRA_EINVAL;
-    }
-    if (o.init_cols) {
-        if (o.preprocess != LRA_PRE_NONE) return LRA_EINVAL;
-        for (int a = 0; a < r; a++) {
-            if (o.init_cols[a] < 0 || o.init_cols[a] >= n) return LRA_EINVAL;
-            for (int b = 0; b < a; b++)
-                if (o.init_cols[a] == o.init_cols[b]) return LRA_EINVAL;
-        }
-    }
 
     std::lock_guard<std::mutex> lk(g_mu);
     Workspace *ws = nullptr;
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
     DevInfo dinfo;
     if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
-    const int max_team = std::min(dinfo.cus, kMaxTeam);
-    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
-
-    // Team size: the smallest number of workgroups whose panel slices fit in
-    // LDS, but at least one workgroup per 160 items (more workgroups shorten
-    // the per-decision scans, fewer make each team selection cheaper; 160 was
-    // the best trade-off measured on the 20000 x 20000 rank-50 workload).
-    int team;
-    LdsPlan plan;
-    // real width of the sketch panel (the Fourier sketch keeps Re and Im)
-    const int wsk = o.preprocess == LRA_PRE_ASRFT ? 2 * o.ah_samples : o.ah_samples;
-    if (o.team_size > 0) {
-        team = std::min(o.team_size, max_team);
-        plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
-    } else {
-        team = (int)std::min<int64_t>(max_team, std::max<int64_t>(1, (std::max(m, n) + 159) / 160));
-        plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
-        while (!plan.fits && team < max_team) {
-            team++;
-            plan = plan_lds(m, n, r, o.preprocess, wsk, team, lds_budget);
-        }
-    }
-    if (!plan.fits) return LRA_EUNSUPPORTED;
-    cfg.panel_bytes = (int32_t)plan.panel_bytes;
-    const size_t dyn = plan.dyn_bytes;
-    if (plan.sketch_global) {
-        const size_t need = (size_t)team * (plan.ipw_s | 1) * wsk * sizeof(double);
-        if (ws->sketch_cap < need) {
+    if ((st = plan_cur(dinfo, m, n, r, &cp)) != LRA_OK) return st;
+    CAConfig &cfg = cp.cfg;
+    if (cp.sketch_bytes) {
+        if (ws->sketch_cap < cp.sketch_bytes) {
             (void)hipStreamSynchronize(stream);
             (void)hipFree(ws->sketch);
             ws->sketch = nullptr;
             ws->sketch_cap = 0;
-            if (hipMalloc(&ws->sketch, need) != hipSuccess) return LRA_ENOMEM;
-            ws->sketch_cap = need;
+            if (hipMalloc(&ws->sketch, cp.sketch_bytes) != hipSuccess) return LRA_ENOMEM;
+            ws->sketch_cap = cp.sketch_bytes;
         }
         cfg.sketch_ws = ws->sketch;
     }
-
-    if (o.init_cols) {
-        if (hipMemcpyAsync(ws->init_cols, o.init_cols, sizeof(int64_t) * r, hipMemcpyHostToDevice, stream) !=
+    if (cp.o.init_cols) {
+        if (hipMemcpyAsync(ws->init_cols, cp.o.init_cols, sizeof(int64_t) * r, hipMemcpyHostToDevice, stream) !=
             hipSuccess)
             return LRA_EDEVICE;
         cfg.init_cols = ws->init_cols;
     }
-    if (o.preprocess == LRA_PRE_BIDIAG) {
+    if (cp.o.preprocess == LRA_PRE_BIDIAG) {
         if (!ws->bidiag && hipMalloc(&ws->bidiag, sizeof(int32_t) * lra::kBdTableInts) != hipSuccess)
             return LRA_ENOMEM;
-        if (lra::launch_bidiag_table(seed, (m >= n) ? m : n, o.ah_depth, o.ah_samples, ws->bidiag, stream) !=
+        if (lra::launch_bidiag_table(seed, (m >= n) ? m : n, cp.o.ah_depth, cp.o.ah_samples, ws->bidiag, stream) !=
             hipSuccess) {
             (void)hipGetLastError();
             return LRA_EDEVICE;
@@ -318,7 +403,43 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
     // a team selection normally completes in microseconds; two seconds
     // without the expected word means the launch has failed
     TeamWs tws{ws->xw, (uint64_t)dinfo.wall_khz * 2000ull};
-    hipError_t e = lra::launch_team(dt, W, m, n, lda, seed, cfg, tws, team, dyn, I_out, J_out, U_out, info, stream);
+    hipError_t e = lra::launch_team(dt, W, m, n, lda, seed, cfg, tws, cp.team, cp.lds.dyn_bytes, I_out, J_out, U_out,
+                                    info, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
+lra_status lra_cur_noalloc(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, int32_t sweeps,
+                           uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out, double *U_out,
+                           lra_info *info, hipStream_t stream) {
+    CurPlan cp;
+    lra_status st = check_cur(W, dt, m, n, lda, r, sweeps, opts, I_out, J_out, U_out, &cp);
+    if (st != LRA_OK) return st;
+    if (cp.o.init_cols) return LRA_EINVAL;  // a host array would need a staging copy
+
+    std::lock_guard<std::mutex> lk(g_mu);
+    NaDev *nd = nullptr;
+    if ((st = na_dev(&nd)) != LRA_OK) return st;
+    if ((st = plan_cur(nd->info, m, n, r, &cp)) != LRA_OK) return st;
+    if (cp.sketch_bytes > kNaSketchBytes) return LRA_EUNSUPPORTED;
+    CAConfig &cfg = cp.cfg;
+    uint64_t *xw = reinterpret_cast<uint64_t *>(nd->ptr + kNaXwOffset);
+    if (cp.sketch_bytes) cfg.sketch_ws = reinterpret_cast<double *>(nd->ptr + kNaSketchOffset);
+    if (cp.o.preprocess == LRA_PRE_BIDIAG) {
+        int32_t *tab = reinterpret_cast<int32_t *>(nd->ptr + kNaBdOffset);
+        if (lra::launch_bidiag_table(seed, (m >= n) ? m : n, cp.o.ah_depth, cp.o.ah_samples, tab, stream) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return LRA_EDEVICE;
+        }
+        cfg.bd_table = tab;
+    }
+    TeamWs tws{xw, (uint64_t)nd->info.wall_khz * 2000ull};
+    hipError_t e = lra::launch_team(dt, W, m, n, lda, seed, cfg, tws, cp.team, cp.lds.dyn_bytes, I_out, J_out, U_out,
+                                    info, stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;
@@ -549,7 +670,7 @@ lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, i
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
     const size_t bytes = lra::leverage_scratch_bytes(m, n, r);
     void *scr = nullptr;
-    if ((st = ws_scratch(ws, stream, bytes + 64, &scr)) != LRA_OK) return st;
+    if ((st = ws_work(ws, stream, bytes + 64, &scr)) != LRA_OK) return st;
     double *lw = static_cast<double *>(scr);
     int32_t *flags = reinterpret_cast<int32_t *>(static_cast<char *>(scr) + bytes);
     hipError_t e = lra::launch_leverage(dt, W, m, n, lda, r, I0, J0, k, l, seed, lw, flags, I_out, J_out, U_out,
@@ -712,10 +833,10 @@ lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64
     Workspace *ws = nullptr;
     lra_status st;
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
-    void *scratch = nullptr;
-    if ((st = ws_scratch(ws, stream, lra::residual_scratch_bytes(m, n, r, q, s, prec), &scratch)) != LRA_OK)
+    void *scr = nullptr;
+    if ((st = ws_work(ws, stream, lra::residual_scratch_bytes(m, n, r, q, s, prec), &scr)) != LRA_OK)
         return st;
-    if (lra::launch_residual(dt, W, m, n, lda, r, I, J, U, q, s, seed, prec, moments, scratch, stream) !=
+    if (lra::launch_residual(dt, W, m, n, lda, r, I, J, U, q, s, seed, prec, moments, scr, stream) !=
         hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;
@@ -736,9 +857,9 @@ lra_status lra_cur_adjoint(int64_t count, int64_t m, int64_t n, int32_t r, const
     Workspace *ws = nullptr;
     lra_status st;
     if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
-    void *scratch = nullptr;
-    if ((st = ws_scratch(ws, stream, lra::adjoint_scratch_bytes(count, m, n, nnz, r), &scratch)) != LRA_OK) return st;
-    if (lra::launch_adjoint(count, m, n, r, C, R, G, nnz, om_row, om_col, col_order, a_om, loss, dC, dR, dG, scratch,
+    void *scr = nullptr;
+    if ((st = ws_work(ws, stream, lra::adjoint_scratch_bytes(count, m, n, nnz, r), &scr)) != LRA_OK) return st;
+    if (lra::launch_adjoint(count, m, n, r, C, R, G, nnz, om_row, om_col, col_order, a_om, loss, dC, dR, dG, scr,
                             status, stream) != hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;
