@@ -74,6 +74,7 @@ def lib():
         L.orc_residual.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, P, P]
         L.orc_cur_adjoint.argtypes = [P, P, P, i64, i64, ct.c_int, P, P, P, i64, P, P, P, P]
         L.orc_residual_moments.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, i64, i64, u64, P]
+        L.orc_posterior_test.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, P, P, P, i64, i64, u64, dbl, dbl, P]
         L.orc_fmm_entries.argtypes = [P, i64, P, i64, P]
         L.orc_hadamard_apply.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, u64, P]
         L.orc_feistel.argtypes = [u64, ct.c_int, i64, i64]
@@ -99,7 +100,7 @@ def lib():
                   "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag",
                   "orc_hadamard_apply", "orc_pinv_trunc", "orc_projective_select", "orc_projective_cur",
                   "orc_draw_uniform", "orc_uniform_cur", "orc_sketch_fourier", "orc_leverage_scores",
-                  "orc_leverage_cur"):
+                  "orc_leverage_cur", "orc_posterior_test"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -464,6 +465,23 @@ def residual_moments(A, I, J, U, q: int = 0, s: int = 0, seed: int = 0) -> np.nd
     if st:
         raise ValueError("residual_moments: status %d" % st)
     return out
+
+
+def posterior_test(A, I, J, U, q: int, s: int, seed: int, tau: float, z: float) -> dict:
+    """The a-posteriori variance test on a seeded q x s sample of E = A - C U R
+    (orc_posterior_test): K, mean, mean_abs, var, threshold, accept."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    I = np.ascontiguousarray(I, np.int64)
+    J = np.ascontiguousarray(J, np.int64)
+    U = np.ascontiguousarray(U, np.float64)
+    out = np.zeros(6)
+    st = lib().orc_posterior_test(_p(A), _dtype_code(A), m, n, n, len(I), _p(I), _p(J), _p(U), q, s, seed,
+                                  ct.c_double(tau), ct.c_double(z), _p(out))
+    if st:
+        raise ValueError("posterior_test: status %d" % st)
+    return {"K": int(out[0]), "mean": out[1], "mean_abs": out[2], "var": out[3], "threshold": out[4],
+            "accept": bool(out[5])}
 
 
 def rel_fro(A, I, J, U) -> float:

@@ -1123,6 +1123,69 @@ int orc_residual_moments(const void *A, int dtype, int64_t m, int64_t n, int64_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Superfast a-posteriori test (Section 4, the subsection on matrices       */
+/* filled with i.i.d. values of one variable): the K = q s entries g_i of a  */
+/* random q x s submatrix of E = W - C U R (rows from stream 3, columns from */
+/* stream 4, as orc_residual_moments) are taken as observed values of one   */
+/* Gaussian variable; then a customary test for its variance.               */
+/*   mean_abs = (1/K) sum |g_i|      (the observed average as printed)       */
+/*   mean     = (1/K) sum g_i                                               */
+/*   var      = (1/K) sum (g_i - mean)^2                                     */
+/* Reading: the centre of the printed variance is the sample mean (the      */
+/* printed average of |g_i| would bias it upwards for a centred variable).  */
+/* Test of H0: sigma^2 >= tau^2 against sigma^2 < tau^2 at the one-sided    */
+/* normal level z of the chi-square statistic K var / sigma^2 (mean K - 1,  */
+/* variance 2 (K - 1)): accept the LRA (reject H0) iff                       */
+/*   K var <= tau^2 ((K - 1) - z sqrt(2 (K - 1))),                          */
+/* i.e. var <= (1 - t) tau^2 (K - 1) / K with the paper's relative         */
+/* deviation t = z sqrt(2 / (K - 1)).                                        */
+/* out: [K, mean, mean_abs, var, threshold on var, accept (1 or 0)].        */
+/* ------------------------------------------------------------------------ */
+int orc_posterior_test(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,
+                       const int64_t *J, const double *U, int64_t q, int64_t s, uint64_t seed, double tau, double z,
+                       double *out) {
+    if (!A || !I || !J || !U || !out || r < 1 || m < 1 || n < 1 || lda < n || q < 1 || s < 1 || q > m || s > n ||
+        q * s < 2 || !(tau > 0.0) || !isfinite(tau) || !isfinite(z))
+        return ORC_EINVAL;
+    const int64_t K = q * s;
+    int64_t *rows = (int64_t *)malloc(sizeof(int64_t) * (size_t)q);
+    int64_t *cols = (int64_t *)malloc(sizeof(int64_t) * (size_t)s);
+    orc_draw_distinct(seed, 3, m, q, rows);
+    orc_draw_distinct(seed, 4, n, s, cols);
+    /* the sampled entries of E, entry (a, c) at g[a s + c] */
+    double *g = (double *)malloc(sizeof(double) * (size_t)K);
+    for (int64_t a = 0; a < q; a++)
+        for (int64_t c = 0; c < s; c++) {
+            double x = 0.0; /* (C U R)[rows[a], cols[c]] = sum_i C[rows[a], i] (U R)[i, cols[c]] */
+            for (int i = 0; i < r; i++) {
+                double ur = 0.0;
+                for (int j = 0; j < r; j++) ur += U[i * r + j] * orc_get(A, dtype, lda, I[j], cols[c]);
+                x += orc_get(A, dtype, lda, rows[a], J[i]) * ur;
+            }
+            g[a * s + c] = orc_get(A, dtype, lda, rows[a], cols[c]) - x;
+        }
+    double sum = 0.0, sabs = 0.0;
+    for (int64_t k = 0; k < K; k++) {
+        sum += g[k];
+        sabs += fabs(g[k]);
+    }
+    const double mean = sum / (double)K;
+    double ss = 0.0;
+    for (int64_t k = 0; k < K; k++) ss += (g[k] - mean) * (g[k] - mean);
+    const double var = ss / (double)K;
+    const double dof = (double)(K - 1);
+    const double thr = tau * tau * (dof - z * sqrt(2.0 * dof)) / (double)K;
+    out[0] = (double)K;
+    out[1] = mean;
+    out[2] = sabs / (double)K;
+    out[3] = var;
+    out[4] = thr;
+    out[5] = var <= thr ? 1.0 : 0.0;
+    free(rows); free(cols); free(g);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Far-field interaction block of two planar point sets (the Superfast      */
 /* Multipole discussion in Section "Some Implications and Extensions of Our */
 /* Study": generators of blocks K_ij = 1/|x_i - y_j| between well separated */
