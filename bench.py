@@ -179,6 +179,13 @@ def main():
         "swaps_total": info["swaps_total"],
     }
 
+    hop_ns = lra.lra_probe_exchange(20000)
+    sel = selections_per_lra(M, N, RANK, info["sweeps_run"], info["swaps_total"], 1, SAMPLES)
+    min_ms = sel * hop_ns * 1e-6
+    rec["latency_roofline"] = {"bound": "cross-XCD exchange latency", "selections": sel, "hop_ns": hop_ns,
+                               "min_ms": min_ms, "achieved_ms": kernel_ms, "frac": min_ms / kernel_ms}
+    if not args.no_secondary:
+        rec["hbm_stream_probe"] = hbm_stream_probe(torch)
     if resid is not None:
         rec["residual"] = resid
     if not args.no_cpu_baseline:
@@ -194,7 +201,7 @@ def main():
                 break
         rec["cpu_baseline"] = {"value": len(times) / sum(times), "unit": "LRAs/s", "cores": 1, "kind": "oracle",
                                "sample": "%d full LRAs of the same 20000x20000 workload, single-threaded FP64 oracle"
-                                         % len(times)}
+                                         % len(times), "host": host_info()}
         rows = np.sort(np.random.default_rng(0).choice(M, 400, replace=False))
         A64 = A_np[rows].astype(np.float64)
         Xo = A64[:, res.J] @ res.U @ A_np[res.I].astype(np.float64)
@@ -313,6 +320,58 @@ def oracle_free_sign(seed, c):
     return -1.0 if z >> 63 else 1.0
 
 
+def host_info():
+    """Host cores and CPU model, for the CPU baselines."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def oracle_rate(jobs, threads, seconds):
+    """Run oracle jobs (callables) on `threads` host threads (the oracle's
+    calls release the interpreter lock) for about `seconds`, or until the
+    list is used up; returns (jobs done, wall seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    done = 0
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        for i in range(0, len(jobs), threads):
+            list(ex.map(lambda f: f(), jobs[i:i + threads]))
+            done += len(jobs[i:i + threads])
+            if time.perf_counter() - t0 >= seconds:
+                break
+    return done, time.perf_counter() - t0
+
+
+def hbm_stream_probe(torch):
+    """Attainable HBM bandwidth from torch kernels on 2 GiB: a device-to-device
+    copy (read + write) and a sum (read)."""
+    x = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    nbytes = x.numel() * 4
+    ms_copy = _time_events(torch, lambda: y.copy_(x), 10, 2)
+    ms_sum = _time_events(torch, lambda: x.sum(), 10, 2)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"copy_gbs": 2 * nbytes / (ms_copy * 1e-3) / 1e9, "read_gbs": nbytes / (ms_sum * 1e-3) / 1e9,
+            "bytes": nbytes, "kernels": "torch copy_ and sum on 2 GiB fp32"}
+
+
+def selections_per_lra(m, n, r, sweeps_run, swaps_total, pre, samples):
+    """Team-wide decisions of one LRA: r QRP pivots of the sketch start, r LU
+    pivots and one stop test per step (2 per sweep, plus the seed row step
+    when the sketch picks rows), and one per swap."""
+    steps = 2 * sweeps_run + (1 if (pre and m < n) else 0)
+    return (r if pre else 0) + steps * (r + 1) + swaps_total
+
+
 def _time_events(torch, fn, steps, warmup):
     """Mean milliseconds of fn() over `steps` calls, HIP events on the current stream."""
     for _ in range(warmup):
@@ -393,7 +452,24 @@ def bench_batched(lra, workloads, torch, np, args):
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": None},
         "useful_bytes_per_batch": nbytes,
+        "bin_rules": [list(q) for q in lra.lra_batch_get_rules()],
     }
+    if not args.no_cpu_baseline:
+        import oracle
+        hostbuf = base.cpu().numpy()
+
+        def job(b):
+            o0, m, n = int(desc[b][0]), int(desc[b][1]), int(desc[b][2])
+            return lambda: oracle.ca_cur(hostbuf[o0:o0 + m * n].reshape(m, n), r, sweeps, seed + b)
+
+        nth = os.cpu_count() or 1
+        d1, t1 = oracle_rate([job(b) for b in range(0, count, 97)], 1, args.cpu_seconds / 2)
+        dn, tn = oracle_rate([job(b) for b in range(count)], nth, args.cpu_seconds / 2)
+        res["cpu_baseline"] = {"value": dn / tn, "unit": "LRAs/s", "cores": nth, "kind": "oracle",
+                               "value_1_core": d1 / t1,
+                               "sample": "%d blocks on %d threads, %d blocks on 1 thread (blocks in index order, "
+                                         "sizes as in the batch)" % (dn, nth, d1),
+                               "host": host_info()}
     # the same blocks by CUR with uniform leverage scores (k = l = 4r = 64
     # rows and columns drawn with replacement, rank-16 canonical nucleus):
     # only the 64 x 64 generator of each block is read
@@ -491,7 +567,21 @@ def bench_adjoint(lra, workloads, torch, np, args):
     st = out["r"][4]
     nbytes = count * (2 * 8 * (m * r + r * n + r * r) + nnz * (4 + 4 + 4 + 8))
     gbs = nbytes / (ms * 1e-3) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = os.cpu_count() or 1
+        sample = min(count, 2 * nth)
+        host = [(C[b].cpu().numpy(), R[b].cpu().numpy(), G[b].cpu().numpy(), om_row[b].cpu().numpy(),
+                 om_col[b].cpu().numpy(), a_om[b].cpu().numpy()) for b in range(sample)]
+        jobs = [(lambda h=h: oracle.cur_adjoint(*h)) for h in host]
+        d1, t1 = oracle_rate(jobs[:2], 1, args.cpu_seconds / 2)
+        dn, tn = oracle_rate(jobs, nth, args.cpu_seconds / 2)
+        cpu = {"value": dn / tn, "unit": "blocks/s", "cores": nth, "kind": "oracle", "value_1_core": d1 / t1,
+               "sample": "%d blocks on %d threads, %d on 1 thread (FP64 analytic loss and gradients)"
+                         % (dn, nth, d1), "host": host_info()}
     return {
+        "cpu_baseline": cpu,
         "workload": "256 blocks 2048x2048 fp32 rank-32 + N(0,1e-5^2), r=32, |Omega|=41943 per block, FP64",
         "blocks_per_s": count / (ms * 1e-3), "ms_per_launch": ms,
         "failed_blocks": int((st != 0).sum().item()),

@@ -222,15 +222,45 @@ typedef struct {
     int64_t offset, m, n, lda;
 } lra_block;
 
-/* C-A CUR of many independent blocks in one persistent launch (one workgroup
- * per block, blocks taken from a device work queue largest first).  Block b
- * uses seed + b.  `blocks` is a HOST array of `count` descriptors; outputs
- * are packed: I_out/J_out int64[count * r], U_out double[count * r * r],
- * infos lra_info[count] (device, may be NULL).  opts->preprocess and
+/* C-A CUR of many independent blocks (one workgroup per block, blocks taken
+ * from device work queues largest first).  Block b uses seed + b and gets
+ * exactly the sets and nucleus that lra_cur returns for it alone with seed
+ * + b.  Blocks are binned by max(m, n) with the rule table below; each bin is
+ * one persistent launch on `stream`, of the register-panel kernel variant
+ * its rule names, or of the LDS-panel kernel when no rule covers the block.
+ * `blocks` is a HOST array of `count` descriptors, copied through a pinned
+ * staging buffer (the call does not wait for the device; a call whose
+ * descriptors equal the previous call's on this stream copies nothing).
+ * Outputs are packed: I_out/J_out int64[count * r], U_out double[count * r *
+ * r], infos lra_info[count] (device, may be NULL).  opts->preprocess and
  * opts->init_cols are not supported here (LRA_EINVAL). */
 lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
                            int32_t sweeps, uint64_t seed, const lra_opts *opts, int64_t *I_out, int64_t *J_out,
                            double *U_out, lra_info *infos, hipStream_t stream);
+
+/* One rule of the batched launch's bin table: blocks of rank r whose larger
+ * dimension is at most max_dim (and above every smaller rule's) run on the
+ * register-panel kernel with items_per_lane x waves x 64 item slots per
+ * workgroup (waves wavefronts of 64 lanes, each lane holding items_per_lane
+ * items of the panel in registers); items_per_lane = 0 sends them to the
+ * LDS-panel kernel.  Variants exist for r = 16 with items_per_lane = 2 and
+ * waves 1 .. 8 (up to 1024 items).  Every variant computes the same results;
+ * only speed differs. */
+typedef struct {
+    int32_t max_dim, r, items_per_lane, waves;
+} lra_batch_rule;
+
+/* Replace the process-wide bin table of lra_cur_batched and
+ * lra_cur_batched_points (count <= 64 rules, applied in increasing max_dim);
+ * count = 0 restores the built-in table, which the project's tuner
+ * (paper_1710_07946_amd/tune_batched.py, timing every variant per bin on this
+ * device) writes at build time.  LRA_EINVAL for a malformed rule,
+ * LRA_EUNSUPPORTED for a variant that is not compiled. */
+lra_status lra_batch_set_rules(const lra_batch_rule *rules, int32_t count);
+
+/* Copy up to `cap` rules of the current table to `out` (host); returns the
+ * number of rules in the table. */
+int32_t lra_batch_get_rules(lra_batch_rule *out, int32_t cap);
 
 /* Refinement of a CUR LRA by its leverage scores (section on refining an
  * LRA with leverage scores: the scores of a crude LRA stand in for those of
@@ -329,6 +359,38 @@ lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64
                         const int64_t *J, const double *U, int32_t q, int32_t s, uint64_t seed, int32_t prec,
                         double *moments, hipStream_t stream);
 
+/* Result of the a-posteriori test (device-resident). */
+typedef struct {
+    int64_t K;         /* entries in the sample, q s */
+    double mean;       /* (1/K) sum g_i over the sampled error entries g_i */
+    double mean_abs;   /* (1/K) sum |g_i| */
+    double var;        /* (1/K) sum (g_i - mean)^2 */
+    double threshold;  /* tau^2 ((K - 1) - z sqrt(2 (K - 1))) / K */
+    int32_t accept;    /* 1 when var <= threshold */
+    int32_t reserved;
+} lra_posterior;
+
+/* Superfast a-posteriori check of a CUR (Section 4, the subsection on LRA of a
+ * matrix filled with i.i.d. values of a single variable): the K = q s entries
+ * g_i of a random q x s submatrix of E = W - C U R (rows and columns drawn as
+ * by lra_residual, streams 3 and 4 of `seed`) are taken as observed values of
+ * one Gaussian variable, and the customary one-sided test for its variance
+ * decides whether the LRA meets the tolerance tau on the error entries' standard
+ * deviation: accept (reject sigma^2 >= tau^2) when K var <= tau^2 ((K - 1) -
+ * z sqrt(2 (K - 1))), the normal form of the chi-square test, with level
+ * Phi(-z) (z = 1.645: 5 %); in the paper's terms the variance may deviate from
+ * its observed value by the relative amount t = z sqrt(2 / (K - 1)).  mean,
+ * mean_abs (the printed average of |g_i|) and var are reported; var is formed
+ * from the sample's moments, sum e^2 / K - mean^2.
+ *   1 <= q, s <= 256, q s >= 2; tau > 0 and z finite (else LRA_EINVAL);
+ *   prec as lra_residual; I, J, U as lra_cur returns them; out device.
+ * Cost O((q + s) r^2 + q s r): only q r + r s + q s entries of W are read.
+ * Asynchronous on `stream`. */
+lra_status lra_posterior_test(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
+                              const int64_t *I, const int64_t *J, const double *U, int32_t q, int32_t s,
+                              uint64_t seed, int32_t prec, double tau, double z, lra_posterior *out,
+                              hipStream_t stream);
+
 /* Adjoint of the CUR reconstruction at fixed index sets, for `count` blocks
  * of equal shape (the paper has no adjoint; this is the derivative of
  * W' = C G^{-1} R with the generator G = W[I, J] as an independent input):
@@ -350,6 +412,14 @@ lra_status lra_cur_adjoint(int64_t count, int64_t m, int64_t n, int32_t r, const
                            const double *G, int64_t nnz, const int32_t *om_row, const int32_t *om_col,
                            const int32_t *col_order, const double *a_om, double *loss, double *dC, double *dR,
                            double *dG, int32_t *status, hipStream_t stream);
+
+/* Measurement helper (not part of the method): the one-way latency of an
+ * exchange between two workgroups on different XCDs through device-scope
+ * atomics, the accesses of the team selections, averaged over `rounds`
+ * (>= 2) hand-offs.  Synchronizes `stream`; *ns_out (host) receives the
+ * nanoseconds per hand-off.  LRA_EDEVICE if a hand-off did not arrive within
+ * 100 ms. */
+lra_status lra_probe_exchange(int32_t rounds, double *ns_out, hipStream_t stream);
 
 /* Free every cached workspace of the calling process. */
 void lra_release(void);

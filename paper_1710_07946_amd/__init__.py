@@ -53,6 +53,15 @@ class lra_pts_block(ct.Structure):
     _fields_ = [("x_off", ct.c_int64), ("y_off", ct.c_int64), ("m", ct.c_int64), ("n", ct.c_int64)]
 
 
+class lra_posterior(ct.Structure):
+    _fields_ = [("K", ct.c_int64), ("mean", ct.c_double), ("mean_abs", ct.c_double), ("var", ct.c_double),
+                ("threshold", ct.c_double), ("accept", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+class lra_batch_rule(ct.Structure):
+    _fields_ = [("max_dim", ct.c_int32), ("r", ct.c_int32), ("items_per_lane", ct.c_int32), ("waves", ct.c_int32)]
+
+
 INFO_BYTES = ct.sizeof(lra_info)
 _lib = None
 
@@ -86,6 +95,10 @@ def load() -> ct.CDLL:
         L.lra_cur_batched_points.argtypes = [P, i64, ct.POINTER(lra_pts_block), i64, i32, i32, ct.c_uint64,
                                              ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_batched_points.restype = ct.c_int
+        L.lra_batch_set_rules.argtypes = [ct.POINTER(lra_batch_rule), ct.c_int32]
+        L.lra_batch_set_rules.restype = ct.c_int
+        L.lra_batch_get_rules.argtypes = [ct.POINTER(lra_batch_rule), ct.c_int32]
+        L.lra_batch_get_rules.restype = ct.c_int32
         L.lra_cur_cynical.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, i32, i32, ct.c_uint64,
                                       ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_cynical.restype = ct.c_int
@@ -102,6 +115,11 @@ def load() -> ct.CDLL:
         L.lra_cur_hadamard.restype = ct.c_int
         L.lra_residual.argtypes = [P, ct.c_int, i64, i64, i64, i32, P, P, P, i32, i32, ct.c_uint64, i32, P, P]
         L.lra_residual.restype = ct.c_int
+        L.lra_posterior_test.argtypes = [P, ct.c_int, i64, i64, i64, i32, P, P, P, i32, i32, ct.c_uint64, i32,
+                                         ct.c_double, ct.c_double, P, P]
+        L.lra_posterior_test.restype = ct.c_int
+        L.lra_probe_exchange.argtypes = [i32, ct.POINTER(ct.c_double), P]
+        L.lra_probe_exchange.restype = ct.c_int
         L.lra_cur_adjoint.argtypes = [i64, i64, i64, i32, P, P, P, i64, P, P, P, P, P, P, P, P, P, P]
         L.lra_cur_adjoint.restype = ct.c_int
         _lib = L
@@ -128,6 +146,26 @@ def lra_strerror(status: int) -> str:
 
 def lra_release() -> None:
     load().lra_release()
+
+
+def lra_batch_set_rules(rules) -> None:
+    """Replace the batched launch's bin table: rules are (max_dim, r,
+    items_per_lane, waves) tuples; an empty list restores the built-in table."""
+    arr = (lra_batch_rule * max(1, len(rules)))()
+    for i, q in enumerate(rules):
+        arr[i] = lra_batch_rule(*(int(v) for v in q))
+    st = load().lra_batch_set_rules(arr, len(rules))
+    if st != LRA_OK:
+        raise LraError(st, "lra_batch_set_rules")
+
+
+def lra_batch_get_rules() -> list:
+    """The current bin table as (max_dim, r, items_per_lane, waves) tuples."""
+    L = load()
+    n = L.lra_batch_get_rules(None, 0)
+    arr = (lra_batch_rule * max(1, n))()
+    L.lra_batch_get_rules(arr, n)
+    return [(q.max_dim, q.r, q.items_per_lane, q.waves) for q in arr[:n]]
 
 
 def lra_default_opts() -> lra_opts:
@@ -514,6 +552,50 @@ def lra_residual(A, I, J, U, q: int = 0, s: int = 0, seed: int = 0, prec: int = 
     if st != LRA_OK:
         raise LraError(st, "lra_residual")
     return out
+
+
+def lra_posterior_test(A, I, J, U, q: int, s: int, seed: int, tau: float, z: float, prec: int = 0, out=None,
+                       stream=None):
+    """The a-posteriori variance test on a seeded q x s sample of the error of
+    the CUR (I, J, U); returns the device-resident lra_posterior record as a
+    uint8 tensor (decode with ``parse_posterior``)."""
+    torch = _torch()
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor with unit column stride")
+    m, n = A.shape
+    r = int(I.numel())
+    for t, dt in ((I, torch.int64), (J, torch.int64), (U, torch.float64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("I, J must be contiguous int64 and U contiguous float64 device tensors")
+    nbytes = ct.sizeof(lra_posterior)
+    if out is None:
+        out = torch.empty(nbytes, dtype=torch.uint8, device=A.device)
+    elif out.dtype != torch.uint8 or out.numel() != nbytes or not out.is_contiguous() or out.device != A.device:
+        raise ValueError("out must be a contiguous uint8 tensor of %d bytes on %s" % (nbytes, A.device))
+    st = load().lra_posterior_test(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r,
+                                   ct.c_void_p(I.data_ptr()), ct.c_void_p(J.data_ptr()), ct.c_void_p(U.data_ptr()),
+                                   q, s, ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), prec, ct.c_double(tau),
+                                   ct.c_double(z), ct.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    if st != LRA_OK:
+        raise LraError(st, "lra_posterior_test")
+    return out
+
+
+def lra_probe_exchange(rounds: int = 20000, stream=None) -> float:
+    """One-way latency (ns) of a hand-off between workgroups on different XCDs."""
+    ns = ct.c_double(0)
+    st = load().lra_probe_exchange(rounds, ct.byref(ns), _stream_ptr(stream))
+    if st != LRA_OK:
+        raise LraError(st, "lra_probe_exchange")
+    return ns.value
+
+
+def parse_posterior(raw) -> dict:
+    """Decode an lra_posterior record (uint8 tensor or array)."""
+    b = np.ascontiguousarray(raw.cpu().numpy() if hasattr(raw, "cpu") else raw, np.uint8)
+    p = lra_posterior.from_buffer_copy(b.tobytes())
+    return {"K": p.K, "mean": p.mean, "mean_abs": p.mean_abs, "var": p.var, "threshold": p.threshold,
+            "accept": bool(p.accept)}
 
 
 def omega_column_order(om_row, om_col):

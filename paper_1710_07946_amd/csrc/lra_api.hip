@@ -27,12 +27,15 @@ using lra::TeamWs;
 
 struct Workspace {
     int device = -1;
-    unsigned *counters = nullptr;   // [0] team barrier, [1] batch queue
+    unsigned *counters = nullptr;   // [1 ..] work queues of the batched launches
     uint64_t *xw = nullptr;         // team exchange words [2][kMaxTeam][kSlotWords]
     int64_t *init_cols = nullptr;   // [kRMax]
-    BlockDesc *blocks = nullptr;
-    int32_t *order = nullptr;
-    int64_t block_cap = 0;
+    unsigned char *desc = nullptr;  // batch descriptors, then the launch order (int32)
+    size_t desc_cap = 0;            // bytes
+    void *stage = nullptr;          // pinned host staging of the descriptors and the order
+    size_t stage_cap = 0;           // bytes
+    hipEvent_t stage_done = nullptr;  // the last copy out of `stage` has completed
+    std::vector<unsigned char> staged;  // bytes of the last staged copy (equal bytes: no copy)
     int32_t *bidiag = nullptr;      // bidiagonal-multiplier column table (kBdTableInts)
     double *sketch = nullptr;       // global sketch panels when they do not fit LDS
     size_t sketch_cap = 0;          // bytes
@@ -51,6 +54,40 @@ lra_status ws_work(Workspace *w, hipStream_t stream, size_t bytes, void **out) {
         w->work_cap = bytes;
     }
     *out = w->work;
+    return LRA_OK;
+}
+
+// Copy `bytes` of host descriptors to the workspace's device descriptor
+// buffer without blocking the host: the bytes go through a pinned staging
+// buffer, which is reused once the previous copy out of it has completed (an
+// event), and a call whose bytes equal the last staged ones copies nothing.
+lra_status stage_desc(Workspace *w, hipStream_t stream, const void *host, size_t bytes, unsigned char **dev_out) {
+    if (w->desc_cap < bytes) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(w->desc);
+        w->desc = nullptr;
+        w->desc_cap = 0;
+        w->staged.clear();
+        if (hipMalloc((void **)&w->desc, bytes) != hipSuccess) return LRA_ENOMEM;
+        w->desc_cap = bytes;
+    }
+    *dev_out = w->desc;
+    if (w->staged.size() == bytes && memcmp(w->staged.data(), host, bytes) == 0) return LRA_OK;
+    if (!w->stage_done && hipEventCreateWithFlags(&w->stage_done, hipEventDisableTiming) != hipSuccess)
+        return LRA_EDEVICE;
+    if (hipEventSynchronize(w->stage_done) != hipSuccess) return LRA_EDEVICE;
+    if (w->stage_cap < bytes) {
+        if (w->stage) (void)hipHostFree(w->stage);
+        w->stage = nullptr;
+        w->stage_cap = 0;
+        if (hipHostMalloc(&w->stage, bytes, hipHostMallocDefault) != hipSuccess) return LRA_ENOMEM;
+        w->stage_cap = bytes;
+    }
+    memcpy(w->stage, host, bytes);
+    w->staged.clear();
+    if (hipMemcpyAsync(w->desc, w->stage, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return LRA_EDEVICE;
+    if (hipEventRecord(w->stage_done, stream) != hipSuccess) return LRA_EDEVICE;
+    w->staged.assign(static_cast<const unsigned char *>(host), static_cast<const unsigned char *>(host) + bytes);
     return LRA_OK;
 }
 
@@ -258,6 +295,151 @@ lra_status query_dev(int dev, DevInfo *d) {
     return LRA_OK;
 }
 
+// ---- batched launches: size bins and their kernel variants
+constexpr int kSrcPoints = 3;  // source code of the point-set form (beside the dtype codes)
+constexpr int kMaxRules = 64;
+
+// Built-in bin table (rank 16, the far-field workload's rank): blocks whose
+// larger dimension is at most max_dim run on the register kernel with
+// items_per_lane x waves x 64 >= max_dim item slots per workgroup; anything
+// no rule covers runs on the LDS kernel.  A table measured by the tuner
+// (tune_batched.py) replaces it at build time.
+std::vector<lra_batch_rule> default_rules() {
+#if __has_include("lra_tuned_rules.inc")
+    static const lra_batch_rule tab[] = {
+#include "lra_tuned_rules.inc"
+    };
+#else
+    static const lra_batch_rule tab[] = {
+        {128, 16, 2, 1}, {256, 16, 2, 2}, {512, 16, 2, 4}, {1024, 16, 2, 8},
+    };
+#endif
+    std::vector<lra_batch_rule> v(tab, tab + sizeof(tab) / sizeof(tab[0]));
+    std::stable_sort(v.begin(), v.end(),
+                     [](const lra_batch_rule &a, const lra_batch_rule &b) { return a.max_dim < b.max_dim; });
+    return v;
+}
+
+std::vector<lra_batch_rule> g_rules;
+bool g_rules_set = false;
+
+const std::vector<lra_batch_rule> &current_rules() {
+    if (!g_rules_set) {
+        g_rules = default_rules();
+        g_rules_set = true;
+    }
+    return g_rules;
+}
+
+// Run a batch: bin the blocks by the rule table, stage the descriptors and the
+// launch order (bins one after another, each largest first by m + n), then
+// one persistent launch per bin on `stream`, the LDS bin and the bins of the
+// largest blocks first.  desc points at `count` 32-byte descriptors
+// (BlockDesc, or PtsDesc for src == kSrcPoints); dims holds (m, n) per block.
+lra_status batched_run(int src, const void *base, const void *desc, const int64_t *dims, int64_t count,
+                       CAConfig cfg, uint64_t seed, int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos,
+                       hipStream_t stream) {
+    const int r = cfg.r;
+    std::lock_guard<std::mutex> lk(g_mu);
+    const std::vector<lra_batch_rule> &rules = current_rules();
+    struct Bin {
+        int P, W;
+        int64_t cap;   // item slots per workgroup (0: LDS kernel)
+        std::vector<int32_t> ids;
+        int64_t maxdim = 0;
+    };
+    std::vector<Bin> bins;
+    auto bin_of = [&](int P, int W) -> Bin & {
+        for (Bin &b : bins)
+            if (b.P == P && b.W == W) return b;
+        bins.push_back(Bin{P, W, (int64_t)64 * P * W, {}, 0});
+        return bins.back();
+    };
+    for (int64_t b = 0; b < count; b++) {
+        const int64_t d = std::max(dims[2 * b], dims[2 * b + 1]);
+        int P = 0, W = 0;
+        for (const lra_batch_rule &q : rules)
+            if (q.r == r && d <= q.max_dim) {
+                P = q.items_per_lane;
+                W = q.waves;
+                break;
+            }
+        Bin &bn = bin_of(P, W);
+        bn.ids.push_back((int32_t)b);
+        bn.maxdim = std::max(bn.maxdim, d);
+    }
+    // the LDS kernel's bin first (it holds the blocks too large for any
+    // register variant), then by capacity, largest first
+    std::stable_sort(bins.begin(), bins.end(), [](const Bin &a, const Bin &b) {
+        if ((a.P == 0) != (b.P == 0)) return a.P == 0;
+        return a.cap > b.cap;
+    });
+    if (bins.size() > 60) return LRA_EUNSUPPORTED;
+    std::vector<unsigned char> host((size_t)count * 32 + (size_t)count * sizeof(int32_t));
+    memcpy(host.data(), desc, (size_t)count * 32);
+    int32_t *ord = reinterpret_cast<int32_t *>(host.data() + (size_t)count * 32);
+    std::vector<int64_t> first(bins.size());
+    int64_t at = 0;
+    for (size_t i = 0; i < bins.size(); i++) {
+        std::vector<int32_t> &ids = bins[i].ids;
+        // longest blocks first (cost ~ (m + n) r^2 per sweep): the tail of
+        // each persistent launch is then made of short blocks
+        std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+            return dims[2 * a] + dims[2 * a + 1] > dims[2 * b] + dims[2 * b + 1];
+        });
+        first[i] = at;
+        for (int32_t id : ids) ord[at++] = id;
+    }
+
+    Workspace *ws = nullptr;
+    lra_status st;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    size_t lds_dyn = 0;
+    for (const Bin &bn : bins) {
+        if (bn.P != 0) continue;
+        const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
+        const LdsPlan plan = plan_lds(bn.maxdim, bn.maxdim, r, LRA_PRE_NONE, 0, 1, lds_budget);
+        if (!plan.fits) return LRA_EUNSUPPORTED;
+        cfg.panel_bytes = (int32_t)plan.panel_bytes;
+        lds_dyn = plan.dyn_bytes;
+    }
+    unsigned char *ddesc = nullptr;
+    if ((st = stage_desc(ws, stream, host.data(), host.size(), &ddesc)) != LRA_OK) return st;
+    const int32_t *dord = reinterpret_cast<const int32_t *>(ddesc + (size_t)count * 32);
+    unsigned *queues = ws->counters + 1;
+    hipLaunchKernelGGL(lra::zero_u32_kernel, dim3(1), dim3(64), 0, stream, queues, (int)bins.size());
+    for (size_t i = 0; i < bins.size(); i++) {
+        const Bin &bn = bins[i];
+        const int64_t cnt = (int64_t)bn.ids.size();
+        hipError_t e;
+        if (bn.P == 0) {
+            int occ = src == kSrcPoints ? lra::points_occupancy(lds_dyn) : lra::batched_occupancy(src, lds_dyn);
+            if (occ < 1) occ = 1;
+            const int grid = (int)std::min<int64_t>((int64_t)dinfo.cus * occ, cnt);
+            if (src == kSrcPoints)
+                e = lra::launch_points(static_cast<const double *>(base), reinterpret_cast<const PtsDesc *>(ddesc),
+                                       dord + first[i], cnt, seed, cfg, queues + i, grid, lds_dyn, I_out, J_out, U_out,
+                                       infos, stream);
+            else
+                e = lra::launch_batched(src, base, reinterpret_cast<const BlockDesc *>(ddesc), dord + first[i], cnt,
+                                        seed, cfg, queues + i, grid, lds_dyn, I_out, J_out, U_out, infos, stream);
+        } else {
+            int occ = lra::reg_occupancy(r, bn.P, bn.W, src);
+            if (occ < 1) occ = 1;
+            const int grid = (int)std::min<int64_t>((int64_t)dinfo.cus * occ, cnt);
+            e = lra::launch_reg(src, r, bn.P, bn.W, base, ddesc, dord + first[i], cnt, seed, cfg, queues + i, grid,
+                                I_out, J_out, U_out, infos, stream);
+        }
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return LRA_EDEVICE;
+        }
+    }
+    return LRA_OK;
+}
+
 // Layout of the no-allocation scratch (byte offsets): the team exchange
 // words for the largest team, the bidiagonal column table, then the global
 // sketch panel, whose size bounds the shapes lra_cur_noalloc accepts.
@@ -338,6 +520,29 @@ const char *lra_strerror(lra_status s) {
     return "unknown status";
 }
 
+lra_status lra_probe_exchange(int32_t rounds, double *ns_out, hipStream_t stream) {
+    if (rounds < 2 || rounds > (1 << 24) || !ns_out) return LRA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    lra_status st;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    void *scr = nullptr;
+    if ((st = ws_work(ws, stream, 64, &scr)) != LRA_OK) return st;
+    uint64_t *buf = static_cast<uint64_t *>(scr);
+    uint64_t host[3] = {0, 0, 0};
+    if (lra::launch_xlat(buf, rounds, (uint64_t)dinfo.wall_khz * 100ull, stream) != hipSuccess ||
+        hipMemcpyAsync(host, buf, sizeof(host), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    if (host[2] || host[1] != (uint64_t)rounds) return LRA_EDEVICE;
+    *ns_out = (double)host[0] * 1e6 / (double)dinfo.wall_khz / (double)rounds;
+    return LRA_OK;
+}
+
 void lra_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
     int cur = 0;
@@ -349,8 +554,9 @@ void lra_release(void) {
         (void)hipFree(w.counters);
         (void)hipFree(w.xw);
         (void)hipFree(w.init_cols);
-        (void)hipFree(w.blocks);
-        (void)hipFree(w.order);
+        (void)hipFree(w.desc);
+        if (w.stage) (void)hipHostFree(w.stage);
+        if (w.stage_done) (void)hipEventDestroy(w.stage_done);
         (void)hipFree(w.sketch);
         (void)hipFree(w.bidiag);
         (void)hipFree(w.work);
@@ -616,27 +822,13 @@ lra_status lra_cur_uniform_batched(const void *base, lra_dtype dt, const lra_blo
     if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
     // the nucleus works on max(k, l) x min(k, l) and min(k, l)^2 doubles
     const size_t dyn = align16(sizeof(double) * (size_t)std::min(k, l) * (size_t)(k + l));
-    if (ws->block_cap < count) {
-        (void)hipStreamSynchronize(stream);
-        (void)hipFree(ws->blocks);
-        (void)hipFree(ws->order);
-        ws->blocks = nullptr;
-        ws->order = nullptr;
-        ws->block_cap = 0;
-        if (hipMalloc(&ws->blocks, sizeof(BlockDesc) * count) != hipSuccess) return LRA_ENOMEM;
-        if (hipMalloc(&ws->order, sizeof(int32_t) * count) != hipSuccess) return LRA_ENOMEM;
-        ws->block_cap = count;
-    }
-    if (hipMemcpyAsync(ws->blocks, desc.data(), sizeof(BlockDesc) * count, hipMemcpyHostToDevice, stream) !=
-        hipSuccess)
-        return LRA_EDEVICE;
-    // the host vector must outlive the copy
-    (void)hipStreamSynchronize(stream);
+    unsigned char *ddesc = nullptr;
+    if ((st = stage_desc(ws, stream, desc.data(), sizeof(BlockDesc) * count, &ddesc)) != LRA_OK) return st;
     int occ = lra::uniform_occupancy(dt, dyn);
     if (occ < 1) occ = 1;
     const int64_t grid = std::min<int64_t>((int64_t)dinfo.cus * occ, count);
-    hipError_t e = lra::launch_uniform(dt, base, ws->blocks, count, seed, r, k, l, (int)grid, dyn, I_out, J_out,
-                                       U_out, infos, stream);
+    hipError_t e = lra::launch_uniform(dt, base, reinterpret_cast<const BlockDesc *>(ddesc), count, seed, r, k, l,
+                                       (int)grid, dyn, I_out, J_out, U_out, infos, stream);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;
@@ -694,61 +886,16 @@ lra_status lra_cur_batched(const void *base, lra_dtype dt, const lra_block *bloc
     if (st != LRA_OK) return st;
     if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
     if (count == 0) return LRA_OK;
-    int64_t maxdim = 0;
     std::vector<BlockDesc> desc((size_t)count);
+    std::vector<int64_t> dims((size_t)2 * count);
     for (int64_t b = 0; b < count; b++) {
         const lra_block &k = blocks[b];
         if (k.offset < 0 || k.m < 1 || k.n < 1 || k.lda < k.n || r > k.m || r > k.n) return LRA_EINVAL;
         desc[b] = BlockDesc{k.offset, k.m, k.n, k.lda};
-        maxdim = std::max(maxdim, std::max(k.m, k.n));
+        dims[2 * b] = k.m;
+        dims[2 * b + 1] = k.n;
     }
-    // longest blocks first (cost ~ (m + n) r^2 per sweep): the tail of the
-    // persistent launch is then made of short blocks
-    std::vector<int32_t> order((size_t)count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return desc[a].m + desc[a].n > desc[b].m + desc[b].n;
-    });
-
-    std::lock_guard<std::mutex> lk(g_mu);
-    Workspace *ws = nullptr;
-    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
-    DevInfo dinfo;
-    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
-    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
-    const LdsPlan plan = plan_lds(maxdim, maxdim, r, LRA_PRE_NONE, 0, 1, lds_budget);
-    if (!plan.fits) return LRA_EUNSUPPORTED;
-    cfg.panel_bytes = (int32_t)plan.panel_bytes;
-    const size_t dyn = plan.dyn_bytes;
-
-    if (ws->block_cap < count) {
-        (void)hipStreamSynchronize(stream);
-        (void)hipFree(ws->blocks);
-        (void)hipFree(ws->order);
-        ws->blocks = nullptr;
-        ws->order = nullptr;
-        ws->block_cap = 0;
-        if (hipMalloc(&ws->blocks, sizeof(BlockDesc) * count) != hipSuccess) return LRA_ENOMEM;
-        if (hipMalloc(&ws->order, sizeof(int32_t) * count) != hipSuccess) return LRA_ENOMEM;
-        ws->block_cap = count;
-    }
-    if (hipMemcpyAsync(ws->blocks, desc.data(), sizeof(BlockDesc) * count, hipMemcpyHostToDevice, stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(ws->order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream) != hipSuccess)
-        return LRA_EDEVICE;
-    // the host vectors must outlive the copies
-    (void)hipStreamSynchronize(stream);
-
-    int occ = lra::batched_occupancy(dt, dyn);
-    if (occ < 1) occ = 1;
-    const int64_t grid = std::min<int64_t>((int64_t)dinfo.cus * occ, count);
-    hipError_t e = lra::launch_batched(dt, base, ws->blocks, ws->order, count, seed, cfg, ws->counters + 1, (int)grid,
-                                       dyn, I_out, J_out, U_out, infos, stream);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return LRA_EDEVICE;
-    }
-    return LRA_OK;
+    return batched_run((int)dt, base, desc.data(), dims.data(), count, cfg, seed, I_out, J_out, U_out, infos, stream);
 }
 
 lra_status lra_cur_batched_points(const double *pts, int64_t npts, const lra_pts_block *blocks, int64_t count,
@@ -763,60 +910,51 @@ lra_status lra_cur_batched_points(const double *pts, int64_t npts, const lra_pts
     if (st != LRA_OK) return st;
     if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
     if (count == 0) return LRA_OK;
-    int64_t maxdim = 0;
     std::vector<PtsDesc> desc((size_t)count);
+    std::vector<int64_t> dims((size_t)2 * count);
     for (int64_t b = 0; b < count; b++) {
         const lra_pts_block &k = blocks[b];
         if (k.x_off < 0 || k.y_off < 0 || k.m < 1 || k.n < 1 || r > k.m || r > k.n) return LRA_EINVAL;
         if (k.m > npts - k.x_off || k.n > npts - k.y_off) return LRA_EINVAL;
         desc[b] = PtsDesc{k.x_off, k.y_off, k.m, k.n};
-        maxdim = std::max(maxdim, std::max(k.m, k.n));
+        dims[2 * b] = k.m;
+        dims[2 * b + 1] = k.n;
     }
-    std::vector<int32_t> order((size_t)count);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return desc[a].m + desc[a].n > desc[b].m + desc[b].n;
-    });
+    return batched_run(kSrcPoints, pts, desc.data(), dims.data(), count, cfg, seed, I_out, J_out, U_out, infos,
+                       stream);
+}
 
+lra_status lra_batch_set_rules(const lra_batch_rule *rules, int32_t count) {
+    if (count < 0 || count > kMaxRules || (count > 0 && !rules)) return LRA_EINVAL;
+    std::vector<lra_batch_rule> v;
+    if (count == 0) {
+        v = default_rules();
+    } else {
+        for (int32_t i = 0; i < count; i++) {
+            const lra_batch_rule &q = rules[i];
+            if (q.max_dim < 1 || q.r < 1 || q.r > kRMax || q.waves < 0 || q.items_per_lane < 0) return LRA_EINVAL;
+            if (q.items_per_lane > 0) {
+                if (!lra::reg_variant_exists(q.r, q.items_per_lane)) return LRA_EUNSUPPORTED;
+                if (q.waves < 1 || q.waves > 8 || (int64_t)64 * q.items_per_lane * q.waves < q.max_dim)
+                    return LRA_EINVAL;
+            }
+            v.push_back(q);
+        }
+        std::stable_sort(v.begin(), v.end(),
+                         [](const lra_batch_rule &a, const lra_batch_rule &b) { return a.max_dim < b.max_dim; });
+    }
     std::lock_guard<std::mutex> lk(g_mu);
-    Workspace *ws = nullptr;
-    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
-    DevInfo dinfo;
-    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
-    const size_t lds_budget = (size_t)dinfo.lds - lra::static_lds_bytes() - 256;
-    const LdsPlan plan = plan_lds(maxdim, maxdim, r, LRA_PRE_NONE, 0, 1, lds_budget);
-    if (!plan.fits) return LRA_EUNSUPPORTED;
-    cfg.panel_bytes = (int32_t)plan.panel_bytes;
-    const size_t dyn = plan.dyn_bytes;
-
-    if (ws->block_cap < count) {
-        (void)hipStreamSynchronize(stream);
-        (void)hipFree(ws->blocks);
-        (void)hipFree(ws->order);
-        ws->blocks = nullptr;
-        ws->order = nullptr;
-        ws->block_cap = 0;
-        if (hipMalloc(&ws->blocks, sizeof(BlockDesc) * count) != hipSuccess) return LRA_ENOMEM;
-        if (hipMalloc(&ws->order, sizeof(int32_t) * count) != hipSuccess) return LRA_ENOMEM;
-        ws->block_cap = count;
-    }
-    PtsDesc *dblocks = reinterpret_cast<PtsDesc *>(ws->blocks);
-    if (hipMemcpyAsync(dblocks, desc.data(), sizeof(PtsDesc) * count, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(ws->order, order.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, stream) != hipSuccess)
-        return LRA_EDEVICE;
-    // the host vectors must outlive the copies
-    (void)hipStreamSynchronize(stream);
-
-    int occ = lra::points_occupancy(dyn);
-    if (occ < 1) occ = 1;
-    const int64_t grid = std::min<int64_t>((int64_t)dinfo.cus * occ, count);
-    hipError_t e = lra::launch_points(pts, dblocks, ws->order, count, seed, cfg, ws->counters + 1, (int)grid, dyn,
-                                      I_out, J_out, U_out, infos, stream);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return LRA_EDEVICE;
-    }
+    g_rules = v;
+    g_rules_set = true;
     return LRA_OK;
+}
+
+int32_t lra_batch_get_rules(lra_batch_rule *out, int32_t cap) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const std::vector<lra_batch_rule> &v = current_rules();
+    const int32_t n = (int32_t)v.size();
+    for (int32_t i = 0; i < n && i < cap && out; i++) out[i] = v[i];
+    return n;
 }
 
 lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r, const int64_t *I,
@@ -838,6 +976,33 @@ lra_status lra_residual(const void *W, lra_dtype dt, int64_t m, int64_t n, int64
         return st;
     if (lra::launch_residual(dt, W, m, n, lda, r, I, J, U, q, s, seed, prec, moments, scr, stream) !=
         hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
+lra_status lra_posterior_test(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
+                              const int64_t *I, const int64_t *J, const double *U, int32_t q, int32_t s,
+                              uint64_t seed, int32_t prec, double tau, double z, lra_posterior *out,
+                              hipStream_t stream) {
+    if (!W || !I || !J || !U || !out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (prec != LRA_PREC_PLAIN && prec != LRA_PREC_MIXED) return LRA_EINVAL;
+    if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n) return LRA_EINVAL;
+    if (q < 1 || s < 1 || q > 256 || s > 256 || q > m || s > n || (int64_t)q * s < 2) return LRA_EINVAL;
+    if (!(tau > 0.0) || !std::isfinite(tau) || !std::isfinite(z)) return LRA_EINVAL;
+    if (m >= ((int64_t)1 << 39) || n >= ((int64_t)1 << 39)) return LRA_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    lra_status st;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    const size_t bytes = (lra::residual_scratch_bytes(m, n, r, q, s, prec) + 255) & ~size_t(255);
+    void *scr = nullptr;
+    if ((st = ws_work(ws, stream, bytes + 4 * sizeof(double), &scr)) != LRA_OK) return st;
+    double *mom = reinterpret_cast<double *>(static_cast<char *>(scr) + bytes);
+    if (lra::launch_residual(dt, W, m, n, lda, r, I, J, U, q, s, seed, prec, mom, scr, stream) != hipSuccess ||
+        lra::launch_posterior(mom, (int64_t)q * s, tau, z, out, stream) != hipSuccess) {
         (void)hipGetLastError();
         return LRA_EDEVICE;
     }

@@ -24,6 +24,7 @@
 
 #include <algorithm>
 
+#include "lra_common.h"
 #include "lra_device.h"
 #include "lra_internal.h"
 
@@ -61,98 +62,6 @@ __device__ uint64_t g_sel_done[kSelTrace * 256];
 #else
 #define LRA_TR(ev, val) ((void)0)
 #endif
-
-// ---------------------------------------------------------------- argmax
-// Candidates are ordered by value, then lowest item, then lowest slot: the
-// tie rule of the oracle's sequential scans.
-struct Best {
-    double v;      // |value| compared; -1 when there is no candidate
-    int64_t item;  // global item id (row or column of W)
-    int32_t slot;  // basis slot (swap search) or 0
-    int32_t aux;   // owner workgroup (team reduction only)
-};
-
-// (bitwise on the comparisons: no branches in the wavefront reductions)
-__device__ __forceinline__ bool better(double v1, int64_t i1, int s1, double v2, int64_t i2, int s2) {
-    return (v1 > v2) | ((v1 == v2) & ((i1 < i2) | ((i1 == i2) & (s1 < s2))));
-}
-
-__device__ __forceinline__ Best none() { return Best{-1.0, INT64_MAX, 0x7fffffff, -1}; }
-
-__device__ __forceinline__ void consider(Best &b, double v, int64_t item, int slot, int aux = -1) {
-    if (better(v, item, slot, b.v, b.item, b.slot)) b = Best{v, item, slot, aux};
-}
-
-// Wavefront argmax without LDS traffic: four DPP butterflies (quad swaps,
-// half-row and row mirrors) leave every lane of a 16-lane row with the row's
-// best, then two row broadcasts (row 0 into row 1 and row 2 into row 3, then
-// row 1 into rows 2 and 3) leave the wavefront's best in lane 63.  Lanes a
-// step does not write keep their own value.  The order is total, so the
-// result does not depend on the tree's shape.  All 64 lanes must be active.
-template <int CTRL, int RM = 0xf>
-__device__ __forceinline__ int dpp32(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, RM, 0xf, false);
-}
-template <int CTRL, int RM = 0xf>
-__device__ __forceinline__ int64_t dpp64(int64_t v) {
-    const int lo = dpp32<CTRL, RM>((int)(uint32_t)v), hi = dpp32<CTRL, RM>((int)(uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-__device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
-    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-template <int CTRL, int RM = 0xf>
-__device__ __forceinline__ void dpp_step(Best &b) {
-    const double ov = __longlong_as_double(dpp64<CTRL, RM>(__double_as_longlong(b.v)));
-    const int64_t oi = dpp64<CTRL, RM>(b.item);
-    const int os = dpp32<CTRL, RM>(b.slot), oa = dpp32<CTRL, RM>(b.aux);
-    const bool up = better(ov, oi, os, b.v, b.item, b.slot);
-    b.v = up ? ov : b.v;
-    b.item = up ? oi : b.item;
-    b.slot = up ? os : b.slot;
-    b.aux = up ? oa : b.aux;
-}
-__device__ __forceinline__ Best rdl_best(const Best &b, int lane) {
-    return Best{__longlong_as_double(rdl64(__double_as_longlong(b.v), lane)), rdl64(b.item, lane),
-                __builtin_amdgcn_readlane(b.slot, lane), __builtin_amdgcn_readlane(b.aux, lane)};
-}
-constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
-constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
-constexpr int kDppHalfMirror = 0x141;
-constexpr int kDppMirror = 0x140;
-constexpr int kDppRowBcast15 = 0x142;  // lane 15 of a row to the whole next row
-constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
-
-__device__ __forceinline__ Best wave_reduce(Best b) {
-    dpp_step<kDppQuadSwap1>(b);
-    dpp_step<kDppQuadSwap2>(b);
-    dpp_step<kDppHalfMirror>(b);
-    dpp_step<kDppMirror>(b);
-    dpp_step<kDppRowBcast15, 0xa>(b);
-    dpp_step<kDppRowBcast31, 0xc>(b);
-    return rdl_best(b, 63);
-}
-
-// The same over lanes 0..7 only (the other lanes' values are ignored): the
-// two quad swaps and the half-row mirror combine the first eight lanes.
-__device__ __forceinline__ Best reduce8(Best b) {
-    dpp_step<kDppQuadSwap1>(b);
-    dpp_step<kDppQuadSwap2>(b);
-    dpp_step<kDppHalfMirror>(b);
-    return rdl_best(b, 0);
-}
-
-__device__ __forceinline__ int wave_or(int f) {
-    f |= dpp32<kDppQuadSwap1>(f);
-    f |= dpp32<kDppQuadSwap2>(f);
-    f |= dpp32<kDppHalfMirror>(f);
-    f |= dpp32<kDppMirror>(f);
-    f |= dpp32<kDppRowBcast15, 0xa>(f);
-    f |= dpp32<kDppRowBcast31, 0xc>(f);
-    return __builtin_amdgcn_readlane(f, 63);
-}
 
 // ---------------------------------------------------------------- LDS state
 struct Smem {
@@ -636,22 +545,6 @@ __device__ __forceinline__ void axpy_slots(double *panel, const double *w, int o
     if (n & 1) axpy_chunk<1>(panel, w, o, pstep, j, sub, f);
 }
 
-// Sort r <= 64 distinct indices in LDS ascending: every lane of one wave
-// takes one entry, counts the entries below it with shuffles and stores it at
-// its rank.
-__device__ __forceinline__ void sort_set_wave(int64_t *a, int r) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t x = lane < r ? a[lane] : INT64_MAX;
-    int rank = 0;
-    for (int j = 0; j < r; j++) {
-        const int64_t y = __shfl(x, j);
-        rank += (y < x) || (y == x && j < lane);
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (lane < r) a[rank] = x;
-    __builtin_amdgcn_wave_barrier();
-}
-
 __device__ __forceinline__ void fail_status(Smem &sm, int st, int rank) {
     if (threadIdx.x == 0) {
         sm.status = st;
@@ -699,6 +592,7 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
     const LaneMap ld = lane_map(g.cnt, r, 1, kNWave - 1);  // overlap lanes (waves 1..)
     const int subd = ld.sub, sd = ld.s, grpd = ld.grp, ngrpd = ld.ngrp;
     double pk = 1.0;
+    int fix_li = -1;  // the workgroup's best item of the last selection, if another item won
     for (int k = 0; k < r; k++) {
 #ifdef LRA_TRACE
         const uint64_t q0 = wall_clock64();
@@ -709,6 +603,15 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             if (k > 0) {
                 const double l = panel[(k - 1) * st + li] / pk;
                 if (ahead) {
+                    if (li == fix_li) {
+                        // its columns from k on still lack elimination k-2
+                        // (the look-ahead published it with the elimination
+                        // applied on the fly): apply it before elimination k-1
+                        const int jf = (k <= s) ? s : s + ((k - s + sub - 1) / sub) * sub;
+                        if (jf <= jlast)
+                            axpy_slots(panel, sm.wprev[k & 1], jf * st + li, pstep, jf, sub, (jlast - jf) / sub + 1,
+                                       panel[(k - 2) * st + li]);
+                    }
                     if (k % sub == s) {
                         const double x = panel[k * st + li] - l * sm.wrow[k];
                         panel[k * st + li] = x;
@@ -761,22 +664,17 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             if (lw % ngrp == grp && s == 0) flags[lw] = (uint8_t)(k + 1);
         }
         // the workgroup's best item, if it did not win, takes elimination k-1
-        // on its columns past k (one thread per column), before the next scan
+        // on its columns past k in the next scan (its owner lanes, before they
+        // apply elimination k), so no barrier is needed here
         const int64_t lb = sm.loc_item;
-        if (ahead && k > 0 && lb != wit && lb >= g.base && lb < g.base + g.cnt && tid < r - 1 - k) {
-            const int li = (int)(lb - g.base);
-            const int j = k + 1 + tid;
-            panel[j * st + li] -= panel[(k - 1) * st + li] * wp[j];
-        }
+        fix_li = (ahead && k > 0 && lb != wit && lb >= g.base && lb < g.base + g.cnt) ? (int)(lb - g.base) : -1;
         pk = sm.wrow[k];
-        if (ahead) {
-            // the look-ahead keeps the pivot row for the next overlap, and the
-            // fix-up above must land before the next scan reads column k+1
-            if (tid < r) sm.wprev[k & 1][tid] = sm.wrow[tid];
-            __syncthreads();
-        }
-        // (eager: the next scan touches only entries its own lanes own, and
-        // the next selection's first barrier orders everything shared)
+        // the look-ahead keeps the pivot row for the next overlap and fix-up;
+        // their readers run after the next selection's first barrier, or read
+        // the other buffer.  (Eager: the next scan touches only entries its
+        // own lanes own, and the next selection's first barrier orders
+        // everything shared.)
+        if (ahead && tid < r) sm.wprev[k & 1][tid] = sm.wrow[tid];
 #ifdef LRA_TRACE
         if (tid == 0) sm.t_loop[1] += wall_clock64() - q2;
 #endif
@@ -789,22 +687,39 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
         if (!flags[li] && (r - 1) % sub == s) panel[(r - 1) * st + li] /= pk;
     if (tid < r - 1) sm.L11[(r - 1) * (r - 2) / 2 + tid] = sm.wrow[tid];
     __syncthreads();
-    // ---- B = L21 L11^{-1}: the sub lanes of an item solve x L11 = l_i by
-    // column-oriented back substitution (for k = r-1 .. 1, x_k is final and
-    // every x_j, j < k, takes x_j - x_k L11[k][j]); basis items get unit rows.
-    // The lanes of an item sit in one wavefront, whose LDS accesses complete
-    // in program order, so step k reads the x_k its owner finished at step
-    // k+1.
-    for (int li = grp; li < g.cnt; li += ngrp) {
+    // ---- B = L21 L11^{-1}: each item solves x L11 = l_i by column-oriented
+    // back substitution (for k = r-1 .. 1, x_k is final and every x_j, j < k,
+    // takes x_j - x_k L11[k][j]); basis items get unit rows.  One thread per
+    // item, slots in register blocks of 8 from the top: a block first takes
+    // the terms of the finished slots above it, then its own, so every x_j
+    // still receives its terms in decreasing k.
+    for (int li = tid; li < g.cnt; li += kBlock) {
         const int fl = flags[li];
         if (fl) {
-            for (int j = s; j < r; j += sub) panel[j * st + li] = (j == fl - 1) ? 1.0 : 0.0;
+            for (int j = 0; j < r; j++) panel[j * st + li] = (j == fl - 1) ? 1.0 : 0.0;
             continue;
         }
-        for (int k = r - 1; k >= 1; k--) {
-            __builtin_amdgcn_wave_barrier();
-            const double xk = panel[k * st + li];
-            if (s < k) axpy_slots(panel, sm.L11 + k * (k - 1) / 2, s * st + li, pstep, s, sub, (k - 1 - s) / sub + 1, xk);
+        for (int j0 = ((r - 1) / 8) * 8; j0 >= 0; j0 -= 8) {
+            const int nb = min(8, r - j0);
+            double xr[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) xr[u] = u < nb ? panel[(j0 + u) * st + li] : 0.0;
+            for (int k = r - 1; k >= j0 + 8; k--) {
+                const double xk = panel[k * st + li];
+                const double *Lk = sm.L11 + k * (k - 1) / 2 + j0;
+#pragma unroll
+                for (int u = 0; u < 8; u++) xr[u] -= xk * Lk[u];
+            }
+#pragma unroll
+            for (int q = 7; q >= 1; q--) {
+                if (q >= nb) continue;
+                const double *Lq = sm.L11 + (j0 + q) * (j0 + q - 1) / 2 + j0;
+#pragma unroll
+                for (int u = 0; u < q; u++) xr[u] -= xr[q] * Lq[u];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (u < nb) panel[(j0 + u) * st + li] = xr[u];
         }
     }
     __syncthreads();
@@ -876,26 +791,6 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
 }
 
 // ---------------------------------------------------------------- entry sources
-// Where the entries W[i][j] of one matrix come from: a dense row-major array
-// (FP64, FP32 or BF16 as stored, converted to FP64), or, for far-field
-// interaction blocks, evaluated on the fly from the two point sets as
-// K_ij = 1 / |x_i - y_j| in FP64 (dx dx + dy dy, then a correctly rounded
-// square root and division), so that no entry is ever stored.
-template <typename T>
-struct DenseSrc {
-    const T *A;
-    int64_t lda;
-    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const { return Elem<T>::load(A, i * lda + j); }
-};
-struct PointSrc {
-    const double *x;  // row points, (x0, x1) pairs
-    const double *y;  // column points
-    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const {
-        const double dx = x[2 * i] - y[2 * j], dy = x[2 * i + 1] - y[2 * j + 1];
-        return 1.0 / sqrt(dx * dx + dy * dy);
-    }
-};
-
 // The sketch W[K, L] of a dense matrix (cynical CUR): entry (i, j) is
 // W[K[i]][L[j]].
 template <typename T>
@@ -1388,79 +1283,6 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
 #endif
 }
 
-// Nucleus U = G^{-1}, G = W[I, J] (I, J sorted), by LU with partial pivoting
-// (ties to the lowest row) and r column solves, then `refine` steps of
-// X <- X + X (I - G X) (Algorithm algcnnncl with k = l = r).  One workgroup;
-// `ws` holds 4 r^2 doubles.  Writes U (row-major, J-order x I-order).
-template <class Src>
-__device__ __forceinline__ void nucleus(Smem &sm, double *ws, const Src &src, int r, int refine, double *U_out) {
-    const int tid = threadIdx.x;
-    double *G = ws, *LU = ws + r * r, *X = ws + 2 * r * r, *X2 = ws + 3 * r * r;
-    __shared__ int p[kRMax];
-    for (int e = tid; e < r * r; e += kBlock) {
-        const int a = e / r, b = e % r;
-        const double v = src(sm.Iset[a], sm.Jset[b]);
-        G[e] = v;
-        LU[e] = v;
-    }
-    __syncthreads();
-    LRA_TR(22, 0);
-    __shared__ int sing;
-    __shared__ double ld;
-    inverse_lds(LU, X, p, r, kBlock, &sing, &ld);
-    LRA_TR(23, 0);
-    // an exactly zero pivot, or pivot magnitudes spread by more than 1e14 (a
-    // condition estimate from the same factors): truncated pseudo-inverse
-    __shared__ int fallback;
-    if (tid == 0) {
-        int fb = sing;
-        if (!sing) {
-            double pmax = 0.0, pmin = INFINITY;
-            for (int k = 0; k < r; k++) {
-                const double a = fabs(LU[p[k] * r + k]);
-                pmax = a > pmax ? a : pmax;
-                pmin = a < pmin ? a : pmin;
-            }
-            fb = pmax > 1e14 * pmin;
-        }
-        fallback = fb;
-    }
-    __syncthreads();
-    if (fallback) {
-        __shared__ int rank;
-        pinv_jacobi_lds(G, LU, X2, X, r, 1e-14, kBlock, &rank);
-        if (tid == 0) {
-            sm.nucleus_rank = rank;
-            sm.logdet = (rank == r && !sing) ? ld : -INFINITY;
-        }
-        for (int e = tid; e < r * r; e += kBlock) U_out[e] = X[e];
-        return;
-    }
-    if (tid == 0) sm.logdet = ld;
-    for (int it = 0; it < refine; it++) {
-        double *Tm = LU;  // T = I - G X
-        for (int e = tid; e < r * r; e += kBlock) {
-            const int i = e / r, j = e % r;
-            double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll 4
-            for (int q = 0; q < r; q++) s -= G[i * r + q] * X[q * r + j];
-            Tm[e] = s;
-        }
-        __syncthreads();
-        for (int e = tid; e < r * r; e += kBlock) {
-            const int i = e / r, j = e % r;
-            double s = X[e];
-#pragma unroll 4
-            for (int q = 0; q < r; q++) s += X[i * r + q] * Tm[q * r + j];
-            X2[e] = s;
-        }
-        __syncthreads();
-        for (int e = tid; e < r * r; e += kBlock) X[e] = X2[e];
-        __syncthreads();
-    }
-    for (int e = tid; e < r * r; e += kBlock) U_out[e] = X[e];
-}
-
 // ---------------------------------------------------------------- r-projective volume
 // One orthogonaliser pass over every item of the slice: z <- z - f (w . z) w,
 // f = f0 (w . z), w = sm.wrow[0 .. r-1] (the picked item's z), the dot
@@ -1860,7 +1682,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     LRA_TR(38, sm.t_loop[3]);
     LRA_TR(39, sm.t_loop[4]);
 #endif
-    if (tm.rank == 0) nucleus(sm, dyn, src, r, cfg.refine_steps, U_out);
+    if (tm.rank == 0) nucleus(sm, dyn, src, r, cfg.refine_steps, kBlock, U_out);
     LRA_TR(21, 0);
 finish:
     __syncthreads();

@@ -1,0 +1,242 @@
+// lra_common.h -- pieces shared by the C-A kernels: the wavefront argmax with
+// the oracle's tie rule, set sorting, the entry sources through which the
+// kernels read W, and the r x r nucleus.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lra_device.h"
+#include "lra_internal.h"
+
+namespace lra {
+
+// ---------------------------------------------------------------- argmax
+// Candidates are ordered by value, then lowest item, then lowest slot: the
+// tie rule of the oracle's sequential scans.
+struct Best {
+    double v;      // |value| compared; -1 when there is no candidate
+    int64_t item;  // global item id (row or column of W)
+    int32_t slot;  // basis slot (swap search) or 0
+    int32_t aux;   // owner workgroup (team reduction only)
+};
+
+// (bitwise on the comparisons: no branches in the wavefront reductions)
+__device__ __forceinline__ bool better(double v1, int64_t i1, int s1, double v2, int64_t i2, int s2) {
+    return (v1 > v2) | ((v1 == v2) & ((i1 < i2) | ((i1 == i2) & (s1 < s2))));
+}
+
+__device__ __forceinline__ Best none() { return Best{-1.0, INT64_MAX, 0x7fffffff, -1}; }
+
+__device__ __forceinline__ void consider(Best &b, double v, int64_t item, int slot, int aux = -1) {
+    if (better(v, item, slot, b.v, b.item, b.slot)) b = Best{v, item, slot, aux};
+}
+
+// Wavefront argmax without LDS traffic: four DPP butterflies (quad swaps,
+// half-row and row mirrors) leave every lane of a 16-lane row with the row's
+// best, then two row broadcasts (row 0 into row 1 and row 2 into row 3, then
+// row 1 into rows 2 and 3) leave the wavefront's best in lane 63.  Lanes a
+// step does not write keep their own value.  The order is total, so the
+// result does not depend on the tree's shape.  All 64 lanes must be active.
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ int dpp32(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, RM, 0xf, false);
+}
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ int64_t dpp64(int64_t v) {
+    const int lo = dpp32<CTRL, RM>((int)(uint32_t)v), hi = dpp32<CTRL, RM>((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int64_t rdl64(int64_t v, int lane) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ void dpp_step(Best &b) {
+    const double ov = __longlong_as_double(dpp64<CTRL, RM>(__double_as_longlong(b.v)));
+    const int64_t oi = dpp64<CTRL, RM>(b.item);
+    const int os = dpp32<CTRL, RM>(b.slot), oa = dpp32<CTRL, RM>(b.aux);
+    const bool up = better(ov, oi, os, b.v, b.item, b.slot);
+    b.v = up ? ov : b.v;
+    b.item = up ? oi : b.item;
+    b.slot = up ? os : b.slot;
+    b.aux = up ? oa : b.aux;
+}
+__device__ __forceinline__ Best rdl_best(const Best &b, int lane) {
+    return Best{__longlong_as_double(rdl64(__double_as_longlong(b.v), lane)), rdl64(b.item, lane),
+                __builtin_amdgcn_readlane(b.slot, lane), __builtin_amdgcn_readlane(b.aux, lane)};
+}
+constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+constexpr int kDppRowBcast15 = 0x142;  // lane 15 of a row to the whole next row
+constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
+
+__device__ __forceinline__ Best wave_reduce_full(Best b) {
+    dpp_step<kDppQuadSwap1>(b);
+    dpp_step<kDppQuadSwap2>(b);
+    dpp_step<kDppHalfMirror>(b);
+    dpp_step<kDppMirror>(b);
+    dpp_step<kDppRowBcast15, 0xa>(b);
+    dpp_step<kDppRowBcast31, 0xc>(b);
+    return rdl_best(b, 63);
+}
+
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ double dpp_max(double v) {
+    return fmax(v, __longlong_as_double(dpp64<CTRL, RM>(__double_as_longlong(v))));
+}
+
+// The same result, cheaper in the usual case: the largest value alone goes
+// through the butterflies (candidate values are finite, or -1 for none); if
+// exactly one lane holds it, that lane's candidate wins, and ties go through
+// the full (value, item, slot) reduction.
+__device__ __forceinline__ Best wave_reduce(Best b) {
+    double m = dpp_max<kDppQuadSwap1>(b.v);
+    m = dpp_max<kDppQuadSwap2>(m);
+    m = dpp_max<kDppHalfMirror>(m);
+    m = dpp_max<kDppMirror>(m);
+    m = dpp_max<kDppRowBcast15, 0xa>(m);
+    m = dpp_max<kDppRowBcast31, 0xc>(m);
+    const double top = __longlong_as_double(rdl64(__double_as_longlong(m), 63));
+    const unsigned long long hold = __ballot(b.v == top);
+    if (__popcll(hold) == 1) return rdl_best(b, __ffsll((long long)hold) - 1);
+    return wave_reduce_full(b);
+}
+
+// The same over lanes 0..7 only (the other lanes' values are ignored): the
+// two quad swaps and the half-row mirror combine the first eight lanes.
+__device__ __forceinline__ Best reduce8(Best b) {
+    dpp_step<kDppQuadSwap1>(b);
+    dpp_step<kDppQuadSwap2>(b);
+    dpp_step<kDppHalfMirror>(b);
+    return rdl_best(b, 0);
+}
+
+__device__ __forceinline__ int wave_or(int f) {
+    f |= dpp32<kDppQuadSwap1>(f);
+    f |= dpp32<kDppQuadSwap2>(f);
+    f |= dpp32<kDppHalfMirror>(f);
+    f |= dpp32<kDppMirror>(f);
+    f |= dpp32<kDppRowBcast15, 0xa>(f);
+    f |= dpp32<kDppRowBcast31, 0xc>(f);
+    return __builtin_amdgcn_readlane(f, 63);
+}
+
+// Sort r <= 64 distinct indices in LDS ascending: every lane of one wave
+// takes one entry, counts the entries below it with shuffles and stores it at
+// its rank.
+__device__ __forceinline__ void sort_set_wave(int64_t *a, int r) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t x = lane < r ? a[lane] : INT64_MAX;
+    int rank = 0;
+    for (int j = 0; j < r; j++) {
+        const int64_t y = __shfl(x, j);
+        rank += (y < x) || (y == x && j < lane);
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < r) a[rank] = x;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------- entry sources
+// Where the entries W[i][j] of one matrix come from: a dense row-major array
+// (FP64, FP32 or BF16 as stored, converted to FP64), or, for far-field
+// interaction blocks, evaluated on the fly from the two point sets as
+// K_ij = 1 / |x_i - y_j| in FP64 (dx dx + dy dy, then a correctly rounded
+// square root and division), so that no entry is ever stored.
+template <typename T>
+struct DenseSrc {
+    const T *A;
+    int64_t lda;
+    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const { return Elem<T>::load(A, i * lda + j); }
+};
+struct PointSrc {
+    const double *x;  // row points, (x0, x1) pairs
+    const double *y;  // column points
+    __device__ __forceinline__ double operator()(int64_t i, int64_t j) const {
+        const double dx = x[2 * i] - y[2 * j], dy = x[2 * i + 1] - y[2 * j + 1];
+        return 1.0 / sqrt(dx * dx + dy * dy);
+    }
+};
+
+// ---------------------------------------------------------------- nucleus
+// U = G^{-1} for the generator G = W[I, J] of the sorted sets in sm.Iset and
+// sm.Jset (Algorithm algcnnncl with k = l = r: the canonical nucleus is the
+// inverse): LU with partial pivoting and column solves in the oracle's
+// arithmetic, then `refine` steps X <- X + X (I - G X).  An exactly zero pivot,
+// or pivot magnitudes spread by more than 1e14, selects the pseudo-inverse of
+// G truncated at 1e-14 of its largest singular value (one-sided Jacobi).
+// ws holds 4 r^2 doubles of LDS; every one of the workgroup's `nthreads`
+// threads calls.
+template <class SM, class Src>
+__device__ __forceinline__ void nucleus(SM &sm, double *ws, const Src &src, int r, int refine, int nthreads,
+                                        double *U_out) {
+    const int tid = threadIdx.x;
+    double *G = ws, *LU = ws + r * r, *X = ws + 2 * r * r, *X2 = ws + 3 * r * r;
+    __shared__ int p[kRMax];
+    for (int e = tid; e < r * r; e += nthreads) {
+        const int a = e / r, b = e % r;
+        const double v = src(sm.Iset[a], sm.Jset[b]);
+        G[e] = v;
+        LU[e] = v;
+    }
+    __syncthreads();
+    __shared__ int sing;
+    __shared__ double ld;
+    inverse_lds(LU, X, p, r, nthreads, &sing, &ld);
+    // an exactly zero pivot, or pivot magnitudes spread by more than 1e14 (a
+    // condition estimate from the same factors): truncated pseudo-inverse
+    __shared__ int fallback;
+    if (tid == 0) {
+        int fb = sing;
+        if (!sing) {
+            double pmax = 0.0, pmin = INFINITY;
+            for (int k = 0; k < r; k++) {
+                const double a = fabs(LU[p[k] * r + k]);
+                pmax = a > pmax ? a : pmax;
+                pmin = a < pmin ? a : pmin;
+            }
+            fb = pmax > 1e14 * pmin;
+        }
+        fallback = fb;
+    }
+    __syncthreads();
+    if (fallback) {
+        __shared__ int rank;
+        pinv_jacobi_lds(G, LU, X2, X, r, 1e-14, nthreads, &rank);
+        if (tid == 0) {
+            sm.nucleus_rank = rank;
+            sm.logdet = (rank == r && !sing) ? ld : -INFINITY;
+        }
+        for (int e = tid; e < r * r; e += nthreads) U_out[e] = X[e];
+        return;
+    }
+    if (tid == 0) sm.logdet = ld;
+    for (int it = 0; it < refine; it++) {
+        double *Tm = LU;  // T = I - G X
+        for (int e = tid; e < r * r; e += nthreads) {
+            const int i = e / r, j = e % r;
+            double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll 4
+            for (int q = 0; q < r; q++) s -= G[i * r + q] * X[q * r + j];
+            Tm[e] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < r * r; e += nthreads) {
+            const int i = e / r, j = e % r;
+            double s = X[e];
+#pragma unroll 4
+            for (int q = 0; q < r; q++) s += X[i * r + q] * Tm[q * r + j];
+            X2[e] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < r * r; e += nthreads) X[e] = X2[e];
+        __syncthreads();
+    }
+    for (int e = tid; e < r * r; e += nthreads) U_out[e] = X[e];
+}
+
+}  // namespace lra

@@ -151,7 +151,7 @@ __device__ __forceinline__ KeyMax wave_keymax(KeyMax b) {
 // LU holds G on entry and the factors on exit (rows in original order, p the
 // permutation), X receives G^{-1}.  *sing_out = 1 if a pivot is exactly zero
 // (X is then not written); *logdet = log |det G|.  Every thread of the block
-// (nthreads >= 512) must call.
+// (nthreads, a multiple of 64) must call.
 __device__ __forceinline__ void inverse_lds(double *LU, double *X, int *p, int r, int nthreads, int *sing_out,
                                             double *logdet) {
     const int tid = threadIdx.x;
@@ -185,8 +185,8 @@ __device__ __forceinline__ void inverse_lds(double *LU, double *X, int *p, int r
         if (*(volatile int *)sing_out) return;
         const double pk = s_pk;
         const int pr = p[k];
-        const int i = k + 1 + tid / 8, t = tid % 8;
-        if (i < r) {
+        for (int q = tid; q < (r - k - 1) * 8; q += nthreads) {
+            const int i = k + 1 + q / 8, t = q % 8;
             const int pi = p[i];
             const double l = LU[pi * r + k] / pk;
             for (int j = k + 1 + t; j < r; j += 8) LU[pi * r + j] -= l * LU[pr * r + j];
@@ -258,7 +258,7 @@ __device__ __forceinline__ void draw_uniform_wave(uint64_t seed, uint64_t stream
 // of v_j a_j^T / sigma_j^2.  Each pair is handled by 16 lanes (its three dot
 // products summed as a butterfly, so rounding differs from the oracle's
 // sequential sums).  G, A, V, X: r x r in LDS (A and V are work space).
-// Every thread of the block (nthreads >= 512) must call; r <= 64.
+// Every thread of the block (nthreads, a multiple of 64) must call; r <= 64.
 __device__ __forceinline__ void jacobi_pair(int t, int k, int rp, int &p, int &q) {
     const int a = (k == 0) ? 0 : ((k - 1 + t) % (rp - 1)) + 1;
     const int kk = rp - 1 - k;

@@ -93,11 +93,23 @@ size_t residual_scratch_bytes(int64_t m, int64_t n, int r, int q, int s, int pre
 hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,
                            const int64_t *J, const double *U, int q, int s, uint64_t seed, int prec, double *out,
                            void *scratch, hipStream_t stream);
+hipError_t launch_posterior(const double *moments, int64_t K, double tau, double z, lra_posterior *out,
+                            hipStream_t stream);
 size_t adjoint_scratch_bytes(int64_t count, int64_t m, int64_t n, int64_t nnz, int r);
 hipError_t launch_adjoint(int64_t count, int64_t m, int64_t n, int r, const double *C, const double *R,
                           const double *G, int64_t nnz, const int32_t *orow, const int32_t *ocol,
                           const int32_t *corder, const double *aval, double *loss, double *dC, double *dR,
                           double *dG, void *scratch, int32_t *status, hipStream_t stream);
+hipError_t launch_xlat(uint64_t *buf, int rounds, uint64_t limit, hipStream_t stream);
 size_t static_lds_bytes();
+__global__ void zero_u32_kernel(unsigned *p, int n);
+
+// Batched C-A with register-resident panels (lra_batch.hip): variants exist
+// for rank r and P items per lane; `src` is the dtype code, or 3 for point sets.
+bool reg_variant_exists(int r, int P);
+int reg_occupancy(int r, int P, int waves, int src);
+hipError_t launch_reg(int src, int r, int P, int waves, const void *base, const void *blocks, const int32_t *order,
+                      int64_t count, uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, int64_t *I_out,
+                      int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
 
 }  // namespace lra

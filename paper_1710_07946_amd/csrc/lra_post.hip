@@ -480,6 +480,34 @@ static hipError_t residual_t(const void *Av, int64_t m, int64_t n, int64_t lda, 
     return hipGetLastError();
 }
 
+// The a-posteriori variance test on the moments of a q x s residual sample
+// (Section 4: the sampled error entries as observed values of one Gaussian
+// variable): mean, mean of |g|, variance sum e^2 / K - mean^2 (clamped at
+// 0), and the one-sided test K var <= tau^2 ((K - 1) - z sqrt(2 (K - 1))).
+__global__ void posterior_kernel(const double *mom, int64_t K, double tau, double z, lra_posterior *out) {
+    if (threadIdx.x != 0) return;
+    const double k = (double)K;
+    const double mean = mom[0] / k;
+    const double var = fmax(mom[1] / k - mean * mean, 0.0);
+    const double dof = (double)(K - 1);
+    const double thr = tau * tau * (dof - z * sqrt(2.0 * dof)) / k;
+    lra_posterior p;
+    p.K = K;
+    p.mean = mean;
+    p.mean_abs = mom[2] / k;
+    p.var = var;
+    p.threshold = thr;
+    p.accept = var <= thr ? 1 : 0;
+    p.reserved = 0;
+    *out = p;
+}
+
+hipError_t launch_posterior(const double *moments, int64_t K, double tau, double z, lra_posterior *out,
+                            hipStream_t stream) {
+    hipLaunchKernelGGL(posterior_kernel, dim3(1), dim3(64), 0, stream, moments, K, tau, z, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_residual(int dtype, const void *A, int64_t m, int64_t n, int64_t lda, int r, const int64_t *I,
                            const int64_t *J, const double *U, int q, int s, uint64_t seed, int prec, double *out,
                            void *scratch, hipStream_t stream) {

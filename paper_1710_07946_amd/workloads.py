@@ -169,12 +169,13 @@ def sample_omega(m: int, n: int, count: int, seed: int):
 
 # ---------------------------------------------------------------- device-side generators
 def fmm_batch_device(count: int, device, shape_seed: int = 1021, block_seed0: int = 1022000,
-                     align_elems: int = 64):
+                     align_elems: int = 64, shapes=None):
     """``fmm_batch`` evaluated on a GPU: the same shapes, points and layout (points
     from the same NumPy streams), kernel values computed in FP64 and rounded
-    to FP32.  Returns (flat device tensor, descriptors int64[count, 4])."""
+    to FP32.  ``shapes`` = (ms, ns) replaces the seeded shapes.  Returns (flat
+    device tensor, descriptors int64[count, 4])."""
     import torch
-    ms, ns = fmm_block_shapes(count, seed=shape_seed)
+    ms, ns = fmm_block_shapes(count, seed=shape_seed) if shapes is None else shapes
     desc = np.zeros((count, 4), np.int64)
     off = 0
     for b in range(count):

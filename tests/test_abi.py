@@ -298,3 +298,27 @@ def test_caller_outputs_are_checked_before_any_call():
     lra._check_out(o, k, l, l * k, 1, dev)
     with pytest.raises(ValueError):
         lra._check_out(o, l, k, l * k, 1, dev)
+
+
+def test_batch_rule_table_checked_on_host(lib):
+    """The bin table API validates its rules without touching a device."""
+    assert ct.sizeof(lra.lra_batch_rule) == 16
+    default = lra.lra_batch_get_rules()
+    assert default and all(q[2] in (0, 2) for q in default)
+    E, U = lra.LRA_EINVAL, lra.LRA_EUNSUPPORTED
+
+    def status(rules):
+        arr = (lra.lra_batch_rule * max(1, len(rules)))(*[lra.lra_batch_rule(*q) for q in rules])
+        return lib.lra_batch_set_rules(arr, len(rules))
+
+    assert status([(512, 16, 2, 2)]) == E         # 2 x 2 x 64 = 256 item slots < 512
+    assert status([(512, 16, 2, 9)]) == E         # at most 8 wavefronts
+    assert status([(0, 16, 2, 1)]) == E
+    assert status([(128, 65, 2, 1)]) == E         # rank above 64
+    assert status([(256, 8, 2, 2)]) == U          # no register variant for rank 8
+    assert status([(256, 16, 3, 2)]) == U         # nor for 3 items per lane
+    assert lib.lra_batch_set_rules(None, -1) == E
+    assert status([(1 << 20, 16, 0, 0), (256, 16, 2, 2)]) == lra.LRA_OK
+    assert lra.lra_batch_get_rules() == [(256, 16, 2, 2), (1 << 20, 16, 0, 0)]  # sorted by max_dim
+    lra.lra_batch_set_rules([])
+    assert lra.lra_batch_get_rules() == default
