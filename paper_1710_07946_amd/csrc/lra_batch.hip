@@ -29,6 +29,22 @@ namespace {
 
 constexpr int kRegMaxWaves = 8;
 
+// Built with -DLRA_TRACE, workgroup 0 of each launch adds the wall-clock
+// ticks of its phases (gathers, LU, B solve, swaps, nucleus) and its counts
+// of decisions and blocks to g_regtr, which lra_trace_reg() copies out.
+#ifdef LRA_TRACE
+__device__ uint64_t g_regtr[16];
+#define REG_TIC(v) const uint64_t v = (blockIdx.x == 0 && threadIdx.x == 0) ? wall_clock64() : 0
+#define REG_TOC(slot, v) \
+    do { if (blockIdx.x == 0 && threadIdx.x == 0) g_regtr[slot] += wall_clock64() - v; } while (0)
+#define REG_CNT(slot, n) \
+    do { if (blockIdx.x == 0 && threadIdx.x == 0) g_regtr[slot] += (n); } while (0)
+#else
+#define REG_TIC(v) ((void)0)
+#define REG_TOC(slot, v) ((void)0)
+#define REG_CNT(slot, n) ((void)0)
+#endif
+
 template <int R>
 struct RegSmem {
     int64_t Iset[R], Jset[R], Iprev[R], Jprev[R];
@@ -58,20 +74,29 @@ __device__ __forceinline__ int64_t reg_item(int p, int nw) {
 // x 0 = 0 and adding zeros leaves x unchanged).
 template <int R>
 __device__ __forceinline__ double onehot(const double (&x)[R], int j) {
-    double v = 0.0;
+    static_assert((R & (R - 1)) == 0, "a power-of-two width");
+    // a binary tree of selects on the bits of j: R - 1 selects
+    double v[R];
 #pragma unroll
-    for (int t = 0; t < R; t++) v += x[t] * (double)(t == j);
-    return v;
+    for (int t = 0; t < R; t++) v[t] = x[t];
+#pragma unroll
+    for (int h = 1; h < R; h <<= 1) {
+        const bool hi = (j & h) != 0;
+#pragma unroll
+        for (int t = 0; t < R; t += 2 * h) v[t] = hi ? v[t + h] : v[t];
+    }
+    return v[0];
 }
 
 // One decision of the workgroup: the wavefront reductions, then (W > 1) the
 // W partials through LDS, so every wavefront holds the same winner and flag;
-// the winner's panel row (its R entries) is returned in w of every lane.
+// the winner's panel row (its R entries) lands in sm.wrow.  The row is read
+// from LDS where it is used (a uniform value: no registers held for it).
 // The order is total (value, then lowest item, then lowest slot), so the
 // result does not depend on how the candidates were split.
 template <int R, int P>
 __device__ __forceinline__ void reg_select(RegSmem<R> &sm, int nw, Best b, int flag, const double (&x)[P][R],
-                                           double (&w)[R], Best &win, int &wflag) {
+                                           Best &win, int &wflag) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     b = wave_reduce(b);
     flag = wave_or(flag);
@@ -98,8 +123,6 @@ __device__ __forceinline__ void reg_select(RegSmem<R> &sm, int nw, Best b, int f
             for (int t = 0; t < R; t++) sm.wrow[t] = x[p][t];
         }
     if (nw > 1) __syncthreads();
-#pragma unroll
-    for (int t = 0; t < R; t++) w[t] = sm.wrow[t];
 }
 
 // Step K of the pivoted LU (Algorithm alggos, stages 1-2) on the register
@@ -109,8 +132,8 @@ __device__ __forceinline__ void reg_select(RegSmem<R> &sm, int nw, Best b, int f
 // gives pivot row K.  Returns false (status set) on a non-finite entry or a
 // zero pivot.
 template <int R, int P, int K>
-__device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R], int (&fl)[P], double (&w)[R],
-                                       int bad, double pk) {
+__device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R], int (&fl)[P], int bad,
+                                       double pk) {
     const int tid = threadIdx.x;
     __builtin_amdgcn_sched_barrier(0);  // no step's work moves into another's
     Best b = none();
@@ -120,14 +143,14 @@ __device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R]
         if (K > 0) {
             const double l = x[p][K > 0 ? K - 1 : 0] / pk;
 #pragma unroll
-            for (int t = K; t < R; t++) x[p][t] -= l * w[t];
+            for (int t = K; t < R; t++) x[p][t] -= l * sm.wrow[t];
             x[p][K > 0 ? K - 1 : 0] = l;
         }
         consider(b, fabs(x[p][K]), reg_item(p, nw), 0);
     }
     Best win;
     int wf;
-    reg_select<R, P>(sm, nw, b, K == 0 ? bad : 0, x, w, win, wf);
+    reg_select<R, P>(sm, nw, b, K == 0 ? bad : 0, x, win, wf);
     if (wf || !(win.v > 0.0)) {
         if (tid == 0) {
             sm.status = wf ? LRA_EINVAL : LRA_ESINGULAR;
@@ -139,18 +162,19 @@ __device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R]
     if (tid == 0) {
         sm.slot_item[K] = win.item;
 #pragma unroll
-        for (int j = 0; j < K; j++) sm.L11[K * (K - 1) / 2 + j] = w[j];
+        for (int j = 0; j < K; j++) sm.L11[K * (K - 1) / 2 + j] = sm.wrow[j];
     }
 #pragma unroll
     for (int p = 0; p < P; p++)
         if (reg_item(p, nw) == win.item) fl[p] = K + 1;
     if constexpr (K + 1 < R) {
-        return reg_lu<R, P, K + 1>(sm, nw, x, fl, w, 0, w[K]);
+        return reg_lu<R, P, K + 1>(sm, nw, x, fl, 0, sm.wrow[K]);
     } else {
         // last multipliers (no trailing columns)
+        const double pl = sm.wrow[R - 1];
 #pragma unroll
         for (int p = 0; p < P; p++)
-            if (fl[p] == 0) x[p][R - 1] /= w[R - 1];
+            if (fl[p] == 0) x[p][R - 1] /= pl;
         return true;
     }
 }
@@ -171,6 +195,7 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
     double x[P][R];
     int fl[P];  // 0: candidate item, s + 1: basis item of slot s, -1: no item
     int bad = 0;
+    REG_TIC(t_g);
     {
         int64_t sv[R];
 #pragma unroll
@@ -201,11 +226,22 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
 #pragma unroll
             for (int t = 0; t < R; t++) bad |= (fl[p] == 0) & !isfinite(x[p][t]);
     }
-    double w[R];
+#ifdef LRA_TRACE
+    if (tid == 0 && blockIdx.x == 0) {
+        // the gather's loads have landed once their values are used
+        double s0 = 0.0;
 #pragma unroll
-    for (int t = 0; t < R; t++) w[t] = 0.0;
-    if (!reg_lu<R, P, 0>(sm, nw, x, fl, w, bad, 1.0)) return false;
+        for (int p = 0; p < P; p++) s0 += x[p][0];
+        if (s0 == 1.2345e300) g_regtr[15] = 1;
+    }
+#endif
+    REG_TOC(0, t_g);
+    REG_TIC(t_lu);
+    if (!reg_lu<R, P, 0>(sm, nw, x, fl, bad, 1.0)) return false;
     __syncthreads();  // L11 written by thread 0
+    REG_TOC(1, t_lu);
+    REG_CNT(6, R);
+    REG_TIC(t_b);
     // ---- B = L21 L11^{-1}: for k = R-1 .. 1, x_k is final and every x_j,
     // j < k, takes x_j - x_k L11[k][j]; basis items get unit rows
 #pragma unroll
@@ -226,6 +262,8 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
         }
         __builtin_amdgcn_sched_barrier(0);  // one row of L11 in registers at a time
     }
+    REG_TOC(2, t_b);
+    REG_TIC(t_sw);
     // ---- swaps, each update fused with the next scan
     const double thr = 1.0 + delta;
     int swaps = 0, js = -1;
@@ -252,8 +290,9 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
                 continue;
             }
             if (f != 0.0) {
+                // w = B[i*,:] - e_js^T, formed from the row in LDS
 #pragma unroll
-                for (int t = 0; t < R; t++) x[p][t] -= f * w[t];
+                for (int t = 0; t < R; t++) x[p][t] -= f * (sm.wrow[t] - (double)(t == js));
             }
             double vb = -1.0;
             int jb = 0;
@@ -267,24 +306,23 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
         }
         Best win;
         int wf;
-        reg_select<R, P>(sm, nw, b, 0, x, w, win, wf);
+        reg_select<R, P>(sm, nw, b, 0, x, win, wf);
         const double v = win.v;
         if (v < 0.0 || v <= thr) break;  // no candidate left, or dominant
         if (swaps >= max_swaps) {
             converged = 0;
             break;
         }
-        // w <- B[i*,:] - e_js^T, the vector of the rank-one update
+        // the next scan applies B <- B - B[:,js] (B[i*,:] - e_js^T) / B[i*,js]
         js = win.slot;
-        const double piv = onehot(w, js);
-#pragma unroll
-        for (int t = 0; t < R; t++) w[t] -= (double)(t == js);
         wit = win.item;
-        pv = piv;
+        pv = sm.wrow[js];
         if (tid == 0) sm.slot_item[js] = wit;
         swaps++;
     }
     swaps_total += swaps;
+    REG_TOC(3, t_sw);
+    REG_CNT(7, swaps + 1);
     __syncthreads();  // slot_item written by thread 0 (wavefront 0 sorts it)
     if (tid < 64) {
         if (tid < R) set_out[tid] = sm.slot_item[tid];
@@ -334,7 +372,10 @@ __device__ __forceinline__ void reg_solve(RegSmem<R> &sm, int nw, const Src &src
         }
         __syncthreads();
     }
+    REG_TIC(t_n);
     if (ok) nucleus(sm, sm.nuc, src, R, refine, 64 * nw, U_out);
+    REG_TOC(4, t_n);
+    REG_CNT(8, 1);
     __syncthreads();
     const int st = sm.status;
     if (tid < R) {
@@ -375,9 +416,11 @@ __device__ __forceinline__ void reg_loop(const Desc *blocks, const int32_t *orde
         if (job >= count) break;
         const int32_t b = order[job];
         const Desc d = blocks[b];
+        REG_TIC(t_blk);
         reg_solve<R, P>(sm, nw, make(d), d.m, d.n, seed + (uint64_t)b, sweeps, delta, max_swaps, refine,
                         I_out + (int64_t)b * R, J_out + (int64_t)b * R, U_out + (int64_t)b * R * R,
                         infos ? infos + b : nullptr);
+        REG_TOC(5, t_blk);
         __syncthreads();
     }
 }
@@ -460,3 +503,15 @@ hipError_t launch_reg(int src, int r, int P, int waves, const void *base, const 
 }
 
 }  // namespace lra
+
+#ifdef LRA_TRACE
+// Copy and clear the register kernel's phase ticks (tracing builds only):
+// gathers, LU, B solve, swaps, nucleus, whole blocks; LU decisions, swap
+// decisions, blocks.
+extern "C" int lra_trace_reg(uint64_t *host) {
+    if (hipMemcpyFromSymbol(host, HIP_SYMBOL(lra::g_regtr), sizeof(uint64_t) * 16) != hipSuccess) return -1;
+    uint64_t z[16] = {0};
+    if (hipMemcpyToSymbol(HIP_SYMBOL(lra::g_regtr), z, sizeof(z)) != hipSuccess) return -1;
+    return 16;
+}
+#endif

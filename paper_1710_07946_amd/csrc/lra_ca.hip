@@ -329,7 +329,8 @@ enum SelMode { kSelPlain = 0, kSelHouseholder = 1, kSelSwap = 2 };
 // sm.wrow holds B[i*,:] - e_j*^T, the vector of the rank-one swap update.
 template <class RowFn, class Overlap>
 __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const Geo &g, int width, int mode,
-                                            int hstep, const RowFn &rowf, const Overlap &overlap) {
+                                            int hstep, const RowFn &rowf, const Overlap &overlap,
+                                            double pub_min = -1.0) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #ifdef LRA_TRACE
     const uint64_t t_in = wall_clock64();
@@ -387,11 +388,15 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                 if (tm.epoch < kSelTrace && tm.rank < 256) g_sel_pub[tm.epoch * 256 + tm.rank] = wall_clock64();
 #endif
             }
-            for (int t = lane; t < width; t += kWave) {
-                const double x = loc.v >= 0 ? rowf(t, loc.item) : 0.0;
-                const uint64_t u = (uint64_t)__double_as_longlong(x);
-                xput<32>(myrow + 2 * t, tag, (uint32_t)u);
-                xput<32>(myrow + 2 * t + 1, tag, (uint32_t)(u >> 32));
+            // a candidate at or below pub_min cannot be acted on (a swap
+            // needs |B_ij| > 1 + delta): its row is not needed, not published
+            if (loc.v > pub_min) {
+                for (int t = lane; t < width; t += kWave) {
+                    const double x = rowf(t, loc.item);
+                    const uint64_t u = (uint64_t)__double_as_longlong(x);
+                    xput<32>(myrow + 2 * t, tag, (uint32_t)u);
+                    xput<32>(myrow + 2 * t + 1, tag, (uint32_t)(u >> 32));
+                }
             }
             // every lane polls up to kMaxTeam / 64 headers, all loads at once
             // (null: past the end of the team, nothing to read)
@@ -425,7 +430,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
 #endif
             // no candidate in the whole team (every item is in the basis):
             // there is no winner row to fetch
-            const bool have = win.v >= 0.0 && win.aux >= 0 && win.aux < tm.size;
+            const bool have = win.v > pub_min && win.aux >= 0 && win.aux < tm.size;
             for (int t = lane; t < width; t += kWave) {
                 double x = 0.0;
                 if (have) {
@@ -554,8 +559,8 @@ __device__ __forceinline__ void fail_status(Smem &sm, int st, int rank) {
 }
 
 __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *panel, const Geo &g,
-                                            int width, int mode = kSelPlain, int hstep = 0) {
-    team_select(tm, sm, b, flag, g, width, mode, hstep, PanelRow{panel, g.st, g.base}, NoOverlap{});
+                                            int width, int mode = kSelPlain, int hstep = 0, double pub_min = -1.0) {
+    team_select(tm, sm, b, flag, g, width, mode, hstep, PanelRow{panel, g.st, g.base}, NoOverlap{}, pub_min);
 }
 
 // ---------------------------------------------------------------- maxvol
@@ -592,7 +597,6 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
     const LaneMap ld = lane_map(g.cnt, r, 1, kNWave - 1);  // overlap lanes (waves 1..)
     const int subd = ld.sub, sd = ld.s, grpd = ld.grp, ngrpd = ld.ngrp;
     double pk = 1.0;
-    int fix_li = -1;  // the workgroup's best item of the last selection, if another item won
     for (int k = 0; k < r; k++) {
 #ifdef LRA_TRACE
         const uint64_t q0 = wall_clock64();
@@ -603,15 +607,6 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             if (k > 0) {
                 const double l = panel[(k - 1) * st + li] / pk;
                 if (ahead) {
-                    if (li == fix_li) {
-                        // its columns from k on still lack elimination k-2
-                        // (the look-ahead published it with the elimination
-                        // applied on the fly): apply it before elimination k-1
-                        const int jf = (k <= s) ? s : s + ((k - s + sub - 1) / sub) * sub;
-                        if (jf <= jlast)
-                            axpy_slots(panel, sm.wprev[k & 1], jf * st + li, pstep, jf, sub, (jlast - jf) / sub + 1,
-                                       panel[(k - 2) * st + li]);
-                    }
                     if (k % sub == s) {
                         const double x = panel[k * st + li] - l * sm.wrow[k];
                         panel[k * st + li] = x;
@@ -664,17 +659,24 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             if (lw % ngrp == grp && s == 0) flags[lw] = (uint8_t)(k + 1);
         }
         // the workgroup's best item, if it did not win, takes elimination k-1
-        // on its columns past k in the next scan (its owner lanes, before they
-        // apply elimination k), so no barrier is needed here
+        // on its columns past k (one thread per column), before the next scan
+        // (spread over threads: done in the scan by the item's own lanes it
+        // makes this workgroup the team's last to publish)
         const int64_t lb = sm.loc_item;
-        fix_li = (ahead && k > 0 && lb != wit && lb >= g.base && lb < g.base + g.cnt) ? (int)(lb - g.base) : -1;
+        if (ahead && k > 0 && lb != wit && lb >= g.base && lb < g.base + g.cnt && tid < r - 1 - k) {
+            const int li = (int)(lb - g.base);
+            const int j = k + 1 + tid;
+            panel[j * st + li] -= panel[(k - 1) * st + li] * wp[j];
+        }
         pk = sm.wrow[k];
-        // the look-ahead keeps the pivot row for the next overlap and fix-up;
-        // their readers run after the next selection's first barrier, or read
-        // the other buffer.  (Eager: the next scan touches only entries its
-        // own lanes own, and the next selection's first barrier orders
-        // everything shared.)
-        if (ahead && tid < r) sm.wprev[k & 1][tid] = sm.wrow[tid];
+        if (ahead) {
+            // the look-ahead keeps the pivot row for the next overlap, and the
+            // fix-up above must land before the next scan reads column k+1
+            if (tid < r) sm.wprev[k & 1][tid] = sm.wrow[tid];
+            __syncthreads();
+        }
+        // (eager: the next scan touches only entries its own lanes own, and
+        // the next selection's first barrier orders everything shared)
 #ifdef LRA_TRACE
         if (tid == 0) sm.t_loop[1] += wall_clock64() - q2;
 #endif
@@ -704,6 +706,7 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             double xr[8];
 #pragma unroll
             for (int u = 0; u < 8; u++) xr[u] = u < nb ? panel[(j0 + u) * st + li] : 0.0;
+#pragma unroll 4
             for (int k = r - 1; k >= j0 + 8; k--) {
                 const double xk = panel[k * st + li];
                 const double *Lk = sm.L11 + k * (k - 1) / 2 + j0;
@@ -768,7 +771,7 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
         const uint64_t q1 = wall_clock64();
         if (tid == 0) sm.t_loop[2] += q1 - q0;
 #endif
-        team_select(tm, sm, b, 0, panel, g, r, kSelSwap);
+        team_select(tm, sm, b, 0, panel, g, r, kSelSwap, 0, thr);
 #ifdef LRA_TRACE
         const uint64_t q2 = wall_clock64();
 #endif

@@ -186,7 +186,13 @@ __device__ __forceinline__ void nucleus(SM &sm, double *ws, const Src &src, int 
     __syncthreads();
     __shared__ int sing;
     __shared__ double ld;
-    inverse_lds(LU, X, p, r, nthreads, &sing, &ld);
+    // one wavefront for small r (no barriers); the whole workgroup for
+    // larger r, where the single wavefront's solves are latency-bound (both
+    // compute every entry with the same operations)
+    if (r <= 24)
+        inverse_wave(LU, X, p, r, &sing, &ld);
+    else
+        inverse_lds(LU, X, p, r, nthreads, &sing, &ld);
     // an exactly zero pivot, or pivot magnitudes spread by more than 1e14 (a
     // condition estimate from the same factors): truncated pseudo-inverse
     __shared__ int fallback;

@@ -228,6 +228,65 @@ __device__ __forceinline__ void inverse_lds(double *LU, double *X, int *p, int r
     __syncthreads();
 }
 
+// The inverse of inverse_lds, every entry computed by the same operations in
+// the same order, run by wavefront 0 alone (lockstep, so no barriers; the
+// other wavefronts return at once and the caller synchronizes): lane i holds
+// permutation position i, the pivot search is a DPP argmax over the lanes,
+// lane i eliminates row p_i, and lane c solves column c of the inverse
+// (forward: X[i][c] takes its terms in increasing j; backward: x_i =
+// (y_i - sum_{j > i} U[p_i][j] x_j) / U[p_i][i] with j increasing).  LDS
+// accesses of one wavefront complete in program order.  r <= 64.
+__device__ __forceinline__ void inverse_wave(double *LU, double *X, int *p, int r, int *sing_out, double *logdet) {
+    if (threadIdx.x >= kWave) return;
+    const int lane = threadIdx.x;
+    int pi = lane;  // row at permutation position `lane`
+    double ld = 0.0;
+    int sing = 0;
+    for (int k = 0; k < r; k++) {
+        const bool cand = lane >= k && lane < r;
+        KeyMax c{cand ? fabs(LU[pi * r + k]) : -1.0, cand ? pi : 0x7fffffff, lane};
+        c = wave_keymax(c);
+        if (c.v == 0.0) {
+            sing = 1;
+            break;
+        }
+        const int pw = __builtin_amdgcn_readlane(pi, c.who), pkr = __builtin_amdgcn_readlane(pi, k);
+        pi = (lane == k) ? pw : (lane == c.who ? pkr : pi);
+        const double pk = LU[pw * r + k];
+        ld += log(fabs(pk));
+        __builtin_amdgcn_wave_barrier();
+        if (lane > k && lane < r) {
+            const double l = LU[pi * r + k] / pk;
+            for (int j = k + 1; j < r; j++) LU[pi * r + j] -= l * LU[pw * r + j];
+            LU[pi * r + k] = l;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane < r) p[lane] = pi;
+    if (lane == 0) {
+        *sing_out = sing;
+        *logdet = ld;
+    }
+    if (sing) return;
+    __builtin_amdgcn_wave_barrier();
+    // forward, column c by lane c: X[i][c] = (p_i == c) - sum_{j < i} L[p_i][j] X[j][c]
+    if (lane < r) {
+        const int c = lane;
+        for (int i = 0; i < r; i++) X[i * r + c] = (p[i] == c) ? 1.0 : 0.0;
+        for (int j = 0; j < r - 1; j++) {
+            const double xj = X[j * r + c];
+            for (int i = j + 1; i < r; i++) X[i * r + c] -= LU[p[i] * r + j] * xj;
+        }
+        // backward: x_i = (y_i - sum_{j > i} U[p_i][j] x_j) / U[p_i][i], j increasing
+        for (int ii = r - 1; ii >= 0; ii--) {
+            const int q = p[ii];
+            double sum = X[ii * r + c];
+            for (int j = ii + 1; j < r; j++) sum -= LU[q * r + j] * X[j * r + c];
+            X[ii * r + c] = sum / LU[q * r + ii];
+        }
+    }
+}
+
 // k i.i.d. draws from [0, n) with replacement, in draw order: the accepted
 // outputs of the stream (the top 2^64 mod n words rejected), reduced mod n.
 // Run by all 64 lanes of one wave: 64 counters are hashed at once and the
