@@ -32,24 +32,52 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
 
-# HBM bytes per launch of the C-A kernel on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE passes scaled by a plain 1 GiB copy's readings
-# (profiles/ca_team_kernel_20000x20000_r50.md).  They describe the kernel
-# built from the sources with this SHA-1 and are reported only while the
-# sources still hash to it.
-KERNEL_SOURCES = ("paper_1710_07946_amd/csrc/lra_ca.hip", "paper_1710_07946_amd/csrc/lra_device.h",
-                  "paper_1710_07946_amd/csrc/lra_internal.h", "paper_1710_07946_amd/build.py")
-COUNTED_SHA1 = "e4fb55dd5835059470c67f35f482ffc065f2c95d"
-COUNTED_TRAFFIC = 293640.9 * (1048576.0 / 524308.2) * 1024 + 141207.9 * 1.0 * 1024
+# HBM bytes per timed unit of a line, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# passes (KiB per dispatch of the line's kernels, summed over one unit),
+# scaled by what the same counters read for a plain 1 GiB device copy
+# (1 GiB read, 1 GiB written).  Each entry describes the kernels built from
+# the listed sources with the SHA-1 given and is reported only while those
+# sources still hash to it.  The summaries with the commands are under
+# profiles/.
+_CS = "paper_1710_07946_amd/csrc/"
+SRC_TEAM = (_CS + "lra_ca.hip", _CS + "lra_device.h", _CS + "lra_internal.h", "paper_1710_07946_amd/build.py")
+SRC_BATCH = (_CS + "lra_batch.hip", _CS + "lra_common.h", _CS + "lra_device.h", _CS + "lra_internal.h",
+             _CS + "lra_api.hip", "paper_1710_07946_amd/build.py")
+SRC_POST = (_CS + "lra_post.hip", _CS + "lra_device.h", _CS + "lra_internal.h", "paper_1710_07946_amd/build.py")
+# line: (sources, SHA-1, FETCH_SIZE KiB per unit, WRITE_SIZE KiB per unit, copy FETCH KiB, copy WRITE KiB)
+TRAFFIC_COUNTS = {
+    # one LRA: one ca_team_kernel dispatch (profiles/ca_team_kernel_20000x20000_r50.md)
+    "headline": (SRC_TEAM, "e4fb55dd5835059470c67f35f482ffc065f2c95d", 293640.9, 141207.9, 524308.2, 1048576.0),
+    # one batch: the four bin dispatches of ca_reg_kernel (profiles/ca_reg_kernel_fmm4096_r16.md)
+    "batched": (SRC_BATCH, "f626233ded7b18dabd1602245a98d81aeea90bfd", 4 * 1067069.0, 4 * 2407.2,
+                524308.1, 1048576.0),
+    # one batch: the four bin dispatches of ca_reg_points_kernel
+    "points": (SRC_BATCH, "f626233ded7b18dabd1602245a98d81aeea90bfd", 4 * 9688.3, 4 * 2407.9,
+               524308.1, 1048576.0),
+    # one full residual: the resid_kernel dispatch (FP64 core; BF16 x 3 core)
+    # (profiles/resid_kernels_20000x20000_r50.md)
+    "residual_fp64": (SRC_POST, "3e641c35d2fc1e35e48a59e7185335df640bce19", 971912.0, 68.7, 524308.1, 1048576.0),
+    "residual_mixed": (SRC_POST, "3e641c35d2fc1e35e48a59e7185335df640bce19", 960211.1, 68.7, 524308.1, 1048576.0),
+    # one launch of 256 blocks: the seven adj_* dispatches (profiles/adjoint_kernels_256x2048_r32.md)
+    "adjoint": (SRC_POST, "3e641c35d2fc1e35e48a59e7185335df640bce19", 1174547.9, 563408.0, 524308.1, 1048576.0),
+}
 
 
-def kernel_sources_sha1():
+def sources_sha1(files):
     import hashlib
     h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def counted_traffic(line):
+    """Counter bytes per unit of `line`, or None once its kernels' sources changed."""
+    src, sha, fetch, write, copy_fetch, copy_write = TRAFFIC_COUNTS[line]
+    if sources_sha1(src) != sha:
+        return None
+    return 1024.0 * (fetch * (1048576.0 / copy_fetch) + write * (1048576.0 / copy_write))
 
 
 def algorithmic_bytes(m, n, r, sweeps_run, depth, samples, elem):
@@ -75,6 +103,13 @@ def main():
     ap.add_argument("--only", choices=["batched", "points", "cynical", "adjoint", "tall", "residual", "starts"],
                     default=None,
                     help="time one secondary line alone and print it (for profiling)")
+    ap.add_argument("--no-plain-loop", action="store_true",
+                    help="batched line: skip the comparison loop of single-LRA launches")
+    ap.add_argument("--save-sets", default=None,
+                    help="residual / adjoint line: write the index sets of the forward C-A to this .npz")
+    ap.add_argument("--sets", default=None,
+                    help="residual / adjoint line: read the index sets from this .npz instead of running the "
+                         "forward C-A (so a profiled run holds only the line's own kernels)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -110,12 +145,21 @@ def main():
     A = torch.from_numpy(A_np).cuda()
     kw = dict(preprocess=lra.LRA_PRE_ASRHT, ah_depth=DEPTH, ah_samples=SAMPLES)
 
-    out = lra.lra_cur(A, RANK, SWEEPS, SEED, **kw)
-    torch.cuda.synchronize()
     if args.only == "residual":
-        print(json.dumps({"residual": residual_fields(lra, torch, A, out.I, out.J, out.U, M, N, RANK, 4,
+        if args.sets:
+            z = np.load(args.sets)
+            I, J = (torch.from_numpy(z[k]).cuda() for k in ("I", "J"))
+            U = torch.from_numpy(z["U"]).cuda()
+        else:
+            out = lra.lra_cur(A, RANK, SWEEPS, SEED, **kw)
+            I, J, U = out.I, out.J, out.U
+            if args.save_sets:
+                np.savez(args.save_sets, I=I.cpu().numpy(), J=J.cpu().numpy(), U=U.cpu().numpy())
+        print(json.dumps({"residual": residual_fields(lra, torch, A, I, J, U, M, N, RANK, 4,
                                                       max(2, args.steps // 5))}), flush=True)
         return
+    out = lra.lra_cur(A, RANK, SWEEPS, SEED, **kw)
+    torch.cuda.synchronize()
     if args.only == "starts":
         print(json.dumps({"bidiag_start": bench_bidiag_start(lra, torch, np, A, args),
                           "fourier_start": bench_fourier_start(lra, torch, np, A, args),
@@ -170,7 +214,7 @@ def main():
                    "seed": SEED, "input_dtype": "fp32"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": COUNTED_TRAFFIC if kernel_sources_sha1() == COUNTED_SHA1 else None},
+                     "traffic": counted_traffic("headline")},
         "useful_bytes_per_lra": nbytes,
         "kernel_ms": kernel_ms,
         "host_wall_ms_per_step": wall * 1e3 / args.steps,
@@ -403,6 +447,10 @@ def residual_fields(lra, torch, A, I, J, U, m, n, r, elem, steps):
     tflops = flops / (ms_full * 1e-3) / 1e12
     gbs_mixed = m * n * elem / (ms_mixed * 1e-3) / 1e9
     err_full = math.sqrt(full[1] / full[3])
+    # counter bytes describe the 20000 x 20000 FP32 headline matrix only
+    headline = (m, n, r, elem) == (M, N, RANK, 4)
+    traffic_fp64 = counted_traffic("residual_fp64") if headline else None
+    traffic_mixed = counted_traffic("residual_mixed") if headline else None
     err_mixed = math.sqrt(mixed[1] / mixed[3])
     return {
         "ms_full_fp64": ms_full, "ms_full_mixed": ms_mixed, "ms_sampled_256x256": ms_samp,
@@ -411,9 +459,9 @@ def residual_fields(lra, torch, A, I, J, U, m, n, r, elem, steps):
         "mixed_vs_fp64_rel_diff_of_err": abs(err_mixed - err_full) / err_full,
         "rel_fro_err_sampled_256x256": float(math.sqrt(samp[1] / samp[3])),
         "roofline_fp64": {"bound": "mfma", "achieved": tflops, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                          "frac": tflops / FP64_PEAK_TFS, "traffic": None},
+                          "frac": tflops / FP64_PEAK_TFS, "traffic": traffic_fp64},
         "roofline_mixed": {"bound": "hbm", "achieved": gbs_mixed, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": gbs_mixed / HBM_PEAK_GBS, "traffic": None},
+                           "frac": gbs_mixed / HBM_PEAK_GBS, "traffic": traffic_mixed},
     }
 
 
@@ -431,27 +479,35 @@ def bench_batched(lra, workloads, torch, np, args):
     infos = out.info()
     bad = [i for i in infos if i["status"] != 0]
     nbytes = sum(4 * (inf["sweeps_run"] * (int(d[1]) * r + r * int(d[2])) + r * r) for inf, d in zip(infos, desc))
+    sector_bytes = sum(inf["sweeps_run"] * (64 * int(d[1]) * min(r, -(-int(d[2]) // 16)) + 4 * r * int(d[2]))
+                       + 64 * r * r for inf, d in zip(infos, desc))
     loop_n = 256
-    views = [base[int(d[0]):int(d[0]) + int(d[1]) * int(d[2])].view(int(d[1]), int(d[2])) for d in desc[:loop_n]]
-    outs = [lra.lra_cur(views[b], r, sweeps, seed + b) for b in range(loop_n)]
+    ms_loop, same = float("nan"), None
+    if not args.no_plain_loop:
+        views = [base[int(d[0]):int(d[0]) + int(d[1]) * int(d[2])].view(int(d[1]), int(d[2])) for d in desc[:loop_n]]
+        outs = [lra.lra_cur(views[b], r, sweeps, seed + b) for b in range(loop_n)]
 
-    def loop():
-        for b in range(loop_n):
-            lra.lra_cur(views[b], r, sweeps, seed + b, out=outs[b])
+        def loop():
+            for b in range(loop_n):
+                lra.lra_cur(views[b], r, sweeps, seed + b, out=outs[b])
 
-    ms_loop = _time_events(torch, loop, 2, 1)
-    same = all(outs[b].I.cpu().tolist() == out.I[b].cpu().tolist() and
-               outs[b].J.cpu().tolist() == out.J[b].cpu().tolist() for b in range(8))
+        ms_loop = _time_events(torch, loop, 2, 1)
+        same = all(outs[b].I.cpu().tolist() == out.I[b].cpu().tolist() and
+                   outs[b].J.cpu().tolist() == out.J[b].cpu().tolist() for b in range(8))
+        del outs, views
     gbs = nbytes / (ms * 1e-3) / 1e9
     res = {
         "workload": "4096 FMM blocks 1/|x-y|, m, n uniform in 64..1024, fp32; r=16, 3 sweeps, random start",
         "lras_per_s": count / (ms * 1e-3), "ms_per_batch": ms,
-        "plain_loop_lras_per_s": loop_n / (ms_loop * 1e-3), "plain_loop_sample": "first %d blocks" % loop_n,
-        "speedup_vs_plain_loop": (count / ms) / (loop_n / ms_loop),
-        "failed_blocks": len(bad), "first_8_match_plain_calls": bool(same),
+        "plain_loop_lras_per_s": None if args.no_plain_loop else loop_n / (ms_loop * 1e-3),
+        "plain_loop_sample": "first %d blocks" % loop_n,
+        "speedup_vs_plain_loop": None if args.no_plain_loop else (count / ms) / (loop_n / ms_loop),
+        "failed_blocks": len(bad), "first_8_match_plain_calls": same,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": counted_traffic("batched")},
         "useful_bytes_per_batch": nbytes,
+        # a strided FP32 column entry moves at least one 64-byte sector
+        "sector_bytes_per_batch": sector_bytes,
         "bin_rules": [list(q) for q in lra.lra_batch_get_rules()],
     }
     if not args.no_cpu_baseline:
@@ -499,7 +555,7 @@ def bench_batched(lra, workloads, torch, np, args):
                      "frac": gbs_u / HBM_PEAK_GBS, "traffic": None},
         "useful_bytes_per_batch": nbytes_u,
     }
-    del base, out, outs, views, uo
+    del base, out, uo
     torch.cuda.empty_cache()
     return res
 
@@ -526,7 +582,7 @@ def bench_points(lra, workloads, torch, np, args):
         "lras_per_s": count / (ms * 1e-3), "ms_per_batch": ms, "failed_blocks": len(bad),
         "entries_per_batch": entries, "point_bytes": int(pts_np.nbytes),
         "roofline": {"bound": "alu", "achieved": tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                     "frac": tfs / FP64_PEAK_TFS, "traffic": None},
+                     "frac": tfs / FP64_PEAK_TFS, "traffic": counted_traffic("points")},
     }
     del pts, out
     torch.cuda.empty_cache()
@@ -542,17 +598,27 @@ def bench_adjoint(lra, workloads, torch, np, args):
     Cs, Rs, Gs, rows, cols, vals = [], [], [], [], [], []
     g = torch.Generator(device="cuda")
     g.manual_seed(4242)
+    sets = np.load(args.sets) if args.sets else None
+    saved_I, saved_J = [], []
     for b in range(count):
         A = workloads.factor_gaussian_device(m, n, r, 1e-5, 6000 + b, "cuda")
-        res = lra.lra_cur(A, r, 3, 7000 + b)
+        if sets is not None:
+            Ib, Jb = torch.from_numpy(sets["I"][b]).cuda(), torch.from_numpy(sets["J"][b]).cuda()
+        else:
+            res = lra.lra_cur(A, r, 3, 7000 + b)
+            Ib, Jb = res.I, res.J
+            saved_I.append(Ib.cpu().numpy())
+            saved_J.append(Jb.cpu().numpy())
         A64 = A.to(torch.float64)
-        Cs.append(A64[:, res.J])
-        Rs.append(A64[res.I])
-        Gs.append(A64[res.I][:, res.J])
+        Cs.append(A64[:, Jb])
+        Rs.append(A64[Ib])
+        Gs.append(A64[Ib][:, Jb])
         flat = torch.sort(torch.randperm(m * n, generator=g, device="cuda")[:nnz]).values
         rows.append((flat // n).to(torch.int32))
         cols.append((flat % n).to(torch.int32))
         vals.append(A64.reshape(-1)[flat])
+    if args.save_sets and sets is None:
+        np.savez(args.save_sets, I=np.stack(saved_I), J=np.stack(saved_J))
     C, R, G = (torch.stack(x).contiguous() for x in (Cs, Rs, Gs))
     om_row, om_col, a_om = (torch.stack(x).contiguous() for x in (rows, cols, vals))
     order = lra.omega_column_order(om_row, om_col)
@@ -586,7 +652,7 @@ def bench_adjoint(lra, workloads, torch, np, args):
         "blocks_per_s": count / (ms * 1e-3), "ms_per_launch": ms,
         "failed_blocks": int((st != 0).sum().item()),
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": counted_traffic("adjoint")},
         "useful_bytes_per_launch": nbytes,
     }
 
