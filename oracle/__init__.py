@@ -95,12 +95,14 @@ def lib():
                                          dbl, i32, P, P, P, P]
         L.orc_draw_uniform.argtypes = [u64, u64, i64, i64, P]
         L.orc_uniform_cur.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P, P]
+        L.orc_sketch_scores.argtypes = [P, i64, ct.c_int, ct.c_int, P, P]
+        L.orc_dmm_ca.argtypes = [P, ct.c_int, i64, i64, i64, ct.c_int, ct.c_int, ct.c_int, ct.c_int, u64, P, P, P, P]
         for f in ("orc_draw_distinct", "orc_panel_lu", "orc_maxvol", "orc_sketch", "orc_qrp",
                   "orc_inverse", "orc_refine_inverse", "orc_ca_cur", "orc_residual", "orc_cur_adjoint", "orc_residual_moments",
                   "orc_fmm_entries", "orc_cynical", "orc_bidiag_column", "orc_sketch_bidiag",
                   "orc_hadamard_apply", "orc_pinv_trunc", "orc_projective_select", "orc_projective_cur",
                   "orc_draw_uniform", "orc_uniform_cur", "orc_sketch_fourier", "orc_leverage_scores",
-                  "orc_leverage_cur", "orc_posterior_test"):
+                  "orc_leverage_cur", "orc_posterior_test", "orc_sketch_scores", "orc_dmm_ca"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -433,6 +435,35 @@ def leverage_cur(A: np.ndarray, I0, J0, k: int, l: int, seed: int) -> CurResult:
     info = _Info()
     st = lib().orc_leverage_cur(_p(A), _dtype_code(A), m, n, n, r, _p(I0), _p(J0), k, l, seed, _p(I), _p(J),
                                 _p(U), ct.byref(info))
+    return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
+                     info.min_margin, info.det_log_abs, info.nucleus_rank)
+
+
+def sketch_scores(P: np.ndarray, r: int):
+    """(status, q, cdf): rank-r leverage scores of the rows of the sketch P
+    (items x w), q_i = |row i of its r dominant left singular vectors|^2
+    (summing to r), and their running sums."""
+    P = np.ascontiguousarray(P, np.float64)
+    items, w = P.shape
+    q = np.zeros(items)
+    cdf = np.zeros(items)
+    st = lib().orc_sketch_scores(_p(P), items, w, r, _p(q), _p(cdf))
+    return st, q, cdf
+
+
+def dmm_ca(A: np.ndarray, r: int, k: int, l: int, iters: int, seed: int) -> CurResult:
+    """C-A with DMM08 leverage-score sampling of every sketch (see
+    orc_dmm_ca): I has k rows, J l columns (sorted, duplicates kept), U is
+    l x k; min_margin is the smallest relative distance of a draw from the
+    boundary of the item it picked."""
+    A = np.ascontiguousarray(A)
+    m, n = A.shape
+    I = np.full(k, -1, np.int64)
+    J = np.full(l, -1, np.int64)
+    U = np.zeros((l, k))
+    info = _Info()
+    st = lib().orc_dmm_ca(_p(A), _dtype_code(A), m, n, n, r, k, l, iters, seed, _p(I), _p(J), _p(U),
+                          ct.byref(info))
     return CurResult(st, I, J, U, info.sweeps_run, info.swaps_total, info.converged, info.rank_found,
                      info.min_margin, info.det_log_abs, info.nucleus_rank)
 

@@ -1875,3 +1875,235 @@ int orc_leverage_scores(const double *P, int64_t items, int r, double *q, double
     if (!P || !q || !cdf || items < 1 || r < 1) return ORC_EINVAL;
     return orc_leverage(P, items, r, q, cdf);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Rank-r leverage scores of the items of a sketch P (items x w, item-      */
+/* major, w >= r): eq. eqlevsc with beta = 1, p_i = |u_i^(r)|^2 / r, u_i^(r) */
+/* row i of the items x r factor of P's r dominant left singular vectors.   */
+/* Plain one-sided Jacobi (Hestenes) SVD of P: cyclic sweeps over the       */
+/* column pairs (a, b), a < b, in row order; a pair is rotated when         */
+/* |g| > w eps sqrt(al be) (al = |p_a|^2, be = |p_b|^2, g = p_a . p_b) so   */
+/* that it becomes orthogonal; sweeps until none rotates (at most 80).      */
+/* Then sigma_a = |p_a|; kept are the r largest (ties to the lower index)   */
+/* among those with sigma_a^2 > 1e-13 sigma_max^2, and q_i = the sum over   */
+/* the kept, largest first, of (P_ia / sigma_a)^2 (so the q_i sum to the     */
+/* number kept).  Reading: a sketch of numerical rank below r (a row drawn   */
+/* twice) gives the scores of its whole dominant subspace; 1e-13 lies far    */
+/* above the rounding level of sigma^2 however it is computed and far below */
+/* the top singular values of the inputs the method is meant for.           */
+/* cdf[i] = q_0 + ... + q_i.  ESINGULAR when nothing is kept (P = 0).        */
+/* ------------------------------------------------------------------------ */
+static int orc_top_scores(const double *P, int64_t items, int w, int r, double *q, double *cdf) {
+    double *B = (double *)malloc(sizeof(double) * (size_t)items * (size_t)w);   /* column-major copy */
+    double *sig = (double *)malloc(sizeof(double) * (size_t)w);
+    int *top = (int *)malloc(sizeof(int) * (size_t)w);
+    for (int a = 0; a < w; a++)
+        for (int64_t i = 0; i < items; i++) B[(size_t)a * items + i] = P[i * w + a];
+    const double tol = (double)w * 0x1p-52;
+    for (int sweep = 0; sweep < 80; sweep++) {
+        int rotated = 0;
+        for (int a = 0; a < w - 1; a++)
+            for (int b = a + 1; b < w; b++) {
+                double *x = B + (size_t)a * items, *y = B + (size_t)b * items;
+                double al = 0.0, be = 0.0, g = 0.0;
+                for (int64_t i = 0; i < items; i++) {
+                    al += x[i] * x[i];
+                    be += y[i] * y[i];
+                    g += x[i] * y[i];
+                }
+                if (g == 0.0 || fabs(g) <= tol * sqrt(al * be)) continue;
+                const double ze = (be - al) / (2.0 * g);
+                const double t = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+                if (s == 0.0) continue;
+                for (int64_t i = 0; i < items; i++) {
+                    const double u = x[i], v = y[i];
+                    x[i] = c * u - s * v;
+                    y[i] = s * u + c * v;
+                }
+                rotated = 1;
+            }
+        if (!rotated) break;
+    }
+    for (int a = 0; a < w; a++) {
+        double s2 = 0.0;
+        for (int64_t i = 0; i < items; i++) s2 += B[(size_t)a * items + i] * B[(size_t)a * items + i];
+        sig[a] = sqrt(s2);
+    }
+    /* the r largest, largest first (selection; ties to the lower index) */
+    double smax = 0.0;
+    for (int a = 0; a < w; a++) smax = sig[a] > smax ? sig[a] : smax;
+    int kept = 0;
+    for (int t = 0; t < r; t++) {
+        int best = -1;
+        for (int a = 0; a < w; a++) {
+            int used = 0;
+            for (int u = 0; u < t; u++) used |= top[u] == a;
+            if (!used && (best < 0 || sig[a] > sig[best])) best = a;
+        }
+        top[t] = best;
+        if (sig[best] * sig[best] > 1e-13 * (smax * smax)) kept = t + 1;
+    }
+    int st = kept > 0 ? ORC_OK : ORC_ESINGULAR;
+    double acc = 0.0;
+    for (int64_t i = 0; i < items && st == ORC_OK; i++) {
+        double s = 0.0;
+        for (int t = 0; t < kept; t++) {
+            const double u = B[(size_t)top[t] * items + i] / sig[top[t]];
+            s += u * u;
+        }
+        q[i] = s;
+        acc += s;
+        cdf[i] = acc;
+    }
+    free(B); free(sig); free(top);
+    return st;
+}
+
+/* Rank-r scores of a sketch, exported for the pins. */
+int orc_sketch_scores(const double *P, int64_t items, int w, int r, double *q, double *cdf) {
+    if (!P || !q || !cdf || items < 1 || w < 1 || r < 1 || r > w) return ORC_EINVAL;
+    return orc_top_scores(P, items, w, r, q, cdf);
+}
+
+/* Distance of the draws of orc_sample_scores from the nearest boundary of  */
+/* the items they picked, relative to S: min over t of min(cdf[i_t] - u_t S, */
+/* u_t S - cdf[i_t - 1]) / S (cdf[-1] = 0).  A draw whose u_t S moves by     */
+/* less than this keeps its item.                                           */
+static double orc_sample_margin(const double *cdf, int64_t items, uint64_t seed, uint64_t stream, int k,
+                                const int64_t *picked) {
+    const double S = cdf[items - 1];
+    double mg = 1.0;
+    for (int t = 0; t < k; t++) {
+        const double u = (double)(orc_rng_u64(seed, stream, (uint64_t)t) >> 11) * 0x1p-53;
+        const double target = u * S;
+        const int64_t i = picked[t];
+        const double hi = (cdf[i] - target) / S, lo = (target - (i > 0 ? cdf[i - 1] : 0.0)) / S;
+        const double d = hi < lo ? hi : lo;
+        mg = d < mg ? d : mg;
+    }
+    return mg;
+}
+
+/* Pairs (index, scale) sorted by index, for keeping each drawn item's     */
+/* rescaling factor beside it.                                              */
+typedef struct {
+    int64_t idx;
+    double scale;
+} orc_drawn;
+
+static int cmp_drawn(const void *a, const void *b) {
+    const int64_t x = ((const orc_drawn *)a)->idx, y = ((const orc_drawn *)b)->idx;
+    return (x > y) - (x < y);
+}
+
+/* One half-step of C-A with DMM08 sampling: scores of the sketch P (items x */
+/* w) by orc_top_scores, then cnt draws by them (Algorithm algsmplex,        */
+/* orc_sample_scores on `stream`), sorted ascending with duplicates kept,    */
+/* and each draw's rescaling 1 / sqrt(cnt q_i / S) of Algorithm algsmplex.  */
+static int orc_dmm_half(const double *P, int64_t items, int w, int r, int cnt, uint64_t seed, uint64_t stream,
+                        int64_t *set, double *scale, double *margin) {
+    double *q = (double *)malloc(sizeof(double) * (size_t)items);
+    double *cdf = (double *)malloc(sizeof(double) * (size_t)items);
+    orc_drawn *dr = (orc_drawn *)malloc(sizeof(orc_drawn) * (size_t)cnt);
+    int st = orc_top_scores(P, items, w, r, q, cdf);
+    if (st == ORC_OK) {
+        orc_sample_scores(cdf, items, seed, stream, cnt, set);
+        const double mg = orc_sample_margin(cdf, items, seed, stream, cnt, set);
+        *margin = mg < *margin ? mg : *margin;
+        const double S = cdf[items - 1];
+        for (int t = 0; t < cnt; t++) {
+            dr[t].idx = set[t];
+            dr[t].scale = 1.0 / sqrt(((double)cnt * q[set[t]]) / S);
+        }
+        qsort(dr, (size_t)cnt, sizeof(orc_drawn), cmp_drawn);
+        for (int t = 0; t < cnt; t++) {
+            set[t] = dr[t].idx;
+            scale[t] = dr[t].scale;
+        }
+    }
+    free(q); free(cdf); free(dr);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* C-A whose step subalgorithm is the leverage-score sampling of DMM08      */
+/* applied to every vertical and horizontal sketch (Section "Testing C-A    */
+/* acceleration of the algorithms of DMM08", Tables 7 and 8: eight C-A      */
+/* iterations; the sampling is that of Algorithm algcurlevsc with Algorithm */
+/* algsmplex, the scores those of eq. eqlevsc with beta = 1 taken of the     */
+/* sketch in place of W).                                                    */
+/*   start: J = l uniform draws (stream 8), D = sqrt(n / l) I (uniform       */
+/*          scores, as in orc_uniform_cur);                                 */
+/*   iteration t = 0 .. iters - 1:                                          */
+/*     rows:    sketch W[:, J] D (m x l); its rank-r row scores; k draws     */
+/*              (stream 16 + 2t) -> I sorted, Dbar = diag(1/sqrt(k p_i));    */
+/*     columns: sketch Dbar W[I, :] (k x n); its rank-r column scores; l     */
+/*              draws (stream 17 + 2t) -> J sorted, D = diag(1/sqrt(l p_j)); */
+/*   nucleus: M = Dbar W[I, J] D, U = D M_r^+ Dbar (orc_pinv_trunc).         */
+/* Readings: the sketches are rescaled as Algorithm algcurlevsc rescales C   */
+/* before its row scores (stage 3 takes them of (C D)^T), on both sides;     */
+/* draws are Exactly(k) / Exactly(l) (Algorithm algsmplex), so every step    */
+/* returns k rows and l columns; one iteration is a row step then a column  */
+/* step, so the last two steps are Algorithm algcurlevsc applied to W^T      */
+/* with the row scores of the last vertical sketch.                          */
+/* info: sweeps_run = iters, nucleus_rank, det_log_abs = log v_{2,r}(M),    */
+/* min_margin = the smallest relative distance of a draw from the boundary  */
+/* of the item it picked (orc_sample_margin) over all steps.  A non-finite  */
+/* entry read is EINVAL; a zero sketch is ESINGULAR.                        */
+/* ------------------------------------------------------------------------ */
+int orc_dmm_ca(const void *A, int dtype, int64_t m, int64_t n, int64_t lda, int r, int k, int l, int iters,
+               uint64_t seed, int64_t *I_out, int64_t *J_out, double *U_out, orc_info *info_out) {
+    orc_info info = {0, 0, 1, 0, 0, 0, 1.0, 0.0};
+    info.rank_found = r;
+    if (!A || !I_out || !J_out || !U_out || r < 1 || k < r || l < r || iters < 1 || m < 1 || n < 1 || lda < n ||
+        (int64_t)r > (m < n ? m : n) || dtype < 0 || dtype > 2) {
+        info.converged = 0;
+        if (info_out) *info_out = info;
+        return ORC_EINVAL;
+    }
+    double *P = (double *)malloc(sizeof(double) * (size_t)(m > n ? m : n) * (size_t)(k > l ? k : l));
+    double *dl = (double *)malloc(sizeof(double) * (size_t)l), *dk = (double *)malloc(sizeof(double) * (size_t)k);
+    double *M = (double *)malloc(sizeof(double) * (size_t)k * (size_t)l);
+    int st = ORC_OK;
+    orc_draw_uniform(seed, 8, n, l, J_out);
+    qsort(J_out, (size_t)l, sizeof(int64_t), cmp_i64);
+    for (int b = 0; b < l; b++) dl[b] = sqrt((double)n / (double)l);
+    double margin = 1.0;
+    for (int t = 0; t < iters && st == ORC_OK; t++) {
+        for (int64_t i = 0; i < m && st == ORC_OK; i++)
+            for (int b = 0; b < l; b++) {
+                const double w = orc_get(A, dtype, lda, i, J_out[b]);
+                if (!isfinite(w)) { st = ORC_EINVAL; break; }
+                P[i * l + b] = w * dl[b];
+            }
+        if (st == ORC_OK) st = orc_dmm_half(P, m, l, r, k, seed, 16 + 2 * (uint64_t)t, I_out, dk, &margin);
+        for (int64_t j = 0; j < n && st == ORC_OK; j++)
+            for (int a = 0; a < k; a++) {
+                const double w = orc_get(A, dtype, lda, I_out[a], j);
+                if (!isfinite(w)) { st = ORC_EINVAL; break; }
+                P[j * k + a] = dk[a] * w;
+            }
+        if (st == ORC_OK) st = orc_dmm_half(P, n, k, r, l, seed, 17 + 2 * (uint64_t)t, J_out, dl, &margin);
+        info.sweeps_run = t + 1;
+    }
+    for (int a = 0; a < k && st == ORC_OK; a++)
+        for (int b = 0; b < l; b++) {
+            const double w = orc_get(A, dtype, lda, I_out[a], J_out[b]);
+            if (!isfinite(w)) { st = ORC_EINVAL; break; }
+            M[a * l + b] = (dk[a] * w) * dl[b];
+        }
+    if (st == ORC_OK) {
+        int nr = r;
+        st = orc_pinv_trunc(M, k, l, r, U_out, &nr, &info.det_log_abs);
+        info.nucleus_rank = nr;
+        for (int b = 0; b < l; b++)
+            for (int a = 0; a < k; a++) U_out[b * k + a] = (dl[b] * U_out[b * k + a]) * dk[a];
+    }
+    info.min_margin = margin;
+    if (st == ORC_ESINGULAR) info.rank_found = 0;
+    if (st != ORC_OK) info.converged = 0;
+    free(P); free(dl); free(dk); free(M);
+    if (info_out) *info_out = info;
+    return st;
+}
