@@ -312,6 +312,36 @@ lra_status lra_cur_uniform_batched(const void *base, lra_dtype dt, const lra_blo
                                    int32_t k, int32_t l, uint64_t seed, int64_t *I_out, int64_t *J_out, double *U_out,
                                    lra_info *infos, hipStream_t stream);
 
+/* C-A whose step subalgorithm is the leverage-score sampling of DMM08 on
+ * every vertical and horizontal sketch (Section "Testing C-A acceleration of
+ * the algorithms of DMM08", Tables 7 and 8; sampling of Algorithm
+ * algcurlevsc by Algorithm algsmplex; scores of eq. eqlevsc with beta = 1
+ * taken of the sketch), for many blocks, one workgroup per block.  Block b
+ * (seed + b):
+ *   J = l uniform column draws with replacement (stream 8), D = sqrt(n / l);
+ *   iteration t = 0 .. iters - 1:
+ *     I = k draws by the rank-r row scores of the sketch W[:, J] D (stream
+ *       16 + 2t), Dbar = diag(1 / sqrt(k p_i));
+ *     J = l draws by the rank-r column scores of Dbar W[I, :] (stream
+ *       17 + 2t), D = diag(1 / sqrt(l p_j));
+ *   U = D M_r^+ Dbar, M = Dbar W[I, J] D (truncated pseudo-inverse as in
+ *   lra_cur_uniform_batched).
+ * Rank-r scores: p_i proportional to |row i of the sketch's r dominant left
+ * singular vectors|^2, those with squared singular value above 1e-13 times
+ * the largest; draws u_t = (x >> 11) 2^-53 (SplitMix64 output t), the first
+ * item whose running sum of scores exceeds u_t S.  I, J sorted ascending,
+ * duplicates kept.  Outputs (device) packed as for lra_cur_uniform_batched:
+ * I_out int64[count * k], J_out int64[count * l], U_out double[count * l * k];
+ * infos (device, may be NULL): status, sweeps_run = iters, nucleus_rank,
+ * det_log_abs of M.  A non-finite entry read gives that block LRA_EINVAL, a
+ * zero sketch LRA_ESINGULAR, with I = J = -1 and U = NaN.
+ * 1 <= r <= min(k, l, m, n) per block; k, l <= 64; iters >= 1.  Scratch:
+ * 16 max(m, n) bytes per workgroup of the stream's cached workspace.
+ * Asynchronous on `stream`. */
+lra_status lra_cur_dmm_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
+                               int32_t k, int32_t l, int32_t iters, uint64_t seed, int64_t *I_out, int64_t *J_out,
+                               double *U_out, lra_info *infos, hipStream_t stream);
+
 /* One far-field interaction block given by its two point sets: rows are the
  * m points starting at point x_off of the point buffer, columns the n points
  * starting at point y_off. */

@@ -110,6 +110,9 @@ def load() -> ct.CDLL:
         L.lra_cur_uniform_batched.argtypes = [P, ct.c_int, ct.POINTER(lra_block), i64, i32, i32, i32, ct.c_uint64,
                                               P, P, P, P, P]
         L.lra_cur_uniform_batched.restype = ct.c_int
+        L.lra_cur_dmm_batched.argtypes = [P, ct.c_int, ct.POINTER(lra_block), i64, i32, i32, i32, i32, ct.c_uint64,
+                                          P, P, P, P, P]
+        L.lra_cur_dmm_batched.restype = ct.c_int
         L.lra_cur_hadamard.argtypes = [P, ct.c_int, i64, i64, i64, i32, i32, ct.c_uint64, i32,
                                        ct.POINTER(lra_opts), P, P, P, P, P]
         L.lra_cur_hadamard.restype = ct.c_int
@@ -451,6 +454,53 @@ def lra_cur_uniform_batched(base, blocks, r: int, k: int, l: int, seed: int, *, 
     if st != LRA_OK:
         raise LraError(st, "lra_cur_uniform_batched")
     return out
+
+
+def lra_cur_dmm_batched(base, blocks, r: int, k: int, l: int, iters: int, seed: int, *, out: CurOut | None = None,
+                        stream=None) -> CurOut:
+    """C-A with DMM08 leverage-score sampling of every sketch for `count`
+    blocks of the flat device tensor `base` (descriptors as in
+    ``lra_cur_batched``): per block k rows, l columns (sorted, duplicates
+    kept) and U (l x k) after `iters` iterations.  Block b uses seed + b.
+    Asynchronous like ``lra_cur``."""
+    torch = _torch()
+    if base.dim() != 1 or not base.is_cuda:
+        raise ValueError("base must be a flat device tensor")
+    desc = np.ascontiguousarray(blocks, np.int64).reshape(-1, 4)
+    count = desc.shape[0]
+    if count:
+        off, m, n, ld = desc.T
+        end = off + (m - 1) * ld + n
+        if (off < 0).any() or (m < 1).any() or (n < 1).any() or (ld < n).any() or int(end.max()) > base.numel():
+            raise ValueError("block descriptors reach outside the base tensor")
+    dev = base.device
+    if out is None:
+        out = CurOut(torch.empty((count, k), dtype=torch.int64, device=dev),
+                     torch.empty((count, l), dtype=torch.int64, device=dev),
+                     torch.empty((count, l, k), dtype=torch.float64, device=dev),
+                     torch.empty(count * INFO_BYTES, dtype=torch.uint8, device=dev))
+    else:
+        _check_out(out, count * k, count * l, count * l * k, count, dev)
+    arr = (lra_block * max(count, 1))()
+    ct.memmove(arr, desc.ctypes.data, desc.nbytes)
+    st = load().lra_cur_dmm_batched(ct.c_void_p(base.data_ptr()), _dtype_code(base), arr, count, r, k, l, iters,
+                                    ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.c_void_p(out.I.data_ptr()),
+                                    ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
+                                    ct.c_void_p(out.info_raw.data_ptr()), _stream_ptr(stream))
+    if st != LRA_OK:
+        raise LraError(st, "lra_cur_dmm_batched")
+    return out
+
+
+def lra_cur_dmm(A, r: int, k: int, l: int, iters: int, seed: int, *, stream=None) -> CurOut:
+    """C-A with DMM08 sampling of one 2-D device tensor (row-major rows, unit
+    column stride): a batch of one block covering A."""
+    if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor with unit column stride")
+    m, n = A.shape
+    flat = A.as_strided(((m - 1) * A.stride(0) + n,), (1,))
+    out = lra_cur_dmm_batched(flat, [[0, m, n, A.stride(0)]], r, k, l, iters, seed, stream=stream)
+    return CurOut(out.I[0], out.J[0], out.U[0], out.info_raw)
 
 
 def lra_cur_uniform(A, r: int, k: int, l: int, seed: int, *, stream=None) -> CurOut:

@@ -836,6 +836,44 @@ lra_status lra_cur_uniform_batched(const void *base, lra_dtype dt, const lra_blo
     return LRA_OK;
 }
 
+lra_status lra_cur_dmm_batched(const void *base, lra_dtype dt, const lra_block *blocks, int64_t count, int32_t r,
+                               int32_t k, int32_t l, int32_t iters, uint64_t seed, int64_t *I_out, int64_t *J_out,
+                               double *U_out, lra_info *infos, hipStream_t stream) {
+    if (!base || !blocks || count < 0 || !I_out || !J_out || !U_out) return LRA_EINVAL;
+    if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
+    if (r < 1 || k < r || l < r || k > kRMax || l > kRMax || iters < 1 || count > (int64_t)INT32_MAX)
+        return LRA_EINVAL;
+    std::vector<BlockDesc> desc((size_t)count);
+    int64_t items = 1;
+    for (int64_t b = 0; b < count; b++) {
+        const lra_block &q = blocks[b];
+        if (q.offset < 0 || q.m < 1 || q.n < 1 || q.lda < q.n || r > q.m || r > q.n) return LRA_EINVAL;
+        desc[b] = BlockDesc{q.offset, q.m, q.n, q.lda};
+        items = std::max(items, std::max(q.m, q.n));
+    }
+    if (count == 0) return LRA_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Workspace *ws = nullptr;
+    lra_status st;
+    if ((st = get_ws(stream, &ws)) != LRA_OK) return st;
+    DevInfo dinfo;
+    if ((st = dev_info(ws->device, &dinfo)) != LRA_OK) return st;
+    int occ = lra::dmm_occupancy(dt);
+    if (occ < 1) occ = 1;
+    const int64_t grid = std::min<int64_t>((int64_t)dinfo.cus * occ, count);
+    void *scr = nullptr;
+    if ((st = ws_work(ws, stream, sizeof(double) * 2 * (size_t)items * (size_t)grid, &scr)) != LRA_OK) return st;
+    unsigned char *ddesc = nullptr;
+    if ((st = stage_desc(ws, stream, desc.data(), sizeof(BlockDesc) * count, &ddesc)) != LRA_OK) return st;
+    hipError_t e = lra::launch_dmm(dt, base, reinterpret_cast<const BlockDesc *>(ddesc), count, seed, r, k, l, iters,
+                                   static_cast<double *>(scr), items, (int)grid, I_out, J_out, U_out, infos, stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return LRA_EDEVICE;
+    }
+    return LRA_OK;
+}
+
 lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
                             const int64_t *I0, const int64_t *J0, int32_t k, int32_t l, uint64_t seed,
                             int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {

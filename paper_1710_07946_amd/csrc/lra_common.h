@@ -245,4 +245,196 @@ __device__ __forceinline__ void nucleus(SM &sm, double *ws, const Src &src, int 
     for (int e = tid; e < r * r; e += nthreads) U_out[e] = X[e];
 }
 
+// ---------------------------------------------------------------- truncated nucleus
+// Sum over the 16 lanes of a DPP row, every lane receiving the same value:
+// quad swaps, then the half-row and row mirrors pair equal partial sums, so
+// each step adds the same two numbers (in either order) in every lane.
+__device__ __forceinline__ double row_sum16(double v) {
+    v += __longlong_as_double(dpp64<kDppQuadSwap1>(__double_as_longlong(v)));
+    v += __longlong_as_double(dpp64<kDppQuadSwap2>(__double_as_longlong(v)));
+    v += __longlong_as_double(dpp64<kDppHalfMirror>(__double_as_longlong(v)));
+    v += __longlong_as_double(dpp64<kDppMirror>(__double_as_longlong(v)));
+    return v;
+}
+
+// One-sided Jacobi (Hestenes) sweeps on the nc columns (length nr <= 64) of
+// A, column-major in LDS, accumulating the rotations in V (nc x nc,
+// column-major, set to the identity by the caller): the oracle's round-robin
+// pair order (a dummy position for odd nc), a pair rotated unless
+// |a_p . a_q| <= nr eps sqrt(|a_p|^2 |a_q|^2), eps = 2^-52, or a column is
+// negligible (|a|^2 <= (nr eps)^2 times the largest squared column norm at
+// the sweep's start), or the sine is zero; sweeps until none rotates, at most
+// 60.  Each pair runs on the 16 lanes of a DPP row.  On return the columns of
+// A = A_in V are orthogonal.  One workgroup of kBlock threads, every thread
+// calls.
+__device__ __forceinline__ void jacobi_sweeps(double *A, double *V, int nr, int nc) {
+    const int tid = threadIdx.x;
+    __shared__ int s_rot;
+    __shared__ double s_nrm[kRMax];
+    __shared__ double s_big;
+    const int lp = nc + (nc & 1);
+    const int grp = tid / 16, j = tid % 16, ngrp = kBlock / 16;
+    const double tol = (double)nr * 0x1p-52;
+    for (int sweep = 0; sweep < 60 && nc > 1; sweep++) {
+        // squared column norms, then their maximum
+        for (int c = grp; c < nc; c += ngrp) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int u = 0; u < kRMax / 16; u++) {
+                const int i = j + 16 * u;
+                const double x = i < nr ? A[c * nr + i] : 0.0;
+                s2 += x * x;
+            }
+            s2 = row_sum16(s2);
+            if (j == 0) s_nrm[c] = s2;
+        }
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        if (tid == 0) {
+            double bg = 0.0;
+            for (int c = 0; c < nc; c++) bg = s_nrm[c] > bg ? s_nrm[c] : bg;
+            s_big = bg;
+        }
+        __syncthreads();
+        const double negl = tol * tol * s_big;
+        for (int t = 0; t < lp - 1; t++) {
+            for (int pr = grp; pr < lp / 2; pr += ngrp) {
+                int pc, qc;
+                jacobi_pair(t, pr, lp, pc, qc);
+                if (qc >= nc) continue;
+                const double *ap = A + pc * nr, *aq = A + qc * nr;
+                double x[kRMax / 16], y[kRMax / 16];
+#pragma unroll
+                for (int u = 0; u < kRMax / 16; u++) {
+                    const int i = j + 16 * u;
+                    x[u] = i < nr ? ap[i] : 0.0;
+                    y[u] = i < nr ? aq[i] : 0.0;
+                }
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int u = 0; u < kRMax / 16; u++) {
+                    al += x[u] * x[u];
+                    be += y[u] * y[u];
+                    ga += x[u] * y[u];
+                }
+                al = row_sum16(al);
+                be = row_sum16(be);
+                ga = row_sum16(ga);
+                if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+                if (al <= negl || be <= negl) continue;
+                const double ze = (be - al) / (2.0 * ga);
+                const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                if (sn == 0.0) continue;
+#pragma unroll
+                for (int u = 0; u < kRMax / 16; u++) {
+                    const int i = j + 16 * u;
+                    if (i < nr) {
+                        A[pc * nr + i] = cs * x[u] - sn * y[u];
+                        A[qc * nr + i] = sn * x[u] + cs * y[u];
+                    }
+                }
+                double vx[kRMax / 16], vy[kRMax / 16];
+#pragma unroll
+                for (int u = 0; u < kRMax / 16; u++) {
+                    const int i = j + 16 * u;
+                    vx[u] = i < nc ? V[pc * nc + i] : 0.0;
+                    vy[u] = i < nc ? V[qc * nc + i] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kRMax / 16; u++) {
+                    const int i = j + 16 * u;
+                    if (i < nc) {
+                        V[pc * nc + i] = cs * vx[u] - sn * vy[u];
+                        V[qc * nc + i] = sn * vx[u] + cs * vy[u];
+                    }
+                }
+                if (j == 0) s_rot = 1;
+            }
+            __syncthreads();
+        }
+        const int rot = *(volatile int *)&s_rot;
+        __syncthreads();
+        if (!rot) break;
+    }
+}
+
+// Nucleus of a k x l generator (Algorithm algcnnncl): U = G_r^+, the
+// pseudo-inverse of G's rank-r SVD truncation, G = src(I[a], J[b]).
+// One-sided Jacobi on the nc = min(k, l) columns (length nr = max(k, l)) of
+// G, or of G^T when G is wide, in the oracle's round-robin order (a dummy
+// position for odd nc; a pair rotated unless |a_p . a_q| <= nr eps
+// sqrt(|a_p|^2 |a_q|^2), eps = 2^-52, or a column is negligible, |a|^2 <=
+// (nr eps)^2 times the largest squared column norm at the sweep's start, or
+// the sine is zero; sweeps until none rotates, at most 60), each pair on
+// the 16 lanes of a DPP row; then the r largest sigma_j
+// above max(1e-14, nr eps) max sigma (ties to the lower j) are kept.  With B = A V
+// rotated: U = sum over kept j of v_j b_j^T / sigma_j^2 (G tall) or
+// b_j v_j^T / sigma_j^2 (G wide), l x k row-major.  ws: nr nc + nc^2
+// doubles, column-major, so that a pair's lanes read consecutive entries.
+// sm.nucleus_rank = the number kept, sm.logdet = the sum of their logs.
+// dl, dr: the generator is taken as (dl G) dr entrywise and U returned as
+// (dr U) dl, the scalar rescalings Dbar, D of a CUR by sampling; dla / dra
+// (optional) give one factor per row of G and per column instead.
+// One workgroup, every thread calls.
+template <class SM, class Src>
+__device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src, int k, int l, int r,
+                                              double *U_out, double dl = 1.0, double dr = 1.0,
+                                              const double *dla = nullptr, const double *dra = nullptr) {
+    const int tid = threadIdx.x;
+    const bool wide = k < l;
+    const int nr = wide ? l : k, nc = wide ? k : l;
+    double *A = ws, *V = ws + nr * nc;
+    __shared__ double s_sig[kRMax];
+    __shared__ int s_keep[kRMax];
+    for (int e = tid; e < nr * nc; e += kBlock) {
+        const int i = e % nr, c = e / nr;
+        const int ia = wide ? c : i, jb = wide ? i : c;  // row (I) and column (J) of the entry
+        A[e] = ((dla ? dla[ia] : dl) * src(sm.Iset[ia], sm.Jset[jb])) * (dra ? dra[jb] : dr);
+    }
+    for (int e = tid; e < nc * nc; e += kBlock) V[e] = (e / nc == e % nc) ? 1.0 : 0.0;
+    __syncthreads();
+    jacobi_sweeps(A, V, nr, nc);
+    for (int c = tid; c < nc; c += kBlock) {
+        double s2 = 0.0;
+        for (int i = 0; i < nr; i++) s2 += A[c * nr + i] * A[c * nr + i];
+        s_sig[c] = sqrt(s2);
+    }
+    __syncthreads();
+    if (tid < nc) {
+        double smax = 0.0;
+        int above = 0;
+        for (int c = 0; c < nc; c++) {
+            smax = s_sig[c] > smax ? s_sig[c] : smax;
+            above += (s_sig[c] > s_sig[tid] || (s_sig[c] == s_sig[tid] && c < tid)) ? 1 : 0;
+        }
+        // rank tolerance max(1e-14, max(k, l) eps): never below the level at
+        // which the rotation test leaves a column as negligible
+        const double thr = fmax(1e-14, (double)nr * 0x1p-52);
+        s_keep[tid] = (above < r && s_sig[tid] > thr * smax) ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int kept = 0;
+        double lv = 0.0;
+        for (int c = 0; c < nc; c++)
+            if (s_keep[c]) {
+                kept++;
+                lv += log(s_sig[c]);
+            }
+        sm.nucleus_rank = kept;
+        sm.logdet = lv;
+    }
+    for (int e = tid; e < l * k; e += kBlock) {
+        const int a = e / k, bb = e % k;
+        double acc = 0.0;
+        for (int c = 0; c < nc; c++)
+            if (s_keep[c])
+                acc += (wide ? A[c * nr + a] * V[c * nc + bb] : V[c * nc + a] * A[c * nr + bb]) /
+                       (s_sig[c] * s_sig[c]);
+        U_out[e] = ((dra ? dra[a] : dr) * acc) * (dla ? dla[bb] : dl);
+    }
+    __syncthreads();
+}
+
 }  // namespace lra

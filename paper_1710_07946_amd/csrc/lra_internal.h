@@ -101,6 +101,13 @@ hipError_t launch_adjoint(int64_t count, int64_t m, int64_t n, int r, const doub
                           const int32_t *corder, const double *aval, double *loss, double *dC, double *dR,
                           double *dG, void *scratch, int32_t *status, hipStream_t stream);
 hipError_t launch_xlat(uint64_t *buf, int rounds, uint64_t limit, hipStream_t stream);
+// C-A with DMM08 sampling of every sketch (lra_dmm.hip): one workgroup per
+// block; scratch holds 2 scratch_items doubles per workgroup of the grid.
+size_t dmm_lds_bytes();
+int dmm_occupancy(int dtype);
+hipError_t launch_dmm(int dtype, const void *base, const BlockDesc *blocks, int64_t count, uint64_t seed, int r, int k,
+                      int l, int iters, double *scratch, int64_t scratch_items, int grid, int64_t *I_out,
+                      int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
 size_t static_lds_bytes();
 __global__ void zero_u32_kernel(unsigned *p, int n);
 

@@ -20,6 +20,11 @@ blocks; see the experiments section and the FMM section of the paper):
   Laplacian from the unit circle to the circle of radius 2 (the integral-
   equation input of the tests of the pre-processors), normalized to unit
   spectral norm; deterministic.
+* ``graded_lowrank``      X diag(s) Y + noise with Gaussian factors and the
+  column scales s_a = 10^(-2 a / (r - 1)) (numerical rank r, singular values
+  spread over two decades), FP32, the stand-in for the integral-equation
+  inputs of the tests of C-A with DMM08 sampling (1000 x 1000, numerical
+  rank up to 25, Tables 7 and 8).
 * ``decaying_spectrum``   tall matrix with 64 unit singular values followed by
   an i^-2 decay floored at 1e-7 (generated on the device: its 8.8 TFLOP
   construction is out of reach of a host).
@@ -149,6 +154,37 @@ def laplacian_single_layer(n: int, quad: int = 8, dtype=np.float64) -> np.ndarra
     c /= np.abs(np.fft.fft(c)).max()
     idx = (np.arange(n)[None, :] - np.arange(n)[:, None]) % n
     return np.ascontiguousarray(c[idx].astype(dtype))
+
+
+def graded_lowrank(m: int, n: int, r: int, noise: float, seed: int, dtype=np.float32) -> np.ndarray:
+    """X diag(s) Y / ||X diag(s) Y||_F + N(0, noise^2), X (m x r), Y (r x n)
+    standard Gaussian, s_a = 10^(-2 a / (r - 1)) (s = 1 for r = 1)."""
+    g = np.random.default_rng(seed)
+    s = 10.0 ** (-2.0 * np.arange(r) / max(r - 1, 1))
+    A = (g.standard_normal((m, r)) * s) @ g.standard_normal((r, n))
+    A /= np.linalg.norm(A)
+    A += noise * g.standard_normal((m, n))
+    return np.ascontiguousarray(A.astype(dtype))
+
+
+def graded_lowrank_batch_device(count: int, m: int, n: int, r: int, noise: float, seed0: int, device):
+    """`count` ``graded_lowrank`` blocks (FP32) generated on a GPU by torch's
+    device generator (block b seeded with seed0 + b), stored back to back in a
+    flat tensor.  Returns (flat device tensor, descriptors int64[count, 4])."""
+    import torch
+    desc = np.array([(b * m * n, m, n, n) for b in range(count)], np.int64)
+    flat = torch.empty(count * m * n, dtype=torch.float32, device=device)
+    s = torch.tensor(10.0 ** (-2.0 * np.arange(r) / max(r - 1, 1)), dtype=torch.float64, device=device)
+    g = torch.Generator(device=device)
+    for b in range(count):
+        g.manual_seed(seed0 + b)
+        X = torch.randn(m, r, generator=g, device=device, dtype=torch.float64) * s
+        Y = torch.randn(r, n, generator=g, device=device, dtype=torch.float64)
+        A = X @ Y
+        A /= torch.linalg.norm(A)
+        A += noise * torch.randn(m, n, generator=g, device=device, dtype=torch.float64)
+        flat[b * m * n:(b + 1) * m * n] = A.to(torch.float32).reshape(-1)
+    return flat, desc
 
 
 def decaying_spectrum_sigma(n: int, lead: int = 64, floor: float = 1e-7) -> np.ndarray:
