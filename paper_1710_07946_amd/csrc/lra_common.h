@@ -265,9 +265,11 @@ __device__ __forceinline__ double row_sum16(double v) {
 // negligible (|a|^2 <= (nr eps)^2 times the largest squared column norm at
 // the sweep's start), or the sine is zero; sweeps until none rotates, at most
 // 60.  Each pair runs on the 16 lanes of a DPP row.  On return the columns of
-// A = A_in V are orthogonal.  One workgroup of kBlock threads, every thread
-// calls.
-__device__ __forceinline__ void jacobi_sweeps(double *A, double *V, int nr, int nc) {
+// A = A_in V are orthogonal; returns the number of sweeps run.  pair_floor >
+// 0 also leaves alone a pair whose two squared norms are both at most
+// pair_floor times that largest one (for callers that need only the dominant
+// columns).  One workgroup of kBlock threads, every thread calls.
+__device__ __forceinline__ int jacobi_sweeps(double *A, double *V, int nr, int nc, double pair_floor = 0.0) {
     const int tid = threadIdx.x;
     __shared__ int s_rot;
     __shared__ double s_nrm[kRMax];
@@ -275,7 +277,8 @@ __device__ __forceinline__ void jacobi_sweeps(double *A, double *V, int nr, int 
     const int lp = nc + (nc & 1);
     const int grp = tid / 16, j = tid % 16, ngrp = kBlock / 16;
     const double tol = (double)nr * 0x1p-52;
-    for (int sweep = 0; sweep < 60 && nc > 1; sweep++) {
+    int sweep = 0;
+    for (; sweep < 60 && nc > 1; sweep++) {
         // squared column norms, then their maximum
         for (int c = grp; c < nc; c += ngrp) {
             double s2 = 0.0;
@@ -296,7 +299,7 @@ __device__ __forceinline__ void jacobi_sweeps(double *A, double *V, int nr, int 
             s_big = bg;
         }
         __syncthreads();
-        const double negl = tol * tol * s_big;
+        const double negl = tol * tol * s_big, small = pair_floor * s_big;
         for (int t = 0; t < lp - 1; t++) {
             for (int pr = grp; pr < lp / 2; pr += ngrp) {
                 int pc, qc;
@@ -322,6 +325,7 @@ __device__ __forceinline__ void jacobi_sweeps(double *A, double *V, int nr, int 
                 ga = row_sum16(ga);
                 if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
                 if (al <= negl || be <= negl) continue;
+                if (al <= small && be <= small) continue;
                 const double ze = (be - al) / (2.0 * ga);
                 const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
                 const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -357,6 +361,7 @@ __device__ __forceinline__ void jacobi_sweeps(double *A, double *V, int nr, int 
         __syncthreads();
         if (!rot) break;
     }
+    return nc > 1 ? (sweep < 60 ? sweep + 1 : 60) : 0;
 }
 
 // Nucleus of a k x l generator (Algorithm algcnnncl): U = G_r^+, the

@@ -30,12 +30,38 @@
 #include "lra_common.h"
 
 namespace lra {
+
+// Built with -DLRA_TRACE, workgroup 0 adds the wall-clock ticks of each phase
+// (and the Jacobi sweeps and half-steps) to g_dmmtr; lra_trace_dmm() copies
+// them out and clears them.
+#ifdef LRA_TRACE
+__device__ uint64_t g_dmmtr[8];
+#define DMM_TIC(v) const uint64_t v = (blockIdx.x == 0 && threadIdx.x == 0) ? wall_clock64() : 0
+#define DMM_TOC(slot, v) \
+    do { if (blockIdx.x == 0 && threadIdx.x == 0) g_dmmtr[slot] += wall_clock64() - v; } while (0)
+#define DMM_CNT(slot, n) \
+    do { if (blockIdx.x == 0 && threadIdx.x == 0) g_dmmtr[slot] += (n); } while (0)
+#else
+#define DMM_TIC(v) ((void)0)
+#define DMM_TOC(slot, v) ((void)0)
+#define DMM_CNT(slot, n) ((void)0)
+#endif
+
 namespace {
 
-constexpr int kDmmChunk = 64;             // sketch rows staged per Gram pass
+constexpr int kDmmChunk = 64;             // sketch rows staged in LDS at a time
 constexpr int kDmmPs = kRMax + 1;         // their LDS row stride (doubles)
-constexpr int kDmmProj = 16;              // kept directions projected per pass over an item
-constexpr int kDmmGram = kRMax * kRMax / kBlock;  // Gram entries per thread
+typedef double v4d __attribute__((ext_vector_type(4)));
+// Pairs of Gram columns whose norms are both below 1e-10 of the largest
+// (eigenvalues below 1e-10 lambda_max) are not rotated against each other:
+// they can mix only directions far below the kept ones.
+constexpr double kDmmPairFloor = 1e-20;
+
+// FP64 MFMA 16x16x4: A operand of lane l is A[l % 16][l / 16], B operand
+// B[l / 16][l % 16], output v is D[l / 16 + 4 v][l % 16].
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 struct DmmSmem {
     int64_t Iset[kRMax], Jset[kRMax];
@@ -57,6 +83,28 @@ __device__ __forceinline__ double sketch_entry(const DmmSmem &sm, const DenseSrc
     return ROWS ? src(item, sm.Jset[c]) * sm.dl[c] : sm.dk[c] * src(sm.Iset[c], item);
 }
 
+// Stage items i0 .. i0 + 63 of the sketch into Pc (row-major, stride
+// kDmmPs), zero beyond the last item (up to a multiple of 4) and in columns
+// w .. wp - 1; returns whether a staged entry is not finite.
+template <bool ROWS, typename T>
+__device__ __forceinline__ int stage_chunk(const DmmSmem &sm, const DenseSrc<T> &src, double *Pc, int64_t i0,
+                                           int64_t items, int w, int wp) {
+    const int nb = items - i0 < kDmmChunk ? (int)(items - i0) : kDmmChunk, nb4 = (nb + 3) & ~3;
+    int bad = 0;
+    for (int e = threadIdx.x; e < nb4 * wp; e += kBlock) {
+        // row step: a row's entries side by side; column step: a selected
+        // row's run of consecutive columns side by side
+        const int it = ROWS ? e / wp : e % nb4, c = ROWS ? e % wp : e / nb4;
+        double x = 0.0;
+        if (it < nb && c < w) {
+            x = sketch_entry<ROWS>(sm, src, i0 + it, c);
+            bad |= !isfinite(x);
+        }
+        Pc[it * kDmmPs + c] = x;
+    }
+    return bad;
+}
+
 // One half-step (see the file comment).  ROWS: items = rows of W, w = l,
 // draws k rows into sm.Iset / sm.dk; else items = columns, w = k, draws l
 // columns into sm.Jset / sm.dl.  q, cdf: `items` doubles of this
@@ -66,50 +114,57 @@ __device__ __forceinline__ void dmm_half(DmmSmem &sm, double *lds, const DenseSr
                                          int cnt, uint64_t seed, uint64_t stream, double *q, double *cdf) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     double *A = lds, *V = lds + kRMax * kRMax, *Pc = lds + 2 * kRMax * kRMax;
-    // 1. Gram matrix
-    double acc[kDmmGram];
-#pragma unroll
-    for (int u = 0; u < kDmmGram; u++) acc[u] = 0.0;
+    double *Ps = Pc + kDmmChunk * kDmmPs;  // per-tile score partials, 4 x kDmmChunk
+    // 1. Gram matrix on the FP64 matrix cores: 16 x 16 tiles (ta, tb) of G,
+    // tile t = wave + 8 u, each product over 4 staged items
+    DMM_TIC(t0);
+    const int nt = (w + 15) / 16, wp = 16 * nt;
+    v4d acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
     int bad = 0;
     for (int64_t i0 = 0; i0 < items; i0 += kDmmChunk) {
-        const int nb = items - i0 < kDmmChunk ? (int)(items - i0) : kDmmChunk;
-        for (int e = tid; e < nb * w; e += kBlock) {
-            // row step: a row's w entries side by side; column step: a
-            // selected row's run of consecutive columns side by side
-            const int it = ROWS ? e / w : e % nb, c = ROWS ? e % w : e / nb;
-            const double x = sketch_entry<ROWS>(sm, src, i0 + it, c);
-            bad |= !isfinite(x);
-            Pc[it * kDmmPs + c] = x;
-        }
+        bad |= stage_chunk<ROWS>(sm, src, Pc, i0, items, w, wp);
         __syncthreads();
+        const int nb4 = ((items - i0 < kDmmChunk ? (int)(items - i0) : kDmmChunk) + 3) & ~3;
 #pragma unroll
-        for (int u = 0; u < kDmmGram; u++) {
-            const int e = tid + u * kBlock;
-            if (e < w * w) {
-                const int a = e % w, b = e / w;
-                double s = acc[u];
-                for (int it = 0; it < nb; it++) s += Pc[it * kDmmPs + a] * Pc[it * kDmmPs + b];
-                acc[u] = s;
+        for (int u = 0; u < 2; u++) {
+            const int t = wv + 8 * u;
+            if (t < nt * nt) {
+                const double *pa = Pc + (lane >> 4) * kDmmPs + 16 * (t % nt) + (lane & 15);
+                const double *pb = Pc + (lane >> 4) * kDmmPs + 16 * (t / nt) + (lane & 15);
+                v4d c = acc[u];
+                for (int it = 0; it < nb4; it += 4) c = mfma4(pa[it * kDmmPs], pb[it * kDmmPs], c);
+                acc[u] = c;
             }
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < kDmmGram; u++) {
-        const int e = tid + u * kBlock;
-        if (e < w * w) {
-            A[e] = acc[u];  // column b, row a (G is symmetric)
-            V[e] = (e / w == e % w) ? 1.0 : 0.0;
+    for (int u = 0; u < 2; u++) {
+        const int t = wv + 8 * u;
+        if (t < nt * nt) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const int a = 16 * (t % nt) + (lane >> 4) + 4 * v, bcol = 16 * (t / nt) + (lane & 15);
+                if (a < w && bcol < w) A[bcol * w + a] = acc[u][v];  // column bcol, row a
+            }
         }
     }
+    for (int e = tid; e < w * w; e += kBlock) V[e] = (e / w == e % w) ? 1.0 : 0.0;
     bad = __syncthreads_or(bad);
     if (bad) {
         if (tid == 0) sm.status = LRA_EINVAL;
         __syncthreads();
         return;
     }
+    DMM_TOC(0, t0);
     // 2. eigenvectors of G
-    jacobi_sweeps(A, V, w, w);
+    DMM_TIC(t1);
+    const int nsw = jacobi_sweeps(A, V, w, w, kDmmPairFloor);
+    DMM_TOC(1, t1);
+    DMM_CNT(6, nsw);
+    DMM_CNT(7, 1);
+    (void)nsw;
+    DMM_TIC(t2);
     // 3. the kept directions, largest first
     for (int c = tid; c < w; c += kBlock) {
         double s2 = 0.0;
@@ -138,27 +193,48 @@ __device__ __forceinline__ void dmm_half(DmmSmem &sm, double *lds, const DenseSr
     __syncthreads();
     const int nk = sm.nkeep;
     if (nk == 0) return;
-    // scores and their running sums, kBlock items at a time
-    for (int64_t i0 = 0; i0 < items; i0 += kBlock) {
-        const int64_t i = i0 + tid;
-        double s = 0.0;
-        if (i < items) {
-            for (int t0 = 0; t0 < nk; t0 += kDmmProj) {
-                double pr[kDmmProj];
+    // scores of kDmmChunk staged items at a time on the matrix cores: the
+    // projections P_i . v_a of 16 items x 16 kept directions per tile, squared, divided by
+    // lambda_a and summed over the tile's directions (the 16 lanes of a DPP
+    // row), then over the direction tiles in order; tile t: items
+    // 16 (t % 4), directions 16 (t / 4), waves taking tiles in turn
+    const int ndt = (nk + 15) / 16;
+    for (int64_t i0 = 0; i0 < items; i0 += kDmmChunk) {
+        stage_chunk<ROWS>(sm, src, Pc, i0, items, w, wp);
+        __syncthreads();
+        for (int t = wv; t < 4 * ndt; t += kBlock / kWave) {
+            const int it0 = 16 * (t % 4), d0 = 16 * (t / 4);
+            const int dj = d0 + (lane & 15);
+            const int vcol = dj < nk ? sm.keep[dj] : 0;
+            const double *pa = Pc + (it0 + (lane & 15)) * kDmmPs + (lane >> 4);
+            const double *pv = V + vcol * w + (lane >> 4);
+            v4d c = {0.0, 0.0, 0.0, 0.0};
+            for (int c0 = 0; c0 < wp; c0 += 4) {
+                const bool in = c0 + (lane >> 4) < w && dj < nk;
+                c = mfma4(pa[c0], in ? pv[c0] : 0.0, c);
+            }
+            const double il = dj < nk ? 1.0 / sm.lam[vcol] : 0.0;
 #pragma unroll
-                for (int t = 0; t < kDmmProj; t++) pr[t] = 0.0;
-                for (int c = 0; c < w; c++) {
-                    const double x = sketch_entry<ROWS>(sm, src, i, c);
-#pragma unroll
-                    for (int t = 0; t < kDmmProj; t++)
-                        if (t0 + t < nk) pr[t] += x * V[sm.keep[t0 + t] * w + c];
-                }
-#pragma unroll
-                for (int t = 0; t < kDmmProj; t++)
-                    if (t0 + t < nk) s += pr[t] * pr[t] / sm.lam[sm.keep[t0 + t]];
+            for (int v = 0; v < 4; v++) {
+                const double y = row_sum16(c[v] * c[v] * il);
+                if ((lane & 15) == 0) Ps[(t / 4) * kDmmChunk + it0 + (lane >> 4) + 4 * v] = y;
             }
         }
-        // inclusive scan: within the wavefront, then the wavefront totals in order
+        __syncthreads();
+        if (tid < kDmmChunk && i0 + tid < items) {
+            double sc = 0.0;
+            for (int dt = 0; dt < ndt; dt++) sc += Ps[dt * kDmmChunk + tid];
+            q[i0 + tid] = sc;
+        }
+        __syncthreads();
+    }
+    __threadfence_block();
+    __syncthreads();
+    // running sums in item order: a wavefront scan per kBlock items, the
+    // wavefront totals added in order
+    for (int64_t i0 = 0; i0 < items; i0 += kBlock) {
+        const int64_t i = i0 + tid;
+        const double s = i < items ? q[i] : 0.0;
         double incl = s;
 #pragma unroll
         for (int off = 1; off < kWave; off <<= 1) {
@@ -169,10 +245,7 @@ __device__ __forceinline__ void dmm_half(DmmSmem &sm, double *lds, const DenseSr
         __syncthreads();
         double base = sm.carry;
         for (int v = 0; v < wv; v++) base += sm.wtot[v];
-        if (i < items) {
-            q[i] = s;
-            cdf[i] = base + incl;
-        }
+        if (i < items) cdf[i] = base + incl;
         __syncthreads();
         if (tid == kBlock - 1) {
             double c = sm.carry;
@@ -182,7 +255,9 @@ __device__ __forceinline__ void dmm_half(DmmSmem &sm, double *lds, const DenseSr
         __threadfence_block();
         __syncthreads();
     }
+    DMM_TOC(2, t2);
     // 4. draws, rescaling and sort (one wavefront)
+    DMM_TIC(t3);
     if (tid < kWave) {
         const double S = sm.carry;
         int64_t idx = INT64_MAX;
@@ -215,6 +290,7 @@ __device__ __forceinline__ void dmm_half(DmmSmem &sm, double *lds, const DenseSr
         }
     }
     __syncthreads();
+    DMM_TOC(3, t3);
 }
 
 template <typename T>
@@ -250,7 +326,10 @@ __global__ void __launch_bounds__(kBlock) ca_dmm_kernel(const T *base, const Blo
         const int st = sm.status;
         double *const U = U_out + b * (int64_t)l * k;
         if (st == LRA_OK) {
+            DMM_TIC(t4);
             nucleus_trunc(sm, lds, src, k, l, r, U, 1.0, 1.0, sm.dk, sm.dl);
+            DMM_TOC(4, t4);
+            DMM_CNT(5, 1);
         } else {
             for (int e = tid; e < l * k; e += kBlock) U[e] = __builtin_nan("");
         }
@@ -288,7 +367,9 @@ hipError_t launch_dmm_t(const void *base, const BlockDesc *blocks, int64_t count
 
 }  // namespace
 
-size_t dmm_lds_bytes() { return sizeof(double) * (2 * (size_t)kRMax * kRMax + (size_t)kDmmChunk * kDmmPs); }
+size_t dmm_lds_bytes() {
+    return sizeof(double) * (2 * (size_t)kRMax * kRMax + (size_t)kDmmChunk * kDmmPs + 4 * (size_t)kDmmChunk);
+}
 
 int dmm_occupancy(int dtype) {
     int blocks = 0;
@@ -320,3 +401,12 @@ hipError_t launch_dmm(int dtype, const void *base, const BlockDesc *blocks, int6
 }
 
 }  // namespace lra
+
+#ifdef LRA_TRACE
+extern "C" int lra_trace_dmm(uint64_t *host) {
+    if (hipMemcpyFromSymbol(host, HIP_SYMBOL(lra::g_dmmtr), sizeof(uint64_t) * 8) != hipSuccess) return -1;
+    uint64_t z[8] = {0};
+    if (hipMemcpyToSymbol(HIP_SYMBOL(lra::g_dmmtr), z, sizeof(z)) != hipSuccess) return -1;
+    return 8;
+}
+#endif
