@@ -100,7 +100,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true",
                     help="time only the headline LRA (skip batched, residual and adjoint lines)")
-    ap.add_argument("--only", choices=["batched", "points", "cynical", "adjoint", "tall", "residual", "starts"],
+    ap.add_argument("--only", choices=["batched", "points", "cynical", "adjoint", "tall", "residual", "starts", "dmm"],
                     default=None,
                     help="time one secondary line alone and print it (for profiling)")
     ap.add_argument("--no-plain-loop", action="store_true",
@@ -134,9 +134,9 @@ def main():
     from paper_1710_07946_amd import workloads
 
     lra.load()
-    if args.only in ("batched", "points", "cynical", "adjoint", "tall"):
+    if args.only in ("batched", "points", "cynical", "adjoint", "tall", "dmm"):
         fn = {"batched": bench_batched, "points": bench_points, "cynical": bench_cynical, "adjoint": bench_adjoint,
-              "tall": bench_tall}[args.only]
+              "tall": bench_tall, "dmm": bench_dmm}[args.only]
         print(json.dumps({args.only: fn(lra, workloads, torch, np, args)}), flush=True)
         return
     t0 = time.time()
@@ -267,6 +267,7 @@ def main():
             "adjoint_2048": bench_adjoint(lra, workloads, torch, np, args),
             "tall_65536x8192": bench_tall(lra, workloads, torch, np, args),
             "cynical_20000x20000_r16": bench_cynical(lra, workloads, torch, np, args),
+            "dmm08_ca_1000x1000": bench_dmm(lra, workloads, torch, np, args),
         }
     print(json.dumps(rec), flush=True)
 
@@ -301,11 +302,13 @@ def bench_fourier_start(lra, torch, np, A, args):
 
 
 def bench_leverage(lra, torch, np, A, args):
-    """Refinement of the headline CUR by its leverage scores: k = l = 64 rows
-    and columns drawn by the scores of the r = 50 C-A CUR's own factors,
-    U = D M_50^+ Dbar (the crude CUR from the headline call, not timed)."""
+    """Refinement of the headline CUR by its leverage scores: k = l = 4r = 200
+    rows and columns drawn by the scores of the r = 50 C-A CUR's own factors,
+    U = D M_50^+ Dbar (the crude CUR from the headline call, not timed).
+    4r is far below the sample sizes of Theorem thdmm (which grow with
+    r^2 / eps^2); the line reports what it reaches."""
     base = lra.lra_cur(A, RANK, SWEEPS, SEED, preprocess=lra.LRA_PRE_ASRHT, ah_depth=3, ah_samples=SAMPLES)
-    k = 64
+    k = 4 * RANK
     out = lra.lra_cur_leverage(A, base.I, base.J, k, k, SEED)
     ms = _time_events(torch, lambda: lra.lra_cur_leverage(A, base.I, base.J, k, k, SEED, out=out),
                       max(2, args.steps // 5), 1)
@@ -314,8 +317,8 @@ def bench_leverage(lra, torch, np, A, args):
     base_mom = lra.lra_residual(A, base.I, base.J, base.U).cpu().numpy()
     nbytes = 4 * (RANK * (M + N) + k * k)  # C and R read once, the generator
     gbs = nbytes / (ms * 1e-3) / 1e9
-    return {"workload": "headline matrix; leverage scores of its r=50 C-A CUR's factors, k=l=64 draws, "
-                        "rank-50 canonical nucleus",
+    return {"workload": "headline matrix; leverage scores of its r=50 C-A CUR's factors, k=l=200 draws (4r, "
+                        "below the Theorem thdmm sample sizes), rank-50 canonical nucleus",
             "lras_per_s": 1e3 / ms, "ms_per_lra": ms, "status": info["status"],
             "rel_fro_err": float(np.sqrt(mom[1] / mom[3])), "crude_rel_fro_err": float(np.sqrt(base_mom[1] / base_mom[3])),
             "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -655,6 +658,60 @@ def bench_adjoint(lra, workloads, torch, np, args):
                      "frac": gbs / HBM_PEAK_GBS, "traffic": counted_traffic("adjoint")},
         "useful_bytes_per_launch": nbytes,
     }
+
+
+def bench_dmm(lra, workloads, torch, np, args):
+    """C-A with DMM08 leverage-score sampling of every sketch (the C-A tests
+    of Tables 7 and 8: 1000 x 1000 inputs of low numerical rank, eight
+    iterations, k = l = 4r, 2r, r) on 256 blocks 1000 x 1000 FP32 of
+    numerical rank 16 (graded Gaussian factors + N(0, 1e-6^2)), one launch
+    per k; r = 16.  The k = l = 64 launch is the line's figure."""
+    count, m, n, r, iters, seed = 256, 1000, 1000, 16, 8, 3000
+    t0 = time.time()
+    base, desc = workloads.graded_lowrank_batch_device(count, m, n, r, 1e-6, 8000, "cuda")
+    torch.cuda.synchronize()
+    print("# dmm blocks generated in %.1f s" % (time.time() - t0), file=sys.stderr, flush=True)
+    res = {"workload": "256 blocks 1000x1000 fp32, X diag(10^(-2a/15)) Y + N(0,1e-6^2) (numerical rank 16); "
+                       "r=16, 8 iterations of DMM08 row / column sampling on the sketches; k=l in {64, 32, 16}"}
+    host = None
+    for k in (64, 32, 16):
+        out = lra.lra_cur_dmm_batched(base, desc, r, k, k, iters, seed)
+        ms = _time_events(torch, lambda: lra.lra_cur_dmm_batched(base, desc, r, k, k, iters, seed, out=out),
+                          max(2, args.steps // 10), 1)
+        infos = out.info()
+        I, J, U = out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy()
+        if host is None:
+            host = base[:8 * m * n].cpu().numpy().reshape(8, m, n).astype(np.float64)
+        errs = []
+        for b in range(8):
+            X = host[b][:, J[b]] @ U[b] @ host[b][I[b]]
+            errs.append(float(np.linalg.norm(host[b] - X) / np.linalg.norm(host[b])))
+        # FP64 flops on the matrix cores per LRA: the Gram matrix (2 items w^2)
+        # and the projections (2 items w r) of each half-step
+        flops = count * iters * (2.0 * m * k * k + 2.0 * m * k * r + 2.0 * n * k * k + 2.0 * n * k * r)
+        tfs = flops / (ms * 1e-3) / 1e12
+        line = {"lras_per_s": count / (ms * 1e-3), "ms_per_batch": ms,
+                "failed_blocks": sum(1 for i in infos if i["status"] != 0),
+                "median_rel_fro_err_8_blocks": float(np.median(errs))}
+        if k == 64:
+            line["roofline"] = {"bound": "mfma", "achieved": tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                                "frac": tfs / FP64_PEAK_TFS, "traffic": None}
+            line["useful_bytes_per_batch"] = count * (iters * 2 * (m * k + k * n) * 4 + k * k * 4)
+        res["k%d" % k] = line
+    if not args.no_cpu_baseline:
+        import oracle
+        nth = os.cpu_count() or 1
+        jobs = [(lambda b=b: oracle.dmm_ca(host[b].astype(np.float32), r, 64, 64, iters, seed + b))
+                for b in range(8)]
+        d1, t1 = oracle_rate(jobs[:2], 1, args.cpu_seconds / 2)
+        dn, tn = oracle_rate(jobs, nth, args.cpu_seconds / 2)
+        res["cpu_baseline"] = {"value": dn / tn, "unit": "LRAs/s", "cores": nth, "kind": "oracle",
+                               "value_1_core": d1 / t1,
+                               "sample": "%d blocks (k=l=64) on %d threads, %d on 1 thread" % (dn, nth, d1),
+                               "host": host_info()}
+    del base
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_cynical(lra, workloads, torch, np, args):

@@ -279,12 +279,13 @@ int32_t lra_batch_get_rules(lra_batch_rule *out, int32_t cap);
  * Outputs (device): I_out int64[k], J_out int64[l], U_out double[l * k]
  * (row-major, W ~ W[:, J] U W[I, :]); info (device, may be NULL):
  * nucleus_rank, det_log_abs = log of the kept singular values' product of M.
- * 1 <= r <= min(m, n, 64); r <= k, l <= 64.  The call copies I0 and J0 to
+ * 1 <= r <= min(m, n, 64); r <= k, l <= 256.  The call copies I0 and J0 to
  * the host and synchronizes `stream` to check them (LRA_EINVAL when out of
  * range); a non-finite entry read gives status LRA_EINVAL, a rank-deficient
  * factor LRA_ESINGULAR (in info), with I = J = -1 and U = NaN.  Scratch:
- * 8 (2 + r) (n + m) bytes + 128 KiB of the stream's cached workspace (the
- * FP64 copy of C and R, scores, running sums, Gram matrices and factors). */
+ * 8 (2 + r) (n + m) bytes + 1152 KiB of the stream's cached workspace (the
+ * FP64 copy of C and R, scores, running sums, Gram matrices and factors,
+ * and the nucleus's rotations when k or l exceeds 64). */
 lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t lda, int32_t r,
                             const int64_t *I0, const int64_t *J0, int32_t k, int32_t l, uint64_t seed,
                             int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream);

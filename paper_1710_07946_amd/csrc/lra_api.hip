@@ -22,6 +22,7 @@ using lra::PtsDesc;
 using lra::CAConfig;
 using lra::kBlock;
 using lra::kLMax;
+using lra::kSMax;
 using lra::kRMax;
 using lra::TeamWs;
 
@@ -879,8 +880,8 @@ lra_status lra_cur_leverage(const void *W, lra_dtype dt, int64_t m, int64_t n, i
                             int64_t *I_out, int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
     if (!W || !I0 || !J0 || !I_out || !J_out || !U_out) return LRA_EINVAL;
     if (dt != LRA_F64 && dt != LRA_F32 && dt != LRA_BF16) return LRA_EINVAL;
-    if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n || k < r || l < r || k > kRMax ||
-        l > kRMax)
+    if (m < 1 || n < 1 || lda < n || r < 1 || r > kRMax || r > m || r > n || k < r || l < r || k > kSMax ||
+        l > kSMax)
         return LRA_EINVAL;
     // the crude LRA's sets are read back and checked before any kernel reads
     // the matrix through them

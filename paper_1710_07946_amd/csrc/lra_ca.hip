@@ -1855,14 +1855,19 @@ __global__ void __launch_bounds__(kBlock) ca_uniform_kernel(const T *base, const
 // (n + m), P (r x (n + m)); flags: [0] non-finite entry, [1] Gram not
 // positive definite.
 struct LevSmem {
-    int64_t Iset[kRMax], Jset[kRMax];
-    int64_t I0[kRMax], J0[kRMax];
-    double dk[kRMax], dl[kRMax];
+    int64_t Iset[kSMax], Jset[kSMax];
+    int64_t tmp[2 * kSMax];
+    double dk[kSMax], dl[kSMax];
     int32_t nucleus_rank;
     double logdet;
 };
 
 __device__ __forceinline__ double *lev_scores(double *ws) { return ws + 4 * kRMax * kRMax; }
+// Jacobi work space of the nucleus beyond 64 rows or columns: after the
+// scores, running sums and the FP64 factors (2 kSMax^2 doubles).
+__device__ __forceinline__ double *lev_jacobi_ws(double *ws, int64_t m, int64_t n, int r) {
+    return lev_scores(ws) + (size_t)(2 + r) * (size_t)(n + m);
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) lev_gather_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int r,
@@ -2073,20 +2078,26 @@ __global__ void __launch_bounds__(kBlock) lev_pick_kernel(const T *A, int64_t m,
             else sm.Iset[t] = lo;
         }
         __syncthreads();
-        if (tid < kWave) {
-            sort_set_wave(sm.Jset, l);
-            sort_set_wave(sm.Iset, k);
-        }
-        __syncthreads();
+        sort_two_sets(sm.Jset, l, sm.Iset, k, sm.tmp);
         if (tid < l) sm.dl[tid] = 1.0 / sqrt(((double)l * q[sm.Jset[tid]]) / cdf[n - 1]);
-        if (tid >= kRMax && tid < kRMax + k)
-            sm.dk[tid - kRMax] = 1.0 / sqrt(((double)k * q[n + sm.Iset[tid - kRMax]]) / cdf[n + m - 1]);
+        if (tid >= kSMax && tid < kSMax + k)
+            sm.dk[tid - kSMax] = 1.0 / sqrt(((double)k * q[n + sm.Iset[tid - kSMax]]) / cdf[n + m - 1]);
         __syncthreads();
         int bad = 0;
         for (int e = tid; e < k * l; e += kBlock) bad |= !isfinite(src(sm.Iset[e / l], sm.Jset[e % l]));
         if (__syncthreads_or(bad)) st = LRA_EINVAL;
     }
-    if (st == LRA_OK) nucleus_trunc(sm, dyn, src, k, l, r, U_out, 1.0, 1.0, sm.dk, sm.dl);
+    if (st == LRA_OK) {
+        // up to 64 rows or columns the rotations run in LDS, beyond in the
+        // global workspace (one workgroup: L2-resident)
+        const int nr = k > l ? k : l;
+        if (nr <= kRMax)
+            nucleus_trunc<kRMax / 16>(sm, dyn, src, k, l, r, U_out, 1.0, 1.0, sm.dk, sm.dl);
+        else if (nr <= 128)
+            nucleus_trunc<8>(sm, lev_jacobi_ws(ws, m, n, r), src, k, l, r, U_out, 1.0, 1.0, sm.dk, sm.dl);
+        else
+            nucleus_trunc<16>(sm, lev_jacobi_ws(ws, m, n, r), src, k, l, r, U_out, 1.0, 1.0, sm.dk, sm.dl);
+    }
     if (tid < k) I_out[tid] = st == LRA_OK ? sm.Iset[tid] : -1;
     if (tid < l) J_out[tid] = st == LRA_OK ? sm.Jset[tid] : -1;
     if (st != LRA_OK)
@@ -2386,7 +2397,7 @@ static hipError_t launch_leverage_t(const void *A, int64_t m, int64_t n, int64_t
     hipLaunchKernelGGL(lev_chol_kernel, dim3(2), dim3(kBlock), 0, stream, r, ws, flags);
     hipLaunchKernelGGL(lev_score_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, stream, m, n, r, ws);
     hipLaunchKernelGGL(lev_cdf_kernel, dim3(2), dim3(256), 0, stream, m, n, ws);
-    const size_t dyn = sizeof(double) * (size_t)std::min(k, l) * (size_t)(k + l);
+    const size_t dyn = std::max(k, l) <= kRMax ? sizeof(double) * (size_t)std::min(k, l) * (size_t)(k + l) : 0;
     auto kern = lev_pick_kernel<T>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)e;
@@ -2412,7 +2423,7 @@ hipError_t launch_leverage(int dtype, const void *A, int64_t m, int64_t n, int64
 }
 
 size_t leverage_scratch_bytes(int64_t m, int64_t n, int r) {
-    return sizeof(double) * ((size_t)4 * kRMax * kRMax + (size_t)(2 + r) * (size_t)(n + m));
+    return sizeof(double) * ((size_t)4 * kRMax * kRMax + (size_t)(2 + r) * (size_t)(n + m) + 2 * (size_t)kSMax * kSMax);
 }
 
 template <typename T>

@@ -141,6 +141,32 @@ __device__ __forceinline__ void sort_set_wave(int64_t *a, int r) {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Sort two sets of at most kBlock / 2 indices ascending at once (threads
+// 0 .. kBlock/2 - 1 rank the first, the others the second; each entry goes
+// to its rank, ties kept in order), staged through tmp (na + nb entries).
+// Every thread of the workgroup calls.
+__device__ __forceinline__ void sort_two_sets(int64_t *a, int na, int64_t *b, int nb, int64_t *tmp) {
+    const int tid = threadIdx.x, half = kBlock / 2;
+    const bool first = tid < half;
+    const int t = first ? tid : tid - half, cnt = first ? na : nb;
+    int64_t *set = first ? a : b;
+    int64_t *out = first ? tmp : tmp + na;
+    int64_t x = 0;
+    int rank = 0;
+    if (t < cnt) {
+        x = set[t];
+        for (int j = 0; j < cnt; j++) {
+            const int64_t y = set[j];
+            rank += (y < x) || (y == x && j < t);
+        }
+    }
+    __syncthreads();
+    if (t < cnt) out[rank] = x;
+    __syncthreads();
+    if (t < cnt) set[t] = out[t];
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------- entry sources
 // Where the entries W[i][j] of one matrix come from: a dense row-major array
 // (FP64, FP32 or BF16 as stored, converted to FP64), or, for far-field
@@ -257,9 +283,10 @@ __device__ __forceinline__ double row_sum16(double v) {
     return v;
 }
 
-// One-sided Jacobi (Hestenes) sweeps on the nc columns (length nr <= 64) of
-// A, column-major in LDS, accumulating the rotations in V (nc x nc,
-// column-major, set to the identity by the caller): the oracle's round-robin
+// One-sided Jacobi (Hestenes) sweeps on the nc <= nr columns (length
+// nr <= 16 RL, RL entries per lane) of A, column-major in LDS or global
+// memory, accumulating the rotations in V (nc x nc, column-major, set to the
+// identity by the caller): the oracle's round-robin
 // pair order (a dummy position for odd nc), a pair rotated unless
 // |a_p . a_q| <= nr eps sqrt(|a_p|^2 |a_q|^2), eps = 2^-52, or a column is
 // negligible (|a|^2 <= (nr eps)^2 times the largest squared column norm at
@@ -269,10 +296,11 @@ __device__ __forceinline__ double row_sum16(double v) {
 // 0 also leaves alone a pair whose two squared norms are both at most
 // pair_floor times that largest one (for callers that need only the dominant
 // columns).  One workgroup of kBlock threads, every thread calls.
+template <int RL = kRMax / 16>
 __device__ __forceinline__ int jacobi_sweeps(double *A, double *V, int nr, int nc, double pair_floor = 0.0) {
     const int tid = threadIdx.x;
     __shared__ int s_rot;
-    __shared__ double s_nrm[kRMax];
+    __shared__ double s_nrm[16 * RL];
     __shared__ double s_big;
     const int lp = nc + (nc & 1);
     const int grp = tid / 16, j = tid % 16, ngrp = kBlock / 16;
@@ -283,7 +311,7 @@ __device__ __forceinline__ int jacobi_sweeps(double *A, double *V, int nr, int n
         for (int c = grp; c < nc; c += ngrp) {
             double s2 = 0.0;
 #pragma unroll
-            for (int u = 0; u < kRMax / 16; u++) {
+            for (int u = 0; u < RL; u++) {
                 const int i = j + 16 * u;
                 const double x = i < nr ? A[c * nr + i] : 0.0;
                 s2 += x * x;
@@ -306,16 +334,16 @@ __device__ __forceinline__ int jacobi_sweeps(double *A, double *V, int nr, int n
                 jacobi_pair(t, pr, lp, pc, qc);
                 if (qc >= nc) continue;
                 const double *ap = A + pc * nr, *aq = A + qc * nr;
-                double x[kRMax / 16], y[kRMax / 16];
+                double x[RL], y[RL];
 #pragma unroll
-                for (int u = 0; u < kRMax / 16; u++) {
+                for (int u = 0; u < RL; u++) {
                     const int i = j + 16 * u;
                     x[u] = i < nr ? ap[i] : 0.0;
                     y[u] = i < nr ? aq[i] : 0.0;
                 }
                 double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-                for (int u = 0; u < kRMax / 16; u++) {
+                for (int u = 0; u < RL; u++) {
                     al += x[u] * x[u];
                     be += y[u] * y[u];
                     ga += x[u] * y[u];
@@ -331,22 +359,22 @@ __device__ __forceinline__ int jacobi_sweeps(double *A, double *V, int nr, int n
                 const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
                 if (sn == 0.0) continue;
 #pragma unroll
-                for (int u = 0; u < kRMax / 16; u++) {
+                for (int u = 0; u < RL; u++) {
                     const int i = j + 16 * u;
                     if (i < nr) {
                         A[pc * nr + i] = cs * x[u] - sn * y[u];
                         A[qc * nr + i] = sn * x[u] + cs * y[u];
                     }
                 }
-                double vx[kRMax / 16], vy[kRMax / 16];
+                double vx[RL], vy[RL];
 #pragma unroll
-                for (int u = 0; u < kRMax / 16; u++) {
+                for (int u = 0; u < RL; u++) {
                     const int i = j + 16 * u;
                     vx[u] = i < nc ? V[pc * nc + i] : 0.0;
                     vy[u] = i < nc ? V[qc * nc + i] : 0.0;
                 }
 #pragma unroll
-                for (int u = 0; u < kRMax / 16; u++) {
+                for (int u = 0; u < RL; u++) {
                     const int i = j + 16 * u;
                     if (i < nc) {
                         V[pc * nc + i] = cs * vx[u] - sn * vy[u];
@@ -380,9 +408,10 @@ __device__ __forceinline__ int jacobi_sweeps(double *A, double *V, int nr, int n
 // sm.nucleus_rank = the number kept, sm.logdet = the sum of their logs.
 // dl, dr: the generator is taken as (dl G) dr entrywise and U returned as
 // (dr U) dl, the scalar rescalings Dbar, D of a CUR by sampling; dla / dra
-// (optional) give one factor per row of G and per column instead.
-// One workgroup, every thread calls.
-template <class SM, class Src>
+// (optional) give one factor per row of G and per column instead.  RL: rows
+// per lane of the rotations, max(k, l) <= 16 RL; ws may lie in LDS or in
+// global memory.  One workgroup, every thread calls.
+template <int RL = kRMax / 16, class SM, class Src>
 __device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src, int k, int l, int r,
                                               double *U_out, double dl = 1.0, double dr = 1.0,
                                               const double *dla = nullptr, const double *dra = nullptr) {
@@ -390,8 +419,8 @@ __device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src
     const bool wide = k < l;
     const int nr = wide ? l : k, nc = wide ? k : l;
     double *A = ws, *V = ws + nr * nc;
-    __shared__ double s_sig[kRMax];
-    __shared__ int s_keep[kRMax];
+    __shared__ double s_sig[16 * RL];
+    __shared__ int s_keep[16 * RL];
     for (int e = tid; e < nr * nc; e += kBlock) {
         const int i = e % nr, c = e / nr;
         const int ia = wide ? c : i, jb = wide ? i : c;  // row (I) and column (J) of the entry
@@ -399,7 +428,7 @@ __device__ __forceinline__ void nucleus_trunc(SM &sm, double *ws, const Src &src
     }
     for (int e = tid; e < nc * nc; e += kBlock) V[e] = (e / nc == e % nc) ? 1.0 : 0.0;
     __syncthreads();
-    jacobi_sweeps(A, V, nr, nc);
+    jacobi_sweeps<RL>(A, V, nr, nc);
     for (int c = tid; c < nc; c += kBlock) {
         double s2 = 0.0;
         for (int i = 0; i < nr; i++) s2 += A[c * nr + i] * A[c * nr + i];

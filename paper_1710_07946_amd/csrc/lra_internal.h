@@ -11,6 +11,7 @@ namespace lra {
 constexpr int kBlock = 512;  // threads per workgroup (8 wavefronts, two per SIMD)
 constexpr int kRMax = 64;    // largest supported rank
 constexpr int kLMax = 256;   // largest number of sampled SRHT columns
+constexpr int kSMax = 256;   // largest number of rows or columns drawn by the leverage-score refinement
 
 // Team exchange (64-bit tagged words): per workgroup and parity 2 header
 // words (value, item, slot and flags in two 60-bit payloads) and 2 words per

@@ -167,10 +167,10 @@ def test_leverage_invalid_arguments_rejected_on_host(lib):
 
     assert call(k=3) == E            # k < r
     assert call(l=3) == E            # l < r
-    assert call(k=65) == E
-    assert call(l=65) == E
+    assert call(k=257) == E          # more than 256 draws on a side
+    assert call(l=257) == E
     assert call(r=0) == E
-    assert call(r=65, k=65, l=65) == E
+    assert call(r=65, k=65, l=65) == E   # rank above 64
     assert call(m=3, r=4) == E       # r > m
     assert call(lda=79) == E
     assert call(dt=7) == E

@@ -86,6 +86,16 @@ def test_shapes_fp32(lra, r, k, l):
     check(A, run(lra, A, base.I, base.J, k, l, 13), o, r)
 
 
+@pytest.mark.parametrize("k,l", [(65, 130), (128, 128), (200, 96), (256, 256), (256, 20)])
+def test_samples_beyond_64(lra, k, l):
+    # more than 64 draws on a side: the nucleus's rotations run in the
+    # global workspace with 8 or 16 rows per lane
+    A = workloads.factor_gaussian(900, 700, 16, 1e-5, seeds=(17, 18, 19)).astype(np.float32)
+    base = oracle.ca_cur(A, 16, 1, 41)
+    o = oracle.leverage_cur(A, base.I, base.J, k, l, 23)
+    check(A, run(lra, A, base.I, base.J, k, l, 23), o, 16)
+
+
 def test_bf16_with_repeated_draws(lra):
     A32 = workloads.orthogonal_lowrank(30, 25, 3, noise=1e-3, seeds=(1, 2, 3)).astype(np.float32)
     A = (A32.view(np.uint32) >> 16).astype(np.uint16)
@@ -121,18 +131,19 @@ def test_out_of_range_sets_are_rejected_on_the_host(lra):
 
 def test_headline_size_sampled(lra):
     # the benchmark's refinement: the 20000 x 20000 headline matrix, crude
-    # sets from its C-A CUR, k = l = 64; reconstruction parity on 2000 rows
+    # sets from its C-A CUR, k = l = 200 (4 r); reconstruction parity on 2000
+    # rows
     m = n = 20000
     Ad = workloads.factor_gaussian_device(m, n, 50, 1e-6, 1011, "cuda")
     base = lra.lra_cur(Ad, 50, 4, 2011, preprocess=lra.LRA_PRE_ASRHT, ah_depth=3, ah_samples=100)
     I0, J0 = base.I.cpu().numpy(), base.J.cpu().numpy()
-    out = lra.lra_cur_leverage(Ad, base.I, base.J, 64, 64, 7)
+    out = lra.lra_cur_leverage(Ad, base.I, base.J, 200, 200, 7)
     torch.cuda.synchronize()
     g = (out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy(), out.info())
     A = Ad.cpu().numpy()
     del Ad
     torch.cuda.empty_cache()
-    o = oracle.leverage_cur(A, I0, J0, 64, 64, 7)
+    o = oracle.leverage_cur(A, I0, J0, 200, 200, 7)
     rows = np.sort(np.random.default_rng(0).choice(m, 2000, replace=False))
     check(A, g, o, 50, rows=rows)
 
