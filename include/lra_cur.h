@@ -85,6 +85,7 @@ typedef struct {
     int32_t ah_samples;    /* sampled multiplier columns l (r <= l <= 256); <= 0 selects 2 r */
     int32_t refine_steps;  /* iterative refinement steps of the nucleus inverse; default 0 */
     int32_t team_size;     /* workgroups cooperating on one LRA; <= 0 chooses automatically */
+    int32_t track_margin;  /* 1: report lra_info.min_margin (C-A entry points; costs time), 0 (default): NaN */
     const int64_t *init_cols; /* optional HOST array of r distinct start columns (warm start) */
 } lra_opts;
 
@@ -98,7 +99,22 @@ typedef struct {
     int32_t nucleus_rank;  /* r, or the rank kept by the truncated pseudo-inverse nucleus */
     int32_t reserved;
     double det_log_abs;    /* log |det W[I, J]| of the final generator (-inf if singular) */
+    double min_margin;     /* the smallest relative margin of the run's decisions (below); NaN where not tracked */
 } lra_info;
+/* min_margin: with opts.track_margin = 1, lra_cur, lra_cur_noalloc,
+ * lra_cur_hadamard and the batched C-A entry points take, at every
+ * decision, the gap between the winner and the runner-up relative to the
+ * winner, (v1 - v2) / v1, over all candidates (pivot |C_ik| of the panel LU,
+ * |B_ij| of a swap search, squared norm of the sketch QRP; 1 without a
+ * runner-up, 0 for a tie), and at every stop test of a swap search
+ * |v1 - (1 + delta)| / (1 + delta); the minimum over the run, 1 when nothing
+ * was decided.  A decision whose margin is near rounding level could go the
+ * other way under a perturbation of that size.  Tracking carries the best two
+ * values through every reduction (a separate kernel instantiation; about
+ * 8% slower for one team LRA, 15% for a batch).  lra_cur_dmm_batched reports
+ * the smallest distance of a draw's target u_t S from the running sums that
+ * bound the item it picked, relative to S.  The other entry points report
+ * NaN. */
 
 /* Fill *o with the defaults listed above. */
 void lra_default_opts(lra_opts *o);

@@ -36,13 +36,14 @@ class LraError(RuntimeError):
 class lra_opts(ct.Structure):
     _fields_ = [("delta", ct.c_double), ("max_swaps", ct.c_int32), ("preprocess", ct.c_int32),
                 ("ah_depth", ct.c_int32), ("ah_samples", ct.c_int32), ("refine_steps", ct.c_int32),
-                ("team_size", ct.c_int32), ("init_cols", ct.POINTER(ct.c_int64))]
+                ("team_size", ct.c_int32), ("track_margin", ct.c_int32), ("init_cols", ct.POINTER(ct.c_int64))]
 
 
 class lra_info(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("sweeps_run", ct.c_int32), ("swaps_total", ct.c_int32),
                 ("converged", ct.c_int32), ("rank_found", ct.c_int32), ("team_size", ct.c_int32),
-                ("nucleus_rank", ct.c_int32), ("reserved", ct.c_int32), ("det_log_abs", ct.c_double)]
+                ("nucleus_rank", ct.c_int32), ("reserved", ct.c_int32), ("det_log_abs", ct.c_double),
+                ("min_margin", ct.c_double)]
 
 
 class lra_block(ct.Structure):
@@ -200,8 +201,10 @@ def _stream_ptr(stream):
     return ct.c_void_p(s.cuda_stream)
 
 
-def _make_opts(delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps, team_size, init_cols):
+def _make_opts(delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps, team_size, init_cols,
+               track_margin=False):
     o = lra_default_opts()
+    o.track_margin = 1 if track_margin else 0
     o.delta = delta
     o.max_swaps = max_swaps
     o.preprocess = preprocess
@@ -255,7 +258,7 @@ def _check_out(out: CurOut, n_i: int, n_j: int, n_u: int, n_info: int, dev) -> N
 
 # ------------------------------------------------------------------ entry points
 def _cur_entry(name: str, A, r, sweeps, seed, delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps,
-               team_size, init_cols, out, stream) -> CurOut:
+               team_size, init_cols, out, stream, track_margin=False) -> CurOut:
     torch = _torch()
     if A.dim() != 2 or A.stride(1) != 1 or not A.is_cuda:
         raise ValueError("A must be a 2-D device tensor with unit column stride")
@@ -267,7 +270,8 @@ def _cur_entry(name: str, A, r, sweeps, seed, delta, max_swaps, preprocess, ah_d
                      torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
     else:
         _check_out(out, r, r, r * r, 1, dev)
-    o, keep = _make_opts(delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps, team_size, init_cols)
+    o, keep = _make_opts(delta, max_swaps, preprocess, ah_depth, ah_samples, refine_steps, team_size, init_cols,
+                         track_margin)
     st = getattr(load(), name)(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, sweeps,
                                ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
                                ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
@@ -280,28 +284,32 @@ def _cur_entry(name: str, A, r, sweeps, seed, delta, max_swaps, preprocess, ah_d
 
 def lra_cur(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
             preprocess: int = LRA_PRE_NONE, ah_depth: int = 3, ah_samples: int = 0, refine_steps: int = 0,
-            team_size: int = 0, init_cols=None, out: CurOut | None = None, stream=None) -> CurOut:
+            team_size: int = 0, init_cols=None, out: CurOut | None = None, stream=None,
+            track_margin: bool = False) -> CurOut:
     """C-A CUR of a 2-D device tensor (row-major rows, unit column stride).
 
     Asynchronous on the current (or given) stream; the returned tensors are
     filled when the stream reaches the launch.  ``CurOut.info()`` syncs.
+    ``track_margin`` reports the decisions' smallest margin in the info.
     """
     return _cur_entry("lra_cur", A, r, sweeps, seed, delta, max_swaps, preprocess, ah_depth, ah_samples,
-                      refine_steps, team_size, init_cols, out, stream)
+                      refine_steps, team_size, init_cols, out, stream, track_margin)
 
 
 def lra_cur_noalloc(A, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
                     preprocess: int = LRA_PRE_NONE, ah_depth: int = 3, ah_samples: int = 0, refine_steps: int = 0,
-                    team_size: int = 0, out: CurOut | None = None, stream=None) -> CurOut:
+                    team_size: int = 0, out: CurOut | None = None, stream=None,
+                    track_margin: bool = False) -> CurOut:
     """``lra_cur`` with every work buffer in the library's fixed per-GPU scratch
     (no device allocation by the library; pass ``out`` to allocate nothing
     here either).  Calls that overlap on one GPU race."""
     return _cur_entry("lra_cur_noalloc", A, r, sweeps, seed, delta, max_swaps, preprocess, ah_depth, ah_samples,
-                      refine_steps, team_size, None, out, stream)
+                      refine_steps, team_size, None, out, stream, track_margin)
 
 
 def lra_cur_hadamard(A, r: int, sweeps: int, seed: int, d: int, *, delta: float = 0.01, max_swaps: int = -1,
-                     refine_steps: int = 0, team_size: int = 0, out: CurOut | None = None, stream=None) -> CurOut:
+                     refine_steps: int = 0, team_size: int = 0, out: CurOut | None = None, stream=None,
+                     track_margin: bool = False) -> CurOut:
     """C-A CUR of the pre-processed matrix W' = W D (H_{2^d} (x) I_s) (m x N, N the
     multiple of 2^d at or above n), its entries formed on the fly; J indexes the
     columns of W'.  Asynchronous like ``lra_cur``."""
@@ -316,7 +324,7 @@ def lra_cur_hadamard(A, r: int, sweeps: int, seed: int, d: int, *, delta: float 
                      torch.empty(INFO_BYTES, dtype=torch.uint8, device=dev))
     else:
         _check_out(out, r, r, r * r, 1, dev)
-    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, team_size, None)
+    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, team_size, None, track_margin)
     st = load().lra_cur_hadamard(ct.c_void_p(A.data_ptr()), _dtype_code(A), m, n, A.stride(0), r, sweeps,
                                  ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), d, ct.byref(o), ct.c_void_p(out.I.data_ptr()),
                                  ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
@@ -385,7 +393,8 @@ def lra_cur_projective(A, r: int, k: int, l: int, sweeps: int, seed: int, *, del
 
 
 def lra_cur_batched(base, blocks, r: int, sweeps: int, seed: int, *, delta: float = 0.01, max_swaps: int = -1,
-                    refine_steps: int = 0, out: CurOut | None = None, stream=None) -> CurOut:
+                    refine_steps: int = 0, out: CurOut | None = None, stream=None,
+                    track_margin: bool = False) -> CurOut:
     """C-A CUR of `count` blocks stored in the flat device tensor `base`.
 
     ``blocks`` is an int64 array of shape (count, 4): (offset, m, n, lda) in
@@ -411,7 +420,7 @@ def lra_cur_batched(base, blocks, r: int, sweeps: int, seed: int, *, delta: floa
         _check_out(out, count * r, count * r, count * r * r, count, dev)
     arr = (lra_block * max(count, 1))()
     ct.memmove(arr, desc.ctypes.data, desc.nbytes)
-    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, 0, None)
+    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, 0, None, track_margin)
     st = load().lra_cur_batched(ct.c_void_p(base.data_ptr()), _dtype_code(base), arr, count, r, sweeps,
                                 ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o), ct.c_void_p(out.I.data_ptr()),
                                 ct.c_void_p(out.J.data_ptr()), ct.c_void_p(out.U.data_ptr()),
@@ -547,7 +556,7 @@ def lra_cur_leverage(A, I0, J0, k: int, l: int, seed: int, *, out: CurOut | None
 
 def lra_cur_batched_points(pts, blocks, r: int, sweeps: int, seed: int, *, delta: float = 0.01,
                            max_swaps: int = -1, refine_steps: int = 0, out: CurOut | None = None,
-                           stream=None) -> CurOut:
+                           stream=None, track_margin: bool = False) -> CurOut:
     """C-A CUR of `count` far-field blocks K_ij = 1/|x_i - y_j| evaluated on the
     fly from the device float64 point tensor `pts` of shape (npts, 2).
 
@@ -570,7 +579,7 @@ def lra_cur_batched_points(pts, blocks, r: int, sweeps: int, seed: int, *, delta
         _check_out(out, count * r, count * r, count * r * r, count, dev)
     arr = (lra_pts_block * max(count, 1))()
     ct.memmove(arr, desc.ctypes.data, desc.nbytes)
-    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, 0, None)
+    o, keep = _make_opts(delta, max_swaps, LRA_PRE_NONE, 3, 0, refine_steps, 0, None, track_margin)
     st = load().lra_cur_batched_points(ct.c_void_p(pts.data_ptr()), pts.shape[0], arr, count, r, sweeps,
                                        ct.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), ct.byref(o),
                                        ct.c_void_p(out.I.data_ptr()), ct.c_void_p(out.J.data_ptr()),

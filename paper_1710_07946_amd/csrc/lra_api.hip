@@ -171,6 +171,7 @@ lra_status fill_config(const lra_opts *opts, int32_t r, int32_t sweeps, CAConfig
     c->init_cols = nullptr;
     c->sketch_ws = nullptr;
     c->bd_table = nullptr;
+    c->margins = o.track_margin ? 1 : 0;
     *o_out = o;
     return LRA_OK;
 }
@@ -506,6 +507,7 @@ void lra_default_opts(lra_opts *o) {
     o->ah_samples = 0;
     o->refine_steps = 0;
     o->team_size = 0;
+    o->track_margin = 0;
     o->init_cols = nullptr;
 }
 
@@ -715,6 +717,7 @@ lra_status lra_cur_cynical(const void *W, lra_dtype dt, int64_t m, int64_t n, in
     lra_status st = fill_config(opts, k, std::max(loops, 1), &ck, &o);
     if (st != LRA_OK) return st;
     if ((st = fill_config(opts, r, sweeps, &cr, &o2)) != LRA_OK) return st;
+    ck.margins = cr.margins = 0;  // the cynical CUR does not track decision margins
     if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
 
     std::lock_guard<std::mutex> lk(g_mu);
@@ -766,6 +769,7 @@ lra_status lra_cur_projective(const void *W, lra_dtype dt, int64_t m, int64_t n,
     lra_opts o;
     lra_status st = fill_config(opts, r, sweeps, &cfg, &o);
     if (st != LRA_OK) return st;
+    cfg.margins = 0;  // the r-projective CUR does not track decision margins
     if (o.preprocess != LRA_PRE_NONE || o.init_cols) return LRA_EINVAL;
 
     std::lock_guard<std::mutex> lk(g_mu);

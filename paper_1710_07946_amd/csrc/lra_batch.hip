@@ -53,7 +53,9 @@ struct RegSmem {
     double wrow[R];
     double nuc[4 * R * R];
     Best red[kRegMaxWaves];
+    double red2[kRegMaxWaves];
     int32_t red_flag[kRegMaxWaves];
+    double mmin;   // smallest decision margin of the block so far
     int32_t job;
     int32_t status;
     int32_t rank_found;
@@ -89,26 +91,36 @@ __device__ __forceinline__ double onehot(const double (&x)[R], int j) {
 }
 
 // One decision of the workgroup: the wavefront reductions, then (W > 1) the
-// W partials through LDS, so every wavefront holds the same winner and flag;
+// W partials through LDS, so every wavefront holds the same winner, flag and
+// runner-up value (v2: the largest candidate value other than the winner's,
+// b2 being each thread's own runner-up);
 // the winner's panel row (its R entries) lands in sm.wrow.  The row is read
 // from LDS where it is used (a uniform value: no registers held for it).
 // The order is total (value, then lowest item, then lowest slot), so the
 // result does not depend on how the candidates were split.
-template <int R, int P>
-__device__ __forceinline__ void reg_select(RegSmem<R> &sm, int nw, Best b, int flag, const double (&x)[P][R],
-                                           Best &win, int &wflag) {
+template <int R, int P, bool M>
+__device__ __forceinline__ void reg_select(RegSmem<R> &sm, int nw, Best b, double b2, int flag,
+                                           const double (&x)[P][R], Best &win, int &wflag, double &v2) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    b = wave_reduce(b);
+    v2 = -1.0;
+    if constexpr (M) b = wave_reduce2(b, b2, v2);
+    else b = wave_reduce(b);
     flag = wave_or(flag);
     if (nw > 1) {
         if (lane == 0) {
             sm.red[wv] = b;
+            if constexpr (M) sm.red2[wv] = v2;
             sm.red_flag[wv] = flag;
         }
         __syncthreads();
         const Best c = lane < nw ? sm.red[lane] : none();
         const int f = lane < nw ? sm.red_flag[lane] : 0;
         b = reduce8(c);
+        if constexpr (M) {
+            double t1 = c.v, t2 = lane < nw ? sm.red2[lane] : -1.0;
+            top2_8(t1, t2);
+            v2 = t2;
+        }
         flag = wave_or(f);
     }
     win = b;
@@ -131,12 +143,13 @@ __device__ __forceinline__ void reg_select(RegSmem<R> &sm, int nw, Best b, int f
 // largest |x_K| (lowest item among equals) becomes basis slot K, its row
 // gives pivot row K.  Returns false (status set) on a non-finite entry or a
 // zero pivot.
-template <int R, int P, int K>
+template <int R, int P, int K, bool M>
 __device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R], int (&fl)[P], int bad,
                                        double pk) {
     const int tid = threadIdx.x;
     __builtin_amdgcn_sched_barrier(0);  // no step's work moves into another's
     Best b = none();
+    double b2 = -1.0;
 #pragma unroll
     for (int p = 0; p < P; p++) {
         if (fl[p] != 0) continue;
@@ -146,11 +159,13 @@ __device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R]
             for (int t = K; t < R; t++) x[p][t] -= l * sm.wrow[t];
             x[p][K > 0 ? K - 1 : 0] = l;
         }
-        consider(b, fabs(x[p][K]), reg_item(p, nw), 0);
+        if constexpr (M) consider2(b, b2, fabs(x[p][K]), reg_item(p, nw), 0);
+        else consider(b, fabs(x[p][K]), reg_item(p, nw), 0);
     }
     Best win;
     int wf;
-    reg_select<R, P>(sm, nw, b, K == 0 ? bad : 0, x, win, wf);
+    double v2;
+    reg_select<R, P, M>(sm, nw, b, b2, K == 0 ? bad : 0, x, win, wf, v2);
     if (wf || !(win.v > 0.0)) {
         if (tid == 0) {
             sm.status = wf ? LRA_EINVAL : LRA_ESINGULAR;
@@ -160,6 +175,7 @@ __device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R]
         return false;
     }
     if (tid == 0) {
+        if constexpr (M) sm.mmin = fmin(sm.mmin, decision_gap(win.v, v2));
         sm.slot_item[K] = win.item;
 #pragma unroll
         for (int j = 0; j < K; j++) sm.L11[K * (K - 1) / 2 + j] = sm.wrow[j];
@@ -168,7 +184,7 @@ __device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R]
     for (int p = 0; p < P; p++)
         if (reg_item(p, nw) == win.item) fl[p] = K + 1;
     if constexpr (K + 1 < R) {
-        return reg_lu<R, P, K + 1>(sm, nw, x, fl, 0, sm.wrow[K]);
+        return reg_lu<R, P, K + 1, M>(sm, nw, x, fl, 0, sm.wrow[K]);
     } else {
         // last multipliers (no trailing columns)
         const double pl = sm.wrow[R - 1];
@@ -187,7 +203,7 @@ __device__ __forceinline__ bool reg_lu(RegSmem<R> &sm, int nw, double (&x)[P][R]
 // with the rank-one update of B, each fused with the next scan.  Returns
 // false (status set) on a non-finite entry or a rank-deficient panel; else
 // set_out holds the new sorted set.
-template <int R, int P, class Src>
+template <int R, int P, bool M, class Src>
 __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src, int64_t items, bool col,
                                          const int64_t *set_in, int64_t *set_out, double delta, int max_swaps,
                                          int32_t &swaps_total, int32_t &converged) {
@@ -237,7 +253,7 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
 #endif
     REG_TOC(0, t_g);
     REG_TIC(t_lu);
-    if (!reg_lu<R, P, 0>(sm, nw, x, fl, bad, 1.0)) return false;
+    if (!reg_lu<R, P, 0, M>(sm, nw, x, fl, bad, 1.0)) return false;
     __syncthreads();  // L11 written by thread 0
     REG_TOC(1, t_lu);
     REG_CNT(6, R);
@@ -271,6 +287,7 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
     double pv = 1.0;
     for (;;) {
         Best b = none();
+        double b2 = -1.0;
 #pragma unroll
         for (int p = 0; p < P; p++) {
             if (fl[p] < 0) continue;
@@ -294,25 +311,37 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
 #pragma unroll
                 for (int t = 0; t < R; t++) x[p][t] -= f * (sm.wrow[t] - (double)(t == js));
             }
-            double vb = -1.0;
+            double vb = -1.0, vb2 = -1.0;
             int jb = 0;
 #pragma unroll
             for (int t = 0; t < R; t++) {
                 const bool up = fabs(x[p][t]) > vb;
                 jb = up ? t : jb;
+                if constexpr (M) vb2 = fmax(vb2, fmin(fabs(x[p][t]), vb));
                 vb = fmax(vb, fabs(x[p][t]));  // finite entries: the same value as up ? |x| : vb
             }
-            consider(b, vb, it, jb);
+            if constexpr (M) {
+                b2 = fmax(b2, vb2);
+                consider2(b, b2, vb, it, jb);
+            } else {
+                consider(b, vb, it, jb);
+            }
         }
         Best win;
         int wf;
-        reg_select<R, P>(sm, nw, b, 0, x, win, wf);
+        double v2;
+        reg_select<R, P, M>(sm, nw, b, b2, 0, x, win, wf, v2);
         const double v = win.v;
+        // margins: the stop test's, then (a swap) the search's
+        if constexpr (M)
+            if (v >= 0.0 && tid == 0) sm.mmin = fmin(sm.mmin, fabs(v - thr) / thr);
         if (v < 0.0 || v <= thr) break;  // no candidate left, or dominant
         if (swaps >= max_swaps) {
             converged = 0;
             break;
         }
+        if constexpr (M)
+            if (tid == 0) sm.mmin = fmin(sm.mmin, decision_gap(v, v2));
         // the next scan applies B <- B - B[:,js] (B[i*,:] - e_js^T) / B[i*,js]
         js = win.slot;
         wit = win.item;
@@ -333,7 +362,7 @@ __device__ __forceinline__ bool reg_step(RegSmem<R> &sm, int nw, const Src &src,
 }
 
 // The whole LRA of one block (the C-A loop of lra_cur with a random start).
-template <int R, int P, class Src>
+template <int R, int P, bool M, class Src>
 __device__ __forceinline__ void reg_solve(RegSmem<R> &sm, int nw, const Src &src, int64_t m, int64_t n, uint64_t seed,
                                           int sweeps, double delta, int max_swaps, int refine, int64_t *I_out,
                                           int64_t *J_out, double *U_out, lra_info *info) {
@@ -344,6 +373,7 @@ __device__ __forceinline__ void reg_solve(RegSmem<R> &sm, int nw, const Src &src
         sm.rank_found = R;
         sm.nucleus_rank = R;
         sm.logdet = 0.0;
+        sm.mmin = 1.0;
     }
     if (tid < 64) {
         draw_distinct_wave(seed, 0, n, R, sm.Jset);
@@ -356,7 +386,7 @@ __device__ __forceinline__ void reg_solve(RegSmem<R> &sm, int nw, const Src &src
     // inlined once)
     for (int st = 0; st < 2 * sweeps; st++) {
         const bool col = (st & 1) == 0;
-        ok = reg_step<R, P>(sm, nw, src, col ? m : n, col, col ? sm.Jset : sm.Iset, col ? sm.Iset : sm.Jset, delta,
+        ok = reg_step<R, P, M>(sm, nw, src, col ? m : n, col, col ? sm.Jset : sm.Iset, col ? sm.Iset : sm.Jset, delta,
                             max_swaps, swaps_total, converged);
         if (!ok) break;
         if (col) continue;
@@ -395,13 +425,14 @@ __device__ __forceinline__ void reg_solve(RegSmem<R> &sm, int nw, const Src &src
         inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
         inf.reserved = 0;
         inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
+        inf.min_margin = M ? sm.mmin : __builtin_nan("");
         *info = inf;
     }
 }
 
 // Persistent loop over the blocks order[0 .. count) of one bin, taken from
 // *queue; workgroups of 64 nw threads.
-template <int R, int P, class Desc, class MakeSrc>
+template <int R, int P, bool M, class Desc, class MakeSrc>
 __device__ __forceinline__ void reg_loop(const Desc *blocks, const int32_t *order, int64_t count, uint64_t seed,
                                          int sweeps, double delta, int max_swaps, int refine, unsigned *queue,
                                          int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos,
@@ -417,7 +448,7 @@ __device__ __forceinline__ void reg_loop(const Desc *blocks, const int32_t *orde
         const int32_t b = order[job];
         const Desc d = blocks[b];
         REG_TIC(t_blk);
-        reg_solve<R, P>(sm, nw, make(d), d.m, d.n, seed + (uint64_t)b, sweeps, delta, max_swaps, refine,
+        reg_solve<R, P, M>(sm, nw, make(d), d.m, d.n, seed + (uint64_t)b, sweeps, delta, max_swaps, refine,
                         I_out + (int64_t)b * R, J_out + (int64_t)b * R, U_out + (int64_t)b * R * R,
                         infos ? infos + b : nullptr);
         REG_TOC(5, t_blk);
@@ -439,41 +470,42 @@ struct MakePoints {
     }
 };
 
-template <int R, int P, typename T>
+template <int R, int P, typename T, bool M>
 __global__ void __launch_bounds__(64 * kRegMaxWaves) ca_reg_kernel(const T *base, const BlockDesc *blocks,
                                                                    const int32_t *order, int64_t count, uint64_t seed,
                                                                    int sweeps, double delta, int max_swaps, int refine,
                                                                    unsigned *queue, int64_t *I_out, int64_t *J_out,
                                                                    double *U_out, lra_info *infos) {
-    reg_loop<R, P>(blocks, order, count, seed, sweeps, delta, max_swaps, refine, queue, I_out, J_out, U_out, infos,
-                   MakeDense<T>{base});
+    reg_loop<R, P, M>(blocks, order, count, seed, sweeps, delta, max_swaps, refine, queue, I_out, J_out, U_out, infos,
+                      MakeDense<T>{base});
 }
 
-template <int R, int P>
+template <int R, int P, bool M>
 __global__ void __launch_bounds__(64 * kRegMaxWaves) ca_reg_points_kernel(const double *pts, const PtsDesc *blocks,
                                                                           const int32_t *order, int64_t count,
                                                                           uint64_t seed, int sweeps, double delta,
                                                                           int max_swaps, int refine, unsigned *queue,
                                                                           int64_t *I_out, int64_t *J_out,
                                                                           double *U_out, lra_info *infos) {
-    reg_loop<R, P>(blocks, order, count, seed, sweeps, delta, max_swaps, refine, queue, I_out, J_out, U_out, infos,
-                   MakePoints{pts});
+    reg_loop<R, P, M>(blocks, order, count, seed, sweeps, delta, max_swaps, refine, queue, I_out, J_out, U_out, infos,
+                      MakePoints{pts});
 }
 
 // Kernel of a register variant for a source (a dtype code; any other value:
 // point sets).
-template <int R, int P>
+template <int R, int P, bool M>
 const void *reg_kernel_fn(int src) {
     switch (src) {
-    case LRA_F64: return (const void *)ca_reg_kernel<R, P, double>;
-    case LRA_F32: return (const void *)ca_reg_kernel<R, P, float>;
-    case LRA_BF16: return (const void *)ca_reg_kernel<R, P, uint16_t>;
-    default: return (const void *)ca_reg_points_kernel<R, P>;
+    case LRA_F64: return (const void *)ca_reg_kernel<R, P, double, M>;
+    case LRA_F32: return (const void *)ca_reg_kernel<R, P, float, M>;
+    case LRA_BF16: return (const void *)ca_reg_kernel<R, P, uint16_t, M>;
+    default: return (const void *)ca_reg_points_kernel<R, P, M>;
     }
 }
 
-const void *reg_kernel(int R, int P, int src) {
-    if (R == 16 && P == 2) return reg_kernel_fn<16, 2>(src);
+// (margins: the instantiation that tracks the decisions' margins)
+const void *reg_kernel(int R, int P, int src, bool margins = true) {
+    if (R == 16 && P == 2) return margins ? reg_kernel_fn<16, 2, true>(src) : reg_kernel_fn<16, 2, false>(src);
     return nullptr;
 }
 
@@ -492,7 +524,7 @@ int reg_occupancy(int r, int P, int waves, int src) {
 hipError_t launch_reg(int src, int r, int P, int waves, const void *base, const void *blocks, const int32_t *order,
                       int64_t count, uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, int64_t *I_out,
                       int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream) {
-    const void *f = reg_kernel(r, P, src);
+    const void *f = reg_kernel(r, P, src, cfg.margins != 0);
     if (!f || waves < 1 || waves > kRegMaxWaves || grid < 1) return hipErrorInvalidValue;
     int sweeps = cfg.sweeps, max_swaps = cfg.max_swaps, refine = cfg.refine_steps;
     double delta = cfg.delta;

@@ -74,8 +74,11 @@ struct Smem {
     double wprev[2][kRMax];  // LU: the pivot rows of the last two steps
     int64_t loc_item;        // the workgroup's best item of the last selection (-1: none)
     Best red[kNWave];
+    double red2[kNWave];     // each wavefront's runner-up value
     int32_t red_flag[kNWave];
     Best win;
+    double win_v2;   // the team's runner-up value (in the winner's workgroup; NaN elsewhere)
+    double mmin;     // smallest decision margin this workgroup has seen
     int32_t win_flag;
     int32_t status;
     int32_t rank_found;
@@ -327,10 +330,10 @@ enum SelMode { kSelPlain = 0, kSelHouseholder = 1, kSelSwap = 2 };
 // vtv = sum of v_c^2 in index order).  With kSelSwap it keeps the winner's
 // entry at its slot in sm.pivot and subtracts 1 there in sm.wrow, so that
 // sm.wrow holds B[i*,:] - e_j*^T, the vector of the rank-one swap update.
-template <class RowFn, class Overlap>
+template <bool M, class RowFn, class Overlap>
 __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const Geo &g, int width, int mode,
                                             int hstep, const RowFn &rowf, const Overlap &overlap,
-                                            double pub_min = -1.0) {
+                                            double pub_min = -1.0, double b2 = -1.0) {
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #ifdef LRA_TRACE
     const uint64_t t_in = wall_clock64();
@@ -338,10 +341,13 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
 #ifdef LRA_TRACE
     if (lane == 0) sm.t_arr[w] = t_in;
 #endif
-    b = wave_reduce(b);
+    double wv2 = -1.0;
+    if constexpr (M) b = wave_reduce2(b, b2, wv2);
+    else b = wave_reduce(b);
     flag = wave_or(flag);
     if (lane == 0) {
         sm.red[w] = b;
+        if constexpr (M) sm.red2[w] = wv2;
         sm.red_flag[w] = flag;
     }
     __syncthreads();
@@ -359,11 +365,19 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
     int f = lane < kNWave ? sm.red_flag[lane] : 0;
     loc = reduce8(loc);
     f = wave_or(f);
+    // (M) the workgroup's runner-up: the best two values of the wavefronts' pairs
+    double lv2 = -1.0;
+    if constexpr (M) {
+        double lv1 = lane < kNWave ? sm.red[lane].v : -1.0;
+        lv2 = lane < kNWave ? sm.red2[lane] : -1.0;
+        top2_8(lv1, lv2);
+    }
     if (w != 0) overlap(loc.v >= 0.0 ? loc.item : (int64_t)-1);
     if (w == 0) {
         if (lane == 0) sm.loc_item = loc.v >= 0.0 ? loc.item : (int64_t)-1;
         Best win;
         int wf;
+        double v2 = lv2;
         if (tm.size == 1) {
             win = loc;
             wf = f;
@@ -402,6 +416,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
             // (null: past the end of the team, nothing to read)
             Best c = none();
             int cf = 0;
+            double hv[4];  // each polled workgroup's best value
             {
                 const uint64_t *ps[4 * kHdrWords];
 #pragma unroll
@@ -415,15 +430,29 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                 xget<4 * kHdrWords, 4>(ps, htag, d, &sm.xfail, tm.spin_limit);
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
+                    hv[q] = -1.0;
                     if (lane + q * kWave >= tm.size) continue;
                     int fl;
                     const Best o = decode_hdr(d[q * kHdrWords], d[q * kHdrWords + 1], lane + q * kWave, fl);
+                    if constexpr (M) hv[q] = o.v;
                     if (better(o.v, o.item, o.slot, c.v, c.item, c.slot)) c = o;
                     cf |= fl;
                 }
             }
             win = wave_reduce(c);
             wf = wave_or(cf);
+            // (M) the team's runner-up, known in the winner's workgroup: its
+            // own runner-up and the second best of the workgroups' bests
+            if constexpr (M) {
+                double h1 = -1.0, h2 = -1.0;
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    h2 = fmax(h2, fmin(hv[q], h1));
+                    h1 = fmax(h1, hv[q]);
+                }
+                top2_wave(h1, h2);
+                v2 = win.aux == tm.rank ? fmax(lv2, h2) : __builtin_nan("");
+            }
 #ifdef LRA_TRACE
             t_b = wall_clock64();
             if (lane == 0 && tm.epoch < kSelTrace && tm.rank < 256) g_sel_done[tm.epoch * 256 + tm.rank] = t_b;
@@ -455,6 +484,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
         __builtin_amdgcn_wave_barrier();  // sm.wrow written by every lane above
         if (lane == 0) {
             sm.win = win;
+            sm.win_v2 = v2;
             sm.win_flag = wf;
             if (mode == kSelHouseholder && win.v > 0.0) {
                 const double nx = sqrt(win.v);
@@ -496,9 +526,9 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
 // order: x <- x - f w (w = B[i*,:] - e_j*^T, skipped when f = 0), then the
 // running largest magnitude, the lowest slot among equals.  `o` is the panel
 // offset of the item's current slot j (stride pstep = sub * st per slot).
-template <int N>
+template <int N, bool M>
 __device__ __forceinline__ void swap_chunk(double *panel, const double *wrow, int &o, int pstep, int &j, int sub,
-                                           double f, double &vb, int &jb) {
+                                           double f, double &vb, double &vb2, int &jb) {
     double x[N];
 #pragma unroll
     for (int u = 0; u < N; u++) x[u] = panel[o + u * pstep];
@@ -517,6 +547,7 @@ __device__ __forceinline__ void swap_chunk(double *panel, const double *wrow, in
     for (int u = 0; u < N; u++) {
         const bool up = fabs(x[u]) > vb;
         kb = up ? u : kb;
+        if constexpr (M) vb2 = fmax(vb2, fmin(fabs(x[u]), vb));  // the runner-up among the slots seen
         vb = fmax(vb, fabs(x[u]));  // finite entries: the same value as up ? |x| : vb
     }
     if (kb >= 0) jb = j + kb * sub;
@@ -558,9 +589,18 @@ __device__ __forceinline__ void fail_status(Smem &sm, int st, int rank) {
     __syncthreads();
 }
 
+template <bool M = false>
 __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag, const double *panel, const Geo &g,
-                                            int width, int mode = kSelPlain, int hstep = 0, double pub_min = -1.0) {
-    team_select(tm, sm, b, flag, g, width, mode, hstep, PanelRow{panel, g.st, g.base}, NoOverlap{}, pub_min);
+                                            int width, int mode = kSelPlain, int hstep = 0, double pub_min = -1.0,
+                                            double b2 = -1.0) {
+    team_select<M>(tm, sm, b, flag, g, width, mode, hstep, PanelRow{panel, g.st, g.base}, NoOverlap{}, pub_min, b2);
+}
+
+// A decision's margin (decision_gap of the winner and the team's runner-up),
+// folded into the workgroup's minimum by the winner's workgroup (the others
+// see NaN for the runner-up).  Thread 0.
+__device__ __forceinline__ void note_margin(Smem &sm) {
+    if (threadIdx.x == 0 && !isnan(sm.win_v2)) sm.mmin = fmin(sm.mmin, decision_gap(sm.win.v, sm.win_v2));
 }
 
 // ---------------------------------------------------------------- maxvol
@@ -575,6 +615,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
 // applied lazily, fused with the scan for the next decision; the arithmetic of
 // every entry is the oracle's, in the oracle's order.  On return sm.slot_item
 // holds the basis in slot order.  `bad` flags a non-finite entry gathered.
+template <bool M>
 __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Geo &g, int r,
                                        double delta, int max_swaps, int bad, int32_t &swaps_total, int32_t &converged) {
     const int tid = threadIdx.x;
@@ -602,6 +643,7 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
         const uint64_t q0 = wall_clock64();
 #endif
         Best b = none();
+        double b2 = -1.0;
         for (int li = grp; li < g.cnt; li += ngrp) {
             if (flags[li]) continue;
             if (k > 0) {
@@ -610,16 +652,21 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
                     if (k % sub == s) {
                         const double x = panel[k * st + li] - l * sm.wrow[k];
                         panel[k * st + li] = x;
-                        consider(b, fabs(x), g.base + li, 0);
+                        if constexpr (M) consider2(b, b2, fabs(x), g.base + li, 0);
+                        else consider(b, fabs(x), g.base + li, 0);
                     }
                 } else {
                     const int jf = (k <= s) ? s : s + ((k - s + sub - 1) / sub) * sub;  // first owned slot >= k
                     if (jf <= jlast) axpy_slots(panel, sm.wrow, jf * st + li, pstep, jf, sub, (jlast - jf) / sub + 1, l);
-                    if (k % sub == s) consider(b, fabs(panel[k * st + li]), g.base + li, 0);
+                    if (k % sub == s) {
+                        if constexpr (M) consider2(b, b2, fabs(panel[k * st + li]), g.base + li, 0);
+                        else consider(b, fabs(panel[k * st + li]), g.base + li, 0);
+                    }
                 }
                 if ((k - 1) % sub == s) panel[(k - 1) * st + li] = l;
             } else if (k % sub == s) {
-                consider(b, fabs(panel[k * st + li]), g.base + li, 0);
+                if constexpr (M) consider2(b, b2, fabs(panel[k * st + li]), g.base + li, 0);
+                else consider(b, fabs(panel[k * st + li]), g.base + li, 0);
             }
         }
         if (k > 0 && tid < k - 1) sm.L11[(k - 1) * (k - 2) / 2 + tid] = sm.wrow[tid];
@@ -646,12 +693,13 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
                 axpy_slots(panel, wp, jf * st + li, subd * st, jf, subd, n, panel[(k - 1) * st + li]);
             }
         };
-        team_select(tm, sm, b, k == 0 ? bad : 0, g, r, kSelPlain, 0, rowf, overlap);
+        team_select<M>(tm, sm, b, k == 0 ? bad : 0, g, r, kSelPlain, 0, rowf, overlap, -1.0, b2);
 #ifdef LRA_TRACE
         const uint64_t q2 = wall_clock64();
 #endif
         if (sm.win_flag) return fail_status(sm, LRA_EINVAL, 0);
         if (!(sm.win.v > 0.0)) return fail_status(sm, LRA_ESINGULAR, k);
+        if constexpr (M) note_margin(sm);
         const int64_t wit = sm.win.item;
         if (tid == 0) sm.slot_item[k] = wit;
         if (wit >= g.base && wit < g.base + g.cnt) {
@@ -740,6 +788,7 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
         const uint64_t q0 = wall_clock64();
 #endif
         Best b = none();
+        double b2 = -1.0;
         for (int li = grp; li < g.cnt; li += ngrp) {
             const int fl = flags[li];
             const int64_t it = g.base + li;
@@ -759,28 +808,39 @@ __device__ __forceinline__ void maxvol(Team &tm, Smem &sm, double *panel, uint8_
             // B[i,:] -= f (B[i*,:] - e_js^T) on the owned slots, and the scan of
             // the owned slots (largest magnitude, lowest slot among equals):
             // full chunks, then the remainder in chunks of 4, 2 and 1
-            double vb = -1.0;
+            double vb = -1.0, vb2 = -1.0;
             int jb = 0, j = s, k = nown, o = s * st + li;
-            for (; k >= kChunk; k -= kChunk) swap_chunk<kChunk>(panel, sm.wrow, o, pstep, j, sub, f, vb, jb);
-            if (k & 4) swap_chunk<4>(panel, sm.wrow, o, pstep, j, sub, f, vb, jb);
-            if (k & 2) swap_chunk<2>(panel, sm.wrow, o, pstep, j, sub, f, vb, jb);
-            if (k & 1) swap_chunk<1>(panel, sm.wrow, o, pstep, j, sub, f, vb, jb);
-            if (jlast >= 0) consider(b, vb, it, jb);
+            for (; k >= kChunk; k -= kChunk) swap_chunk<kChunk, M>(panel, sm.wrow, o, pstep, j, sub, f, vb, vb2, jb);
+            if (k & 4) swap_chunk<4, M>(panel, sm.wrow, o, pstep, j, sub, f, vb, vb2, jb);
+            if (k & 2) swap_chunk<2, M>(panel, sm.wrow, o, pstep, j, sub, f, vb, vb2, jb);
+            if (k & 1) swap_chunk<1, M>(panel, sm.wrow, o, pstep, j, sub, f, vb, vb2, jb);
+            if (jlast >= 0) {
+                if constexpr (M) {
+                    b2 = fmax(b2, vb2);
+                    consider2(b, b2, vb, it, jb);
+                } else {
+                    consider(b, vb, it, jb);
+                }
+            }
         }
 #ifdef LRA_TRACE
         const uint64_t q1 = wall_clock64();
         if (tid == 0) sm.t_loop[2] += q1 - q0;
 #endif
-        team_select(tm, sm, b, 0, panel, g, r, kSelSwap, 0, thr);
+        team_select<M>(tm, sm, b, 0, panel, g, r, kSelSwap, 0, thr, b2);
 #ifdef LRA_TRACE
         const uint64_t q2 = wall_clock64();
 #endif
         const double v = sm.win.v;
+        // the stop test's margin (every workgroup sees the winner's value)
+        if constexpr (M)
+            if (v >= 0.0 && tid == 0) sm.mmin = fmin(sm.mmin, fabs(v - thr) / thr);
         if (v < 0.0 || v <= thr) break;  // no candidate left, or dominant
         if (swaps >= max_swaps) {
             converged = 0;
             break;
         }
+        if constexpr (M) note_margin(sm);
         js = sm.win.slot;
         wit = sm.win.item;
         pv = sm.pivot;
@@ -867,7 +927,7 @@ __device__ __forceinline__ int gather_panel(double *panel, const Geo &g, const S
 // One C-A step.  col = true: panel = W[:, set_in] (items = rows of W);
 // col = false: panel = W[set_in, :]^T (items = columns).  set_out receives
 // the new sorted set.
-template <class Src>
+template <bool M, class Src>
 __device__ __forceinline__ void ca_step(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Src &src, int64_t m,
                                        int64_t n, int r, bool col, const int64_t *set_in, int64_t *set_out,
                                        const CAConfig &cfg, int32_t &swaps_total, int32_t &converged) {
@@ -877,7 +937,7 @@ __device__ __forceinline__ void ca_step(Team &tm, Smem &sm, double *panel, uint8
     for (int li = threadIdx.x; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
     LRA_TR(12, 0);
-    maxvol(tm, sm, panel, flags, g, r, cfg.delta, cfg.max_swaps, bad, swaps_total, converged);
+    maxvol<M>(tm, sm, panel, flags, g, r, cfg.delta, cfg.max_swaps, bad, swaps_total, converged);
 #ifdef LRA_TRACE
     LRA_TR(13, sm.t_select);
 #endif
@@ -1000,6 +1060,7 @@ __global__ void __launch_bounds__(256) bidiag_table_kernel(uint64_t seed, int64_
 // norm ends the loop with ESINGULAR (rank = the step), a flagged non-finite
 // entry (`bad`) with EINVAL.  Same thread-to-item mapping as every other
 // per-item loop here (li = tid, tid + kBlock, ...).
+template <bool M = false>
 __device__ __forceinline__ void team_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Geo &g, int width,
                                          int steps, int bad, bool flush, int64_t *out, double *tup, double *tdiag) {
     const int tid = threadIdx.x;
@@ -1007,6 +1068,7 @@ __device__ __forceinline__ void team_qrp(Team &tm, Smem &sm, double *panel, uint
     for (int gg = 0; gg < steps + (flush ? 1 : 0); gg++) {
         const bool last = gg == steps;
         Best b = none();
+        double b2 = -1.0;
         const double vtv = sm.vtv;
         for (int li = tid; li < g.cnt; li += kBlock) {
             if (flags[li]) continue;
@@ -1027,12 +1089,14 @@ __device__ __forceinline__ void team_qrp(Team &tm, Smem &sm, double *panel, uint
                 int o = gg * ipw + li, c = gg;
                 LRA_QRP_RUN(qrp_nrm, width - gg, panel, o, ipw, c, nrm);
             }
-            consider(b, nrm, g.base + li, 0);
+            if constexpr (M) consider2(b, b2, nrm, g.base + li, 0);
+            else consider(b, nrm, g.base + li, 0);
         }
         if (last) break;
-        team_select(tm, sm, b, gg == 0 ? bad : 0, panel, g, width, kSelHouseholder, gg);
+        team_select<M>(tm, sm, b, gg == 0 ? bad : 0, panel, g, width, kSelHouseholder, gg, -1.0, b2);
         if (sm.win_flag) return fail_status(sm, LRA_EINVAL, 0);
         if (!(sm.win.v > 0.0)) return fail_status(sm, LRA_ESINGULAR, gg);
+        if constexpr (M) note_margin(sm);
         const int64_t wit = sm.win.item;
         if (tid == 0) out[gg] = wit;
         if (tup && tid < gg) tup[gg * (gg - 1) / 2 + tid] = sm.wrow[tid];
@@ -1102,7 +1166,7 @@ __device__ __forceinline__ void unit_root(int64_t m, int64_t N, double &c_out, d
     }
 }
 
-template <bool kFourier, class Src>
+template <bool kFourier, bool M, class Src>
 __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, uint8_t *flags, const Src &src, int64_t m,
                                           int64_t n, int r, int side, int d, int l, uint64_t seed, int64_t *out,
                                           const int32_t *bd) {
@@ -1278,7 +1342,7 @@ __device__ __forceinline__ void sketch_qrp(Team &tm, Smem &sm, double *panel, ui
     for (int li = tid; li < g.cnt; li += kBlock) flags[li] = 0;
     __syncthreads();
     LRA_TR(3, 0);
-    team_qrp(tm, sm, panel, flags, g, kFourier ? 2 * l : l, r, bad, false, out, nullptr, nullptr);
+    team_qrp<M>(tm, sm, panel, flags, g, kFourier ? 2 * l : l, r, bad, false, out, nullptr, nullptr);
     if (sm.status != LRA_OK) return;
     __syncthreads();
 #ifdef LRA_TRACE
@@ -1416,7 +1480,7 @@ __device__ __forceinline__ void projvol_select(Team &tm, Smem &sm, double *panel
 // on a sketch); swaps_base and team_report fold in an earlier phase.
 // kFourier: the instantiation that seeds from the abridged Fourier sketch
 // (a separate kernel, so that the other starts carry none of its code).
-template <bool kFourier = false, class Src>
+template <bool kFourier, bool M, class Src>
 __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_t *flags, const Src &src, int64_t m,
                                         int64_t n, uint64_t seed, const CAConfig &cfg, int64_t *I_out, int64_t *J_out,
                                         double *U_out, lra_info *info, const int64_t *imap = nullptr,
@@ -1431,6 +1495,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
         sm.rank_found = r;
         sm.nucleus_rank = r;
         sm.xfail = 0;
+        sm.mmin = 1.0;
 #ifdef LRA_TRACE
         sm.t_select = 0;
         sm.t_part[0] = sm.t_part[1] = sm.t_part[2] = sm.t_part[3] = sm.t_part[4] = 0;
@@ -1452,10 +1517,10 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
         if (cfg.sketch_ws) {
             const int64_t st_s = (((side ? n : m) + tm.size - 1) / tm.size) | 1;
             const int wsk = kFourier ? 2 * cfg.ah_samples : cfg.ah_samples;
-            sketch_qrp<kFourier>(tm, sm, cfg.sketch_ws + (size_t)tm.rank * st_s * wsk, flags, src, m, n, r, side,
+            sketch_qrp<kFourier, M>(tm, sm, cfg.sketch_ws + (size_t)tm.rank * st_s * wsk, flags, src, m, n, r, side,
                                  cfg.ah_depth, cfg.ah_samples, seed, side ? sm.Jset : sm.Iset, bd);
         } else {
-            sketch_qrp<kFourier>(tm, sm, dyn, flags, src, m, n, r, side, cfg.ah_depth, cfg.ah_samples, seed,
+            sketch_qrp<kFourier, M>(tm, sm, dyn, flags, src, m, n, r, side, cfg.ah_depth, cfg.ah_samples, seed,
                                  side ? sm.Jset : sm.Iset, bd);
         }
         if (sm.status != LRA_OK) goto finish;
@@ -1479,7 +1544,7 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     // step per sweep (one call site: the step is inlined once)
     for (int st = 0; st < seed_step + 2 * cfg.sweeps; st++) {
         const bool col = st >= seed_step && ((st - seed_step) & 1) == 0;
-        ca_step(tm, sm, dyn, flags, src, m, n, r, col, col ? sm.Jset : sm.Iset, col ? sm.Iset : sm.Jset, cfg,
+        ca_step<M>(tm, sm, dyn, flags, src, m, n, r, col, col ? sm.Jset : sm.Iset, col ? sm.Iset : sm.Jset, cfg,
                 swaps_total, converged);
         if (sm.status != LRA_OK) goto finish;
         if (st < seed_step || col) continue;
@@ -1514,7 +1579,37 @@ __device__ __forceinline__ void ca_solve(Team &tm, Smem &sm, double *dyn, uint8_
     LRA_TR(21, 0);
 finish:
     __syncthreads();
+    // the run's smallest decision margin: a team folds every workgroup's own
+    // into the info record's margin word (zeroed before the launch) as the
+    // complement of its bits, so that the largest word holds the smallest
+    // margin, and counts arrivals in its spare word; workgroup 0 waits for all
+    double mm = __builtin_nan("");
+    if constexpr (M) {
+        if (tm.size == 1) {
+            mm = sm.mmin;
+        } else if (info && tid == 0) {
+            unsigned long long *mw = reinterpret_cast<unsigned long long *>(&info->min_margin);
+            unsigned *cnt = reinterpret_cast<unsigned *>(&info->reserved);
+            atomicMax(mw, ~(unsigned long long)__double_as_longlong(sm.mmin));
+            __threadfence();
+            atomicAdd(cnt, 1u);
+            if (tm.rank == 0) {
+                const uint64_t t0 = wall_clock64();
+                while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)tm.size) {
+                    if (wall_clock64() - t0 > tm.spin_limit) {
+                        sm.xfail = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __threadfence();
+                mm = __longlong_as_double(
+                    (long long)~__hip_atomic_load(mw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            }
+        }
+    }
     if (tm.rank != 0) return;
+    __syncthreads();
     const int st = sm.xfail ? LRA_EDEVICE : sm.status;
     if (tid < r) {
         I_out[tid] = st == LRA_OK ? (imap ? imap[sm.Iset[tid]] : sm.Iset[tid]) : -1;
@@ -1533,12 +1628,13 @@ finish:
         inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
         inf.reserved = 0;
         inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
+        inf.min_margin = mm;
         *info = inf;
     }
 }
 
 // ---------------------------------------------------------------- kernels
-template <typename T, bool kFourier = false>
+template <typename T, bool kFourier, bool M>
 __global__ void __launch_bounds__(kBlock) ca_team_kernel(const T *A, int64_t m, int64_t n, int64_t lda, uint64_t seed,
                                                          CAConfig cfg, TeamWs ws, int64_t *I_out, int64_t *J_out,
                                                          double *U_out, lra_info *info) {
@@ -1552,11 +1648,11 @@ __global__ void __launch_bounds__(kBlock) ca_team_kernel(const T *A, int64_t m, 
     tm.epoch = 0;
     tm.xw = ws.xw;
     tm.spin_limit = ws.spin_limit;
-    ca_solve<kFourier>(tm, sm, dyn, flags, DenseSrc<T>{A, lda}, m, n, seed, cfg, I_out, J_out, U_out, info);
+    ca_solve<kFourier, M>(tm, sm, dyn, flags, DenseSrc<T>{A, lda}, m, n, seed, cfg, I_out, J_out, U_out, info);
 }
 
 // C-A CUR of the pre-processed matrix W' = W M (HadamardSrc), m x N.
-template <typename T>
+template <typename T, bool M>
 __global__ void __launch_bounds__(kBlock) ca_hadamard_kernel(const T *A, int64_t m, int64_t n, int64_t lda, int d,
                                                              uint64_t seed, CAConfig cfg, TeamWs ws, int64_t *I_out,
                                                              int64_t *J_out, double *U_out, lra_info *info) {
@@ -1572,7 +1668,7 @@ __global__ void __launch_bounds__(kBlock) ca_hadamard_kernel(const T *A, int64_t
     tm.spin_limit = ws.spin_limit;
     const int q2 = 1 << d;
     const int64_t s = (n + q2 - 1) / q2;
-    ca_solve(tm, sm, dyn, flags, HadamardSrc<T>{A, lda, n, s, q2, seed}, m, (int64_t)q2 * s, seed, cfg, I_out, J_out,
+    ca_solve<false, M>(tm, sm, dyn, flags, HadamardSrc<T>{A, lda, n, s, q2, seed}, m, (int64_t)q2 * s, seed, cfg, I_out, J_out,
              U_out, info);
 }
 
@@ -1617,9 +1713,9 @@ __global__ void __launch_bounds__(kBlock) ca_cynical_kernel(const T *A, int64_t 
     __syncthreads();
     int32_t swaps = 0, converged = 1;
     for (int s = 0; s < loops; s++) {
-        ca_step(tm, sm, dyn, flags, src, m, n, k, true, sm.Jset, sm.Iset, cfg_k, swaps, converged);
+        ca_step<false>(tm, sm, dyn, flags, src, m, n, k, true, sm.Jset, sm.Iset, cfg_k, swaps, converged);
         if (sm.status != LRA_OK) break;
-        ca_step(tm, sm, dyn, flags, src, m, n, k, false, sm.Iset, sm.Jset, cfg_k, swaps, converged);
+        ca_step<false>(tm, sm, dyn, flags, src, m, n, k, false, sm.Iset, sm.Jset, cfg_k, swaps, converged);
         if (sm.status != LRA_OK) break;
         bool same = s > 0;
         for (int j = 0; j < k && same; j++) same = (sm.Iset[j] == sm.Iprev[j]) && (sm.Jset[j] == sm.Jprev[j]);
@@ -1652,6 +1748,7 @@ __global__ void __launch_bounds__(kBlock) ca_cynical_kernel(const T *A, int64_t 
             inf.nucleus_rank = 0;
             inf.reserved = 0;
             inf.det_log_abs = 0.0;
+            inf.min_margin = __builtin_nan("");
             *info = inf;
         }
         return;
@@ -1670,7 +1767,7 @@ __global__ void __launch_bounds__(kBlock) ca_cynical_kernel(const T *A, int64_t 
     solo.epoch = 0;
     solo.xw = nullptr;
     solo.spin_limit = 0;
-    ca_solve(solo, sm, dyn, flags, IndexedSrc<T>{A, lda, Kset, Lset}, k, k, seed + 1, cfg_r, I_out, J_out, U_out,
+    ca_solve<false, false>(solo, sm, dyn, flags, IndexedSrc<T>{A, lda, Kset, Lset}, k, k, seed + 1, cfg_r, I_out, J_out, U_out,
              info, Kset, Lset, swaps, team);
 }
 
@@ -1762,6 +1859,7 @@ __global__ void __launch_bounds__(kBlock) ca_projective_kernel(const T *A, int64
         inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
         inf.reserved = 0;
         inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
+        inf.min_margin = __builtin_nan("");
         *info = inf;
     }
 }
@@ -1824,6 +1922,7 @@ __global__ void __launch_bounds__(kBlock) ca_uniform_kernel(const T *base, const
             inf.nucleus_rank = bad ? 0 : sm.nucleus_rank;
             inf.reserved = 0;
             inf.det_log_abs = bad ? 0.0 : sm.logdet;
+            inf.min_margin = __builtin_nan("");
             infos[b] = inf;
         }
         __syncthreads();
@@ -2113,11 +2212,12 @@ __global__ void __launch_bounds__(kBlock) lev_pick_kernel(const T *A, int64_t m,
         inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
         inf.reserved = 0;
         inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
+        inf.min_margin = __builtin_nan("");
         *info = inf;
     }
 }
 
-template <typename T>
+template <typename T, bool M>
 __global__ void __launch_bounds__(kBlock) ca_batched_kernel(const T *base, const BlockDesc *blocks, const int32_t *order,
                                                             int64_t count, uint64_t seed, CAConfig cfg, unsigned *queue,
                                                             int64_t *I_out, int64_t *J_out, double *U_out,
@@ -2141,7 +2241,7 @@ __global__ void __launch_bounds__(kBlock) ca_batched_kernel(const T *base, const
         if (job >= count) break;
         const int32_t b = order[job];
         const BlockDesc d = blocks[b];
-        ca_solve(tm, sm, dyn, flags, DenseSrc<T>{base + d.offset, d.lda}, d.m, d.n, seed + (uint64_t)b, cfg,
+        ca_solve<false, M>(tm, sm, dyn, flags, DenseSrc<T>{base + d.offset, d.lda}, d.m, d.n, seed + (uint64_t)b, cfg,
                  I_out + (int64_t)b * r, J_out + (int64_t)b * r, U_out + (int64_t)b * r * r,
                  infos ? infos + b : nullptr);
         __syncthreads();
@@ -2150,6 +2250,7 @@ __global__ void __launch_bounds__(kBlock) ca_batched_kernel(const T *base, const
 
 // Far-field blocks evaluated from their point sets: the batched loop with
 // entries computed on the fly.
+template <bool M>
 __global__ void __launch_bounds__(kBlock) ca_points_kernel(const double *pts, const PtsDesc *blocks,
                                                            const int32_t *order, int64_t count, uint64_t seed,
                                                            CAConfig cfg, unsigned *queue, int64_t *I_out,
@@ -2173,7 +2274,7 @@ __global__ void __launch_bounds__(kBlock) ca_points_kernel(const double *pts, co
         if (job >= count) break;
         const int32_t b = order[job];
         const PtsDesc d = blocks[b];
-        ca_solve(tm, sm, dyn, flags, PointSrc{pts + 2 * d.x_off, pts + 2 * d.y_off}, d.m, d.n, seed + (uint64_t)b, cfg,
+        ca_solve<false, M>(tm, sm, dyn, flags, PointSrc{pts + 2 * d.x_off, pts + 2 * d.y_off}, d.m, d.n, seed + (uint64_t)b, cfg,
                  I_out + (int64_t)b * r, J_out + (int64_t)b * r, U_out + (int64_t)b * r * r,
                  infos ? infos + b : nullptr);
         __syncthreads();
@@ -2189,18 +2290,32 @@ __global__ void zero_u64_kernel(uint64_t *p, int64_t n) {
         p[i] = 0ull;
 }
 
+// The exchange words, and (info non-null) the info record's margin word and
+// arrival counter, which a team's workgroups fold their margins into.
+__global__ void zero_team_kernel(uint64_t *p, int64_t n, lra_info *info) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+    if (info && blockIdx.x == 0 && threadIdx.x == 0) {
+        info->reserved = 0;
+        *reinterpret_cast<unsigned long long *>(&info->min_margin) = 0ull;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename T>
 static hipError_t launch_team_t(const void *A, int64_t m, int64_t n, int64_t lda, uint64_t seed, const CAConfig &cfg,
                                 const TeamWs &ws, int team, size_t dyn_bytes, int64_t *I_out, int64_t *J_out,
                                 double *U_out, lra_info *info, hipStream_t stream) {
-    auto kern = cfg.pre == LRA_PRE_ASRFT ? ca_team_kernel<T, true> : ca_team_kernel<T, false>;
+    // margins (cfg.margins) select the instantiation that tracks them
+    auto kern = cfg.margins ? (cfg.pre == LRA_PRE_ASRFT ? ca_team_kernel<T, true, true> : ca_team_kernel<T, false, true>)
+                            : (cfg.pre == LRA_PRE_ASRFT ? ca_team_kernel<T, true, false>
+                                                        : ca_team_kernel<T, false, false>);
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     if (team > 1) {
         const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
-        hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
-                           stream, ws.xw, words);
+        hipLaunchKernelGGL(zero_team_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
+                           stream, ws.xw, words, cfg.margins ? info : nullptr);
     }
     const T *Ap = static_cast<const T *>(A);
     CAConfig c = cfg;
@@ -2228,13 +2343,13 @@ template <typename T>
 static hipError_t launch_hadamard_t(const void *A, int64_t m, int64_t n, int64_t lda, int d, uint64_t seed,
                                     const CAConfig &cfg, const TeamWs &ws, int team, size_t dyn_bytes, int64_t *I_out,
                                     int64_t *J_out, double *U_out, lra_info *info, hipStream_t stream) {
-    auto kern = ca_hadamard_kernel<T>;
+    auto kern = cfg.margins ? ca_hadamard_kernel<T, true> : ca_hadamard_kernel<T, false>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     if (team > 1) {
         const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
-        hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
-                           stream, ws.xw, words);
+        hipLaunchKernelGGL(zero_team_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
+                           stream, ws.xw, words, cfg.margins ? info : nullptr);
     }
     const T *Ap = static_cast<const T *>(A);
     CAConfig c = cfg;
@@ -2431,7 +2546,7 @@ static hipError_t launch_batched_t(const void *base, const BlockDesc *blocks, co
                                    uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
                                    int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos,
                                    hipStream_t stream) {
-    auto kern = ca_batched_kernel<T>;
+    auto kern = cfg.margins ? ca_batched_kernel<T, true> : ca_batched_kernel<T, false>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, queue, 1);
@@ -2459,18 +2574,18 @@ hipError_t launch_batched(int dtype, const void *base, const BlockDesc *blocks, 
 hipError_t launch_points(const double *pts, const PtsDesc *blocks, const int32_t *order, int64_t count,
                          uint64_t seed, const CAConfig &cfg, unsigned *queue, int grid, size_t dyn_bytes,
                          int64_t *I_out, int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream) {
-    hipError_t e =
-        hipFuncSetAttribute((const void *)ca_points_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
+    auto kern = cfg.margins ? ca_points_kernel<true> : ca_points_kernel<false>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, queue, 1);
-    hipLaunchKernelGGL(ca_points_kernel, dim3(grid), dim3(kBlock), dyn_bytes, stream, pts, blocks, order, count, seed,
-                       cfg, queue, I_out, J_out, U_out, infos);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), dyn_bytes, stream, pts, blocks, order, count, seed, cfg, queue,
+                       I_out, J_out, U_out, infos);
     return hipGetLastError();
 }
 
 int points_occupancy(size_t dyn_bytes) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_points_kernel, kBlock, dyn_bytes) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_points_kernel<true>, kBlock, dyn_bytes) != hipSuccess)
         return 0;
     return blocks;
 }
@@ -2479,11 +2594,11 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
     int blocks = 0;
     hipError_t e;
     if (dtype == LRA_F64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_batched_kernel<double>, kBlock, dyn_bytes);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_batched_kernel<double, true>, kBlock, dyn_bytes);
     else if (dtype == LRA_F32)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_batched_kernel<float>, kBlock, dyn_bytes);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_batched_kernel<float, true>, kBlock, dyn_bytes);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_batched_kernel<uint16_t>, kBlock, dyn_bytes);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, ca_batched_kernel<uint16_t, true>, kBlock, dyn_bytes);
     if (e != hipSuccess) return 0;
     return blocks;
 }
@@ -2494,17 +2609,41 @@ int batched_occupancy(int dtype, size_t dyn_bytes) {
 size_t static_lds_bytes() {
     static size_t bytes = 0;
     if (bytes == 0) {
-        const void *fns[22] = {(const void *)ca_team_kernel<double>,       (const void *)ca_team_kernel<float>,
-                               (const void *)ca_team_kernel<uint16_t>,     (const void *)ca_batched_kernel<double>,
-                               (const void *)ca_batched_kernel<float>,     (const void *)ca_batched_kernel<uint16_t>,
-                               (const void *)ca_points_kernel,             (const void *)ca_cynical_kernel<double>,
-                               (const void *)ca_cynical_kernel<float>,     (const void *)ca_cynical_kernel<uint16_t>,
-                               (const void *)ca_hadamard_kernel<double>,   (const void *)ca_hadamard_kernel<float>,
-                               (const void *)ca_hadamard_kernel<uint16_t>, (const void *)ca_projective_kernel<double>,
-                               (const void *)ca_projective_kernel<float>,  (const void *)ca_projective_kernel<uint16_t>,
-                               (const void *)ca_uniform_kernel<double>,    (const void *)ca_uniform_kernel<float>,
-                               (const void *)ca_uniform_kernel<uint16_t>,  (const void *)ca_team_kernel<double, true>,
-                               (const void *)ca_team_kernel<float, true>,  (const void *)ca_team_kernel<uint16_t, true>};
+        const void *fns[] = {(const void *)ca_team_kernel<double, false, false>,
+                             (const void *)ca_team_kernel<float, false, false>,
+                             (const void *)ca_team_kernel<uint16_t, false, false>,
+                             (const void *)ca_team_kernel<double, false, true>,
+                             (const void *)ca_team_kernel<float, false, true>,
+                             (const void *)ca_team_kernel<uint16_t, false, true>,
+                             (const void *)ca_team_kernel<double, true, false>,
+                             (const void *)ca_team_kernel<float, true, false>,
+                             (const void *)ca_team_kernel<uint16_t, true, false>,
+                             (const void *)ca_team_kernel<double, true, true>,
+                             (const void *)ca_team_kernel<float, true, true>,
+                             (const void *)ca_team_kernel<uint16_t, true, true>,
+                             (const void *)ca_batched_kernel<double, false>,
+                             (const void *)ca_batched_kernel<float, false>,
+                             (const void *)ca_batched_kernel<uint16_t, false>,
+                             (const void *)ca_batched_kernel<double, true>,
+                             (const void *)ca_batched_kernel<float, true>,
+                             (const void *)ca_batched_kernel<uint16_t, true>,
+                             (const void *)ca_points_kernel<false>,
+                             (const void *)ca_points_kernel<true>,
+                             (const void *)ca_cynical_kernel<double>,
+                             (const void *)ca_cynical_kernel<float>,
+                             (const void *)ca_cynical_kernel<uint16_t>,
+                             (const void *)ca_hadamard_kernel<double, false>,
+                             (const void *)ca_hadamard_kernel<float, false>,
+                             (const void *)ca_hadamard_kernel<uint16_t, false>,
+                             (const void *)ca_hadamard_kernel<double, true>,
+                             (const void *)ca_hadamard_kernel<float, true>,
+                             (const void *)ca_hadamard_kernel<uint16_t, true>,
+                             (const void *)ca_projective_kernel<double>,
+                             (const void *)ca_projective_kernel<float>,
+                             (const void *)ca_projective_kernel<uint16_t>,
+                             (const void *)ca_uniform_kernel<double>,
+                             (const void *)ca_uniform_kernel<float>,
+                             (const void *)ca_uniform_kernel<uint16_t>};
         size_t mx = sizeof(Smem) + sizeof(int) * kRMax;
         for (const void *f : fns) {
             hipFuncAttributes attr;

@@ -106,6 +106,98 @@ __device__ __forceinline__ Best wave_reduce(Best b) {
     return wave_reduce_full(b);
 }
 
+// Largest value over the wavefront, in every lane.
+__device__ __forceinline__ double wave_max(double v) {
+    v = dpp_max<kDppQuadSwap1>(v);
+    v = dpp_max<kDppQuadSwap2>(v);
+    v = dpp_max<kDppHalfMirror>(v);
+    v = dpp_max<kDppMirror>(v);
+    v = dpp_max<kDppRowBcast15, 0xa>(v);
+    v = dpp_max<kDppRowBcast31, 0xc>(v);
+    return __longlong_as_double(rdl64(__double_as_longlong(v), 63));
+}
+
+// Largest value over lanes 0..7, in every lane.
+__device__ __forceinline__ double max8(double v) {
+    v = dpp_max<kDppQuadSwap1>(v);
+    v = dpp_max<kDppQuadSwap2>(v);
+    v = dpp_max<kDppHalfMirror>(v);
+    return __longlong_as_double(rdl64(__double_as_longlong(v), 0));
+}
+
+// The best two values of two disjoint candidate sets, merged: the lane's
+// (m, m2) with those of the lane the DPP control names; a lane the row mask
+// leaves unwritten merges with the empty set (-1, -1).
+template <int CTRL, int RM = 0xf>
+__device__ __forceinline__ void pair_step(double &m, double &m2) {
+    constexpr int kNegOneHi = (int)0xBFF00000;  // high word of -1.0 (low word 0)
+    const uint64_t a = (uint64_t)__double_as_longlong(m), a2 = (uint64_t)__double_as_longlong(m2);
+    const int olo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)a, CTRL, RM, 0xf, false);
+    const int ohi = __builtin_amdgcn_update_dpp(kNegOneHi, (int)(uint32_t)(a >> 32), CTRL, RM, 0xf, false);
+    const int plo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)a2, CTRL, RM, 0xf, false);
+    const int phi = __builtin_amdgcn_update_dpp(kNegOneHi, (int)(uint32_t)(a2 >> 32), CTRL, RM, 0xf, false);
+    const double o = __longlong_as_double((long long)(((uint64_t)(uint32_t)ohi << 32) | (uint32_t)olo));
+    const double o2 = __longlong_as_double((long long)(((uint64_t)(uint32_t)phi << 32) | (uint32_t)plo));
+    m2 = fmax(fmax(m2, o2), fmin(m, o));
+    m = fmax(m, o);
+}
+
+// wave_reduce, and the runner-up value of the wavefront (all lanes): the
+// largest value among the lanes' candidates other than the winner, b2 being
+// each lane's own runner-up (-1 for none).  Equal values count, so a tie
+// leaves the runner-up equal to the winner's value.  The best two values
+// travel through the butterflies together (the pair merge of disjoint sets
+// is exact and order-free).
+__device__ __forceinline__ Best wave_reduce2(Best b, double b2, double &v2) {
+    double m = b.v, m2 = b2;
+    pair_step<kDppQuadSwap1>(m, m2);
+    pair_step<kDppQuadSwap2>(m, m2);
+    pair_step<kDppHalfMirror>(m, m2);
+    pair_step<kDppMirror>(m, m2);
+    pair_step<kDppRowBcast15, 0xa>(m, m2);
+    pair_step<kDppRowBcast31, 0xc>(m, m2);
+    const double top = __longlong_as_double(rdl64(__double_as_longlong(m), 63));
+    v2 = __longlong_as_double(rdl64(__double_as_longlong(m2), 63));
+    const unsigned long long hold = __ballot(b.v == top);
+    if (__popcll(hold) == 1) return rdl_best(b, __ffsll((long long)hold) - 1);
+    return wave_reduce_full(b);
+}
+
+// The best two values over lanes 0..7 (others ignored), in every lane.
+__device__ __forceinline__ void top2_8(double &m, double &m2) {
+    pair_step<kDppQuadSwap1>(m, m2);
+    pair_step<kDppQuadSwap2>(m, m2);
+    pair_step<kDppHalfMirror>(m, m2);
+    m = __longlong_as_double(rdl64(__double_as_longlong(m), 0));
+    m2 = __longlong_as_double(rdl64(__double_as_longlong(m2), 0));
+}
+
+// The best two values over the wavefront, in every lane.
+__device__ __forceinline__ void top2_wave(double &m, double &m2) {
+    pair_step<kDppQuadSwap1>(m, m2);
+    pair_step<kDppQuadSwap2>(m, m2);
+    pair_step<kDppHalfMirror>(m, m2);
+    pair_step<kDppMirror>(m, m2);
+    pair_step<kDppRowBcast15, 0xa>(m, m2);
+    pair_step<kDppRowBcast31, 0xc>(m, m2);
+    m = __longlong_as_double(rdl64(__double_as_longlong(m), 63));
+    m2 = __longlong_as_double(rdl64(__double_as_longlong(m2), 63));
+}
+
+// A candidate's value v, tracked with the runner-up b2 of the candidates seen
+// so far (the largest value other than the best one; -1 for none).
+__device__ __forceinline__ void consider2(Best &b, double &b2, double v, int64_t item, int slot) {
+    b2 = fmax(b2, fmin(v, b.v));
+    consider(b, v, item, slot);
+}
+
+// The relative gap (v1 - v2) / v1 between a decision's winner and runner-up
+// (1 without a runner-up, 0 for a zero winner).
+__device__ __forceinline__ double decision_gap(double v1, double v2) {
+    if (v2 < 0.0) return 1.0;
+    return v1 > 0.0 ? (v1 - v2) / v1 : 0.0;
+}
+
 // The same over lanes 0..7 only (the other lanes' values are ignored): the
 // two quad swaps and the half-row mirror combine the first eight lanes.
 __device__ __forceinline__ Best reduce8(Best b) {

@@ -74,6 +74,7 @@ struct DmmSmem {
     int status;
     int32_t nucleus_rank;
     double logdet;
+    double mmin;   // smallest distance of a draw from its item's boundaries, relative to S
 };
 
 // Entry (item, c) of the row-step sketch W[:, J] D (ROWS) or of the
@@ -261,7 +262,7 @@ __device__ __forceinline__ void dmm_half(DmmSmem &sm, double *lds, const DenseSr
     if (tid < kWave) {
         const double S = sm.carry;
         int64_t idx = INT64_MAX;
-        double sc = 0.0;
+        double sc = 0.0, gap = 1.0;
         if (tid < cnt) {
             const double u = (double)(sm64(seed, stream, (uint64_t)tid) >> 11) * 0x1p-53;
             const double target = u * S;
@@ -273,7 +274,10 @@ __device__ __forceinline__ void dmm_half(DmmSmem &sm, double *lds, const DenseSr
             }
             idx = lo;
             sc = 1.0 / sqrt(((double)cnt * q[lo]) / S);
+            gap = fmin((cdf[lo] - target) / S, (target - (lo > 0 ? cdf[lo - 1] : 0.0)) / S);
         }
+        gap = -wave_max(-gap);
+        if (tid == 0) sm.mmin = fmin(sm.mmin, gap);
         int rank = 0;
         for (int j = 0; j < cnt; j++) {
             const int64_t y = __shfl(idx, j);
@@ -313,7 +317,10 @@ __global__ void __launch_bounds__(kBlock) ca_dmm_kernel(const T *base, const Blo
             __builtin_amdgcn_wave_barrier();
             sort_set_wave(sm.Jset, l);
             if (tid < l) sm.dl[tid] = sqrt((double)d.n / (double)l);
-            if (tid == 0) sm.status = LRA_OK;
+            if (tid == 0) {
+                sm.status = LRA_OK;
+                sm.mmin = 1.0;
+            }
         }
         __syncthreads();
         int t = 0;
@@ -346,6 +353,7 @@ __global__ void __launch_bounds__(kBlock) ca_dmm_kernel(const T *base, const Blo
             inf.nucleus_rank = st == LRA_OK ? sm.nucleus_rank : 0;
             inf.reserved = 0;
             inf.det_log_abs = st == LRA_OK ? sm.logdet : 0.0;
+            inf.min_margin = sm.mmin;
             infos[b] = inf;
         }
         __syncthreads();

@@ -30,6 +30,7 @@ struct CAConfig {
     const int64_t *init_cols; // device copy of the warm-start columns, or null
     double *sketch_ws;        // global sketch panels [team][ipw * l] when they do not fit LDS, else null
     const int32_t *bd_table;  // bidiagonal start: per sampled column its term count, positions, coefficients
+    int32_t margins;          // 1: report the decisions' smallest margin in lra_info.min_margin (else NaN)
 };
 
 // Complex coefficients of the abridged Fourier sketch (l 2^d <= kAftCoefs,
@@ -111,6 +112,7 @@ hipError_t launch_dmm(int dtype, const void *base, const BlockDesc *blocks, int6
                       int64_t *J_out, double *U_out, lra_info *infos, hipStream_t stream);
 size_t static_lds_bytes();
 __global__ void zero_u32_kernel(unsigned *p, int n);
+__global__ void zero_team_kernel(uint64_t *p, int64_t n, lra_info *info);
 
 // Batched C-A with register-resident panels (lra_batch.hip): variants exist
 // for rank r and P items per lane; `src` is the dtype code, or 3 for point sets.

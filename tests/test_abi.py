@@ -40,10 +40,13 @@ def test_strerror(lib):
 
 
 def test_struct_layouts():
-    assert ct.sizeof(lra.lra_info) == 40
+    assert ct.sizeof(lra.lra_info) == 48
     assert ct.sizeof(lra.lra_block) == 32
     assert ct.sizeof(lra.lra_pts_block) == 32
-    assert ct.sizeof(lra.lra_opts) == 40
+    assert ct.sizeof(lra.lra_opts) == 48
+    assert lra.lra_opts.track_margin.offset == 32 and lra.lra_opts.init_cols.offset == 40
+    assert lra.lra_info.min_margin.offset == 40
+    assert lra.lra_default_opts().track_margin == 0      # margins are opt-in
 
 
 def _call(lib, m=100, n=80, lda=80, r=5, sweeps=2, dt=1, opts=None, ptr=0x1000):

@@ -57,7 +57,7 @@ def to_device(flat):
 
 def run(lra, base, desc, r, sweeps, seed, rules, **kw):
     lra.lra_batch_set_rules(rules)
-    out = lra.lra_cur_batched(base, desc, r, sweeps, seed, **kw)
+    out = lra.lra_cur_batched(base, desc, r, sweeps, seed, track_margin=True, **kw)
     torch.cuda.synchronize()
     return out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy(), out.info()
 
@@ -138,7 +138,7 @@ def test_points_variants_equal_the_lds_kernel(lra):
     outs = []
     for rules in (LDS_ONLY, []):
         lra.lra_batch_set_rules(rules)
-        out = lra.lra_cur_batched_points(dpts, desc, 16, 3, 300)
+        out = lra.lra_cur_batched_points(dpts, desc, 16, 3, 300, track_margin=True)
         torch.cuda.synchronize()
         outs.append((out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy(), out.info()))
     same(outs[1], outs[0])

@@ -35,7 +35,7 @@ def test_cynical_512_fp64(lra, loops):
     A = workloads.orthogonal_lowrank()
     o = oracle.cynical(A, 10, 40, loops, 3, 2001)
     g = gpu_cynical(lra, A, 10, 40, loops, 3, 2001)
-    assert_parity(A, g, o, 1e-6)
+    assert_parity(A, g, o, 1e-6, margin=False)
     assert g[3]["team_size"] == (1 if loops == 0 else 4)
 
 
@@ -46,7 +46,7 @@ def test_cynical_fp32_rank16_k64_team(lra):
     o = oracle.cynical(A, 16, 64, 1, 3, 9)
     g = gpu_cynical(lra, A, 16, 64, 1, 3, 9)
     assert g[3]["team_size"] > 1
-    assert_parity(A, g, o, 1e-4)
+    assert_parity(A, g, o, 1e-4, margin=False)
 
 
 def test_cynical_team_size_does_not_change_results(lra):

@@ -61,6 +61,8 @@ def check(g, o, A):
     if o.min_margin > 1e-9:
         assert I.tolist() == o.I.tolist() and J.tolist() == o.J.tolist()
         assert info["nucleus_rank"] == o.nucleus_rank
+        # the sampling margin: the same draws, running sums equal to rounding
+        assert abs(info["min_margin"] - o.min_margin) <= 1e-12, (info["min_margin"], o.min_margin)
         Xo = A64[:, o.J] @ o.U @ A64[o.I]
         d = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
         print("  sets equal, recon diff %.2e (margin %.1e)" % (d, o.min_margin), flush=True)

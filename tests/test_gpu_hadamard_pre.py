@@ -26,7 +26,7 @@ def lra():
 def gpu_hadamard(lra, A_np, r, sweeps, seed, d, **kw):
     print("gpu_hadamard", A_np.shape, A_np.dtype, "r=%d sweeps=%d seed=%d d=%d" % (r, sweeps, seed, d), kw,
           flush=True)
-    out = lra.lra_cur_hadamard(torch.from_numpy(A_np).cuda(), r, sweeps, seed, d, **kw)
+    out = lra.lra_cur_hadamard(torch.from_numpy(A_np).cuda(), r, sweeps, seed, d, track_margin=True, **kw)
     torch.cuda.synchronize()
     return out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy(), out.info()
 

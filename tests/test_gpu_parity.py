@@ -36,6 +36,7 @@ def gpu_cur(lra, A_np, r, sweeps, seed, **kw):
         A = torch.from_numpy(A_np.view(np.int16)).view(torch.bfloat16).cuda()
     else:
         A = torch.from_numpy(A_np).cuda()
+    kw.setdefault("track_margin", True)
     out = lra.lra_cur(A, r, sweeps, seed, **kw)
     torch.cuda.synchronize()
     return out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy(), out.info()
@@ -51,7 +52,10 @@ def recon_rows(A64, I, J, U, rows):
     return A64[np.ix_(rows, J)] @ U @ A64[I]
 
 
-def assert_parity(A_np, g, o, tol, sample_rows=None):
+def assert_parity(A_np, g, o, tol, sample_rows=None, margin=True):
+    """margin: the entry point reports lra_info.min_margin (the C-A paths),
+    which then equals the oracle's exactly: both take every decision's
+    winner and runner-up from bit-identical values with the same formula."""
     I, J, U, info = g
     assert info["status"] == o.status, (info, o.status)
     if o.status != 0:
@@ -71,6 +75,10 @@ def assert_parity(A_np, g, o, tol, sample_rows=None):
         assert np.abs(U - o.U).max() <= 1e-12 * np.abs(o.U).max()
         assert info["sweeps_run"] == o.sweeps_run and info["swaps_total"] == o.swaps_total
         assert info["converged"] == o.converged
+        if margin:
+            assert info["min_margin"] == o.min_margin, (info["min_margin"], o.min_margin)
+        else:
+            assert np.isnan(info["min_margin"])
     else:
         # the last row step leaves J dominant in A[I, :]
         R = A64[I]
@@ -84,6 +92,21 @@ def test_cfg_512_fp64_rank10(lra):
     o = oracle.ca_cur(A, 10, 3, 2001)
     g = gpu_cur(lra, A, 10, 3, 2001)
     assert_parity(A, g, o, 1e-6)
+
+
+@pytest.mark.parametrize("team", [1, 4, 125])
+def test_margin_tracking_is_opt_in_and_changes_nothing_else(lra, team):
+    """Without track_margin the info's min_margin is NaN (the instantiation
+    without the runner-up bookkeeping); with it, the oracle's value; the sets,
+    nucleus and every other field are the same either way."""
+    A = workloads.orthogonal_lowrank(900, 700, 12, noise=1e-8, seeds=(8, 9, 10))
+    o = oracle.ca_cur(A, 12, 3, 5, preprocess=1, ah_depth=2, ah_samples=24)
+    g0 = gpu_cur(lra, A, 12, 3, 5, team_size=team, preprocess=1, ah_depth=2, ah_samples=24, track_margin=False)
+    g1 = gpu_cur(lra, A, 12, 3, 5, team_size=team, preprocess=1, ah_depth=2, ah_samples=24)
+    assert np.isnan(g0[3]["min_margin"]) and g1[3]["min_margin"] == o.min_margin
+    assert all(np.array_equal(a, b) for a, b in zip(g0[:3], g1[:3]))
+    assert {k: v for k, v in g0[3].items() if k != "min_margin"} == \
+        {k: v for k, v in g1[3].items() if k != "min_margin"}
 
 
 @pytest.mark.parametrize("team", [1, 2, 3, 7, 64])
@@ -224,7 +247,7 @@ def test_cfg_65536x8192_left_asrht_rank64(lra):
     kw = dict(preprocess=1, ah_depth=3, ah_samples=128, refine_steps=2)
     o = oracle.ca_cur(A, 64, 4, 2051, **kw)
     print("oracle", o.status, o.sweeps_run, o.swaps_total, o.min_margin, flush=True)
-    out = lra.lra_cur(Ad, 64, 4, 2051, **kw)
+    out = lra.lra_cur(Ad, 64, 4, 2051, track_margin=True, **kw)
     torch.cuda.synchronize()
     g = (out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy(), out.info())
     print("gpu", g[3], flush=True)
@@ -249,7 +272,7 @@ def test_batched_matches_oracle_and_plain_calls(lra):
     flat, desc = workloads.fmm_batch(count, shape_seed=5, block_seed0=700)
     base = torch.from_numpy(flat).cuda()
     r = 16
-    out = lra.lra_cur_batched(base, desc, r, 3, 1000)
+    out = lra.lra_cur_batched(base, desc, r, 3, 1000, track_margin=True)
     torch.cuda.synchronize()
     I, J, U = out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy()
     infos = out.info()
@@ -270,7 +293,7 @@ def test_batched_4096_fmm_blocks_sampled(lra):
     spread over the size range checked against the oracle on the same bytes."""
     count, r = 4096, 16
     base, desc = workloads.fmm_batch_device(count, "cuda")
-    out = lra.lra_cur_batched(base, desc, r, 3, 1000)
+    out = lra.lra_cur_batched(base, desc, r, 3, 1000, track_margin=True)
     torch.cuda.synchronize()
     infos = out.info()
     assert all(i["status"] == 0 for i in infos)

@@ -34,7 +34,7 @@ def test_points_match_oracle(lra):
     count, r = 24, 16
     pts, desc = workloads.fmm_points(count, shape_seed=5, block_seed0=700)
     print("points batch", count, "blocks, r=16, 3 sweeps", flush=True)
-    out = lra.lra_cur_batched_points(torch.from_numpy(pts).cuda(), desc, r, 3, 1000)
+    out = lra.lra_cur_batched_points(torch.from_numpy(pts).cuda(), desc, r, 3, 1000, track_margin=True)
     torch.cuda.synchronize()
     I, J, U = out.I.cpu().numpy(), out.J.cpu().numpy(), out.U.cpu().numpy()
     infos = out.info()
@@ -59,8 +59,8 @@ def test_points_equal_the_dense_path_on_oracle_entries(lra):
         off += m * n
     flat = torch.from_numpy(np.concatenate(parts)).cuda()
     print("dense twin of", count, "point blocks", flush=True)
-    dense = lra.lra_cur_batched(flat, np.array(blocks, np.int64), r, 3, 1000)
-    pt = lra.lra_cur_batched_points(torch.from_numpy(pts).cuda(), desc, r, 3, 1000)
+    dense = lra.lra_cur_batched(flat, np.array(blocks, np.int64), r, 3, 1000, track_margin=True)
+    pt = lra.lra_cur_batched_points(torch.from_numpy(pts).cuda(), desc, r, 3, 1000, track_margin=True)
     torch.cuda.synchronize()
     assert torch.equal(dense.I, pt.I) and torch.equal(dense.J, pt.J)
     assert torch.equal(dense.U, pt.U)
@@ -74,7 +74,7 @@ def test_points_4096_blocks_sampled(lra):
     count, r = 4096, 16
     pts, desc = workloads.fmm_points(count)
     print("points batch 4096 blocks", flush=True)
-    out = lra.lra_cur_batched_points(torch.from_numpy(pts).cuda(), desc, r, 3, 1000)
+    out = lra.lra_cur_batched_points(torch.from_numpy(pts).cuda(), desc, r, 3, 1000, track_margin=True)
     torch.cuda.synchronize()
     infos = out.info()
     assert all(i["status"] == 0 for i in infos)
@@ -97,7 +97,7 @@ def test_coinciding_points_flag_only_their_block(lra):
     j0 = int(oracle.draw_distinct(1001, 0, n, 8)[0])  # a column of block 1's start set
     pts[yo + j0] = pts[xo + 7]
     print("points batch with a coinciding pair in block 1", flush=True)
-    out = lra.lra_cur_batched_points(torch.from_numpy(pts).cuda(), desc, 8, 2, 1000)
+    out = lra.lra_cur_batched_points(torch.from_numpy(pts).cuda(), desc, 8, 2, 1000, track_margin=True)
     torch.cuda.synchronize()
     infos = out.info()
     assert infos[1]["status"] == lra.LRA_EINVAL

@@ -146,7 +146,8 @@ def test_random_case(lra, idx):
     try:
         if path in ("plain", "asrht", "bidiag", "fourier"):
             o = oracle.ca_cur(A, c["r"], c["sweeps"], c["seed"], **c["kw"])
-            out = lra.lra_cur(to_dev(A), c["r"], c["sweeps"], c["seed"], team_size=c["team"], **c["kw"])
+            out = lra.lra_cur(to_dev(A), c["r"], c["sweeps"], c["seed"], team_size=c["team"], track_margin=True,
+                              **c["kw"])
         elif path == "projective":
             o = oracle.projective_cur(A, c["r"], c["k"], c["l"], 2, c["seed"], delta=c["delta"])
             out = lra.lra_cur_projective(to_dev(A), c["r"], c["k"], c["l"], 2, c["seed"], delta=c["delta"],
@@ -178,3 +179,10 @@ def test_random_case(lra, idx):
     check_sets(A, I, J, U, info, o, tol, dominant_rows=path in ("plain", "asrht", "bidiag", "fourier"))
     if path == "projective" and o.status == 0 and o.min_margin >= 1e-6:
         assert info["swaps_total"] == o.swaps_total
+    # lra_cur reports the decisions' smallest margin; with the same decisions
+    # (stable, or taken alike) it is the oracle's exactly
+    if path in ("plain", "asrht", "bidiag", "fourier") and o.status == 0:
+        if I.tolist() == o.I.tolist() and J.tolist() == o.J.tolist() and info["swaps_total"] == o.swaps_total:
+            assert info["min_margin"] == o.min_margin, (info["min_margin"], o.min_margin)
+    elif path != "uniform":
+        assert np.isnan(info["min_margin"])

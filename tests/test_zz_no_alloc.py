@@ -37,6 +37,7 @@ def _call(name, A, r, sweeps, seed, **kw):
 
 
 def _same(A, r, sweeps, seed, **kw):
+    kw.setdefault("track_margin", 1)   # every info field, the team's margin word included
     print("noalloc case: %s %s r=%d sweeps=%d seed=%d %s" % (tuple(A.shape), A.dtype, r, sweeps, seed, kw), flush=True)
     ref = _call("lra_cur", A, r, sweeps, seed, **kw)
     got = _call("lra_cur_noalloc", A, r, sweeps, seed, **kw)
