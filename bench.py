@@ -223,6 +223,14 @@ def main():
         "swaps_total": info["swaps_total"],
     }
 
+    # the decisions' smallest margin, from a run of the instantiation that
+    # tracks it (outside the timed steps; its own time reported beside)
+    mout = lra.lra_cur(A, RANK, SWEEPS, SEED, track_margin=True, **kw)
+    ms_tracked = _time_events(torch, lambda: lra.lra_cur(A, RANK, SWEEPS, SEED, out=mout, track_margin=True, **kw),
+                              max(2, args.steps // 5), 1)
+    minfo = mout.info()
+    rec["decision_margin"] = {"min_margin": minfo["min_margin"], "ms_per_lra_tracked": ms_tracked,
+                              "sets_equal_untracked": bool(torch.equal(mout.I, out.I) and torch.equal(mout.J, out.J))}
     hop_ns = lra.lra_probe_exchange(20000)
     sel = selections_per_lra(M, N, RANK, info["sweeps_run"], info["swaps_total"], 1, SAMPLES)
     min_ms = sel * hop_ns * 1e-6
@@ -253,6 +261,7 @@ def main():
         rec["parity"] = {"sets_equal": bool(I.tolist() == res.I.tolist() and J.tolist() == res.J.tolist()),
                          "recon_rel_fro_diff_sampled": float(np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)),
                          "oracle_min_margin": res.min_margin,
+                         "gpu_min_margin": minfo["min_margin"],
                          "rel_fro_err_vs_A_sampled": float(np.linalg.norm(A64 - Xg) / np.linalg.norm(A64))}
     if not args.no_secondary:
         rec["bidiag_start"] = bench_bidiag_start(lra, torch, np, A, args)
