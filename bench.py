@@ -40,26 +40,27 @@ FP64_PEAK_TFS = 78.6
 # sources still hash to it.  The summaries with the commands are under
 # profiles/.
 _CS = "paper_1710_07946_amd/csrc/"
-SRC_TEAM = (_CS + "lra_ca.hip", _CS + "lra_device.h", _CS + "lra_internal.h", "paper_1710_07946_amd/build.py")
+SRC_TEAM = (_CS + "lra_ca.hip", _CS + "lra_common.h", _CS + "lra_device.h", _CS + "lra_internal.h",
+            _CS + "lra_api.hip", "paper_1710_07946_amd/build.py")
 SRC_BATCH = (_CS + "lra_batch.hip", _CS + "lra_common.h", _CS + "lra_device.h", _CS + "lra_internal.h",
              _CS + "lra_api.hip", "paper_1710_07946_amd/build.py")
 SRC_POST = (_CS + "lra_post.hip", _CS + "lra_device.h", _CS + "lra_internal.h", "paper_1710_07946_amd/build.py")
 # line: (sources, SHA-1, FETCH_SIZE KiB per unit, WRITE_SIZE KiB per unit, copy FETCH KiB, copy WRITE KiB)
 TRAFFIC_COUNTS = {
     # one LRA: one ca_team_kernel dispatch (profiles/ca_team_kernel_20000x20000_r50.md)
-    "headline": (SRC_TEAM, "e4fb55dd5835059470c67f35f482ffc065f2c95d", 293640.9, 141207.9, 524308.2, 1048576.0),
+    "headline": (SRC_TEAM, "1be69a080d8c73ac95aa5c72fd20f37a74154901", 295436.3, 108622.0, 524308.3, 1048576.0),
     # one batch: the four bin dispatches of ca_reg_kernel (profiles/ca_reg_kernel_fmm4096_r16.md)
-    "batched": (SRC_BATCH, "f626233ded7b18dabd1602245a98d81aeea90bfd", 4 * 1067069.0, 4 * 2407.2,
-                524308.1, 1048576.0),
+    "batched": (SRC_BATCH, "15c08d321fe1eb4136dd8efe74259436234513e7", 967.0 + 310778.9 + 3948909.4 + 7852.9, 38.0 + 1638.1 + 7639.5 + 313.5,
+                524308.3, 1048576.0),
     # one batch: the four bin dispatches of ca_reg_points_kernel
-    "points": (SRC_BATCH, "f626233ded7b18dabd1602245a98d81aeea90bfd", 4 * 9688.3, 4 * 2407.9,
-               524308.1, 1048576.0),
+    "points": (SRC_BATCH, "15c08d321fe1eb4136dd8efe74259436234513e7", 815.6 + 4329.9 + 32442.1 + 1165.1, 38.0 + 1637.7 + 7643.4 + 313.5,
+               524308.3, 1048576.0),
     # one full residual: the resid_kernel dispatch (FP64 core; BF16 x 3 core)
     # (profiles/resid_kernels_20000x20000_r50.md)
-    "residual_fp64": (SRC_POST, "3e641c35d2fc1e35e48a59e7185335df640bce19", 971912.0, 68.7, 524308.1, 1048576.0),
-    "residual_mixed": (SRC_POST, "3e641c35d2fc1e35e48a59e7185335df640bce19", 960211.1, 68.7, 524308.1, 1048576.0),
+    "residual_fp64": (SRC_POST, "f1303d01f45c7773b3be4cf878c8f19ad5c3c0bd", 968806.6, 68.7, 524308.3, 1048576.0),
+    "residual_mixed": (SRC_POST, "f1303d01f45c7773b3be4cf878c8f19ad5c3c0bd", 959549.0, 68.7, 524308.3, 1048576.0),
     # one launch of 256 blocks: the seven adj_* dispatches (profiles/adjoint_kernels_256x2048_r32.md)
-    "adjoint": (SRC_POST, "3e641c35d2fc1e35e48a59e7185335df640bce19", 1174547.9, 563408.0, 524308.1, 1048576.0),
+    "adjoint": (SRC_POST, "f1303d01f45c7773b3be4cf878c8f19ad5c3c0bd", 1174108.9, 563413.1, 524308.3, 1048576.0),
 }
 
 
