@@ -135,7 +135,7 @@ lra_status lra_cur(const void *W, lra_dtype dt, int64_t m, int64_t n, int64_t ld
                    double *U_out, lra_info *info, hipStream_t stream);
 
 /* Bytes of device scratch that lra_cur_noalloc keeps on each GPU it runs on. */
-#define LRA_NOALLOC_SCRATCH_BYTES 10626048
+#define LRA_NOALLOC_SCRATCH_BYTES 10683392
 
 /* lra_cur for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same

@@ -101,7 +101,7 @@ struct Smem {
 struct Team {
     int rank, size;
     unsigned epoch;   // number of team selections so far (same in every workgroup)
-    uint64_t *xw;     // exchange words: headers [2][size][kHdrWords], then rows [2][size][kRowWords]; zeroed per launch
+    uint64_t *xw;     // exchange words: headers [2][size][kHdrStride], then rows [2][size][kRowWords]; zeroed per launch
     uint64_t spin_limit;  // wall-clock ticks a poll may wait
 };
 
@@ -385,11 +385,11 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
         } else {
             const uint32_t tag = tm.epoch + 1u, htag = tag & 0xfu;
             const int par = tm.epoch & 1;
-            // all headers of a parity are contiguous (one coalesced read per
-            // wave); rows live in a separate region
-            uint64_t *hdrs = tm.xw + (size_t)par * tm.size * kHdrWords;
-            uint64_t *rows = tm.xw + (size_t)2 * tm.size * kHdrWords + (size_t)par * tm.size * kRowWords;
-            uint64_t *mine = hdrs + (size_t)tm.rank * kHdrWords;
+            // every header on a line of its own (each read with the others,
+            // all loads in flight at once); rows live in a separate region
+            uint64_t *hdrs = tm.xw + (size_t)par * tm.size * kHdrStride;
+            uint64_t *rows = tm.xw + (size_t)2 * tm.size * kHdrStride + (size_t)par * tm.size * kRowWords;
+            uint64_t *mine = hdrs + (size_t)tm.rank * kHdrStride;
             uint64_t *myrow = rows + (size_t)tm.rank * kRowWords;
             // the header goes out first: the team waits on headers, while a
             // row is read only after its header has won
@@ -424,7 +424,7 @@ __device__ __forceinline__ void team_select(Team &tm, Smem &sm, Best b, int flag
                     const int g0 = lane + q * kWave;
 #pragma unroll
                     for (int w = 0; w < kHdrWords; w++)
-                        ps[q * kHdrWords + w] = g0 < tm.size ? hdrs + (size_t)g0 * kHdrWords + w : nullptr;
+                        ps[q * kHdrWords + w] = g0 < tm.size ? hdrs + (size_t)g0 * kHdrStride + w : nullptr;
                 }
                 uint64_t d[4 * kHdrWords];
                 xget<4 * kHdrWords, 4>(ps, htag, d, &sm.xfail, tm.spin_limit);
@@ -2313,7 +2313,7 @@ static hipError_t launch_team_t(const void *A, int64_t m, int64_t n, int64_t lda
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     if (team > 1) {
-        const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
+        const int64_t words = (int64_t)2 * team * kSlotWords;
         hipLaunchKernelGGL(zero_team_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
                            stream, ws.xw, words, cfg.margins ? info : nullptr);
     }
@@ -2347,7 +2347,7 @@ static hipError_t launch_hadamard_t(const void *A, int64_t m, int64_t n, int64_t
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     if (team > 1) {
-        const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
+        const int64_t words = (int64_t)2 * team * kSlotWords;
         hipLaunchKernelGGL(zero_team_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
                            stream, ws.xw, words, cfg.margins ? info : nullptr);
     }
@@ -2389,7 +2389,7 @@ static hipError_t launch_cynical_t(const void *A, int64_t m, int64_t n, int64_t 
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     if (team > 1) {
-        const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
+        const int64_t words = (int64_t)2 * team * kSlotWords;
         hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
                            stream, ws.xw, words);
     }
@@ -2427,7 +2427,7 @@ static hipError_t launch_projective_t(const void *A, int64_t m, int64_t n, int64
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_bytes);
     (void)e;
     if (team > 1) {
-        const int64_t words = (int64_t)2 * team * (kHdrWords + kRowWords);
+        const int64_t words = (int64_t)2 * team * kSlotWords;
         hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)std::min<int64_t>(256, (words + 255) / 256)), dim3(256), 0,
                            stream, ws.xw, words);
     }

@@ -14,12 +14,15 @@ constexpr int kLMax = 256;   // largest number of sampled SRHT columns
 constexpr int kSMax = 256;   // largest number of rows or columns drawn by the leverage-score refinement
 
 // Team exchange (64-bit tagged words): per workgroup and parity 2 header
-// words (value, item, slot and flags in two 60-bit payloads) and 2 words per
-// row entry.
+// words (value, item, slot and flags in two 60-bit payloads), each
+// workgroup's header on a 128-byte line of its own (headers sharing a line
+// serialise the stores of different workgroups to it), and 2 words per row
+// entry.
 constexpr int kHdrWords = 2;
+constexpr int kHdrStride = 16;
 constexpr int kMaxTeam = 256;
 constexpr int kRowWords = 2 * kLMax;
-constexpr int kSlotWords = kHdrWords + kRowWords;  // exchange words per workgroup and parity
+constexpr int kSlotWords = kHdrStride + kRowWords;  // exchange words per workgroup and parity
 
 struct CAConfig {
     int32_t r, sweeps;
