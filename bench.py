@@ -48,19 +48,19 @@ SRC_POST = (_CS + "lra_post.hip", _CS + "lra_device.h", _CS + "lra_internal.h", 
 # line: (sources, SHA-1, FETCH_SIZE KiB per unit, WRITE_SIZE KiB per unit, copy FETCH KiB, copy WRITE KiB)
 TRAFFIC_COUNTS = {
     # one LRA: one ca_team_kernel dispatch (profiles/ca_team_kernel_20000x20000_r50.md)
-    "headline": (SRC_TEAM, "1be69a080d8c73ac95aa5c72fd20f37a74154901", 295436.3, 108622.0, 524308.3, 1048576.0),
+    "headline": (SRC_TEAM, "ea5f152c8eb184449e18381ef8481ef409fd586e", 325022.8, 108622.0, 524308.2, 1048576.0),
     # one batch: the four bin dispatches of ca_reg_kernel (profiles/ca_reg_kernel_fmm4096_r16.md)
-    "batched": (SRC_BATCH, "15c08d321fe1eb4136dd8efe74259436234513e7", 967.0 + 310778.9 + 3948909.4 + 7852.9, 38.0 + 1638.1 + 7639.5 + 313.5,
-                524308.3, 1048576.0),
+    "batched": (SRC_BATCH, "178db4791ebf57fb8191e4168ef37c8e4eab14f2", 967.0 + 309103.3 + 3948961.9 + 7843.7, 38.0 + 1638.1 + 7639.3 + 313.5,
+                524308.2, 1048576.0),
     # one batch: the four bin dispatches of ca_reg_points_kernel
-    "points": (SRC_BATCH, "15c08d321fe1eb4136dd8efe74259436234513e7", 815.6 + 4329.9 + 32442.1 + 1165.1, 38.0 + 1637.7 + 7643.4 + 313.5,
-               524308.3, 1048576.0),
+    "points": (SRC_BATCH, "178db4791ebf57fb8191e4168ef37c8e4eab14f2", 815.6 + 4330.1 + 32443.1 + 1165.1, 38.0 + 1637.7 + 7643.0 + 313.5,
+               524308.2, 1048576.0),
     # one full residual: the resid_kernel dispatch (FP64 core; BF16 x 3 core)
     # (profiles/resid_kernels_20000x20000_r50.md)
-    "residual_fp64": (SRC_POST, "f1303d01f45c7773b3be4cf878c8f19ad5c3c0bd", 968806.6, 68.7, 524308.3, 1048576.0),
-    "residual_mixed": (SRC_POST, "f1303d01f45c7773b3be4cf878c8f19ad5c3c0bd", 959549.0, 68.7, 524308.3, 1048576.0),
+    "residual_fp64": (SRC_POST, "be83459b920890769ea07f68e587dfd02a3fed7b", 972149.4, 68.7, 524308.2, 1048576.0),
+    "residual_mixed": (SRC_POST, "be83459b920890769ea07f68e587dfd02a3fed7b", 965536.3, 68.7, 524308.2, 1048576.0),
     # one launch of 256 blocks: the seven adj_* dispatches (profiles/adjoint_kernels_256x2048_r32.md)
-    "adjoint": (SRC_POST, "f1303d01f45c7773b3be4cf878c8f19ad5c3c0bd", 1174108.9, 563413.1, 524308.3, 1048576.0),
+    "adjoint": (SRC_POST, "be83459b920890769ea07f68e587dfd02a3fed7b", 1174708.3, 563418.4, 524308.2, 1048576.0),
 }
 
 
