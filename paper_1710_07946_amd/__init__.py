@@ -77,6 +77,10 @@ def load() -> ct.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("HIP library not built: %s (run paper_1710_07946_amd/build.py)" % LIB_PATH)
+        # torch first: the library must bind to the HIP runtime torch loads,
+        # or the process holds two runtimes and torch's device pointers are
+        # foreign to the library's (its first call fails with LRA_EDEVICE)
+        import torch  # noqa: F401
         L = ct.CDLL(LIB_PATH)
         P, i64, i32 = ct.c_void_p, ct.c_int64, ct.c_int32
         L.lra_default_opts.argtypes = [ct.POINTER(lra_opts)]

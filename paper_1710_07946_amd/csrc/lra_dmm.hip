@@ -9,7 +9,8 @@
 // the current rescaling when read, never stored):
 //   1. Gram matrix G = P^T P (w x w) in LDS, P staged through LDS 64 items
 //      at a time, each entry summed over the items in increasing order;
-//   2. one-sided Jacobi sweeps on G (the truncated nucleus's rotation loop):
+//   2. one-sided Jacobi sweeps on G (the truncated nucleus's rotation loop,
+//      without the rotations among directions far below the kept ones):
 //      G V = V Lambda, so the eigenvalues of G, the squared singular values
 //      of P, are the column norms and V its right singular vectors;
 //   3. kept: the r largest eigenvalues above 1e-13 times the largest (ties
@@ -52,10 +53,13 @@ namespace {
 constexpr int kDmmChunk = 64;             // sketch rows staged in LDS at a time
 constexpr int kDmmPs = kRMax + 1;         // their LDS row stride (doubles)
 typedef double v4d __attribute__((ext_vector_type(4)));
-// Pairs of Gram columns whose norms are both below 1e-10 of the largest
-// (eigenvalues below 1e-10 lambda_max) are not rotated against each other:
-// they can mix only directions far below the kept ones.
+// Pairs of Gram columns whose squared norms are both below 1e-20 of the
+// largest, or both below 1e-4 of the r-th largest (eigenvalues below 1e-10
+// lambda_max, or below 1e-2 lambda_r), are not rotated against each other:
+// they can mix only directions far below the kept ones, while every pair
+// with a column above the floor is still rotated until orthogonal.
 constexpr double kDmmPairFloor = 1e-20;
+constexpr double kDmmGapFloor = 1e-4;
 
 // FP64 MFMA 16x16x4: A operand of lane l is A[l % 16][l / 16], B operand
 // B[l / 16][l % 16], output v is D[l / 16 + 4 v][l % 16].
@@ -104,6 +108,122 @@ __device__ __forceinline__ int stage_chunk(const DmmSmem &sm, const DenseSrc<T> 
         Pc[it * kDmmPs + c] = x;
     }
     return bad;
+}
+
+// One-sided Jacobi sweeps on the w x w Gram matrix A (column-major, in
+// LDS), rotations accumulated in V (set to the identity by the caller): the
+// rotation loop of the truncated nucleus (round-robin pairs, a pair rotated
+// unless |a_p . a_q| <= w eps sqrt(|a_p|^2 |a_q|^2), eps = 2^-52, or a
+// column is negligible, or the sine is zero; at most 60 sweeps, each pair on
+// the 16 lanes of a DPP row), with the pair floor above recomputed at every
+// sweep's start from the squared column norms.  Returns the sweeps run.
+__device__ __forceinline__ int dmm_sweeps(double *A, double *V, int w, int r) {
+    constexpr int RL = kRMax / 16;
+    const int tid = threadIdx.x;
+    __shared__ int s_rot;
+    __shared__ double s_nrm[kRMax];
+    __shared__ double s_small, s_negl;
+    const int lp = w + (w & 1);
+    const int grp = tid / 16, j = tid % 16, ngrp = kBlock / 16;
+    const double tol = (double)w * 0x1p-52;
+    int sweep = 0;
+    for (; sweep < 60 && w > 1; sweep++) {
+        for (int c = grp; c < w; c += ngrp) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int u = 0; u < RL; u++) {
+                const int i = j + 16 * u;
+                const double x = i < w ? A[c * w + i] : 0.0;
+                s2 += x * x;
+            }
+            s2 = row_sum16(s2);
+            if (j == 0) s_nrm[c] = s2;
+        }
+        if (tid == 0) s_rot = 0;
+        __syncthreads();
+        if (tid < kWave) {
+            // the largest and the r-th largest squared norm (one wavefront,
+            // w <= 64; with r >= w no pair can fall below the r-th largest)
+            const double x = tid < w ? s_nrm[tid] : -1.0;
+            int gt = 0, ge = 0;
+            if (r < w) {
+                for (int c = 0; c < w; c++) {
+                    gt += s_nrm[c] > x ? 1 : 0;
+                    ge += s_nrm[c] >= x ? 1 : 0;
+                }
+            }
+            const double big = wave_max(x);
+            const unsigned long long at = __ballot(r < w && tid < w && gt < r && r <= ge);
+            const double rth = at ? __shfl(x, __ffsll((long long)at) - 1) : 0.0;
+            if (tid == 0) {
+                s_negl = tol * tol * big;
+                s_small = fmax(kDmmPairFloor * big, kDmmGapFloor * rth);
+            }
+        }
+        __syncthreads();
+        const double negl = s_negl, small = s_small;
+        for (int t = 0; t < lp - 1; t++) {
+            for (int pr = grp; pr < lp / 2; pr += ngrp) {
+                int pc, qc;
+                jacobi_pair(t, pr, lp, pc, qc);
+                if (qc >= w) continue;
+                const double *ap = A + pc * w, *aq = A + qc * w;
+                double x[RL], y[RL];
+#pragma unroll
+                for (int u = 0; u < RL; u++) {
+                    const int i = j + 16 * u;
+                    x[u] = i < w ? ap[i] : 0.0;
+                    y[u] = i < w ? aq[i] : 0.0;
+                }
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int u = 0; u < RL; u++) {
+                    al += x[u] * x[u];
+                    be += y[u] * y[u];
+                    ga += x[u] * y[u];
+                }
+                al = row_sum16(al);
+                be = row_sum16(be);
+                ga = row_sum16(ga);
+                if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+                if (al <= negl || be <= negl) continue;
+                if (al <= small && be <= small) continue;
+                const double ze = (be - al) / (2.0 * ga);
+                const double tt = (ze >= 0.0 ? 1.0 : -1.0) / (fabs(ze) + sqrt(1.0 + ze * ze));
+                const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
+                if (sn == 0.0) continue;
+#pragma unroll
+                for (int u = 0; u < RL; u++) {
+                    const int i = j + 16 * u;
+                    if (i < w) {
+                        A[pc * w + i] = cs * x[u] - sn * y[u];
+                        A[qc * w + i] = sn * x[u] + cs * y[u];
+                    }
+                }
+                double vx[RL], vy[RL];
+#pragma unroll
+                for (int u = 0; u < RL; u++) {
+                    const int i = j + 16 * u;
+                    vx[u] = i < w ? V[pc * w + i] : 0.0;
+                    vy[u] = i < w ? V[qc * w + i] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < RL; u++) {
+                    const int i = j + 16 * u;
+                    if (i < w) {
+                        V[pc * w + i] = cs * vx[u] - sn * vy[u];
+                        V[qc * w + i] = sn * vx[u] + cs * vy[u];
+                    }
+                }
+                if (j == 0) s_rot = 1;
+            }
+            __syncthreads();
+        }
+        const int rot = *(volatile int *)&s_rot;
+        __syncthreads();
+        if (!rot) break;
+    }
+    return w > 1 ? (sweep < 60 ? sweep + 1 : 60) : 0;
 }
 
 // One half-step (see the file comment).  ROWS: items = rows of W, w = l,
@@ -160,7 +280,7 @@ __device__ __forceinline__ void dmm_half(DmmSmem &sm, double *lds, const DenseSr
     DMM_TOC(0, t0);
     // 2. eigenvectors of G
     DMM_TIC(t1);
-    const int nsw = jacobi_sweeps(A, V, w, w, kDmmPairFloor);
+    const int nsw = dmm_sweeps(A, V, w, r);
     DMM_TOC(1, t1);
     DMM_CNT(6, nsw);
     DMM_CNT(7, 1);
