@@ -45,6 +45,8 @@ SRC_TEAM = (_CS + "lra_ca.hip", _CS + "lra_common.h", _CS + "lra_device.h", _CS 
 SRC_BATCH = (_CS + "lra_batch.hip", _CS + "lra_common.h", _CS + "lra_device.h", _CS + "lra_internal.h",
              _CS + "lra_api.hip", "paper_1710_07946_amd/build.py")
 SRC_POST = (_CS + "lra_post.hip", _CS + "lra_device.h", _CS + "lra_internal.h", "paper_1710_07946_amd/build.py")
+SRC_DMM = (_CS + "lra_dmm.hip", _CS + "lra_common.h", _CS + "lra_device.h", _CS + "lra_internal.h",
+           _CS + "lra_api.hip", "paper_1710_07946_amd/build.py")
 # line: (sources, SHA-1, FETCH_SIZE KiB per unit, WRITE_SIZE KiB per unit, copy FETCH KiB, copy WRITE KiB)
 TRAFFIC_COUNTS = {
     # one LRA: one ca_team_kernel dispatch (profiles/ca_team_kernel_20000x20000_r50.md)
@@ -61,6 +63,9 @@ TRAFFIC_COUNTS = {
     "residual_mixed": (SRC_POST, "be83459b920890769ea07f68e587dfd02a3fed7b", 965536.3, 68.7, 524308.2, 1048576.0),
     # one launch of 256 blocks: the seven adj_* dispatches (profiles/adjoint_kernels_256x2048_r32.md)
     "adjoint": (SRC_POST, "be83459b920890769ea07f68e587dfd02a3fed7b", 1174708.3, 563418.4, 524308.2, 1048576.0),
+    # one batch of 256 DMM08 C-A LRAs at k = l = 64: one ca_dmm_kernel dispatch
+    # (profiles/ca_dmm_kernel_256x1000x1000_r16.md)
+    "dmm_k64": (SRC_DMM, "937bf9044a9df50b72f0c2717eefc55621864995", 7496471.4, 72464.1, 524308.2, 1048576.0),
 }
 
 
@@ -719,7 +724,7 @@ def bench_dmm(lra, workloads, torch, np, args):
                 "median_rel_fro_err_8_blocks": float(np.median(errs))}
         if k == 64:
             line["roofline"] = {"bound": "mfma", "achieved": tfs, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                                "frac": tfs / FP64_PEAK_TFS, "traffic": None}
+                                "frac": tfs / FP64_PEAK_TFS, "traffic": counted_traffic("dmm_k64")}
             line["useful_bytes_per_batch"] = count * (iters * 2 * (m * k + k * n) * 4 + k * k * 4)
         res["k%d" % k] = line
     if not args.no_cpu_baseline:
