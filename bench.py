@@ -50,7 +50,7 @@ SRC_DMM = (_CS + "lra_dmm.hip", _CS + "lra_common.h", _CS + "lra_device.h", _CS 
 # line: (sources, SHA-1, FETCH_SIZE KiB per unit, WRITE_SIZE KiB per unit, copy FETCH KiB, copy WRITE KiB)
 TRAFFIC_COUNTS = {
     # one LRA: one ca_team_kernel dispatch (profiles/ca_team_kernel_20000x20000_r50.md)
-    "headline": (SRC_TEAM, "ea5f152c8eb184449e18381ef8481ef409fd586e", 325022.8, 108622.0, 524308.2, 1048576.0),
+    "headline": (SRC_TEAM, "ea7f432bf3c150ca12aaa4bc28419e1d07f89a3e", 324544.3, 108622.0, 524308.2, 1048576.0),
     # one batch: the four bin dispatches of ca_reg_kernel (profiles/ca_reg_kernel_fmm4096_r16.md)
     "batched": (SRC_BATCH, "178db4791ebf57fb8191e4168ef37c8e4eab14f2", 967.0 + 309103.3 + 3948961.9 + 7843.7, 38.0 + 1638.1 + 7639.3 + 313.5,
                 524308.2, 1048576.0),
