@@ -227,6 +227,19 @@ def test_asrht_start(lra, m, n, d, l, r, team):
     assert_parity(A, g, o, 1e-4)
 
 
+@pytest.mark.parametrize("team", [40, 100, 150, 220])
+def test_header_poll_widths(lra, team):
+    """Teams that give each polling lane one to four header groups (up to 64,
+    128, 192 and 256 workgroups) return the oracle's LRA: the header wait
+    differs only in how many headers each lane reads."""
+    A = workloads.factor_gaussian(6000, 3000, 20, 1e-7, seeds=(6000, 3000, 5), dtype=np.float32)
+    o = oracle.ca_cur(A, 20, 2, 4242, preprocess=1, ah_depth=2, ah_samples=40)
+    print("team", team, flush=True)
+    g = gpu_cur(lra, A, 20, 2, 4242, preprocess=1, ah_depth=2, ah_samples=40, team_size=team)
+    assert g[3]["team_size"] == team
+    assert_parity(A, g, o, 1e-4)
+
+
 def test_cfg_20000_fp32_asrht_rank50(lra):
     """20000 x 20000 FP32 factor-Gaussian rank 50 + N(0, 1e-6^2), abridged SRHT
     (d = 3, l = 100), r = 50, 4 sweeps: the benchmark workload, in the launch
